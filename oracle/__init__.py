@@ -1,0 +1,216 @@
+"""FP64 CPU oracle of the unstructured S_N sweep (ctypes wrapper of snx_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: tests, the smoke check and the benchmark's CPU
+baseline use it to check and time the GPU library.  The product library never
+imports it, and it imports nothing from the product library.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsnx_oracle.so")
+_SRC = os.path.join(_HERE, "snx_oracle.c")
+
+_dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+
+ERRORS = {0: "OK", -1: "E_ARG", -2: "E_STATE", -3: "E_MESH", -4: "E_CYCLE", -6: "E_OOM", -7: "E_NOCONV"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"oracle {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def build(force: bool = True) -> str:
+    """Compile snx_oracle.c into libsnx_oracle.so with gcc (OpenMP over groups)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ct.CDLL(_LIB_PATH)
+        vp = ct.c_void_p
+        nullable_d = ct.c_void_p
+        L.snxo_gauss_legendre.argtypes = [ct.c_int, _dp, _dp]
+        L.snxo_quadrature.argtypes = [ct.c_int, ct.c_int, _dp, _dp]
+        L.snxo_create.argtypes = [ct.POINTER(vp)]
+        L.snxo_destroy.argtypes = [vp]
+        L.snxo_destroy.restype = None
+        L.snxo_set_mesh.argtypes = [vp, ct.c_int, ct.c_int, _dp, _ip]
+        L.snxo_set_quadrature.argtypes = [vp, ct.c_int, _dp, _dp]
+        L.snxo_set_materials.argtypes = [vp, ct.c_int, _dp, _dp, _dp]
+        L.snxo_set_boundary.argtypes = [vp, ct.c_int, nullable_d]
+        L.snxo_set_hooks.argtypes = [vp, nullable_d, nullable_d]
+        L.snxo_setup.argtypes = [vp]
+        L.snxo_sweep.argtypes = [vp, nullable_d, _dp, nullable_d, nullable_d, nullable_d]
+        L.snxo_solve.argtypes = [vp, ct.c_double, ct.c_int, nullable_d, _dp,
+                                 ct.POINTER(ct.c_int), ct.POINTER(ct.c_double), nullable_d]
+        L.snxo_balance.argtypes = [vp, nullable_d, _dp, _dp, _dp]
+        L.snxo_integrated_flux.argtypes = [vp, _dp, _dp]
+        L.snxo_get_geometry.argtypes = [vp] + [nullable_d] * 7
+        L.snxo_get_dag.argtypes = [vp, nullable_d, nullable_d, nullable_d]
+        L.snxo_last_error.argtypes = [vp]
+        L.snxo_last_error.restype = ct.c_char_p
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+def gauss_legendre(n: int):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    rc = lib().snxo_gauss_legendre(n, x, w)
+    if rc:
+        raise OracleError(rc, "gauss_legendre")
+    return x, w
+
+
+def quadrature(npolar: int, nazim: int):
+    nang = 8 * npolar * nazim
+    om = np.zeros((nang, 3))
+    w = np.zeros(nang)
+    rc = lib().snxo_quadrature(npolar, nazim, om, w)
+    if rc:
+        raise OracleError(rc, "quadrature")
+    return om, w
+
+
+class Oracle:
+    """One transport problem on the CPU in FP64.
+
+    Arrays use the same exchange layouts as the GPU library: phi[ncell][G][8].
+    """
+
+    def __init__(self, xyz, cell_vert, omega, w, sigma_t, sigma_s, q,
+                 boundary_kind: int = 0, psi_b=None, ang_src=None, bnd_in=None, setup: bool = True):
+        L = lib()
+        h = ct.c_void_p()
+        self._check(L.snxo_create(ct.byref(h)), "create")
+        self.h = h
+        self.xyz = np.ascontiguousarray(xyz, np.float64)
+        self.cell_vert = np.ascontiguousarray(cell_vert, np.int32)
+        self.omega = np.ascontiguousarray(omega, np.float64)
+        self.w = np.ascontiguousarray(w, np.float64)
+        self.sigma_t = np.ascontiguousarray(sigma_t, np.float64)
+        self.sigma_s = np.ascontiguousarray(sigma_s, np.float64)
+        self.q = np.ascontiguousarray(q, np.float64)
+        self.ncell = self.cell_vert.shape[0]
+        self.nang = self.omega.shape[0]
+        self.G = self.sigma_t.shape[1]
+        self._check(L.snxo_set_mesh(h, self.ncell, self.xyz.shape[0], self.xyz, self.cell_vert), "set_mesh")
+        self._check(L.snxo_set_quadrature(h, self.nang, self.omega, self.w), "set_quadrature")
+        self._check(L.snxo_set_materials(h, self.G, self.sigma_t, self.sigma_s, self.q), "set_materials")
+        self.psi_b = None if psi_b is None else np.ascontiguousarray(psi_b, np.float64)
+        self._check(L.snxo_set_boundary(h, boundary_kind, _ptr(self.psi_b)), "set_boundary")
+        self.set_hooks(ang_src, bnd_in)
+        if setup:
+            self.setup()
+
+    @classmethod
+    def from_problem(cls, prob, **kw):
+        om, w = quadrature(prob.npolar, prob.nazim)
+        return cls(prob.mesh.xyz, prob.mesh.cell_vert, om, w, prob.mat.sigma_t, prob.mat.sigma_s,
+                   prob.mat.q, prob.boundary_kind, prob.psi_b, **kw)
+
+    def _check(self, rc, what):
+        if rc:
+            msg = lib().snxo_last_error(self.h).decode() if getattr(self, "h", None) else what
+            raise OracleError(rc, f"{what}: {msg}")
+
+    def set_hooks(self, ang_src=None, bnd_in=None):
+        self._ang_src = None if ang_src is None else np.ascontiguousarray(ang_src, np.float64)
+        self._bnd_in = None if bnd_in is None else np.ascontiguousarray(bnd_in, np.float64)
+        self._check(lib().snxo_set_hooks(self.h, _ptr(self._ang_src), _ptr(self._bnd_in)), "set_hooks")
+
+    def setup(self):
+        self._check(lib().snxo_setup(self.h), "setup")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().snxo_destroy(h)
+            self.h = None
+
+    def zeros_phi(self):
+        return np.zeros((self.ncell, self.G, 8))
+
+    def sweep(self, phi_in=None, want_psi=False, want_leak=False, want_leak_ang=False):
+        phi_out = self.zeros_phi()
+        pin = None if phi_in is None else np.ascontiguousarray(phi_in, np.float64)
+        psi = np.zeros((self.nang, self.ncell, self.G, 8)) if want_psi else None
+        leak = np.zeros((self.ncell, self.G)) if want_leak else None
+        leak_ang = np.zeros((self.nang, self.ncell, self.G)) if want_leak_ang else None
+        self._check(lib().snxo_sweep(self.h, _ptr(pin), phi_out, _ptr(psi), _ptr(leak), _ptr(leak_ang)), "sweep")
+        out = {"phi": phi_out}
+        if want_psi:
+            out["psi"] = psi
+        if want_leak:
+            out["leak"] = leak
+        if want_leak_ang:
+            out["leak_ang"] = leak_ang
+        return out
+
+    def solve(self, tol, max_it, phi0=None, allow_noconv=False):
+        phi = self.zeros_phi()
+        it = ct.c_int(0)
+        eps = ct.c_double(0.0)
+        hist = np.zeros(max_it)
+        p0 = None if phi0 is None else np.ascontiguousarray(phi0, np.float64)
+        rc = lib().snxo_solve(self.h, tol, max_it, _ptr(p0), phi, ct.byref(it), ct.byref(eps), _ptr(hist))
+        if rc and not (allow_noconv and rc == -7):
+            self._check(rc, "solve")
+        return {"phi": phi, "iters": it.value, "eps": eps.value, "hist": hist[: it.value], "status": rc}
+
+    def balance(self, phi_in, phi_out, leak):
+        out = np.zeros((self.G, 4))
+        pin = None if phi_in is None else np.ascontiguousarray(phi_in, np.float64)
+        self._check(lib().snxo_balance(self.h, _ptr(pin), np.ascontiguousarray(phi_out), np.ascontiguousarray(leak), out), "balance")
+        return out
+
+    def integrated_flux(self, phi):
+        out = np.zeros((self.G, 2))
+        self._check(lib().snxo_integrated_flux(self.h, np.ascontiguousarray(phi, np.float64), out), "integrated_flux")
+        return out
+
+    def geometry(self):
+        C = self.ncell
+        g = {"M": np.zeros((C, 8, 8)), "S": np.zeros((C, 3, 8, 8)), "F": np.zeros((C, 6, 3, 4, 4)),
+             "area": np.zeros((C, 6, 3)), "nbr": np.zeros((C, 6), np.int32),
+             "nbr_face": np.zeros((C, 6), np.int32), "perm": np.zeros((C, 6, 4), np.int32)}
+        self._check(lib().snxo_get_geometry(self.h, *[_ptr(g[k]) for k in
+                    ("M", "S", "F", "area", "nbr", "nbr_face", "perm")]), "get_geometry")
+        return g
+
+    def dag(self):
+        C = self.ncell
+        d = {"inflow": np.zeros((8, C), np.int32), "level": np.zeros((8, C), np.int32),
+             "order": np.zeros((8, C), np.int32)}
+        self._check(lib().snxo_get_dag(self.h, _ptr(d["inflow"]), _ptr(d["level"]), _ptr(d["order"])), "get_dag")
+        return d
+
+
+def face_nodes(f: int):
+    """Local vertices of face f = 2*axis + side (bit `axis` of the index equals side)."""
+    axis, side = divmod(f, 2)
+    return [j for j in range(8) if ((j >> axis) & 1) == side]

@@ -1,0 +1,747 @@
+/*
+ * snx_oracle.c -- FP64 CPU reference of the unstructured S_N sweep.
+ *
+ * TEST INFRASTRUCTURE ONLY (see snx_oracle.h).  Plain loops, double precision,
+ * no blocking or fusion: each function follows the definition it cites so that
+ * it can be checked against the paper by eye.
+ */
+#include "snx_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define PI 3.14159265358979323846
+
+struct snxo_problem {
+    int ncell, nvert, nang, G;
+    double *xyz;        /* [nvert][3] */
+    int32_t *cv;        /* [ncell][8] */
+    double *omega, *w;  /* [nang][3], [nang] */
+    double *sigt, *sigs, *q; /* [ncell][G] */
+    int bkind;
+    double *psib;       /* [G] */
+    const double *ang_src, *bnd_in; /* test hooks, not owned */
+    int ready;
+    /* derived by setup */
+    double *M, *S, *F, *area;       /* [C][64], [C][3][64], [C][6][3][16], [C][6][3] */
+    int32_t *nbr, *nbrf, *perm;     /* [C][6], [C][6], [C][6][4] */
+    int32_t *inflow, *level, *order;/* [8][C] each */
+    char err[256];
+};
+
+/* ---------------------------------------------------------------- helpers */
+
+static int fail(snxo_problem *p, int code, const char *msg) {
+    if (p) snprintf(p->err, sizeof p->err, "%s", msg);
+    return code;
+}
+
+const char *snxo_last_error(snxo_problem *p) { return p ? p->err : "null problem"; }
+
+/* Local vertex j = a + 2b + 4c sits at reference corner (2a-1, 2b-1, 2c-1). */
+static double corner(int j, int d) { return ((j >> d) & 1) ? 1.0 : -1.0; }
+
+/* Trilinear basis f_j(xi) = prod_d (1 + corner_jd xi_d)/2 and its reference gradient. */
+static void basis(const double xi[3], double f[8], double df[8][3]) {
+    for (int j = 0; j < 8; ++j) {
+        double h[3], dh[3];
+        for (int d = 0; d < 3; ++d) {
+            h[d] = 0.5 * (1.0 + corner(j, d) * xi[d]);
+            dh[d] = 0.5 * corner(j, d);
+        }
+        f[j] = h[0] * h[1] * h[2];
+        df[j][0] = dh[0] * h[1] * h[2];
+        df[j][1] = h[0] * dh[1] * h[2];
+        df[j][2] = h[0] * h[1] * dh[2];
+    }
+}
+
+/* Face f = 2*axis + side holds the local vertices whose bit `axis` equals side,
+ * listed in increasing local index. */
+static void face_nodes(int f, int fn[4]) {
+    int axis = f / 2, side = f % 2, k = 0;
+    for (int j = 0; j < 8; ++j)
+        if (((j >> axis) & 1) == side) fn[k++] = j;
+}
+
+static double det3(const double J[3][3]) {
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+         - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+         + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+/* x(xi) Jacobian J[a][b] = d x_a / d xi_b. */
+static void jacobian(const double X[8][3], const double df[8][3], double J[3][3]) {
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int j = 0; j < 8; ++j) s += X[j][a] * df[j][b];
+            J[a][b] = s;
+        }
+}
+
+/* Solve the n x n system A x = b by LU with partial pivoting (A, b overwritten). */
+static int lu_solve(int n, double *A, double *b, double *x) {
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        double best = fabs(A[k * n + k]);
+        for (int i = k + 1; i < n; ++i)
+            if (fabs(A[i * n + k]) > best) { best = fabs(A[i * n + k]); piv = i; }
+        if (best == 0.0) return -1;
+        if (piv != k) {
+            for (int j = 0; j < n; ++j) { double t = A[k * n + j]; A[k * n + j] = A[piv * n + j]; A[piv * n + j] = t; }
+            double t = b[k]; b[k] = b[piv]; b[piv] = t;
+        }
+        for (int i = k + 1; i < n; ++i) {
+            double l = A[i * n + k] / A[k * n + k];
+            A[i * n + k] = l;
+            for (int j = k + 1; j < n; ++j) A[i * n + j] -= l * A[k * n + j];
+            b[i] -= l * b[k];
+        }
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = b[i];
+        for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * x[j];
+        x[i] = s / A[i * n + i];
+    }
+    return 0;
+}
+
+/* Octant sign vector s_o: bit 0 -> x negative, bit 1 -> y, bit 2 -> z. */
+static void octant_signs(int o, double s[3]) {
+    for (int d = 0; d < 3; ++d) s[d] = ((o >> d) & 1) ? -1.0 : 1.0;
+}
+
+static int octant_of(const double om[3]) {
+    return (om[0] < 0.0 ? 1 : 0) + (om[1] < 0.0 ? 2 : 0) + (om[2] < 0.0 ? 4 : 0);
+}
+
+/* ------------------------------------------------------------ quadrature */
+
+int snxo_gauss_legendre(int n, double *x, double *w) {
+    if (n < 1 || !x || !w) return SNXO_E_ARG;
+    /* Newton iteration on P_n from the Chebyshev-like initial guess. */
+    for (int i = 0; i < n; ++i) {
+        double z = cos(PI * (i + 0.75) / (n + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1; p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1.0; }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1; p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+        }
+        x[n - 1 - i] = z;                       /* ascending order */
+        w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+    return SNXO_OK;
+}
+
+int snxo_quadrature(int npolar, int nazim, double *omega, double *w) {
+    if (npolar < 1 || nazim < 1 || !omega || !w) return SNXO_E_ARG;
+    int m = 2 * npolar;
+    double *gx = malloc(sizeof(double) * m), *gw = malloc(sizeof(double) * m);
+    if (!gx || !gw) { free(gx); free(gw); return SNXO_E_OOM; }
+    snxo_gauss_legendre(m, gx, gw);
+    int per = npolar * nazim;
+    for (int o = 0; o < 8; ++o) {
+        double s[3];
+        octant_signs(o, s);
+        for (int k = 0; k < npolar; ++k) {
+            double mu = gx[npolar + k];         /* positive half, ascending */
+            double wmu = gw[npolar + k];
+            double st = sqrt(1.0 - mu * mu);
+            for (int j = 0; j < nazim; ++j) {
+                double om = (j + 0.5) * (0.5 * PI) / nazim;
+                int n = o * per + k * nazim + j;
+                omega[3 * n + 0] = s[0] * st * cos(om);
+                omega[3 * n + 1] = s[1] * st * sin(om);
+                omega[3 * n + 2] = s[2] * mu;
+                w[n] = wmu * (0.5 * PI) / nazim;
+            }
+        }
+    }
+    free(gx); free(gw);
+    return SNXO_OK;
+}
+
+/* ------------------------------------------------------------ lifecycle */
+
+static void free_derived(snxo_problem *p) {
+    free(p->M); free(p->S); free(p->F); free(p->area);
+    free(p->nbr); free(p->nbrf); free(p->perm);
+    free(p->inflow); free(p->level); free(p->order);
+    p->M = p->S = p->F = p->area = NULL;
+    p->nbr = p->nbrf = p->perm = p->inflow = p->level = p->order = NULL;
+    p->ready = 0;
+}
+
+int snxo_create(snxo_problem **out) {
+    if (!out) return SNXO_E_ARG;
+    *out = calloc(1, sizeof(snxo_problem));
+    return *out ? SNXO_OK : SNXO_E_OOM;
+}
+
+void snxo_destroy(snxo_problem *p) {
+    if (!p) return;
+    free_derived(p);
+    free(p->xyz); free(p->cv); free(p->omega); free(p->w);
+    free(p->sigt); free(p->sigs); free(p->q); free(p->psib);
+    free(p);
+}
+
+static double *dup_d(const double *src, size_t n) {
+    double *d = malloc(sizeof(double) * (n ? n : 1));
+    if (d && src) memcpy(d, src, sizeof(double) * n);
+    return d;
+}
+
+int snxo_set_mesh(snxo_problem *p, int ncell, int nvert, const double *xyz, const int32_t *cv) {
+    if (!p || ncell < 1 || nvert < 8 || !xyz || !cv) return fail(p, SNXO_E_ARG, "bad mesh arguments");
+    for (long i = 0; i < 8L * ncell; ++i)
+        if (cv[i] < 0 || cv[i] >= nvert) return fail(p, SNXO_E_ARG, "vertex index out of range");
+    free(p->xyz); free(p->cv);
+    p->xyz = dup_d(xyz, 3 * (size_t)nvert);
+    p->cv = malloc(sizeof(int32_t) * 8 * (size_t)ncell);
+    if (!p->xyz || !p->cv) return fail(p, SNXO_E_OOM, "out of memory");
+    memcpy(p->cv, cv, sizeof(int32_t) * 8 * (size_t)ncell);
+    p->ncell = ncell; p->nvert = nvert;
+    free_derived(p);
+    return SNXO_OK;
+}
+
+int snxo_set_quadrature(snxo_problem *p, int nang, const double *omega, const double *w) {
+    if (!p || nang < 8 || nang % 8 || !omega || !w) return fail(p, SNXO_E_ARG, "bad quadrature");
+    int per = nang / 8;
+    for (int n = 0; n < nang; ++n) {
+        if (omega[3 * n] == 0.0 || omega[3 * n + 1] == 0.0 || omega[3 * n + 2] == 0.0)
+            return fail(p, SNXO_E_ARG, "direction on an octant boundary");
+        if (octant_of(omega + 3 * n) != n / per)
+            return fail(p, SNXO_E_ARG, "directions not grouped by octant");
+    }
+    free(p->omega); free(p->w);
+    p->omega = dup_d(omega, 3 * (size_t)nang);
+    p->w = dup_d(w, (size_t)nang);
+    if (!p->omega || !p->w) return fail(p, SNXO_E_OOM, "out of memory");
+    p->nang = nang;
+    return SNXO_OK;
+}
+
+int snxo_set_materials(snxo_problem *p, int G, const double *st, const double *ss, const double *q) {
+    if (!p || G < 1 || !st || !ss || !q || p->ncell < 1) return fail(p, SNXO_E_ARG, "bad materials");
+    size_t n = (size_t)p->ncell * G;
+    free(p->sigt); free(p->sigs); free(p->q);
+    p->sigt = dup_d(st, n); p->sigs = dup_d(ss, n); p->q = dup_d(q, n);
+    if (!p->sigt || !p->sigs || !p->q) return fail(p, SNXO_E_OOM, "out of memory");
+    p->G = G;
+    return SNXO_OK;
+}
+
+int snxo_set_boundary(snxo_problem *p, int kind, const double *psi_b) {
+    if (!p || (kind != 0 && kind != 1) || (kind == 1 && (!psi_b || p->G < 1)))
+        return fail(p, SNXO_E_ARG, "bad boundary");
+    free(p->psib);
+    p->psib = NULL;
+    p->bkind = kind;
+    if (kind == 1) {
+        p->psib = dup_d(psi_b, (size_t)p->G);
+        if (!p->psib) return fail(p, SNXO_E_OOM, "out of memory");
+    }
+    return SNXO_OK;
+}
+
+int snxo_set_hooks(snxo_problem *p, const double *ang_src, const double *bnd_in) {
+    if (!p) return SNXO_E_ARG;
+    p->ang_src = ang_src;
+    p->bnd_in = bnd_in;
+    return SNXO_OK;
+}
+
+/* --------------------------------------------------------------- topology */
+
+typedef struct { int32_t key[4]; int32_t cell, face; } face_rec;
+
+static int cmp_rec(const void *a, const void *b) {
+    const face_rec *x = a, *y = b;
+    for (int i = 0; i < 4; ++i)
+        if (x->key[i] != y->key[i]) return x->key[i] < y->key[i] ? -1 : 1;
+    long ix = 6L * x->cell + x->face, iy = 6L * y->cell + y->face;
+    return ix < iy ? -1 : (ix > iy);
+}
+
+static int cmp_i32(const void *a, const void *b) {
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return x < y ? -1 : (x > y);
+}
+
+/* Faces are matched across cells by their sorted global-vertex 4-tuples. */
+static int build_topology(snxo_problem *p) {
+    int C = p->ncell;
+    face_rec *r = malloc(sizeof(face_rec) * 6 * (size_t)C);
+    if (!r) return fail(p, SNXO_E_OOM, "out of memory");
+    for (int K = 0; K < C; ++K)
+        for (int f = 0; f < 6; ++f) {
+            int fn[4];
+            face_nodes(f, fn);
+            face_rec *e = &r[6 * K + f];
+            for (int k = 0; k < 4; ++k) e->key[k] = p->cv[8 * K + fn[k]];
+            qsort(e->key, 4, sizeof(int32_t), cmp_i32);
+            for (int k = 1; k < 4; ++k)
+                if (e->key[k] == e->key[k - 1]) { free(r); return fail(p, SNXO_E_MESH, "degenerate face"); }
+            e->cell = K; e->face = f;
+        }
+    qsort(r, 6 * (size_t)C, sizeof(face_rec), cmp_rec);
+    for (long i = 0; i < 6L * C; ++i) { p->nbr[i] = -1; p->nbrf[i] = -1; }
+    long i = 0;
+    while (i < 6L * C) {
+        long j = i + 1;
+        while (j < 6L * C && memcmp(r[j].key, r[i].key, sizeof r[i].key) == 0) ++j;
+        if (j - i > 2) { free(r); return fail(p, SNXO_E_MESH, "face shared by more than two cells"); }
+        if (j - i == 2) {
+            int K = r[i].cell, f = r[i].face, N = r[i + 1].cell, g = r[i + 1].face;
+            if (K == N) { free(r); return fail(p, SNXO_E_MESH, "cell glued to itself"); }
+            p->nbr[6 * K + f] = N; p->nbrf[6 * K + f] = g;
+            p->nbr[6 * N + g] = K; p->nbrf[6 * N + g] = f;
+        }
+        i = j;
+    }
+    free(r);
+    /* Neighbour's local vertex at each of my face nodes. */
+    for (int K = 0; K < C; ++K)
+        for (int f = 0; f < 6; ++f) {
+            int fn[4];
+            face_nodes(f, fn);
+            int N = p->nbr[6 * K + f];
+            for (int k = 0; k < 4; ++k) {
+                int32_t v = p->cv[8 * K + fn[k]], found = -1;
+                if (N >= 0)
+                    for (int jj = 0; jj < 8; ++jj)
+                        if (p->cv[8 * N + jj] == v) found = jj;
+                p->perm[24 * K + 4 * f + k] = found;
+                if (N >= 0 && found < 0) return fail(p, SNXO_E_MESH, "face vertices do not match");
+            }
+        }
+    return SNXO_OK;
+}
+
+/* --------------------------------------------------------------- geometry */
+
+/* Mass and stiffness by 2x2x2 Gauss (points +-1/sqrt3, unit weights):
+ * M_ij = int f_i f_j dV,  S^a_ij = int f_i d f_j / d x_a dV. */
+static int cell_volume_matrices(snxo_problem *p, int K) {
+    double X[8][3];
+    for (int j = 0; j < 8; ++j)
+        for (int a = 0; a < 3; ++a) X[j][a] = p->xyz[3 * p->cv[8 * K + j] + a];
+    double *M = p->M + 64L * K, *S = p->S + 192L * K;
+    memset(M, 0, sizeof(double) * 64);
+    memset(S, 0, sizeof(double) * 192);
+    const double g = 1.0 / sqrt(3.0);
+    for (int qp = 0; qp < 8; ++qp) {
+        double xi[3] = { corner(qp, 0) * g, corner(qp, 1) * g, corner(qp, 2) * g };
+        double f[8], df[8][3], J[3][3];
+        basis(xi, f, df);
+        jacobian(X, df, J);
+        double dJ = det3(J);
+        if (!(dJ > 0.0)) return fail(p, SNXO_E_MESH, "non-positive Jacobian at a Gauss point");
+        /* physical gradient: solve J^T grad_x = grad_xi, via the inverse J^{-1} */
+        double inv[3][3];
+        inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / dJ;
+        inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / dJ;
+        inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / dJ;
+        inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / dJ;
+        inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / dJ;
+        inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / dJ;
+        inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / dJ;
+        inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / dJ;
+        inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / dJ;
+        double gx[8][3];
+        for (int j = 0; j < 8; ++j)
+            for (int a = 0; a < 3; ++a)   /* (J^{-T} grad_xi)_a = sum_b inv[b][a] dxi_b */
+                gx[j][a] = inv[0][a] * df[j][0] + inv[1][a] * df[j][1] + inv[2][a] * df[j][2];
+        for (int i = 0; i < 8; ++i)
+            for (int j = 0; j < 8; ++j) {
+                M[8 * i + j] += dJ * f[i] * f[j];
+                for (int a = 0; a < 3; ++a) S[64 * a + 8 * i + j] += dJ * f[i] * gx[j][a];
+            }
+    }
+    return SNXO_OK;
+}
+
+/* Face matrices by 2x2 Gauss on the face parametrised by the two remaining
+ * reference coordinates (s, t) in increasing axis order; N = +-(dx/ds x dx/dt)
+ * oriented outward.  F^a_kl = sum_q N_a f_k f_l over face nodes k, l;
+ * area vector A = sum_q N. */
+static void face_matrices(snxo_problem *p, int K, int f, double F[3][16], double A[3]) {
+    double X[8][3];
+    for (int j = 0; j < 8; ++j)
+        for (int a = 0; a < 3; ++a) X[j][a] = p->xyz[3 * p->cv[8 * K + j] + a];
+    int axis = f / 2, side = f % 2, fn[4];
+    face_nodes(f, fn);
+    int u = (axis == 0) ? 1 : 0, v = (axis == 2) ? 1 : 2;
+    /* dx/du x dx/dv points along +xi_axis for axis 0 and 2, along -xi_axis for axis 1 */
+    double sgn = (axis == 1 ? -1.0 : 1.0) * (side ? 1.0 : -1.0);
+    const double g = 1.0 / sqrt(3.0);
+    memset(F, 0, sizeof(double) * 48);
+    A[0] = A[1] = A[2] = 0.0;
+    for (int qp = 0; qp < 4; ++qp) {
+        double xi[3];
+        xi[axis] = side ? 1.0 : -1.0;
+        xi[u] = corner(qp, 0) * g;
+        xi[v] = corner(qp, 1) * g;
+        double fb[8], df[8][3], J[3][3];
+        basis(xi, fb, df);
+        jacobian(X, df, J);
+        double tu[3] = { J[0][u], J[1][u], J[2][u] }, tv[3] = { J[0][v], J[1][v], J[2][v] };
+        double N[3] = { sgn * (tu[1] * tv[2] - tu[2] * tv[1]),
+                        sgn * (tu[2] * tv[0] - tu[0] * tv[2]),
+                        sgn * (tu[0] * tv[1] - tu[1] * tv[0]) };
+        for (int a = 0; a < 3; ++a) {
+            A[a] += N[a];
+            for (int k = 0; k < 4; ++k)
+                for (int l = 0; l < 4; ++l) F[a][4 * k + l] += N[a] * fb[fn[k]] * fb[fn[l]];
+        }
+    }
+}
+
+static int build_geometry(snxo_problem *p) {
+    int C = p->ncell;
+    for (int K = 0; K < C; ++K) {
+        int rc = cell_volume_matrices(p, K);
+        if (rc) return rc;
+    }
+    /* Each interior face is integrated once, on the side with the smaller
+     * (cell, face) index; the other side takes the negated values at the
+     * matching nodes so the two sides cancel exactly. */
+    for (int K = 0; K < C; ++K)
+        for (int f = 0; f < 6; ++f) {
+            int N = p->nbr[6 * K + f], g = p->nbrf[6 * K + f];
+            if (N >= 0 && 6L * N + g < 6L * K + f) continue;
+            double F[3][16], A[3];
+            face_matrices(p, K, f, F, A);
+            double *FK = p->F + 288L * K + 48 * f, *AK = p->area + 18L * K + 3 * f;
+            memcpy(FK, F, sizeof F);
+            memcpy(AK, A, sizeof A);
+            if (N < 0) continue;
+            int fnN[4], pos[4];
+            face_nodes(g, fnN);
+            for (int k = 0; k < 4; ++k) {
+                pos[k] = -1;
+                for (int m = 0; m < 4; ++m)
+                    if (fnN[m] == p->perm[24 * K + 4 * f + k]) pos[k] = m;
+                if (pos[k] < 0) return fail(p, SNXO_E_MESH, "neighbour node not on matched face");
+            }
+            double *FN = p->F + 288L * N + 48 * g, *AN = p->area + 18L * N + 3 * g;
+            for (int a = 0; a < 3; ++a) {
+                AN[a] = -A[a];
+                for (int k = 0; k < 4; ++k)
+                    for (int l = 0; l < 4; ++l) FN[16 * a + 4 * pos[k] + pos[l]] = -F[a][4 * k + l];
+            }
+        }
+    return SNXO_OK;
+}
+
+/* ------------------------------------------------- designation and levels */
+
+/* Face f of K is inflow for octant o when s_o . A_f < 0 (one designation per
+ * octant); Kahn's algorithm gives a topological order and the t-levels. */
+static int build_dag(snxo_problem *p) {
+    int C = p->ncell;
+    int32_t *indeg = malloc(sizeof(int32_t) * C), *queue = malloc(sizeof(int32_t) * C);
+    if (!indeg || !queue) { free(indeg); free(queue); return fail(p, SNXO_E_OOM, "out of memory"); }
+    for (int o = 0; o < 8; ++o) {
+        double s[3];
+        octant_signs(o, s);
+        int32_t *in = p->inflow + (long)o * C, *lev = p->level + (long)o * C, *ord = p->order + (long)o * C;
+        for (int K = 0; K < C; ++K) {
+            int mask = 0;
+            indeg[K] = 0;
+            for (int f = 0; f < 6; ++f) {
+                const double *A = p->area + 18L * K + 3 * f;
+                double d = s[0] * A[0] + s[1] * A[1] + s[2] * A[2];
+                if (d == 0.0) { free(indeg); free(queue); return fail(p, SNXO_E_MESH, "face tangent to an octant diagonal"); }
+                if (d < 0.0) {
+                    mask |= 1 << f;
+                    if (p->nbr[6 * K + f] >= 0) indeg[K]++;
+                }
+            }
+            in[K] = mask;
+            lev[K] = 0;
+        }
+        int head = 0, tail = 0;
+        for (int K = 0; K < C; ++K)
+            if (indeg[K] == 0) queue[tail++] = K;
+        while (head < tail) {
+            int K = queue[head++];
+            ord[head - 1] = K;
+            for (int f = 0; f < 6; ++f) {
+                int N = p->nbr[6 * K + f];
+                if (N < 0 || (in[K] >> f) & 1) continue;
+                if (lev[N] < lev[K] + 1) lev[N] = lev[K] + 1;
+                if (--indeg[N] == 0) queue[tail++] = N;
+            }
+        }
+        if (tail != C) { free(indeg); free(queue); return fail(p, SNXO_E_CYCLE, "upwind graph has a cycle"); }
+    }
+    free(indeg); free(queue);
+    return SNXO_OK;
+}
+
+int snxo_setup(snxo_problem *p) {
+    if (!p || !p->cv || !p->omega || !p->sigt) return fail(p, SNXO_E_STATE, "mesh, quadrature and materials must be set");
+    free_derived(p);
+    size_t C = (size_t)p->ncell;
+    p->M = malloc(sizeof(double) * 64 * C);
+    p->S = malloc(sizeof(double) * 192 * C);
+    p->F = calloc(288 * C, sizeof(double));
+    p->area = calloc(18 * C, sizeof(double));
+    p->nbr = malloc(sizeof(int32_t) * 6 * C);
+    p->nbrf = malloc(sizeof(int32_t) * 6 * C);
+    p->perm = malloc(sizeof(int32_t) * 24 * C);
+    p->inflow = malloc(sizeof(int32_t) * 8 * C);
+    p->level = malloc(sizeof(int32_t) * 8 * C);
+    p->order = malloc(sizeof(int32_t) * 8 * C);
+    if (!p->M || !p->S || !p->F || !p->area || !p->nbr || !p->nbrf || !p->perm || !p->inflow || !p->level || !p->order) {
+        free_derived(p);
+        return fail(p, SNXO_E_OOM, "out of memory");
+    }
+    int rc = build_topology(p);
+    if (!rc) rc = build_geometry(p);
+    if (!rc) rc = build_dag(p);
+    if (rc) { free_derived(p); return rc; }
+    p->ready = 1;
+    return SNXO_OK;
+}
+
+/* ------------------------------------------------------------------ sweep */
+
+/* One (cell, angle, group) local system of the upwind DG form:
+ *   A = sum_a Om_a S^a + sigma_t M - sum_{f in} sum_a Om_a F^a_f
+ *   b = M q - sum_{f in} (Om . F_f) psi_up_f
+ * with q the nodal source values and psi_up the upwind trace at f's nodes. */
+static int solve_local(const snxo_problem *p, int K, int n, int g, const double *qnodal,
+                       const double *psi_cur /*[C][8] this angle and group*/, double x[8],
+                       double *leak_out) {
+    const double *om = p->omega + 3 * n;
+    const double *M = p->M + 64L * K, *S = p->S + 192L * K;
+    int o = n / (p->nang / 8);
+    int mask = p->inflow[(long)o * p->ncell + K];
+    double sigt = p->sigt[(long)K * p->G + g];
+    double A[64], b[8], up[6][4];
+    for (int i = 0; i < 8; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < 8; ++j) {
+            A[8 * i + j] = om[0] * S[8 * i + j] + om[1] * S[64 + 8 * i + j] + om[2] * S[128 + 8 * i + j]
+                         + sigt * M[8 * i + j];
+            s += M[8 * i + j] * qnodal[j];
+        }
+        b[i] = s;
+    }
+    for (int f = 0; f < 6; ++f) {
+        if (!((mask >> f) & 1)) continue;
+        int fn[4];
+        face_nodes(f, fn);
+        const double *F = p->F + 288L * K + 48 * f;
+        int N = p->nbr[6 * K + f];
+        for (int l = 0; l < 4; ++l) {
+            if (N >= 0) up[f][l] = psi_cur[8L * N + p->perm[24 * K + 4 * f + l]];
+            else if (p->bnd_in) up[f][l] = p->bnd_in[((((long)K * 6 + f) * p->nang + n) * p->G + g) * 4 + l];
+            else if (p->bkind == 1) up[f][l] = p->psib[g];
+            else up[f][l] = 0.0;
+        }
+        for (int k = 0; k < 4; ++k) {
+            double s = 0.0;
+            for (int l = 0; l < 4; ++l) {
+                double of = om[0] * F[4 * k + l] + om[1] * F[16 + 4 * k + l] + om[2] * F[32 + 4 * k + l];
+                A[8 * fn[k] + fn[l]] -= of;
+                s += of * up[f][l];
+            }
+            b[fn[k]] -= s;
+        }
+    }
+    if (lu_solve(8, A, b, x)) return -1;
+    if (leak_out) {
+        /* net outflow through the upwind traces: own values on outflow faces,
+         * upwind values on inflow faces */
+        double L = 0.0;
+        for (int f = 0; f < 6; ++f) {
+            int fn[4];
+            face_nodes(f, fn);
+            const double *F = p->F + 288L * K + 48 * f;
+            int in = (mask >> f) & 1;
+            for (int k = 0; k < 4; ++k)
+                for (int l = 0; l < 4; ++l) {
+                    double of = om[0] * F[4 * k + l] + om[1] * F[16 + 4 * k + l] + om[2] * F[32 + 4 * k + l];
+                    L += of * (in ? up[f][l] : x[fn[l]]);
+                }
+        }
+        *leak_out = L;
+    }
+    return 0;
+}
+
+int snxo_sweep(snxo_problem *p, const double *phi_in, double *phi_out,
+               double *psi_all, double *leak, double *leak_ang) {
+    if (!p || !p->ready) return fail(p, SNXO_E_STATE, "setup has not run");
+    if (!phi_out) return fail(p, SNXO_E_ARG, "phi_out is NULL");
+    int C = p->ncell, G = p->G, nang = p->nang, per = nang / 8;
+    memset(phi_out, 0, sizeof(double) * 8 * (size_t)C * G);
+    if (leak) memset(leak, 0, sizeof(double) * (size_t)C * G);
+    int bad = 0;
+    /* Groups are independent: each group's angle sum runs sequentially over
+     * (octant, angle) so the result does not depend on the thread count. */
+    #pragma omp parallel for schedule(dynamic, 1) reduction(|:bad)
+    for (int g = 0; g < G; ++g) {
+        double *psi_cur = malloc(sizeof(double) * 8 * (size_t)C);
+        if (!psi_cur) { bad = 1; continue; }
+        for (int o = 0; o < 8; ++o)
+            for (int a = 0; a < per; ++a) {
+                int n = o * per + a;
+                for (int t = 0; t < C; ++t) {
+                    int K = p->order[(long)o * C + t];
+                    double qn[8], x[8], L = 0.0;
+                    if (p->ang_src) {
+                        for (int j = 0; j < 8; ++j) qn[j] = p->ang_src[(((long)K * nang + n) * G + g) * 8 + j];
+                    } else {
+                        for (int j = 0; j < 8; ++j) {
+                            double ph = phi_in ? phi_in[((long)K * G + g) * 8 + j] : 0.0;
+                            qn[j] = (p->q[(long)K * G + g] + p->sigs[(long)K * G + g] * ph) / (4.0 * PI);
+                        }
+                    }
+                    if (solve_local(p, K, n, g, qn, psi_cur, x, (leak || leak_ang) ? &L : NULL)) { bad = 1; break; }
+                    for (int j = 0; j < 8; ++j) {
+                        psi_cur[8L * K + j] = x[j];
+                        phi_out[((long)K * G + g) * 8 + j] += p->w[n] * x[j];
+                        if (psi_all) psi_all[(((long)n * C + K) * G + g) * 8 + j] = x[j];
+                    }
+                    if (leak) leak[(long)K * G + g] += p->w[n] * L;
+                    if (leak_ang) leak_ang[((long)n * C + K) * G + g] = L;
+                }
+            }
+        free(psi_cur);
+    }
+    if (bad) return fail(p, SNXO_E_MESH, "singular local system or out of memory");
+    return SNXO_OK;
+}
+
+/* Relative max-norm change ||phi_new - phi_old||_inf / ||phi_new||_inf. */
+static double rel_change(const double *a, const double *b, size_t n) {
+    double num = 0.0, den = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        double d = fabs(a[i] - b[i]);
+        if (d > num) num = d;
+        if (fabs(a[i]) > den) den = fabs(a[i]);
+    }
+    return den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
+}
+
+int snxo_solve(snxo_problem *p, double tol, int max_it, const double *phi0,
+               double *phi_out, int *iters, double *eps, double *hist) {
+    if (!p || !p->ready) return fail(p, SNXO_E_STATE, "setup has not run");
+    if (!phi_out || max_it < 1) return fail(p, SNXO_E_ARG, "bad solve arguments");
+    size_t n = 8 * (size_t)p->ncell * p->G;
+    double *cur = malloc(sizeof(double) * n);
+    if (!cur) return fail(p, SNXO_E_OOM, "out of memory");
+    if (phi0) memcpy(cur, phi0, sizeof(double) * n); else memset(cur, 0, sizeof(double) * n);
+    int it = 0, rc = SNXO_OK;
+    double e = INFINITY;
+    while (it < max_it) {
+        rc = snxo_sweep(p, cur, phi_out, NULL, NULL, NULL);
+        if (rc) break;
+        e = rel_change(phi_out, cur, n);
+        if (hist) hist[it] = e;
+        ++it;
+        memcpy(cur, phi_out, sizeof(double) * n);
+        if (e <= tol) break;
+    }
+    free(cur);
+    if (iters) *iters = it;
+    if (eps) *eps = e;
+    if (rc) return rc;
+    return e <= tol ? SNXO_OK : SNXO_E_NOCONV;
+}
+
+/* Cell balance of one sweep: source 1^T M (Q + sigma_s phi_in) equals
+ * absorption sigma_t 1^T M phi_out plus angle-weighted net outflow. */
+int snxo_balance(snxo_problem *p, const double *phi_in, const double *phi_out,
+                 const double *leak, double *out) {
+    if (!p || !p->ready) return fail(p, SNXO_E_STATE, "setup has not run");
+    if (!phi_out || !leak || !out) return fail(p, SNXO_E_ARG, "bad balance arguments");
+    int C = p->ncell, G = p->G;
+    for (int g = 0; g < G; ++g) {
+        double src = 0.0, ab = 0.0, lk = 0.0, worst = 0.0;
+        for (int K = 0; K < C; ++K) {
+            const double *M = p->M + 64L * K;
+            double s = 0.0, a = 0.0;
+            for (int i = 0; i < 8; ++i)
+                for (int j = 0; j < 8; ++j) {
+                    double ph = phi_in ? phi_in[((long)K * G + g) * 8 + j] : 0.0;
+                    s += M[8 * i + j] * (p->q[(long)K * G + g] + p->sigs[(long)K * G + g] * ph);
+                    a += M[8 * i + j] * p->sigt[(long)K * G + g] * phi_out[((long)K * G + g) * 8 + j];
+                }
+            double l = leak[(long)K * G + g];
+            double scale = fmax(fabs(s), fmax(fabs(a), fabs(l)));
+            double rel = scale > 0.0 ? fabs(s - a - l) / scale : 0.0;
+            if (rel > worst) worst = rel;
+            src += s; ab += a; lk += l;
+        }
+        out[4 * g + 0] = src; out[4 * g + 1] = ab; out[4 * g + 2] = lk; out[4 * g + 3] = worst;
+    }
+    return SNXO_OK;
+}
+
+int snxo_integrated_flux(snxo_problem *p, const double *phi, double *out) {
+    if (!p || !p->ready || !phi || !out) return fail(p, SNXO_E_ARG, "bad arguments");
+    int C = p->ncell, G = p->G;
+    for (int g = 0; g < G; ++g) {
+        double s = 0.0, v = 0.0;
+        for (int K = 0; K < C; ++K) {
+            const double *M = p->M + 64L * K;
+            for (int i = 0; i < 8; ++i) {
+                s += phi[((long)K * G + g) * 8 + i];
+                for (int j = 0; j < 8; ++j) v += M[8 * i + j] * phi[((long)K * G + g) * 8 + j];
+            }
+        }
+        out[2 * g] = s; out[2 * g + 1] = v;
+    }
+    return SNXO_OK;
+}
+
+int snxo_get_geometry(snxo_problem *p, double *M, double *S, double *F, double *area,
+                      int32_t *nbr, int32_t *nbr_face, int32_t *perm) {
+    if (!p || !p->ready) return fail(p, SNXO_E_STATE, "setup has not run");
+    size_t C = (size_t)p->ncell;
+    if (M) memcpy(M, p->M, sizeof(double) * 64 * C);
+    if (S) memcpy(S, p->S, sizeof(double) * 192 * C);
+    if (F) memcpy(F, p->F, sizeof(double) * 288 * C);
+    if (area) memcpy(area, p->area, sizeof(double) * 18 * C);
+    if (nbr) memcpy(nbr, p->nbr, sizeof(int32_t) * 6 * C);
+    if (nbr_face) memcpy(nbr_face, p->nbrf, sizeof(int32_t) * 6 * C);
+    if (perm) memcpy(perm, p->perm, sizeof(int32_t) * 24 * C);
+    return SNXO_OK;
+}
+
+int snxo_get_dag(snxo_problem *p, int32_t *inflow, int32_t *level, int32_t *order) {
+    if (!p || !p->ready) return fail(p, SNXO_E_STATE, "setup has not run");
+    size_t C = (size_t)p->ncell;
+    if (inflow) memcpy(inflow, p->inflow, sizeof(int32_t) * 8 * C);
+    if (level) memcpy(level, p->level, sizeof(int32_t) * 8 * C);
+    if (order) memcpy(order, p->order, sizeof(int32_t) * 8 * C);
+    return SNXO_OK;
+}

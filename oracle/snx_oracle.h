@@ -1,0 +1,109 @@
+/*
+ * snx_oracle.h -- plain, slow FP64 CPU reference for the unstructured S_N sweep.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may include, link
+ * or call this code; it exists so that tests, the smoke check and the CPU
+ * baseline of the benchmark can compare the GPU library against an obviously
+ * correct implementation written straight from the method's definition:
+ *
+ *   - steady linear Boltzmann transport, Eq. 1, with a fixed isotropic source,
+ *     within-group isotropic scattering, vacuum or isotropic-inflow boundaries;
+ *   - S_N discrete ordinates grouped by octant (Section 2) with a product
+ *     quadrature; scalar flux phi = sum_n w_n psi_n (Eq. 2);
+ *   - first-order (trilinear) discontinuous Galerkin on hexahedra, one 8x8
+ *     "assemble + solve" per (cell, angle, group) using the element arrays of
+ *     Table 1 (mass, stiffness, face normals, face nodes, neighbours);
+ *   - the sweep: cells visited in a topological order of the upwind
+ *     dependency DAG (Section 2.1), octant by octant, angle by angle;
+ *   - source iteration, and the integrated flux of Eq. 3.
+ *
+ * All arithmetic is double precision; local systems use LU with partial
+ * pivoting.  Every reading of a point the paper leaves open (node ordering,
+ * quadrature set, normalisation, upwind designation, convergence norm) is
+ * listed in the repository's design notes.
+ *
+ * Layouts (row-major C arrays, all host memory, owned by the caller unless
+ * stated): xyz[nvert][3]; cell_vert[ncell][8] with local vertex j = a+2b+4c at
+ * reference corner (2a-1, 2b-1, 2c-1); omega[nang][3]; w[nang];
+ * sigma_t, sigma_s, q: [ncell][G]; phi: [ncell][G][8].
+ */
+#ifndef SNX_ORACLE_H
+#define SNX_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SNXO_OK = 0,
+    SNXO_E_ARG = -1,
+    SNXO_E_STATE = -2,
+    SNXO_E_MESH = -3,
+    SNXO_E_CYCLE = -4,
+    SNXO_E_OOM = -6,
+    SNXO_E_NOCONV = -7
+};
+
+typedef struct snxo_problem snxo_problem;
+
+/* n-point Gauss-Legendre rule on [-1,1], nodes ascending. */
+int snxo_gauss_legendre(int n, double *x, double *w);
+
+/* Product quadrature: npolar positive nodes of the 2*npolar-point
+ * Gauss-Legendre rule in mu = Omega_z, nazim equal azimuths per octant.
+ * Fills omega[8*npolar*nazim][3], w[8*npolar*nazim]; sum w = 4 pi.
+ * Octant o = 4[Oz<0] + 2[Oy<0] + [Ox<0]; within an octant polar-major. */
+int snxo_quadrature(int npolar, int nazim, double *omega, double *w);
+
+int  snxo_create(snxo_problem **out);
+void snxo_destroy(snxo_problem *p);
+int  snxo_set_mesh(snxo_problem *p, int ncell, int nvert, const double *xyz, const int32_t *cell_vert);
+int  snxo_set_quadrature(snxo_problem *p, int nang, const double *omega, const double *w);
+int  snxo_set_materials(snxo_problem *p, int ngroup, const double *sigma_t,
+                        const double *sigma_s, const double *q);
+/* kind 0 = vacuum, 1 = isotropic inflow psi_b[g] on every inflow boundary face. */
+int  snxo_set_boundary(snxo_problem *p, int kind, const double *psi_b);
+/* Test hooks (may be NULL to clear).  ang_src[ncell][nang][G][8]: nodal values
+ * of an angle-dependent source replacing (Q + sigma_s phi)/(4 pi).
+ * bnd_in[ncell][6][nang][G][4]: nodal inflow values on boundary faces. */
+int  snxo_set_hooks(snxo_problem *p, const double *ang_src, const double *bnd_in);
+/* Topology, geometry, upwind designation and levelling. */
+int  snxo_setup(snxo_problem *p);
+
+/* One source iteration: phi_out = sum_n w_n psi_n where psi solves the sweep
+ * with scattering source from phi_in.  Optional outputs (NULL to skip):
+ * psi_all[nang][ncell][G][8], leak[ncell][G] (angle-weighted net outflow),
+ * leak_ang[nang][ncell][G] (per-angle net outflow). */
+int  snxo_sweep(snxo_problem *p, const double *phi_in, double *phi_out,
+                double *psi_all, double *leak, double *leak_ang);
+
+/* Source iteration from phi0 (NULL = zero) until the relative max-norm change
+ * is <= tol or max_it sweeps.  hist[max_it] (nullable) receives each change. */
+int  snxo_solve(snxo_problem *p, double tol, int max_it, const double *phi0,
+                double *phi_out, int *iters, double *eps, double *hist);
+
+/* Particle balance of one sweep phi_in -> phi_out with its leak[ncell][G]:
+ * out[G][4] = source, absorption, leakage, max cell relative imbalance. */
+int  snxo_balance(snxo_problem *p, const double *phi_in, const double *phi_out,
+                  const double *leak, double *out);
+
+/* Integrated flux (Eq. 3): per group the sum over cells and dofs of phi, and
+ * the volume integral 1^T M phi; out[G][2]. */
+int  snxo_integrated_flux(snxo_problem *p, const double *phi, double *out);
+
+/* Exports for tests.  M[ncell][64], S[ncell][3][64], F[ncell][6][3][16],
+ * area[ncell][6][3], nbr[ncell][6] (-1 boundary), nbr_face[ncell][6],
+ * perm[ncell][6][4] (neighbour local vertex at each of my face nodes). */
+int  snxo_get_geometry(snxo_problem *p, double *M, double *S, double *F, double *area,
+                       int32_t *nbr, int32_t *nbr_face, int32_t *perm);
+/* inflow[8][ncell] bit f set when face f is inflow; level[8][ncell];
+ * order[8][ncell] the topological order used by the sweep. */
+int  snxo_get_dag(snxo_problem *p, int32_t *inflow, int32_t *level, int32_t *order);
+const char *snxo_last_error(snxo_problem *p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,86 @@
+"""Shared test helpers: special meshes and dense reference systems.
+
+The dense systems here are assembled from element matrices handed out by the
+code under test; they check the sweep's ordering, upwinding and face coupling
+with a different algorithm (one global dense solve instead of a sweep in
+topological order with local solves).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_2510_11513_amd import inputs
+
+FOUR_PI = 4.0 * np.pi
+
+
+def face_nodes(f):
+    axis, side = divmod(f, 2)
+    return [j for j in range(8) if ((j >> axis) & 1) == side]
+
+
+def affine_mesh(n, L, t=(0.0, 0.0, 0.0), seed=0, permute=True):
+    """Unjittered n^3 grid mapped by x -> L x + t (every cell a parallelepiped)."""
+    m = inputs.make_mesh(n, 0.0, seed=seed, permute=permute)
+    m.xyz = np.ascontiguousarray(m.xyz @ np.asarray(L, float).T + np.asarray(t, float))
+    return m
+
+
+def ref_1d():
+    """1D linear Lagrange basis on [-1, 1]: mass and f_a * f_b' integrals."""
+    m = np.array([[2.0, 1.0], [1.0, 2.0]]) / 3.0
+    d = np.array([[-0.5, 0.5], [-0.5, 0.5]])
+    return m, d
+
+
+def kron3(ax, ay, az):
+    """Tensor operator for local index j = a + 2b + 4c (a fastest)."""
+    return np.kron(az, np.kron(ay, ax))
+
+
+def dense_angle_matrix(geo, dag, omega, n, nang, sigt_g):
+    """Global matrix of one angle's upwind DG system (interior coupling only)."""
+    C = geo["M"].shape[0]
+    o = n // (nang // 8)
+    om = omega[n]
+    Gm = np.zeros((8 * C, 8 * C))
+    for K in range(C):
+        A = np.einsum("a,aij->ij", om, geo["S"][K]) + sigt_g[K] * geo["M"][K]
+        Gm[8 * K:8 * K + 8, 8 * K:8 * K + 8] += A
+        mask = dag["inflow"][o, K]
+        for f in range(6):
+            if not (mask >> f) & 1:
+                continue
+            fn = face_nodes(f)
+            OF = np.einsum("a,akl->kl", om, geo["F"][K, f])
+            N = geo["nbr"][K, f]
+            for k in range(4):
+                for l in range(4):
+                    Gm[8 * K + fn[k], 8 * K + fn[l]] -= OF[k, l]
+                    if N >= 0:
+                        Gm[8 * K + fn[k], 8 * N + geo["perm"][K, f, l]] += OF[k, l]
+    return Gm
+
+
+def boundary_rhs(geo, dag, omega, n, nang, psi_b):
+    """-(Omega.F) psi_b on inflow boundary faces for a constant inflow psi_b."""
+    C = geo["M"].shape[0]
+    o = n // (nang // 8)
+    om = omega[n]
+    rhs = np.zeros(8 * C)
+    for K in range(C):
+        mask = dag["inflow"][o, K]
+        for f in range(6):
+            if (mask >> f) & 1 and geo["nbr"][K, f] < 0:
+                fn = face_nodes(f)
+                OF = np.einsum("a,akl->kl", om, geo["F"][K, f])
+                for k in range(4):
+                    rhs[8 * K + fn[k]] -= OF[k].sum() * psi_b
+    return rhs
+
+
+def rel_err_per_group(a, b):
+    """max |a-b| / max |b| for each group of phi[ncell][G][8]."""
+    num = np.abs(a - b).max(axis=(0, 2))
+    den = np.abs(b).max(axis=(0, 2))
+    return num / np.where(den > 0, den, 1.0)
