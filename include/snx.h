@@ -1,0 +1,154 @@
+/*
+ * snx.h -- C ABI of the MI355X (gfx950) unstructured S_N transport sweep.
+ *
+ * The library solves steady, fixed-source, multigroup linear Boltzmann
+ * transport (Eq. 1 of "An Asynchronous Many-Task Algorithm for Unstructured
+ * S_N Transport on Shared Memory Systems") with within-group isotropic
+ * scattering and no group coupling, on unstructured hexahedral meshes,
+ * discretised by S_N discrete ordinates grouped in octants (Section 2) and
+ * first-order discontinuous Galerkin finite elements (one 8x8 "assemble and
+ * solve" per cell, angle and group; Table 1 lists the element arrays).  One
+ * source iteration is a sweep over the upwind dependency DAG of every
+ * direction (Section 2.1) followed by the angle reduction phi = sum_n w_n
+ * psi_n (Eq. 2); the GPU sweep schedules (cell, octant) tasks from a device
+ * queue fed by atomic dependency counters, the GPU form of the work-first
+ * many-task sweep of Algorithm 1 (Section 3).
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns snx_status; the library never throws across the ABI.
+ *     On failure snx_last_error() describes the cause.
+ *   - "host" pointers are read during the call only (the library copies
+ *     them); "device" pointers are caller-owned device memory on the
+ *     problem's device and must stay valid until the work enqueued on the
+ *     given stream has completed.
+ *   - stream is a hipStream_t (NULL = the default stream).
+ *   - Scalar flux layout (exchange format): phi[ncell][G][8] float32, cell
+ *     ids as given to snx_set_mesh, local dof j = vertex j of the cell.
+ *   - Local vertex j = a + 2b + 4c of a cell is the reference corner
+ *     (2a-1, 2b-1, 2c-1) of [-1,1]^3; face f = 2*axis + side holds the
+ *     vertices whose bit `axis` equals side.
+ *   - Directions: omega[nang][3], unit vectors grouped by octant
+ *     o = 4[Oz<0] + 2[Oy<0] + [Ox<0], the same count in every octant;
+ *     weights w[nang] sum to 4 pi; phi = sum_n w_n psi_n.
+ *   - A problem object is used by one host thread at a time; distinct
+ *     problems are independent.
+ */
+#ifndef SNX_H
+#define SNX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t snx_status;
+#define SNX_OK        0
+#define SNX_E_ARG    (-1)  /* invalid argument (NULL, size out of range)            */
+#define SNX_E_STATE  (-2)  /* call out of order (e.g. sweep before setup)           */
+#define SNX_E_MESH   (-3)  /* non-conforming face, detJ <= 0, face on an octant diagonal */
+#define SNX_E_CYCLE  (-4)  /* the upwind graph of some octant has a cycle           */
+#define SNX_E_DEVICE (-5)  /* HIP runtime error or sweep watchdog expiry            */
+#define SNX_E_OOM    (-6)  /* device or host allocation failed                      */
+#define SNX_E_NOCONV (-7)  /* max_it reached; info and phi still filled             */
+
+typedef struct snx_problem snx_problem;
+typedef struct snx_batch snx_batch;
+
+typedef struct snx_solve_info {
+    int32_t iterations;      /* sweeps performed                                   */
+    int32_t status;          /* SNX_OK or SNX_E_NOCONV                             */
+    double  residual;        /* last ||phi_l+1 - phi_l||_inf / ||phi_l+1||_inf (FP64) */
+    double  wall_ms;         /* host wall time of the solve                        */
+    double  solves_per_s;    /* cell-angle-group solves per second over the solve  */
+} snx_solve_info;
+
+/* Create a problem bound to HIP device `device`.  *out receives the handle. */
+snx_status snx_create(snx_problem **out, int32_t device);
+/* Free the problem and every device buffer it owns.  NULL is ignored. */
+void snx_destroy(snx_problem *p);
+/* Last error message of p (or of the most recent failed snx_create if p is NULL). */
+const char *snx_last_error(const snx_problem *p);
+
+/* Mesh of hexahedra: host xyz[nvert][3] (float64), host cell_vert[ncell][8]
+ * (int32 vertex ids, local vertex convention above).  Faces are matched by
+ * their vertex sets (Table 1: face_nodes, elem_neighbors); unmatched faces are
+ * boundary faces.  Invalidates a previous setup.  Errors: SNX_E_ARG. */
+snx_status snx_set_mesh(snx_problem *p, int64_t ncell, int64_t nvert,
+                        const double *xyz, const int32_t *cell_vert);
+
+/* Angular quadrature (Section 2: S_N directions grouped by octant): host
+ * omega[nang][3], host w[nang].  nang must be a positive multiple of 8 with
+ * nang/8 <= 64.  Errors: SNX_E_ARG (not grouped by octant, zero component). */
+snx_status snx_set_quadrature(snx_problem *p, int32_t nang, const double *omega, const double *w);
+
+/* Product quadrature helper (no problem needed): the npolar positive nodes of
+ * the 2*npolar-point Gauss-Legendre rule in mu = Omega_z times nazim equal
+ * azimuths (k + 1/2) (pi/2) / nazim per octant, weight w_mu * pi / (2 nazim);
+ * octant-major, then polar-major.  Host omega[8*npolar*nazim][3] and
+ * w[8*npolar*nazim] are written.  Errors: SNX_E_ARG. */
+snx_status snx_quadrature_product(int32_t npolar, int32_t nazim, double *omega, double *w);
+
+/* Per-cell per-group data (Eq. 1 cross sections and fixed source): host
+ * sigma_t, sigma_s, q, each [ncell][G] float64; q is the isotropic source
+ * density, the angular source being q / (4 pi).  1 <= G <= 256, set after
+ * the mesh.  Errors: SNX_E_ARG, SNX_E_STATE. */
+snx_status snx_set_materials(snx_problem *p, int32_t ngroup, const double *sigma_t,
+                             const double *sigma_s, const double *q);
+
+/* Boundary condition on inflow boundary faces: kind 0 = vacuum (default),
+ * kind 1 = isotropic inflow psi_in[G] (host float64). */
+snx_status snx_set_boundary(snx_problem *p, int32_t kind, const double *psi_in);
+
+/* Build everything one mesh needs, on the device: face matching, element
+ * matrices (FP64 integration, FP32 storage), per-octant upwind designation
+ * (face f of cell K is inflow for octant o when s_o . A_f < 0, A_f the face's
+ * outward area vector), DAG levelling and dependency counters.  Synchronous.
+ * Errors: SNX_E_STATE (inputs missing), SNX_E_MESH, SNX_E_CYCLE, SNX_E_OOM,
+ * SNX_E_DEVICE. */
+snx_status snx_setup(snx_problem *p, void *stream);
+
+/* One source iteration: the scattering source from device phi_in
+ * (NULL = zero flux), one full sweep of all octants, angles and groups, and
+ * the compensated angle reduction into device phi_out (Eq. 2).  phi_in and
+ * phi_out may not alias.  Asynchronous on stream.  Errors: SNX_E_STATE,
+ * SNX_E_ARG; device faults surface at the next synchronising call. */
+snx_status snx_sweep(snx_problem *p, const float *phi_in, float *phi_out, void *stream);
+
+/* Source iteration from device phi0 (NULL = zero start) until the FP64
+ * relative max-norm change is <= tol or max_it sweeps; the final iterate is
+ * written to device phi.  info (host, nullable) is filled.  Synchronous.
+ * Returns SNX_E_NOCONV when max_it is reached first (phi and info filled),
+ * SNX_E_DEVICE on a watchdog expiry. */
+snx_status snx_solve(snx_problem *p, double tol, int32_t max_it, const float *phi0,
+                     float *phi, snx_solve_info *info, void *stream);
+
+/* Particle balance (FP64) of the most recent sweep, which must have started
+ * from device phi_in (NULL = zero) and produced device phi_out.  host out[G][4]
+ * = total source, absorption, net leakage, and the largest per-cell relative
+ * imbalance |src - abs - leak| / max(|src|, |abs|, |leak|).  Synchronous. */
+snx_status snx_balance(snx_problem *p, const float *phi_in, const float *phi_out,
+                       double *out, void *stream);
+
+/* Integrated flux of Eq. 3 per group, FP64: host out[G][2] = (sum of phi over
+ * cells and dofs, volume integral 1^T M phi).  Synchronous. */
+snx_status snx_integrated_flux(snx_problem *p, const float *phi, double *out, void *stream);
+
+/* Level structure from setup: host level[8][ncell] (t-level of each cell per
+ * octant) and host nlevels[8]; either may be NULL.  Synchronous. */
+snx_status snx_get_levels(snx_problem *p, int32_t *level, int32_t *nlevels);
+
+/* Sweep schedule knobs: threads per task workgroup (64..1024, multiple of
+ * 64, at least G), resident workgroups per CU (0 = occupancy maximum) and
+ * the graph chunk length of snx_solve (iterations per host check).
+ * Any argument <= 0 keeps the current value. */
+snx_status snx_set_schedule(snx_problem *p, int32_t threads, int32_t wg_per_cu, int32_t chunk);
+
+/* Statistics of the most recent sweep, host out[4]: tasks executed, queue
+ * polls that found no ready task, watchdog flag, reserved.  Synchronous. */
+snx_status snx_sweep_stats(snx_problem *p, int64_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,76 @@
+"""Builds libsnx.so (gfx950) in-tree with hipcc.
+
+    python -m paper_2510_11513_amd.build
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+LIB = os.path.join(PKG, "libsnx.so")
+ARCH = "gfx950"
+
+SOURCES = ["api.hip", "k_geometry.hip", "k_dag.hip", "k_sweep.hip", "k_reduce.hip", "host.cpp"]
+
+HIP_FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    # packed FP32 instructions stay disabled in all device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-command-line-argument", "-Wno-unused-function",
+]
+
+
+def hipcc() -> str:
+    for c in ("/opt/rocm/bin/hipcc", "hipcc"):
+        if os.path.exists(c) or c == "hipcc":
+            return c
+    raise RuntimeError("hipcc not found")
+
+
+def build(verbose: bool = False, jobs: int = 6) -> str:
+    """Compiles every source to an object in parallel, then links the shared library."""
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    procs, objs = [], []
+    for src in SOURCES:
+        obj = os.path.join(objdir, src.rsplit(".", 1)[0] + ".o")
+        objs.append(obj)
+        lang = ["-x", "hip"]
+        cmd = [hipcc(), *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *lang, "-c",
+               os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        if len(procs) >= jobs:
+            _wait(procs.pop(0))
+    for pr in procs:
+        _wait(pr)
+    tmp = LIB + f".tmp{os.getpid()}"
+    link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    if verbose:
+        print(" ".join(link), flush=True)
+    out = subprocess.run(link, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if out.returncode:
+        raise RuntimeError("link failed:\n" + out.stdout.decode())
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def _wait(item):
+    src, pr = item
+    out, _ = pr.communicate()
+    text = out.decode()
+    if pr.returncode:
+        raise RuntimeError(f"compiling {src} failed:\n{text}")
+    warn = [l for l in text.splitlines() if "warning" in l and "packed-fp32-ops" not in l
+            and "argument unused" not in l]
+    if warn:
+        sys.stderr.write(f"[{src}]\n" + "\n".join(warn) + "\n")
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

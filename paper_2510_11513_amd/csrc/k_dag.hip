@@ -1,0 +1,102 @@
+// Per-octant upwind designation and topological levelling on the device.
+//
+// The sweep of one direction visits cells after all their upwind neighbours
+// (Section 2.1: the dependencies form a DAG; UnSNAP groups cells into t-level
+// "buckets" and merges the buckets of all angles of an octant).  Here one
+// designation serves a whole octant: face f of cell K is inflow for octant o
+// when s_o . A_f < 0, with s_o the octant's sign vector and A_f the outward
+// area vector.  A_f is antisymmetric across interior faces, so exactly one
+// side of every face is upwind.  One workgroup per octant peels the DAG level
+// by level: level(K) = 1 + max level of its upwind neighbours.
+#include "snx_internal.h"
+
+namespace snx {
+namespace {
+
+constexpr int kDagThreads = 1024;
+
+__global__ __launch_bounds__(kDagThreads) void k_dag(int C, const int *__restrict__ nbr,
+                                                     const double *__restrict__ area,
+                                                     unsigned char *__restrict__ inmask, int *__restrict__ indeg,
+                                                     int *__restrict__ level, int *__restrict__ hist,
+                                                     int *__restrict__ nlev, int *__restrict__ seeds,
+                                                     int *__restrict__ nseed, int *__restrict__ scratch,
+                                                     int *__restrict__ err) {
+    const int o = blockIdx.x;
+    const double sx = (o & 1) ? -1.0 : 1.0, sy = (o & 2) ? -1.0 : 1.0, sz = (o & 4) ? -1.0 : 1.0;
+    int *rem = scratch + (size_t)o * 3 * C;       // remaining upwind faces per cell
+    int *cur = rem + C;                             // current frontier
+    int *nxt = cur + C;                             // next frontier
+    __shared__ int s_ncur, s_nnext, s_maxin;
+    if (threadIdx.x == 0) { s_ncur = 0; s_nnext = 0; s_maxin = 0; }
+    __syncthreads();
+    for (int K = threadIdx.x; K < C; K += blockDim.x) {
+        int mask = 0, nin = 0, nall = 0;
+        for (int f = 0; f < 6; ++f) {
+            const double *A = area + ((size_t)K * 6 + f) * 3;
+            double d = sx * A[0] + sy * A[1] + sz * A[2];
+            if (d == 0.0) atomicOr(err, 2);
+            if (d < 0.0) {
+                mask |= 1 << f;
+                ++nall;
+                if (nbr[(size_t)K * 6 + f] >= 0) ++nin;
+            }
+        }
+        inmask[(size_t)o * C + K] = (unsigned char)mask;
+        indeg[(size_t)o * C + K] = nin;
+        rem[K] = nin;
+        atomicMax(&s_maxin, nall);
+        if (nin == 0) {
+            int i = atomicAdd(&s_ncur, 1);
+            cur[i] = K;
+            level[(size_t)o * C + K] = 0;
+        }
+    }
+    __syncthreads();
+    int lev = 0, total = 0;
+    for (;;) {
+        const int n = s_ncur;
+        if (n == 0) break;
+        total += n;
+        if (threadIdx.x == 0) hist[(size_t)o * (C + 1) + lev] = n;
+        if (lev == 0) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) seeds[(size_t)o * C + i] = cur[i];
+            if (threadIdx.x == 0) nseed[o] = n;
+        }
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const int K = cur[i];
+            const int mask = inmask[(size_t)o * C + K];
+            for (int f = 0; f < 6; ++f) {
+                if ((mask >> f) & 1) continue;
+                const int N = nbr[(size_t)K * 6 + f];
+                if (N < 0) continue;
+                if (atomicSub(&rem[N], 1) == 1) {
+                    level[(size_t)o * C + N] = lev + 1;
+                    nxt[atomicAdd(&s_nnext, 1)] = N;
+                }
+            }
+        }
+        __syncthreads();
+        int *t = cur; cur = nxt; nxt = t;
+        ++lev;
+        __syncthreads();
+        if (threadIdx.x == 0) { s_ncur = s_nnext; s_nnext = 0; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        nlev[o] = lev;
+        nlev[8 + o] = s_maxin;
+        if (total != C) atomicOr(err, 4);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_dag_one(int C, const int *nbr, const double *area, unsigned char *inmask, int *indeg, int *level,
+                          int *hist, int *nlev, int *seeds, int *nseed, int *scratch, int *err, hipStream_t s) {
+    hipLaunchKernelGGL(k_dag, dim3(8), dim3(kDagThreads), 0, s, C, nbr, area, inmask, indeg, level, hist, nlev,
+                       seeds, nseed, scratch, err);
+    return hipGetLastError();
+}
+
+}  // namespace snx

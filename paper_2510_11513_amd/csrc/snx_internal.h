@@ -1,0 +1,96 @@
+// Internal declarations of the gfx950 S_N sweep library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "snx.h"
+
+namespace snx {
+
+constexpr int kMaxAnglesPerOctant = 64;
+constexpr int kMaxGroups = 256;
+constexpr float kInv4Pi = 0.0795774715459476679f;
+
+// Control block of the device task queue of one sweep launch.
+struct QueueCtl {
+    unsigned head;      // next queue slot to pop
+    unsigned tail;      // next queue slot to fill
+    unsigned epoch;     // sweep number since setup (counters count to indeg * epoch)
+    unsigned abort;     // set by a watchdog expiry; every worker then exits
+    unsigned long long polls_empty;  // polls that found the popped slot not yet filled
+    unsigned long long tasks_done;
+};
+
+// Per-problem view used by the device kernels.  All pointers are device memory.
+struct DevProblem {
+    int C, G, A;                 // cells, groups, angles per octant
+    int nang;
+    long long task_base;         // first global task id of this problem (task = base + o*C + K)
+    const float *M;              // [C][64]       mass M_ij = int f_i f_j
+    const float *S;              // [C][3][64]    stiffness S^a_ij = int f_i df_j/dx_a
+    const float *F;              // [C][6][3][16] face matrices F^a_kl on face nodes
+    const int *nbr;              // [C][6]        neighbour across face, -1 on the boundary
+    const unsigned *perm;        // [C][6]        neighbour's local vertex at my face node k, 8 bits each
+    const unsigned char *inmask; // [8][C]        inflow-face bit mask per octant
+    const int *indeg;            // [8][C]        interior inflow faces per octant
+    const float *sigt;           // [C][G]
+    const float *sigs;           // [C][G]
+    const float *q;              // [C][G]
+    float *r;                    // [C][G][8]     M (Q + sigma_s phi) / (4 pi)
+    const float *omega;          // [8*A][3]
+    const float *w;              // [8*A]
+    const float *psib;           // [G] isotropic inflow, or nullptr (vacuum)
+    float *psi;                  // [8][C][8][A][G] angular flux handoff
+    float *slot;                 // [8][C][G][8]  per-octant compensated partial sums
+    float *slotc;                // [8][C][G][8]  their compensation terms
+    unsigned *cnt;               // [8][C]        dependency counters (count up across sweeps)
+};
+
+// Iteration record of snx_solve's device-side control.
+struct IterCtl {
+    unsigned long long num_bits;  // max |phi_new - phi_old| (FP64 bit pattern, non-negative)
+    unsigned long long den_bits;  // max |phi_new|
+    unsigned blocks_done;
+    int iter;                     // completed iterations
+    int stop;                     // 1 = converged, 2 = max_it reached, 3 = device error
+    int max_it;
+    double tol;
+    double last_eps;
+};
+
+// ------------------------------------------------------------- launchers
+hipError_t launch_geometry(const double *xyz, const int *cell_vert, const int *nbr, const int *nbr_face,
+                           const unsigned *perm, int C, float *M, float *S, float *F, double *area,
+                           int *err_flag, hipStream_t s);
+hipError_t launch_dag_one(int C, const int *nbr, const double *area, unsigned char *inmask, int *indeg, int *level,
+                          int *hist, int *nlev, int *seeds, int *nseed, int *scratch, int *err, hipStream_t s);
+hipError_t launch_sweep(const DevProblem *probs, int nprob, const long long *task_base, long long total,
+                        QueueCtl *ctl, unsigned long long *queue, const int *seeds, int nseed, const int *stop_flag,
+                        int threads, int grid, int maxA, int maxG, int maxin, unsigned long long watchdog,
+                        hipStream_t s);
+size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin);
+int sweep_occupancy(int threads, size_t lds);
+hipError_t launch_source(const DevProblem *probs, int prob, int C, int G, const float *phi, int *stop_flag,
+                         hipStream_t s);
+hipError_t launch_reduce(const DevProblem *probs, int prob, int C, int G, float *phi_out, const float *phi_old,
+                         bool update_source, IterCtl *ic, int *stop_flag, hipStream_t s);
+hipError_t launch_balance(const DevProblem *probs, int prob, int C, int G, const float *phi_in, const float *phi_out,
+                          double *partial, double *out, hipStream_t s);
+hipError_t launch_integrated_flux(const float *M, const float *phi, int C, int G, double *partial, double *out,
+                                  hipStream_t s);
+size_t partial_blocks(int C, int G);
+hipError_t launch_fill_f32(float *p, size_t n, float v, hipStream_t s);
+hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s);
+hipError_t launch_copy_f32(float *dst, const float *src, size_t n, const int *stop_flag, hipStream_t s);
+hipError_t launch_iter_init(IterCtl *ic, int *stop_flag, int max_it, double tol, hipStream_t s);
+
+// ------------------------------------------------------------- host helpers
+int topology(int C, int nvert, const int *cell_vert, std::vector<int> &nbr, std::vector<int> &nbr_face,
+             std::vector<unsigned> &perm, std::string &err);
+int product_quadrature(int npolar, int nazim, double *omega, double *w);
+
+}  // namespace snx

@@ -1,0 +1,220 @@
+"""Python binding of libsnx.so (the gfx950 S_N sweep library).
+
+Argument marshalling only: every step of the transport path runs in the HIP
+kernels behind the C ABI declared in include/snx.h.  PyTorch supplies device
+memory (tensors' data pointers) and streams.  There is no fallback: if the
+library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsnx.so")
+
+STATUS = {0: "SNX_OK", -1: "SNX_E_ARG", -2: "SNX_E_STATE", -3: "SNX_E_MESH", -4: "SNX_E_CYCLE",
+          -5: "SNX_E_DEVICE", -6: "SNX_E_OOM", -7: "SNX_E_NOCONV"}
+SNX_E_NOCONV = -7
+
+EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_set_quadrature",
+           "snx_quadrature_product", "snx_set_materials", "snx_set_boundary", "snx_setup", "snx_sweep",
+           "snx_solve", "snx_balance", "snx_integrated_flux", "snx_get_levels", "snx_set_schedule",
+           "snx_sweep_stats"]
+
+
+class SnxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SolveInfo(ct.Structure):
+    _fields_ = [("iterations", ct.c_int32), ("status", ct.c_int32), ("residual", ct.c_double),
+                ("wall_ms", ct.c_double), ("solves_per_s", ct.c_double)]
+
+
+_lib = None
+_dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_vp = ct.c_void_p
+
+
+def load(path: str = LIB_PATH):
+    """Loads libsnx.so and declares the C signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run `python -m paper_2510_11513_amd.build`")
+    L = ct.CDLL(path)
+    L.snx_create.argtypes = [ct.POINTER(_vp), ct.c_int32]
+    L.snx_destroy.argtypes = [_vp]
+    L.snx_destroy.restype = None
+    L.snx_last_error.argtypes = [_vp]
+    L.snx_last_error.restype = ct.c_char_p
+    L.snx_set_mesh.argtypes = [_vp, ct.c_int64, ct.c_int64, _dp, _ip]
+    L.snx_set_quadrature.argtypes = [_vp, ct.c_int32, _dp, _dp]
+    L.snx_quadrature_product.argtypes = [ct.c_int32, ct.c_int32, _dp, _dp]
+    L.snx_set_materials.argtypes = [_vp, ct.c_int32, _dp, _dp, _dp]
+    L.snx_set_boundary.argtypes = [_vp, ct.c_int32, _vp]
+    L.snx_setup.argtypes = [_vp, _vp]
+    L.snx_sweep.argtypes = [_vp, _vp, _vp, _vp]
+    L.snx_solve.argtypes = [_vp, ct.c_double, ct.c_int32, _vp, _vp, ct.POINTER(SolveInfo), _vp]
+    L.snx_balance.argtypes = [_vp, _vp, _vp, _dp, _vp]
+    L.snx_integrated_flux.argtypes = [_vp, _vp, _dp, _vp]
+    L.snx_get_levels.argtypes = [_vp, _vp, _vp]
+    L.snx_set_schedule.argtypes = [_vp, ct.c_int32, ct.c_int32, ct.c_int32]
+    L.snx_sweep_stats.argtypes = [_vp, _vp]
+    for name in EXPORTS:
+        if name not in ("snx_destroy", "snx_last_error"):
+            getattr(L, name).restype = ct.c_int32
+    _lib = L
+    return L
+
+
+def quadrature_product(npolar: int, nazim: int):
+    """Product quadrature from the library: (omega[8*npolar*nazim][3], w[...])."""
+    nang = 8 * npolar * nazim
+    om = np.zeros((nang, 3))
+    w = np.zeros(nang)
+    rc = load().snx_quadrature_product(npolar, nazim, om, w)
+    if rc:
+        raise SnxError(rc, "quadrature_product")
+    return om, w
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ct.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ct.c_void_p(stream.cuda_stream)
+
+
+class Problem:
+    """One transport problem resident on a GPU.
+
+    Flux tensors are torch.float32 of shape [ncell, G, 8] on the problem's
+    device (the exchange layout of the C ABI).
+    """
+
+    def __init__(self, device: int = 0):
+        L = load()
+        h = ct.c_void_p()
+        rc = L.snx_create(ct.byref(h), device)
+        if rc:
+            raise SnxError(rc, L.snx_last_error(None).decode())
+        self.h = h
+        self.device = device
+        self.ncell = self.G = self.nang = 0
+
+    def _check(self, rc, what, allow=()):
+        if rc and rc not in allow:
+            raise SnxError(rc, f"{what}: {load().snx_last_error(self.h).decode()}")
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            load().snx_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- inputs
+    def set_mesh(self, xyz, cell_vert):
+        xyz = np.ascontiguousarray(xyz, np.float64)
+        cv = np.ascontiguousarray(cell_vert, np.int32)
+        self._check(load().snx_set_mesh(self.h, cv.shape[0], xyz.shape[0], xyz, cv), "set_mesh")
+        self.ncell = cv.shape[0]
+
+    def set_quadrature(self, omega, w):
+        om = np.ascontiguousarray(omega, np.float64)
+        w = np.ascontiguousarray(w, np.float64)
+        self._check(load().snx_set_quadrature(self.h, om.shape[0], om, w), "set_quadrature")
+        self.nang = om.shape[0]
+
+    def set_materials(self, sigma_t, sigma_s, q):
+        st = np.ascontiguousarray(sigma_t, np.float64)
+        ss = np.ascontiguousarray(sigma_s, np.float64)
+        qq = np.ascontiguousarray(q, np.float64)
+        self._check(load().snx_set_materials(self.h, st.shape[1], st, ss, qq), "set_materials")
+        self.G = st.shape[1]
+
+    def set_boundary(self, kind: int, psi_in=None):
+        arr = None if psi_in is None else np.ascontiguousarray(psi_in, np.float64)
+        ptr = None if arr is None else arr.ctypes.data_as(ct.c_void_p)
+        self._check(load().snx_set_boundary(self.h, kind, ptr), "set_boundary")
+
+    def setup(self, stream=None):
+        self._check(load().snx_setup(self.h, _stream(stream)), "setup")
+
+    @classmethod
+    def from_problem(cls, prob, device: int = 0, setup: bool = True, quadrature=None):
+        """Loads a generated problem (paper_2510_11513_amd.inputs.Problem) into the library."""
+        p = cls(device)
+        p.set_mesh(prob.mesh.xyz, prob.mesh.cell_vert)
+        om, w = quadrature if quadrature is not None else quadrature_product(prob.npolar, prob.nazim)
+        p.set_quadrature(om, w)
+        p.set_materials(prob.mat.sigma_t, prob.mat.sigma_s, prob.mat.q)
+        if prob.boundary_kind:
+            p.set_boundary(prob.boundary_kind, prob.psi_b)
+        if setup:
+            p.setup()
+        return p
+
+    # ------------------------------------------------------------- compute
+    def empty_phi(self):
+        import torch
+        return torch.empty((self.ncell, self.G, 8), dtype=torch.float32, device=f"cuda:{self.device}")
+
+    def sweep(self, phi_in=None, phi_out=None, stream=None):
+        if phi_out is None:
+            phi_out = self.empty_phi()
+        self._check(load().snx_sweep(self.h, _ptr(phi_in), _ptr(phi_out), _stream(stream)), "sweep")
+        return phi_out
+
+    def solve(self, tol: float, max_it: int, phi0=None, phi=None, stream=None, allow_noconv=False):
+        if phi is None:
+            phi = self.empty_phi()
+        info = SolveInfo()
+        rc = load().snx_solve(self.h, tol, max_it, _ptr(phi0), _ptr(phi), ct.byref(info), _stream(stream))
+        self._check(rc, "solve", allow=(SNX_E_NOCONV,) if allow_noconv else ())
+        return phi, {"iterations": info.iterations, "status": info.status, "residual": info.residual,
+                     "wall_ms": info.wall_ms, "solves_per_s": info.solves_per_s, "rc": rc}
+
+    def balance(self, phi_in, phi_out, stream=None):
+        out = np.zeros((self.G, 4))
+        self._check(load().snx_balance(self.h, _ptr(phi_in), _ptr(phi_out), out, _stream(stream)), "balance")
+        return out
+
+    def integrated_flux(self, phi, stream=None):
+        out = np.zeros((self.G, 2))
+        self._check(load().snx_integrated_flux(self.h, _ptr(phi), out, _stream(stream)), "integrated_flux")
+        return out
+
+    def levels(self):
+        lev = np.zeros((8, self.ncell), np.int32)
+        nl = np.zeros(8, np.int32)
+        self._check(load().snx_get_levels(self.h, lev.ctypes.data_as(ct.c_void_p), nl.ctypes.data_as(ct.c_void_p)),
+                    "get_levels")
+        return lev, nl
+
+    def set_schedule(self, threads: int = 0, wg_per_cu: int = 0, chunk: int = 0):
+        self._check(load().snx_set_schedule(self.h, threads, wg_per_cu, chunk), "set_schedule")
+
+    def sweep_stats(self):
+        out = np.zeros(4, np.int64)
+        self._check(load().snx_sweep_stats(self.h, out.ctypes.data_as(ct.c_void_p)), "sweep_stats")
+        return {"tasks": int(out[0]), "empty_polls": int(out[1]), "abort": int(out[2]), "grid": int(out[3])}
