@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 unstructured S_N sweep (one MI355X).
+
+A step is one source iteration of the whole hot path on one synthetic
+problem: scattering-source update, the persistent dependency-driven sweep of
+all octants, angles and groups, the compensated angle reduction and the FP64
+convergence residual (graph-captured, as snx_solve runs it).  Setup (element
+matrices, designation, levelling) is done once per mesh before timing.
+
+Default workload: 32^3 jittered hex grid (32,768 cells, ids permuted),
+3x4 product quadrature (96 angles), 16 groups, two materials in a seeded
+4^3-block checkerboard (sigma_t 0.5 / 5.0, c 0.3 / 0.9, source 1 / 0),
+per-group cross-section scaling 0.8..1.2, vacuum boundaries.
+
+Prints one JSON line (rank 0).  `value` is cell-angle-group solves per second
+over the timed steps with all inputs resident in HBM.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-angle-group solves/s per sweep; time-to-1e-6 learned vs plain start"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "cfg2": (2, "32^3 jittered hex (32768 cells), 96 angles (3x4 product), 16 groups, two-material 4^3 blocks"),
+    "cfg1": (1, "8^3 jittered hex (512 cells), 32 angles (2x2), 4 groups, sigma_t 1, c 0.5"),
+    "cfg3": (3, "64^3 jittered hex (262144 cells), 256 angles (4x8), 64 groups, log-uniform 8^3 blocks"),
+    "paper16": (0, "16^3 jittered hex (4096 cells), 128 angles (4x4), 16 groups, sigma_t 1, c 0.5"),
+}
+
+
+def bytes_per_task(n: int, A: int, A_o: int, G: int) -> float:
+    """Algorithmic bytes per (cell, angle, group) solve of one source iteration.
+
+    32 B written psi (8 FP32 dofs); 16 B read per interior inflow face, of
+    which a cell of an n^3 grid has 3(n-1)/n per octant on average; 140 B per
+    (cell, group) per iteration (source in, flux out, source update, cross
+    section) over A angles; 120 B of cell geometry per (cell, octant) over
+    A_o * G solves.
+    """
+    return 32.0 + 48.0 * (n - 1) / n + 140.0 / A + 120.0 / (A_o * G)
+
+
+def kernel_hash() -> str:
+    path = os.path.join(ROOT, "paper_2510_11513_amd", "csrc", "k_sweep.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary, if still current."""
+    path = os.path.join(ROOT, "profiles", f"k_sweep_{workload}_pmc.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    h = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not h or not t or h.group(1) != kernel_hash():
+        return None
+    return float(t.group(1))
+
+
+def cpu_baseline(prob, groups: int, sweeps: int):
+    """The FP64 oracle (test infrastructure), untuned, on a bounded sample of the same workload."""
+    import numpy as np
+    import oracle
+    from paper_2510_11513_amd import inputs
+    G = prob.mat.ngroup
+    gs = max(1, min(groups, G))
+    mat = inputs.Materials(prob.mat.sigma_t[:, :gs].copy(), prob.mat.sigma_s[:, :gs].copy(), prob.mat.q[:, :gs].copy())
+    sub = inputs.Problem(prob.name, prob.mesh, mat, prob.npolar, prob.nazim, prob.tol)
+    o = oracle.Oracle.from_problem(sub)
+    phi = np.zeros((prob.mesh.ncell, gs, 8))
+    t0 = time.perf_counter()
+    for _ in range(sweeps):
+        phi = o.sweep(phi)["phi"]
+    dt = time.perf_counter() - t0
+    solves = prob.mesh.ncell * prob.nang * gs * sweeps
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": solves / dt, "unit": "solves/s", "cores": min(threads, gs), "kind": "oracle",
+            "sample": f"{sweeps} FP64 source iteration(s) of the same mesh and quadrature for groups 0..{gs - 1} "
+                      f"of {G} ({solves:.3g} solves, {dt:.2f} s; the oracle runs one OpenMP thread per group)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--threads", type=int, default=0, help="sweep workgroup size (0 = library default)")
+    ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-groups", type=int, default=16)
+    ap.add_argument("--cpu-sweeps", type=int, default=1)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference kernel for HBM counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(sharding is described in the design notes); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2510_11513_amd import inputs, snx
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    cfg, desc = WORKLOADS[args.workload]
+    prob = inputs.config_problem(cfg)
+    C, G, nang = prob.mesh.ncell, prob.mat.ngroup, prob.nang
+    p = snx.Problem.from_problem(prob, setup=False)
+    if args.threads or args.wg_per_cu:
+        p.set_schedule(threads=args.threads, wg_per_cu=args.wg_per_cu)
+    t_setup = time.perf_counter()
+    p.setup()
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    print(f"[bench] {args.workload}: setup {t_setup:.2f} s; warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
+
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    phi = p.empty_phi()
+    if args.warmup:
+        p.solve(0.0, args.warmup, phi=phi, allow_noconv=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi, info = p.solve(0.0, args.steps, phi=phi, allow_noconv=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert info["iterations"] == args.steps, info
+    solves_per_step = C * nang * G
+    value = solves_per_step * args.steps / dt
+    print(f"[bench] timed {args.steps} steps in {dt:.3f} s; residual {info['residual']:.3e}", file=sys.stderr,
+          flush=True)
+
+    # live duration of the dominant kernel (the sweep) from HIP events on its stream
+    ms_sweep = p.profile_sweep(max(5, min(args.steps, 20)), phi_in=phi)
+    stats = p.sweep_stats()
+    bpt = bytes_per_task(prob.mesh.n, nang, nang // 8, G)
+    bytes_launch = bpt * solves_per_step
+    achieved = bytes_launch / (ms_sweep * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_sweep", "kernel_ms": round(ms_sweep, 4), "bytes_per_solve": round(bpt, 2),
+                "solves_per_launch": solves_per_step}
+    out = {"metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{args.workload}: {desc}", "cells": C, "angles": nang, "groups": G,
+                      "solves_per_step": solves_per_step, "sweep_grid": stats["grid"],
+                      "setup_s": round(t_setup, 3)},
+           "roofline": roofline}
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_groups, args.cpu_sweeps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -144,6 +144,13 @@ snx_status snx_get_levels(snx_problem *p, int32_t *level, int32_t *nlevels);
  * Any argument <= 0 keeps the current value. */
 snx_status snx_set_schedule(snx_problem *p, int32_t threads, int32_t wg_per_cu, int32_t chunk);
 
+/* Times the sweep kernel alone: nsweeps source iterations from device phi_in
+ * (NULL = zero) into device phi_out, with HIP events recorded on `stream`
+ * immediately around each sweep-kernel launch; host *ms receives the mean
+ * sweep-kernel duration in milliseconds.  Synchronous. */
+snx_status snx_profile_sweep(snx_problem *p, int32_t nsweeps, const float *phi_in, float *phi_out, double *ms,
+                             void *stream);
+
 /* Statistics of the most recent sweep, host out[4]: tasks executed, queue
  * polls that found no ready task, watchdog flag, reserved.  Synchronous. */
 snx_status snx_sweep_stats(snx_problem *p, int64_t *out);

@@ -388,11 +388,15 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     return SNX_OK;
 }
 
-static snx_status enqueue_sweep(snx_problem *p, const int *stop, hipStream_t s) {
+static snx_status enqueue_sweep(snx_problem *p, const int *stop, hipStream_t s, hipEvent_t ev0 = nullptr,
+                                hipEvent_t ev1 = nullptr) {
     SweepSched &sc = p->sched;
-    HIPCHK(p, launch_sweep(sc.d_probs, sc.nprob, sc.d_base, sc.total, sc.d_ctl, sc.d_queue, sc.d_seeds, sc.nseed,
-                           stop, sc.threads, sc.grid, sc.maxA, sc.maxG, sc.maxin, p->watchdog_ticks, s),
+    HIPCHK(p, launch_sweep_prologue(sc.d_ctl, sc.d_queue, sc.d_seeds, sc.nseed, stop, s), "sweep prologue");
+    if (ev0) HIPCHK(p, hipEventRecord(ev0, s), "event");
+    HIPCHK(p, launch_sweep_kernel(sc.d_probs, sc.nprob, sc.d_base, sc.total, sc.d_ctl, sc.d_queue, stop, sc.threads,
+                                  sc.grid, sc.maxA, sc.maxG, sc.maxin, p->watchdog_ticks, s),
            "sweep launch");
+    if (ev1) HIPCHK(p, hipEventRecord(ev1, s), "event");
     return SNX_OK;
 }
 
@@ -530,6 +534,38 @@ snx_status snx_set_schedule(snx_problem *p, int32_t threads, int32_t wg_per_cu, 
     drop_graph(p);
     if (p->ready) return configure_grid(p, p->sched);
     return SNX_OK;
+}
+
+snx_status snx_profile_sweep(snx_problem *p, int32_t nsweeps, const float *phi_in, float *phi_out, double *ms,
+                             void *stream) {
+    if (!p) return SNX_E_ARG;
+    if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
+    if (nsweeps < 1 || !phi_out || !ms || phi_in == phi_out) return fail(p, SNX_E_ARG, "bad profile arguments");
+    HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<hipEvent_t> ev(2 * nsweeps, nullptr);
+    snx_status st = SNX_OK;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) { st = fail(p, SNX_E_DEVICE, "hipEventCreate failed"); break; }
+    for (int i = 0; i < nsweeps && !st; ++i) {
+        hipError_t e = launch_source(p->sched.d_probs, 0, p->C, p->G, phi_in, nullptr, s);
+        if (e != hipSuccess) { st = hip_fail(p, e, "source"); break; }
+        st = enqueue_sweep(p, nullptr, s, ev[2 * i], ev[2 * i + 1]);
+        if (st) break;
+        e = launch_reduce(p->sched.d_probs, 0, p->C, p->G, phi_out, nullptr, false, nullptr, nullptr, s);
+        if (e != hipSuccess) st = hip_fail(p, e, "reduce");
+    }
+    double total = 0.0;
+    if (!st && hipStreamSynchronize(s) != hipSuccess) st = fail(p, SNX_E_DEVICE, "profile sync failed");
+    for (int i = 0; i < nsweeps && !st; ++i) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) != hipSuccess) st = fail(p, SNX_E_DEVICE, "event timing");
+        total += t;
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (!st) *ms = total / nsweeps;
+    return st;
 }
 
 snx_status snx_sweep_stats(snx_problem *p, int64_t *out) {

@@ -368,13 +368,15 @@ int sweep_occupancy(int threads, size_t lds) {
     return nb;
 }
 
-hipError_t launch_sweep(const DevProblem *probs, int nprob, const long long *task_base, long long total,
-                        QueueCtl *ctl, unsigned long long *queue, const int *seeds, int nseed, const int *stop_flag,
-                        int threads, int grid, int maxA, int maxG, int maxin, unsigned long long watchdog,
-                        hipStream_t s) {
+hipError_t launch_sweep_prologue(QueueCtl *ctl, unsigned long long *queue, const int *seeds, int nseed,
+                                 const int *stop_flag, hipStream_t s) {
     hipLaunchKernelGGL(k_sweep_prologue, dim3(1), dim3(256), 0, s, ctl, queue, seeds, nseed, stop_flag);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, long long total,
+                               QueueCtl *ctl, unsigned long long *queue, const int *stop_flag, int threads, int grid,
+                               int maxA, int maxG, int maxin, unsigned long long watchdog, hipStream_t s) {
     const size_t lds = sweep_lds_bytes(threads, maxA, maxG, maxin);
     switch (threads) {
         case 64: return launch_nt<64>(probs, nprob, task_base, total, ctl, queue, stop_flag, maxA, maxG, maxin, grid, lds, watchdog, s);

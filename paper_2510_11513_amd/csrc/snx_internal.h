@@ -68,10 +68,11 @@ hipError_t launch_geometry(const double *xyz, const int *cell_vert, const int *n
                            int *err_flag, hipStream_t s);
 hipError_t launch_dag_one(int C, const int *nbr, const double *area, unsigned char *inmask, int *indeg, int *level,
                           int *hist, int *nlev, int *seeds, int *nseed, int *scratch, int *err, hipStream_t s);
-hipError_t launch_sweep(const DevProblem *probs, int nprob, const long long *task_base, long long total,
-                        QueueCtl *ctl, unsigned long long *queue, const int *seeds, int nseed, const int *stop_flag,
-                        int threads, int grid, int maxA, int maxG, int maxin, unsigned long long watchdog,
-                        hipStream_t s);
+hipError_t launch_sweep_prologue(QueueCtl *ctl, unsigned long long *queue, const int *seeds, int nseed,
+                                 const int *stop_flag, hipStream_t s);
+hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, long long total,
+                               QueueCtl *ctl, unsigned long long *queue, const int *stop_flag, int threads, int grid,
+                               int maxA, int maxG, int maxin, unsigned long long watchdog, hipStream_t s);
 size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin);
 int sweep_occupancy(int threads, size_t lds);
 hipError_t launch_source(const DevProblem *probs, int prob, int C, int G, const float *phi, int *stop_flag,

@@ -22,7 +22,7 @@ SNX_E_NOCONV = -7
 EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_set_quadrature",
            "snx_quadrature_product", "snx_set_materials", "snx_set_boundary", "snx_setup", "snx_sweep",
            "snx_solve", "snx_balance", "snx_integrated_flux", "snx_get_levels", "snx_set_schedule",
-           "snx_sweep_stats"]
+           "snx_sweep_stats", "snx_profile_sweep"]
 
 
 class SnxError(RuntimeError):
@@ -68,6 +68,7 @@ def load(path: str = LIB_PATH):
     L.snx_get_levels.argtypes = [_vp, _vp, _vp]
     L.snx_set_schedule.argtypes = [_vp, ct.c_int32, ct.c_int32, ct.c_int32]
     L.snx_sweep_stats.argtypes = [_vp, _vp]
+    L.snx_profile_sweep.argtypes = [_vp, ct.c_int32, _vp, _vp, ct.POINTER(ct.c_double), _vp]
     for name in EXPORTS:
         if name not in ("snx_destroy", "snx_last_error"):
             getattr(L, name).restype = ct.c_int32
@@ -213,6 +214,15 @@ class Problem:
 
     def set_schedule(self, threads: int = 0, wg_per_cu: int = 0, chunk: int = 0):
         self._check(load().snx_set_schedule(self.h, threads, wg_per_cu, chunk), "set_schedule")
+
+    def profile_sweep(self, nsweeps: int, phi_in=None, phi_out=None, stream=None) -> float:
+        """Mean duration (ms) of the sweep kernel alone, from HIP events on its stream."""
+        if phi_out is None:
+            phi_out = self.empty_phi()
+        ms = ct.c_double(0.0)
+        self._check(load().snx_profile_sweep(self.h, nsweeps, _ptr(phi_in), _ptr(phi_out), ct.byref(ms),
+                                             _stream(stream)), "profile_sweep")
+        return ms.value
 
     def sweep_stats(self):
         out = np.zeros(4, np.int64)
