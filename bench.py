@@ -141,7 +141,9 @@ def main():
 
     phi = p.empty_phi()
     if args.warmup:
+        p.set_schedule(chunk=args.warmup)     # one graph replay, no early-exit dispatches
         p.solve(0.0, args.warmup, phi=phi, allow_noconv=True)
+    p.set_schedule(chunk=args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     phi, info = p.solve(0.0, args.steps, phi=phi, allow_noconv=True)
@@ -169,6 +171,7 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{args.workload}: {desc}", "cells": C, "angles": nang, "groups": G,
                       "solves_per_step": solves_per_step, "sweep_grid": stats["grid"],
+                      "sweep_threads": stats["threads"], "continued_tasks": stats["continued"],
                       "setup_s": round(t_setup, 3)},
            "roofline": roofline}
     if not args.no_cpu_baseline:

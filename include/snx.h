@@ -138,10 +138,10 @@ snx_status snx_integrated_flux(snx_problem *p, const float *phi, double *out, vo
  * octant) and host nlevels[8]; either may be NULL.  Synchronous. */
 snx_status snx_get_levels(snx_problem *p, int32_t *level, int32_t *nlevels);
 
-/* Sweep schedule knobs: threads per task workgroup (64..1024, multiple of
- * 64, at least G), resident workgroups per CU (0 = occupancy maximum) and
- * the graph chunk length of snx_solve (iterations per host check).
- * Any argument <= 0 keeps the current value. */
+/* Sweep schedule knobs: threads per task workgroup (64, 128, 256 or 512,
+ * at least G), resident workgroups per CU (capped at the occupancy
+ * maximum) and the graph chunk length of snx_solve (iterations captured per
+ * host check).  Any argument <= 0 keeps the current value. */
 snx_status snx_set_schedule(snx_problem *p, int32_t threads, int32_t wg_per_cu, int32_t chunk);
 
 /* Times the sweep kernel alone: nsweeps source iterations from device phi_in
@@ -151,8 +151,12 @@ snx_status snx_set_schedule(snx_problem *p, int32_t threads, int32_t wg_per_cu, 
 snx_status snx_profile_sweep(snx_problem *p, int32_t nsweeps, const float *phi_in, float *phi_out, double *ms,
                              void *stream);
 
-/* Statistics of the most recent sweep, host out[4]: tasks executed, queue
- * polls that found no ready task, watchdog flag, reserved.  Synchronous. */
+/* Statistics of the most recent sweep, host out[11]: tasks executed, queue
+ * polls that found no ready task, abort flag (1 watchdog, 2 queue overflow),
+ * resident workgroups of the sweep launch, tasks run by the workgroup that made
+ * them ready, threads per workgroup, then shader-clock cycles summed over
+ * workgroups spent waiting on the queue, staging cell data, building the
+ * per-angle operators, solving, and publishing to downwind cells.  Synchronous. */
 snx_status snx_sweep_stats(snx_problem *p, int64_t *out);
 
 #ifdef __cplusplus

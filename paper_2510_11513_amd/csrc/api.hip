@@ -35,7 +35,8 @@ struct DevAlloc {
 struct SweepSched {
     DevProblem *d_probs = nullptr;
     long long *d_base = nullptr;
-    QueueCtl *d_ctl = nullptr;
+    SweepCtl *d_ctl = nullptr;
+    SweepCtl host_ctl{};                 // static part (queue layout, seeds, XCC map) uploaded on reset
     unsigned long long *d_queue = nullptr;
     int *d_seeds = nullptr;
     int nprob = 0, nseed = 0;
@@ -71,9 +72,10 @@ struct snx_problem {
     unsigned long long watchdog_ticks = 0;
     int chunk = 8;
     int threads = 256, wg_per_cu = 0;   // requested sweep schedule
+    int nq = 1;                         // task queues = XCDs seen on the device
+    int xcc_queue[kMaxXcc] = {0};       // home queue of each hardware XCC id
 
-    hipGraphExec_t graph = nullptr;
-    bool graph_valid = false;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};   // chunk starting from ping-pong buffer 0 / 1
 };
 
 static snx_status fail(snx_problem *p, snx_status code, const std::string &msg) {
@@ -93,9 +95,10 @@ static snx_status hip_fail(snx_problem *p, hipError_t e, const char *what) {
     } while (0)
 
 static void drop_graph(snx_problem *p) {
-    if (p->graph) (void)hipGraphExecDestroy(p->graph);
-    p->graph = nullptr;
-    p->graph_valid = false;
+    for (auto &g : p->graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
 }
 
 static void drop_device(snx_problem *p) {
@@ -106,12 +109,38 @@ static void drop_device(snx_problem *p) {
     p->sched = SweepSched{};
 }
 
-// Zero the scheduler state: counters, epoch, queue and abort flag.
+// Zero the scheduler state: counters, epoch, queue slots, abort flag and queue
+// statistics, and upload the static queue layout.
 static hipError_t reset_schedule(snx_problem *p, hipStream_t s) {
     hipError_t e = launch_fill_u32(p->hp.cnt, (size_t)8 * p->C, 0u, s);
-    if (e == hipSuccess) e = hipMemsetAsync(p->sched.d_ctl, 0, sizeof(QueueCtl), s);
     if (e == hipSuccess) e = hipMemsetAsync(p->sched.d_queue, 0, sizeof(unsigned long long) * (size_t)p->sched.total, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->sched.d_ctl, &p->sched.host_ctl, sizeof(SweepCtl), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     return e;
+}
+
+// Queue layout of a sweep: octant o goes to queue o mod nq; each queue's slots
+// hold every task of its octants, seeds first.
+static void layout_queues(SweepCtl &c, int nq, const int *xcc_queue, const std::vector<long long> &cells_per_problem,
+                          const std::vector<std::vector<int>> &seeds_by_octant, std::vector<int> &seeds) {
+    c = SweepCtl{};
+    c.nq = nq;
+    for (int x = 0; x < kMaxXcc; ++x) c.xcc_queue[x] = xcc_queue[x];
+    long long base = 0;
+    seeds.clear();
+    for (int q = 0; q < nq; ++q) {
+        long long tot = 0;
+        c.qseed_base[q] = (int)seeds.size();
+        for (int o = q; o < 8; o += nq) {
+            for (long long cp : cells_per_problem) tot += cp;
+            seeds.insert(seeds.end(), seeds_by_octant[o].begin(), seeds_by_octant[o].end());
+        }
+        c.qseed_count[q] = (int)seeds.size() - c.qseed_base[q];
+        c.qbase[q] = base;
+        c.qtotal[q] = tot;
+        base += tot;
+    }
 }
 
 static int cu_count(int device) {
@@ -157,6 +186,30 @@ snx_status snx_create(snx_problem **out, int32_t device) {
     int rate_khz = 0;
     if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || rate_khz <= 0)
         rate_khz = 100000;
+    // Which XCDs do workgroups land on?  Each distinct XCC id becomes one task queue.
+    {
+        const int nb = 8 * cu_count(device);
+        int *d_ids = nullptr;
+        std::vector<int> ids(nb, 0);
+        e = hipMalloc((void **)&d_ids, sizeof(int) * nb);
+        if (e == hipSuccess) e = launch_xcc_probe(d_ids, nb, p->cap_stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(ids.data(), d_ids, sizeof(int) * nb, hipMemcpyDeviceToHost, p->cap_stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->cap_stream);
+        if (d_ids) (void)hipFree(d_ids);
+        if (e != hipSuccess) {
+            g_create_error = std::string("XCD probe failed: ") + hipGetErrorString(e);
+            (void)hipStreamDestroy(p->cap_stream);
+            (void)hipHostFree(p->pinned);
+            delete p;
+            return SNX_E_DEVICE;
+        }
+        bool seen[kMaxXcc] = {false};
+        for (int v : ids) seen[v & (kMaxXcc - 1)] = true;
+        int nq = 0;
+        for (int x = 0; x < kMaxXcc; ++x)
+            if (seen[x] && nq < kMaxQueues) p->xcc_queue[x] = nq++;
+        p->nq = std::max(1, nq);
+    }
     p->watchdog_ticks = (unsigned long long)rate_khz * 1000ull * 20ull;   // 20 s without a ready task
     *out = p;
     return SNX_OK;
@@ -272,6 +325,8 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     ALLOC(d_perm, sizeof(unsigned) * 6 * C);
     ALLOC(dM, sizeof(float) * 64 * C);
     ALLOC(dS, sizeof(float) * 192 * C);
+    float *dT;
+    ALLOC(dT, sizeof(float) * 8 * 192 * C);
     ALLOC(dF, sizeof(float) * 288 * C);
     ALLOC(p->d_area, sizeof(double) * 18 * C);
     ALLOC(dmask, 8 * C);
@@ -303,7 +358,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     SweepSched &sc = p->sched;
     ALLOC(sc.d_probs, sizeof(DevProblem));
     ALLOC(sc.d_base, sizeof(long long) * 2);
-    ALLOC(sc.d_ctl, sizeof(QueueCtl));
+    ALLOC(sc.d_ctl, sizeof(SweepCtl));
     ALLOC(sc.d_queue, sizeof(unsigned long long) * 8 * C);
     ALLOC(sc.d_seeds, sizeof(int) * 8 * C);
 #undef ALLOC
@@ -358,14 +413,18 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     int maxin = 0;
     for (int o = 0; o < 8; ++o) maxin = std::max(maxin, nlev[8 + o]);
 
-    // level-0 tasks of every octant become the queue's seeds
+    HIPCHK(p, launch_octant_operators(p->C, dS, dF, dmask, dT, s), "octant operators");
+
+    // level-0 tasks of every octant become the queues' seeds
     std::vector<int> seeds_host(8 * C), seeds;
+    std::vector<std::vector<int>> seeds_by_octant(8);
     HIPCHK(p, hipMemcpy(seeds_host.data(), dseeds, sizeof(int) * 8 * C, hipMemcpyDeviceToHost), "copy");
     for (int o = 0; o < 8; ++o)
-        for (int i = 0; i < nseed[o]; ++i) seeds.push_back(o * p->C + seeds_host[(size_t)o * C + i]);
+        for (int i = 0; i < nseed[o]; ++i) seeds_by_octant[o].push_back(o * p->C + seeds_host[(size_t)o * C + i]);
+    layout_queues(sc.host_ctl, p->nq, p->xcc_queue, std::vector<long long>{(long long)p->C}, seeds_by_octant, seeds);
 
     hp.C = p->C; hp.G = p->G; hp.A = p->A; hp.nang = p->nang; hp.task_base = 0;
-    hp.M = dM; hp.S = dS; hp.F = dF; hp.nbr = d_nbr; hp.perm = d_perm; hp.inmask = dmask; hp.indeg = dindeg;
+    hp.M = dM; hp.S = dS; hp.T = dT; hp.F = dF; hp.nbr = d_nbr; hp.perm = d_perm; hp.inmask = dmask; hp.indeg = dindeg;
     hp.sigt = dsigt; hp.sigs = dsigs; hp.q = dq; hp.r = dr; hp.omega = dom; hp.w = dw; hp.psib = dpsib;
     hp.psi = dpsi; hp.slot = dslot; hp.slotc = dslotc; hp.cnt = dcnt;
     sc.nprob = 1;
@@ -391,10 +450,10 @@ snx_status snx_setup(snx_problem *p, void *stream) {
 static snx_status enqueue_sweep(snx_problem *p, const int *stop, hipStream_t s, hipEvent_t ev0 = nullptr,
                                 hipEvent_t ev1 = nullptr) {
     SweepSched &sc = p->sched;
-    HIPCHK(p, launch_sweep_prologue(sc.d_ctl, sc.d_queue, sc.d_seeds, sc.nseed, stop, s), "sweep prologue");
+    HIPCHK(p, launch_sweep_prologue(sc.d_ctl, sc.d_queue, sc.d_seeds, stop, s), "sweep prologue");
     if (ev0) HIPCHK(p, hipEventRecord(ev0, s), "event");
-    HIPCHK(p, launch_sweep_kernel(sc.d_probs, sc.nprob, sc.d_base, sc.total, sc.d_ctl, sc.d_queue, stop, sc.threads,
-                                  sc.grid, sc.maxA, sc.maxG, sc.maxin, p->watchdog_ticks, s),
+    HIPCHK(p, launch_sweep_kernel(sc.d_probs, sc.nprob, sc.d_base, sc.d_ctl, sc.d_queue, stop, sc.threads, sc.grid,
+                                  sc.maxA, sc.maxG, sc.maxin, p->watchdog_ticks, s),
            "sweep launch");
     if (ev1) HIPCHK(p, hipEventRecord(ev1, s), "event");
     return SNX_OK;
@@ -413,16 +472,17 @@ snx_status snx_sweep(snx_problem *p, const float *phi_in, float *phi_out, void *
     return SNX_OK;
 }
 
-static snx_status build_graph(snx_problem *p) {
-    drop_graph(p);
+// Captures `chunk` source iterations whose first one reads ping-pong buffer `parity`.
+static snx_status build_graph(snx_problem *p, int parity) {
     hipStream_t cs = p->cap_stream;
     HIPCHK(p, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
     snx_status st = SNX_OK;
     for (int i = 0; i < p->chunk && !st; ++i) {
         st = enqueue_sweep(p, p->d_stop, cs);
         if (!st) {
-            hipError_t e = launch_reduce(p->sched.d_probs, 0, p->C, p->G, p->d_phi[(i + 1) & 1], p->d_phi[i & 1],
-                                         true, p->d_ic, p->d_stop, cs);
+            const int cur = (parity + i) & 1;
+            hipError_t e = launch_reduce(p->sched.d_probs, 0, p->C, p->G, p->d_phi[cur ^ 1], p->d_phi[cur], true,
+                                         p->d_ic, p->d_stop, cs);
             if (e != hipSuccess) st = hip_fail(p, e, "reduce launch");
         }
     }
@@ -430,10 +490,9 @@ static snx_status build_graph(snx_problem *p) {
     hipError_t e = hipStreamEndCapture(cs, &g);
     if (st) { if (g) (void)hipGraphDestroy(g); return st; }
     if (e != hipSuccess) return hip_fail(p, e, "end capture");
-    e = hipGraphInstantiate(&p->graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&p->graph[parity], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(p, e, "graph instantiate");
-    p->graph_valid = true;
     return SNX_OK;
 }
 
@@ -446,30 +505,33 @@ snx_status snx_solve(snx_problem *p, double tol, int32_t max_it, const float *ph
     hipStream_t s = (hipStream_t)stream;
     const auto t0 = std::chrono::steady_clock::now();
     const size_t nphi = (size_t)p->C * p->G * 8;
-    if (!p->graph_valid) {
-        snx_status st = build_graph(p);
-        if (st) return st;
-    }
     HIPCHK(p, launch_iter_init(p->d_ic, p->d_stop, max_it, tol, s), "init");
     if (phi0) HIPCHK(p, launch_copy_f32(p->d_phi[0], phi0, nphi, nullptr, s), "copy");
     else HIPCHK(p, launch_fill_f32(p->d_phi[0], nphi, 0.f, s), "fill");
     HIPCHK(p, launch_source(p->sched.d_probs, 0, p->C, p->G, p->d_phi[0], nullptr, s), "source");
     IterCtl *hic = reinterpret_cast<IterCtl *>(p->pinned);
-    QueueCtl *hq = reinterpret_cast<QueueCtl *>(reinterpret_cast<char *>(p->pinned) + 1024);
+    unsigned *habort = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(p->pinned) + 1024);
     int *hstop = reinterpret_cast<int *>(reinterpret_cast<char *>(p->pinned) + 2048);
     const long long max_launch = (max_it + p->chunk - 1) / p->chunk + 1;
+    int done_iters = 0;
     for (long long l = 0; l < max_launch; ++l) {
-        HIPCHK(p, hipGraphLaunch(p->graph, s), "graph launch");
+        const int parity = done_iters & 1;
+        if (!p->graph[parity]) {
+            snx_status st = build_graph(p, parity);
+            if (st) return st;
+        }
+        HIPCHK(p, hipGraphLaunch(p->graph[parity], s), "graph launch");
         HIPCHK(p, hipMemcpyAsync(hic, p->d_ic, sizeof(IterCtl), hipMemcpyDeviceToHost, s), "copy");
-        HIPCHK(p, hipMemcpyAsync(hq, p->sched.d_ctl, sizeof(QueueCtl), hipMemcpyDeviceToHost, s), "copy");
+        HIPCHK(p, hipMemcpyAsync(habort, &p->sched.d_ctl->abort, sizeof(unsigned), hipMemcpyDeviceToHost, s), "copy");
         HIPCHK(p, hipMemcpyAsync(hstop, p->d_stop, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
         HIPCHK(p, hipStreamSynchronize(s), "solve");
-        if (hq->abort) {
+        if (*habort) {
             (void)reset_schedule(p, s);
             (void)hipStreamSynchronize(s);
             return fail(p, SNX_E_DEVICE, "sweep watchdog expired (no ready task)");
         }
         if (*hstop) break;
+        done_iters = hic->iter;
     }
     const int iters = hic->iter;
     HIPCHK(p, launch_copy_f32(phi, p->d_phi[iters & 1], nphi, nullptr, s), "copy");
@@ -523,14 +585,14 @@ snx_status snx_get_levels(snx_problem *p, int32_t *level, int32_t *nlevels) {
 snx_status snx_set_schedule(snx_problem *p, int32_t threads, int32_t wg_per_cu, int32_t chunk) {
     if (!p) return SNX_E_ARG;
     if (threads > 0) {
-        if (threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)
-            return fail(p, SNX_E_ARG, "threads must be 64, 128, 256, 512 or 1024");
+        if (threads != 64 && threads != 128 && threads != 256 && threads != 512)
+            return fail(p, SNX_E_ARG, "threads must be 64, 128, 256 or 512");
         if (p->have_mat && threads < p->G) return fail(p, SNX_E_ARG, "threads must be at least G");
         p->threads = threads;
         p->sched.threads = threads;
     }
     if (wg_per_cu > 0) { p->wg_per_cu = wg_per_cu; p->sched.wg_per_cu = wg_per_cu; }
-    if (chunk > 0) p->chunk = (chunk + 1) & ~1;   // even: the ping-pong buffers line up across replays
+    if (chunk > 0) p->chunk = chunk;
     drop_graph(p);
     if (p->ready) return configure_grid(p, p->sched);
     return SNX_OK;
@@ -572,13 +634,20 @@ snx_status snx_sweep_stats(snx_problem *p, int64_t *out) {
     if (!p || !out) return SNX_E_ARG;
     if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
-    QueueCtl h{};
+    std::vector<SweepCtl> h(1);
     HIPCHK(p, hipDeviceSynchronize(), "sync");
-    HIPCHK(p, hipMemcpy(&h, p->sched.d_ctl, sizeof(QueueCtl), hipMemcpyDeviceToHost), "copy");
-    out[0] = (int64_t)h.tasks_done;
-    out[1] = (int64_t)h.polls_empty;
-    out[2] = (int64_t)h.abort;
+    HIPCHK(p, hipMemcpy(h.data(), p->sched.d_ctl, sizeof(SweepCtl), hipMemcpyDeviceToHost), "copy");
+    for (int i = 0; i < 11; ++i) out[i] = 0;
+    for (int q = 0; q < h[0].nq; ++q) {
+        const QueueCtl &Q = h[0].q[q];
+        out[0] += (int64_t)Q.tasks_done;
+        out[1] += (int64_t)Q.polls_empty;
+        out[4] += (int64_t)Q.continued;
+        for (int i = 0; i < 5; ++i) out[6 + i] += (int64_t)Q.phase[i];
+    }
+    out[2] = (int64_t)h[0].abort;
     out[3] = (int64_t)p->sched.grid;
+    out[5] = (int64_t)p->sched.threads;
     return SNX_OK;
 }
 

@@ -100,3 +100,40 @@ hipError_t launch_dag_one(int C, const int *nbr, const double *area, unsigned ch
 }
 
 }  // namespace snx
+
+namespace snx {
+namespace {
+
+// T^a_ij = S^a_ij - sum over inflow faces f of octant o of F^a_f at (i, j) when both
+// i and j lie on f: the angle-independent part of the upwind operator
+// B_n = sum_a Omega_a T^a of every direction of the octant.
+__global__ void k_octant_operators(int C, const float *__restrict__ S, const float *__restrict__ F,
+                                   const unsigned char *__restrict__ inmask, float *__restrict__ T) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 8LL * C * 192) return;
+    const int e = (int)(t % 192);
+    const long long oc = t / 192;            // o * C + K
+    const int K = (int)(oc % C);
+    const int a = e >> 6, ij = e & 63, i = ij >> 3, j = ij & 7;
+    const int mask = inmask[oc];
+    float v = S[(size_t)K * 192 + e];
+    for (int f = 0; f < 6; ++f) {
+        const int axis = f >> 1, side = f & 1;
+        if (!((mask >> f) & 1) || ((i >> axis) & 1) != side || ((j >> axis) & 1) != side) continue;
+        const int ki = axis == 0 ? i >> 1 : (axis == 1 ? (i & 1) | ((i >> 2) << 1) : i & 3);
+        const int kj = axis == 0 ? j >> 1 : (axis == 1 ? (j & 1) | ((j >> 2) << 1) : j & 3);
+        v -= F[((size_t)K * 6 + f) * 48 + a * 16 + ki * 4 + kj];
+    }
+    T[t] = v;
+}
+
+}  // namespace
+
+hipError_t launch_octant_operators(int C, const float *S, const float *F, const unsigned char *inmask, float *T,
+                                   hipStream_t s) {
+    const long long n = 8LL * C * 192;
+    hipLaunchKernelGGL(k_octant_operators, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, C, S, F, inmask, T);
+    return hipGetLastError();
+}
+
+}  // namespace snx

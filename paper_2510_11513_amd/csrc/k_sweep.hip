@@ -1,68 +1,84 @@
 // Persistent, dependency-driven S_N sweep on gfx950.
 //
 // The paper's many-task sweep (Section 3, Algorithm 1) starts one task per
-// direction at the first element, and a task, after solving its element for
-// all groups, generates the task of every downwind neighbour for which it was
-// the last upwind dependency, detected with per-element atomic counters.
-// On the GPU a task is one (cell, octant) pair of one problem: all A angles of
-// the octant and all G groups of the cell are solved by one workgroup, one
-// (angle, group) system per lane.  Tasks whose counters are complete are
-// pushed to a device queue; resident workgroups pop queue slots in order and
-// wait for the slot to be filled.  Every octant shares one upwind designation,
-// so a cell's (octant) task covers every angle of that octant.
+// direction at the first element; a task solves its element for all groups
+// and then generates the task of every downwind neighbour for which it was the
+// last upwind dependency, found with per-element atomic counters; work-first
+// generation runs the new task on the generating thread unless another thread
+// steals it from that thread's queue.
 //
-// Per task (lane = (angle n, group g)), the upwind DG system of the cell is
+// On the GPU a task is one (cell, octant) pair of one problem: every angle of
+// the octant and every group of the cell is solved by one workgroup, one
+// (angle, group) system per lane.  One designation serves all angles of an
+// octant, so the cell's task covers the whole octant.  When a task completes
+// the last dependency of downwind cells, its workgroup runs one of them next
+// (work-first continuation) and pushes the others to a device queue; idle
+// workgroups pop queue slots in order and wait for the slot to be filled.
+//
+// Per lane (angle n, group g) the upwind DG system of the cell is
 //   A = sum_a Om_a S^a + sigma_t M - sum_{f in} Om.F_f       (8x8)
 //   b = r_g - sum_{f in} (Om.F_f) psi_up_f,   r_g = M (Q + sigma_s phi) / (4 pi)
 // assembled from a per-angle operator B_n = sum_a Om_a S^a - sum_in Om.F_f built
 // once per task in LDS, and solved by unpivoted LU in registers, row by row.
 //
-// Cross-CU / cross-XCD hand-off.  The solution psi of a task is stored with
-// agent-coherent (sc1) stores and read by consumers with agent-coherent loads;
-// every wave waits for its stores to complete (vmcnt(0)) before the workgroup
-// increments downstream counters.  Other data is read-only during the kernel
-// and stays cacheable.
+// Hand-off across CUs and XCDs: psi is stored with agent-coherent (sc1)
+// stores and read with agent-coherent loads; every wave waits for its stores
+// to complete (vmcnt(0)) before the workgroup increments downstream counters.
+// Everything else is read-only during the kernel and stays cacheable.
 //
-// The angle reduction phi = sum_n w_n psi_n (Eq. 2) is done in the task: the
-// weighted solutions of each round of lanes are staged in LDS and added in
-// increasing angle order with a compensated (TwoSum) sum per (group, dof);
-// the per-octant partial and its compensation go to the octant's slot.  The
-// summation order is fixed, so results do not depend on the schedule.
+// The angle reduction phi = sum_n w_n psi_n (Eq. 2) is done in the task: each
+// round's weighted solutions are staged in LDS and added in increasing angle
+// order with a compensated (TwoSum) sum per (group, dof); the per-octant
+// partial and its compensation go to the octant's slot.  The order is fixed,
+// so results do not depend on the schedule.
 #include "snx_internal.h"
 
 namespace snx {
 namespace {
 
-__device__ inline float ld_agent(const float *p) {
+// Global address space: loads and stores through these pointers compile to
+// global_* instructions instead of flat ones (device pass only).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GLOBAL __attribute__((address_space(1)))
+#else
+#define GLOBAL
+#endif
+
+template <typename T>
+__device__ __forceinline__ GLOBAL T *gp(T *p) { return (GLOBAL T *)p; }
+
+__device__ __forceinline__ float ld_agent(const GLOBAL float *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void st_agent(float *p, float v) {
+__device__ __forceinline__ void st_agent(GLOBAL float *p, float v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // face f = 2*axis + side: face-local vertex k -> cell-local vertex
-__device__ inline int face_vertex(int f, int k) {
+__device__ __forceinline__ int face_vertex(int f, int k) {
     const int axis = f >> 1, side = f & 1;
     if (axis == 0) return (k << 1) | side;
     if (axis == 1) return (k & 1) | (side << 1) | ((k >> 1) << 2);
     return (side << 2) | k;
 }
 // cell-local vertex j on a face of the given axis -> face-local index
-__device__ inline int face_index(int axis, int j) {
+__device__ __forceinline__ int face_index(int axis, int j) {
     if (axis == 0) return j >> 1;
     if (axis == 1) return (j & 1) | ((j >> 2) << 1);
     return j & 3;
 }
 
 // Knuth's TwoSum: s + e == a + b exactly.
-__device__ inline void two_sum(float a, float b, float &s, float &e) {
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
     s = a + b;
     const float bb = s - a;
     e = (a - (s - bb)) + (b - bb);
 }
 
-__device__ inline int find_problem(const long long *__restrict__ base, int nprob, long long task) {
+__device__ __forceinline__ int find_problem(const long long *__restrict__ base, int nprob, long long task) {
     int lo = 0, hi = nprob - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -71,100 +87,201 @@ __device__ inline int find_problem(const long long *__restrict__ base, int nprob
     return lo;
 }
 
-// LDS layout (floats): M[64] S[192] Fin[6][48] om[A][4] Bop[A][64] Cop[A][maxin][16]
-//                      wpsi[NT][8] red_s[G][8] red_c[G][8]
+// The per-lane inputs of one (angle, group) system: source dofs, sigma_t and the
+// upwind traces of every inflow face (mask-predicated, one slot per face).
+struct LaneIn {
+    float r[8];
+    float sig;
+    float up[6][4];
+};
+
+__device__ __forceinline__ void load_lane(const DevProblem &P, int K, int mask, int n, int g,
+                                          const GLOBAL float *psi_o, size_t cell_psi, LaneIn &L) {
+    const int G = P.G, A = P.A;
+    const GLOBAL float4 *rv = reinterpret_cast<const GLOBAL float4 *>(gp(P.r) + ((size_t)K * G + g) * 8);
+    const float4 r0 = rv[0], r1 = rv[1];
+    L.r[0] = r0.x; L.r[1] = r0.y; L.r[2] = r0.z; L.r[3] = r0.w;
+    L.r[4] = r1.x; L.r[5] = r1.y; L.r[6] = r1.z; L.r[7] = r1.w;
+    L.sig = gp(P.sigt)[(size_t)K * G + g];
+    const float psib = P.psib ? gp(P.psib)[g] : 0.f;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        if (!((mask >> f) & 1)) continue;
+        const int N = uni(gp(P.nbr)[(size_t)K * 6 + f]);
+        if (N >= 0) {
+            const unsigned pm = (unsigned)uni((int)gp(P.perm)[(size_t)K * 6 + f]);
+            const GLOBAL float *pn = psi_o + (size_t)N * cell_psi + (size_t)n * G + g;
+#pragma unroll
+            for (int l = 0; l < 4; ++l) L.up[f][l] = ld_agent(pn + (size_t)((pm >> (8 * l)) & 0xff) * A * G);
+        } else {
+#pragma unroll
+            for (int l = 0; l < 4; ++l) L.up[f][l] = psib;
+        }
+    }
+}
+
+// Hardware id of the XCD (accelerator complex die) this wave runs on.
+__device__ __forceinline__ int xcc_id() {
+    return __builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & (kMaxXcc - 1);   // HW_REG_XCC_ID[3:0]
+}
+
+__device__ __forceinline__ unsigned ld_agent_u32(const unsigned *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Pops the next slot of queue q and waits for it.  A workgroup whose queue has
+// no task left moves on to the next queue (stealing); -1 when every queue is
+// done or on abort.
+__device__ long long pop_task(SweepCtl *ctl, unsigned long long *queue, int &q, int nq, unsigned epoch,
+                              unsigned long long watchdog, unsigned long long &polls) {
+    for (int tried = 0; tried < nq; ++tried, q = q + 1 < nq ? q + 1 : 0) {
+        QueueCtl *Q = &ctl->q[q];
+        const long long qt = ctl->qtotal[q];
+        if ((long long)ld_agent_u32(&Q->done) >= qt) continue;
+        const unsigned slot = atomicAdd(&Q->head, 1u);
+        const GLOBAL unsigned long long *qs = gp(queue) + ctl->qbase[q];
+        const unsigned long long t0 = wall_clock64();
+        int backoff = 1;
+        for (unsigned k = 1;; ++k) {
+            if ((long long)slot < qt) {
+                const unsigned long long v = __hip_atomic_load(qs + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((unsigned)(v >> 32) == epoch) return (long long)(v & 0xffffffffull);
+            }
+            if ((k & 7) == 0) {
+                if ((long long)ld_agent_u32(&Q->done) >= qt) break;        // this queue is finished
+                if (ld_agent_u32(&ctl->abort)) return -1;
+            }
+            ++polls;
+            if (wall_clock64() - t0 > watchdog) {
+                __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return -1;
+            }
+            for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(1);
+            backoff = backoff < 8 ? 2 * backoff : 8;
+        }
+    }
+    return -1;
+}
+
+// LDS layout (floats): M[64] T[3][64] Fin[6][48] om[A][4] Bop[A][64] Cop[A][maxin][16]
+//                      wpsi[2][NT][8] red_s[G][8] red_c[G][8]
 template <int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(const DevProblem *__restrict__ probs, int nprob,
-                                              const long long *__restrict__ task_base, long long total,
-                                              QueueCtl *__restrict__ ctl, unsigned long long *__restrict__ queue,
-                                              const int *__restrict__ stop_flag, int maxA, int maxG, int maxin,
-                                              unsigned long long watchdog) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(
+    const DevProblem *__restrict__ probs, int nprob, const long long *__restrict__ task_base,
+    SweepCtl *__restrict__ ctl, unsigned long long *__restrict__ queue, const int *__restrict__ stop_flag, int maxA,
+    int maxG, int maxin, unsigned long long watchdog) {
     extern __shared__ __align__(16) float lds[];
     __shared__ long long s_task;
+    __shared__ int s_q;
+    __shared__ int s_nready;
+    __shared__ long long s_ready[6];
     if (stop_flag && *stop_flag) return;
     const unsigned epoch = ctl->epoch;
+    const int nq = ctl->nq;
     const int tid = threadIdx.x;
+    int q = ctl->xcc_queue[xcc_id()];       // home queue: the one of this XCD
 
     float *sM = lds;
-    float *sS = sM + 64;
-    float *sF = sS + 192;                 // up to 6 inflow faces x 48
+    float *sT = sM + 64;                  // T^x, T^y, T^z of this (cell, octant)
+    float *sF = sT + 192;                 // up to 6 inflow faces x 48
     float *sOm = sF + 6 * 48;             // [maxA][4]: omega xyz, weight
     float *sB = sOm + 4 * maxA;           // [maxA][64]
     float *sC = sB + 64 * maxA;           // [maxA][maxin][16]
-    float *sW = sC + 16 * maxin * maxA;   // [NT][8]
-    float *sRs = sW + 8 * NT;             // [maxG][8]
+    float *sW = sC + 16 * maxin * maxA;   // [2][NT][8]
+    float *sRs = sW + 16 * NT;            // [maxG][8]
     float *sRc = sRs + 8 * maxG;          // [maxG][8]
 
-    unsigned long long my_polls = 0, my_tasks = 0;
+    // Workgroup statistics, kept in LDS and touched by thread 0 only: polls, tasks,
+    // continued tasks, tasks not yet added to the queue's done count, and the
+    // shader-clock cycles of the five phases of a task.
+    __shared__ unsigned long long s_stat[4], s_ph[5], s_mark;
+    if (tid == 0) {
+        for (int i = 0; i < 4; ++i) s_stat[i] = 0;
+        for (int i = 0; i < 5; ++i) s_ph[i] = 0;
+    }
+    long long cont = -1;
     for (;;) {
-        if (tid == 0) {
-            long long task = -1;
-            const unsigned slot = atomicAdd(&ctl->head, 1u);
-            if ((long long)slot < total) {
-                const unsigned long long t0 = wall_clock64();
-                for (;;) {
-                    const unsigned long long v =
-                        __hip_atomic_load(&queue[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if ((unsigned)(v >> 32) == epoch) { task = (long long)(v & 0xffffffffull); break; }
-                    if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-                    ++my_polls;
-                    if (wall_clock64() - t0 > watchdog) {
-                        __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
+        long long task = cont;
+        if (tid == 0) s_mark = clock64();
+        if (task < 0) {
+            if (tid == 0) {
+                if (s_stat[3]) {
+                    __hip_atomic_fetch_add(&ctl->q[q].done, (unsigned)s_stat[3], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    s_stat[3] = 0;
                 }
+                unsigned long long polls = 0;
+                s_task = pop_task(ctl, queue, q, nq, epoch, watchdog, polls);
+                s_stat[0] += polls;
+                s_q = q;
+                const unsigned long long t = clock64();
+                s_ph[0] += t - s_mark;
+                s_mark = t;
             }
-            s_task = task;
+            __syncthreads();
+            task = s_task;
+            q = s_q;
+            if (task < 0) break;
+        } else if (tid == 0) {
+            ++s_stat[2];
         }
-        __syncthreads();
-        const long long task = s_task;
-        if (task < 0) break;
 
         // ---------------------------------------------------------- decode
-        const int p = find_problem(task_base, nprob, task);
+        const int p = uni(find_problem(task_base, nprob, task));
         const DevProblem &P = probs[p];
         const int C = P.C, G = P.G, A = P.A;
         const long long local = task - P.task_base;
-        const int o = (int)(local / C);
-        const int K = (int)(local - (long long)o * C);
-        const int mask = P.inmask[(size_t)o * C + K];
+        const int o = uni((int)(local / C));
+        const int K = uni((int)(local - (long long)o * C));
+        const int mask = uni(gp(P.inmask)[(size_t)o * C + K]);
         const int nin = __popc(mask);
+        const int AG = A * G;
+        const size_t cell_psi = (size_t)8 * A * G;          // floats per (octant, cell)
+        GLOBAL float *psi_o = gp(P.psi) + (size_t)o * C * cell_psi;
 
         // ---------------------------------------------------- stage geometry
-        for (int i = tid; i < 64; i += NT) sM[i] = P.M[(size_t)K * 64 + i];
-        for (int i = tid; i < 192; i += NT) sS[i] = P.S[(size_t)K * 192 + i];
-#pragma unroll
-        for (int f = 0; f < 6; ++f) {
-            if (!((mask >> f) & 1)) continue;
-            const int s = __popc(mask & ((1 << f) - 1));   // slot of face f among the inflow faces
-            for (int i = tid; i < 48; i += NT) sF[s * 48 + i] = P.F[((size_t)K * 6 + f) * 48 + i];
+        // Cell data (M, T^a of this octant, inflow face matrices) as float4s; the
+        // lane inputs are issued only after these reach LDS, so the wait for the
+        // cell data never includes the (agent-coherent, slower) upwind loads.
+        const int nst = 64 + 12 * nin;                          // float4s to stage
+        auto stage_item = [&](int i) -> float4 {
+            if (i < 16) return reinterpret_cast<const GLOBAL float4 *>(gp(P.M) + (size_t)K * 64)[i];
+            if (i < 64) return reinterpret_cast<const GLOBAL float4 *>(gp(P.T) + ((size_t)o * C + K) * 192)[i - 16];
+            const int s = (i - 64) / 12, e = (i - 64) - s * 12;
+            int m = mask;                                       // face of inflow slot s: s-th set bit of mask
+            for (int k = 0; k < s; ++k) m &= m - 1;
+            const int f = __ffs(m) - 1;
+            return reinterpret_cast<const GLOBAL float4 *>(gp(P.F) + ((size_t)K * 6 + f) * 48)[e];
+        };
+        float4 om4 = make_float4(0.f, 0.f, 0.f, 0.f);          // direction and weight of angle tid (A <= 64 <= NT)
+        if constexpr (NT >= 136) {
+            // at most one item per thread: all loads in flight together
+            const float4 st = tid < nst ? stage_item(tid) : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (tid < A) {
+                const int n = o * A + tid;
+                om4 = make_float4(gp(P.omega)[3 * n + 0], gp(P.omega)[3 * n + 1], gp(P.omega)[3 * n + 2], gp(P.w)[n]);
+            }
+            if (tid < nst) reinterpret_cast<float4 *>(sM)[tid] = st;   // M, T and F are contiguous in LDS
+        } else {
+            if (tid < A) {
+                const int n = o * A + tid;
+                om4 = make_float4(gp(P.omega)[3 * n + 0], gp(P.omega)[3 * n + 1], gp(P.omega)[3 * n + 2], gp(P.w)[n]);
+            }
+            for (int i = tid; i < nst; i += NT) reinterpret_cast<float4 *>(sM)[i] = stage_item(i);
         }
-        for (int i = tid; i < A; i += NT) {
-            const int n = o * A + i;
-            sOm[4 * i + 0] = P.omega[3 * n + 0];
-            sOm[4 * i + 1] = P.omega[3 * n + 1];
-            sOm[4 * i + 2] = P.omega[3 * n + 2];
-            sOm[4 * i + 3] = P.w[n];
-        }
+        if (tid < A) reinterpret_cast<float4 *>(sOm)[tid] = om4;
+        // the first round's lane inputs are in flight during the operator build
+        LaneIn L;
+        if (tid < AG) load_lane(P, K, mask, tid / G, tid % G, psi_o, cell_psi, L);
         for (int i = tid; i < G * 8; i += NT) { sRs[i] = 0.f; sRc[i] = 0.f; }
         __syncthreads();
+        if (tid == 0) s_nready = 0;
+        if (tid == 0) { const unsigned long long t = clock64(); s_ph[1] += t - s_mark; s_mark = t; }
 
         // ------------------------------------- per-angle operators B_n, C_n,f
         for (int e = tid; e < A * 64; e += NT) {
-            const int n = e >> 6, ij = e & 63, i = ij >> 3, j = ij & 7;
-            const float ox = sOm[4 * n], oy = sOm[4 * n + 1], oz = sOm[4 * n + 2];
-            float v = ox * sS[ij] + oy * sS[64 + ij] + oz * sS[128 + ij];
-#pragma unroll
-            for (int f = 0; f < 6; ++f) {
-                const int axis = f >> 1, side = f & 1;
-                if (((mask >> f) & 1) && ((i >> axis) & 1) == side && ((j >> axis) & 1) == side) {
-                    const int kl = face_index(axis, i) * 4 + face_index(axis, j);
-                    const float *Fs = sF + __popc(mask & ((1 << f) - 1)) * 48;
-                    v -= ox * Fs[kl] + oy * Fs[16 + kl] + oz * Fs[32 + kl];
-                }
-            }
-            sB[e] = v;
+            const int n = e >> 6, ij = e & 63;
+            sB[e] = sOm[4 * n] * sT[ij] + sOm[4 * n + 1] * sT[64 + ij] + sOm[4 * n + 2] * sT[128 + ij];
         }
         for (int e = tid; e < A * nin * 16; e += NT) {
             const int n = e / (nin * 16), rem = e - n * nin * 16, s = rem >> 4, kl = rem & 15;
@@ -173,50 +290,36 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 sOm[4 * n] * Fs[kl] + sOm[4 * n + 1] * Fs[16 + kl] + sOm[4 * n + 2] * Fs[32 + kl];
         }
         __syncthreads();
+        if (tid == 0) { const unsigned long long t = clock64(); s_ph[2] += t - s_mark; s_mark = t; }
 
         // ------------------------------------------------ rounds of lanes
-        const int AG = A * G;
-        const size_t cell_psi = (size_t)8 * A * G;          // floats per (octant, cell)
-        float *psi_o = P.psi + (size_t)o * C * cell_psi;
-        for (int base = 0; base < AG; base += NT) {
+        int buf = 0;
+        for (int base = 0; base < AG; base += NT, buf ^= 1) {
             const int pi = base + tid;
+            float *sWb = sW + buf * NT * 8;
             if (pi < AG) {
                 const int n = pi / G, g = pi - n * G;
-                const float sig = P.sigt[(size_t)K * G + g];
                 float b[8];
-                const float4 *rv = reinterpret_cast<const float4 *>(P.r + ((size_t)K * G + g) * 8);
-                const float4 r0 = rv[0], r1 = rv[1];
-                b[0] = r0.x; b[1] = r0.y; b[2] = r0.z; b[3] = r0.w;
-                b[4] = r1.x; b[5] = r1.y; b[6] = r1.z; b[7] = r1.w;
-                const float psib = P.psib ? P.psib[g] : 0.f;
+#pragma unroll
+                for (int d = 0; d < 8; ++d) b[d] = L.r[d];
 #pragma unroll
                 for (int f = 0; f < 6; ++f) {
                     if (!((mask >> f) & 1)) continue;
-                    const int s = __popc(mask & ((1 << f) - 1));
-                    float up[4];
-                    const int N = P.nbr[(size_t)K * 6 + f];
-                    if (N >= 0) {
-                        const unsigned pm = P.perm[(size_t)K * 6 + f];
-                        const float *pn = psi_o + (size_t)N * cell_psi + (size_t)n * G + g;
-#pragma unroll
-                        for (int l = 0; l < 4; ++l) {
-                            const int jn = (pm >> (8 * l)) & 0xff;
-                            up[l] = ld_agent(pn + (size_t)jn * A * G);
-                        }
-                    } else {
-#pragma unroll
-                        for (int l = 0; l < 4; ++l) up[l] = psib;
-                    }
-                    const float *Cs = sC + (n * maxin + s) * 16;
+                    const float *Cs = sC + (n * maxin + __popc(mask & ((1 << f) - 1))) * 16;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        float t = Cs[k * 4] * up[0];
-                        t = __builtin_fmaf(Cs[k * 4 + 1], up[1], t);
-                        t = __builtin_fmaf(Cs[k * 4 + 2], up[2], t);
-                        t = __builtin_fmaf(Cs[k * 4 + 3], up[3], t);
+                        float t = Cs[k * 4] * L.up[f][0];
+                        t = __builtin_fmaf(Cs[k * 4 + 1], L.up[f][1], t);
+                        t = __builtin_fmaf(Cs[k * 4 + 2], L.up[f][2], t);
+                        t = __builtin_fmaf(Cs[k * 4 + 3], L.up[f][3], t);
                         b[face_vertex(f, k)] -= t;
                     }
                 }
+                const float sig = L.sig;
+                // the next round's inputs are in flight during this round's solve
+                const int pn = pi + NT;
+                if (pn < AG) load_lane(P, K, mask, pn / G, pn % G, psi_o, cell_psi, L);
+
                 // Unpivoted LU, one row of A = B_n + sigma_t M at a time (Doolittle by rows):
                 // row i is reduced by the finished rows k < i; only the strict upper
                 // triangle and the pivots stay live.
@@ -249,38 +352,38 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     for (int j = k + 1; j < 8; ++j) t = __builtin_fmaf(-U[k][j], b[j], t);
                     b[k] = t * inv[k];
                 }
-                float *pk = psi_o + (size_t)K * cell_psi + (size_t)n * G + g;
+                GLOBAL float *pk = psi_o + (size_t)K * cell_psi + (size_t)n * G + g;
                 const float wn = sOm[4 * n + 3];
 #pragma unroll
                 for (int d = 0; d < 8; ++d) {
                     st_agent(pk + (size_t)d * A * G, b[d]);
-                    sW[tid * 8 + d] = wn * b[d];
+                    sWb[tid * 8 + d] = wn * b[d];
                 }
             }
             __syncthreads();
-            // compensated accumulation in increasing angle order, one (group, dof) per reducer
+            // compensated accumulation in increasing angle order, one (group, dof) per reducer;
+            // the other buffer takes the next round's values meanwhile
             const int hi = min(base + NT, AG);
             for (int e = tid; e < G * 8; e += NT) {
                 const int g = e >> 3, d = e & 7;
                 float s = sRs[e], c = sRc[e];
-                int p0 = base + ((g - base % G) % G + G) % G;
-                for (int q = p0; q < hi; q += G) {
+                for (int q = base + ((g - base % G) % G + G) % G; q < hi; q += G) {
                     float t, err;
-                    two_sum(s, sW[(q - base) * 8 + d], t, err);
+                    two_sum(s, sWb[(q - base) * 8 + d], t, err);
                     s = t;
                     c += err;
                 }
                 sRs[e] = s;
                 sRc[e] = c;
             }
-            __syncthreads();
         }
 
+        if (tid == 0) { const unsigned long long t = clock64(); s_ph[3] += t - s_mark; s_mark = t; }
         // ------------------------------------------------------ octant slot
         const size_t sbase = ((size_t)o * C + K) * G * 8;
         for (int e = tid; e < G * 8; e += NT) {
-            P.slot[sbase + e] = sRs[e];
-            P.slotc[sbase + e] = sRc[e];
+            gp(P.slot)[sbase + e] = sRs[e];
+            gp(P.slotc)[sbase + e] = sRc[e];
         }
 
         // --------------------------------------------- publish to downwind
@@ -288,57 +391,82 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         __syncthreads();
         if (tid < 6) {
             const int f = tid;
-            const int N = ((mask >> f) & 1) ? -1 : P.nbr[(size_t)K * 6 + f];
+            const int N = ((mask >> f) & 1) ? -1 : gp(P.nbr)[(size_t)K * 6 + f];
             if (N >= 0) {
-                const unsigned old = __hip_atomic_fetch_add(&P.cnt[(size_t)o * C + N], 1u, __ATOMIC_RELAXED,
+                const unsigned old = __hip_atomic_fetch_add(gp(P.cnt) + (size_t)o * C + N, 1u, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned target = (unsigned)P.indeg[(size_t)o * C + N] * epoch;
-                if (old + 1u == target) {
-                    const unsigned slot = atomicAdd(&ctl->tail, 1u);
-                    const unsigned long long v =
-                        ((unsigned long long)epoch << 32) | (unsigned long long)(P.task_base + (long long)o * C + N);
-                    if ((long long)slot < total)
-                        __hip_atomic_store(&queue[slot], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    else   // more pushes than tasks: counters inconsistent with the DAG
-                        __hip_atomic_store(&ctl->abort, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
+                const unsigned target = (unsigned)gp(P.indeg)[(size_t)o * C + N] * epoch;
+                if (old + 1u == target) s_ready[atomicAdd(&s_nready, 1)] = P.task_base + (long long)o * C + N;
             }
         }
-        ++my_tasks;
         __syncthreads();
+        const int nr = s_nready;
+        cont = nr > 0 ? s_ready[0] : -1;
+        if (tid == 0) s_ph[4] += clock64() - s_mark;
+        if (tid == 0) {
+            ++s_stat[3];
+            ++s_stat[1];
+            // downwind cells are in the same octant, hence in this task's queue
+            const int qo = o % nq;
+            for (int i = 1; i < nr; ++i) {
+                const unsigned slot = atomicAdd(&ctl->q[qo].tail, 1u);
+                const unsigned long long v = ((unsigned long long)epoch << 32) | (unsigned long long)s_ready[i];
+                if ((long long)slot < ctl->qtotal[qo])
+                    __hip_atomic_store(gp(queue) + ctl->qbase[qo] + slot, v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                else   // more pushes than tasks: counters inconsistent with the DAG
+                    __hip_atomic_store(&ctl->abort, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
     }
     if (tid == 0) {
-        atomicAdd(&ctl->polls_empty, my_polls);
-        atomicAdd(&ctl->tasks_done, my_tasks);
+        QueueCtl *Q = &ctl->q[ctl->xcc_queue[xcc_id()]];
+        atomicAdd(&Q->polls_empty, s_stat[0]);
+        atomicAdd(&Q->tasks_done, s_stat[1]);
+        atomicAdd(&Q->continued, s_stat[2]);
+        for (int i = 0; i < 5; ++i) atomicAdd(&Q->phase[i], s_ph[i]);
     }
 }
 
-// Starts a sweep: advances the epoch, empties the queue and pushes the tasks
-// with no interior upwind face (level 0 of every octant).
-__global__ void k_sweep_prologue(QueueCtl *ctl, unsigned long long *queue, const int *__restrict__ seeds, int nseed,
+// Starts a sweep: advances the epoch, empties the queues and pushes the tasks
+// with no interior upwind face (level 0 of every octant) to their queues.
+__global__ void k_sweep_prologue(SweepCtl *ctl, unsigned long long *queue, const int *__restrict__ seeds,
                                  const int *stop_flag) {
     if (stop_flag && *stop_flag) return;
     __shared__ unsigned s_epoch;
     if (threadIdx.x == 0) s_epoch = ctl->epoch + 1u;
     __syncthreads();
     const unsigned e = s_epoch;
-    for (int i = threadIdx.x; i < nseed; i += blockDim.x)
-        queue[i] = ((unsigned long long)e << 32) | (unsigned)seeds[i];
-    if (threadIdx.x == 0) {
-        ctl->epoch = e;
-        ctl->head = 0;
-        ctl->tail = (unsigned)nseed;
-        ctl->polls_empty = 0;
-        ctl->tasks_done = 0;
+    const int nq = ctl->nq;
+    for (int q = 0; q < nq; ++q) {
+        const int b = ctl->qseed_base[q], n = ctl->qseed_count[q];
+        for (int i = threadIdx.x; i < n; i += blockDim.x)
+            queue[ctl->qbase[q] + i] = ((unsigned long long)e << 32) | (unsigned)seeds[b + i];
     }
+    for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+        QueueCtl *Q = &ctl->q[q];
+        Q->head = 0;
+        Q->tail = (unsigned)ctl->qseed_count[q];
+        Q->done = 0;
+        Q->polls_empty = 0;
+        Q->tasks_done = 0;
+        Q->continued = 0;
+        for (int i = 0; i < 5; ++i) Q->phase[i] = 0;
+    }
+    if (threadIdx.x == 0) ctl->epoch = e;
+}
+
+// Records the XCD id each workgroup runs on (set-up probe of the device's XCDs).
+__global__ void k_xcc_probe(int *out) {
+    if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
 }
 
 template <int NT>
-hipError_t launch_nt(const DevProblem *probs, int nprob, const long long *task_base, long long total, QueueCtl *ctl,
+hipError_t launch_nt(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                      unsigned long long *queue, const int *stop_flag, int maxA, int maxG, int maxin, int grid,
                      size_t lds, unsigned long long watchdog, hipStream_t s) {
-    hipLaunchKernelGGL(k_sweep<NT>, dim3(grid), dim3(NT), lds, s, probs, nprob, task_base, total, ctl, queue,
-                       stop_flag, maxA, maxG, maxin, watchdog);
+    hipLaunchKernelGGL(k_sweep<NT>, dim3(grid), dim3(NT), lds, s, probs, nprob, task_base, ctl, queue, stop_flag, maxA,
+                       maxG, maxin, watchdog);
     return hipGetLastError();
 }
 
@@ -349,7 +477,7 @@ const void *kernel_ptr() { return reinterpret_cast<const void *>(&k_sweep<NT>); 
 
 size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin) {
     size_t floats = 64 + 192 + 6 * 48 + 4 * (size_t)maxA + 64 * (size_t)maxA + 16 * (size_t)maxin * maxA +
-                    8 * (size_t)threads + 16 * (size_t)maxG;
+                    16 * (size_t)threads + 16 * (size_t)maxG;
     return floats * sizeof(float);
 }
 
@@ -360,7 +488,6 @@ int sweep_occupancy(int threads, size_t lds) {
         case 128: k = kernel_ptr<128>(); break;
         case 256: k = kernel_ptr<256>(); break;
         case 512: k = kernel_ptr<512>(); break;
-        case 1024: k = kernel_ptr<1024>(); break;
         default: return 0;
     }
     int nb = 0;
@@ -368,22 +495,26 @@ int sweep_occupancy(int threads, size_t lds) {
     return nb;
 }
 
-hipError_t launch_sweep_prologue(QueueCtl *ctl, unsigned long long *queue, const int *seeds, int nseed,
-                                 const int *stop_flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_sweep_prologue, dim3(1), dim3(256), 0, s, ctl, queue, seeds, nseed, stop_flag);
+hipError_t launch_sweep_prologue(SweepCtl *ctl, unsigned long long *queue, const int *seeds, const int *stop_flag,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(k_sweep_prologue, dim3(1), dim3(256), 0, s, ctl, queue, seeds, stop_flag);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, long long total,
-                               QueueCtl *ctl, unsigned long long *queue, const int *stop_flag, int threads, int grid,
-                               int maxA, int maxG, int maxin, unsigned long long watchdog, hipStream_t s) {
+hipError_t launch_xcc_probe(int *out, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_xcc_probe, dim3(nblocks), dim3(64), 0, s, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
+                               unsigned long long *queue, const int *stop_flag, int threads, int grid, int maxA,
+                               int maxG, int maxin, unsigned long long watchdog, hipStream_t s) {
     const size_t lds = sweep_lds_bytes(threads, maxA, maxG, maxin);
     switch (threads) {
-        case 64: return launch_nt<64>(probs, nprob, task_base, total, ctl, queue, stop_flag, maxA, maxG, maxin, grid, lds, watchdog, s);
-        case 128: return launch_nt<128>(probs, nprob, task_base, total, ctl, queue, stop_flag, maxA, maxG, maxin, grid, lds, watchdog, s);
-        case 256: return launch_nt<256>(probs, nprob, task_base, total, ctl, queue, stop_flag, maxA, maxG, maxin, grid, lds, watchdog, s);
-        case 512: return launch_nt<512>(probs, nprob, task_base, total, ctl, queue, stop_flag, maxA, maxG, maxin, grid, lds, watchdog, s);
-        case 1024: return launch_nt<1024>(probs, nprob, task_base, total, ctl, queue, stop_flag, maxA, maxG, maxin, grid, lds, watchdog, s);
+        case 64: return launch_nt<64>(probs, nprob, task_base, ctl, queue, stop_flag, maxA, maxG, maxin, grid, lds, watchdog, s);
+        case 128: return launch_nt<128>(probs, nprob, task_base, ctl, queue, stop_flag, maxA, maxG, maxin, grid, lds, watchdog, s);
+        case 256: return launch_nt<256>(probs, nprob, task_base, ctl, queue, stop_flag, maxA, maxG, maxin, grid, lds, watchdog, s);
+        case 512: return launch_nt<512>(probs, nprob, task_base, ctl, queue, stop_flag, maxA, maxG, maxin, grid, lds, watchdog, s);
         default: return hipErrorInvalidValue;
     }
 }

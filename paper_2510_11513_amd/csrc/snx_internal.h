@@ -15,14 +15,36 @@ constexpr int kMaxAnglesPerOctant = 64;
 constexpr int kMaxGroups = 256;
 constexpr float kInv4Pi = 0.0795774715459476679f;
 
-// Control block of the device task queue of one sweep launch.
-struct QueueCtl {
-    unsigned head;      // next queue slot to pop
-    unsigned tail;      // next queue slot to fill
-    unsigned epoch;     // sweep number since setup (counters count to indeg * epoch)
-    unsigned abort;     // set by a watchdog expiry; every worker then exits
+constexpr int kMaxQueues = 16;   // task queues of a sweep (one per XCD of the device)
+constexpr int kMaxXcc = 32;      // range of hardware XCC ids mapped to queues
+
+// One task queue: octants are assigned to queues (o mod nq), and each queue is
+// served by the workgroups of one XCD, so a sweep's hand-offs stay in that
+// XCD's L2.  128-byte aligned so that queues do not share cache lines.
+struct alignas(128) QueueCtl {
+    unsigned head;      // next slot to pop
+    unsigned tail;      // next slot to fill
+    unsigned done;      // tasks of this queue completed, flushed before a workgroup waits
+    unsigned pad;
     unsigned long long polls_empty;  // polls that found the popped slot not yet filled
-    unsigned long long tasks_done;
+    unsigned long long tasks_done;   // tasks executed (statistics)
+    unsigned long long continued;    // tasks run by the workgroup that made them ready (statistics)
+    unsigned long long phase[5];     // shader-clock cycles summed over workgroups: waiting on the queue,
+                                     // staging, operator build, solve rounds, publishing to downwind
+};
+
+// Control block of one sweep launch.
+struct SweepCtl {
+    unsigned epoch;     // sweep number since setup (counters count to indeg * epoch)
+    unsigned abort;     // set by a watchdog expiry (1) or a queue overflow (2); every worker then exits
+    int nq;             // queues in use
+    int pad;
+    int xcc_queue[kMaxXcc];                 // home queue of the workgroups of each XCC id
+    long long qbase[kMaxQueues];            // first slot of each queue in the slot array
+    long long qtotal[kMaxQueues];           // tasks of each queue per sweep
+    int qseed_base[kMaxQueues];             // first seed of each queue in the seed list
+    int qseed_count[kMaxQueues];
+    QueueCtl q[kMaxQueues];
 };
 
 // Per-problem view used by the device kernels.  All pointers are device memory.
@@ -36,6 +58,7 @@ struct DevProblem {
     const int *nbr;              // [C][6]        neighbour across face, -1 on the boundary
     const unsigned *perm;        // [C][6]        neighbour's local vertex at my face node k, 8 bits each
     const unsigned char *inmask; // [8][C]        inflow-face bit mask per octant
+    const float *T;              // [8][C][3][64] T^a = S^a - sum_{f inflow} F^a_f (embedded), per octant
     const int *indeg;            // [8][C]        interior inflow faces per octant
     const float *sigt;           // [C][G]
     const float *sigs;           // [C][G]
@@ -68,11 +91,14 @@ hipError_t launch_geometry(const double *xyz, const int *cell_vert, const int *n
                            int *err_flag, hipStream_t s);
 hipError_t launch_dag_one(int C, const int *nbr, const double *area, unsigned char *inmask, int *indeg, int *level,
                           int *hist, int *nlev, int *seeds, int *nseed, int *scratch, int *err, hipStream_t s);
-hipError_t launch_sweep_prologue(QueueCtl *ctl, unsigned long long *queue, const int *seeds, int nseed,
-                                 const int *stop_flag, hipStream_t s);
-hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, long long total,
-                               QueueCtl *ctl, unsigned long long *queue, const int *stop_flag, int threads, int grid,
-                               int maxA, int maxG, int maxin, unsigned long long watchdog, hipStream_t s);
+hipError_t launch_sweep_prologue(SweepCtl *ctl, unsigned long long *queue, const int *seeds, const int *stop_flag,
+                                 hipStream_t s);
+hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
+                               unsigned long long *queue, const int *stop_flag, int threads, int grid, int maxA,
+                               int maxG, int maxin, unsigned long long watchdog, hipStream_t s);
+hipError_t launch_xcc_probe(int *out, int nblocks, hipStream_t s);
+hipError_t launch_octant_operators(int C, const float *S, const float *F, const unsigned char *inmask, float *T,
+                                   hipStream_t s);
 size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin);
 int sweep_occupancy(int threads, size_t lds);
 hipError_t launch_source(const DevProblem *probs, int prob, int C, int G, const float *phi, int *stop_flag,

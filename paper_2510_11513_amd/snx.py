@@ -225,6 +225,8 @@ class Problem:
         return ms.value
 
     def sweep_stats(self):
-        out = np.zeros(4, np.int64)
+        out = np.zeros(11, np.int64)
         self._check(load().snx_sweep_stats(self.h, out.ctypes.data_as(ct.c_void_p)), "sweep_stats")
-        return {"tasks": int(out[0]), "empty_polls": int(out[1]), "abort": int(out[2]), "grid": int(out[3])}
+        return {"tasks": int(out[0]), "empty_polls": int(out[1]), "abort": int(out[2]), "grid": int(out[3]),
+                "continued": int(out[4]), "threads": int(out[5]),
+                "cycles": dict(zip(("queue_wait", "stage", "build", "solve", "publish"), map(int, out[6:11])))}
