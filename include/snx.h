@@ -139,10 +139,18 @@ snx_status snx_integrated_flux(snx_problem *p, const float *phi, double *out, vo
 snx_status snx_get_levels(snx_problem *p, int32_t *level, int32_t *nlevels);
 
 /* Sweep schedule knobs: threads per task workgroup (64, 128, 256 or 512,
- * at least G), resident workgroups per CU (capped at the occupancy
- * maximum) and the graph chunk length of snx_solve (iterations captured per
- * host check).  Any argument <= 0 keeps the current value. */
+ * at least G; a (cell, octant) task's (angle, group) solves run 64 per
+ * wavefront), resident workgroups per CU (capped at the occupancy maximum)
+ * and the graph chunk length of snx_solve (iterations captured per host
+ * check).  Any argument <= 0 keeps the current value. */
 snx_status snx_set_schedule(snx_problem *p, int32_t threads, int32_t wg_per_cu, int32_t chunk);
+
+/* Schedule autotuner: times a few sweeps of every (threads, workgroups per
+ * CU) candidate on this problem and keeps the fastest.  cache_path (nullable)
+ * is a text file of JSON lines keyed by device and problem shape: a hit skips
+ * the timing, a miss appends the result.  host chosen[2] (nullable) receives
+ * (threads, workgroups per CU).  Synchronous. */
+snx_status snx_tune(snx_problem *p, const char *cache_path, int32_t *chosen, void *stream);
 
 /* Times the sweep kernel alone: nsweeps source iterations from device phi_in
  * (NULL = zero) into device phi_out, with HIP events recorded on `stream`
@@ -158,6 +166,41 @@ snx_status snx_profile_sweep(snx_problem *p, int32_t nsweeps, const float *phi_i
  * workgroups spent waiting on the queue, staging cell data, building the
  * per-angle operators, solving, and publishing to downwind cells.  Synchronous. */
 snx_status snx_sweep_stats(snx_problem *p, int64_t *out);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent problems (uneven sizes, group and angle counts) share one
+ * persistent sweep launch per source iteration: their (cell, octant) tasks are
+ * interleaved in the same device queues, and snx_batch_solve replays one
+ * graph-captured chunk of iterations for all of them, retiring each problem
+ * from later sweeps once it has converged.  The problems must have been set up
+ * (snx_setup) on one device and must outlive the batch; a batch never changes
+ * a problem's data, only its sweep counters and flux buffers. */
+
+/* Create a batch over n set-up problems.  Errors: SNX_E_ARG, SNX_E_STATE,
+ * SNX_E_OOM; the message is available from snx_batch_last_error(NULL). */
+snx_status snx_batch_create(snx_batch **out, int32_t n, snx_problem *const *probs);
+void snx_batch_destroy(snx_batch *b);
+const char *snx_batch_last_error(const snx_batch *b);
+/* As snx_set_schedule, with threads at least the largest G of the batch. */
+snx_status snx_batch_set_schedule(snx_batch *b, int32_t threads, int32_t wg_per_cu, int32_t chunk);
+/* As snx_tune, over the whole batch. */
+snx_status snx_batch_tune(snx_batch *b, const char *cache_path, int32_t *chosen, void *stream);
+/* One source iteration of every problem: host arrays of n device pointers
+ * phi_in (nullable array, nullable entries = zero flux) and phi_out.
+ * Synchronous. */
+snx_status snx_batch_sweep(snx_batch *b, const float *const *phi_in, float *const *phi_out, void *stream);
+/* Source iteration of every problem to tol or max_it, as snx_solve; host
+ * arrays of n device pointers phi0 (nullable array or entries = zero start)
+ * and phi; host infos[n] (nullable).  Returns SNX_E_NOCONV when any problem
+ * stopped at max_it.  Synchronous. */
+snx_status snx_batch_solve(snx_batch *b, double tol, int32_t max_it, const float *const *phi0, float *const *phi,
+                           snx_solve_info *infos, void *stream);
+/* Mean duration (ms) of the batch's sweep kernel over nsweeps sweeps of every
+ * problem, from HIP events on stream (the sources in place are reused).
+ * Synchronous. */
+snx_status snx_batch_profile_sweep(snx_batch *b, int32_t nsweeps, double *ms, void *stream);
+/* As snx_sweep_stats, for the most recent sweep of the batch. */
+snx_status snx_batch_stats(snx_batch *b, int64_t *out);
 
 #ifdef __cplusplus
 }

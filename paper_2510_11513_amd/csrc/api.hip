@@ -1,12 +1,20 @@
-// C ABI of the gfx950 S_N sweep library: problem state, set-up orchestration,
-// sweep and the graph-captured source-iteration loop.
+// C ABI of the gfx950 S_N sweep library: problems, batches, the sweep schedule,
+// the graph-captured source-iteration loop and the schedule autotuner.
+//
+// A schedule drives one persistent sweep launch over one or more problems:
+// the merged problem table, the task queues (one per XCD), the seeds and the
+// per-problem iteration records.  A problem owns a schedule of one; a batch
+// owns a schedule over its problems, so many uneven problems share every
+// launch of the graph-captured loop, and a converged problem simply stops
+// contributing tasks to later sweeps.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
 
 #include "snx_internal.h"
-
 
 using namespace snx;
 
@@ -28,27 +36,62 @@ struct DevAlloc {
     }
 };
 
+int cu_count(int device) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n <= 0) n = 256;
+    return n;
+}
+
 }  // namespace
 
-// Everything one sweep schedule needs: the merged problem table, the queue and
-// the seed tasks.  A single problem is a schedule of one.
-struct SweepSched {
+// ----------------------------------------------------------------- schedule
+
+struct Sched {
+    int device = 0;
+    std::vector<snx_problem *> probs;        // not owned
+    DevAlloc mem;
     DevProblem *d_probs = nullptr;
-    long long *d_base = nullptr;
+    long long *d_base = nullptr;             // [nprob + 1] first task of each problem
     SweepCtl *d_ctl = nullptr;
-    SweepCtl host_ctl{};                 // static part (queue layout, seeds, XCC map) uploaded on reset
-    unsigned long long *d_queue = nullptr;
-    int *d_seeds = nullptr;
-    int nprob = 0, nseed = 0;
+    unsigned long long *d_queue = nullptr;   // [total] slots, queue q from host_ctl.qbase[q]
+    int *d_seeds = nullptr, *d_seed_off = nullptr;
+    int *d_blk_base = nullptr;               // [nprob + 1] reduce blocks per problem
+    int nblk = 0;
+    float **d_buf = nullptr;                 // [2][nprob] ping-pong flux buffers of the problems
+    float **d_user = nullptr;                // [2][nprob] caller pointers of the current call
+    IterCtl *d_ic = nullptr;                 // [nprob]
+    int *d_stop = nullptr;                   // [nprob]
+    void *pinned = nullptr;                  // host staging: pointer arrays and read-backs
+    SweepCtl host_ctl{};
+    std::vector<DevProblem> hprobs;
     long long total = 0;
-    int maxA = 0, maxG = 0, maxin = 0;
-    int threads = 256, wg_per_cu = 0, grid = 0;
+    int maxA = 0, maxG = 0, maxin = 1;
+    int threads = 256, wg_per_cu = 0, grid = 0, chunk = 8;
+    unsigned long long watchdog = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};   // chunk starting from ping-pong buffer 0 / 1
+    std::string err;
+
+    int nprob() const { return (int)probs.size(); }
+    void drop_graphs() {
+        for (auto &g : graph) {
+            if (g) (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    }
+    void release() {
+        drop_graphs();
+        mem.release();
+        if (pinned) (void)hipHostFree(pinned);
+        pinned = nullptr;
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        cap_stream = nullptr;
+    }
 };
 
 struct snx_problem {
     int device = 0;
     std::string err;
-    hipStream_t cap_stream = nullptr;
     void *pinned = nullptr;            // host staging for small read-backs
 
     // host inputs
@@ -61,107 +104,440 @@ struct snx_problem {
     bool ready = false;
     DevAlloc mem;
     DevProblem hp{};
-    SweepSched sched;
     std::vector<int> level, nlev;
+    std::vector<std::vector<int>> seeds_by_octant;   // local task ids (o*C + K) of level-0 cells
+    int maxin = 1;
     int *d_err = nullptr;
-    IterCtl *d_ic = nullptr;
-    int *d_stop = nullptr;
     float *d_phi[2] = {nullptr, nullptr};
     double *d_partial = nullptr, *d_out4 = nullptr;
     double *d_area = nullptr;
     unsigned long long watchdog_ticks = 0;
-    int chunk = 8;
-    int threads = 256, wg_per_cu = 0;   // requested sweep schedule
+    int threads = 256, wg_per_cu = 0, chunk = 8;   // requested sweep schedule
     int nq = 1;                         // task queues = XCDs seen on the device
     int xcc_queue[kMaxXcc] = {0};       // home queue of each hardware XCC id
-
-    hipGraphExec_t graph[2] = {nullptr, nullptr};   // chunk starting from ping-pong buffer 0 / 1
+    Sched sched;                        // the problem's own schedule of one
 };
 
-static snx_status fail(snx_problem *p, snx_status code, const std::string &msg) {
+struct snx_batch {
+    int device = 0;
+    Sched sched;
+    int threads = 256, wg_per_cu = 0, chunk = 8;
+};
+
+namespace {
+
+snx_status fail_msg(std::string &err, snx_status code, const std::string &msg) {
+    err = msg;
+    return code;
+}
+snx_status fail(snx_problem *p, snx_status code, const std::string &msg) {
     if (p) p->err = msg;
     return code;
 }
-
-static snx_status hip_fail(snx_problem *p, hipError_t e, const char *what) {
-    return fail(p, e == hipErrorOutOfMemory ? SNX_E_OOM : SNX_E_DEVICE,
-                std::string(what) + ": " + hipGetErrorString(e));
+snx_status hip_fail_msg(std::string &err, hipError_t e, const char *what) {
+    return fail_msg(err, e == hipErrorOutOfMemory ? SNX_E_OOM : SNX_E_DEVICE,
+                    std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIPCHK(p, expr, what)                                   \
-    do {                                                        \
-        hipError_t e_ = (expr);                                 \
-        if (e_ != hipSuccess) return hip_fail((p), e_, (what)); \
+#define HIPCHK_E(err, expr, what)                                      \
+    do {                                                               \
+        hipError_t e_ = (expr);                                        \
+        if (e_ != hipSuccess) return hip_fail_msg((err), e_, (what));  \
     } while (0)
+#define HIPCHK(p, expr, what) HIPCHK_E((p)->err, expr, what)
 
-static void drop_graph(snx_problem *p) {
-    for (auto &g : p->graph) {
-        if (g) (void)hipGraphExecDestroy(g);
-        g = nullptr;
-    }
-}
-
-static void drop_device(snx_problem *p) {
-    drop_graph(p);
+void drop_device(snx_problem *p) {
+    p->sched.release();
+    p->sched = Sched{};
     p->mem.release();
     p->ready = false;
     p->hp = DevProblem{};
-    p->sched = SweepSched{};
 }
 
-// Zero the scheduler state: counters, epoch, queue slots, abort flag and queue
-// statistics, and upload the static queue layout.
-static hipError_t reset_schedule(snx_problem *p, hipStream_t s) {
-    hipError_t e = launch_fill_u32(p->hp.cnt, (size_t)8 * p->C, 0u, s);
-    if (e == hipSuccess) e = hipMemsetAsync(p->sched.d_queue, 0, sizeof(unsigned long long) * (size_t)p->sched.total, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(p->sched.d_ctl, &p->sched.host_ctl, sizeof(SweepCtl), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    return e;
-}
-
-// Queue layout of a sweep: octant o goes to queue o mod nq; each queue's slots
-// hold every task of its octants, seeds first.
-static void layout_queues(SweepCtl &c, int nq, const int *xcc_queue, const std::vector<long long> &cells_per_problem,
-                          const std::vector<std::vector<int>> &seeds_by_octant, std::vector<int> &seeds) {
-    c = SweepCtl{};
-    c.nq = nq;
-    for (int x = 0; x < kMaxXcc; ++x) c.xcc_queue[x] = xcc_queue[x];
-    long long base = 0;
-    seeds.clear();
-    for (int q = 0; q < nq; ++q) {
-        long long tot = 0;
-        c.qseed_base[q] = (int)seeds.size();
-        for (int o = q; o < 8; o += nq) {
-            for (long long cp : cells_per_problem) tot += cp;
-            seeds.insert(seeds.end(), seeds_by_octant[o].begin(), seeds_by_octant[o].end());
-        }
-        c.qseed_count[q] = (int)seeds.size() - c.qseed_base[q];
-        c.qbase[q] = base;
-        c.qtotal[q] = tot;
-        base += tot;
-    }
-}
-
-static int cu_count(int device) {
-    int n = 0;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n <= 0) n = 256;
-    return n;
-}
-
-static snx_status configure_grid(snx_problem *p, SweepSched &sc) {
+// Grid of the persistent sweep: resident workgroups per CU times the CUs.
+snx_status configure_grid(Sched &sc) {
     const size_t lds = sweep_lds_bytes(sc.threads, sc.maxA, sc.maxG, sc.maxin);
-    if (lds > 64 * 1024) return fail(p, SNX_E_ARG, "task does not fit in 64 KB of LDS (too many angles or groups)");
-    int occ = sweep_occupancy(sc.threads, lds);
-    if (occ <= 0) return fail(p, SNX_E_ARG, "sweep kernel cannot be resident with this schedule");
-    int per_cu = sc.wg_per_cu > 0 ? std::min(sc.wg_per_cu, occ) : occ;
-    long long grid = (long long)cu_count(p->device) * per_cu;
+    if (lds > 64 * 1024) return fail_msg(sc.err, SNX_E_ARG, "task does not fit in 64 KB of LDS (too many angles or groups)");
+    const int occ = sweep_occupancy(sc.threads, lds);
+    if (occ <= 0) return fail_msg(sc.err, SNX_E_ARG, "sweep kernel cannot be resident with this schedule");
+    const int per_cu = sc.wg_per_cu > 0 ? std::min(sc.wg_per_cu, occ) : occ;
+    long long grid = (long long)cu_count(sc.device) * per_cu;
     if (grid > sc.total) grid = sc.total;
     sc.grid = (int)std::max(1LL, grid);
     return SNX_OK;
 }
 
+// Zero the scheduler state of every problem of the schedule (counters, epochs)
+// and of the schedule (queue slots, abort flag, statistics); upload the layout.
+hipError_t reset_schedule(Sched &sc, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (const DevProblem &P : sc.hprobs) {
+        if (e == hipSuccess) e = launch_fill_u32(P.cnt, (size_t)8 * P.C, 0u, s);
+        if (e == hipSuccess) e = launch_fill_u32(P.epoch, 1, 0u, s);
+    }
+    if (e == hipSuccess) e = hipMemsetAsync(sc.d_queue, 0, sizeof(unsigned long long) * (size_t)sc.total, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(sc.d_ctl, &sc.host_ctl, sizeof(SweepCtl), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+}
+
+// Builds a schedule over set-up problems (all on one device).
+snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int threads, int wg_per_cu, int chunk,
+                       hipStream_t s) {
+    sc.release();
+    sc.probs = probs;
+    snx_problem *p0 = probs[0];
+    sc.device = p0->device;
+    sc.watchdog = p0->watchdog_ticks;
+    const int n = (int)probs.size();
+    HIPCHK_E(sc.err, hipStreamCreateWithFlags(&sc.cap_stream, hipStreamNonBlocking), "stream");
+    HIPCHK_E(sc.err, hipHostMalloc(&sc.pinned, 64 * (size_t)n + 4096, hipHostMallocDefault), "pinned");
+
+    sc.hprobs.clear();
+    std::vector<long long> base(n + 1, 0);
+    std::vector<int> blk(n + 1, 0), seed_off(8 * n + 1, 0), seeds;
+    sc.maxA = sc.maxG = 0;
+    sc.maxin = 1;
+    for (int i = 0; i < n; ++i) {
+        snx_problem *p = probs[i];
+        DevProblem P = p->hp;
+        P.task_base = base[i];
+        sc.hprobs.push_back(P);
+        base[i + 1] = base[i] + 8LL * p->C;
+        blk[i + 1] = blk[i] + (int)(((long long)p->C * p->G + 255) / 256);
+        sc.maxA = std::max(sc.maxA, p->A);
+        sc.maxG = std::max(sc.maxG, p->G);
+        sc.maxin = std::max(sc.maxin, p->maxin);
+        for (int o = 0; o < 8; ++o) {
+            seed_off[i * 8 + o] = (int)seeds.size();
+            seeds.insert(seeds.end(), p->seeds_by_octant[o].begin(), p->seeds_by_octant[o].end());
+        }
+    }
+    seed_off[8 * n] = (int)seeds.size();
+    sc.total = base[n];
+    sc.nblk = blk[n];
+    sc.threads = threads;
+    while (sc.threads < sc.maxG) sc.threads *= 2;
+    sc.wg_per_cu = wg_per_cu;
+    sc.chunk = chunk;
+
+    // queue layout: octant o to queue o mod nq; each queue can hold all tasks of its octants
+    SweepCtl &c = sc.host_ctl;
+    c = SweepCtl{};
+    c.nq = p0->nq;
+    for (int x = 0; x < kMaxXcc; ++x) c.xcc_queue[x] = p0->xcc_queue[x];
+    long long qb = 0;
+    for (int q = 0; q < c.nq; ++q) {
+        long long tot = 0;
+        for (int o = q; o < 8; o += c.nq)
+            for (snx_problem *p : probs) tot += p->C;
+        c.qbase[q] = qb;
+        c.qtotal[q] = tot;
+        qb += tot;
+    }
+
+    DevAlloc &m = sc.mem;
+#define SALLOC(ptr, bytes) HIPCHK_E(sc.err, m.alloc((void **)&(ptr), (bytes)), "device allocation")
+    SALLOC(sc.d_probs, sizeof(DevProblem) * n);
+    SALLOC(sc.d_base, sizeof(long long) * (n + 1));
+    SALLOC(sc.d_ctl, sizeof(SweepCtl));
+    SALLOC(sc.d_queue, sizeof(unsigned long long) * sc.total);
+    SALLOC(sc.d_seeds, sizeof(int) * std::max<size_t>(1, seeds.size()));
+    SALLOC(sc.d_seed_off, sizeof(int) * (8 * n + 1));
+    SALLOC(sc.d_blk_base, sizeof(int) * (n + 1));
+    SALLOC(sc.d_buf, sizeof(float *) * 2 * n);
+    SALLOC(sc.d_user, sizeof(float *) * 2 * n);
+    SALLOC(sc.d_ic, sizeof(IterCtl) * n);
+    SALLOC(sc.d_stop, sizeof(int) * n);
+#undef SALLOC
+    std::vector<float *> bufs(2 * n);
+    for (int i = 0; i < n; ++i) {
+        bufs[i] = probs[i]->d_phi[0];
+        bufs[n + i] = probs[i]->d_phi[1];
+    }
+    HIPCHK_E(sc.err, hipMemcpy(sc.d_probs, sc.hprobs.data(), sizeof(DevProblem) * n, hipMemcpyHostToDevice), "copy");
+    HIPCHK_E(sc.err, hipMemcpy(sc.d_base, base.data(), sizeof(long long) * (n + 1), hipMemcpyHostToDevice), "copy");
+    if (!seeds.empty())
+        HIPCHK_E(sc.err, hipMemcpy(sc.d_seeds, seeds.data(), sizeof(int) * seeds.size(), hipMemcpyHostToDevice), "copy");
+    HIPCHK_E(sc.err, hipMemcpy(sc.d_seed_off, seed_off.data(), sizeof(int) * (8 * n + 1), hipMemcpyHostToDevice), "copy");
+    HIPCHK_E(sc.err, hipMemcpy(sc.d_blk_base, blk.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice), "copy");
+    HIPCHK_E(sc.err, hipMemcpy(sc.d_buf, bufs.data(), sizeof(float *) * 2 * n, hipMemcpyHostToDevice), "copy");
+    HIPCHK_E(sc.err, hipMemset(sc.d_stop, 0, sizeof(int) * n), "memset");
+    HIPCHK_E(sc.err, reset_schedule(sc, s), "reset");
+    return configure_grid(sc);
+}
+
+// Prologue and persistent sweep of the schedule; events (optional) bracket the
+// sweep kernel alone.
+snx_status enqueue_sweep(Sched &sc, const int *stops, hipStream_t s, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr) {
+    HIPCHK_E(sc.err, launch_sweep_prologue(sc.d_ctl, sc.d_queue, sc.d_probs, sc.nprob(), sc.d_seeds, sc.d_seed_off,
+                                           stops, s), "sweep prologue");
+    if (ev0) HIPCHK_E(sc.err, hipEventRecord(ev0, s), "event");
+    HIPCHK_E(sc.err, launch_sweep_kernel(sc.d_probs, sc.nprob(), sc.d_base, sc.d_ctl, sc.d_queue, sc.threads, sc.grid,
+                                         sc.maxA, sc.maxG, sc.maxin, sc.watchdog, s), "sweep launch");
+    if (ev1) HIPCHK_E(sc.err, hipEventRecord(ev1, s), "event");
+    return SNX_OK;
+}
+
+// Uploads caller pointers: d_user[0][p] = a[p], d_user[1][p] = b[p] (either array may be NULL).
+snx_status upload_user(Sched &sc, const float *const *a, const float *const *b, hipStream_t s) {
+    const int n = sc.nprob();
+    const float **h = reinterpret_cast<const float **>(sc.pinned);
+    HIPCHK_E(sc.err, hipStreamSynchronize(s), "sync");        // the staging area may still be read
+    for (int i = 0; i < n; ++i) {
+        h[i] = a ? a[i] : nullptr;
+        h[n + i] = b ? b[i] : nullptr;
+    }
+    HIPCHK_E(sc.err, hipMemcpyAsync(sc.d_user, h, sizeof(float *) * 2 * n, hipMemcpyHostToDevice, s), "copy");
+    HIPCHK_E(sc.err, hipStreamSynchronize(s), "sync");
+    return SNX_OK;
+}
+
+// One source iteration of every problem: source from d_user[0], sweep, reduction into d_user[1].
+snx_status sched_sweep(Sched &sc, const float *const *phi_in, float *const *phi_out, hipStream_t s) {
+    snx_status st = upload_user(sc, phi_in, phi_out, s);
+    if (st) return st;
+    const int n = sc.nprob();
+    HIPCHK_E(sc.err, launch_iter_init_batch(sc.d_ic, sc.d_stop, n, 1, 0.0, s), "init");
+    HIPCHK_E(sc.err, launch_source_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_user, nullptr, s), "source");
+    st = enqueue_sweep(sc, nullptr, s);
+    if (st) return st;
+    HIPCHK_E(sc.err, launch_reduce_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_user + n, nullptr, 0, nullptr,
+                                         sc.d_stop, s), "reduce");
+    return SNX_OK;
+}
+
+// Captures `chunk` source iterations whose first one reads ping-pong buffer `parity`.
+snx_status build_graph(Sched &sc, int parity) {
+    hipStream_t cs = sc.cap_stream;
+    const int n = sc.nprob();
+    HIPCHK_E(sc.err, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+    snx_status st = SNX_OK;
+    for (int i = 0; i < sc.chunk && !st; ++i) {
+        st = enqueue_sweep(sc, sc.d_stop, cs);
+        if (!st) {
+            const int cur = (parity + i) & 1;
+            hipError_t e = launch_reduce_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_buf + (cur ^ 1) * n,
+                                               sc.d_buf + cur * n, 1, sc.d_ic, sc.d_stop, cs);
+            if (e != hipSuccess) st = hip_fail_msg(sc.err, e, "reduce launch");
+        }
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    if (st) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) return hip_fail_msg(sc.err, e, "end capture");
+    e = hipGraphInstantiate(&sc.graph[parity], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail_msg(sc.err, e, "graph instantiate");
+    return SNX_OK;
+}
+
+// Source iteration of every problem of the schedule until each one's FP64
+// relative change is <= tol or max_it; graph replays of `chunk` iterations,
+// with converged problems retired from later sweeps.
+snx_status sched_solve(Sched &sc, double tol, int max_it, const float *const *phi0, float *const *phi,
+                       snx_solve_info *infos, hipStream_t s) {
+    const int n = sc.nprob();
+    const auto t0 = std::chrono::steady_clock::now();
+    snx_status st = upload_user(sc, phi0, nullptr, s);
+    if (st) return st;
+    HIPCHK_E(sc.err, launch_iter_init_batch(sc.d_ic, sc.d_stop, n, max_it, tol, s), "init");
+    HIPCHK_E(sc.err, launch_copy_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_buf, sc.d_user, s), "copy");
+    HIPCHK_E(sc.err, launch_source_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_buf, nullptr, s), "source");
+    char *pin = reinterpret_cast<char *>(sc.pinned);
+    IterCtl *hic = reinterpret_cast<IterCtl *>(pin + 16 * (size_t)n);
+    int *hstop = reinterpret_cast<int *>(pin + 64 * (size_t)n);
+    unsigned *habort = reinterpret_cast<unsigned *>(pin + 64 * (size_t)n + 2048);
+    static_assert(sizeof(IterCtl) <= 48, "IterCtl staging");
+    const long long max_launch = (max_it + sc.chunk - 1) / sc.chunk + 1;
+    int done_iters = 0;
+    for (long long l = 0; l < max_launch; ++l) {
+        const int parity = done_iters & 1;
+        if (!sc.graph[parity]) {
+            st = build_graph(sc, parity);
+            if (st) return st;
+        }
+        HIPCHK_E(sc.err, hipGraphLaunch(sc.graph[parity], s), "graph launch");
+        HIPCHK_E(sc.err, hipMemcpyAsync(hstop, sc.d_stop, sizeof(int) * n, hipMemcpyDeviceToHost, s), "copy");
+        HIPCHK_E(sc.err, hipMemcpyAsync(habort, &sc.d_ctl->abort, sizeof(unsigned), hipMemcpyDeviceToHost, s), "copy");
+        HIPCHK_E(sc.err, hipStreamSynchronize(s), "solve");
+        if (*habort) {
+            (void)reset_schedule(sc, s);
+            return fail_msg(sc.err, SNX_E_DEVICE, "sweep watchdog expired (no ready task)");
+        }
+        bool all = true;
+        for (int i = 0; i < n; ++i) all = all && hstop[i];
+        if (all) break;
+        // every problem still running has done chunk more iterations
+        done_iters += sc.chunk;
+    }
+    HIPCHK_E(sc.err, hipMemcpyAsync(hic, sc.d_ic, sizeof(IterCtl) * n, hipMemcpyDeviceToHost, s), "copy");
+    HIPCHK_E(sc.err, hipStreamSynchronize(s), "solve");
+    // each problem's final iterate sits in buffer (its iterations mod 2)
+    std::vector<const float *> src(n);
+    for (int i = 0; i < n; ++i) src[i] = sc.probs[i]->d_phi[hic[i].iter & 1];
+    std::vector<IterCtl> ic(hic, hic + n);
+    std::vector<int> stops(hstop, hstop + n);
+    st = upload_user(sc, src.data(), phi, s);
+    if (st) return st;
+    HIPCHK_E(sc.err, launch_copy_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_user + n, sc.d_user, s), "copy");
+    HIPCHK_E(sc.err, hipStreamSynchronize(s), "solve");
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    bool conv = true;
+    for (int i = 0; i < n; ++i) {
+        conv = conv && stops[i] == 1;
+        if (infos) {
+            const snx_problem *p = sc.probs[i];
+            infos[i].iterations = ic[i].iter;
+            infos[i].status = stops[i] == 1 ? SNX_OK : SNX_E_NOCONV;
+            infos[i].residual = ic[i].last_eps;
+            infos[i].wall_ms = ms;
+            infos[i].solves_per_s = ms > 0 ? (double)ic[i].iter * p->C * p->nang * p->G / (ms * 1e-3) : 0.0;
+        }
+    }
+    return conv ? SNX_OK : fail_msg(sc.err, SNX_E_NOCONV, "max_it reached before the tolerance");
+}
+
+// Statistics of the most recent sweep of the schedule (see snx_sweep_stats).
+snx_status sched_stats(Sched &sc, int64_t *out) {
+    std::vector<SweepCtl> h(1);
+    HIPCHK_E(sc.err, hipDeviceSynchronize(), "sync");
+    HIPCHK_E(sc.err, hipMemcpy(h.data(), sc.d_ctl, sizeof(SweepCtl), hipMemcpyDeviceToHost), "copy");
+    for (int i = 0; i < 11; ++i) out[i] = 0;
+    for (int q = 0; q < h[0].nq; ++q) {
+        const QueueCtl &Q = h[0].q[q];
+        out[0] += (int64_t)Q.tasks_done;
+        out[1] += (int64_t)Q.polls_empty;
+        out[4] += (int64_t)Q.continued;
+        for (int i = 0; i < 5; ++i) out[6 + i] += (int64_t)Q.phase[i];
+    }
+    out[2] = (int64_t)h[0].abort;
+    out[3] = (int64_t)sc.grid;
+    out[5] = (int64_t)sc.threads;
+    return SNX_OK;
+}
+
+// Mean duration (ms) of the sweep kernel over `reps` sweeps, from events on s.
+snx_status time_sweeps(Sched &sc, int reps, hipStream_t s, double *ms) {
+    std::vector<hipEvent_t> ev(2 * reps, nullptr);
+    snx_status st = SNX_OK;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) { st = fail_msg(sc.err, SNX_E_DEVICE, "hipEventCreate failed"); break; }
+    for (int i = 0; i < reps && !st; ++i) st = enqueue_sweep(sc, nullptr, s, ev[2 * i], ev[2 * i + 1]);
+    if (!st && hipStreamSynchronize(s) != hipSuccess) st = fail_msg(sc.err, SNX_E_DEVICE, "sync failed");
+    double total = 0.0;
+    for (int i = 0; i < reps && !st; ++i) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) != hipSuccess) st = fail_msg(sc.err, SNX_E_DEVICE, "event");
+        total += t;
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (!st) *ms = total / reps;
+    return st;
+}
+
+// ---------------------------------------------------------------- autotuner
+//
+// The schedule's knobs are the workgroup width (threads, i.e. how many of a
+// task's (angle, group) solves run side by side: 64 per wavefront) and the
+// resident workgroups per CU.  The tuner times a few sweeps of every candidate
+// on the actual problems and keeps the fastest; results are cached in a text
+// file of JSON lines keyed by device and problem shape.
+
+std::string tune_key(const Sched &sc) {
+    hipDeviceProp_t prop{};
+    (void)hipGetDeviceProperties(&prop, sc.device);
+    long long cells = 0, solves = 0;
+    for (const snx_problem *p : sc.probs) {
+        cells += p->C;
+        solves += (long long)p->C * p->nang * p->G;
+    }
+    int cb = 0, sb = 0;   // size buckets: log2 of cells and solves
+    while ((1LL << (cb + 1)) <= cells) ++cb;
+    while ((1LL << (sb + 1)) <= solves) ++sb;
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s|cu%d|np%d|A%d|G%d|c%d|s%d", prop.gcnArchName, cu_count(sc.device),
+                  sc.nprob(), sc.maxA, sc.maxG, cb, sb);
+    return buf;
+}
+
+bool cache_lookup(const char *path, const std::string &key, int &threads, int &wg) {
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[300];
+        int t = 0, w = 0;
+        if (std::sscanf(line, "{\"key\": \"%299[^\"]\", \"threads\": %d, \"wg_per_cu\": %d", k, &t, &w) == 3 &&
+            key == k) {
+            threads = t;
+            wg = w;
+            found = true;   // the last entry for a key wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, int threads, int wg, double ms) {
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"wg_per_cu\": %d, \"ms\": %.6f}\n", key.c_str(), threads, wg,
+                 ms);
+    std::fclose(f);
+}
+
+snx_status tune_sched(Sched &sc, const char *cache, hipStream_t s, int *out_threads, int *out_wg, double *out_ms) {
+    const std::string key = tune_key(sc);
+    int t = 0, w = 0;
+    if (cache_lookup(cache, key, t, w) && t >= sc.maxG) {
+        sc.threads = t;
+        sc.wg_per_cu = w;
+        sc.drop_graphs();
+        if (!configure_grid(sc)) {
+            *out_threads = t;
+            *out_wg = w;
+            *out_ms = -1.0;
+            return SNX_OK;
+        }
+    }
+    double best = 1e300;
+    int bt = sc.threads, bw = sc.wg_per_cu;
+    for (int th : {64, 128, 256, 512}) {
+        if (th < sc.maxG) continue;
+        for (int wg : {0, 2, 4, 8}) {
+            sc.threads = th;
+            sc.wg_per_cu = wg;
+            if (configure_grid(sc)) continue;
+            double ms = 0.0;
+            snx_status st = time_sweeps(sc, 1, s, &ms);           // warm-up
+            if (!st) st = time_sweeps(sc, 3, s, &ms);
+            if (st) return st;
+            if (ms < best) { best = ms; bt = th; bw = wg; }
+        }
+    }
+    sc.threads = bt;
+    sc.wg_per_cu = bw;
+    sc.drop_graphs();
+    snx_status st = configure_grid(sc);
+    if (st) return st;
+    cache_store(cache, key, bt, bw, best);
+    *out_threads = bt;
+    *out_wg = bw;
+    *out_ms = best;
+    return SNX_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+// ----------------------------------------------------------------- problems
 
 snx_status snx_create(snx_problem **out, int32_t device) {
     if (!out) { g_create_error = "out is NULL"; return SNX_E_ARG; }
@@ -175,30 +551,27 @@ snx_status snx_create(snx_problem **out, int32_t device) {
     if (!p) { g_create_error = "out of host memory"; return SNX_E_OOM; }
     p->device = device;
     hipError_t e = hipSetDevice(device);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipHostMalloc(&p->pinned, 4096, hipHostMallocDefault);
     if (e != hipSuccess) {
         g_create_error = std::string("HIP initialisation failed: ") + hipGetErrorString(e);
-        if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
         delete p;
         return SNX_E_DEVICE;
     }
     int rate_khz = 0;
     if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || rate_khz <= 0)
         rate_khz = 100000;
+    p->watchdog_ticks = (unsigned long long)rate_khz * 1000ull * 20ull;   // 20 s without a ready task
     // Which XCDs do workgroups land on?  Each distinct XCC id becomes one task queue.
     {
         const int nb = 8 * cu_count(device);
         int *d_ids = nullptr;
         std::vector<int> ids(nb, 0);
         e = hipMalloc((void **)&d_ids, sizeof(int) * nb);
-        if (e == hipSuccess) e = launch_xcc_probe(d_ids, nb, p->cap_stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(ids.data(), d_ids, sizeof(int) * nb, hipMemcpyDeviceToHost, p->cap_stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(p->cap_stream);
+        if (e == hipSuccess) e = launch_xcc_probe(d_ids, nb, nullptr);
+        if (e == hipSuccess) e = hipMemcpy(ids.data(), d_ids, sizeof(int) * nb, hipMemcpyDeviceToHost);
         if (d_ids) (void)hipFree(d_ids);
         if (e != hipSuccess) {
             g_create_error = std::string("XCD probe failed: ") + hipGetErrorString(e);
-            (void)hipStreamDestroy(p->cap_stream);
             (void)hipHostFree(p->pinned);
             delete p;
             return SNX_E_DEVICE;
@@ -210,7 +583,6 @@ snx_status snx_create(snx_problem **out, int32_t device) {
             if (seen[x] && nq < kMaxQueues) p->xcc_queue[x] = nq++;
         p->nq = std::max(1, nq);
     }
-    p->watchdog_ticks = (unsigned long long)rate_khz * 1000ull * 20ull;   // 20 s without a ready task
     *out = p;
     return SNX_OK;
 }
@@ -220,7 +592,6 @@ void snx_destroy(snx_problem *p) {
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
     drop_device(p);
-    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     if (p->pinned) (void)hipHostFree(p->pinned);
     delete p;
 }
@@ -315,8 +686,8 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     DevAlloc &m = p->mem;
     DevProblem &hp = p->hp;
     double *d_xyz; int *d_cv, *d_nbr, *d_nbrf; unsigned *d_perm;
-    float *dM, *dS, *dF, *dsigt, *dsigs, *dq, *dr, *dom, *dw, *dpsib = nullptr, *dpsi, *dslot, *dslotc;
-    unsigned char *dmask; int *dindeg, *dlevel, *dhist, *dnlev, *dseeds, *dnseed, *dscratch; unsigned *dcnt;
+    float *dM, *dS, *dT, *dF, *dsigt, *dsigs, *dq, *dr, *dom, *dw, *dpsib = nullptr, *dpsi, *dslot, *dslotc;
+    unsigned char *dmask; int *dindeg, *dlevel, *dhist, *dnlev, *dseeds, *dnseed, *dscratch; unsigned *dcnt, *depoch;
 #define ALLOC(ptr, bytes) HIPCHK(p, m.alloc((void **)&(ptr), (bytes)), "device allocation")
     ALLOC(d_xyz, sizeof(double) * 3 * p->nvert);
     ALLOC(d_cv, sizeof(int) * 8 * C);
@@ -325,7 +696,6 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     ALLOC(d_perm, sizeof(unsigned) * 6 * C);
     ALLOC(dM, sizeof(float) * 64 * C);
     ALLOC(dS, sizeof(float) * 192 * C);
-    float *dT;
     ALLOC(dT, sizeof(float) * 8 * 192 * C);
     ALLOC(dF, sizeof(float) * 288 * C);
     ALLOC(p->d_area, sizeof(double) * 18 * C);
@@ -349,25 +719,19 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     ALLOC(dslot, sizeof(float) * 8 * C * G * 8);
     ALLOC(dslotc, sizeof(float) * 8 * C * G * 8);
     ALLOC(dcnt, sizeof(unsigned) * 8 * C);
-    ALLOC(p->d_ic, sizeof(IterCtl));
-    ALLOC(p->d_stop, sizeof(int));
+    ALLOC(depoch, sizeof(unsigned));
     ALLOC(p->d_phi[0], sizeof(float) * C * G * 8);
     ALLOC(p->d_phi[1], sizeof(float) * C * G * 8);
     ALLOC(p->d_partial, sizeof(double) * partial_blocks(p->C, p->G) * G * 4);
     ALLOC(p->d_out4, sizeof(double) * G * 4);
-    SweepSched &sc = p->sched;
-    ALLOC(sc.d_probs, sizeof(DevProblem));
-    ALLOC(sc.d_base, sizeof(long long) * 2);
-    ALLOC(sc.d_ctl, sizeof(SweepCtl));
-    ALLOC(sc.d_queue, sizeof(unsigned long long) * 8 * C);
-    ALLOC(sc.d_seeds, sizeof(int) * 8 * C);
 #undef ALLOC
 
     // host -> device (FP64 mesh; FP32 materials and quadrature)
     std::vector<float> f32(std::max<size_t>({C * G, (size_t)3 * p->nang, G}));
     auto up32 = [&](float *dst, const std::vector<double> &src) {
         for (size_t i = 0; i < src.size(); ++i) f32[i] = (float)src[i];
-        return hipMemcpyAsync(dst, f32.data(), sizeof(float) * src.size(), hipMemcpyHostToDevice, s);
+        hipError_t e = hipMemcpyAsync(dst, f32.data(), sizeof(float) * src.size(), hipMemcpyHostToDevice, s);
+        return e == hipSuccess ? hipStreamSynchronize(s) : e;     // f32 is reused by the next upload
     };
     HIPCHK(p, hipMemcpyAsync(d_xyz, p->xyz.data(), sizeof(double) * 3 * p->nvert, hipMemcpyHostToDevice, s), "copy");
     HIPCHK(p, hipMemcpyAsync(d_cv, p->cv.data(), sizeof(int) * 8 * C, hipMemcpyHostToDevice, s), "copy");
@@ -376,19 +740,11 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     HIPCHK(p, hipMemcpyAsync(d_perm, perm.data(), sizeof(unsigned) * 6 * C, hipMemcpyHostToDevice, s), "copy");
     HIPCHK(p, hipStreamSynchronize(s), "sync");
     HIPCHK(p, up32(dsigt, p->sigt), "copy");
-    HIPCHK(p, hipStreamSynchronize(s), "sync");
     HIPCHK(p, up32(dsigs, p->sigs), "copy");
-    HIPCHK(p, hipStreamSynchronize(s), "sync");
     HIPCHK(p, up32(dq, p->q), "copy");
-    HIPCHK(p, hipStreamSynchronize(s), "sync");
     HIPCHK(p, up32(dom, p->omega), "copy");
-    HIPCHK(p, hipStreamSynchronize(s), "sync");
     HIPCHK(p, up32(dw, p->w), "copy");
-    HIPCHK(p, hipStreamSynchronize(s), "sync");
-    if (dpsib) {
-        HIPCHK(p, up32(dpsib, p->psib), "copy");
-        HIPCHK(p, hipStreamSynchronize(s), "sync");
-    }
+    if (dpsib) HIPCHK(p, up32(dpsib, p->psib), "copy");
     HIPCHK(p, hipMemsetAsync(p->d_err, 0, sizeof(int), s), "memset");
     HIPCHK(p, hipMemsetAsync(dF, 0, sizeof(float) * 288 * C, s), "memset");
 
@@ -410,54 +766,39 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     p->level.resize(8 * C);
     HIPCHK(p, hipMemcpy(p->level.data(), dlevel, sizeof(int) * 8 * C, hipMemcpyDeviceToHost), "copy");
     p->nlev.assign(nlev.begin(), nlev.begin() + 8);
-    int maxin = 0;
-    for (int o = 0; o < 8; ++o) maxin = std::max(maxin, nlev[8 + o]);
+    p->maxin = 1;
+    for (int o = 0; o < 8; ++o) p->maxin = std::max(p->maxin, nlev[8 + o]);
 
     HIPCHK(p, launch_octant_operators(p->C, dS, dF, dmask, dT, s), "octant operators");
 
-    // level-0 tasks of every octant become the queues' seeds
-    std::vector<int> seeds_host(8 * C), seeds;
-    std::vector<std::vector<int>> seeds_by_octant(8);
+    // level-0 tasks of every octant are the seeds of a sweep
+    std::vector<int> seeds_host(8 * C);
     HIPCHK(p, hipMemcpy(seeds_host.data(), dseeds, sizeof(int) * 8 * C, hipMemcpyDeviceToHost), "copy");
+    p->seeds_by_octant.assign(8, {});
     for (int o = 0; o < 8; ++o)
-        for (int i = 0; i < nseed[o]; ++i) seeds_by_octant[o].push_back(o * p->C + seeds_host[(size_t)o * C + i]);
-    layout_queues(sc.host_ctl, p->nq, p->xcc_queue, std::vector<long long>{(long long)p->C}, seeds_by_octant, seeds);
+        for (int i = 0; i < nseed[o]; ++i) p->seeds_by_octant[o].push_back(o * p->C + seeds_host[(size_t)o * C + i]);
 
-    hp.C = p->C; hp.G = p->G; hp.A = p->A; hp.nang = p->nang; hp.task_base = 0;
+    hp.C = p->C; hp.G = p->G; hp.A = p->A; hp.nang = p->nang; hp.task_base = 0; hp.epoch = depoch;
     hp.M = dM; hp.S = dS; hp.T = dT; hp.F = dF; hp.nbr = d_nbr; hp.perm = d_perm; hp.inmask = dmask; hp.indeg = dindeg;
     hp.sigt = dsigt; hp.sigs = dsigs; hp.q = dq; hp.r = dr; hp.omega = dom; hp.w = dw; hp.psib = dpsib;
     hp.psi = dpsi; hp.slot = dslot; hp.slotc = dslotc; hp.cnt = dcnt;
-    sc.nprob = 1;
-    sc.total = 8LL * p->C;
-    sc.nseed = (int)seeds.size();
-    sc.maxA = p->A; sc.maxG = p->G; sc.maxin = std::max(1, maxin);
-    sc.threads = p->threads;
-    sc.wg_per_cu = p->wg_per_cu;
-    while (sc.threads < p->G) sc.threads *= 2;
-    long long base[2] = {0, sc.total};
-    HIPCHK(p, hipMemcpy(sc.d_probs, &hp, sizeof(DevProblem), hipMemcpyHostToDevice), "copy");
-    HIPCHK(p, hipMemcpy(sc.d_base, base, sizeof(base), hipMemcpyHostToDevice), "copy");
-    HIPCHK(p, hipMemcpy(sc.d_seeds, seeds.data(), sizeof(int) * seeds.size(), hipMemcpyHostToDevice), "copy");
-    HIPCHK(p, reset_schedule(p, s), "reset");
     HIPCHK(p, launch_fill_f32(dr, C * G * 8, 0.f, s), "fill");
     HIPCHK(p, hipStreamSynchronize(s), "setup");
-    snx_status st = configure_grid(p, sc);
-    if (st) { drop_device(p); return st; }
+    snx_status st = build_sched(p->sched, {p}, p->threads, p->wg_per_cu, p->chunk, s);
+    if (st) {
+        std::string msg = p->sched.err;
+        drop_device(p);
+        return fail(p, st, msg);
+    }
     p->ready = true;
     return SNX_OK;
 }
 
-static snx_status enqueue_sweep(snx_problem *p, const int *stop, hipStream_t s, hipEvent_t ev0 = nullptr,
-                                hipEvent_t ev1 = nullptr) {
-    SweepSched &sc = p->sched;
-    HIPCHK(p, launch_sweep_prologue(sc.d_ctl, sc.d_queue, sc.d_seeds, stop, s), "sweep prologue");
-    if (ev0) HIPCHK(p, hipEventRecord(ev0, s), "event");
-    HIPCHK(p, launch_sweep_kernel(sc.d_probs, sc.nprob, sc.d_base, sc.d_ctl, sc.d_queue, stop, sc.threads, sc.grid,
-                                  sc.maxA, sc.maxG, sc.maxin, p->watchdog_ticks, s),
-           "sweep launch");
-    if (ev1) HIPCHK(p, hipEventRecord(ev1, s), "event");
-    return SNX_OK;
-}
+#define SCHED_ERR(p, expr)                                   \
+    do {                                                     \
+        snx_status st_ = (expr);                             \
+        if (st_) return fail((p), st_, (p)->sched.err);      \
+    } while (0)
 
 snx_status snx_sweep(snx_problem *p, const float *phi_in, float *phi_out, void *stream) {
     if (!p) return SNX_E_ARG;
@@ -466,33 +807,8 @@ snx_status snx_sweep(snx_problem *p, const float *phi_in, float *phi_out, void *
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(p, launch_source(p->sched.d_probs, 0, p->C, p->G, phi_in, nullptr, s), "source");
-    snx_status st = enqueue_sweep(p, nullptr, s);
-    if (st) return st;
+    SCHED_ERR(p, enqueue_sweep(p->sched, nullptr, s));
     HIPCHK(p, launch_reduce(p->sched.d_probs, 0, p->C, p->G, phi_out, nullptr, false, nullptr, nullptr, s), "reduce");
-    return SNX_OK;
-}
-
-// Captures `chunk` source iterations whose first one reads ping-pong buffer `parity`.
-static snx_status build_graph(snx_problem *p, int parity) {
-    hipStream_t cs = p->cap_stream;
-    HIPCHK(p, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
-    snx_status st = SNX_OK;
-    for (int i = 0; i < p->chunk && !st; ++i) {
-        st = enqueue_sweep(p, p->d_stop, cs);
-        if (!st) {
-            const int cur = (parity + i) & 1;
-            hipError_t e = launch_reduce(p->sched.d_probs, 0, p->C, p->G, p->d_phi[cur ^ 1], p->d_phi[cur], true,
-                                         p->d_ic, p->d_stop, cs);
-            if (e != hipSuccess) st = hip_fail(p, e, "reduce launch");
-        }
-    }
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(cs, &g);
-    if (st) { if (g) (void)hipGraphDestroy(g); return st; }
-    if (e != hipSuccess) return hip_fail(p, e, "end capture");
-    e = hipGraphInstantiate(&p->graph[parity], g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return hip_fail(p, e, "graph instantiate");
     return SNX_OK;
 }
 
@@ -502,50 +818,11 @@ snx_status snx_solve(snx_problem *p, double tol, int32_t max_it, const float *ph
     if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
     if (!phi || max_it < 1 || !(tol >= 0.0)) return fail(p, SNX_E_ARG, "bad solve arguments");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
-    hipStream_t s = (hipStream_t)stream;
-    const auto t0 = std::chrono::steady_clock::now();
-    const size_t nphi = (size_t)p->C * p->G * 8;
-    HIPCHK(p, launch_iter_init(p->d_ic, p->d_stop, max_it, tol, s), "init");
-    if (phi0) HIPCHK(p, launch_copy_f32(p->d_phi[0], phi0, nphi, nullptr, s), "copy");
-    else HIPCHK(p, launch_fill_f32(p->d_phi[0], nphi, 0.f, s), "fill");
-    HIPCHK(p, launch_source(p->sched.d_probs, 0, p->C, p->G, p->d_phi[0], nullptr, s), "source");
-    IterCtl *hic = reinterpret_cast<IterCtl *>(p->pinned);
-    unsigned *habort = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(p->pinned) + 1024);
-    int *hstop = reinterpret_cast<int *>(reinterpret_cast<char *>(p->pinned) + 2048);
-    const long long max_launch = (max_it + p->chunk - 1) / p->chunk + 1;
-    int done_iters = 0;
-    for (long long l = 0; l < max_launch; ++l) {
-        const int parity = done_iters & 1;
-        if (!p->graph[parity]) {
-            snx_status st = build_graph(p, parity);
-            if (st) return st;
-        }
-        HIPCHK(p, hipGraphLaunch(p->graph[parity], s), "graph launch");
-        HIPCHK(p, hipMemcpyAsync(hic, p->d_ic, sizeof(IterCtl), hipMemcpyDeviceToHost, s), "copy");
-        HIPCHK(p, hipMemcpyAsync(habort, &p->sched.d_ctl->abort, sizeof(unsigned), hipMemcpyDeviceToHost, s), "copy");
-        HIPCHK(p, hipMemcpyAsync(hstop, p->d_stop, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
-        HIPCHK(p, hipStreamSynchronize(s), "solve");
-        if (*habort) {
-            (void)reset_schedule(p, s);
-            (void)hipStreamSynchronize(s);
-            return fail(p, SNX_E_DEVICE, "sweep watchdog expired (no ready task)");
-        }
-        if (*hstop) break;
-        done_iters = hic->iter;
-    }
-    const int iters = hic->iter;
-    HIPCHK(p, launch_copy_f32(phi, p->d_phi[iters & 1], nphi, nullptr, s), "copy");
-    HIPCHK(p, hipStreamSynchronize(s), "solve");
-    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    const bool conv = *hstop == 1;
-    if (info) {
-        info->iterations = iters;
-        info->status = conv ? SNX_OK : SNX_E_NOCONV;
-        info->residual = hic->last_eps;
-        info->wall_ms = ms;
-        info->solves_per_s = ms > 0 ? (double)iters * p->C * p->nang * p->G / (ms * 1e-3) : 0.0;
-    }
-    return conv ? SNX_OK : fail(p, SNX_E_NOCONV, "max_it reached before the tolerance");
+    const float *in[1] = {phi0};
+    float *out[1] = {phi};
+    snx_status st = sched_solve(p->sched, tol, max_it, in, out, info, (hipStream_t)stream);
+    if (st) return fail(p, st, p->sched.err);
+    return SNX_OK;
 }
 
 snx_status snx_balance(snx_problem *p, const float *phi_in, const float *phi_out, double *out, void *stream) {
@@ -589,12 +866,28 @@ snx_status snx_set_schedule(snx_problem *p, int32_t threads, int32_t wg_per_cu, 
             return fail(p, SNX_E_ARG, "threads must be 64, 128, 256 or 512");
         if (p->have_mat && threads < p->G) return fail(p, SNX_E_ARG, "threads must be at least G");
         p->threads = threads;
-        p->sched.threads = threads;
     }
-    if (wg_per_cu > 0) { p->wg_per_cu = wg_per_cu; p->sched.wg_per_cu = wg_per_cu; }
+    if (wg_per_cu > 0) p->wg_per_cu = wg_per_cu;
     if (chunk > 0) p->chunk = chunk;
-    drop_graph(p);
-    if (p->ready) return configure_grid(p, p->sched);
+    if (!p->ready) return SNX_OK;
+    p->sched.threads = p->threads;
+    p->sched.wg_per_cu = p->wg_per_cu;
+    p->sched.chunk = p->chunk;
+    p->sched.drop_graphs();
+    SCHED_ERR(p, configure_grid(p->sched));
+    return SNX_OK;
+}
+
+snx_status snx_tune(snx_problem *p, const char *cache_path, int32_t *chosen, void *stream) {
+    if (!p) return SNX_E_ARG;
+    if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
+    HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
+    int t = 0, w = 0;
+    double ms = 0;
+    SCHED_ERR(p, tune_sched(p->sched, cache_path, (hipStream_t)stream, &t, &w, &ms));
+    p->threads = t;
+    p->wg_per_cu = w;
+    if (chosen) { chosen[0] = t; chosen[1] = w; }
     return SNX_OK;
 }
 
@@ -611,11 +904,11 @@ snx_status snx_profile_sweep(snx_problem *p, int32_t nsweeps, const float *phi_i
         if (hipEventCreate(&e) != hipSuccess) { st = fail(p, SNX_E_DEVICE, "hipEventCreate failed"); break; }
     for (int i = 0; i < nsweeps && !st; ++i) {
         hipError_t e = launch_source(p->sched.d_probs, 0, p->C, p->G, phi_in, nullptr, s);
-        if (e != hipSuccess) { st = hip_fail(p, e, "source"); break; }
-        st = enqueue_sweep(p, nullptr, s, ev[2 * i], ev[2 * i + 1]);
-        if (st) break;
+        if (e != hipSuccess) { st = fail(p, SNX_E_DEVICE, "source launch failed"); break; }
+        st = enqueue_sweep(p->sched, nullptr, s, ev[2 * i], ev[2 * i + 1]);
+        if (st) { st = fail(p, st, p->sched.err); break; }
         e = launch_reduce(p->sched.d_probs, 0, p->C, p->G, phi_out, nullptr, false, nullptr, nullptr, s);
-        if (e != hipSuccess) st = hip_fail(p, e, "reduce");
+        if (e != hipSuccess) st = fail(p, SNX_E_DEVICE, "reduce launch failed");
     }
     double total = 0.0;
     if (!st && hipStreamSynchronize(s) != hipSuccess) st = fail(p, SNX_E_DEVICE, "profile sync failed");
@@ -634,21 +927,104 @@ snx_status snx_sweep_stats(snx_problem *p, int64_t *out) {
     if (!p || !out) return SNX_E_ARG;
     if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
-    std::vector<SweepCtl> h(1);
-    HIPCHK(p, hipDeviceSynchronize(), "sync");
-    HIPCHK(p, hipMemcpy(h.data(), p->sched.d_ctl, sizeof(SweepCtl), hipMemcpyDeviceToHost), "copy");
-    for (int i = 0; i < 11; ++i) out[i] = 0;
-    for (int q = 0; q < h[0].nq; ++q) {
-        const QueueCtl &Q = h[0].q[q];
-        out[0] += (int64_t)Q.tasks_done;
-        out[1] += (int64_t)Q.polls_empty;
-        out[4] += (int64_t)Q.continued;
-        for (int i = 0; i < 5; ++i) out[6 + i] += (int64_t)Q.phase[i];
-    }
-    out[2] = (int64_t)h[0].abort;
-    out[3] = (int64_t)p->sched.grid;
-    out[5] = (int64_t)p->sched.threads;
+    SCHED_ERR(p, sched_stats(p->sched, out));
     return SNX_OK;
+}
+
+// ------------------------------------------------------------------ batches
+
+snx_status snx_batch_create(snx_batch **out, int32_t n, snx_problem *const *probs) {
+    if (!out || n < 1 || !probs) { g_create_error = "bad batch arguments"; return SNX_E_ARG; }
+    *out = nullptr;
+    std::vector<snx_problem *> v(probs, probs + n);
+    for (snx_problem *p : v) {
+        if (!p || !p->ready) { g_create_error = "every problem of a batch must be set up"; return SNX_E_STATE; }
+        if (p->device != v[0]->device) { g_create_error = "the problems of a batch must share a device"; return SNX_E_ARG; }
+    }
+    snx_batch *b = new (std::nothrow) snx_batch();
+    if (!b) { g_create_error = "out of host memory"; return SNX_E_OOM; }
+    b->device = v[0]->device;
+    if (hipSetDevice(b->device) != hipSuccess) { delete b; g_create_error = "hipSetDevice failed"; return SNX_E_DEVICE; }
+    snx_status st = build_sched(b->sched, v, b->threads, b->wg_per_cu, b->chunk, nullptr);
+    if (st) {
+        g_create_error = b->sched.err;
+        b->sched.release();
+        delete b;
+        return st;
+    }
+    *out = b;
+    return SNX_OK;
+}
+
+void snx_batch_destroy(snx_batch *b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    b->sched.release();
+    delete b;
+}
+
+const char *snx_batch_last_error(const snx_batch *b) { return b ? b->sched.err.c_str() : g_create_error.c_str(); }
+
+snx_status snx_batch_set_schedule(snx_batch *b, int32_t threads, int32_t wg_per_cu, int32_t chunk) {
+    if (!b) return SNX_E_ARG;
+    if (threads > 0) {
+        if (threads != 64 && threads != 128 && threads != 256 && threads != 512)
+            return fail_msg(b->sched.err, SNX_E_ARG, "threads must be 64, 128, 256 or 512");
+        if (threads < b->sched.maxG) return fail_msg(b->sched.err, SNX_E_ARG, "threads must be at least the largest G");
+        b->sched.threads = threads;
+    }
+    if (wg_per_cu > 0) b->sched.wg_per_cu = wg_per_cu;
+    if (chunk > 0) b->sched.chunk = chunk;
+    b->sched.drop_graphs();
+    return configure_grid(b->sched);
+}
+
+snx_status snx_batch_tune(snx_batch *b, const char *cache_path, int32_t *chosen, void *stream) {
+    if (!b) return SNX_E_ARG;
+    if (hipSetDevice(b->device) != hipSuccess) return fail_msg(b->sched.err, SNX_E_DEVICE, "hipSetDevice failed");
+    int t = 0, w = 0;
+    double ms = 0;
+    snx_status st = tune_sched(b->sched, cache_path, (hipStream_t)stream, &t, &w, &ms);
+    if (st) return st;
+    if (chosen) { chosen[0] = t; chosen[1] = w; }
+    return SNX_OK;
+}
+
+snx_status snx_batch_sweep(snx_batch *b, const float *const *phi_in, float *const *phi_out, void *stream) {
+    if (!b) return SNX_E_ARG;
+    if (!phi_out) return fail_msg(b->sched.err, SNX_E_ARG, "phi_out is required");
+    for (int i = 0; i < b->sched.nprob(); ++i)
+        if (!phi_out[i] || (phi_in && phi_in[i] == phi_out[i]))
+            return fail_msg(b->sched.err, SNX_E_ARG, "each phi_out must be non-NULL and distinct from its phi_in");
+    if (hipSetDevice(b->device) != hipSuccess) return fail_msg(b->sched.err, SNX_E_DEVICE, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)stream;
+    snx_status st = sched_sweep(b->sched, phi_in, phi_out, s);
+    if (st) return st;
+    HIPCHK_E(b->sched.err, hipStreamSynchronize(s), "batch sweep");
+    return SNX_OK;
+}
+
+snx_status snx_batch_solve(snx_batch *b, double tol, int32_t max_it, const float *const *phi0, float *const *phi,
+                           snx_solve_info *infos, void *stream) {
+    if (!b) return SNX_E_ARG;
+    if (!phi || max_it < 1 || !(tol >= 0.0)) return fail_msg(b->sched.err, SNX_E_ARG, "bad solve arguments");
+    for (int i = 0; i < b->sched.nprob(); ++i)
+        if (!phi[i]) return fail_msg(b->sched.err, SNX_E_ARG, "every phi must be non-NULL");
+    if (hipSetDevice(b->device) != hipSuccess) return fail_msg(b->sched.err, SNX_E_DEVICE, "hipSetDevice failed");
+    return sched_solve(b->sched, tol, max_it, phi0, phi, infos, (hipStream_t)stream);
+}
+
+snx_status snx_batch_profile_sweep(snx_batch *b, int32_t nsweeps, double *ms, void *stream) {
+    if (!b || nsweeps < 1 || !ms) return SNX_E_ARG;
+    if (hipSetDevice(b->device) != hipSuccess) return fail_msg(b->sched.err, SNX_E_DEVICE, "hipSetDevice failed");
+    return time_sweeps(b->sched, nsweeps, (hipStream_t)stream, ms);
+}
+
+snx_status snx_batch_stats(snx_batch *b, int64_t *out) {
+    if (!b || !out) return SNX_E_ARG;
+    if (hipSetDevice(b->device) != hipSuccess) return fail_msg(b->sched.err, SNX_E_DEVICE, "hipSetDevice failed");
+    return sched_stats(b->sched, out);
 }
 
 }  // extern "C"

@@ -49,61 +49,58 @@ __global__ void k_source(const DevProblem *__restrict__ probs, int prob, const f
 
 __device__ inline unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
 
-// One thread per (cell, group): octant-slot reduction, optional source update,
-// optional residual against phi_old with a last-block finalisation.
-__global__ __launch_bounds__(256) void k_reduce(const DevProblem *__restrict__ probs, int prob,
-                                                float *__restrict__ phi_out, const float *__restrict__ phi_old,
-                                                int update_source, IterCtl *__restrict__ ic,
-                                                int *__restrict__ stop_flag) {
-    if (stop_flag && *stop_flag) return;
-    const DevProblem &P = probs[prob];
+// Octant-slot reduction of one (cell, group) of P: phi = sum_o (slot_o + comp_o)
+// in octant order with TwoSum; optional source update r = M (Q + sigma_s phi)/(4 pi);
+// returns the FP64 residual terms |phi - phi_old| and |phi| (maxima over dofs).
+__device__ inline void reduce_one(const DevProblem &P, long long t, float *__restrict__ phi_out,
+                                  const float *__restrict__ phi_old, int update_source, double &num, double &den) {
     const long long CG = (long long)P.C * P.G;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    double num = 0.0, den = 0.0;
-    if (t < CG) {
-        float s[8], c[8];
+    float s[8], c[8];
 #pragma unroll
-        for (int d = 0; d < 8; ++d) { s[d] = 0.f; c[d] = 0.f; }
-        for (int o = 0; o < 8; ++o) {
-            const size_t off = ((size_t)o * CG + t) * 8;
-            const float4 *sv = reinterpret_cast<const float4 *>(P.slot + off);
-            const float4 *cv = reinterpret_cast<const float4 *>(P.slotc + off);
-            const float4 a0 = sv[0], a1 = sv[1], b0 = cv[0], b1 = cv[1];
-            const float sa[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-            const float ca[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+    for (int d = 0; d < 8; ++d) { s[d] = 0.f; c[d] = 0.f; }
+    for (int o = 0; o < 8; ++o) {
+        const size_t off = ((size_t)o * CG + t) * 8;
+        const float4 *sv = reinterpret_cast<const float4 *>(P.slot + off);
+        const float4 *cv = reinterpret_cast<const float4 *>(P.slotc + off);
+        const float4 a0 = sv[0], a1 = sv[1], b0 = cv[0], b1 = cv[1];
+        const float sa[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+        const float ca[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
-            for (int d = 0; d < 8; ++d) {
-                float u, e;
-                two_sum(s[d], sa[d], u, e);
-                s[d] = u;
-                c[d] += e + ca[d];
-            }
-        }
-        float ph[8];
-#pragma unroll
-        for (int d = 0; d < 8; ++d) ph[d] = s[d] + c[d];
-        float4 *po = reinterpret_cast<float4 *>(phi_out + t * 8);
-        po[0] = make_float4(ph[0], ph[1], ph[2], ph[3]);
-        po[1] = make_float4(ph[4], ph[5], ph[6], ph[7]);
-        if (update_source) {
-            const int K = (int)(t / P.G);
-            float r[8];
-            source_dofs(P.M + (size_t)K * 64, P.q[t], P.sigs[t], ph, r);
-            float4 *ro = reinterpret_cast<float4 *>(P.r + t * 8);
-            ro[0] = make_float4(r[0], r[1], r[2], r[3]);
-            ro[1] = make_float4(r[4], r[5], r[6], r[7]);
-        }
-        if (phi_old) {
-#pragma unroll
-            for (int d = 0; d < 8; ++d) {
-                const double nw = (double)ph[d], od = (double)phi_old[t * 8 + d];
-                num = fmax(num, fabs(nw - od));
-                den = fmax(den, fabs(nw));
-            }
+        for (int d = 0; d < 8; ++d) {
+            float u, e;
+            two_sum(s[d], sa[d], u, e);
+            s[d] = u;
+            c[d] += e + ca[d];
         }
     }
-    if (!ic || !phi_old) return;
-    // block max, then one atomicMax per block on the bit patterns (non-negative doubles order like integers)
+    float ph[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) ph[d] = s[d] + c[d];
+    float4 *po = reinterpret_cast<float4 *>(phi_out + t * 8);
+    po[0] = make_float4(ph[0], ph[1], ph[2], ph[3]);
+    po[1] = make_float4(ph[4], ph[5], ph[6], ph[7]);
+    if (update_source) {
+        const int K = (int)(t / P.G);
+        float r[8];
+        source_dofs(P.M + (size_t)K * 64, P.q[t], P.sigs[t], ph, r);
+        float4 *ro = reinterpret_cast<float4 *>(P.r + t * 8);
+        ro[0] = make_float4(r[0], r[1], r[2], r[3]);
+        ro[1] = make_float4(r[4], r[5], r[6], r[7]);
+    }
+    if (phi_old) {
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const double nw = (double)ph[d], od = (double)phi_old[t * 8 + d];
+            num = fmax(num, fabs(nw - od));
+            den = fmax(den, fabs(nw));
+        }
+    }
+}
+
+// Block maxima of the residual terms, then one atomicMax per block (non-negative
+// doubles order like their bit patterns); the last block of the problem turns
+// them into eps and sets the stop flag on convergence or at max_it.
+__device__ inline void residual_finish(double num, double den, IterCtl *ic, int *stop_flag, unsigned nblocks) {
     __shared__ double s_num[256], s_den[256];
     s_num[threadIdx.x] = num;
     s_den[threadIdx.x] = den;
@@ -120,7 +117,7 @@ __global__ __launch_bounds__(256) void k_reduce(const DevProblem *__restrict__ p
         atomicMax(&ic->den_bits, dbits(s_den[0]));
         __threadfence();
         const unsigned done = atomicAdd(&ic->blocks_done, 1u);
-        if (done == gridDim.x - 1) {
+        if (done == nblocks - 1) {
             __threadfence();
             const double nm = __longlong_as_double((long long)atomicAdd(&ic->num_bits, 0ull));
             const double dn = __longlong_as_double((long long)atomicAdd(&ic->den_bits, 0ull));
@@ -134,6 +131,90 @@ __global__ __launch_bounds__(256) void k_reduce(const DevProblem *__restrict__ p
             else if (ic->iter >= ic->max_it) *stop_flag = 2;
         }
     }
+}
+
+// One thread per (cell, group) of one problem.
+__global__ __launch_bounds__(256) void k_reduce(const DevProblem *__restrict__ probs, int prob,
+                                                float *__restrict__ phi_out, const float *__restrict__ phi_old,
+                                                int update_source, IterCtl *__restrict__ ic,
+                                                int *__restrict__ stop_flag) {
+    if (stop_flag && *stop_flag) return;
+    const DevProblem &P = probs[prob];
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double num = 0.0, den = 0.0;
+    if (t < (long long)P.C * P.G) reduce_one(P, t, phi_out, phi_old, update_source, num, den);
+    if (!ic || !phi_old) return;
+    residual_finish(num, den, ic, stop_flag, gridDim.x);
+}
+
+__device__ inline int block_problem(const int *__restrict__ blk_base, int nprob, int b) {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (blk_base[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// The same over every problem of a batch; blocks of one problem are contiguous.
+__global__ __launch_bounds__(256) void k_reduce_batch(const DevProblem *__restrict__ probs, int nprob,
+                                                      const int *__restrict__ blk_base, float *const *phi_out,
+                                                      float *const *phi_old, int update_source,
+                                                      IterCtl *__restrict__ ic, int *__restrict__ stops) {
+    const int p = block_problem(blk_base, nprob, blockIdx.x);
+    if (stops[p]) return;
+    const DevProblem &P = probs[p];
+    const long long t = (long long)(blockIdx.x - blk_base[p]) * blockDim.x + threadIdx.x;
+    double num = 0.0, den = 0.0;
+    const float *old = phi_old ? phi_old[p] : nullptr;
+    if (t < (long long)P.C * P.G) reduce_one(P, t, phi_out[p], old, update_source, num, den);
+    if (!ic || !old) return;
+    residual_finish(num, den, ic + p, stops + p, blk_base[p + 1] - blk_base[p]);
+}
+
+__global__ __launch_bounds__(256) void k_source_batch(const DevProblem *__restrict__ probs, int nprob,
+                                                      const int *__restrict__ blk_base, float *const *phi,
+                                                      const int *__restrict__ stops) {
+    const int p = block_problem(blk_base, nprob, blockIdx.x);
+    if (stops && stops[p]) return;
+    const DevProblem &P = probs[p];
+    const long long t = (long long)(blockIdx.x - blk_base[p]) * blockDim.x + threadIdx.x;
+    if (t >= (long long)P.C * P.G) return;
+    const int K = (int)(t / P.G);
+    float ph[8], r[8];
+    const float *f = phi ? phi[p] : nullptr;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ph[j] = f ? f[t * 8 + j] : 0.f;
+    source_dofs(P.M + (size_t)K * 64, P.q[t], P.sigs[t], ph, r);
+    float4 *out = reinterpret_cast<float4 *>(P.r + t * 8);
+    out[0] = make_float4(r[0], r[1], r[2], r[3]);
+    out[1] = make_float4(r[4], r[5], r[6], r[7]);
+}
+
+// dst[p] = src[p] (or zero when src[p] is NULL), [C][G][8] floats per problem.
+__global__ __launch_bounds__(256) void k_copy_batch(const DevProblem *__restrict__ probs, int nprob,
+                                                    const int *__restrict__ blk_base, float *const *dst,
+                                                    float *const *src) {
+    const int p = block_problem(blk_base, nprob, blockIdx.x);
+    const DevProblem &P = probs[p];
+    const long long t = (long long)(blockIdx.x - blk_base[p]) * blockDim.x + threadIdx.x;
+    if (t >= (long long)P.C * P.G) return;
+    const float *s = src[p];
+    float *d = dst[p];
+    for (int j = 0; j < 8; ++j) d[t * 8 + j] = s ? s[t * 8 + j] : 0.f;
+}
+
+__global__ void k_iter_init_batch(IterCtl *ic, int *stops, int nprob, int max_it, double tol) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob) return;
+    ic[p].num_bits = 0ull;
+    ic[p].den_bits = 0ull;
+    ic[p].blocks_done = 0u;
+    ic[p].iter = 0;
+    ic[p].max_it = max_it;
+    ic[p].tol = tol;
+    ic[p].last_eps = __builtin_inf();
+    stops[p] = 0;
 }
 
 __global__ void k_iter_init(IterCtl *ic, int *stop_flag, int max_it, double tol) {
@@ -343,6 +424,31 @@ hipError_t launch_copy_f32(float *dst, const float *src, size_t n, const int *st
     hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, src, n, stop_flag);
     return hipGetLastError();
 }
+hipError_t launch_source_batch(const DevProblem *probs, int nprob, const int *blk_base, int nblk, float *const *phi,
+                               const int *stops, hipStream_t s) {
+    hipLaunchKernelGGL(k_source_batch, dim3(nblk), dim3(256), 0, s, probs, nprob, blk_base, phi, stops);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_batch(const DevProblem *probs, int nprob, const int *blk_base, int nblk,
+                               float *const *phi_out, float *const *phi_old, int update_source, IterCtl *ic,
+                               int *stops, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_batch, dim3(nblk), dim3(256), 0, s, probs, nprob, blk_base, phi_out, phi_old,
+                       update_source, ic, stops);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_batch(const DevProblem *probs, int nprob, const int *blk_base, int nblk, float *const *dst,
+                             float *const *src, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_batch, dim3(nblk), dim3(256), 0, s, probs, nprob, blk_base, dst, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_iter_init_batch(IterCtl *ic, int *stops, int nprob, int max_it, double tol, hipStream_t s) {
+    hipLaunchKernelGGL(k_iter_init_batch, dim3((nprob + 63) / 64), dim3(64), 0, s, ic, stops, nprob, max_it, tol);
+    return hipGetLastError();
+}
+
 hipError_t launch_iter_init(IterCtl *ic, int *stop_flag, int max_it, double tol, hipStream_t s) {
     hipLaunchKernelGGL(k_iter_init, dim3(1), dim3(1), 0, s, ic, stop_flag, max_it, tol);
     return hipGetLastError();

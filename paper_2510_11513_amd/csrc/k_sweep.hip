@@ -168,14 +168,14 @@ __device__ long long pop_task(SweepCtl *ctl, unsigned long long *queue, int &q, 
 template <int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(
     const DevProblem *__restrict__ probs, int nprob, const long long *__restrict__ task_base,
-    SweepCtl *__restrict__ ctl, unsigned long long *__restrict__ queue, const int *__restrict__ stop_flag, int maxA,
-    int maxG, int maxin, unsigned long long watchdog) {
+    SweepCtl *__restrict__ ctl, unsigned long long *__restrict__ queue, int maxA, int maxG, int maxin,
+    unsigned long long watchdog) {
     extern __shared__ __align__(16) float lds[];
     __shared__ long long s_task;
     __shared__ int s_q;
     __shared__ int s_nready;
     __shared__ long long s_ready[6];
-    if (stop_flag && *stop_flag) return;
+    if (ctl->nactive == 0) return;
     const unsigned epoch = ctl->epoch;
     const int nq = ctl->nq;
     const int tid = threadIdx.x;
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             if (N >= 0) {
                 const unsigned old = __hip_atomic_fetch_add(gp(P.cnt) + (size_t)o * C + N, 1u, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned target = (unsigned)gp(P.indeg)[(size_t)o * C + N] * epoch;
+                const unsigned target = (unsigned)gp(P.indeg)[(size_t)o * C + N] * *P.epoch;
                 if (old + 1u == target) s_ready[atomicAdd(&s_nready, 1)] = P.task_base + (long long)o * C + N;
             }
         }
@@ -428,32 +428,50 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
 }
 
-// Starts a sweep: advances the epoch, empties the queues and pushes the tasks
-// with no interior upwind face (level 0 of every octant) to their queues.
-__global__ void k_sweep_prologue(SweepCtl *ctl, unsigned long long *queue, const int *__restrict__ seeds,
-                                 const int *stop_flag) {
-    if (stop_flag && *stop_flag) return;
-    __shared__ unsigned s_epoch;
-    if (threadIdx.x == 0) s_epoch = ctl->epoch + 1u;
-    __syncthreads();
-    const unsigned e = s_epoch;
+// Starts a sweep: advances the schedule's epoch and the epoch of every active
+// problem (stops[p] == 0), sizes each queue for the active problems' tasks of
+// its octants and pushes their level-0 tasks (cells with no interior upwind
+// face) as seeds.  One workgroup; problems and seeds are few.
+__global__ void k_sweep_prologue(SweepCtl *ctl, unsigned long long *queue, const DevProblem *__restrict__ probs,
+                                 int nprob, const int *__restrict__ seeds, const int *__restrict__ seed_off,
+                                 const int *__restrict__ stops) {
+    __shared__ long long s_tail[kMaxQueues];
     const int nq = ctl->nq;
-    for (int q = 0; q < nq; ++q) {
-        const int b = ctl->qseed_base[q], n = ctl->qseed_count[q];
-        for (int i = threadIdx.x; i < n; i += blockDim.x)
-            queue[ctl->qbase[q] + i] = ((unsigned long long)e << 32) | (unsigned)seeds[b + i];
+    if (threadIdx.x == 0) {
+        const unsigned e = ctl->epoch + 1u;
+        int nact = 0;
+        for (int q = 0; q < nq; ++q) {
+            long long tot = 0, tail = 0;
+            for (int o = q; o < 8; o += nq)
+                for (int p = 0; p < nprob; ++p) {
+                    if (stops && stops[p]) continue;
+                    tot += probs[p].C;
+                    for (int i = seed_off[p * 8 + o]; i < seed_off[p * 8 + o + 1]; ++i)
+                        queue[ctl->qbase[q] + tail++] =
+                            ((unsigned long long)e << 32) | (unsigned long long)(probs[p].task_base + seeds[i]);
+                }
+            ctl->qtotal[q] = tot;
+            s_tail[q] = tail;
+        }
+        for (int p = 0; p < nprob; ++p)
+            if (!(stops && stops[p])) {
+                *probs[p].epoch += 1u;
+                ++nact;
+            }
+        ctl->nactive = nact;
+        ctl->epoch = e;
     }
+    __syncthreads();
     for (int q = threadIdx.x; q < nq; q += blockDim.x) {
         QueueCtl *Q = &ctl->q[q];
         Q->head = 0;
-        Q->tail = (unsigned)ctl->qseed_count[q];
+        Q->tail = (unsigned)s_tail[q];
         Q->done = 0;
         Q->polls_empty = 0;
         Q->tasks_done = 0;
         Q->continued = 0;
         for (int i = 0; i < 5; ++i) Q->phase[i] = 0;
     }
-    if (threadIdx.x == 0) ctl->epoch = e;
 }
 
 // Records the XCD id each workgroup runs on (set-up probe of the device's XCDs).
@@ -463,10 +481,10 @@ __global__ void k_xcc_probe(int *out) {
 
 template <int NT>
 hipError_t launch_nt(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
-                     unsigned long long *queue, const int *stop_flag, int maxA, int maxG, int maxin, int grid,
-                     size_t lds, unsigned long long watchdog, hipStream_t s) {
-    hipLaunchKernelGGL(k_sweep<NT>, dim3(grid), dim3(NT), lds, s, probs, nprob, task_base, ctl, queue, stop_flag, maxA,
-                       maxG, maxin, watchdog);
+                     unsigned long long *queue, int maxA, int maxG, int maxin, int grid, size_t lds,
+                     unsigned long long watchdog, hipStream_t s) {
+    hipLaunchKernelGGL(k_sweep<NT>, dim3(grid), dim3(NT), lds, s, probs, nprob, task_base, ctl, queue, maxA, maxG,
+                       maxin, watchdog);
     return hipGetLastError();
 }
 
@@ -495,9 +513,9 @@ int sweep_occupancy(int threads, size_t lds) {
     return nb;
 }
 
-hipError_t launch_sweep_prologue(SweepCtl *ctl, unsigned long long *queue, const int *seeds, const int *stop_flag,
-                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_sweep_prologue, dim3(1), dim3(256), 0, s, ctl, queue, seeds, stop_flag);
+hipError_t launch_sweep_prologue(SweepCtl *ctl, unsigned long long *queue, const DevProblem *probs, int nprob,
+                                 const int *seeds, const int *seed_off, const int *stops, hipStream_t s) {
+    hipLaunchKernelGGL(k_sweep_prologue, dim3(1), dim3(64), 0, s, ctl, queue, probs, nprob, seeds, seed_off, stops);
     return hipGetLastError();
 }
 
@@ -507,14 +525,14 @@ hipError_t launch_xcc_probe(int *out, int nblocks, hipStream_t s) {
 }
 
 hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
-                               unsigned long long *queue, const int *stop_flag, int threads, int grid, int maxA,
-                               int maxG, int maxin, unsigned long long watchdog, hipStream_t s) {
+                               unsigned long long *queue, int threads, int grid, int maxA, int maxG, int maxin,
+                               unsigned long long watchdog, hipStream_t s) {
     const size_t lds = sweep_lds_bytes(threads, maxA, maxG, maxin);
     switch (threads) {
-        case 64: return launch_nt<64>(probs, nprob, task_base, ctl, queue, stop_flag, maxA, maxG, maxin, grid, lds, watchdog, s);
-        case 128: return launch_nt<128>(probs, nprob, task_base, ctl, queue, stop_flag, maxA, maxG, maxin, grid, lds, watchdog, s);
-        case 256: return launch_nt<256>(probs, nprob, task_base, ctl, queue, stop_flag, maxA, maxG, maxin, grid, lds, watchdog, s);
-        case 512: return launch_nt<512>(probs, nprob, task_base, ctl, queue, stop_flag, maxA, maxG, maxin, grid, lds, watchdog, s);
+        case 64: return launch_nt<64>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds, watchdog, s);
+        case 128: return launch_nt<128>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds, watchdog, s);
+        case 256: return launch_nt<256>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds, watchdog, s);
+        case 512: return launch_nt<512>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds, watchdog, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -35,15 +35,13 @@ struct alignas(128) QueueCtl {
 
 // Control block of one sweep launch.
 struct SweepCtl {
-    unsigned epoch;     // sweep number since setup (counters count to indeg * epoch)
+    unsigned epoch;     // sweep number of this schedule (tags queue entries)
     unsigned abort;     // set by a watchdog expiry (1) or a queue overflow (2); every worker then exits
     int nq;             // queues in use
-    int pad;
+    int nactive;        // problems swept this time (0: the sweep kernel returns at once)
     int xcc_queue[kMaxXcc];                 // home queue of the workgroups of each XCC id
     long long qbase[kMaxQueues];            // first slot of each queue in the slot array
-    long long qtotal[kMaxQueues];           // tasks of each queue per sweep
-    int qseed_base[kMaxQueues];             // first seed of each queue in the seed list
-    int qseed_count[kMaxQueues];
+    long long qtotal[kMaxQueues];           // tasks of each queue in this sweep (active problems only)
     QueueCtl q[kMaxQueues];
 };
 
@@ -52,6 +50,7 @@ struct DevProblem {
     int C, G, A;                 // cells, groups, angles per octant
     int nang;
     long long task_base;         // first global task id of this problem (task = base + o*C + K)
+    unsigned *epoch;             // sweeps of this problem so far; its counters count to indeg * epoch
     const float *M;              // [C][64]       mass M_ij = int f_i f_j
     const float *S;              // [C][3][64]    stiffness S^a_ij = int f_i df_j/dx_a
     const float *F;              // [C][6][3][16] face matrices F^a_kl on face nodes
@@ -91,11 +90,11 @@ hipError_t launch_geometry(const double *xyz, const int *cell_vert, const int *n
                            int *err_flag, hipStream_t s);
 hipError_t launch_dag_one(int C, const int *nbr, const double *area, unsigned char *inmask, int *indeg, int *level,
                           int *hist, int *nlev, int *seeds, int *nseed, int *scratch, int *err, hipStream_t s);
-hipError_t launch_sweep_prologue(SweepCtl *ctl, unsigned long long *queue, const int *seeds, const int *stop_flag,
-                                 hipStream_t s);
+hipError_t launch_sweep_prologue(SweepCtl *ctl, unsigned long long *queue, const DevProblem *probs, int nprob,
+                                 const int *seeds, const int *seed_off, const int *stops, hipStream_t s);
 hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
-                               unsigned long long *queue, const int *stop_flag, int threads, int grid, int maxA,
-                               int maxG, int maxin, unsigned long long watchdog, hipStream_t s);
+                               unsigned long long *queue, int threads, int grid, int maxA, int maxG, int maxin,
+                               unsigned long long watchdog, hipStream_t s);
 hipError_t launch_xcc_probe(int *out, int nblocks, hipStream_t s);
 hipError_t launch_octant_operators(int C, const float *S, const float *F, const unsigned char *inmask, float *T,
                                    hipStream_t s);
@@ -114,6 +113,17 @@ hipError_t launch_fill_f32(float *p, size_t n, float v, hipStream_t s);
 hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s);
 hipError_t launch_copy_f32(float *dst, const float *src, size_t n, const int *stop_flag, hipStream_t s);
 hipError_t launch_iter_init(IterCtl *ic, int *stop_flag, int max_it, double tol, hipStream_t s);
+// Batched forms over the problems of a schedule: per-problem stop flags and
+// iteration records; blk_base[p] is the first block of problem p (256 (cell,
+// group) pairs per block), phi pointer arrays live in device memory.
+hipError_t launch_source_batch(const DevProblem *probs, int nprob, const int *blk_base, int nblk,
+                               float *const *phi, const int *stops, hipStream_t s);
+hipError_t launch_reduce_batch(const DevProblem *probs, int nprob, const int *blk_base, int nblk,
+                               float *const *phi_out, float *const *phi_old, int update_source, IterCtl *ic,
+                               int *stops, hipStream_t s);
+hipError_t launch_iter_init_batch(IterCtl *ic, int *stops, int nprob, int max_it, double tol, hipStream_t s);
+hipError_t launch_copy_batch(const DevProblem *probs, int nprob, const int *blk_base, int nblk, float *const *dst,
+                             float *const *src, hipStream_t s);
 
 // ------------------------------------------------------------- host helpers
 int topology(int C, int nvert, const int *cell_vert, std::vector<int> &nbr, std::vector<int> &nbr_face,

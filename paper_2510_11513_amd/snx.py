@@ -22,7 +22,9 @@ SNX_E_NOCONV = -7
 EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_set_quadrature",
            "snx_quadrature_product", "snx_set_materials", "snx_set_boundary", "snx_setup", "snx_sweep",
            "snx_solve", "snx_balance", "snx_integrated_flux", "snx_get_levels", "snx_set_schedule",
-           "snx_sweep_stats", "snx_profile_sweep"]
+           "snx_sweep_stats", "snx_profile_sweep", "snx_tune", "snx_batch_create", "snx_batch_destroy",
+           "snx_batch_last_error", "snx_batch_set_schedule", "snx_batch_tune", "snx_batch_sweep",
+           "snx_batch_solve", "snx_batch_profile_sweep", "snx_batch_stats"]
 
 
 class SnxError(RuntimeError):
@@ -69,8 +71,20 @@ def load(path: str = LIB_PATH):
     L.snx_set_schedule.argtypes = [_vp, ct.c_int32, ct.c_int32, ct.c_int32]
     L.snx_sweep_stats.argtypes = [_vp, _vp]
     L.snx_profile_sweep.argtypes = [_vp, ct.c_int32, _vp, _vp, ct.POINTER(ct.c_double), _vp]
+    L.snx_tune.argtypes = [_vp, ct.c_char_p, _vp, _vp]
+    L.snx_batch_create.argtypes = [ct.POINTER(_vp), ct.c_int32, _vp]
+    L.snx_batch_destroy.argtypes = [_vp]
+    L.snx_batch_destroy.restype = None
+    L.snx_batch_last_error.argtypes = [_vp]
+    L.snx_batch_last_error.restype = ct.c_char_p
+    L.snx_batch_set_schedule.argtypes = [_vp, ct.c_int32, ct.c_int32, ct.c_int32]
+    L.snx_batch_tune.argtypes = [_vp, ct.c_char_p, _vp, _vp]
+    L.snx_batch_sweep.argtypes = [_vp, _vp, _vp, _vp]
+    L.snx_batch_solve.argtypes = [_vp, ct.c_double, ct.c_int32, _vp, _vp, _vp, _vp]
+    L.snx_batch_profile_sweep.argtypes = [_vp, ct.c_int32, ct.POINTER(ct.c_double), _vp]
+    L.snx_batch_stats.argtypes = [_vp, _vp]
     for name in EXPORTS:
-        if name not in ("snx_destroy", "snx_last_error"):
+        if name not in ("snx_destroy", "snx_last_error", "snx_batch_destroy", "snx_batch_last_error"):
             getattr(L, name).restype = ct.c_int32
     _lib = L
     return L
@@ -224,9 +238,95 @@ class Problem:
                                              _stream(stream)), "profile_sweep")
         return ms.value
 
+    def tune(self, cache_path=None, stream=None):
+        """Autotunes the sweep schedule on this problem; returns (threads, workgroups per CU)."""
+        chosen = np.zeros(2, np.int32)
+        path = None if cache_path is None else str(cache_path).encode()
+        self._check(load().snx_tune(self.h, path, chosen.ctypes.data_as(ct.c_void_p), _stream(stream)), "tune")
+        return int(chosen[0]), int(chosen[1])
+
     def sweep_stats(self):
         out = np.zeros(11, np.int64)
         self._check(load().snx_sweep_stats(self.h, out.ctypes.data_as(ct.c_void_p)), "sweep_stats")
-        return {"tasks": int(out[0]), "empty_polls": int(out[1]), "abort": int(out[2]), "grid": int(out[3]),
-                "continued": int(out[4]), "threads": int(out[5]),
-                "cycles": dict(zip(("queue_wait", "stage", "build", "solve", "publish"), map(int, out[6:11])))}
+        return _stats(out)
+
+
+def _stats(out):
+    return {"tasks": int(out[0]), "empty_polls": int(out[1]), "abort": int(out[2]), "grid": int(out[3]),
+            "continued": int(out[4]), "threads": int(out[5]),
+            "cycles": dict(zip(("queue_wait", "stage", "build", "solve", "publish"), map(int, out[6:11])))}
+
+
+def _ptr_array(tensors):
+    arr = (ct.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = None if t is None else t.data_ptr()
+    return arr
+
+
+class Batch:
+    """Independent set-up problems sharing every sweep launch (see snx_batch_* in snx.h)."""
+
+    def __init__(self, problems):
+        L = load()
+        self.problems = list(problems)       # keeps the problems alive
+        hs = (ct.c_void_p * len(self.problems))(*[p.h.value for p in self.problems])
+        h = ct.c_void_p()
+        rc = L.snx_batch_create(ct.byref(h), len(self.problems), hs)
+        if rc:
+            raise SnxError(rc, L.snx_batch_last_error(None).decode())
+        self.h = h
+
+    def _check(self, rc, what, allow=()):
+        if rc and rc not in allow:
+            raise SnxError(rc, f"{what}: {load().snx_batch_last_error(self.h).decode()}")
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            load().snx_batch_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_schedule(self, threads: int = 0, wg_per_cu: int = 0, chunk: int = 0):
+        self._check(load().snx_batch_set_schedule(self.h, threads, wg_per_cu, chunk), "batch_set_schedule")
+
+    def tune(self, cache_path=None, stream=None):
+        chosen = np.zeros(2, np.int32)
+        path = None if cache_path is None else str(cache_path).encode()
+        self._check(load().snx_batch_tune(self.h, path, chosen.ctypes.data_as(ct.c_void_p), _stream(stream)),
+                    "batch_tune")
+        return int(chosen[0]), int(chosen[1])
+
+    def sweep(self, phi_in=None, phi_out=None, stream=None):
+        if phi_out is None:
+            phi_out = [p.empty_phi() for p in self.problems]
+        pin = None if phi_in is None else _ptr_array(phi_in)
+        self._check(load().snx_batch_sweep(self.h, pin, _ptr_array(phi_out), _stream(stream)), "batch_sweep")
+        return phi_out
+
+    def solve(self, tol: float, max_it: int, phi0=None, phi=None, stream=None, allow_noconv=False):
+        if phi is None:
+            phi = [p.empty_phi() for p in self.problems]
+        infos = (SolveInfo * len(self.problems))()
+        p0 = None if phi0 is None else _ptr_array(phi0)
+        rc = load().snx_batch_solve(self.h, tol, max_it, p0, _ptr_array(phi), infos, _stream(stream))
+        self._check(rc, "batch_solve", allow=(SNX_E_NOCONV,) if allow_noconv else ())
+        return phi, [{"iterations": i.iterations, "status": i.status, "residual": i.residual,
+                      "wall_ms": i.wall_ms, "solves_per_s": i.solves_per_s} for i in infos], rc
+
+    def profile_sweep(self, nsweeps: int, stream=None) -> float:
+        ms = ct.c_double(0.0)
+        self._check(load().snx_batch_profile_sweep(self.h, nsweeps, ct.byref(ms), _stream(stream)),
+                    "batch_profile_sweep")
+        return ms.value
+
+    def stats(self):
+        out = np.zeros(11, np.int64)
+        self._check(load().snx_batch_stats(self.h, out.ctypes.data_as(ct.c_void_p)), "batch_stats")
+        return _stats(out)
