@@ -202,6 +202,75 @@ snx_status snx_batch_profile_sweep(snx_batch *b, int32_t nsweeps, double *ms, vo
 /* As snx_sweep_stats, for the most recent sweep of the batch. */
 snx_status snx_batch_stats(snx_batch *b, int64_t *out);
 
+
+/* ---- learned initial guess ------------------------------------------------
+ * A face-adjacency message-passing network predicts the converged cell-average
+ * scalar flux of every (cell, group) from the problem's data; the prediction,
+ * broadcast to the 8 dofs, seeds source iteration (the fixed point of the
+ * iteration does not depend on the start, so the result is unchanged; only
+ * the number of sweeps is).  The method of the paper starts from zero; the
+ * network is an addition of this library.
+ *
+ * Nodes are (cell, group) pairs v = K*G + g; node v's neighbours are group g
+ * of the cells across K's faces.  With hidden width H = 64 and L layers:
+ *   h0 = relu(x W_in + b_in), h_l = relu([h_{l-1}, mean_nbr h_{l-1}] W_l + b_l),
+ *   z = h_L w_out + b_out,  z predicts y = log(mean of the 8 dofs of phi + 1e-4).
+ * Parameters are one FP32 vector in the order W_in [8][H], b_in [H],
+ * (W_l [2H][H], b_l [H]) for l = 1..L, w_out [H], b_out [1], row-major.  The
+ * layer products run in BF16 (weights and activations) with FP32 accumulation.
+ * Node features x [C*G][8] FP32: log sigma_t, c = sigma_s/sigma_t, q,
+ * log(q/sigma_a + 1e-2), (boundary faces)/3, log(sigma_t * volume^(1/3)),
+ * log(max(1 - c, 1e-6)), 1.  nbr is [C][6] int32, -1 on the boundary.
+ * The loss is the mean over nodes of (z - y)^2; training is AdamW
+ * (beta1 0.9, beta2 0.999, eps 1e-8, decoupled weight decay).  Gradients are
+ * reduced in a fixed order, so training is deterministic.  Every call is
+ * stream-ordered on `stream` unless it says synchronous. */
+typedef struct snx_gnn snx_gnn;
+
+/* Network on HIP device `device`; hidden must be 64, 1 <= layers <= 8.
+ * Weights are drawn normal with variance 2/fan_in from a 64-bit Mersenne
+ * twister seeded with `seed`; biases are zero.  Errors: SNX_E_ARG, SNX_E_DEVICE
+ * (message from snx_gnn_last_error(NULL)). */
+snx_status snx_gnn_create(snx_gnn **out, int32_t device, int32_t hidden, int32_t layers, uint64_t seed);
+/* Free the network and its device memory.  NULL is ignored. */
+void snx_gnn_destroy(snx_gnn *g);
+const char *snx_gnn_last_error(const snx_gnn *g);
+/* Number of FP32 parameters (33665 for 4 layers). */
+snx_status snx_gnn_num_params(const snx_gnn *g, int64_t *n);
+/* Copy the parameters to / from a host array of snx_gnn_num_params floats.
+ * Setting them also resets the optimiser state.  Synchronous. */
+snx_status snx_gnn_get_params(snx_gnn *g, float *host);
+snx_status snx_gnn_set_params(snx_gnn *g, const float *host);
+/* Parameter file: "SNXGNN1\0", int32 {64, layers, nparams}, then the FP32
+ * parameters (little-endian).  Load rejects a file of another shape with
+ * SNX_E_ARG.  Synchronous. */
+snx_status snx_gnn_save(snx_gnn *g, const char *path);
+snx_status snx_gnn_load(snx_gnn *g, const char *path);
+/* Node features of a set-up problem into device x [C*G][8], and its face
+ * adjacency into device nbr [C][6] (nbr may be NULL).  SNX_E_STATE if p is
+ * not set up. */
+snx_status snx_gnn_features(snx_problem *p, float *x, int32_t *nbr, void *stream);
+/* Regression targets y [ncell*G] = log(mean of the 8 dofs + 1e-4) of a
+ * device flux phi [ncell][G][8]. */
+snx_status snx_gnn_targets(const float *phi, int64_t ncell, int32_t G, float *y, void *stream);
+/* Forward pass on device inputs: z [ncell*G] (device, caller-owned).  The
+ * network keeps a workspace sized for the largest graph it has seen. */
+snx_status snx_gnn_forward(snx_gnn *g, const float *x, const int32_t *nbr, int64_t ncell, int32_t G, float *z,
+                           void *stream);
+/* Loss and its gradient: *loss (host, may be NULL) and grad_host (host array
+ * of snx_gnn_num_params floats, may be NULL).  Synchronous. */
+snx_status snx_gnn_grad(snx_gnn *g, const float *x, const int32_t *nbr, int64_t ncell, int32_t G, const float *y,
+                        float *loss, float *grad_host, void *stream);
+/* One AdamW step on the graph (x, nbr, y) with learning rate lr > 0 and
+ * decoupled weight decay; *loss (may be NULL) is the loss before the step.
+ * Synchronous (the loss is read back). */
+snx_status snx_gnn_train_step(snx_gnn *g, const float *x, const int32_t *nbr, int64_t ncell, int32_t G,
+                              const float *y, float lr, float weight_decay, float *loss, void *stream);
+/* Predicted starting flux of a set-up problem into device phi0 [C][G][8]:
+ * max(exp(z) - 1e-4, 0) on every dof of a cell.  SNX_E_STATE if p is not set
+ * up, SNX_E_ARG if it lives on another device. */
+snx_status snx_gnn_predict(snx_gnn *g, snx_problem *p, float *phi0, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -923,6 +923,17 @@ snx_status snx_profile_sweep(snx_problem *p, int32_t nsweeps, const float *phi_i
     return st;
 }
 
+}  // extern "C"
+
+bool snx::problem_view(const snx_problem *p, DevProblem *out, int *device) {
+    if (!p || !p->ready) return false;
+    *out = p->hp;
+    *device = p->device;
+    return true;
+}
+
+extern "C" {
+
 snx_status snx_sweep_stats(snx_problem *p, int64_t *out) {
     if (!p || !out) return SNX_E_ARG;
     if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");

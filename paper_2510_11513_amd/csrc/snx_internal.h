@@ -125,6 +125,31 @@ hipError_t launch_iter_init_batch(IterCtl *ic, int *stops, int nprob, int max_it
 hipError_t launch_copy_batch(const DevProblem *probs, int nprob, const int *blk_base, int nblk, float *const *dst,
                              float *const *src, hipStream_t s);
 
+// message-passing network (hidden width 64); bf16 buffers are passed as void*
+size_t gnn_bwd_grid(long long Nn);
+hipError_t gnn_layer_fwd(const void *hin, void *hout, const int *nbr, const float *inv_deg, int G, long long Nn,
+                         const void *Wt, const float *b, hipStream_t s);
+hipError_t gnn_layer_bwd(const void *hprev, const void *hcur, const float *dH, const int *nbr, const float *inv_deg,
+                         int G, long long Nn, const void *W, float *dHprev, float *dM, float *dWpart, float *dbpart,
+                         hipStream_t s);
+hipError_t gnn_input_fwd(const float *x, const float *Win, const float *bin, void *h0, long long Nn, hipStream_t s);
+hipError_t gnn_input_bwd(const float *x, const void *h0, const float *dH0, long long Nn, float *dWpart, float *dbpart,
+                         int grid, hipStream_t s);
+hipError_t gnn_head_fwd(const void *h, const float *wout, const float *bout, float *z, long long Nn, hipStream_t s);
+hipError_t gnn_head_bwd(const void *h, const float *z, const float *y, const float *wout, long long Nn, float *dH,
+                        float *part, int grid, hipStream_t s);
+hipError_t gnn_sum_partials(const float *part, int nblk, int n, float *out, float scale, hipStream_t s);
+hipError_t gnn_adamw(float *w, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
+                     float wd, float c1, float c2, hipStream_t s);
+hipError_t gnn_to_bf16(const float *W, void *Wb, void *Wt, hipStream_t s);
+hipError_t gnn_features(const DevProblem &P, float *x, int *nbr_out, hipStream_t s);
+hipError_t gnn_inv_degree(const int *nbr, int C, float *inv_deg, hipStream_t s);
+hipError_t gnn_targets(const float *phi, long long Nn, float *y, hipStream_t s);
+hipError_t gnn_expand(const float *z, long long Nn, float *phi, hipStream_t s);
+
+// Device view of a set-up problem (false if it is not set up).
+bool problem_view(const snx_problem *p, DevProblem *out, int *device);
+
 // ------------------------------------------------------------- host helpers
 int topology(int C, int nvert, const int *cell_vert, std::vector<int> &nbr, std::vector<int> &nbr_face,
              std::vector<unsigned> &perm, std::string &err);

@@ -24,7 +24,12 @@ EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_s
            "snx_solve", "snx_balance", "snx_integrated_flux", "snx_get_levels", "snx_set_schedule",
            "snx_sweep_stats", "snx_profile_sweep", "snx_tune", "snx_batch_create", "snx_batch_destroy",
            "snx_batch_last_error", "snx_batch_set_schedule", "snx_batch_tune", "snx_batch_sweep",
-           "snx_batch_solve", "snx_batch_profile_sweep", "snx_batch_stats"]
+           "snx_batch_solve", "snx_batch_profile_sweep", "snx_batch_stats", "snx_gnn_create", "snx_gnn_destroy",
+           "snx_gnn_last_error", "snx_gnn_num_params", "snx_gnn_get_params", "snx_gnn_set_params", "snx_gnn_save",
+           "snx_gnn_load", "snx_gnn_features", "snx_gnn_targets", "snx_gnn_forward", "snx_gnn_grad",
+           "snx_gnn_train_step", "snx_gnn_predict"]
+_NO_STATUS = ("snx_destroy", "snx_last_error", "snx_batch_destroy", "snx_batch_last_error", "snx_gnn_destroy",
+              "snx_gnn_last_error")
 
 
 class SnxError(RuntimeError):
@@ -51,6 +56,9 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built: run `python -m paper_2510_11513_amd.build`")
+    # torch first: its HIP runtime (soname libamdhip64.so.7) then satisfies the
+    # library's dependency, so the process holds one runtime, not two.
+    import torch  # noqa: F401
     L = ct.CDLL(path)
     L.snx_create.argtypes = [ct.POINTER(_vp), ct.c_int32]
     L.snx_destroy.argtypes = [_vp]
@@ -83,8 +91,26 @@ def load(path: str = LIB_PATH):
     L.snx_batch_solve.argtypes = [_vp, ct.c_double, ct.c_int32, _vp, _vp, _vp, _vp]
     L.snx_batch_profile_sweep.argtypes = [_vp, ct.c_int32, ct.POINTER(ct.c_double), _vp]
     L.snx_batch_stats.argtypes = [_vp, _vp]
+    _fp = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+    L.snx_gnn_create.argtypes = [ct.POINTER(_vp), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_uint64]
+    L.snx_gnn_destroy.argtypes = [_vp]
+    L.snx_gnn_destroy.restype = None
+    L.snx_gnn_last_error.argtypes = [_vp]
+    L.snx_gnn_last_error.restype = ct.c_char_p
+    L.snx_gnn_num_params.argtypes = [_vp, ct.POINTER(ct.c_int64)]
+    L.snx_gnn_get_params.argtypes = [_vp, _fp]
+    L.snx_gnn_set_params.argtypes = [_vp, _fp]
+    L.snx_gnn_save.argtypes = [_vp, ct.c_char_p]
+    L.snx_gnn_load.argtypes = [_vp, ct.c_char_p]
+    L.snx_gnn_features.argtypes = [_vp, _vp, _vp, _vp]
+    L.snx_gnn_targets.argtypes = [_vp, ct.c_int64, ct.c_int32, _vp, _vp]
+    L.snx_gnn_forward.argtypes = [_vp, _vp, _vp, ct.c_int64, ct.c_int32, _vp, _vp]
+    L.snx_gnn_grad.argtypes = [_vp, _vp, _vp, ct.c_int64, ct.c_int32, _vp, ct.POINTER(ct.c_float), _vp, _vp]
+    L.snx_gnn_train_step.argtypes = [_vp, _vp, _vp, ct.c_int64, ct.c_int32, _vp, ct.c_float, ct.c_float,
+                                     ct.POINTER(ct.c_float), _vp]
+    L.snx_gnn_predict.argtypes = [_vp, _vp, _vp, _vp]
     for name in EXPORTS:
-        if name not in ("snx_destroy", "snx_last_error", "snx_batch_destroy", "snx_batch_last_error"):
+        if name not in _NO_STATUS:
             getattr(L, name).restype = ct.c_int32
     _lib = L
     return L
@@ -107,6 +133,12 @@ def _ptr(t):
     return ct.c_void_p(t.data_ptr())
 
 
+def _init_torch():
+    """Initialise torch's HIP context before the library's first device call."""
+    import torch
+    torch.cuda.init()
+
+
 def _stream(stream):
     import torch
     if stream is None:
@@ -123,6 +155,7 @@ class Problem:
 
     def __init__(self, device: int = 0):
         L = load()
+        _init_torch()
         h = ct.c_void_p()
         rc = L.snx_create(ct.byref(h), device)
         if rc:
@@ -330,3 +363,115 @@ class Batch:
         out = np.zeros(11, np.int64)
         self._check(load().snx_batch_stats(self.h, out.ctypes.data_as(ct.c_void_p)), "batch_stats")
         return _stats(out)
+
+
+class Gnn:
+    """The message-passing network of the learned initial guess, on one GPU.
+
+    Device inputs are torch tensors: features x [C*G, 8] float32, adjacency
+    nbr [C, 6] int32, targets y [C*G] float32.
+    """
+
+    def __init__(self, device: int = 0, layers: int = 4, seed: int = 0, hidden: int = 64):
+        L = load()
+        _init_torch()
+        h = ct.c_void_p()
+        rc = L.snx_gnn_create(ct.byref(h), device, hidden, layers, seed)
+        if rc:
+            raise SnxError(rc, L.snx_gnn_last_error(None).decode())
+        self.h = h
+        self.device = device
+        self.layers = layers
+        n = ct.c_int64()
+        self._check(L.snx_gnn_num_params(h, ct.byref(n)), "num_params")
+        self.nparams = n.value
+
+    def _check(self, rc, what):
+        if rc:
+            raise SnxError(rc, f"{what}: {load().snx_gnn_last_error(self.h).decode()}")
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            load().snx_gnn_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.nparams, np.float32)
+        self._check(load().snx_gnn_get_params(self.h, out), "get_params")
+        return out
+
+    def set_params(self, theta):
+        arr = np.ascontiguousarray(theta, np.float32)
+        if arr.size != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters, got {arr.size}")
+        self._check(load().snx_gnn_set_params(self.h, arr), "set_params")
+
+    def save(self, path):
+        self._check(load().snx_gnn_save(self.h, os.fsencode(str(path))), "save")
+
+    def load_file(self, path):
+        self._check(load().snx_gnn_load(self.h, os.fsencode(str(path))), "load")
+
+    @staticmethod
+    def features(problem: "Problem", stream=None):
+        """(x [C*G, 8], nbr [C, 6]) of a set-up problem, on its device."""
+        import torch
+        dev = torch.device("cuda", problem.device)
+        x = torch.empty((problem.ncell * problem.G, 8), dtype=torch.float32, device=dev)
+        nbr = torch.empty((problem.ncell, 6), dtype=torch.int32, device=dev)
+        rc = load().snx_gnn_features(problem.h, _ptr(x), _ptr(nbr), _stream(stream))
+        problem._check(rc, "gnn_features")
+        return x, nbr
+
+    @staticmethod
+    def targets(phi, stream=None):
+        import torch
+        C, G = phi.shape[0], phi.shape[1]
+        y = torch.empty(C * G, dtype=torch.float32, device=phi.device)
+        rc = load().snx_gnn_targets(_ptr(phi.contiguous()), C, G, _ptr(y), _stream(stream))
+        if rc:
+            raise SnxError(rc, "gnn_targets")
+        return y
+
+    @staticmethod
+    def _shape(x, nbr):
+        C = nbr.shape[0]
+        if x.shape[0] % C or x.shape[1] != 8 or nbr.shape[1] != 6:
+            raise ValueError("x must be [C*G, 8] and nbr [C, 6]")
+        if x.dtype.itemsize != 4 or nbr.dtype.itemsize != 4 or not x.is_contiguous() or not nbr.is_contiguous():
+            raise ValueError("x float32 and nbr int32, contiguous")
+        return C, x.shape[0] // C
+
+    def forward(self, x, nbr, stream=None):
+        import torch
+        C, G = self._shape(x, nbr)
+        z = torch.empty(C * G, dtype=torch.float32, device=x.device)
+        self._check(load().snx_gnn_forward(self.h, _ptr(x), _ptr(nbr), C, G, _ptr(z), _stream(stream)), "forward")
+        return z
+
+    def grad(self, x, nbr, y, stream=None):
+        C, G = self._shape(x, nbr)
+        loss = ct.c_float()
+        g = np.zeros(self.nparams, np.float32)
+        self._check(load().snx_gnn_grad(self.h, _ptr(x), _ptr(nbr), C, G, _ptr(y), ct.byref(loss),
+                                        g.ctypes.data_as(ct.c_void_p), _stream(stream)), "grad")
+        return loss.value, g
+
+    def train_step(self, x, nbr, y, lr: float, weight_decay: float = 0.0, stream=None) -> float:
+        C, G = self._shape(x, nbr)
+        loss = ct.c_float()
+        self._check(load().snx_gnn_train_step(self.h, _ptr(x), _ptr(nbr), C, G, _ptr(y), lr, weight_decay,
+                                              ct.byref(loss), _stream(stream)), "train_step")
+        return loss.value
+
+    def predict(self, problem: "Problem", stream=None):
+        """Starting flux [C, G, 8] of a set-up problem."""
+        phi0 = problem.empty_phi()
+        self._check(load().snx_gnn_predict(self.h, problem.h, _ptr(phi0), _stream(stream)), "predict")
+        return phi0

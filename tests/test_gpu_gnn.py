@@ -1,0 +1,177 @@
+"""The learned initial guess on the GPU: BF16 MFMA network against the FP64 reference,
+training, and learned-start solves against the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import gnn as ref
+from paper_2510_11513_amd import inputs
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(__file__), "..", "paper_2510_11513_amd", "weights", "gnn_l4_h64.bin")
+
+
+def _problem(n=6, index=0):
+    return inputs.config_problem(5, index, scaled=True, n=n)
+
+
+def _reference_inputs(pr):
+    """FP64 features and adjacency of a problem from the oracle's own geometry."""
+    o = oracle.Oracle.from_problem(pr)
+    g = o.geometry()
+    vol = g["M"].sum(axis=(1, 2))
+    nb = (g["nbr"] < 0).sum(axis=1)
+    x = ref.features(pr.mat.sigma_t, pr.mat.sigma_s, pr.mat.q, vol, nb)
+    return x, g["nbr"], o
+
+
+def _quantised(theta, layers=4):
+    """Parameters as the GPU uses them: the layer matrices W_l rounded to bfloat16."""
+    P = ref.unpack(theta.astype(np.float64), 64, layers)
+    for l in range(1, layers + 1):
+        P[f"W{l}"] = ref.round_bf16(P[f"W{l}"])
+    return ref.pack(P, 64, layers)
+
+
+def _random_theta(seed, layers=4):
+    rng = np.random.default_rng(seed)
+    theta = ref.init_params(seed, 64, layers)
+    return (theta + rng.normal(0, 0.02, theta.shape)).astype(np.float32)
+
+
+def test_features_and_adjacency_match_reference():
+    import torch
+    from paper_2510_11513_amd import snx
+    pr = _problem(5)
+    p = snx.Problem.from_problem(pr)
+    x, nbr = snx.Gnn.features(p)
+    torch.cuda.synchronize()
+    xr, nbr_r, _ = _reference_inputs(pr)
+    assert np.array_equal(nbr.cpu().numpy(), nbr_r)
+    xg = x.cpu().numpy().reshape(pr.mesh.ncell, pr.mat.ngroup, 8).astype(np.float64)
+    assert np.abs(xg - xr).max() <= 2e-5 * max(1.0, np.abs(xr).max())
+
+
+def test_forward_matches_fp64_reference_within_bf16_tolerance():
+    import torch
+    from paper_2510_11513_amd import snx
+    pr = _problem(6)
+    p = snx.Problem.from_problem(pr)
+    net = snx.Gnn(0, 4, seed=1)
+    theta = _random_theta(7)
+    net.set_params(theta)
+    x, nbr = snx.Gnn.features(p)
+    z = net.forward(x, nbr).cpu().numpy().reshape(pr.mesh.ncell, pr.mat.ngroup)
+    xr, nbr_r, _ = _reference_inputs(pr)
+    zr, _ = ref.forward(_quantised(theta), xr, nbr_r)
+    err = np.abs(z - zr).max() / np.abs(zr).max()
+    assert err <= 2e-2, err
+    # the prediction is the forward pass mapped to a flux on every dof
+    phi0 = net.predict(p).cpu().numpy()
+    want = np.maximum(np.exp(z.astype(np.float64)) - ref.DELTA, 0.0)
+    assert np.allclose(phi0, want[:, :, None], rtol=1e-5, atol=1e-7)
+
+
+@pytest.mark.parametrize("n,G", [(5, 16), (7, 3)])
+def test_gradient_matches_fp64_reference_within_bf16_tolerance(n, G):
+    import torch
+    from paper_2510_11513_amd import snx
+    rng = np.random.default_rng(n)
+    mesh = inputs.make_mesh(n, 0.2, rng=rng)
+    mat = inputs.materials_loguniform_blocks(mesh, G, rng, 2, 0.9, 0.99, scaled=True)
+    pr = inputs.Problem("g", mesh, mat, 1, 1, 1e-6)
+    p = snx.Problem.from_problem(pr)
+    net = snx.Gnn(0, 4, seed=2)
+    theta = _random_theta(11)
+    net.set_params(theta)
+    x, nbr = snx.Gnn.features(p)
+    y_host = rng.normal(-1.0, 1.0, (mesh.ncell, G))
+    y = torch.as_tensor(y_host.ravel(), dtype=torch.float32, device="cuda")
+    loss, grad = net.grad(x, nbr, y)
+    xr, nbr_r, _ = _reference_inputs(pr)
+    loss_r, grad_r = ref.loss_and_grad(_quantised(theta), xr, nbr_r, y_host.astype(np.float32).astype(np.float64))
+    assert abs(loss - loss_r) <= 1e-2 * abs(loss_r), (loss, loss_r)
+    i = 0
+    for name, shp in ref.param_shapes(64, 4):
+        k = int(np.prod(shp))
+        g, gr = grad[i:i + k].astype(np.float64), grad_r[i:i + k]
+        i += k
+        err = np.linalg.norm(g - gr) / max(np.linalg.norm(gr), 1e-30)
+        assert err <= 3e-2, (name, err)
+    assert np.array_equal(net.grad(x, nbr, y)[1], grad)         # fixed-order reductions: repeatable bits
+
+
+def test_training_reduces_loss_and_is_deterministic():
+    from paper_2510_11513_amd import snx
+    pr = _problem(6)
+    p = snx.Problem.from_problem(pr)
+    phi, _ = p.solve(1e-6, 3000)
+    x, nbr = snx.Gnn.features(p)
+    y = snx.Gnn.targets(phi)
+    nets = [snx.Gnn(0, 4, seed=3), snx.Gnn(0, 4, seed=3)]
+    assert np.array_equal(nets[0].params(), nets[1].params())
+    hist = [[net.train_step(x, nbr, y, 2e-3, 1e-4) for _ in range(60)] for net in nets]
+    assert hist[0] == hist[1]
+    assert np.array_equal(nets[0].params(), nets[1].params())
+    assert hist[0][-1] < 0.2 * hist[0][0], (hist[0][0], hist[0][-1])
+
+
+def test_targets_are_log_cell_average():
+    import torch
+    from paper_2510_11513_amd import snx
+    phi = torch.rand((37, 5, 8), device="cuda") * 3
+    y = snx.Gnn.targets(phi).cpu().numpy()
+    want = ref.targets(phi.cpu().numpy().astype(np.float64)).ravel()
+    assert np.allclose(y, want, rtol=1e-5, atol=1e-6)
+
+
+def test_save_load_roundtrip_and_shape_check(tmp_path):
+    from paper_2510_11513_amd import snx
+    a = snx.Gnn(0, 4, seed=4)
+    path = tmp_path / "net.bin"
+    a.save(path)
+    b = snx.Gnn(0, 4, seed=5)
+    assert not np.array_equal(a.params(), b.params())
+    b.load_file(path)
+    assert np.array_equal(a.params(), b.params())
+    c = snx.Gnn(0, 3, seed=4)
+    with pytest.raises(snx.SnxError) as e:
+        c.load_file(path)
+    assert e.value.code == -1
+    assert a.nparams == 8 * 64 + 64 + 4 * (128 * 64 + 64) + 65
+
+
+def test_learned_start_converges_to_the_same_solution_as_zero_start_and_oracle():
+    from paper_2510_11513_amd import snx
+    rng = np.random.default_rng(9)
+    mesh = inputs.make_mesh(5, 0.2, rng=rng)
+    mat = inputs.materials_loguniform_blocks(mesh, 4, rng, 2, 0.9, 0.99, scaled=True)
+    pr = inputs.Problem("learned-small", mesh, mat, 2, 2, 1e-6)
+    p = snx.Problem.from_problem(pr)
+    net = snx.Gnn(0, 4, seed=6)
+    if os.path.exists(WEIGHTS):
+        net.load_file(WEIGHTS)
+    phi0 = net.predict(p)
+    phi_b, ib = p.solve(1e-6, 5000, phi0=phi0)
+    phi_a, ia = p.solve(1e-6, 5000)
+    assert ib["status"] == 0 and ia["status"] == 0 and ib["residual"] <= 1e-6
+    ref_phi = oracle.Oracle.from_problem(pr).solve(1e-12, 20000)["phi"]
+    for phi in (phi_a, phi_b):
+        assert H.rel_err_per_group(phi.cpu().numpy().astype(np.float64), ref_phi).max() <= 1e-5
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained parameter file")
+def test_trained_network_beats_zero_start_on_held_out_instances():
+    from paper_2510_11513_amd import learned, snx
+    net = snx.Gnn(0, 4)
+    net.load_file(WEIGHTS)
+    recs = learned.evaluate(net, [0, 1, 2], log=None)
+    for r in recs:
+        assert r["b_it"] < r["a_it"], r
+        assert r["b_vs_a"] <= 1e-4, r
+    s = learned.summarize(recs)
+    assert s["b/a_wall_mean"] < 1.0, s
