@@ -91,6 +91,31 @@ def cpu_baseline(prob, groups: int, sweeps: int):
                       f"of {G} ({solves:.3g} solves, {dt:.2f} s; the oracle runs one OpenMP thread per group)"}
 
 
+def learned_start(count: int):
+    """Time to 1e-6 from the trained network's start vs zero start (and the Q/sigma_a control),
+    on the first held-out instances of the high-scattering workload, inference included."""
+    from paper_2510_11513_amd import learned, snx
+    path = os.path.join(ROOT, "paper_2510_11513_amd", "weights", "gnn_l4_h64.bin")
+    if not os.path.exists(path):
+        return None
+    net = snx.Gnn(0, 4)
+    net.load_file(path)
+    recs = learned.evaluate(net, list(range(count)), log=None)
+    summ = learned.summarize(recs)
+    ev = os.path.join(ROOT, "paper_2510_11513_amd", "weights", "gnn_l4_h64.eval.json")
+    full = json.load(open(ev))["summary"] if os.path.exists(ev) else None
+    return {"workload": "32^3 jittered hex, 96 angles, 16 groups, sigma_t log-uniform [0.1, 10] and c in "
+                        "[0.9, 0.99] in 4^3 blocks; tol 1e-6", "instances": count,
+            "wall_ratio_learned_over_zero_median": round(summ["b/a_wall_median"], 4),
+            "iter_ratio_learned_over_zero_median": round(summ["b/a_iterations_median"], 4),
+            "wall_ratio_control_over_zero_median": round(summ["c/a_wall_median"], 4),
+            "zero_start_ms_median": round(summ["a_wall_ms_median"], 2),
+            "learned_vs_zero_max_rel_diff": summ["b_vs_a_max"],
+            "heldout_200_recorded": None if full is None else {
+                k: round(full[k], 4) for k in ("b/a_wall_median", "b/a_wall_mean", "b/a_iterations_median",
+                                               "c/a_wall_median")}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,7 +126,9 @@ def main():
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-groups", type=int, default=16)
-    ap.add_argument("--cpu-sweeps", type=int, default=1)
+    ap.add_argument("--cpu-sweeps", type=int, default=4)
+    ap.add_argument("--learned", type=int, default=4,
+                    help="held-out high-scattering instances for the learned-start comparison (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -174,6 +201,9 @@ def main():
                       "sweep_threads": stats["threads"], "continued_tasks": stats["continued"],
                       "setup_s": round(t_setup, 3)},
            "roofline": roofline}
+    if args.learned > 0:
+        print("[bench] learned vs zero start", file=sys.stderr, flush=True)
+        out["learned"] = learned_start(args.learned)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_groups, args.cpu_sweeps)
