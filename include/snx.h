@@ -138,11 +138,13 @@ snx_status snx_integrated_flux(snx_problem *p, const float *phi, double *out, vo
  * octant) and host nlevels[8]; either may be NULL.  Synchronous. */
 snx_status snx_get_levels(snx_problem *p, int32_t *level, int32_t *nlevels);
 
-/* Sweep schedule knobs: threads per task workgroup (64, 128, 256 or 512,
- * at least G; a (cell, octant) task's (angle, group) solves run 64 per
- * wavefront), resident workgroups per CU (capped at the occupancy maximum)
- * and the graph chunk length of snx_solve (iterations captured per host
- * check).  Any argument <= 0 keeps the current value. */
+/* Sweep schedule knobs: threads per task workgroup (64, 128, 192, 256 or
+ * 512, at least G; a (cell, octant) task's (angle, group) solves run 64 per
+ * wavefront, in rounds when there are more solves than threads), resident
+ * workgroups per CU (capped at the occupancy maximum) and the graph chunk
+ * length of snx_solve (iterations captured per host check).  Any argument
+ * <= 0 keeps the current value; until threads is set, the narrowest width
+ * that holds a whole task in one round (at most 256, at least G) is used. */
 snx_status snx_set_schedule(snx_problem *p, int32_t threads, int32_t wg_per_cu, int32_t chunk);
 
 /* Schedule autotuner: times a few sweeps of every (threads, workgroups per

@@ -66,6 +66,8 @@ struct Sched {
     std::vector<DevProblem> hprobs;
     long long total = 0;
     int maxA = 0, maxG = 0, maxin = 1;
+    int maxAG = 0;                           // largest (angles per octant) * G of the problems
+    bool one = false;                        // every task is one round of lanes (maxAG <= threads)
     int threads = 256, wg_per_cu = 0, grid = 0, chunk = 8;
     unsigned long long watchdog = 0;
     hipStream_t cap_stream = nullptr;
@@ -112,7 +114,7 @@ struct snx_problem {
     double *d_partial = nullptr, *d_out4 = nullptr;
     double *d_area = nullptr;
     unsigned long long watchdog_ticks = 0;
-    int threads = 256, wg_per_cu = 0, chunk = 8;   // requested sweep schedule
+    int threads = 0, wg_per_cu = 0, chunk = 8;     // requested sweep schedule (threads 0: automatic)
     int nq = 1;                         // task queues = XCDs seen on the device
     int xcc_queue[kMaxXcc] = {0};       // home queue of each hardware XCC id
     Sched sched;                        // the problem's own schedule of one
@@ -121,7 +123,7 @@ struct snx_problem {
 struct snx_batch {
     int device = 0;
     Sched sched;
-    int threads = 256, wg_per_cu = 0, chunk = 8;
+    int threads = 0, wg_per_cu = 0, chunk = 8;
 };
 
 namespace {
@@ -154,11 +156,24 @@ void drop_device(snx_problem *p) {
     p->hp = DevProblem{};
 }
 
+// Workgroup width: the requested one if valid and at least G, else the
+// narrowest width that holds a whole task in one round (at most 256), and never
+// less than G.
+int pick_threads(int requested, int maxG, int maxAG) {
+    static const int kWidths[] = {64, 128, 192, 256, 512};
+    if (requested > 0 && sweep_threads_valid(requested) && requested >= maxG) return requested;
+    const int want = requested > 0 ? std::max(requested, maxG) : std::max(maxG, std::min(maxAG, 256));
+    for (int w : kWidths)
+        if (w >= want) return w;
+    return 512;
+}
+
 // Grid of the persistent sweep: resident workgroups per CU times the CUs.
 snx_status configure_grid(Sched &sc) {
-    const size_t lds = sweep_lds_bytes(sc.threads, sc.maxA, sc.maxG, sc.maxin);
+    sc.one = sc.maxAG <= sc.threads;
+    const size_t lds = sweep_lds_bytes(sc.threads, sc.maxA, sc.maxG, sc.maxin, sc.one);
     if (lds > 64 * 1024) return fail_msg(sc.err, SNX_E_ARG, "task does not fit in 64 KB of LDS (too many angles or groups)");
-    const int occ = sweep_occupancy(sc.threads, lds);
+    const int occ = sweep_occupancy(sc.threads, sc.one, lds);
     if (occ <= 0) return fail_msg(sc.err, SNX_E_ARG, "sweep kernel cannot be resident with this schedule");
     const int per_cu = sc.wg_per_cu > 0 ? std::min(sc.wg_per_cu, occ) : occ;
     long long grid = (long long)cu_count(sc.device) * per_cu;
@@ -196,7 +211,7 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
     sc.hprobs.clear();
     std::vector<long long> base(n + 1, 0);
     std::vector<int> blk(n + 1, 0), seed_off(8 * n + 1, 0), seeds;
-    sc.maxA = sc.maxG = 0;
+    sc.maxA = sc.maxG = sc.maxAG = 0;
     sc.maxin = 1;
     for (int i = 0; i < n; ++i) {
         snx_problem *p = probs[i];
@@ -207,6 +222,7 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
         blk[i + 1] = blk[i] + (int)(((long long)p->C * p->G + 255) / 256);
         sc.maxA = std::max(sc.maxA, p->A);
         sc.maxG = std::max(sc.maxG, p->G);
+        sc.maxAG = std::max(sc.maxAG, p->A * p->G);
         sc.maxin = std::max(sc.maxin, p->maxin);
         for (int o = 0; o < 8; ++o) {
             seed_off[i * 8 + o] = (int)seeds.size();
@@ -216,8 +232,7 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
     seed_off[8 * n] = (int)seeds.size();
     sc.total = base[n];
     sc.nblk = blk[n];
-    sc.threads = threads;
-    while (sc.threads < sc.maxG) sc.threads *= 2;
+    sc.threads = pick_threads(threads, sc.maxG, sc.maxAG);
     sc.wg_per_cu = wg_per_cu;
     sc.chunk = chunk;
 
@@ -274,7 +289,8 @@ snx_status enqueue_sweep(Sched &sc, const int *stops, hipStream_t s, hipEvent_t 
     HIPCHK_E(sc.err, launch_sweep_prologue(sc.d_ctl, sc.d_queue, sc.d_probs, sc.nprob(), sc.d_seeds, sc.d_seed_off,
                                            stops, s), "sweep prologue");
     if (ev0) HIPCHK_E(sc.err, hipEventRecord(ev0, s), "event");
-    HIPCHK_E(sc.err, launch_sweep_kernel(sc.d_probs, sc.nprob(), sc.d_base, sc.d_ctl, sc.d_queue, sc.threads, sc.grid,
+    HIPCHK_E(sc.err, launch_sweep_kernel(sc.d_probs, sc.nprob(), sc.d_base, sc.d_ctl, sc.d_queue, sc.threads, sc.one,
+                                         sc.grid,
                                          sc.maxA, sc.maxG, sc.maxin, sc.watchdog, s), "sweep launch");
     if (ev1) HIPCHK_E(sc.err, hipEventRecord(ev1, s), "event");
     return SNX_OK;
@@ -508,7 +524,7 @@ snx_status tune_sched(Sched &sc, const char *cache, hipStream_t s, int *out_thre
     }
     double best = 1e300;
     int bt = sc.threads, bw = sc.wg_per_cu;
-    for (int th : {64, 128, 256, 512}) {
+    for (int th : {64, 128, 192, 256, 512}) {
         if (th < sc.maxG) continue;
         for (int wg : {0, 2, 4, 8}) {
             sc.threads = th;
@@ -862,15 +878,14 @@ snx_status snx_get_levels(snx_problem *p, int32_t *level, int32_t *nlevels) {
 snx_status snx_set_schedule(snx_problem *p, int32_t threads, int32_t wg_per_cu, int32_t chunk) {
     if (!p) return SNX_E_ARG;
     if (threads > 0) {
-        if (threads != 64 && threads != 128 && threads != 256 && threads != 512)
-            return fail(p, SNX_E_ARG, "threads must be 64, 128, 256 or 512");
+        if (!sweep_threads_valid(threads)) return fail(p, SNX_E_ARG, "threads must be 64, 128, 192, 256 or 512");
         if (p->have_mat && threads < p->G) return fail(p, SNX_E_ARG, "threads must be at least G");
         p->threads = threads;
     }
     if (wg_per_cu > 0) p->wg_per_cu = wg_per_cu;
     if (chunk > 0) p->chunk = chunk;
     if (!p->ready) return SNX_OK;
-    p->sched.threads = p->threads;
+    if (p->threads > 0) p->sched.threads = p->threads;
     p->sched.wg_per_cu = p->wg_per_cu;
     p->sched.chunk = p->chunk;
     p->sched.drop_graphs();
@@ -980,8 +995,8 @@ const char *snx_batch_last_error(const snx_batch *b) { return b ? b->sched.err.c
 snx_status snx_batch_set_schedule(snx_batch *b, int32_t threads, int32_t wg_per_cu, int32_t chunk) {
     if (!b) return SNX_E_ARG;
     if (threads > 0) {
-        if (threads != 64 && threads != 128 && threads != 256 && threads != 512)
-            return fail_msg(b->sched.err, SNX_E_ARG, "threads must be 64, 128, 256 or 512");
+        if (!sweep_threads_valid(threads))
+            return fail_msg(b->sched.err, SNX_E_ARG, "threads must be 64, 128, 192, 256 or 512");
         if (threads < b->sched.maxG) return fail_msg(b->sched.err, SNX_E_ARG, "threads must be at least the largest G");
         b->sched.threads = threads;
     }

@@ -36,6 +36,10 @@
 namespace snx {
 namespace {
 
+#ifndef WAVES_ONE
+#define WAVES_ONE 4
+#endif
+
 // Global address space: loads and stores through these pointers compile to
 // global_* instructions instead of flat ones (device pass only).
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -95,28 +99,29 @@ struct LaneIn {
     float up[6][4];
 };
 
-__device__ __forceinline__ void load_lane(const DevProblem &P, int K, int mask, int n, int g,
-                                          const GLOBAL float *psi_o, size_t cell_psi, LaneIn &L) {
-    const int G = P.G, A = P.A;
-    const GLOBAL float4 *rv = reinterpret_cast<const GLOBAL float4 *>(gp(P.r) + ((size_t)K * G + g) * 8);
+// Source dofs and sigma_t of lane (n, g) of cell K: no dependence on other tasks.
+__device__ __forceinline__ void load_own(const DevProblem &P, int K, int g, LaneIn &L) {
+    const GLOBAL float4 *rv = reinterpret_cast<const GLOBAL float4 *>(gp(P.r) + ((size_t)K * P.G + g) * 8);
     const float4 r0 = rv[0], r1 = rv[1];
     L.r[0] = r0.x; L.r[1] = r0.y; L.r[2] = r0.z; L.r[3] = r0.w;
     L.r[4] = r1.x; L.r[5] = r1.y; L.r[6] = r1.z; L.r[7] = r1.w;
-    L.sig = gp(P.sigt)[(size_t)K * G + g];
-    const float psib = P.psib ? gp(P.psib)[g] : 0.f;
+    L.sig = gp(P.sigt)[(size_t)K * P.G + g];
+}
+
+// Upwind traces of lane (n, g) on every inflow face; nb / pm are the task's
+// (uniform) neighbour ids and node permutations, so all loads issue at once.
+// A boundary face reads dof 0 of cell K instead (any valid address); its
+// value is replaced by the inflow ψ_b where the traces are used.
+__device__ __forceinline__ void load_up(int K, int mask, const int (&nb)[6], const unsigned (&pm)[6], int n, int g,
+                                        int G, int A, const GLOBAL float *psi_o, size_t cell_psi, LaneIn &L) {
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         if (!((mask >> f) & 1)) continue;
-        const int N = uni(gp(P.nbr)[(size_t)K * 6 + f]);
-        if (N >= 0) {
-            const unsigned pm = (unsigned)uni((int)gp(P.perm)[(size_t)K * 6 + f]);
-            const GLOBAL float *pn = psi_o + (size_t)N * cell_psi + (size_t)n * G + g;
+        const int N = nb[f] >= 0 ? nb[f] : K;
+        const unsigned perm = nb[f] >= 0 ? pm[f] : 0u;
+        const GLOBAL float *pn = psi_o + (size_t)N * cell_psi + (size_t)n * G + g;
 #pragma unroll
-            for (int l = 0; l < 4; ++l) L.up[f][l] = ld_agent(pn + (size_t)((pm >> (8 * l)) & 0xff) * A * G);
-        } else {
-#pragma unroll
-            for (int l = 0; l < 4; ++l) L.up[f][l] = psib;
-        }
+        for (int l = 0; l < 4; ++l) L.up[f][l] = ld_agent(pn + (size_t)((perm >> (8 * l)) & 0xff) * A * G);
     }
 }
 
@@ -165,8 +170,11 @@ __device__ long long pop_task(SweepCtl *ctl, unsigned long long *queue, int &q, 
 
 // LDS layout (floats): M[64] T[3][64] Fin[6][48] om[A][4] Bop[A][64] Cop[A][maxin][16]
 //                      wpsi[2][NT][8] red_s[G][8] red_c[G][8]
-template <int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(
+// ONE: every problem of the launch has A*G <= NT, so a task is one round of
+// lanes; nothing is prefetched for a next round and wpsi has one buffer, which
+// lowers the register and LDS footprint and lets more workgroups be resident.
+template <int NT, bool ONE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_ONE : 4))) void k_sweep(
     const DevProblem *__restrict__ probs, int nprob, const long long *__restrict__ task_base,
     SweepCtl *__restrict__ ctl, unsigned long long *__restrict__ queue, int maxA, int maxG, int maxin,
     unsigned long long watchdog) {
@@ -174,6 +182,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ long long s_task;
     __shared__ int s_q;
     __shared__ int s_nready;
+    __shared__ int s_desc[13];            // neighbour ids [6], node permutations [6], inflow mask
     __shared__ long long s_ready[6];
     if (ctl->nactive == 0) return;
     const unsigned epoch = ctl->epoch;
@@ -183,12 +192,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
     float *sM = lds;
     float *sT = sM + 64;                  // T^x, T^y, T^z of this (cell, octant)
-    float *sF = sT + 192;                 // up to 6 inflow faces x 48
+    float *sF = sT + 192;                 // the six face matrices F^x, F^y, F^z (48 each)
     float *sOm = sF + 6 * 48;             // [maxA][4]: omega xyz, weight
     float *sB = sOm + 4 * maxA;           // [maxA][64]
     float *sC = sB + 64 * maxA;           // [maxA][maxin][16]
     float *sW = sC + 16 * maxin * maxA;   // [2][NT][8]
-    float *sRs = sW + 16 * NT;            // [maxG][8]
+    float *sRs = sW + (ONE ? 8 : 16) * NT; // [maxG][8]
     float *sRc = sRs + 8 * maxG;          // [maxG][8]
 
     // Workgroup statistics, kept in LDS and touched by thread 0 only: polls, tasks,
@@ -233,49 +242,72 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const long long local = task - P.task_base;
         const int o = uni((int)(local / C));
         const int K = uni((int)(local - (long long)o * C));
-        const int mask = uni(gp(P.inmask)[(size_t)o * C + K]);
-        const int nin = __popc(mask);
         const int AG = A * G;
         const size_t cell_psi = (size_t)8 * A * G;          // floats per (octant, cell)
         GLOBAL float *psi_o = gp(P.psi) + (size_t)o * C * cell_psi;
 
-        // ---------------------------------------------------- stage geometry
-        // Cell data (M, T^a of this octant, inflow face matrices) as float4s; the
-        // lane inputs are issued only after these reach LDS, so the wait for the
-        // cell data never includes the (agent-coherent, slower) upwind loads.
-        const int nst = 64 + 12 * nin;                          // float4s to stage
-        auto stage_item = [&](int i) -> float4 {
+        // ---------------------------------------------------------- stage
+        // One round trip brings the cell data (M, T^a of this octant, the six
+        // face matrices; 136 float4s), the neighbour ids, node permutations and
+        // inflow mask (13 words, to LDS), the directions, and each lane's own
+        // source dofs and sigma_t.  The upwind traces follow in a second round
+        // trip once the neighbour ids are in LDS, all faces at once.
+        constexpr int kGeo = 16 + 48 + 72, kItems = kGeo + 13;
+        auto stage_word = [&](int i) {
+            if (i < 12) {
+                const int f = i % 6;
+                if (i < 6) s_desc[i] = gp(P.nbr)[(size_t)K * 6 + f];
+                else s_desc[i] = (int)gp(P.perm)[(size_t)K * 6 + f];
+            } else {
+                s_desc[12] = gp(P.inmask)[(size_t)o * C + K];
+            }
+        };
+        auto stage_geo = [&](int i) -> float4 {
             if (i < 16) return reinterpret_cast<const GLOBAL float4 *>(gp(P.M) + (size_t)K * 64)[i];
             if (i < 64) return reinterpret_cast<const GLOBAL float4 *>(gp(P.T) + ((size_t)o * C + K) * 192)[i - 16];
-            const int s = (i - 64) / 12, e = (i - 64) - s * 12;
-            int m = mask;                                       // face of inflow slot s: s-th set bit of mask
-            for (int k = 0; k < s; ++k) m &= m - 1;
-            const int f = __ffs(m) - 1;
-            return reinterpret_cast<const GLOBAL float4 *>(gp(P.F) + ((size_t)K * 6 + f) * 48)[e];
+            return reinterpret_cast<const GLOBAL float4 *>(gp(P.F) + (size_t)K * 288)[i - 64];
         };
         float4 om4 = make_float4(0.f, 0.f, 0.f, 0.f);          // direction and weight of angle tid (A <= 64 <= NT)
-        if constexpr (NT >= 136) {
+        LaneIn L;
+        if constexpr (NT >= kItems) {
             // at most one item per thread: all loads in flight together
-            const float4 st = tid < nst ? stage_item(tid) : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 st = tid < kGeo ? stage_geo(tid) : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (tid >= kGeo && tid < kItems) stage_word(tid - kGeo);
             if (tid < A) {
                 const int n = o * A + tid;
                 om4 = make_float4(gp(P.omega)[3 * n + 0], gp(P.omega)[3 * n + 1], gp(P.omega)[3 * n + 2], gp(P.w)[n]);
             }
-            if (tid < nst) reinterpret_cast<float4 *>(sM)[tid] = st;   // M, T and F are contiguous in LDS
+            if (tid < AG) load_own(P, K, tid % G, L);
+            if (tid < kGeo) reinterpret_cast<float4 *>(sM)[tid] = st;   // M, T and F are contiguous in LDS
         } else {
             if (tid < A) {
                 const int n = o * A + tid;
                 om4 = make_float4(gp(P.omega)[3 * n + 0], gp(P.omega)[3 * n + 1], gp(P.omega)[3 * n + 2], gp(P.w)[n]);
             }
-            for (int i = tid; i < nst; i += NT) reinterpret_cast<float4 *>(sM)[i] = stage_item(i);
+            if (tid < AG) load_own(P, K, tid % G, L);
+            for (int i = tid; i < kItems; i += NT) {
+                if (i < kGeo) reinterpret_cast<float4 *>(sM)[i] = stage_geo(i);
+                else stage_word(i - kGeo);
+            }
         }
         if (tid < A) reinterpret_cast<float4 *>(sOm)[tid] = om4;
-        // the first round's lane inputs are in flight during the operator build
-        LaneIn L;
-        if (tid < AG) load_lane(P, K, mask, tid / G, tid % G, psi_o, cell_psi, L);
         for (int i = tid; i < G * 8; i += NT) { sRs[i] = 0.f; sRc[i] = 0.f; }
         __syncthreads();
-        if (tid == 0) s_nready = 0;
+        if (tid == 0) s_nready = 0;   // after the barrier: every thread has read the last task's count
+        const int mask = uni(s_desc[12]);
+        const int nin = __popc(mask);
+        int nb[6];
+        unsigned pm[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            nb[f] = uni(s_desc[f]);
+            pm[f] = (unsigned)uni(s_desc[6 + f]);
+        }
+        // multi-round tasks: the first round's upwind traces are in flight during
+        // the operator build; one-round tasks issue them after it, which keeps
+        // their registers free while the operators are built
+        if constexpr (!ONE)
+            if (tid < AG) load_up(K, mask, nb, pm, tid / G, tid % G, G, A, psi_o, cell_psi, L);
         if (tid == 0) { const unsigned long long t = clock64(); s_ph[1] += t - s_mark; s_mark = t; }
 
         // ------------------------------------- per-angle operators B_n, C_n,f
@@ -285,40 +317,53 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         }
         for (int e = tid; e < A * nin * 16; e += NT) {
             const int n = e / (nin * 16), rem = e - n * nin * 16, s = rem >> 4, kl = rem & 15;
-            const float *Fs = sF + s * 48;
+            int m = mask;                                       // face of inflow slot s: s-th set bit of mask
+            for (int k = 0; k < s; ++k) m &= m - 1;
+            const float *Fs = sF + (__ffs(m) - 1) * 48;
             sC[(n * maxin + s) * 16 + kl] =
                 sOm[4 * n] * Fs[kl] + sOm[4 * n + 1] * Fs[16 + kl] + sOm[4 * n + 2] * Fs[32 + kl];
         }
         __syncthreads();
+        if constexpr (ONE)
+            if (tid < AG) load_up(K, mask, nb, pm, tid / G, tid % G, G, A, psi_o, cell_psi, L);
         if (tid == 0) { const unsigned long long t = clock64(); s_ph[2] += t - s_mark; s_mark = t; }
 
         // ------------------------------------------------ rounds of lanes
         int buf = 0;
-        for (int base = 0; base < AG; base += NT, buf ^= 1) {
+        for (int base = 0; ONE ? base == 0 : base < AG; base += NT, buf ^= 1) {
             const int pi = base + tid;
-            float *sWb = sW + buf * NT * 8;
+            float *sWb = ONE ? sW : sW + buf * NT * 8;
             if (pi < AG) {
                 const int n = pi / G, g = pi - n * G;
                 float b[8];
 #pragma unroll
                 for (int d = 0; d < 8; ++d) b[d] = L.r[d];
+                const float psib = P.psib ? gp(P.psib)[g] : 0.f;
 #pragma unroll
                 for (int f = 0; f < 6; ++f) {
                     if (!((mask >> f) & 1)) continue;
                     const float *Cs = sC + (n * maxin + __popc(mask & ((1 << f) - 1))) * 16;
+                    float u[4];
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) u[l] = nb[f] >= 0 ? L.up[f][l] : psib;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        float t = Cs[k * 4] * L.up[f][0];
-                        t = __builtin_fmaf(Cs[k * 4 + 1], L.up[f][1], t);
-                        t = __builtin_fmaf(Cs[k * 4 + 2], L.up[f][2], t);
-                        t = __builtin_fmaf(Cs[k * 4 + 3], L.up[f][3], t);
+                        float t = Cs[k * 4] * u[0];
+                        t = __builtin_fmaf(Cs[k * 4 + 1], u[1], t);
+                        t = __builtin_fmaf(Cs[k * 4 + 2], u[2], t);
+                        t = __builtin_fmaf(Cs[k * 4 + 3], u[3], t);
                         b[face_vertex(f, k)] -= t;
                     }
                 }
                 const float sig = L.sig;
                 // the next round's inputs are in flight during this round's solve
-                const int pn = pi + NT;
-                if (pn < AG) load_lane(P, K, mask, pn / G, pn % G, psi_o, cell_psi, L);
+                if constexpr (!ONE) {
+                    const int pn = pi + NT;
+                    if (pn < AG) {
+                        load_own(P, K, pn % G, L);
+                        load_up(K, mask, nb, pm, pn / G, pn % G, G, A, psi_o, cell_psi, L);
+                    }
+                }
 
                 // Unpivoted LU, one row of A = B_n + sigma_t M at a time (Doolittle by rows):
                 // row i is reduced by the finished rows k < i; only the strict upper
@@ -344,6 +389,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     inv[i] = __builtin_amdgcn_rcpf(row[i]);
 #pragma unroll
                     for (int j = i + 1; j < 8; ++j) U[i][j] = row[j];
+                    if constexpr (ONE) __builtin_amdgcn_sched_barrier(0);   // one row's loads in flight at a time
                 }
 #pragma unroll
                 for (int k = 7; k >= 0; --k) {
@@ -391,7 +437,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         __syncthreads();
         if (tid < 6) {
             const int f = tid;
-            const int N = ((mask >> f) & 1) ? -1 : gp(P.nbr)[(size_t)K * 6 + f];
+            const int N = ((mask >> f) & 1) ? -1 : s_desc[f];
             if (N >= 0) {
                 const unsigned old = __hip_atomic_fetch_add(gp(P.cnt) + (size_t)o * C + N, 1u, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT);
@@ -479,33 +525,38 @@ __global__ void k_xcc_probe(int *out) {
     if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
 }
 
-template <int NT>
+template <int NT, bool ONE>
 hipError_t launch_nt(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                      unsigned long long *queue, int maxA, int maxG, int maxin, int grid, size_t lds,
                      unsigned long long watchdog, hipStream_t s) {
-    hipLaunchKernelGGL(k_sweep<NT>, dim3(grid), dim3(NT), lds, s, probs, nprob, task_base, ctl, queue, maxA, maxG,
-                       maxin, watchdog);
+    hipLaunchKernelGGL((k_sweep<NT, ONE>), dim3(grid), dim3(NT), lds, s, probs, nprob, task_base, ctl, queue, maxA,
+                       maxG, maxin, watchdog);
     return hipGetLastError();
 }
 
-template <int NT>
-const void *kernel_ptr() { return reinterpret_cast<const void *>(&k_sweep<NT>); }
+template <int NT, bool ONE>
+const void *kernel_ptr() { return reinterpret_cast<const void *>(&k_sweep<NT, ONE>); }
 
 }  // namespace
 
-size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin) {
+bool sweep_threads_valid(int threads) {
+    return threads == 64 || threads == 128 || threads == 192 || threads == 256 || threads == 512;
+}
+
+size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin, bool one) {
     size_t floats = 64 + 192 + 6 * 48 + 4 * (size_t)maxA + 64 * (size_t)maxA + 16 * (size_t)maxin * maxA +
-                    16 * (size_t)threads + 16 * (size_t)maxG;
+                    (one ? 8 : 16) * (size_t)threads + 16 * (size_t)maxG;
     return floats * sizeof(float);
 }
 
-int sweep_occupancy(int threads, size_t lds) {
+int sweep_occupancy(int threads, bool one, size_t lds) {
     const void *k = nullptr;
     switch (threads) {
-        case 64: k = kernel_ptr<64>(); break;
-        case 128: k = kernel_ptr<128>(); break;
-        case 256: k = kernel_ptr<256>(); break;
-        case 512: k = kernel_ptr<512>(); break;
+        case 64: k = one ? kernel_ptr<64, true>() : kernel_ptr<64, false>(); break;
+        case 128: k = one ? kernel_ptr<128, true>() : kernel_ptr<128, false>(); break;
+        case 192: k = one ? kernel_ptr<192, true>() : kernel_ptr<192, false>(); break;
+        case 256: k = one ? kernel_ptr<256, true>() : kernel_ptr<256, false>(); break;
+        case 512: k = one ? kernel_ptr<512, true>() : kernel_ptr<512, false>(); break;
         default: return 0;
     }
     int nb = 0;
@@ -525,16 +576,21 @@ hipError_t launch_xcc_probe(int *out, int nblocks, hipStream_t s) {
 }
 
 hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
-                               unsigned long long *queue, int threads, int grid, int maxA, int maxG, int maxin,
-                               unsigned long long watchdog, hipStream_t s) {
-    const size_t lds = sweep_lds_bytes(threads, maxA, maxG, maxin);
+                               unsigned long long *queue, int threads, bool one, int grid, int maxA, int maxG,
+                               int maxin, unsigned long long watchdog, hipStream_t s) {
+    const size_t lds = sweep_lds_bytes(threads, maxA, maxG, maxin, one);
+#define SNX_LAUNCH(NT)                                                                                            \
+    return one ? launch_nt<NT, true>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds, watchdog, s) \
+               : launch_nt<NT, false>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds, watchdog, s)
     switch (threads) {
-        case 64: return launch_nt<64>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds, watchdog, s);
-        case 128: return launch_nt<128>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds, watchdog, s);
-        case 256: return launch_nt<256>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds, watchdog, s);
-        case 512: return launch_nt<512>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds, watchdog, s);
+        case 64: SNX_LAUNCH(64);
+        case 128: SNX_LAUNCH(128);
+        case 192: SNX_LAUNCH(192);
+        case 256: SNX_LAUNCH(256);
+        case 512: SNX_LAUNCH(512);
         default: return hipErrorInvalidValue;
     }
+#undef SNX_LAUNCH
 }
 
 }  // namespace snx

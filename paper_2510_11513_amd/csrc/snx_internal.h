@@ -93,13 +93,16 @@ hipError_t launch_dag_one(int C, const int *nbr, const double *area, unsigned ch
 hipError_t launch_sweep_prologue(SweepCtl *ctl, unsigned long long *queue, const DevProblem *probs, int nprob,
                                  const int *seeds, const int *seed_off, const int *stops, hipStream_t s);
 hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
-                               unsigned long long *queue, int threads, int grid, int maxA, int maxG, int maxin,
+                               unsigned long long *queue, int threads, bool one, int grid, int maxA, int maxG, int maxin,
                                unsigned long long watchdog, hipStream_t s);
 hipError_t launch_xcc_probe(int *out, int nblocks, hipStream_t s);
 hipError_t launch_octant_operators(int C, const float *S, const float *F, const unsigned char *inmask, float *T,
                                    hipStream_t s);
-size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin);
-int sweep_occupancy(int threads, size_t lds);
+// Workgroup widths of the sweep kernel: 64, 128, 192, 256 or 512.
+bool sweep_threads_valid(int threads);
+// `one`: every problem of the launch has (angles per octant) * G <= threads.
+size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin, bool one);
+int sweep_occupancy(int threads, bool one, size_t lds);
 hipError_t launch_source(const DevProblem *probs, int prob, int C, int G, const float *phi, int *stop_flag,
                          hipStream_t s);
 hipError_t launch_reduce(const DevProblem *probs, int prob, int C, int G, float *phi_out, const float *phi_old,
