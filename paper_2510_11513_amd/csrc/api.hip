@@ -107,7 +107,7 @@ struct snx_problem {
     DevAlloc mem;
     DevProblem hp{};
     std::vector<int> level, nlev;
-    std::vector<std::vector<int>> seeds_by_octant;   // local task ids (o*C + K) of level-0 cells
+    std::vector<std::vector<int>> seeds_by_octant;   // local task ids (8*K + o) of level-0 cells
     int maxin = 1;
     int *d_err = nullptr;
     float *d_phi[2] = {nullptr, nullptr};
@@ -792,7 +792,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     HIPCHK(p, hipMemcpy(seeds_host.data(), dseeds, sizeof(int) * 8 * C, hipMemcpyDeviceToHost), "copy");
     p->seeds_by_octant.assign(8, {});
     for (int o = 0; o < 8; ++o)
-        for (int i = 0; i < nseed[o]; ++i) p->seeds_by_octant[o].push_back(o * p->C + seeds_host[(size_t)o * C + i]);
+        for (int i = 0; i < nseed[o]; ++i) p->seeds_by_octant[o].push_back(8 * seeds_host[(size_t)o * C + i] + o);
 
     hp.C = p->C; hp.G = p->G; hp.A = p->A; hp.nang = p->nang; hp.task_base = 0; hp.epoch = depoch;
     hp.M = dM; hp.S = dS; hp.T = dT; hp.F = dF; hp.nbr = d_nbr; hp.perm = d_perm; hp.inmask = dmask; hp.indeg = dindeg;

@@ -82,6 +82,11 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
     e = (a - (s - bb)) + (b - bb);
 }
 
+// floor(a / b) for 0 <= a < 2^20 and b >= 1 from inv_b ~ 1 / b (within a few ulp):
+// (a + 0.5) / b lies at least 0.5 / b away from an integer, far more than the
+// relative error of inv_b and of the product.
+__device__ __forceinline__ int div_small(int a, float inv_b) { return (int)(((float)a + 0.5f) * inv_b); }
+
 __device__ __forceinline__ int find_problem(const long long *__restrict__ base, int nprob, long long task) {
     int lo = 0, hi = nprob - 1;
     while (lo < hi) {
@@ -108,20 +113,36 @@ __device__ __forceinline__ void load_own(const DevProblem &P, int K, int g, Lane
     L.sig = gp(P.sigt)[(size_t)K * P.G + g];
 }
 
-// Upwind traces of lane (n, g) on every inflow face; nb / pm are the task's
-// (uniform) neighbour ids and node permutations, so all loads issue at once.
-// A boundary face reads dof 0 of cell K instead (any valid address); its
-// value is replaced by the inflow ψ_b where the traces are used.
-__device__ __forceinline__ void load_up(int K, int mask, const int (&nb)[6], const unsigned (&pm)[6], int n, int g,
-                                        int G, int A, const GLOBAL float *psi_o, size_t cell_psi, LaneIn &L) {
+// psi of one (octant, cell) is [dof][angle][group]: lane p = n*G + g of a task
+// finds dof d at float d*A*G + p.  Each cell's block is addressed through a
+// buffer resource (base and size in scalar registers), so a lane's address is
+// the 32-bit byte offset 4p and the dof offset is a scalar: no per-lane 64-bit
+// address arithmetic.  kCoherentAccess is the sc1 cache policy of agent-scope
+// accesses, so hand-offs between CUs and XCDs see each other's values.
+constexpr int kCoherentAccess = 16;
+constexpr int kRawBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t cell_block(const float *psi_o, int cell, int cell_floats) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(psi_o) + (size_t)cell * cell_floats, (short)0,
+                                             cell_floats * 4, kRawBufferWord3);
+}
+
+// Upwind traces of lane p on every inflow face; nb / pm are the task's (uniform)
+// neighbour ids and node permutations, so all loads issue at once.  A boundary
+// face reads dof 0 of cell K instead (any valid address); its value is replaced
+// by the inflow psi_b where the traces are used.
+__device__ __forceinline__ void load_up(int K, int mask, const int (&nb)[6], const unsigned (&pm)[6], int p,
+                                        int AG, const float *psi_o, LaneIn &L) {
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         if (!((mask >> f) & 1)) continue;
         const int N = nb[f] >= 0 ? nb[f] : K;
         const unsigned perm = nb[f] >= 0 ? pm[f] : 0u;
-        const GLOBAL float *pn = psi_o + (size_t)N * cell_psi + (size_t)n * G + g;
+        const __amdgpu_buffer_rsrc_t rs = cell_block(psi_o, N, 8 * AG);
 #pragma unroll
-        for (int l = 0; l < 4; ++l) L.up[f][l] = ld_agent(pn + (size_t)((perm >> (8 * l)) & 0xff) * A * G);
+        for (int l = 0; l < 4; ++l)
+            L.up[f][l] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                rs, 4 * p, (int)((perm >> (8 * l)) & 0xff) * AG * 4, kCoherentAccess));
     }
 }
 
@@ -240,11 +261,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         const DevProblem &P = probs[p];
         const int C = P.C, G = P.G, A = P.A;
         const long long local = task - P.task_base;
-        const int o = uni((int)(local / C));
-        const int K = uni((int)(local - (long long)o * C));
+        const int o = uni((int)(local & 7));                 // task = 8 * cell + octant
+        const int K = uni((int)(local >> 3));
         const int AG = A * G;
+        const float invG = __builtin_amdgcn_rcpf((float)G);
+        const int ln = div_small(tid, invG), lg = tid - ln * G;  // (angle, group) of this lane in the first round
         const size_t cell_psi = (size_t)8 * A * G;          // floats per (octant, cell)
-        GLOBAL float *psi_o = gp(P.psi) + (size_t)o * C * cell_psi;
+        const float *psi_o = P.psi + (size_t)o * C * cell_psi;
 
         // ---------------------------------------------------------- stage
         // One round trip brings the cell data (M, T^a of this octant, the six
@@ -277,14 +300,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 const int n = o * A + tid;
                 om4 = make_float4(gp(P.omega)[3 * n + 0], gp(P.omega)[3 * n + 1], gp(P.omega)[3 * n + 2], gp(P.w)[n]);
             }
-            if (tid < AG) load_own(P, K, tid % G, L);
+            if (tid < AG) load_own(P, K, lg, L);
             if (tid < kGeo) reinterpret_cast<float4 *>(sM)[tid] = st;   // M, T and F are contiguous in LDS
         } else {
             if (tid < A) {
                 const int n = o * A + tid;
                 om4 = make_float4(gp(P.omega)[3 * n + 0], gp(P.omega)[3 * n + 1], gp(P.omega)[3 * n + 2], gp(P.w)[n]);
             }
-            if (tid < AG) load_own(P, K, tid % G, L);
+            if (tid < AG) load_own(P, K, lg, L);
             for (int i = tid; i < kItems; i += NT) {
                 if (i < kGeo) reinterpret_cast<float4 *>(sM)[i] = stage_geo(i);
                 else stage_word(i - kGeo);
@@ -307,7 +330,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         // the operator build; one-round tasks issue them after it, which keeps
         // their registers free while the operators are built
         if constexpr (!ONE)
-            if (tid < AG) load_up(K, mask, nb, pm, tid / G, tid % G, G, A, psi_o, cell_psi, L);
+            if (tid < AG) load_up(K, mask, nb, pm, tid, AG, psi_o, L);
         if (tid == 0) { const unsigned long long t = clock64(); s_ph[1] += t - s_mark; s_mark = t; }
 
         // ------------------------------------- per-angle operators B_n, C_n,f
@@ -315,8 +338,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             const int n = e >> 6, ij = e & 63;
             sB[e] = sOm[4 * n] * sT[ij] + sOm[4 * n + 1] * sT[64 + ij] + sOm[4 * n + 2] * sT[128 + ij];
         }
+        const float inv_nin = __builtin_amdgcn_rcpf((float)max(nin, 1));
         for (int e = tid; e < A * nin * 16; e += NT) {
-            const int n = e / (nin * 16), rem = e - n * nin * 16, s = rem >> 4, kl = rem & 15;
+            const int ns = e >> 4, kl = e & 15;
+            const int n = div_small(ns, inv_nin), s = ns - n * nin;
             int m = mask;                                       // face of inflow slot s: s-th set bit of mask
             for (int k = 0; k < s; ++k) m &= m - 1;
             const float *Fs = sF + (__ffs(m) - 1) * 48;
@@ -325,7 +350,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         }
         __syncthreads();
         if constexpr (ONE)
-            if (tid < AG) load_up(K, mask, nb, pm, tid / G, tid % G, G, A, psi_o, cell_psi, L);
+            if (tid < AG) load_up(K, mask, nb, pm, tid, AG, psi_o, L);
         if (tid == 0) { const unsigned long long t = clock64(); s_ph[2] += t - s_mark; s_mark = t; }
 
         // ------------------------------------------------ rounds of lanes
@@ -334,7 +359,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             const int pi = base + tid;
             float *sWb = ONE ? sW : sW + buf * NT * 8;
             if (pi < AG) {
-                const int n = pi / G, g = pi - n * G;
+                const int n = ONE ? ln : div_small(pi, invG), g = ONE ? lg : pi - n * G;
                 float b[8];
 #pragma unroll
                 for (int d = 0; d < 8; ++d) b[d] = L.r[d];
@@ -360,8 +385,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 if constexpr (!ONE) {
                     const int pn = pi + NT;
                     if (pn < AG) {
-                        load_own(P, K, pn % G, L);
-                        load_up(K, mask, nb, pm, pn / G, pn % G, G, A, psi_o, cell_psi, L);
+                        const int nn = div_small(pn, invG), gn = pn - nn * G;
+                        load_own(P, K, gn, L);
+                        load_up(K, mask, nb, pm, pn, AG, psi_o, L);
                     }
                 }
 
@@ -398,11 +424,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                     for (int j = k + 1; j < 8; ++j) t = __builtin_fmaf(-U[k][j], b[j], t);
                     b[k] = t * inv[k];
                 }
-                GLOBAL float *pk = psi_o + (size_t)K * cell_psi + (size_t)n * G + g;
+                const __amdgpu_buffer_rsrc_t rk = cell_block(psi_o, K, 8 * AG);
                 const float wn = sOm[4 * n + 3];
 #pragma unroll
                 for (int d = 0; d < 8; ++d) {
-                    st_agent(pk + (size_t)d * A * G, b[d]);
+                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, b[d]), rk, 4 * pi, d * AG * 4,
+                                                          kCoherentAccess);
                     sWb[tid * 8 + d] = wn * b[d];
                 }
             }
@@ -413,7 +440,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             for (int e = tid; e < G * 8; e += NT) {
                 const int g = e >> 3, d = e & 7;
                 float s = sRs[e], c = sRc[e];
-                for (int q = base + ((g - base % G) % G + G) % G; q < hi; q += G) {
+                const int q0 = ONE ? g : base + ((g - base % G) % G + G) % G;   // first lane of group g
+                for (int q = q0; q < hi; q += G) {
                     float t, err;
                     two_sum(s, sWb[(q - base) * 8 + d], t, err);
                     s = t;
@@ -442,7 +470,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 const unsigned old = __hip_atomic_fetch_add(gp(P.cnt) + (size_t)o * C + N, 1u, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT);
                 const unsigned target = (unsigned)gp(P.indeg)[(size_t)o * C + N] * *P.epoch;
-                if (old + 1u == target) s_ready[atomicAdd(&s_nready, 1)] = P.task_base + (long long)o * C + N;
+                if (old + 1u == target) s_ready[atomicAdd(&s_nready, 1)] = P.task_base + 8LL * N + o;
             }
         }
         __syncthreads();
