@@ -37,7 +37,7 @@ namespace snx {
 namespace {
 
 #ifndef WAVES_ONE
-#define WAVES_ONE 4
+#define WAVES_ONE 5
 #endif
 
 // Global address space: loads and stores through these pointers compile to
@@ -349,8 +349,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 sOm[4 * n] * Fs[kl] + sOm[4 * n + 1] * Fs[16 + kl] + sOm[4 * n + 2] * Fs[32 + kl];
         }
         __syncthreads();
-        if constexpr (ONE)
-            if (tid < AG) load_up(K, mask, nb, pm, tid, AG, psi_o, L);
         if (tid == 0) { const unsigned long long t = clock64(); s_ph[2] += t - s_mark; s_mark = t; }
 
         // ------------------------------------------------ rounds of lanes
@@ -364,20 +362,66 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
 #pragma unroll
                 for (int d = 0; d < 8; ++d) b[d] = L.r[d];
                 const float psib = P.psib ? gp(P.psib)[g] : 0.f;
+                if constexpr (ONE) {
+                    // Inflow faces in slot order, up to three at a time: the upwind
+                    // traces of a group are loaded together into three slots (all in
+                    // flight at once), then each face takes its slot by a select, so
+                    // the node map of every face stays static.  Hexahedra of the
+                    // meshes here have three inflow faces per octant: one group.
+                    int m = mask;
+                    for (int s0 = 0; s0 < nin; s0 += 3) {
+                        float u[3][4];
+                        const int gmask = m;            // faces of this group: the next three set bits
 #pragma unroll
-                for (int f = 0; f < 6; ++f) {
-                    if (!((mask >> f) & 1)) continue;
-                    const float *Cs = sC + (n * maxin + __popc(mask & ((1 << f) - 1))) * 16;
-                    float u[4];
+                        for (int j = 0; j < 3; ++j) {
+                            const int f = m ? __builtin_ctz(m) : 0;
+                            m &= m - 1;
+                            const bool live = s0 + j < nin;
+                            const int Nf = live ? uni(s_desc[f]) : -1;
+                            const unsigned perm = Nf >= 0 ? (unsigned)uni(s_desc[6 + f]) : 0u;
+                            const __amdgpu_buffer_rsrc_t rs = cell_block(psi_o, Nf >= 0 ? Nf : K, 8 * AG);
 #pragma unroll
-                    for (int l = 0; l < 4; ++l) u[l] = nb[f] >= 0 ? L.up[f][l] : psib;
+                            for (int l = 0; l < 4; ++l) {
+                                const float v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                    rs, 4 * pi, (int)((perm >> (8 * l)) & 0xff) * AG * 4, kCoherentAccess));
+                                u[j][l] = Nf >= 0 ? v : psib;
+                            }
+                        }
+                        const int inflight = gmask & ~m;  // the (up to) three faces just loaded
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        float t = Cs[k * 4] * u[0];
-                        t = __builtin_fmaf(Cs[k * 4 + 1], u[1], t);
-                        t = __builtin_fmaf(Cs[k * 4 + 2], u[2], t);
-                        t = __builtin_fmaf(Cs[k * 4 + 3], u[3], t);
-                        b[face_vertex(f, k)] -= t;
+                        for (int f = 0; f < 6; ++f) {
+                            if (!((inflight >> f) & 1)) continue;
+                            const int j = __popc(inflight & ((1 << f) - 1));
+                            const float *Cs = sC + (n * maxin + s0 + j) * 16;
+                            float uf[4];
+#pragma unroll
+                            for (int l = 0; l < 4; ++l) uf[l] = j == 0 ? u[0][l] : (j == 1 ? u[1][l] : u[2][l]);
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                float t = Cs[k * 4] * uf[0];
+                                t = __builtin_fmaf(Cs[k * 4 + 1], uf[1], t);
+                                t = __builtin_fmaf(Cs[k * 4 + 2], uf[2], t);
+                                t = __builtin_fmaf(Cs[k * 4 + 3], uf[3], t);
+                                b[face_vertex(f, k)] -= t;
+                            }
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int f = 0; f < 6; ++f) {
+                        if (!((mask >> f) & 1)) continue;
+                        const float *Cs = sC + (n * maxin + __popc(mask & ((1 << f) - 1))) * 16;
+                        float u[4];
+#pragma unroll
+                        for (int l = 0; l < 4; ++l) u[l] = nb[f] >= 0 ? L.up[f][l] : psib;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            float t = Cs[k * 4] * u[0];
+                            t = __builtin_fmaf(Cs[k * 4 + 1], u[1], t);
+                            t = __builtin_fmaf(Cs[k * 4 + 2], u[2], t);
+                            t = __builtin_fmaf(Cs[k * 4 + 3], u[3], t);
+                            b[face_vertex(f, k)] -= t;
+                        }
                     }
                 }
                 const float sig = L.sig;
@@ -441,9 +485,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 const int g = e >> 3, d = e & 7;
                 float s = sRs[e], c = sRc[e];
                 const int q0 = ONE ? g : base + ((g - base % G) % G + G) % G;   // first lane of group g
-                for (int q = q0; q < hi; q += G) {
+                const float *w = sWb + (q0 - base) * 8 + d;
+                int q = q0;
+                for (; q + 3 * G < hi; q += 4 * G, w += 32 * G) {   // four angles' reads in flight together
+                    const float w0 = w[0], w1 = w[8 * G], w2 = w[16 * G], w3 = w[24 * G];
                     float t, err;
-                    two_sum(s, sWb[(q - base) * 8 + d], t, err);
+                    two_sum(s, w0, t, err); s = t; c += err;
+                    two_sum(s, w1, t, err); s = t; c += err;
+                    two_sum(s, w2, t, err); s = t; c += err;
+                    two_sum(s, w3, t, err); s = t; c += err;
+                }
+                for (; q < hi; q += G, w += 8 * G) {
+                    float t, err;
+                    two_sum(s, w[0], t, err);
                     s = t;
                     c += err;
                 }
