@@ -124,6 +124,9 @@ def main():
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--threads", type=int, default=0, help="sweep workgroup size (0 = library default)")
     ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true", help="skip the schedule autotuner (library default schedule)")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2510_11513_amd", "tuning", "mi355x.jsonl"),
+                    help="autotuner cache (JSON lines); a hit reuses the recorded schedule without timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-groups", type=int, default=16)
     ap.add_argument("--cpu-sweeps", type=int, default=4)
@@ -155,8 +158,11 @@ def main():
     p.setup()
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
-    print(f"[bench] {args.workload}: setup {t_setup:.2f} s; warmup {args.warmup}, steps {args.steps}",
-          file=sys.stderr, flush=True)
+    tuned = None
+    if not (args.no_tune or args.threads or args.wg_per_cu):
+        tuned = p.tune(args.tune_cache)   # the library's autotuner (cache hit: the recorded schedule)
+    print(f"[bench] {args.workload}: setup {t_setup:.2f} s; schedule {tuned}; warmup {args.warmup}, "
+          f"steps {args.steps}", file=sys.stderr, flush=True)
 
     if args.calib_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
@@ -198,7 +204,8 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{args.workload}: {desc}", "cells": C, "angles": nang, "groups": G,
                       "solves_per_step": solves_per_step, "sweep_grid": stats["grid"],
-                      "sweep_threads": stats["threads"], "continued_tasks": stats["continued"],
+                      "sweep_threads": stats["threads"], "sweep_wg_per_cu_cap": tuned[1] if tuned else None,
+                      "continued_tasks": stats["continued"],
                       "setup_s": round(t_setup, 3)},
            "roofline": roofline}
     if args.learned > 0:

@@ -55,8 +55,10 @@ struct Sched {
     SweepCtl *d_ctl = nullptr;
     unsigned long long *d_queue = nullptr;   // [total] slots, queue q from host_ctl.qbase[q]
     int *d_seeds = nullptr, *d_seed_off = nullptr;
-    int *d_blk_base = nullptr;               // [nprob + 1] reduce blocks per problem
+    int *d_blk_base = nullptr;               // [nprob + 1] first 256-item block of each problem
     int nblk = 0;
+    int *d_rblk_base = nullptr;              // [nprob + 1] the same for the reduction's 256*kReduceItems blocks
+    int nrblk = 0;
     float **d_buf = nullptr;                 // [2][nprob] ping-pong flux buffers of the problems
     float **d_user = nullptr;                // [2][nprob] caller pointers of the current call
     IterCtl *d_ic = nullptr;                 // [nprob]
@@ -210,7 +212,7 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
 
     sc.hprobs.clear();
     std::vector<long long> base(n + 1, 0);
-    std::vector<int> blk(n + 1, 0), seed_off(8 * n + 1, 0), seeds;
+    std::vector<int> blk(n + 1, 0), rblk(n + 1, 0), seed_off(8 * n + 1, 0), seeds;
     sc.maxA = sc.maxG = sc.maxAG = 0;
     sc.maxin = 1;
     for (int i = 0; i < n; ++i) {
@@ -220,6 +222,7 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
         sc.hprobs.push_back(P);
         base[i + 1] = base[i] + 8LL * p->C;
         blk[i + 1] = blk[i] + (int)(((long long)p->C * p->G + 255) / 256);
+        rblk[i + 1] = rblk[i] + (int)(((long long)p->C * p->G + 256 * kReduceItems - 1) / (256 * kReduceItems));
         sc.maxA = std::max(sc.maxA, p->A);
         sc.maxG = std::max(sc.maxG, p->G);
         sc.maxAG = std::max(sc.maxAG, p->A * p->G);
@@ -232,6 +235,7 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
     seed_off[8 * n] = (int)seeds.size();
     sc.total = base[n];
     sc.nblk = blk[n];
+    sc.nrblk = rblk[n];
     sc.threads = pick_threads(threads, sc.maxG, sc.maxAG);
     sc.wg_per_cu = wg_per_cu;
     sc.chunk = chunk;
@@ -260,6 +264,7 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
     SALLOC(sc.d_seeds, sizeof(int) * std::max<size_t>(1, seeds.size()));
     SALLOC(sc.d_seed_off, sizeof(int) * (8 * n + 1));
     SALLOC(sc.d_blk_base, sizeof(int) * (n + 1));
+    SALLOC(sc.d_rblk_base, sizeof(int) * (n + 1));
     SALLOC(sc.d_buf, sizeof(float *) * 2 * n);
     SALLOC(sc.d_user, sizeof(float *) * 2 * n);
     SALLOC(sc.d_ic, sizeof(IterCtl) * n);
@@ -276,6 +281,7 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
         HIPCHK_E(sc.err, hipMemcpy(sc.d_seeds, seeds.data(), sizeof(int) * seeds.size(), hipMemcpyHostToDevice), "copy");
     HIPCHK_E(sc.err, hipMemcpy(sc.d_seed_off, seed_off.data(), sizeof(int) * (8 * n + 1), hipMemcpyHostToDevice), "copy");
     HIPCHK_E(sc.err, hipMemcpy(sc.d_blk_base, blk.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice), "copy");
+    HIPCHK_E(sc.err, hipMemcpy(sc.d_rblk_base, rblk.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice), "copy");
     HIPCHK_E(sc.err, hipMemcpy(sc.d_buf, bufs.data(), sizeof(float *) * 2 * n, hipMemcpyHostToDevice), "copy");
     HIPCHK_E(sc.err, hipMemset(sc.d_stop, 0, sizeof(int) * n), "memset");
     HIPCHK_E(sc.err, reset_schedule(sc, s), "reset");
@@ -319,7 +325,7 @@ snx_status sched_sweep(Sched &sc, const float *const *phi_in, float *const *phi_
     HIPCHK_E(sc.err, launch_source_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_user, nullptr, s), "source");
     st = enqueue_sweep(sc, nullptr, s);
     if (st) return st;
-    HIPCHK_E(sc.err, launch_reduce_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_user + n, nullptr, 0, nullptr,
+    HIPCHK_E(sc.err, launch_reduce_batch(sc.d_probs, n, sc.d_rblk_base, sc.nrblk, sc.d_user + n, nullptr, 0, nullptr,
                                          sc.d_stop, s), "reduce");
     return SNX_OK;
 }
@@ -334,7 +340,7 @@ snx_status build_graph(Sched &sc, int parity) {
         st = enqueue_sweep(sc, sc.d_stop, cs);
         if (!st) {
             const int cur = (parity + i) & 1;
-            hipError_t e = launch_reduce_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_buf + (cur ^ 1) * n,
+            hipError_t e = launch_reduce_batch(sc.d_probs, n, sc.d_rblk_base, sc.nrblk, sc.d_buf + (cur ^ 1) * n,
                                                sc.d_buf + cur * n, 1, sc.d_ic, sc.d_stop, cs);
             if (e != hipSuccess) st = hip_fail_msg(sc.err, e, "reduce launch");
         }

@@ -115,10 +115,13 @@ __device__ inline void residual_finish(double num, double den, IterCtl *ic, int 
     if (threadIdx.x == 0) {
         atomicMax(&ic->num_bits, dbits(s_num[0]));
         atomicMax(&ic->den_bits, dbits(s_den[0]));
-        __threadfence();
+        // Both maxima are performed at the device's coherence point once their
+        // returns arrive; waiting for them orders them before the count below
+        // without a device-wide fence (which would write back the whole L2).
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         const unsigned done = atomicAdd(&ic->blocks_done, 1u);
         if (done == nblocks - 1) {
-            __threadfence();
+            // every block's maxima precede its count; read them with atomics
             const double nm = __longlong_as_double((long long)atomicAdd(&ic->num_bits, 0ull));
             const double dn = __longlong_as_double((long long)atomicAdd(&ic->den_bits, 0ull));
             const double eps = dn > 0.0 ? nm / dn : (nm > 0.0 ? __builtin_inf() : 0.0);
@@ -164,10 +167,15 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const DevProblem *__restri
     const int p = block_problem(blk_base, nprob, blockIdx.x);
     if (stops[p]) return;
     const DevProblem &P = probs[p];
-    const long long t = (long long)(blockIdx.x - blk_base[p]) * blockDim.x + threadIdx.x;
+    // kReduceItems (cell, group) items per thread, each pass a contiguous run of
+    // blockDim items: fewer blocks, so fewer residual atomics per problem
+    const long long t0 = (long long)(blockIdx.x - blk_base[p]) * blockDim.x * kReduceItems + threadIdx.x;
     double num = 0.0, den = 0.0;
     const float *old = phi_old ? phi_old[p] : nullptr;
-    if (t < (long long)P.C * P.G) reduce_one(P, t, phi_out[p], old, update_source, num, den);
+    for (int k = 0; k < kReduceItems; ++k) {
+        const long long t = t0 + (long long)k * blockDim.x;
+        if (t < (long long)P.C * P.G) reduce_one(P, t, phi_out[p], old, update_source, num, den);
+    }
     if (!ic || !old) return;
     residual_finish(num, den, ic + p, stops + p, blk_base[p + 1] - blk_base[p]);
 }

@@ -16,7 +16,8 @@ constexpr int kMaxGroups = 256;
 constexpr float kInv4Pi = 0.0795774715459476679f;
 
 constexpr int kMaxQueues = 16;   // task queues of a sweep (one per XCD of the device)
-constexpr int kMaxXcc = 32;      // range of hardware XCC ids mapped to queues
+constexpr int kMaxXcc = 32;
+constexpr int kReduceItems = 4;      // (cell, group) items per thread of the batched reduction      // range of hardware XCC ids mapped to queues
 
 // One task queue: octants are assigned to queues (o mod nq), and each queue is
 // served by the workgroups of one XCD, so a sweep's hand-offs stay in that
