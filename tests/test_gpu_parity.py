@@ -97,7 +97,7 @@ def test_edge_shapes(n, G, npol, naz, kind):
     assert H.rel_err_per_group(got, ref).max() <= TOL
 
 
-@pytest.mark.parametrize("threads", [64, 128, 256, 512])
+@pytest.mark.parametrize("threads", [64, 128, 192, 256, 512])
 def test_schedule_does_not_change_bits(threads):
     prob = inputs.config_problem(2, n=5)
     phi32 = _phi_in(prob, 7)
@@ -206,3 +206,31 @@ def test_mesh_with_inverted_cell_is_rejected():
     with pytest.raises(snx.SnxError) as e:
         p.setup()
     assert e.value.code == -3
+
+
+def skewed_stack(G=3, npol=1, naz=2, seed=0):
+    """Two cells stacked in z with the convex cross-section (0,0), (1,0), (4,1), (0,1):
+    the +x face leans so far that, for octant 0, four faces are inflow (-x, +x, -y, -z);
+    in the upper cell the fourth inflow slot is the interior face to the lower cell."""
+    xy = [(0.0, 0.0), (1.0, 0.0), (0.0, 1.0), (4.0, 1.0)]
+    xyz = np.array([(x, y, 0.5 * k) for k in range(3) for (x, y) in xy])
+    cv = np.array([[4 * c + (j & 3) + 4 * (j >> 2) for j in range(8)] for c in range(2)], np.int32)
+    mesh = inputs.Mesh(n=1, xyz=xyz, cell_vert=cv, ijk=np.zeros((2, 3), np.int32),
+                       vert_ijk=np.zeros((12, 3), np.int32))
+    rng = np.random.default_rng(seed)
+    st = rng.uniform(0.5, 2.0, (2, G))
+    mat = inputs.Materials(st, st * rng.uniform(0.2, 0.8, (2, G)), rng.uniform(0.5, 1.5, (2, G)))
+    prob = inputs.Problem("skewed", mesh, mat, npol, naz, 1e-6, boundary_kind=1,
+                          psi_b=rng.uniform(0.1, 1.0, G))
+    return prob
+
+
+@pytest.mark.parametrize("threads,G", [(None, 3), (64, 24)])
+def test_cells_with_four_inflow_faces(threads, G):
+    prob = skewed_stack(G=G, npol=1, naz=2 if G == 3 else 4)
+    mask = oracle.Oracle.from_problem(prob).dag()["inflow"]          # [8][C] inflow-face bit masks
+    nin = np.vectorize(lambda m: bin(int(m)).count("1"))(mask)
+    assert nin.max() == 4                          # the case this test exists for
+    print(f"[case] skewed stack threads={threads} G={G} inflow faces={nin.tolist()}", flush=True)
+    got, ref, _, _ = _sweep_pair(prob, _phi_in(prob, 4), threads=threads)
+    assert H.rel_err_per_group(got, ref).max() <= TOL
