@@ -334,19 +334,36 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         if (tid == 0) { const unsigned long long t = clock64(); s_ph[1] += t - s_mark; s_mark = t; }
 
         // ------------------------------------- per-angle operators B_n, C_n,f
-        for (int e = tid; e < A * 64; e += NT) {
-            const int n = e >> 6, ij = e & 63;
-            sB[e] = sOm[4 * n] * sT[ij] + sOm[4 * n + 1] * sT[64 + ij] + sOm[4 * n + 2] * sT[128 + ij];
-        }
-        const float inv_nin = __builtin_amdgcn_rcpf((float)max(nin, 1));
-        for (int e = tid; e < A * nin * 16; e += NT) {
-            const int ns = e >> 4, kl = e & 15;
-            const int n = div_small(ns, inv_nin), s = ns - n * nin;
-            int m = mask;                                       // face of inflow slot s: s-th set bit of mask
-            for (int k = 0; k < s; ++k) m &= m - 1;
-            const float *Fs = sF + (__ffs(m) - 1) * 48;
-            sC[(n * maxin + s) * 16 + kl] =
-                sOm[4 * n] * Fs[kl] + sOm[4 * n + 1] * Fs[16 + kl] + sOm[4 * n + 2] * Fs[32 + kl];
+        {   // column by column: a thread owns one entry (i, j) of B or of an inflow C
+            // for a share of the angles, so the three operator values are read once
+            // and each angle costs one direction read, three FMAs and one write
+            const int ncol = 64 + 16 * nin;
+            const int nsplit = max(1, NT / ncol);
+            const float inv_ncol = __builtin_amdgcn_rcpf((float)ncol);
+            for (int w = tid; w < ncol * nsplit; w += NT) {
+                const int part = div_small(w, inv_ncol);
+                const int c = w - part * ncol;
+                float vx, vy, vz;
+                float *dst;
+                int stride;
+                if (c < 64) {
+                    vx = sT[c]; vy = sT[64 + c]; vz = sT[128 + c];
+                    dst = sB + c;
+                    stride = 64;
+                } else {
+                    const int s = (c - 64) >> 4, kl = (c - 64) & 15;
+                    int m = mask;                               // face of inflow slot s: s-th set bit of mask
+                    for (int k = 0; k < s; ++k) m &= m - 1;
+                    const float *Fs = sF + (__ffs(m) - 1) * 48;
+                    vx = Fs[kl]; vy = Fs[16 + kl]; vz = Fs[32 + kl];
+                    dst = sC + s * 16 + kl;
+                    stride = maxin * 16;
+                }
+                for (int n = part; n < A; n += nsplit) {
+                    const float4 om = reinterpret_cast<const float4 *>(sOm)[n];
+                    dst[n * stride] = om.x * vx + om.y * vy + om.z * vz;
+                }
+            }
         }
         __syncthreads();
         if (tid == 0) { const unsigned long long t = clock64(); s_ph[2] += t - s_mark; s_mark = t; }
