@@ -163,7 +163,8 @@ __device__ long long pop_task(SweepCtl *ctl, unsigned long long *queue, int &q, 
     for (int tried = 0; tried < nq; ++tried, q = q + 1 < nq ? q + 1 : 0) {
         QueueCtl *Q = &ctl->q[q];
         const long long qt = ctl->qtotal[q];
-        if ((long long)ld_agent_u32(&Q->done) >= qt) continue;
+        // take a slot at once (the finished-queue test below runs while waiting,
+        // so the common case costs one atomic and one load)
         const unsigned slot = atomicAdd(&Q->head, 1u);
         const GLOBAL unsigned long long *qs = gp(queue) + ctl->qbase[q];
         const unsigned long long t0 = wall_clock64();
@@ -205,6 +206,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
     __shared__ int s_nready;
     __shared__ int s_desc[13];            // neighbour ids [6], node permutations [6], inflow mask
     __shared__ long long s_ready[6];
+    __shared__ int s_npush, s_qpush;      // ready tasks s_ready[1..s_npush] still to be queued
     if (ctl->nactive == 0) return;
     const unsigned epoch = ctl->epoch;
     const int nq = ctl->nq;
@@ -228,7 +230,26 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
     if (tid == 0) {
         for (int i = 0; i < 4; ++i) s_stat[i] = 0;
         for (int i = 0; i < 5; ++i) s_ph[i] = 0;
+        s_npush = 0;
     }
+    // Queues the ready tasks the last task did not continue with: one atomic
+    // reserves their slots.  Thread 0 runs it while the next task's stage loads
+    // are in flight, so the round trip overlaps them.
+    auto push_ready = [&]() {
+        const int np = s_npush;
+        if (np <= 0) return;
+        const int qo = s_qpush;
+        const unsigned slot0 = atomicAdd(&ctl->q[qo].tail, (unsigned)np);
+        for (int i = 0; i < np; ++i) {
+            const unsigned long long v = ((unsigned long long)epoch << 32) | (unsigned long long)s_ready[1 + i];
+            if ((long long)(slot0 + i) < ctl->qtotal[qo])
+                __hip_atomic_store(gp(queue) + ctl->qbase[qo] + slot0 + i, v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            else   // more pushes than tasks: counters inconsistent with the DAG
+                __hip_atomic_store(&ctl->abort, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_npush = 0;
+    };
     long long cont = -1;
     for (;;) {
         long long task = cont;
@@ -301,6 +322,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 om4 = make_float4(gp(P.omega)[3 * n + 0], gp(P.omega)[3 * n + 1], gp(P.omega)[3 * n + 2], gp(P.w)[n]);
             }
             if (tid < AG) load_own(P, K, lg, L);
+            if (tid == 0) push_ready();                                // overlaps the loads above
             if (tid < kGeo) reinterpret_cast<float4 *>(sM)[tid] = st;   // M, T and F are contiguous in LDS
         } else {
             if (tid < A) {
@@ -308,6 +330,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 om4 = make_float4(gp(P.omega)[3 * n + 0], gp(P.omega)[3 * n + 1], gp(P.omega)[3 * n + 2], gp(P.w)[n]);
             }
             if (tid < AG) load_own(P, K, lg, L);
+            if (tid == 0) push_ready();
             for (int i = tid; i < kItems; i += NT) {
                 if (i < kGeo) reinterpret_cast<float4 *>(sM)[i] = stage_geo(i);
                 else stage_word(i - kGeo);
@@ -551,17 +574,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         if (tid == 0) {
             ++s_stat[3];
             ++s_stat[1];
-            // downwind cells are in the same octant, hence in this task's queue
-            const int qo = o % nq;
-            for (int i = 1; i < nr; ++i) {
-                const unsigned slot = atomicAdd(&ctl->q[qo].tail, 1u);
-                const unsigned long long v = ((unsigned long long)epoch << 32) | (unsigned long long)s_ready[i];
-                if ((long long)slot < ctl->qtotal[qo])
-                    __hip_atomic_store(gp(queue) + ctl->qbase[qo] + slot, v, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                else   // more pushes than tasks: counters inconsistent with the DAG
-                    __hip_atomic_store(&ctl->abort, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            // downwind cells are in the same octant, hence in this task's queue; the
+            // others are queued during the continuation's stage (nr > 1 implies one)
+            s_npush = nr - 1;
+            s_qpush = o % nq;
         }
     }
     if (tid == 0) {
