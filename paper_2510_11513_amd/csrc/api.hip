@@ -709,7 +709,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     DevProblem &hp = p->hp;
     double *d_xyz; int *d_cv, *d_nbr, *d_nbrf; unsigned *d_perm;
     float *dM, *dS, *dT, *dF, *dsigt, *dsigs, *dq, *dr, *dom, *dw, *dpsib = nullptr, *dpsi, *dslot, *dslotc;
-    unsigned char *dmask; int *dindeg, *dlevel, *dhist, *dnlev, *dseeds, *dnseed, *dscratch; unsigned *dcnt, *depoch;
+    unsigned char *dmask; int *dindeg, *dlevel, *dhist, *dnlev, *dseeds, *dnseed, *dscratch, *drec; unsigned *dcnt, *depoch;
 #define ALLOC(ptr, bytes) HIPCHK(p, m.alloc((void **)&(ptr), (bytes)), "device allocation")
     ALLOC(d_xyz, sizeof(double) * 3 * p->nvert);
     ALLOC(d_cv, sizeof(int) * 8 * C);
@@ -741,6 +741,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     ALLOC(dslot, sizeof(float) * 8 * C * G * 8);
     ALLOC(dslotc, sizeof(float) * 8 * C * G * 8);
     ALLOC(dcnt, sizeof(unsigned) * 8 * C);
+    ALLOC(drec, sizeof(int) * 8 * C * kRecWords);
     ALLOC(depoch, sizeof(unsigned));
     ALLOC(p->d_phi[0], sizeof(float) * C * G * 8);
     ALLOC(p->d_phi[1], sizeof(float) * C * G * 8);
@@ -792,6 +793,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     for (int o = 0; o < 8; ++o) p->maxin = std::max(p->maxin, nlev[8 + o]);
 
     HIPCHK(p, launch_octant_operators(p->C, dS, dF, dmask, dT, s), "octant operators");
+    HIPCHK(p, launch_task_records(p->C, d_nbr, d_perm, dmask, drec, s), "task records");
 
     // level-0 tasks of every octant are the seeds of a sweep
     std::vector<int> seeds_host(8 * C);
@@ -803,7 +805,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     hp.C = p->C; hp.G = p->G; hp.A = p->A; hp.nang = p->nang; hp.task_base = 0; hp.epoch = depoch;
     hp.M = dM; hp.S = dS; hp.T = dT; hp.F = dF; hp.nbr = d_nbr; hp.perm = d_perm; hp.inmask = dmask; hp.indeg = dindeg;
     hp.sigt = dsigt; hp.sigs = dsigs; hp.q = dq; hp.r = dr; hp.omega = dom; hp.w = dw; hp.psib = dpsib;
-    hp.psi = dpsi; hp.slot = dslot; hp.slotc = dslotc; hp.cnt = dcnt;
+    hp.psi = dpsi; hp.slot = dslot; hp.slotc = dslotc; hp.cnt = dcnt; hp.rec = drec;
     HIPCHK(p, launch_fill_f32(dr, C * G * 8, 0.f, s), "fill");
     HIPCHK(p, hipStreamSynchronize(s), "setup");
     snx_status st = build_sched(p->sched, {p}, p->threads, p->wg_per_cu, p->chunk, s);

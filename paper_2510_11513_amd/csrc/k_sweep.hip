@@ -146,6 +146,33 @@ __device__ __forceinline__ void load_up(int K, int mask, const int (&nb)[6], con
     }
 }
 
+// Issues the upwind-trace loads of lane p for up to three inflow faces: the
+// lowest set bits of `faces`.  Returns the faces taken; bit j of `bnd` marks a
+// boundary slot (its loads read dof 0 of cell K, any valid address, and its
+// value is replaced by psi_b where the traces are used).  desc holds the task's
+// neighbour ids [6] and node permutations [6].
+__device__ __forceinline__ int load_slots(int faces, int K, int p, int AG, const float *psi_o, const int *desc,
+                                          float (&u)[3][4], int &bnd) {
+    int m = faces, taken = 0;
+    bnd = 0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const bool live = m != 0;
+        const int f = live ? __builtin_ctz(m) : 0;
+        m &= m - 1;
+        const int Nf = live ? __builtin_amdgcn_readfirstlane(desc[f]) : -1;
+        taken |= live ? 1 << f : 0;
+        bnd |= Nf < 0 ? 1 << j : 0;
+        const unsigned perm = Nf >= 0 ? (unsigned)__builtin_amdgcn_readfirstlane(desc[6 + f]) : 0u;
+        const __amdgpu_buffer_rsrc_t rs = cell_block(psi_o, Nf >= 0 ? Nf : K, 8 * AG);
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+            u[j][l] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                rs, 4 * p, (int)((perm >> (8 * l)) & 0xff) * AG * 4, kCoherentAccess));
+    }
+    return taken;
+}
+
 // Hardware id of the XCD (accelerator complex die) this wave runs on.
 __device__ __forceinline__ int xcc_id() {
     return __builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & (kMaxXcc - 1);   // HW_REG_XCC_ID[3:0]
@@ -204,8 +231,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
     __shared__ long long s_task;
     __shared__ int s_q;
     __shared__ int s_nready;
-    __shared__ int s_desc[13];            // neighbour ids [6], node permutations [6], inflow mask
+    // Task records (own and downwind descriptors, see kRecWords), double-buffered:
+    // a continuation reads its descriptor from the last task's record while its
+    // own record is being loaded into the other buffer.
+    __shared__ __align__(16) int s_rec[2][kRecWords];
     __shared__ long long s_ready[6];
+    __shared__ int s_rface[6];            // face of this task across which s_ready[i] lies
     __shared__ int s_npush, s_qpush;      // ready tasks s_ready[1..s_npush] still to be queued
     if (ctl->nactive == 0) return;
     const unsigned epoch = ctl->epoch;
@@ -222,6 +253,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
     float *sW = sC + 16 * maxin * maxA;   // [2][NT][8]
     float *sRs = sW + (ONE ? 8 : 16) * NT; // [maxG][8]
     float *sRc = sRs + 8 * maxG;          // [maxG][8]
+    float *sUp = sRc + 8 * maxG;          // ONE: [3 slots][4 face nodes][NT] upwind traces
 
     // Workgroup statistics, kept in LDS and touched by thread 0 only: polls, tasks,
     // continued tasks, tasks not yet added to the queue's done count, and the
@@ -251,6 +283,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         s_npush = 0;
     };
     long long cont = -1;
+    int cur = 0;                          // record buffer of the current task
+    int cface = -1, cbuf = 0;             // continuation: its face in the last task's record, and that record's buffer
     for (;;) {
         long long task = cont;
         if (tid == 0) s_mark = clock64();
@@ -290,40 +324,65 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         const size_t cell_psi = (size_t)8 * A * G;          // floats per (octant, cell)
         const float *psi_o = P.psi + (size_t)o * C * cell_psi;
 
-        // ---------------------------------------------------------- stage
-        // One round trip brings the cell data (M, T^a of this octant, the six
-        // face matrices; 136 float4s), the neighbour ids, node permutations and
-        // inflow mask (13 words, to LDS), the directions, and each lane's own
-        // source dofs and sigma_t.  The upwind traces follow in a second round
-        // trip once the neighbour ids are in LDS, all faces at once.
-        constexpr int kGeo = 16 + 48 + 72, kItems = kGeo + 13;
-        auto stage_word = [&](int i) {
-            if (i < 12) {
-                const int f = i % 6;
-                if (i < 6) s_desc[i] = gp(P.nbr)[(size_t)K * 6 + f];
-                else s_desc[i] = (int)gp(P.perm)[(size_t)K * 6 + f];
-            } else {
-                s_desc[12] = gp(P.inmask)[(size_t)o * C + K];
+        // --------------------------------------------- early upwind loads
+        // A continuation already holds its descriptor (the last task's record), so
+        // its first three inflow faces' traces are requested now, straight into
+        // LDS (buffer loads with an LDS destination, one 64-lane run per wave),
+        // together with the stage loads below; other tasks request them as soon
+        // as their record is in LDS.
+        int taken0 = 0, bnd0 = 0;
+        auto early_up = [&](const int *d) {
+            int m = uni(d[12]);
+            const int wbase = uni(tid & ~63);
+#pragma unroll 1
+            for (int j = 0; j < 3 && m; ++j) {
+                const int f = __builtin_ctz(m);
+                m &= m - 1;
+                taken0 |= 1 << f;
+                const int Nf = uni(d[f]);
+                bnd0 |= Nf < 0 ? 1 << j : 0;
+                const unsigned perm = Nf >= 0 ? (unsigned)uni(d[6 + f]) : 0u;
+                const __amdgpu_buffer_rsrc_t rs = cell_block(psi_o, Nf >= 0 ? Nf : K, 8 * AG);
+                if (wbase < AG) {
+#pragma unroll
+                    for (int l = 0; l < 4; ++l)
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                            rs, (__attribute__((address_space(3))) void *)(sUp + (j * 4 + l) * NT + wbase), 4,
+                            4 * tid, (int)((perm >> (8 * l)) & 0xff) * AG * 4, 0, kCoherentAccess);
+                }
             }
         };
-        auto stage_geo = [&](int i) -> float4 {
+        if constexpr (ONE)
+            if (cface >= 0) early_up(&s_rec[cbuf][16 + 13 * cface]);
+
+        // ---------------------------------------------------------- stage
+        // One round trip brings the cell data (M, T^a of this octant, the six
+        // face matrices; 136 float4s) and the task record (24 int4s) to LDS, the
+        // directions, and each lane's own source dofs and sigma_t.
+        constexpr int kGeo = 16 + 48 + 72, kItems = kGeo + kRecWords / 4;
+        int *s_desc = s_rec[cur];             // words 0..12: this task's descriptor
+        auto stage_item = [&](int i) -> float4 {
             if (i < 16) return reinterpret_cast<const GLOBAL float4 *>(gp(P.M) + (size_t)K * 64)[i];
             if (i < 64) return reinterpret_cast<const GLOBAL float4 *>(gp(P.T) + ((size_t)o * C + K) * 192)[i - 16];
-            return reinterpret_cast<const GLOBAL float4 *>(gp(P.F) + (size_t)K * 288)[i - 64];
+            if (i < kGeo) return reinterpret_cast<const GLOBAL float4 *>(gp(P.F) + (size_t)K * 288)[i - 64];
+            return reinterpret_cast<const GLOBAL float4 *>(gp(P.rec) + ((size_t)o * C + K) * kRecWords)[i - kGeo];
+        };
+        auto stage_store = [&](int i, float4 v) {
+            if (i < kGeo) reinterpret_cast<float4 *>(sM)[i] = v;          // M, T and F are contiguous in LDS
+            else reinterpret_cast<float4 *>(s_desc)[i - kGeo] = v;
         };
         float4 om4 = make_float4(0.f, 0.f, 0.f, 0.f);          // direction and weight of angle tid (A <= 64 <= NT)
         LaneIn L;
         if constexpr (NT >= kItems) {
             // at most one item per thread: all loads in flight together
-            const float4 st = tid < kGeo ? stage_geo(tid) : make_float4(0.f, 0.f, 0.f, 0.f);
-            if (tid >= kGeo && tid < kItems) stage_word(tid - kGeo);
+            const float4 st = tid < kItems ? stage_item(tid) : make_float4(0.f, 0.f, 0.f, 0.f);
             if (tid < A) {
                 const int n = o * A + tid;
                 om4 = make_float4(gp(P.omega)[3 * n + 0], gp(P.omega)[3 * n + 1], gp(P.omega)[3 * n + 2], gp(P.w)[n]);
             }
             if (tid < AG) load_own(P, K, lg, L);
             if (tid == 0) push_ready();                                // overlaps the loads above
-            if (tid < kGeo) reinterpret_cast<float4 *>(sM)[tid] = st;   // M, T and F are contiguous in LDS
+            if (tid < kItems) stage_store(tid, st);
         } else {
             if (tid < A) {
                 const int n = o * A + tid;
@@ -331,15 +390,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             }
             if (tid < AG) load_own(P, K, lg, L);
             if (tid == 0) push_ready();
-            for (int i = tid; i < kItems; i += NT) {
-                if (i < kGeo) reinterpret_cast<float4 *>(sM)[i] = stage_geo(i);
-                else stage_word(i - kGeo);
-            }
+            for (int i = tid; i < kItems; i += NT) stage_store(i, stage_item(i));
         }
         if (tid < A) reinterpret_cast<float4 *>(sOm)[tid] = om4;
         for (int i = tid; i < G * 8; i += NT) { sRs[i] = 0.f; sRc[i] = 0.f; }
         __syncthreads();
         if (tid == 0) s_nready = 0;   // after the barrier: every thread has read the last task's count
+        if constexpr (ONE)
+            if (cface < 0) early_up(s_desc);
         const int mask = uni(s_desc[12]);
         const int nin = __popc(mask);
         int nb[6];
@@ -403,39 +461,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 for (int d = 0; d < 8; ++d) b[d] = L.r[d];
                 const float psib = P.psib ? gp(P.psib)[g] : 0.f;
                 if constexpr (ONE) {
-                    // Inflow faces in slot order, up to three at a time: the upwind
-                    // traces of a group are loaded together into three slots (all in
-                    // flight at once), then each face takes its slot by a select, so
-                    // the node map of every face stays static.  Hexahedra of the
-                    // meshes here have three inflow faces per octant: one group.
-                    int m = mask;
-                    for (int s0 = 0; s0 < nin; s0 += 3) {
-                        float u[3][4];
-                        const int gmask = m;            // faces of this group: the next three set bits
-#pragma unroll
-                        for (int j = 0; j < 3; ++j) {
-                            const int f = m ? __builtin_ctz(m) : 0;
-                            m &= m - 1;
-                            const bool live = s0 + j < nin;
-                            const int Nf = live ? uni(s_desc[f]) : -1;
-                            const unsigned perm = Nf >= 0 ? (unsigned)uni(s_desc[6 + f]) : 0u;
-                            const __amdgpu_buffer_rsrc_t rs = cell_block(psi_o, Nf >= 0 ? Nf : K, 8 * AG);
-#pragma unroll
-                            for (int l = 0; l < 4; ++l) {
-                                const float v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                    rs, 4 * pi, (int)((perm >> (8 * l)) & 0xff) * AG * 4, kCoherentAccess));
-                                u[j][l] = Nf >= 0 ? v : psib;
-                            }
-                        }
-                        const int inflight = gmask & ~m;  // the (up to) three faces just loaded
+                    // Inflow faces in slot order, three at a time; each face takes its
+                    // slot by a select, so the node map of every face stays static.
+                    // The first three arrived in LDS (requested early); hexahedra of
+                    // the meshes here have three inflow faces per octant, so later
+                    // groups (loaded into registers here) are rare.
+                    auto apply = [&](int taken, int s0, const float (&u)[3][4], int bnd) {
 #pragma unroll
                         for (int f = 0; f < 6; ++f) {
-                            if (!((inflight >> f) & 1)) continue;
-                            const int j = __popc(inflight & ((1 << f) - 1));
+                            if (!((taken >> f) & 1)) continue;
+                            const int j = __popc(taken & ((1 << f) - 1));
                             const float *Cs = sC + (n * maxin + s0 + j) * 16;
+                            const bool boundary = (bnd >> j) & 1;
                             float uf[4];
 #pragma unroll
-                            for (int l = 0; l < 4; ++l) uf[l] = j == 0 ? u[0][l] : (j == 1 ? u[1][l] : u[2][l]);
+                            for (int l = 0; l < 4; ++l)
+                                uf[l] = boundary ? psib : (j == 0 ? u[0][l] : (j == 1 ? u[1][l] : u[2][l]));
 #pragma unroll
                             for (int k = 0; k < 4; ++k) {
                                 float t = Cs[k * 4] * uf[0];
@@ -445,6 +486,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                                 b[face_vertex(f, k)] -= t;
                             }
                         }
+                    };
+                    {
+                        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the LDS-destined loads have landed
+                        float u0[3][4];
+#pragma unroll
+                        for (int j = 0; j < 3; ++j)
+#pragma unroll
+                            for (int l = 0; l < 4; ++l) u0[j][l] = sUp[(j * 4 + l) * NT + tid];
+                        apply(taken0, 0, u0, bnd0);
+                    }
+                    int rest = mask & ~taken0;
+                    for (int s0 = 3; rest; s0 += 3) {
+                        float u[3][4];
+                        int bnd = 0;
+                        const int taken = load_slots(rest, K, pi, AG, psi_o, s_desc, u, bnd);
+                        rest &= ~taken;
+                        apply(taken, s0, u, bnd);
                     }
                 } else {
 #pragma unroll
@@ -564,12 +622,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 const unsigned old = __hip_atomic_fetch_add(gp(P.cnt) + (size_t)o * C + N, 1u, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT);
                 const unsigned target = (unsigned)gp(P.indeg)[(size_t)o * C + N] * *P.epoch;
-                if (old + 1u == target) s_ready[atomicAdd(&s_nready, 1)] = P.task_base + 8LL * N + o;
+                if (old + 1u == target) {
+                    const int i = atomicAdd(&s_nready, 1);
+                    s_ready[i] = P.task_base + 8LL * N + o;
+                    s_rface[i] = f;
+                }
             }
         }
         __syncthreads();
         const int nr = s_nready;
         cont = nr > 0 ? s_ready[0] : -1;
+        cface = nr > 0 ? s_rface[0] : -1;            // the continuation's descriptor is in this record
+        cbuf = cur;
+        cur ^= 1;
         if (tid == 0) s_ph[4] += clock64() - s_mark;
         if (tid == 0) {
             ++s_stat[3];
@@ -578,6 +643,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             // others are queued during the continuation's stage (nr > 1 implies one)
             s_npush = nr - 1;
             s_qpush = o % nq;
+
         }
     }
     if (tid == 0) {
@@ -660,7 +726,7 @@ bool sweep_threads_valid(int threads) {
 
 size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin, bool one) {
     size_t floats = 64 + 192 + 6 * 48 + 4 * (size_t)maxA + 64 * (size_t)maxA + 16 * (size_t)maxin * maxA +
-                    (one ? 8 : 16) * (size_t)threads + 16 * (size_t)maxG;
+                    (one ? 8 + 12 : 16) * (size_t)threads + 16 * (size_t)maxG;
     return floats * sizeof(float);
 }
 

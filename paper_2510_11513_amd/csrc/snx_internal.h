@@ -17,7 +17,12 @@ constexpr float kInv4Pi = 0.0795774715459476679f;
 
 constexpr int kMaxQueues = 16;   // task queues of a sweep (one per XCD of the device)
 constexpr int kMaxXcc = 32;
-constexpr int kReduceItems = 4;      // (cell, group) items per thread of the batched reduction      // range of hardware XCC ids mapped to queues
+constexpr int kReduceItems = 4;
+// Task record of one (octant, cell), 96 ints (24 int4): words 0..12 the cell's
+// descriptor (neighbour ids [6], node permutations [6], inflow mask of the
+// octant), 13..15 zero, then for each face f at 16 + 13 f the descriptor of the
+// neighbour across f when f is a downwind face (zero otherwise), 94..95 zero.
+constexpr int kRecWords = 96;      // (cell, group) items per thread of the batched reduction      // range of hardware XCC ids mapped to queues
 
 // One task queue: octants are assigned to queues (o mod nq), and each queue is
 // served by the workgroups of one XCD, so a sweep's hand-offs stay in that
@@ -50,7 +55,7 @@ struct SweepCtl {
 struct DevProblem {
     int C, G, A;                 // cells, groups, angles per octant
     int nang;
-    long long task_base;         // first global task id of this problem (task = base + o*C + K)
+    long long task_base;         // first global task id of this problem (task = base + 8*K + o)
     unsigned *epoch;             // sweeps of this problem so far; its counters count to indeg * epoch
     const float *M;              // [C][64]       mass M_ij = int f_i f_j
     const float *S;              // [C][3][64]    stiffness S^a_ij = int f_i df_j/dx_a
@@ -71,6 +76,7 @@ struct DevProblem {
     float *slot;                 // [8][C][G][8]  per-octant compensated partial sums
     float *slotc;                // [8][C][G][8]  their compensation terms
     unsigned *cnt;               // [8][C]        dependency counters (count up across sweeps)
+    const int *rec;              // [8][C][kRecWords] task records (see kRecWords)
 };
 
 // Iteration record of snx_solve's device-side control.
@@ -97,6 +103,8 @@ hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long lo
                                unsigned long long *queue, int threads, bool one, int grid, int maxA, int maxG, int maxin,
                                unsigned long long watchdog, hipStream_t s);
 hipError_t launch_xcc_probe(int *out, int nblocks, hipStream_t s);
+hipError_t launch_task_records(int C, const int *nbr, const unsigned *perm, const unsigned char *inmask, int *rec,
+                               hipStream_t s);
 hipError_t launch_octant_operators(int C, const float *S, const float *F, const unsigned char *inmask, float *T,
                                    hipStream_t s);
 // Workgroup widths of the sweep kernel: 64, 128, 192, 256 or 512.
