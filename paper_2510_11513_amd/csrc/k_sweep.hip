@@ -381,7 +381,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 om4 = make_float4(gp(P.omega)[3 * n + 0], gp(P.omega)[3 * n + 1], gp(P.omega)[3 * n + 2], gp(P.w)[n]);
             }
             if (tid < AG) load_own(P, K, lg, L);
-            if (tid == 0) push_ready();                                // overlaps the loads above
+            if (!ONE && tid == 0) push_ready();                        // overlaps the loads above
             if (tid < kItems) stage_store(tid, st);
         } else {
             if (tid < A) {
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 om4 = make_float4(gp(P.omega)[3 * n + 0], gp(P.omega)[3 * n + 1], gp(P.omega)[3 * n + 2], gp(P.w)[n]);
             }
             if (tid < AG) load_own(P, K, lg, L);
-            if (tid == 0) push_ready();
+            if (!ONE && tid == 0) push_ready();
             for (int i = tid; i < kItems; i += NT) stage_store(i, stage_item(i));
         }
         if (tid < A) reinterpret_cast<float4 *>(sOm)[tid] = om4;
@@ -447,6 +447,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             }
         }
         __syncthreads();
+        // one-round tasks: the last wave queues the last task's other ready tasks
+        // while the lanes solve (it is idle there when A*G <= NT - 64)
+        if constexpr (ONE)
+            if (tid == NT - 64) push_ready();
         if (tid == 0) { const unsigned long long t = clock64(); s_ph[2] += t - s_mark; s_mark = t; }
 
         // ------------------------------------------------ rounds of lanes
