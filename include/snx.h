@@ -147,6 +147,17 @@ snx_status snx_get_levels(snx_problem *p, int32_t *level, int32_t *nlevels);
  * that holds a whole task in one round (at most 256, at least G) is used. */
 snx_status snx_set_schedule(snx_problem *p, int32_t threads, int32_t wg_per_cu, int32_t chunk);
 
+/* Sweep scheme.  SNX_SWEEP_AMT (default): the persistent dependency-driven
+ * sweep (one launch, tasks generated by atomic counters, paper §3).
+ * SNX_SWEEP_BSP: the bulk-synchronous comparator of the paper (§2.1): one
+ * launch per level of the per-octant DAGs (all octants and problems of the
+ * schedule together), the launch boundary acting as the barrier.  Both run the
+ * same task code, so they give the same bits; the mode applies to snx_sweep,
+ * snx_solve and snx_profile_sweep.  snx_sweep_stats reports the last AMT sweep. */
+#define SNX_SWEEP_AMT 0
+#define SNX_SWEEP_BSP 1
+snx_status snx_set_sweep_mode(snx_problem *p, int32_t mode);
+
 /* Schedule autotuner: times a few sweeps of every (threads, workgroups per
  * CU) candidate on this problem and keeps the fastest.  cache_path (nullable)
  * is a text file of JSON lines keyed by device and problem shape: a hit skips
@@ -183,6 +194,8 @@ snx_status snx_sweep_stats(snx_problem *p, int64_t *out);
 snx_status snx_batch_create(snx_batch **out, int32_t n, snx_problem *const *probs);
 void snx_batch_destroy(snx_batch *b);
 const char *snx_batch_last_error(const snx_batch *b);
+/* As snx_set_sweep_mode, for every problem of the batch. */
+snx_status snx_batch_set_sweep_mode(snx_batch *b, int32_t mode);
 /* As snx_set_schedule, with threads at least the largest G of the batch. */
 snx_status snx_batch_set_schedule(snx_batch *b, int32_t threads, int32_t wg_per_cu, int32_t chunk);
 /* As snx_tune, over the whole batch. */

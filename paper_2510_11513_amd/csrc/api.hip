@@ -71,6 +71,9 @@ struct Sched {
     int maxAG = 0;                           // largest (angles per octant) * G of the problems
     bool one = false;                        // every task is one round of lanes (maxAG <= threads)
     int threads = 256, wg_per_cu = 0, grid = 0, chunk = 8;
+    int mode = SNX_SWEEP_AMT;                // SNX_SWEEP_AMT or SNX_SWEEP_BSP
+    long long *d_bsp_tasks = nullptr;        // tasks of every problem ordered by level (BSP comparator)
+    std::vector<long long> bsp_off;          // [levels + 1] offsets into d_bsp_tasks
     unsigned long long watchdog = 0;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};   // chunk starting from ping-pong buffer 0 / 1
@@ -117,6 +120,7 @@ struct snx_problem {
     double *d_area = nullptr;
     unsigned long long watchdog_ticks = 0;
     int threads = 0, wg_per_cu = 0, chunk = 8;     // requested sweep schedule (threads 0: automatic)
+    int mode = SNX_SWEEP_AMT;
     int nq = 1;                         // task queues = XCDs seen on the device
     int xcc_queue[kMaxXcc] = {0};       // home queue of each hardware XCC id
     Sched sched;                        // the problem's own schedule of one
@@ -126,6 +130,7 @@ struct snx_batch {
     int device = 0;
     Sched sched;
     int threads = 0, wg_per_cu = 0, chunk = 8;
+    int mode = SNX_SWEEP_AMT;
 };
 
 namespace {
@@ -234,6 +239,21 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
     }
     seed_off[8 * n] = (int)seeds.size();
     sc.total = base[n];
+    // level lists of the bulk-synchronous comparator: task ids bucketed by level
+    int maxlev = 0;
+    for (snx_problem *p : probs)
+        for (int l : p->level) maxlev = std::max(maxlev, l);
+    sc.bsp_off.assign(maxlev + 2, 0);
+    for (snx_problem *p : probs)
+        for (int l : p->level) ++sc.bsp_off[l + 1];
+    for (int l = 0; l <= maxlev; ++l) sc.bsp_off[l + 1] += sc.bsp_off[l];
+    std::vector<long long> bsp(sc.total), fill(sc.bsp_off.begin(), sc.bsp_off.end() - 1);
+    for (int i = 0; i < n; ++i) {
+        const snx_problem *p = probs[i];
+        for (int o = 0; o < 8; ++o)
+            for (int K = 0; K < p->C; ++K)
+                bsp[fill[p->level[(size_t)o * p->C + K]]++] = base[i] + 8LL * K + o;
+    }
     sc.nblk = blk[n];
     sc.nrblk = rblk[n];
     sc.threads = pick_threads(threads, sc.maxG, sc.maxAG);
@@ -261,6 +281,7 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
     SALLOC(sc.d_base, sizeof(long long) * (n + 1));
     SALLOC(sc.d_ctl, sizeof(SweepCtl));
     SALLOC(sc.d_queue, sizeof(unsigned long long) * sc.total);
+    SALLOC(sc.d_bsp_tasks, sizeof(long long) * sc.total);
     SALLOC(sc.d_seeds, sizeof(int) * std::max<size_t>(1, seeds.size()));
     SALLOC(sc.d_seed_off, sizeof(int) * (8 * n + 1));
     SALLOC(sc.d_blk_base, sizeof(int) * (n + 1));
@@ -277,6 +298,8 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
     }
     HIPCHK_E(sc.err, hipMemcpy(sc.d_probs, sc.hprobs.data(), sizeof(DevProblem) * n, hipMemcpyHostToDevice), "copy");
     HIPCHK_E(sc.err, hipMemcpy(sc.d_base, base.data(), sizeof(long long) * (n + 1), hipMemcpyHostToDevice), "copy");
+    HIPCHK_E(sc.err, hipMemcpy(sc.d_bsp_tasks, bsp.data(), sizeof(long long) * sc.total, hipMemcpyHostToDevice),
+             "copy");
     if (!seeds.empty())
         HIPCHK_E(sc.err, hipMemcpy(sc.d_seeds, seeds.data(), sizeof(int) * seeds.size(), hipMemcpyHostToDevice), "copy");
     HIPCHK_E(sc.err, hipMemcpy(sc.d_seed_off, seed_off.data(), sizeof(int) * (8 * n + 1), hipMemcpyHostToDevice), "copy");
@@ -292,6 +315,15 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
 // sweep kernel alone.
 snx_status enqueue_sweep(Sched &sc, const int *stops, hipStream_t s, hipEvent_t ev0 = nullptr,
                          hipEvent_t ev1 = nullptr) {
+    if (sc.mode == SNX_SWEEP_BSP) {   // one launch per level; the kernel boundary is the barrier
+        if (ev0) HIPCHK_E(sc.err, hipEventRecord(ev0, s), "event");
+        for (size_t l = 0; l + 1 < sc.bsp_off.size(); ++l)
+            HIPCHK_E(sc.err, launch_sweep_level(sc.d_probs, sc.nprob(), sc.d_base, sc.d_ctl, sc.threads, sc.one,
+                                                sc.grid, sc.maxA, sc.maxG, sc.maxin, sc.d_bsp_tasks, sc.bsp_off[l],
+                                                sc.bsp_off[l + 1], stops, s), "level launch");
+        if (ev1) HIPCHK_E(sc.err, hipEventRecord(ev1, s), "event");
+        return SNX_OK;
+    }
     HIPCHK_E(sc.err, launch_sweep_prologue(sc.d_ctl, sc.d_queue, sc.d_probs, sc.nprob(), sc.d_seeds, sc.d_seed_off,
                                            stops, s), "sweep prologue");
     if (ev0) HIPCHK_E(sc.err, hipEventRecord(ev0, s), "event");
@@ -809,6 +841,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     HIPCHK(p, launch_fill_f32(dr, C * G * 8, 0.f, s), "fill");
     HIPCHK(p, hipStreamSynchronize(s), "setup");
     snx_status st = build_sched(p->sched, {p}, p->threads, p->wg_per_cu, p->chunk, s);
+    p->sched.mode = p->mode;
     if (st) {
         std::string msg = p->sched.err;
         drop_device(p);
@@ -880,6 +913,17 @@ snx_status snx_get_levels(snx_problem *p, int32_t *level, int32_t *nlevels) {
     if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
     if (level) std::memcpy(level, p->level.data(), sizeof(int) * p->level.size());
     if (nlevels) std::memcpy(nlevels, p->nlev.data(), sizeof(int) * 8);
+    return SNX_OK;
+}
+
+snx_status snx_set_sweep_mode(snx_problem *p, int32_t mode) {
+    if (!p) return SNX_E_ARG;
+    if (mode != SNX_SWEEP_AMT && mode != SNX_SWEEP_BSP) return fail(p, SNX_E_ARG, "unknown sweep mode");
+    p->mode = mode;
+    if (p->ready) {
+        p->sched.mode = mode;
+        p->sched.drop_graphs();
+    }
     return SNX_OK;
 }
 
@@ -999,6 +1043,15 @@ void snx_batch_destroy(snx_batch *b) {
 }
 
 const char *snx_batch_last_error(const snx_batch *b) { return b ? b->sched.err.c_str() : g_create_error.c_str(); }
+
+snx_status snx_batch_set_sweep_mode(snx_batch *b, int32_t mode) {
+    if (!b) return SNX_E_ARG;
+    if (mode != SNX_SWEEP_AMT && mode != SNX_SWEEP_BSP) return fail_msg(b->sched.err, SNX_E_ARG, "unknown sweep mode");
+    b->mode = mode;
+    b->sched.mode = mode;
+    b->sched.drop_graphs();
+    return SNX_OK;
+}
 
 snx_status snx_batch_set_schedule(snx_batch *b, int32_t threads, int32_t wg_per_cu, int32_t chunk) {
     if (!b) return SNX_E_ARG;

@@ -222,11 +222,18 @@ __device__ long long pop_task(SweepCtl *ctl, unsigned long long *queue, int &q, 
 // ONE: every problem of the launch has A*G <= NT, so a task is one round of
 // lanes; nothing is prefetched for a next round and wpsi has one buffer, which
 // lowers the register and LDS footprint and lets more workgroups be resident.
-template <int NT, bool ONE>
+//
+// BSP: the bulk-synchronous comparator of the paper (§2.1): the launch runs the
+// tasks bsp_tasks[bsp_begin, bsp_end) of one level (of every octant and problem)
+// with a grid-stride loop, and the next level is the next launch; no counters,
+// queues or continuation.  Task bodies are the same code, so results are the
+// same bits.  stops (nullable) marks converged problems of a batch.
+template <int NT, bool ONE, bool BSP>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_ONE : 4))) void k_sweep(
     const DevProblem *__restrict__ probs, int nprob, const long long *__restrict__ task_base,
     SweepCtl *__restrict__ ctl, unsigned long long *__restrict__ queue, int maxA, int maxG, int maxin,
-    unsigned long long watchdog) {
+    unsigned long long watchdog, const long long *__restrict__ bsp_tasks, long long bsp_begin, long long bsp_end,
+    const int *__restrict__ stops) {
     extern __shared__ __align__(16) float lds[];
     __shared__ long long s_task;
     __shared__ int s_q;
@@ -238,7 +245,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
     __shared__ long long s_ready[6];
     __shared__ int s_rface[6];            // face of this task across which s_ready[i] lies
     __shared__ int s_npush, s_qpush;      // ready tasks s_ready[1..s_npush] still to be queued
-    if (ctl->nactive == 0) return;
+    if (!BSP && ctl->nactive == 0) return;
     const unsigned epoch = ctl->epoch;
     const int nq = ctl->nq;
     const int tid = threadIdx.x;
@@ -283,12 +290,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         s_npush = 0;
     };
     long long cont = -1;
+    long long bsp_i = bsp_begin + blockIdx.x;
     int cur = 0;                          // record buffer of the current task
     int cface = -1, cbuf = 0;             // continuation: its face in the last task's record, and that record's buffer
     for (;;) {
         long long task = cont;
         if (tid == 0) s_mark = clock64();
-        if (task < 0) {
+        if constexpr (BSP) {
+            if (bsp_i >= bsp_end) break;
+            task = bsp_tasks[bsp_i];
+            bsp_i += gridDim.x;
+            if (stops && stops[uni(find_problem(task_base, nprob, task))]) continue;
+        } else if (task < 0) {
             if (tid == 0) {
                 if (s_stat[3]) {
                     __hip_atomic_fetch_add(&ctl->q[q].done, (unsigned)s_stat[3], __ATOMIC_RELAXED,
@@ -617,6 +630,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         }
 
         // --------------------------------------------- publish to downwind
+        if constexpr (BSP) {               // the next level is the next launch
+            __syncthreads();
+            continue;
+        }
         wait_stores();
         __syncthreads();
         if (tid < 6) {
@@ -650,7 +667,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
 
         }
     }
-    if (tid == 0) {
+    if (!BSP && tid == 0) {
         QueueCtl *Q = &ctl->q[ctl->xcc_queue[xcc_id()]];
         atomicAdd(&Q->polls_empty, s_stat[0]);
         atomicAdd(&Q->tasks_done, s_stat[1]);
@@ -710,17 +727,18 @@ __global__ void k_xcc_probe(int *out) {
     if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
 }
 
-template <int NT, bool ONE>
+template <int NT, bool ONE, bool BSP>
 hipError_t launch_nt(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                      unsigned long long *queue, int maxA, int maxG, int maxin, int grid, size_t lds,
-                     unsigned long long watchdog, hipStream_t s) {
-    hipLaunchKernelGGL((k_sweep<NT, ONE>), dim3(grid), dim3(NT), lds, s, probs, nprob, task_base, ctl, queue, maxA,
-                       maxG, maxin, watchdog);
+                     unsigned long long watchdog, const long long *bsp_tasks, long long b0, long long b1,
+                     const int *stops, hipStream_t s) {
+    hipLaunchKernelGGL((k_sweep<NT, ONE, BSP>), dim3(grid), dim3(NT), lds, s, probs, nprob, task_base, ctl, queue,
+                       maxA, maxG, maxin, watchdog, bsp_tasks, b0, b1, stops);
     return hipGetLastError();
 }
 
 template <int NT, bool ONE>
-const void *kernel_ptr() { return reinterpret_cast<const void *>(&k_sweep<NT, ONE>); }
+const void *kernel_ptr() { return reinterpret_cast<const void *>(&k_sweep<NT, ONE, false>); }
 
 }  // namespace
 
@@ -764,9 +782,35 @@ hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long lo
                                unsigned long long *queue, int threads, bool one, int grid, int maxA, int maxG,
                                int maxin, unsigned long long watchdog, hipStream_t s) {
     const size_t lds = sweep_lds_bytes(threads, maxA, maxG, maxin, one);
-#define SNX_LAUNCH(NT)                                                                                            \
-    return one ? launch_nt<NT, true>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds, watchdog, s) \
-               : launch_nt<NT, false>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds, watchdog, s)
+#define SNX_LAUNCH(NT)                                                                                             \
+    return one ? launch_nt<NT, true, false>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds,      \
+                                            watchdog, nullptr, 0, 0, nullptr, s)                                   \
+               : launch_nt<NT, false, false>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds,     \
+                                             watchdog, nullptr, 0, 0, nullptr, s)
+    switch (threads) {
+        case 64: SNX_LAUNCH(64);
+        case 128: SNX_LAUNCH(128);
+        case 192: SNX_LAUNCH(192);
+        case 256: SNX_LAUNCH(256);
+        case 512: SNX_LAUNCH(512);
+        default: return hipErrorInvalidValue;
+    }
+#undef SNX_LAUNCH
+}
+
+hipError_t launch_sweep_level(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
+                              int threads, bool one, int grid, int maxA, int maxG, int maxin,
+                              const long long *bsp_tasks, long long begin, long long end, const int *stops,
+                              hipStream_t s) {
+    const size_t lds = sweep_lds_bytes(threads, maxA, maxG, maxin, one);
+    const long long n = end - begin;
+    if (n <= 0) return hipSuccess;
+    const int g = (int)std::min<long long>(grid, n);
+#define SNX_LAUNCH(NT)                                                                                             \
+    return one ? launch_nt<NT, true, true>(probs, nprob, task_base, ctl, nullptr, maxA, maxG, maxin, g, lds, 0,     \
+                                           bsp_tasks, begin, end, stops, s)                                        \
+               : launch_nt<NT, false, true>(probs, nprob, task_base, ctl, nullptr, maxA, maxG, maxin, g, lds, 0,    \
+                                            bsp_tasks, begin, end, stops, s)
     switch (threads) {
         case 64: SNX_LAUNCH(64);
         case 128: SNX_LAUNCH(128);

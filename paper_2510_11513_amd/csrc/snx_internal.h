@@ -102,6 +102,11 @@ hipError_t launch_sweep_prologue(SweepCtl *ctl, unsigned long long *queue, const
 hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                                unsigned long long *queue, int threads, bool one, int grid, int maxA, int maxG, int maxin,
                                unsigned long long watchdog, hipStream_t s);
+// One level of the bulk-synchronous comparator: tasks bsp_tasks[begin, end).
+hipError_t launch_sweep_level(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
+                              int threads, bool one, int grid, int maxA, int maxG, int maxin,
+                              const long long *bsp_tasks, long long begin, long long end, const int *stops,
+                              hipStream_t s);
 hipError_t launch_xcc_probe(int *out, int nblocks, hipStream_t s);
 hipError_t launch_task_records(int C, const int *nbr, const unsigned *perm, const unsigned char *inmask, int *rec,
                                hipStream_t s);

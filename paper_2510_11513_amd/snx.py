@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsnx.so")
 STATUS = {0: "SNX_OK", -1: "SNX_E_ARG", -2: "SNX_E_STATE", -3: "SNX_E_MESH", -4: "SNX_E_CYCLE",
           -5: "SNX_E_DEVICE", -6: "SNX_E_OOM", -7: "SNX_E_NOCONV"}
 SNX_E_NOCONV = -7
+SWEEP_AMT, SWEEP_BSP = 0, 1
 
 EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_set_quadrature",
            "snx_quadrature_product", "snx_set_materials", "snx_set_boundary", "snx_setup", "snx_sweep",
@@ -27,7 +28,7 @@ EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_s
            "snx_batch_solve", "snx_batch_profile_sweep", "snx_batch_stats", "snx_gnn_create", "snx_gnn_destroy",
            "snx_gnn_last_error", "snx_gnn_num_params", "snx_gnn_get_params", "snx_gnn_set_params", "snx_gnn_save",
            "snx_gnn_load", "snx_gnn_features", "snx_gnn_targets", "snx_gnn_forward", "snx_gnn_grad",
-           "snx_gnn_train_step", "snx_gnn_predict"]
+           "snx_gnn_train_step", "snx_gnn_predict", "snx_set_sweep_mode", "snx_batch_set_sweep_mode"]
 _NO_STATUS = ("snx_destroy", "snx_last_error", "snx_batch_destroy", "snx_batch_last_error", "snx_gnn_destroy",
               "snx_gnn_last_error")
 
@@ -77,6 +78,8 @@ def load(path: str = LIB_PATH):
     L.snx_integrated_flux.argtypes = [_vp, _vp, _dp, _vp]
     L.snx_get_levels.argtypes = [_vp, _vp, _vp]
     L.snx_set_schedule.argtypes = [_vp, ct.c_int32, ct.c_int32, ct.c_int32]
+    L.snx_set_sweep_mode.argtypes = [_vp, ct.c_int32]
+    L.snx_batch_set_sweep_mode.argtypes = [_vp, ct.c_int32]
     L.snx_sweep_stats.argtypes = [_vp, _vp]
     L.snx_profile_sweep.argtypes = [_vp, ct.c_int32, _vp, _vp, ct.POINTER(ct.c_double), _vp]
     L.snx_tune.argtypes = [_vp, ct.c_char_p, _vp, _vp]
@@ -262,6 +265,10 @@ class Problem:
     def set_schedule(self, threads: int = 0, wg_per_cu: int = 0, chunk: int = 0):
         self._check(load().snx_set_schedule(self.h, threads, wg_per_cu, chunk), "set_schedule")
 
+    def set_sweep_mode(self, mode: int):
+        """SWEEP_AMT (dependency-driven, default) or SWEEP_BSP (level by level, the comparator)."""
+        self._check(load().snx_set_sweep_mode(self.h, mode), "set_sweep_mode")
+
     def profile_sweep(self, nsweeps: int, phi_in=None, phi_out=None, stream=None) -> float:
         """Mean duration (ms) of the sweep kernel alone, from HIP events on its stream."""
         if phi_out is None:
@@ -328,6 +335,9 @@ class Batch:
 
     def set_schedule(self, threads: int = 0, wg_per_cu: int = 0, chunk: int = 0):
         self._check(load().snx_batch_set_schedule(self.h, threads, wg_per_cu, chunk), "batch_set_schedule")
+
+    def set_sweep_mode(self, mode: int):
+        self._check(load().snx_batch_set_sweep_mode(self.h, mode), "batch_set_sweep_mode")
 
     def tune(self, cache_path=None, stream=None):
         chosen = np.zeros(2, np.int32)

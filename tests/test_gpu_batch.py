@@ -108,3 +108,17 @@ def test_batch_rejects_unready_problem():
     with pytest.raises(snx.SnxError) as e:
         snx.Batch([p])
     assert e.value.code == -2
+
+
+def test_batch_bulk_synchronous_solve_equals_dependency_driven():
+    from paper_2510_11513_amd import snx
+    probs = _uneven(4, seed=11)
+    gp = _setup(probs)
+    batch = snx.Batch(gp)
+    batch.set_schedule(chunk=3)
+    phi_a, inf_a, _ = batch.solve(1e-6, 300)
+    batch.set_sweep_mode(snx.SWEEP_BSP)
+    phi_b, inf_b, _ = batch.solve(1e-6, 300)
+    for i in range(len(probs)):
+        assert inf_a[i]["iterations"] == inf_b[i]["iterations"], i
+        assert np.array_equal(phi_a[i].cpu().numpy(), phi_b[i].cpu().numpy()), i

@@ -234,3 +234,28 @@ def test_cells_with_four_inflow_faces(threads, G):
     print(f"[case] skewed stack threads={threads} G={G} inflow faces={nin.tolist()}", flush=True)
     got, ref, _, _ = _sweep_pair(prob, _phi_in(prob, 4), threads=threads)
     assert H.rel_err_per_group(got, ref).max() <= TOL
+
+
+@pytest.mark.parametrize("case,threads", [("cfg2_n6", None), ("cfg2_n6", 64), ("edge", None), ("skewed", None)])
+def test_bulk_synchronous_comparator_gives_the_same_bits(case, threads):
+    """The level-by-level sweep (the paper's BSP scheme) runs the same task code as the
+    dependency-driven one: identical results, bit for bit, and both match the oracle."""
+    torch = _torch()
+    from paper_2510_11513_amd import snx
+    prob = {"cfg2_n6": lambda: inputs.config_problem(2, n=6), "edge": lambda: _custom(4, 5, 3, 3, seed=9, kind=1),
+            "skewed": lambda: skewed_stack(G=3)}[case]()
+    print(f"[case] bsp {case} threads={threads}", flush=True)
+    p = _gpu(prob, threads)
+    pin = torch.from_numpy(_phi_in(prob, 5)).cuda()
+    amt = p.sweep(pin).cpu().numpy()
+    p.set_sweep_mode(snx.SWEEP_BSP)
+    bsp = p.sweep(pin).cpu().numpy()
+    assert np.array_equal(amt, bsp)
+    ref = oracle.Oracle.from_problem(prob).sweep(_phi_in(prob, 5).astype(np.float64))["phi"]
+    assert H.rel_err_per_group(bsp.astype(np.float64), ref).max() <= TOL
+    # a solve in BSP mode takes the same iterations to the same bits
+    phi_b, ib = p.solve(1e-6, 500)
+    p.set_sweep_mode(snx.SWEEP_AMT)
+    phi_a, ia = p.solve(1e-6, 500)
+    assert ib["iterations"] == ia["iterations"]
+    assert np.array_equal(phi_a.cpu().numpy(), phi_b.cpu().numpy())
