@@ -208,6 +208,12 @@ def main():
                       "continued_tasks": stats["continued"],
                       "setup_s": round(t_setup, 3)},
            "roofline": roofline}
+    # the paper's comparison: the same sweep level by level (bulk-synchronous), same task code
+    p.set_sweep_mode(snx.SWEEP_BSP)
+    ms_bsp = p.profile_sweep(max(5, min(args.steps, 20)), phi_in=phi)
+    p.set_sweep_mode(snx.SWEEP_AMT)
+    out["bsp_comparator"] = {"sweep_ms": round(ms_bsp, 4), "amt_sweep_ms": round(ms_sweep, 4),
+                             "bsp_over_amt": round(ms_bsp / ms_sweep, 3)}
     if args.learned > 0:
         print("[bench] learned vs zero start", file=sys.stderr, flush=True)
         out["learned"] = learned_start(args.learned)
