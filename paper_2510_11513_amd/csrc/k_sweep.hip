@@ -365,8 +365,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 }
             }
         };
-        if constexpr (ONE)
-            if (cface >= 0) early_up(&s_rec[cbuf][16 + 13 * cface]);
 
         // ---------------------------------------------------------- stage
         // One round trip brings the cell data (M, T^a of this octant, the six
@@ -395,6 +393,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             }
             if (tid < AG) load_own(P, K, lg, L);
             if (!ONE && tid == 0) push_ready();                        // overlaps the loads above
+            // a continuation's trace requests go after the stage loads, so waiting
+            // for the stage data below does not wait for them
+            if constexpr (ONE)
+                if (cface >= 0) early_up(&s_rec[cbuf][16 + 13 * cface]);
             if (tid < kItems) stage_store(tid, st);
         } else {
             if (tid < A) {
@@ -403,6 +405,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             }
             if (tid < AG) load_own(P, K, lg, L);
             if (!ONE && tid == 0) push_ready();
+            if constexpr (ONE)
+                if (cface >= 0) early_up(&s_rec[cbuf][16 + 13 * cface]);
             for (int i = tid; i < kItems; i += NT) stage_store(i, stage_item(i));
         }
         if (tid < A) reinterpret_cast<float4 *>(sOm)[tid] = om4;
