@@ -626,15 +626,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         }
 
         if (tid == 0) { const unsigned long long t = clock64(); s_ph[3] += t - s_mark; s_mark = t; }
-        // ------------------------------------------------------ octant slot
+        // Octant slot: the task's compensated partial sums.  Only the reduction
+        // kernel reads them, so in the dependency-driven sweep they are written
+        // after the downwind counters: the wait before the counters covers only ψ.
         const size_t sbase = ((size_t)o * C + K) * G * 8;
-        for (int e = tid; e < G * 8; e += NT) {
-            gp(P.slot)[sbase + e] = sRs[e];
-            gp(P.slotc)[sbase + e] = sRc[e];
-        }
+        auto write_slot = [&]() {
+            for (int e = tid; e < G * 8; e += NT) {
+                gp(P.slot)[sbase + e] = sRs[e];
+                gp(P.slotc)[sbase + e] = sRc[e];
+            }
+        };
 
         // --------------------------------------------- publish to downwind
         if constexpr (BSP) {               // the next level is the next launch
+            write_slot();
             __syncthreads();
             continue;
         }
@@ -660,6 +665,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         cface = nr > 0 ? s_rface[0] : -1;            // the continuation's descriptor is in this record
         cbuf = cur;
         cur ^= 1;
+        write_slot();
         if (tid == 0) s_ph[4] += clock64() - s_mark;
         if (tid == 0) {
             ++s_stat[3];
