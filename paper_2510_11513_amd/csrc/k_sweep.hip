@@ -59,6 +59,23 @@ __device__ __forceinline__ void st_agent(GLOBAL float *p, float v) {
 }
 __device__ __forceinline__ void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Workgroup barrier ordering LDS accesses only.  Unlike __syncthreads it does
+// not wait for the wave's global loads and stores, so psi stores and upwind
+// trace requests stay in flight across it (LDS-destined loads still land
+// before it).  Every hand-off through global memory in the sweep waits for its
+// stores explicitly (wait_stores).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+// Workgroup barrier for data written to LDS by ordinary LDS stores only: it
+// waits for the wave's LDS operations, not for its LDS-destined loads (which
+// may still be staging the next task) nor its global accesses.
+__device__ __forceinline__ void lds_store_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // face f = 2*axis + side: face-local vertex k -> cell-local vertex
@@ -68,6 +85,35 @@ __device__ __forceinline__ int face_vertex(int f, int k) {
     if (axis == 1) return (k & 1) | (side << 1) | ((k >> 1) << 2);
     return (side << 2) | k;
 }
+// b[vertices of face F] -= t (face-local order)
+template <int F>
+__device__ __forceinline__ void sub_face(float (&b)[8], const float (&t)[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) b[face_vertex(F, k)] -= t[k];
+}
+// The same for a wave-uniform face: one scalar branch, static register indices.
+// The distinct empty asm statements keep the compiler from merging the cases
+// into one update at a computed index, which would move b to scratch memory.
+__device__ __forceinline__ void sub_face(int f, float (&b)[8], const float (&t)[4]) {
+    switch (f) {
+    case 0: sub_face<0>(b, t); asm volatile("; face 0"); break;
+    case 1: sub_face<1>(b, t); asm volatile("; face 1"); break;
+    case 2: sub_face<2>(b, t); asm volatile("; face 2"); break;
+    case 3: sub_face<3>(b, t); asm volatile("; face 3"); break;
+    case 4: sub_face<4>(b, t); asm volatile("; face 4"); break;
+    default: sub_face<5>(b, t); asm volatile("; face 5"); break;
+    }
+}
+// t = C u for a 4x4 face operator stored by rows in LDS
+__device__ __forceinline__ void face_apply(const float *C, const float (&u)[4], float (&t)[4]) {
+    const float4 *c = reinterpret_cast<const float4 *>(C);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float4 ck = c[k];
+        t[k] = __builtin_fmaf(ck.w, u[3], __builtin_fmaf(ck.z, u[2], __builtin_fmaf(ck.y, u[1], ck.x * u[0])));
+    }
+}
+
 // cell-local vertex j on a face of the given axis -> face-local index
 __device__ __forceinline__ int face_index(int axis, int j) {
     if (axis == 0) return j >> 1;
@@ -220,8 +266,9 @@ __device__ long long pop_task(SweepCtl *ctl, unsigned long long *queue, int &q, 
 // LDS layout (floats): M[64] T[3][64] Fin[6][48] om[A][4] Bop[A][64] Cop[A][maxin][16]
 //                      wpsi[2][NT][8] red_s[G][8] red_c[G][8]
 // ONE: every problem of the launch has A*G <= NT, so a task is one round of
-// lanes; nothing is prefetched for a next round and wpsi has one buffer, which
-// lowers the register and LDS footprint and lets more workgroups be resident.
+// lanes; nothing is prefetched for a next round, the upwind traces go to a
+// static LDS array and wpsi reuses it, which lowers the register and LDS
+// footprint and lets more workgroups be resident.
 //
 // BSP: the bulk-synchronous comparator of the paper (§2.1): the launch runs the
 // tasks bsp_tasks[bsp_begin, bsp_end) of one level (of every octant and problem)
@@ -238,10 +285,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
     __shared__ long long s_task;
     __shared__ int s_q;
     __shared__ int s_nready;
-    // Task records (own and downwind descriptors, see kRecWords), double-buffered:
-    // a continuation reads its descriptor from the last task's record while its
-    // own record is being loaded into the other buffer.
-    __shared__ __align__(16) int s_rec[2][kRecWords];
     __shared__ long long s_ready[6];
     __shared__ int s_rface[6];            // face of this task across which s_ready[i] lies
     __shared__ int s_npush, s_qpush;      // ready tasks s_ready[1..s_npush] still to be queued
@@ -251,16 +294,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
     const int tid = threadIdx.x;
     int q = ctl->xcc_queue[xcc_id()];       // home queue: the one of this XCD
 
-    float *sM = lds;
-    float *sT = sM + 64;                  // T^x, T^y, T^z of this (cell, octant)
-    float *sF = sT + 192;                 // the six face matrices F^x, F^y, F^z (48 each)
-    float *sOm = sF + 6 * 48;             // [maxA][4]: omega xyz, weight
+    // Two stage buffers (stage_floats each): cell data, task record (own and
+    // downwind descriptors, see kRecWords) and, ONE, source dofs.  A task stages
+    // into buffer cur; a continuation reads its descriptor from the last task's
+    // record in the other buffer while its own is being loaded.
+    const int SB = stage_floats(ONE, maxG);
+    float *sOm = lds + 2 * SB;            // [maxA][4]: omega xyz, weight
     float *sB = sOm + 4 * maxA;           // [maxA][64]
     float *sC = sB + 64 * maxA;           // [maxA][maxin][16]
-    float *sW = sC + 16 * maxin * maxA;   // [2][NT][8]
-    float *sRs = sW + (ONE ? 8 : 16) * NT; // [maxG][8]
+    float *sW = sC + 16 * maxin * maxA;   // multi-round: [2][NT][8] weighted psi
+    float *sRs = sW + (ONE ? 0 : 16) * NT; // [maxG][8]
     float *sRc = sRs + 8 * maxG;          // [maxG][8]
-    float *sUp = sRc + 8 * maxG;          // ONE: [3 slots][4 face nodes][NT] upwind traces
+    // ONE: [3 slots][4 face nodes][NT] upwind traces, filled by LDS-destined loads.
+    // A separate LDS object: reads of the other LDS data then need not wait for
+    // these loads to land.  Its first 8 rows then take the weighted psi, [8][NT]:
+    // each lane overwrites only its own column, after its own trace reads.
+    __shared__ __align__(16) float s_up[ONE ? 12 * NT : 4];
+    float *sUp = s_up;
 
     // Workgroup statistics, kept in LDS and touched by thread 0 only: polls, tasks,
     // continued tasks, tasks not yet added to the queue's done count, and the
@@ -291,7 +341,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
     };
     long long cont = -1;
     long long bsp_i = bsp_begin + blockIdx.x;
-    int cur = 0;                          // record buffer of the current task
+    int cur = 0;                          // stage buffer of the current task
     int cface = -1, cbuf = 0;             // continuation: its face in the last task's record, and that record's buffer
     for (;;) {
         long long task = cont;
@@ -316,7 +366,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 s_ph[0] += t - s_mark;
                 s_mark = t;
             }
-            __syncthreads();
+            lds_barrier();
             task = s_task;
             q = s_q;
             if (task < 0) break;
@@ -328,6 +378,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         const int p = uni(find_problem(task_base, nprob, task));
         const DevProblem &P = probs[p];
         const int C = P.C, G = P.G, A = P.A;
+        const unsigned epoch_p = *P.epoch;
         const long long local = task - P.task_base;
         const int o = uni((int)(local & 7));                 // task = 8 * cell + octant
         const int K = uni((int)(local >> 3));
@@ -369,49 +420,75 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         // ---------------------------------------------------------- stage
         // One round trip brings the cell data (M, T^a of this octant, the six
         // face matrices; 136 float4s) and the task record (24 int4s) to LDS, the
-        // directions, and each lane's own source dofs and sigma_t.
+        // directions, and each lane's sigma_t; one-round tasks also stage the
+        // cell's source dofs of every group (2 float4s per group).
         constexpr int kGeo = 16 + 48 + 72, kItems = kGeo + kRecWords / 4;
-        int *s_desc = s_rec[cur];             // words 0..12: this task's descriptor
-        auto stage_item = [&](int i) -> float4 {
-            if (i < 16) return reinterpret_cast<const GLOBAL float4 *>(gp(P.M) + (size_t)K * 64)[i];
-            if (i < 64) return reinterpret_cast<const GLOBAL float4 *>(gp(P.T) + ((size_t)o * C + K) * 192)[i - 16];
-            if (i < kGeo) return reinterpret_cast<const GLOBAL float4 *>(gp(P.F) + (size_t)K * 288)[i - 64];
-            return reinterpret_cast<const GLOBAL float4 *>(gp(P.rec) + ((size_t)o * C + K) * kRecWords)[i - kGeo];
-        };
-        auto stage_store = [&](int i, float4 v) {
-            if (i < kGeo) reinterpret_cast<float4 *>(sM)[i] = v;          // M, T and F are contiguous in LDS
-            else reinterpret_cast<float4 *>(s_desc)[i - kGeo] = v;
-        };
+        float *const stg = lds + cur * SB;
+        float *const sM = stg;                // M, then T^x, T^y, T^z of this (cell, octant),
+        float *const sT = sM + 64;            // then the six face matrices F^x, F^y, F^z (48 each)
+        float *const sF = sT + 192;
+        int *const s_desc = reinterpret_cast<int *>(stg + 4 * kGeo);   // words 0..12: this task's descriptor
+        const float *const sR = stg + 4 * kItems;                     // ONE: [G][8] source dofs
+        const int *const prev_rec = reinterpret_cast<const int *>(lds + cbuf * SB + 4 * kGeo);
         float4 om4 = make_float4(0.f, 0.f, 0.f, 0.f);          // direction and weight of angle tid (A <= 64 <= NT)
         LaneIn L;
-        if constexpr (NT >= kItems) {
-            // at most one item per thread: all loads in flight together
-            const float4 st = tid < kItems ? stage_item(tid) : make_float4(0.f, 0.f, 0.f, 0.f);
-            if (tid < A) {
-                const int n = o * A + tid;
-                om4 = make_float4(gp(P.omega)[3 * n + 0], gp(P.omega)[3 * n + 1], gp(P.omega)[3 * n + 2], gp(P.w)[n]);
-            }
-            if (tid < AG) load_own(P, K, lg, L);
-            if (!ONE && tid == 0) push_ready();                        // overlaps the loads above
-            // a continuation's trace requests go after the stage loads, so waiting
-            // for the stage data below does not wait for them
-            if constexpr (ONE)
-                if (cface >= 0) early_up(&s_rec[cbuf][16 + 13 * cface]);
-            if (tid < kItems) stage_store(tid, st);
-        } else {
-            if (tid < A) {
-                const int n = o * A + tid;
-                om4 = make_float4(gp(P.omega)[3 * n + 0], gp(P.omega)[3 * n + 1], gp(P.omega)[3 * n + 2], gp(P.w)[n]);
-            }
-            if (tid < AG) load_own(P, K, lg, L);
-            if (!ONE && tid == 0) push_ready();
-            if constexpr (ONE)
-                if (cface >= 0) early_up(&s_rec[cbuf][16 + 13 * cface]);
-            for (int i = tid; i < kItems; i += NT) stage_store(i, stage_item(i));
+        // a continuation is in the same problem and octant: its directions are in LDS
+        const bool new_om = !ONE || cface < 0;
+        if (new_om && tid < A) {
+            const int n = o * A + tid;
+            om4 = make_float4(gp(P.omega)[3 * n + 0], gp(P.omega)[3 * n + 1], gp(P.omega)[3 * n + 2], gp(P.w)[n]);
         }
-        if (tid < A) reinterpret_cast<float4 *>(sOm)[tid] = om4;
+        // ONE: 16-byte LDS-destined loads of the stage items of cell Kc (octant o)
+        // into buffer dst, 64-lane blocks first, first + step, ... (one block per
+        // wave and step); no registers are held for the staged data
+        auto stage_dma = [&](int Kc, float *dst, int first, int step) {
+            const int nitems = kItems + 2 * G;
+            const GLOBAL float *srcM = gp(P.M) + (size_t)Kc * 64;
+            const GLOBAL float *srcT = gp(P.T) + ((size_t)o * C + Kc) * 192;
+            const GLOBAL float *srcF = gp(P.F) + (size_t)Kc * 288;
+            const GLOBAL float *srcRec =
+                reinterpret_cast<const GLOBAL float *>(gp(P.rec) + ((size_t)o * C + Kc) * kRecWords);
+            const GLOBAL float *srcR = gp(P.r) + (size_t)Kc * G * 8;
+            for (int i0 = first; i0 < nitems; i0 += step) {
+                const int i = i0 + (tid & 63);
+                if (i < nitems) {
+                    const GLOBAL float *src = i < 16 ? srcM + 4 * i
+                                            : i < 64 ? srcT + 4 * (i - 16)
+                                            : i < kGeo ? srcF + 4 * (i - 64)
+                                            : i < kItems ? srcRec + 4 * (i - kGeo)
+                                            : srcR + 4 * (i - kItems);
+                    __builtin_amdgcn_global_load_lds((const void *)src,
+                                                     (__attribute__((address_space(3))) void *)(dst + 4 * i0), 16, 0, 0);
+                }
+            }
+        };
+        if constexpr (ONE) {
+            stage_dma(K, stg, uni(tid & ~63), NT);
+            if (tid < AG) L.sig = gp(P.sigt)[(size_t)K * G + lg];
+            // a continuation's trace requests go after the stage loads
+            if (cface >= 0) early_up(prev_rec + 16 + 13 * cface);
+        } else {
+            auto stage_item = [&](int i) -> float4 {
+                if (i < 16) return reinterpret_cast<const GLOBAL float4 *>(gp(P.M) + (size_t)K * 64)[i];
+                if (i < 64) return reinterpret_cast<const GLOBAL float4 *>(gp(P.T) + ((size_t)o * C + K) * 192)[i - 16];
+                if (i < kGeo) return reinterpret_cast<const GLOBAL float4 *>(gp(P.F) + (size_t)K * 288)[i - 64];
+                return reinterpret_cast<const GLOBAL float4 *>(gp(P.rec) + ((size_t)o * C + K) * kRecWords)[i - kGeo];
+            };
+            if constexpr (NT >= kItems) {
+                // at most one item per thread: all loads in flight together
+                const float4 st = tid < kItems ? stage_item(tid) : make_float4(0.f, 0.f, 0.f, 0.f);
+                if (tid < AG) load_own(P, K, lg, L);
+                if (tid == 0) push_ready();                        // overlaps the loads above
+                if (tid < kItems) reinterpret_cast<float4 *>(stg)[tid] = st;
+            } else {
+                if (tid < AG) load_own(P, K, lg, L);
+                if (tid == 0) push_ready();
+                for (int i = tid; i < kItems; i += NT) reinterpret_cast<float4 *>(stg)[i] = stage_item(i);
+            }
+        }
+        if (new_om && tid < A) reinterpret_cast<float4 *>(sOm)[tid] = om4;
         for (int i = tid; i < G * 8; i += NT) { sRs[i] = 0.f; sRc[i] = 0.f; }
-        __syncthreads();
+        lds_barrier();                // the staged data come from LDS-destined loads of every wave
         if (tid == 0) s_nready = 0;   // after the barrier: every thread has read the last task's count
         if constexpr (ONE)
             if (cface < 0) early_up(s_desc);
@@ -463,7 +540,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 }
             }
         }
-        __syncthreads();
+        // only LDS stores cross this barrier: LDS-destined trace loads are read by
+        // the wave that issued them, after its own wait
+        lds_store_barrier();
         // one-round tasks: the last wave queues the last task's other ready tasks
         // while the lanes solve (it is idle there when A*G <= NT - 64)
         if constexpr (ONE)
@@ -474,38 +553,39 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         int buf = 0;
         for (int base = 0; ONE ? base == 0 : base < AG; base += NT, buf ^= 1) {
             const int pi = base + tid;
-            float *sWb = ONE ? sW : sW + buf * NT * 8;
+            float *sWb = ONE ? sUp : sW + buf * NT * 8;   // dof d of lane l: ONE d*NT + l, else 8l + d
             if (pi < AG) {
                 const int n = ONE ? ln : div_small(pi, invG), g = ONE ? lg : pi - n * G;
                 float b[8];
+                if constexpr (ONE) {
+                    const float4 r0 = reinterpret_cast<const float4 *>(sR + 8 * g)[0];
+                    const float4 r1 = reinterpret_cast<const float4 *>(sR + 8 * g)[1];
+                    b[0] = r0.x; b[1] = r0.y; b[2] = r0.z; b[3] = r0.w;
+                    b[4] = r1.x; b[5] = r1.y; b[6] = r1.z; b[7] = r1.w;
+                } else {
 #pragma unroll
-                for (int d = 0; d < 8; ++d) b[d] = L.r[d];
+                    for (int d = 0; d < 8; ++d) b[d] = L.r[d];
+                }
                 const float psib = P.psib ? gp(P.psib)[g] : 0.f;
                 if constexpr (ONE) {
-                    // Inflow faces in slot order, three at a time; each face takes its
-                    // slot by a select, so the node map of every face stays static.
-                    // The first three arrived in LDS (requested early); hexahedra of
-                    // the meshes here have three inflow faces per octant, so later
-                    // groups (loaded into registers here) are rare.
+                    // Inflow faces in slot order (slot s = s-th set bit of the mask),
+                    // three at a time.  The face of a slot is wave-uniform, so the
+                    // node map is picked by one scalar branch per slot.  The first
+                    // three arrived in LDS (requested early); hexahedra of the
+                    // meshes here have three inflow faces per octant, so later groups
+                    // (loaded into registers here) are rare.
                     auto apply = [&](int taken, int s0, const float (&u)[3][4], int bnd) {
 #pragma unroll
-                        for (int f = 0; f < 6; ++f) {
-                            if (!((taken >> f) & 1)) continue;
-                            const int j = __popc(taken & ((1 << f) - 1));
-                            const float *Cs = sC + (n * maxin + s0 + j) * 16;
+                        for (int j = 0; j < 3; ++j) {
+                            if (!taken) break;
+                            const int f = __builtin_ctz(taken);
+                            taken &= taken - 1;
                             const bool boundary = (bnd >> j) & 1;
-                            float uf[4];
+                            float uf[4], t[4];
 #pragma unroll
-                            for (int l = 0; l < 4; ++l)
-                                uf[l] = boundary ? psib : (j == 0 ? u[0][l] : (j == 1 ? u[1][l] : u[2][l]));
-#pragma unroll
-                            for (int k = 0; k < 4; ++k) {
-                                float t = Cs[k * 4] * uf[0];
-                                t = __builtin_fmaf(Cs[k * 4 + 1], uf[1], t);
-                                t = __builtin_fmaf(Cs[k * 4 + 2], uf[2], t);
-                                t = __builtin_fmaf(Cs[k * 4 + 3], uf[3], t);
-                                b[face_vertex(f, k)] -= t;
-                            }
+                            for (int l = 0; l < 4; ++l) uf[l] = boundary ? psib : u[j][l];
+                            face_apply(sC + (n * maxin + s0 + j) * 16, uf, t);
+                            sub_face(f, b, t);
                         }
                     };
                     {
@@ -593,10 +673,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 for (int d = 0; d < 8; ++d) {
                     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, b[d]), rk, 4 * pi, d * AG * 4,
                                                           kCoherentAccess);
-                    sWb[tid * 8 + d] = wn * b[d];
+                    sWb[ONE ? d * NT + tid : tid * 8 + d] = wn * b[d];
                 }
             }
-            __syncthreads();
+            lds_store_barrier();   // the psi stores stay in flight until the publish
             // compensated accumulation in increasing angle order, one (group, dof) per reducer;
             // the other buffer takes the next round's values meanwhile
             const int hi = min(base + NT, AG);
@@ -604,17 +684,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 const int g = e >> 3, d = e & 7;
                 float s = sRs[e], c = sRc[e];
                 const int q0 = ONE ? g : base + ((g - base % G) % G + G) % G;   // first lane of group g
-                const float *w = sWb + (q0 - base) * 8 + d;
+                constexpr int LS = ONE ? 1 : 8;   // stride between lanes
+                const float *w = sWb + (q0 - base) * LS + d * (ONE ? NT : 1);
+                const int st = G * LS;            // next angle, same group
                 int q = q0;
-                for (; q + 3 * G < hi; q += 4 * G, w += 32 * G) {   // four angles' reads in flight together
-                    const float w0 = w[0], w1 = w[8 * G], w2 = w[16 * G], w3 = w[24 * G];
+                for (; q + 3 * G < hi; q += 4 * G, w += 4 * st) {   // four angles' reads in flight together
+                    const float w0 = w[0], w1 = w[st], w2 = w[2 * st], w3 = w[3 * st];
                     float t, err;
                     two_sum(s, w0, t, err); s = t; c += err;
                     two_sum(s, w1, t, err); s = t; c += err;
                     two_sum(s, w2, t, err); s = t; c += err;
                     two_sum(s, w3, t, err); s = t; c += err;
                 }
-                for (; q < hi; q += G, w += 8 * G) {
+                for (; q < hi; q += G, w += st) {
                     float t, err;
                     two_sum(s, w[0], t, err);
                     s = t;
@@ -640,7 +722,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         // --------------------------------------------- publish to downwind
         if constexpr (BSP) {               // the next level is the next launch
             write_slot();
-            __syncthreads();
+            lds_barrier();
             continue;
         }
         wait_stores();
@@ -651,7 +733,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             if (N >= 0) {
                 const unsigned old = __hip_atomic_fetch_add(gp(P.cnt) + (size_t)o * C + N, 1u, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned target = (unsigned)gp(P.indeg)[(size_t)o * C + N] * *P.epoch;
+                const unsigned target = (unsigned)gp(P.indeg)[(size_t)o * C + N] * epoch_p;
                 if (old + 1u == target) {
                     const int i = atomicAdd(&s_nready, 1);
                     s_ready[i] = P.task_base + 8LL * N + o;
@@ -659,7 +741,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         const int nr = s_nready;
         cont = nr > 0 ? s_ready[0] : -1;
         cface = nr > 0 ? s_rface[0] : -1;            // the continuation's descriptor is in this record
@@ -671,7 +753,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             ++s_stat[3];
             ++s_stat[1];
             // downwind cells are in the same octant, hence in this task's queue; the
-            // others are queued during the continuation's stage (nr > 1 implies one)
+            // others are queued during the continuation (nr > 1 implies one)
             s_npush = nr - 1;
             s_qpush = o % nq;
 
@@ -757,8 +839,8 @@ bool sweep_threads_valid(int threads) {
 }
 
 size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin, bool one) {
-    size_t floats = 64 + 192 + 6 * 48 + 4 * (size_t)maxA + 64 * (size_t)maxA + 16 * (size_t)maxin * maxA +
-                    (one ? 8 + 12 : 16) * (size_t)threads + 16 * (size_t)maxG;
+    size_t floats = 2 * (size_t)stage_floats(one, maxG) + 4 * (size_t)maxA + 64 * (size_t)maxA +
+                    16 * (size_t)maxin * maxA + (one ? 0 : 16) * (size_t)threads + 16 * (size_t)maxG;
     return floats * sizeof(float);
 }
 

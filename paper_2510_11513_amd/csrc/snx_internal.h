@@ -16,13 +16,22 @@ constexpr int kMaxGroups = 256;
 constexpr float kInv4Pi = 0.0795774715459476679f;
 
 constexpr int kMaxQueues = 16;   // task queues of a sweep (one per XCD of the device)
-constexpr int kMaxXcc = 32;
-constexpr int kReduceItems = 4;
+constexpr int kMaxXcc = 32;      // range of hardware XCC ids mapped to queues
+constexpr int kReduceItems = 4;  // (cell, group) items per thread of the batched reduction
 // Task record of one (octant, cell), 96 ints (24 int4): words 0..12 the cell's
 // descriptor (neighbour ids [6], node permutations [6], inflow mask of the
 // octant), 13..15 zero, then for each face f at 16 + 13 f the descriptor of the
 // neighbour across f when f is a downwind face (zero otherwise), 94..95 zero.
-constexpr int kRecWords = 96;      // (cell, group) items per thread of the batched reduction      // range of hardware XCC ids mapped to queues
+constexpr int kRecWords = 96;
+
+// LDS stage buffer of one sweep task (floats): the cell data M, T of the octant
+// and the six face matrices (136 float4s), the task record (24 int4s) and, for
+// one-round tasks, the cell's source dofs of every group (2 float4s per group),
+// rounded up to whole 64-lane blocks of 16-byte LDS-destined loads.  A sweep
+// workgroup holds two.
+__host__ __device__ constexpr int stage_floats(bool one, int maxG) {
+    return 256 * ((160 + (one ? 2 * maxG : 0) + 63) / 64);
+}
 
 // One task queue: octants are assigned to queues (o mod nq), and each queue is
 // served by the workgroups of one XCD, so a sweep's hand-offs stay in that
