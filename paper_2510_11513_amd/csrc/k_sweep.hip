@@ -142,21 +142,30 @@ __device__ __forceinline__ int find_problem(const long long *__restrict__ base, 
     return lo;
 }
 
-// The per-lane inputs of one (angle, group) system: source dofs, sigma_t and the
-// upwind traces of every inflow face (mask-predicated, one slot per face).
+// The per-lane inputs of one (angle, group) system: source dofs, sigma_t, the
+// boundary inflow and the upwind traces of every inflow face (mask-predicated,
+// one slot per face).
 struct LaneIn {
     float r[8];
     float sig;
+    float psib;
     float up[6][4];
 };
 
-// Source dofs and sigma_t of lane (n, g) of cell K: no dependence on other tasks.
+// sigma_t and boundary inflow of lane (n, g) of cell K (requested early: the
+// values are used only at the solve).
+__device__ __forceinline__ void load_sig(const DevProblem &P, int K, int g, LaneIn &L) {
+    L.sig = gp(P.sigt)[(size_t)K * P.G + g];
+    L.psib = P.psib ? gp(P.psib)[g] : 0.f;
+}
+// Source dofs, sigma_t and boundary inflow of lane (n, g) of cell K: no
+// dependence on other tasks.
 __device__ __forceinline__ void load_own(const DevProblem &P, int K, int g, LaneIn &L) {
     const GLOBAL float4 *rv = reinterpret_cast<const GLOBAL float4 *>(gp(P.r) + ((size_t)K * P.G + g) * 8);
     const float4 r0 = rv[0], r1 = rv[1];
     L.r[0] = r0.x; L.r[1] = r0.y; L.r[2] = r0.z; L.r[3] = r0.w;
     L.r[4] = r1.x; L.r[5] = r1.y; L.r[6] = r1.z; L.r[7] = r1.w;
-    L.sig = gp(P.sigt)[(size_t)K * P.G + g];
+    load_sig(P, K, g, L);
 }
 
 // psi of one (octant, cell) is [dof][angle][group]: lane p = n*G + g of a task
@@ -294,12 +303,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
     const int tid = threadIdx.x;
     int q = ctl->xcc_queue[xcc_id()];       // home queue: the one of this XCD
 
-    // Two stage buffers (stage_floats each): cell data, task record (own and
-    // downwind descriptors, see kRecWords) and, ONE, source dofs.  A task stages
-    // into buffer cur; a continuation reads its descriptor from the last task's
-    // record in the other buffer while its own is being loaded.
+    // Stage buffers (stage_floats each): cell data, task record (own and
+    // downwind descriptors, see kRecWords) and, ONE, source dofs.  ONE has two:
+    // a task stages into buffer cur, and a continuation reads its descriptor from
+    // the last task's record in the other buffer while its own is being loaded.
     const int SB = stage_floats(ONE, maxG);
-    float *sOm = lds + 2 * SB;            // [maxA][4]: omega xyz, weight
+    float *sOm = lds + stage_buffers(ONE) * SB;   // [maxA][4]: omega xyz, weight
     float *sB = sOm + 4 * maxA;           // [maxA][64]
     float *sC = sB + 64 * maxA;           // [maxA][maxin][16]
     float *sW = sC + 16 * maxin * maxA;   // multi-round: [2][NT][8] weighted psi
@@ -378,7 +387,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         const int p = uni(find_problem(task_base, nprob, task));
         const DevProblem &P = probs[p];
         const int C = P.C, G = P.G, A = P.A;
-        const unsigned epoch_p = *P.epoch;
         const long long local = task - P.task_base;
         const int o = uni((int)(local & 7));                 // task = 8 * cell + octant
         const int K = uni((int)(local >> 3));
@@ -423,13 +431,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         // directions, and each lane's sigma_t; one-round tasks also stage the
         // cell's source dofs of every group (2 float4s per group).
         constexpr int kGeo = 16 + 48 + 72, kItems = kGeo + kRecWords / 4;
-        float *const stg = lds + cur * SB;
+        float *const stg = lds + (ONE ? cur : 0) * SB;
         float *const sM = stg;                // M, then T^x, T^y, T^z of this (cell, octant),
         float *const sT = sM + 64;            // then the six face matrices F^x, F^y, F^z (48 each)
         float *const sF = sT + 192;
         int *const s_desc = reinterpret_cast<int *>(stg + 4 * kGeo);   // words 0..12: this task's descriptor
         const float *const sR = stg + 4 * kItems;                     // ONE: [G][8] source dofs
-        const int *const prev_rec = reinterpret_cast<const int *>(lds + cbuf * SB + 4 * kGeo);
+        const int *const prev_rec = reinterpret_cast<const int *>(lds + (ONE ? cbuf : 0) * SB + 4 * kGeo);
         float4 om4 = make_float4(0.f, 0.f, 0.f, 0.f);          // direction and weight of angle tid (A <= 64 <= NT)
         LaneIn L;
         // a continuation is in the same problem and octant: its directions are in LDS
@@ -452,19 +460,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             for (int i0 = first; i0 < nitems; i0 += step) {
                 const int i = i0 + (tid & 63);
                 if (i < nitems) {
-                    const GLOBAL float *src = i < 16 ? srcM + 4 * i
-                                            : i < 64 ? srcT + 4 * (i - 16)
-                                            : i < kGeo ? srcF + 4 * (i - 64)
-                                            : i < kItems ? srcRec + 4 * (i - kGeo)
-                                            : srcR + 4 * (i - kItems);
-                    __builtin_amdgcn_global_load_lds((const void *)src,
+                    // the item's array and offset, picked by selects (no divergent branches)
+                    unsigned long long a = (unsigned long long)srcM + 16ull * i;
+                    a = i >= 16 ? (unsigned long long)srcT + 16ull * (i - 16) : a;
+                    a = i >= 64 ? (unsigned long long)srcF + 16ull * (i - 64) : a;
+                    a = i >= kGeo ? (unsigned long long)srcRec + 16ull * (i - kGeo) : a;
+                    a = i >= kItems ? (unsigned long long)srcR + 16ull * (i - kItems) : a;
+                    __builtin_amdgcn_global_load_lds((const void *)a,
                                                      (__attribute__((address_space(3))) void *)(dst + 4 * i0), 16, 0, 0);
                 }
             }
         };
         if constexpr (ONE) {
             stage_dma(K, stg, uni(tid & ~63), NT);
-            if (tid < AG) L.sig = gp(P.sigt)[(size_t)K * G + lg];
+            if (tid < AG) load_sig(P, K, lg, L);
             // a continuation's trace requests go after the stage loads
             if (cface >= 0) early_up(prev_rec + 16 + 13 * cface);
         } else {
@@ -566,7 +575,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
 #pragma unroll
                     for (int d = 0; d < 8; ++d) b[d] = L.r[d];
                 }
-                const float psib = P.psib ? gp(P.psib)[g] : 0.f;
+                const float psib = L.psib;
                 if constexpr (ONE) {
                     // Inflow faces in slot order (slot s = s-th set bit of the mask),
                     // three at a time.  The face of a slot is wave-uniform, so the
@@ -733,7 +742,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             if (N >= 0) {
                 const unsigned old = __hip_atomic_fetch_add(gp(P.cnt) + (size_t)o * C + N, 1u, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned target = (unsigned)gp(P.indeg)[(size_t)o * C + N] * epoch_p;
+                const unsigned target = (unsigned)gp(P.indeg)[(size_t)o * C + N] * *gp(P.epoch);
                 if (old + 1u == target) {
                     const int i = atomicAdd(&s_nready, 1);
                     s_ready[i] = P.task_base + 8LL * N + o;
@@ -839,7 +848,7 @@ bool sweep_threads_valid(int threads) {
 }
 
 size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin, bool one) {
-    size_t floats = 2 * (size_t)stage_floats(one, maxG) + 4 * (size_t)maxA + 64 * (size_t)maxA +
+    size_t floats = (size_t)stage_buffers(one) * stage_floats(one, maxG) + 4 * (size_t)maxA + 64 * (size_t)maxA +
                     16 * (size_t)maxin * maxA + (one ? 0 : 16) * (size_t)threads + 16 * (size_t)maxG;
     return floats * sizeof(float);
 }

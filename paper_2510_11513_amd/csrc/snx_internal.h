@@ -25,13 +25,14 @@ constexpr int kReduceItems = 4;  // (cell, group) items per thread of the batche
 constexpr int kRecWords = 96;
 
 // LDS stage buffer of one sweep task (floats): the cell data M, T of the octant
-// and the six face matrices (136 float4s), the task record (24 int4s) and, for
-// one-round tasks, the cell's source dofs of every group (2 float4s per group),
-// rounded up to whole 64-lane blocks of 16-byte LDS-destined loads.  A sweep
-// workgroup holds two.
+// and the six face matrices (136 float4s) and the task record (24 int4s); for
+// one-round tasks also the cell's source dofs of every group (2 float4s per
+// group), rounded up to whole 64-lane blocks of 16-byte LDS-destined loads.
+// One-round sweep workgroups hold two (stage_buffers).
 __host__ __device__ constexpr int stage_floats(bool one, int maxG) {
-    return 256 * ((160 + (one ? 2 * maxG : 0) + 63) / 64);
+    return one ? 256 * ((160 + 2 * maxG + 63) / 64) : 4 * 160;
 }
+__host__ __device__ constexpr int stage_buffers(bool one) { return one ? 2 : 1; }
 
 // One task queue: octants are assigned to queues (o mod nq), and each queue is
 // served by the workgroups of one XCD, so a sweep's hand-offs stay in that
