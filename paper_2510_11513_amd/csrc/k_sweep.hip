@@ -518,34 +518,42 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         if (tid == 0) { const unsigned long long t = clock64(); s_ph[1] += t - s_mark; s_mark = t; }
 
         // ------------------------------------- per-angle operators B_n, C_n,f
-        {   // column by column: a thread owns one entry (i, j) of B or of an inflow C
-            // for a share of the angles, so the three operator values are read once
-            // and each angle costs one direction read, three FMAs and one write
-            const int ncol = 64 + 16 * nin;
-            const int nsplit = max(1, NT / ncol);
-            const float inv_ncol = __builtin_amdgcn_rcpf((float)ncol);
-            for (int w = tid; w < ncol * nsplit; w += NT) {
-                const int part = div_small(w, inv_ncol);
-                const int c = w - part * ncol;
-                float vx, vy, vz;
-                float *dst;
-                int stride;
-                if (c < 64) {
-                    vx = sT[c]; vy = sT[64 + c]; vz = sT[128 + c];
-                    dst = sB + c;
-                    stride = 64;
-                } else {
-                    const int s = (c - 64) >> 4, kl = (c - 64) & 15;
-                    int m = mask;                               // face of inflow slot s: s-th set bit of mask
-                    for (int k = 0; k < s; ++k) m &= m - 1;
-                    const float *Fs = sF + (__ffs(m) - 1) * 48;
-                    vx = Fs[kl]; vy = Fs[16 + kl]; vz = Fs[32 + kl];
-                    dst = sC + s * 16 + kl;
-                    stride = maxin * 16;
-                }
-                for (int n = part; n < A; n += nsplit) {
+        {   // Angles are dealt to waves (wave-uniform loop), entries to lanes: lane l
+            // owns entry l of B (8x8) and entry l & 15 of the inflow operator of slot
+            // l >> 4, so its three operator values are read once and each angle costs
+            // one broadcast direction read, three FMAs per operator and the writes.
+            const int lane = tid & 63, wv = uni(tid >> 6);
+            constexpr int kWaves = NT / 64;
+            const float bx = sT[lane], by = sT[64 + lane], bz = sT[128 + lane];
+            auto slot_coef = [&](int s, float &cx, float &cy, float &cz) {
+                int m = mask;                                   // face of inflow slot s: s-th set bit of mask
+                for (int k = 0; k < s; ++k) m &= m - 1;
+                const float *Fs = sF + (m ? __ffs(m) - 1 : 0) * 48;
+                const int kl = lane & 15;
+                cx = Fs[kl]; cy = Fs[16 + kl]; cz = Fs[32 + kl];
+            };
+            const int s0 = lane >> 4;                           // slots 0..3
+            float cx, cy, cz;
+            slot_coef(s0, cx, cy, cz);
+            const bool c0 = s0 < nin;
+            const float4 *om4s = reinterpret_cast<const float4 *>(sOm);
+            auto put = [&](int n, float4 om) {
+                sB[n * 64 + lane] = om.x * bx + om.y * by + om.z * bz;
+                if (c0) sC[(n * maxin + s0) * 16 + (lane & 15)] = om.x * cx + om.y * cy + om.z * cz;
+            };
+            int n = wv;
+            for (; n + kWaves < A; n += 2 * kWaves) {          // two angles' reads in flight together
+                const float4 oa = om4s[n], ob = om4s[n + kWaves];
+                put(n, oa);
+                put(n + kWaves, ob);
+            }
+            if (n < A) put(n, om4s[n]);
+            if (nin > 4) {                                      // slots 4, 5 (rare)
+                const int s1 = 4 + s0;
+                slot_coef(s1, cx, cy, cz);
+                for (int n = wv; n < A; n += kWaves) {
                     const float4 om = reinterpret_cast<const float4 *>(sOm)[n];
-                    dst[n * stride] = om.x * vx + om.y * vy + om.z * vz;
+                    if (s1 < nin) sC[(n * maxin + s1) * 16 + (lane & 15)] = om.x * cx + om.y * cy + om.z * cz;
                 }
             }
         }
