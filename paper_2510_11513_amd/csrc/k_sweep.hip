@@ -591,17 +591,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                     // three arrived in LDS (requested early); hexahedra of the
                     // meshes here have three inflow faces per octant, so later groups
                     // (loaded into registers here) are rare.
-                    auto apply = [&](int taken, int s0, const float (&u)[3][4], int bnd) {
+                    // boundary slots (bit j of bnd) take the inflow psi_b; interior
+                    // tasks skip the selects
+                    auto set_boundary = [&](float (&u)[3][4], int bnd) {
+                        if (bnd) {
+#pragma unroll
+                            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                                for (int l = 0; l < 4; ++l) u[j][l] = (bnd >> j) & 1 ? psib : u[j][l];
+                        }
+                    };
+                    auto apply = [&](int taken, int s0, const float (&u)[3][4]) {
 #pragma unroll
                         for (int j = 0; j < 3; ++j) {
                             if (!taken) break;
                             const int f = __builtin_ctz(taken);
                             taken &= taken - 1;
-                            const bool boundary = (bnd >> j) & 1;
-                            float uf[4], t[4];
-#pragma unroll
-                            for (int l = 0; l < 4; ++l) uf[l] = boundary ? psib : u[j][l];
-                            face_apply(sC + (n * maxin + s0 + j) * 16, uf, t);
+                            float t[4];
+                            face_apply(sC + (n * maxin + s0 + j) * 16, u[j], t);
                             sub_face(f, b, t);
                         }
                     };
@@ -612,7 +619,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                         for (int j = 0; j < 3; ++j)
 #pragma unroll
                             for (int l = 0; l < 4; ++l) u0[j][l] = sUp[(j * 4 + l) * NT + tid];
-                        apply(taken0, 0, u0, bnd0);
+                        set_boundary(u0, bnd0);
+                        apply(taken0, 0, u0);
                     }
                     int rest = mask & ~taken0;
                     for (int s0 = 3; rest; s0 += 3) {
@@ -620,7 +628,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                         int bnd = 0;
                         const int taken = load_slots(rest, K, pi, AG, psi_o, s_desc, u, bnd);
                         rest &= ~taken;
-                        apply(taken, s0, u, bnd);
+                        set_boundary(u, bnd);
+                        apply(taken, s0, u);
                     }
                 } else {
 #pragma unroll
