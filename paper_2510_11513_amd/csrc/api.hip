@@ -498,7 +498,8 @@ snx_status time_sweeps(Sched &sc, int reps, hipStream_t s, double *ms) {
 // task's (angle, group) solves run side by side: 64 per wavefront) and the
 // resident workgroups per CU.  The tuner times a few sweeps of every candidate
 // on the actual problems and keeps the fastest; results are cached in a text
-// file of JSON lines keyed by device and problem shape.
+// file of JSON lines keyed by device, problem shape and sweep-kernel revision
+// (kSweepRevision: a schedule tuned for another kernel is not reused).
 
 std::string tune_key(const Sched &sc) {
     hipDeviceProp_t prop{};
@@ -512,8 +513,8 @@ std::string tune_key(const Sched &sc) {
     while ((1LL << (cb + 1)) <= cells) ++cb;
     while ((1LL << (sb + 1)) <= solves) ++sb;
     char buf[256];
-    std::snprintf(buf, sizeof buf, "%s|cu%d|np%d|A%d|G%d|c%d|s%d", prop.gcnArchName, cu_count(sc.device),
-                  sc.nprob(), sc.maxA, sc.maxG, cb, sb);
+    std::snprintf(buf, sizeof buf, "%s|cu%d|np%d|A%d|G%d|c%d|s%d|k%d", prop.gcnArchName, cu_count(sc.device),
+                  sc.nprob(), sc.maxA, sc.maxG, cb, sb, kSweepRevision);
     return buf;
 }
 
@@ -560,21 +561,29 @@ snx_status tune_sched(Sched &sc, const char *cache, hipStream_t s, int *out_thre
             return SNX_OK;
         }
     }
-    double best = 1e300;
-    int bt = sc.threads, bw = sc.wg_per_cu;
+    // two passes over the candidates, each candidate's best pass counts (clock and
+    // thermal drift during the first pass does not decide)
+    struct Cand { int th, wg; double ms; };
+    std::vector<Cand> cands;
     for (int th : {64, 128, 192, 256, 512}) {
         if (th < sc.maxG) continue;
-        for (int wg : {0, 2, 4, 8}) {
-            sc.threads = th;
-            sc.wg_per_cu = wg;
+        for (int wg : {0, 2, 4, 8}) cands.push_back({th, wg, 1e300});
+    }
+    for (int pass = 0; pass < 2; ++pass)
+        for (Cand &c : cands) {
+            sc.threads = c.th;
+            sc.wg_per_cu = c.wg;
             if (configure_grid(sc)) continue;
             double ms = 0.0;
             snx_status st = time_sweeps(sc, 1, s, &ms);           // warm-up
             if (!st) st = time_sweeps(sc, 3, s, &ms);
             if (st) return st;
-            if (ms < best) { best = ms; bt = th; bw = wg; }
+            c.ms = std::min(c.ms, ms);
         }
-    }
+    double best = 1e300;
+    int bt = sc.threads, bw = sc.wg_per_cu;
+    for (const Cand &c : cands)
+        if (c.ms < best) { best = c.ms; bt = c.th; bw = c.wg; }
     sc.threads = bt;
     sc.wg_per_cu = bw;
     sc.drop_graphs();

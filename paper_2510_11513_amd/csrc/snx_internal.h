@@ -23,6 +23,9 @@ constexpr int kReduceItems = 4;  // (cell, group) items per thread of the batche
 // octant), 13..15 zero, then for each face f at 16 + 13 f the descriptor of the
 // neighbour across f when f is a downwind face (zero otherwise), 94..95 zero.
 constexpr int kRecWords = 96;
+// Revision of the sweep kernel's schedule behaviour: part of the autotuner's
+// cache key, raised when a kernel change can move the best schedule.
+constexpr int kSweepRevision = 2;
 
 // LDS stage buffer of one sweep task (floats): the cell data M, T of the octant
 // and the six face matrices (136 float4s) and the task record (24 int4s); for
