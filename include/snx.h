@@ -138,6 +138,13 @@ snx_status snx_integrated_flux(snx_problem *p, const float *phi, double *out, vo
  * octant) and host nlevels[8]; either may be NULL.  Synchronous. */
 snx_status snx_get_levels(snx_problem *p, int32_t *level, int32_t *nlevels);
 
+/* The angular flux psi (Eq. 1) of one direction and group from the most recent
+ * sweep of this problem (alone or in a batch): device out[ncell][8] (FP32, the
+ * caller's cell order; the direction index is the one of snx_set_quadrature).
+ * Before any sweep the values are unspecified.  SNX_E_ARG for an angle or
+ * group out of range.  Asynchronous on `stream`. */
+snx_status snx_get_psi(snx_problem *p, int32_t angle, int32_t group, float *out, void *stream);
+
 /* Sweep schedule knobs: threads per task workgroup (64, 128, 192, 256 or
  * 512, at least G; a (cell, octant) task's (angle, group) solves run 64 per
  * wavefront, in rounds when there are more solves than threads), resident

@@ -61,6 +61,7 @@ def lib():
         L.snxo_set_hooks.argtypes = [vp, nullable_d, nullable_d]
         L.snxo_setup.argtypes = [vp]
         L.snxo_sweep.argtypes = [vp, nullable_d, _dp, nullable_d, nullable_d, nullable_d]
+        L.snxo_sweep_angle.argtypes = [vp, nullable_d, ct.c_int, ct.c_int, _dp]
         L.snxo_solve.argtypes = [vp, ct.c_double, ct.c_int, nullable_d, _dp,
                                  ct.POINTER(ct.c_int), ct.POINTER(ct.c_double), nullable_d]
         L.snxo_balance.argtypes = [vp, nullable_d, _dp, _dp, _dp]
@@ -170,6 +171,13 @@ class Oracle:
         if want_leak_ang:
             out["leak_ang"] = leak_ang
         return out
+
+    def sweep_angle(self, phi_in, n, g):
+        """psi[ncell][8] of angle n and group g alone, for the same phi_in as sweep()."""
+        psi = np.zeros((self.ncell, 8))
+        pin = None if phi_in is None else np.ascontiguousarray(phi_in, np.float64)
+        self._check(lib().snxo_sweep_angle(self.h, _ptr(pin), int(n), int(g), psi), "sweep_angle")
+        return psi
 
     def solve(self, tol, max_it, phi0=None, allow_noconv=False):
         phi = self.zeros_phi()

@@ -640,6 +640,34 @@ int snxo_sweep(snxo_problem *p, const double *phi_in, double *phi_out,
     return SNXO_OK;
 }
 
+/* The sweep of one (angle n, group g) alone: psi_out[ncell][8] receives that
+ * angle's and group's psi.  For a given phi_in the angles and groups of one
+ * source iteration are independent (Eq. 1 with the scattering source taken
+ * from phi_in), so this is the same loop as one (n, g) pass of snxo_sweep;
+ * it lets large problems be checked on sampled (angle, group) pairs. */
+int snxo_sweep_angle(snxo_problem *p, const double *phi_in, int n, int g, double *psi_out) {
+    if (!p || !p->ready) return fail(p, SNXO_E_STATE, "setup has not run");
+    if (!psi_out) return fail(p, SNXO_E_ARG, "psi_out is NULL");
+    int C = p->ncell, G = p->G, nang = p->nang, per = nang / 8;
+    if (n < 0 || n >= nang || g < 0 || g >= G) return fail(p, SNXO_E_ARG, "angle or group out of range");
+    int o = n / per;
+    for (int t = 0; t < C; ++t) {
+        int K = p->order[(long)o * C + t];
+        double qn[8], x[8];
+        if (p->ang_src) {
+            for (int j = 0; j < 8; ++j) qn[j] = p->ang_src[(((long)K * nang + n) * G + g) * 8 + j];
+        } else {
+            for (int j = 0; j < 8; ++j) {
+                double ph = phi_in ? phi_in[((long)K * G + g) * 8 + j] : 0.0;
+                qn[j] = (p->q[(long)K * G + g] + p->sigs[(long)K * G + g] * ph) / (4.0 * PI);
+            }
+        }
+        if (solve_local(p, K, n, g, qn, psi_out, x, NULL)) return fail(p, SNXO_E_MESH, "singular local system");
+        for (int j = 0; j < 8; ++j) psi_out[8L * K + j] = x[j];
+    }
+    return SNXO_OK;
+}
+
 /* Relative max-norm change ||phi_new - phi_old||_inf / ||phi_new||_inf. */
 static double rel_change(const double *a, const double *b, size_t n) {
     double num = 0.0, den = 0.0;

@@ -79,6 +79,10 @@ int  snxo_setup(snxo_problem *p);
 int  snxo_sweep(snxo_problem *p, const double *phi_in, double *phi_out,
                 double *psi_all, double *leak, double *leak_ang);
 
+/* The sweep of one (angle n, group g) alone (angles and groups of a source
+ * iteration are independent given phi_in): psi_out[ncell][8]. */
+int  snxo_sweep_angle(snxo_problem *p, const double *phi_in, int n, int g, double *psi_out);
+
 /* Source iteration from phi0 (NULL = zero) until the relative max-norm change
  * is <= tol or max_it sweeps.  hist[max_it] (nullable) receives each change. */
 int  snxo_solve(snxo_problem *p, double tol, int max_it, const double *phi0,

@@ -925,6 +925,16 @@ snx_status snx_get_levels(snx_problem *p, int32_t *level, int32_t *nlevels) {
     return SNX_OK;
 }
 
+snx_status snx_get_psi(snx_problem *p, int32_t angle, int32_t group, float *out, void *stream) {
+    if (!p || !out) return SNX_E_ARG;
+    if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
+    if (angle < 0 || angle >= p->nang || group < 0 || group >= p->G)
+        return fail(p, SNX_E_ARG, "angle or group out of range");
+    HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
+    HIPCHK(p, launch_gather_psi(p->hp.psi, p->C, p->A, p->G, angle, group, out, (hipStream_t)stream), "gather");
+    return SNX_OK;
+}
+
 snx_status snx_set_sweep_mode(snx_problem *p, int32_t mode) {
     if (!p) return SNX_E_ARG;
     if (mode != SNX_SWEEP_AMT && mode != SNX_SWEEP_BSP) return fail(p, SNX_E_ARG, "unknown sweep mode");

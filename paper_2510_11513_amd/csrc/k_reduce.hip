@@ -372,6 +372,17 @@ __global__ void k_copy_f32(float *dst, const float *src, size_t n, const int *st
         dst[i] = src[i];
 }
 
+// psi of one (angle, group) out of the sweep's hand-off array
+// [8 octants][C][8 dofs][A][G]: out[K][d], K in the caller's cell order.
+__global__ void k_gather_psi(const float *__restrict__ psi, int C, int A, int G, int o, int a, int g,
+                             float *__restrict__ out) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < 8LL * C;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long K = i >> 3, d = i & 7;
+        out[i] = psi[(((long long)o * C + K) * 8 + d) * A * G + (long long)a * G + g];
+    }
+}
+
 unsigned grid_for(size_t n, unsigned bs, unsigned cap = 65535u * 4u) {
     size_t g = (n + bs - 1) / bs;
     if (g < 1) g = 1;
@@ -426,6 +437,12 @@ hipError_t launch_fill_f32(float *p, size_t n, float v, hipStream_t s) {
 }
 hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_gather_psi(const float *psi, int C, int A, int G, int angle, int group, float *out,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_psi, dim3(grid_for(8 * (size_t)C, 256)), dim3(256), 0, s, psi, C, A, G, angle / A,
+                       angle % A, group, out);
     return hipGetLastError();
 }
 hipError_t launch_copy_f32(float *dst, const float *src, size_t n, const int *stop_flag, hipStream_t s) {

@@ -142,6 +142,7 @@ size_t partial_blocks(int C, int G);
 hipError_t launch_fill_f32(float *p, size_t n, float v, hipStream_t s);
 hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s);
 hipError_t launch_copy_f32(float *dst, const float *src, size_t n, const int *stop_flag, hipStream_t s);
+hipError_t launch_gather_psi(const float *psi, int C, int A, int G, int angle, int group, float *out, hipStream_t s);
 hipError_t launch_iter_init(IterCtl *ic, int *stop_flag, int max_it, double tol, hipStream_t s);
 // Batched forms over the problems of a schedule: per-problem stop flags and
 // iteration records; blk_base[p] is the first block of problem p (256 (cell,

@@ -28,7 +28,8 @@ EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_s
            "snx_batch_solve", "snx_batch_profile_sweep", "snx_batch_stats", "snx_gnn_create", "snx_gnn_destroy",
            "snx_gnn_last_error", "snx_gnn_num_params", "snx_gnn_get_params", "snx_gnn_set_params", "snx_gnn_save",
            "snx_gnn_load", "snx_gnn_features", "snx_gnn_targets", "snx_gnn_forward", "snx_gnn_grad",
-           "snx_gnn_train_step", "snx_gnn_predict", "snx_set_sweep_mode", "snx_batch_set_sweep_mode"]
+           "snx_gnn_train_step", "snx_gnn_predict", "snx_set_sweep_mode", "snx_batch_set_sweep_mode",
+           "snx_get_psi"]
 _NO_STATUS = ("snx_destroy", "snx_last_error", "snx_batch_destroy", "snx_batch_last_error", "snx_gnn_destroy",
               "snx_gnn_last_error")
 
@@ -77,6 +78,7 @@ def load(path: str = LIB_PATH):
     L.snx_balance.argtypes = [_vp, _vp, _vp, _dp, _vp]
     L.snx_integrated_flux.argtypes = [_vp, _vp, _dp, _vp]
     L.snx_get_levels.argtypes = [_vp, _vp, _vp]
+    L.snx_get_psi.argtypes = [_vp, ct.c_int32, ct.c_int32, _vp, _vp]
     L.snx_set_schedule.argtypes = [_vp, ct.c_int32, ct.c_int32, ct.c_int32]
     L.snx_set_sweep_mode.argtypes = [_vp, ct.c_int32]
     L.snx_batch_set_sweep_mode.argtypes = [_vp, ct.c_int32]
@@ -261,6 +263,13 @@ class Problem:
         self._check(load().snx_get_levels(self.h, lev.ctypes.data_as(ct.c_void_p), nl.ctypes.data_as(ct.c_void_p)),
                     "get_levels")
         return lev, nl
+
+    def psi(self, angle: int, group: int, stream=None):
+        """psi[ncell][8] (device, FP32) of one direction and group from the last sweep."""
+        import torch
+        out = torch.empty((self.ncell, 8), dtype=torch.float32, device=f"cuda:{self.device}")
+        self._check(load().snx_get_psi(self.h, int(angle), int(group), _ptr(out), _stream(stream)), "get_psi")
+        return out
 
     def set_schedule(self, threads: int = 0, wg_per_cu: int = 0, chunk: int = 0):
         self._check(load().snx_set_schedule(self.h, threads, wg_per_cu, chunk), "set_schedule")

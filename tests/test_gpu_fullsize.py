@@ -1,0 +1,160 @@
+"""The workloads at their full sizes, in the launch configuration the benchmark
+uses, against the FP64 oracle (GPU).
+
+* 32^3 / 96 angles / 16 groups (the benchmark workload): every scalar-flux
+  value of one sweep, plus the angular flux of sampled (angle, group) pairs.
+* 64^3 / 256 angles / 64 groups: the angular flux of sampled (angle, group)
+  pairs.  For a given input flux the angles and groups of one source iteration
+  are independent, so the oracle sweeps just those pairs (a full FP64 sweep of
+  4.3e9 solves would take minutes).
+* 64 uneven problems in one batched launch: the full scalar flux of the
+  smallest problems and sampled angular fluxes of the largest.
+* 32^3 high-scattering instance solved to 1e-6 from the learned start and
+  from zero: each converged flux must be a fixed point of the oracle's sweep
+  (one FP64 sweep from it changes it by no more than the iteration tolerance
+  and FP32 round-off allow).
+
+Tolerance: 1e-5 relative (max |gpu - oracle| / max |oracle|) per group for the
+scalar flux and per (angle, group) for the angular flux.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_11513_amd import inputs
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TUNE_CACHE = os.path.join(ROOT, "paper_2510_11513_amd", "tuning", "mi355x.jsonl")
+WEIGHTS = os.path.join(ROOT, "paper_2510_11513_amd", "weights", "gnn_l4_h64.bin")
+
+
+def _phi_in(prob, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 2.0, (prob.mesh.ncell, prob.mat.ngroup, 8)).astype(np.float32)
+
+
+def _psi_rel_err(got, ref):
+    return np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300)
+
+
+def _sampled_pairs(nang, G, count, seed):
+    """(angle, group) pairs spread over the octants and groups."""
+    rng = np.random.default_rng(seed)
+    per = nang // 8
+    octs = rng.permutation(8)[:count]
+    return [(int(o * per + rng.integers(per)), int(rng.integers(G))) for o in octs]
+
+
+def _check_psi_samples(p, o, phi64, pairs, label):
+    for n, g in pairs:
+        got = p.psi(n, g).cpu().numpy().astype(np.float64)
+        ref = o.sweep_angle(phi64, n, g)
+        err = _psi_rel_err(got, ref)
+        print(f"[case] {label} psi angle={n} group={g} rel err {err:.2e}", flush=True)
+        assert err <= TOL, (label, n, g, err)
+
+
+def test_bench_workload_full_size_parity():
+    import torch
+    from paper_2510_11513_amd import snx
+    prob = inputs.config_problem(2)
+    print(f"[case] full size 32^3: C={prob.mesh.ncell} nang={prob.nang} G={prob.mat.ngroup}", flush=True)
+    p = snx.Problem.from_problem(prob)
+    p.tune(TUNE_CACHE)                          # the benchmark's schedule (a cache hit)
+    phi32 = _phi_in(prob, 11)
+    out = p.sweep(torch.from_numpy(phi32).cuda())
+    torch.cuda.synchronize()
+    st = p.sweep_stats()
+    assert st["abort"] == 0 and st["tasks"] == 8 * prob.mesh.ncell, st
+    print(f"[case] schedule threads={st['threads']} grid={st['grid']}", flush=True)
+    o = oracle.Oracle.from_problem(prob)
+    phi64 = phi32.astype(np.float64)
+    ref = o.sweep(phi64)["phi"]
+    err = H.rel_err_per_group(out.cpu().numpy().astype(np.float64), ref)
+    print(f"[case] full size 32^3 phi max rel err {err.max():.2e}", flush=True)
+    assert err.max() <= TOL, err
+    _check_psi_samples(p, o, phi64, _sampled_pairs(prob.nang, prob.mat.ngroup, 4, 12), "32^3")
+    p.close()
+
+
+def test_large_problem_full_size_sampled_parity():
+    import torch
+    from paper_2510_11513_amd import snx
+    prob = inputs.config_problem(3)
+    print(f"[case] full size 64^3: C={prob.mesh.ncell} nang={prob.nang} G={prob.mat.ngroup}", flush=True)
+    p = snx.Problem.from_problem(prob, setup=False)
+    p.set_schedule(threads=256)
+    p.setup()
+    phi32 = _phi_in(prob, 21)
+    out = p.sweep(torch.from_numpy(phi32).cuda())
+    torch.cuda.synchronize()
+    st = p.sweep_stats()
+    assert st["abort"] == 0 and st["tasks"] == 8 * prob.mesh.ncell, st
+    assert bool(torch.isfinite(out).all())
+    del out
+    o = oracle.Oracle.from_problem(prob)
+    _check_psi_samples(p, o, phi32.astype(np.float64), _sampled_pairs(prob.nang, prob.mat.ngroup, 4, 22), "64^3")
+    p.close()
+
+
+def test_batch_full_size_sampled_parity():
+    import torch
+    from paper_2510_11513_amd import snx
+    probs = inputs.batch_problems(64)
+    print(f"[case] full batch: {len(probs)} problems, {sum(pr.mesh.ncell for pr in probs)} cells", flush=True)
+    gp = [snx.Problem.from_problem(pr) for pr in probs]
+    batch = snx.Batch(gp)
+    batch.set_schedule(threads=192)
+    phis = [_phi_in(pr, 100 + i) for i, pr in enumerate(probs)]
+    outs = batch.sweep([torch.from_numpy(x).cuda() for x in phis])
+    torch.cuda.synchronize()
+    st = batch.stats()
+    assert st["abort"] == 0 and st["tasks"] == sum(8 * pr.mesh.ncell for pr in probs), st
+    order = sorted(range(len(probs)), key=lambda i: probs[i].mesh.ncell * probs[i].nang * probs[i].mat.ngroup)
+    for i in order[:2]:                          # the smallest: every scalar-flux value
+        pr = probs[i]
+        ref = oracle.Oracle.from_problem(pr).sweep(phis[i].astype(np.float64))["phi"]
+        err = H.rel_err_per_group(outs[i].cpu().numpy().astype(np.float64), ref)
+        print(f"[case] batch problem {i} (C={pr.mesh.ncell} nang={pr.nang} G={pr.mat.ngroup}) "
+              f"phi max rel err {err.max():.2e}", flush=True)
+        assert err.max() <= TOL, (i, err)
+    for i in order[-2:]:                         # the largest: sampled angular fluxes
+        pr = probs[i]
+        o = oracle.Oracle.from_problem(pr)
+        _check_psi_samples(gp[i], o, phis[i].astype(np.float64),
+                           _sampled_pairs(pr.nang, pr.mat.ngroup, 3, 30 + i), f"batch problem {i}")
+    batch.close()
+    for p in gp:
+        p.close()
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained parameter file")
+def test_learned_start_full_size_is_an_oracle_fixed_point():
+    from paper_2510_11513_amd import learned, snx
+    pr = inputs.config_problem(learned.WORKLOAD, index=7)   # a held-out instance
+    print(f"[case] learned start 32^3 high scattering: C={pr.mesh.ncell} nang={pr.nang} G={pr.mat.ngroup}",
+          flush=True)
+    p = snx.Problem.from_problem(pr)
+    net = snx.Gnn(0, 4)
+    net.load_file(WEIGHTS)
+    phi_l, il = p.solve(learned.TOL, 5000, phi0=net.predict(p))
+    phi_z, iz = p.solve(learned.TOL, 5000)
+    assert il["status"] == 0 and iz["status"] == 0, (il, iz)
+    print(f"[case] iterations learned {il['iterations']} zero {iz['iterations']}", flush=True)
+    o = oracle.Oracle.from_problem(pr)
+    c_max = float((pr.mat.sigma_s / pr.mat.sigma_t).max())
+    for name, phi in (("learned", phi_l), ("zero", phi_z)):
+        x = phi.cpu().numpy().astype(np.float64)
+        y = o.sweep(x)["phi"]
+        err = H.rel_err_per_group(x, y)
+        print(f"[case] {name} start: oracle sweep of the converged flux changes it by {err.max():.2e}", flush=True)
+        assert err.max() <= TOL, (name, err)
+    diff = H.rel_err_per_group(phi_l.cpu().numpy().astype(np.float64), phi_z.cpu().numpy().astype(np.float64))
+    # both are within (residual)/(1 - c) of the fixed point
+    assert diff.max() <= 2 * learned.TOL / (1.0 - c_max) + TOL, diff
+    p.close()

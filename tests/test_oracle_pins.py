@@ -267,6 +267,9 @@ def test_sweep_equals_dense_solve_per_angle(n):
             rhs += H.boundary_rhs(g, d, om, n_ang, om.shape[0], psib[gg])
             x = np.linalg.solve(A, rhs).reshape(m.ncell, 8)
             assert np.abs(x - r["psi"][n_ang, :, gg]).max() < 1e-12 * max(1, np.abs(x).max())
+            # the single-(angle, group) sweep used to check large problems on samples
+            xa = o.sweep_angle(phi_in, n_ang, gg)
+            assert np.abs(x - xa).max() < 1e-12 * max(1, np.abs(x).max())
 
 
 def test_full_system_with_scattering_equals_converged_iteration():
