@@ -30,6 +30,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-angle-group solves/s per sweep; time-to-1e-6 learned vs plain start"
 HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 78.6      # MI355X, FP32 vector without packed instructions
+
+# The paper's run-time table for its own shape (16^3 elements, 128 angles, 16
+# groups, 25 sweeps): seconds on whole CPU nodes, for context only.
+PAPER_SHAPE_CPU_S = {"AMT, AMD EPYC 9354 2x32 cores": 1.85, "AMT, Intel Xeon Gold 6430 2x32 cores": 1.99,
+                     "AMT, NVIDIA Grace 2x72 cores": 1.09, "BSP, NVIDIA Grace 2x72 cores": 1.75}
 
 WORKLOADS = {
     "cfg2": (2, "32^3 jittered hex (32768 cells), 96 angles (3x4 product), 16 groups, two-material 4^3 blocks"),
@@ -49,6 +55,36 @@ def bytes_per_task(n: int, A: int, A_o: int, G: int) -> float:
     A_o * G solves.
     """
     return 32.0 + 48.0 * (n - 1) / n + 140.0 / A + 120.0 / (A_o * G)
+
+
+def flops_per_task(G: int) -> float:
+    """Algorithmic FLOP per solve (an FMA counts two): A = B + sigma_t M (64 FMA),
+    the inflow of three faces (48 FMA), unpivoted LU with forward and back
+    substitution (200 FMA, 8 reciprocals, 36 multiplies), and the per-angle
+    operator B = Omega.S - Omega.F_in (336 FMA per (cell, angle)) over G groups."""
+    return 2.0 * (64 + 48 + 200) + 8 + 36 + 2.0 * 336 / G
+
+
+def paper_shape(steps: int = 25):
+    """The paper's timing shape (16^3, 128 angles, 16 groups): 25 graph-captured sweeps."""
+    import torch
+    from paper_2510_11513_amd import inputs, snx
+    prob = inputs.config_problem(0)
+    p = snx.Problem.from_problem(prob)
+    p.tune(os.path.join(ROOT, "paper_2510_11513_amd", "tuning", "mi355x.jsonl"))
+    phi = p.empty_phi()
+    p.set_schedule(chunk=steps)
+    p.solve(0.0, steps, phi=phi, allow_noconv=True)            # warm-up replay
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.solve(0.0, steps, phi=phi, allow_noconv=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    solves = prob.mesh.ncell * prob.nang * prob.mat.ngroup * steps
+    p.close()
+    return {"workload": f"16^3 jittered hex, 128 angles, 16 groups, {steps} source iterations", "s": round(dt, 5),
+            "solves_per_s": solves / dt,
+            "paper_cpu_s_context": PAPER_SHAPE_CPU_S}
 
 
 def kernel_hash() -> str:
@@ -132,6 +168,7 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=4)
     ap.add_argument("--learned", type=int, default=4,
                     help="held-out high-scattering instances for the learned-start comparison (0 = skip)")
+    ap.add_argument("--paper-shape", type=int, default=1, help="also time the paper's 25-sweep 16^3 shape (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -214,6 +251,13 @@ def main():
     p.set_sweep_mode(snx.SWEEP_AMT)
     out["bsp_comparator"] = {"sweep_ms": round(ms_bsp, 4), "amt_sweep_ms": round(ms_sweep, 4),
                              "bsp_over_amt": round(ms_bsp / ms_sweep, 3)}
+    # the other candidate bound: algorithmic FP32 arithmetic over the same kernel time
+    fpt = flops_per_task(G)
+    tflops = fpt * solves_per_step / (ms_sweep * 1e-3) / 1e12
+    out["valu"] = {"achieved": round(tflops, 2), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": round(tflops / FP32_VALU_PEAK_TFLOPS, 4), "flops_per_solve": round(fpt, 1)}
+    if args.paper_shape:
+        out["paper_shape"] = paper_shape()
     if args.learned > 0:
         print("[bench] learned vs zero start", file=sys.stderr, flush=True)
         out["learned"] = learned_start(args.learned)
