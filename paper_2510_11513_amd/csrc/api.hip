@@ -834,7 +834,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     for (int o = 0; o < 8; ++o) p->maxin = std::max(p->maxin, nlev[8 + o]);
 
     HIPCHK(p, launch_octant_operators(p->C, dS, dF, dmask, dT, s), "octant operators");
-    HIPCHK(p, launch_task_records(p->C, d_nbr, d_perm, dmask, drec, s), "task records");
+    HIPCHK(p, launch_task_records(p->C, d_nbr, d_perm, dmask, dindeg, drec, s), "task records");
 
     // level-0 tasks of every octant are the seeds of a sweep
     std::vector<int> seeds_host(8 * C);

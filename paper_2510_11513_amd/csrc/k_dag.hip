@@ -131,7 +131,8 @@ __global__ void k_octant_operators(int C, const float *__restrict__ S, const flo
 // downwind neighbours, so a task that continues with a downwind cell already
 // holds that cell's descriptor when it starts it.
 __global__ void k_task_records(int C, const int *__restrict__ nbr, const unsigned *__restrict__ perm,
-                               const unsigned char *__restrict__ inmask, int *__restrict__ rec) {
+                               const unsigned char *__restrict__ inmask, const int *__restrict__ indeg,
+                               int *__restrict__ rec) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;   // o * C + K
     if (t >= 8LL * C) return;
     const int o = (int)(t / C), K = (int)(t - (long long)o * C);
@@ -149,19 +150,23 @@ __global__ void k_task_records(int C, const int *__restrict__ nbr, const unsigne
     for (int f = 0; f < 6; ++f) {
         int *d = r + 16 + 13 * f;
         const int N = nbr[(size_t)K * 6 + f];
-        if (!((mask >> f) & 1) && N >= 0) desc(N, d);
-        else
+        if (!((mask >> f) & 1) && N >= 0) {
+            desc(N, d);
+            r[13] |= indeg[(size_t)o * C + N] << (3 * f);   // in-degree of the downwind cell (<= 6)
+        } else {
             for (int w = 0; w < 13; ++w) d[w] = 0;
+        }
     }
     r[94] = r[95] = 0;
 }
 
 }  // namespace
 
-hipError_t launch_task_records(int C, const int *nbr, const unsigned *perm, const unsigned char *inmask, int *rec,
-                               hipStream_t s) {
+hipError_t launch_task_records(int C, const int *nbr, const unsigned *perm, const unsigned char *inmask,
+                               const int *indeg, int *rec, hipStream_t s) {
     const long long n = 8LL * C;
-    hipLaunchKernelGGL(k_task_records, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, C, nbr, perm, inmask, rec);
+    hipLaunchKernelGGL(k_task_records, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, C, nbr, perm, inmask,
+                       indeg, rec);
     return hipGetLastError();
 }
 

@@ -387,6 +387,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         const int p = uni(find_problem(task_base, nprob, task));
         const DevProblem &P = probs[p];
         const int C = P.C, G = P.G, A = P.A;
+        const unsigned epoch_p = *gp(P.epoch);        // the problem's sweep count: counter targets are indeg x epoch
         const long long local = task - P.task_base;
         const int o = uni((int)(local & 7));                 // task = 8 * cell + octant
         const int K = uni((int)(local >> 3));
@@ -759,7 +760,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             if (N >= 0) {
                 const unsigned old = __hip_atomic_fetch_add(gp(P.cnt) + (size_t)o * C + N, 1u, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned target = (unsigned)gp(P.indeg)[(size_t)o * C + N] * *gp(P.epoch);
+                const unsigned target = (unsigned)((s_desc[13] >> (3 * f)) & 7) * epoch_p;
                 if (old + 1u == target) {
                     const int i = atomicAdd(&s_nready, 1);
                     s_ready[i] = P.task_base + 8LL * N + o;

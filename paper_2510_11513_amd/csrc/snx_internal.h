@@ -20,8 +20,10 @@ constexpr int kMaxXcc = 32;      // range of hardware XCC ids mapped to queues
 constexpr int kReduceItems = 4;  // (cell, group) items per thread of the batched reduction
 // Task record of one (octant, cell), 96 ints (24 int4): words 0..12 the cell's
 // descriptor (neighbour ids [6], node permutations [6], inflow mask of the
-// octant), 13..15 zero, then for each face f at 16 + 13 f the descriptor of the
-// neighbour across f when f is a downwind face (zero otherwise), 94..95 zero.
+// octant), word 13 the in-degree of the downwind neighbour across face f in
+// bits 3f..3f+2, 14..15 zero, then for each face f at 16 + 13 f the descriptor
+// of the neighbour across f when f is a downwind face (zero otherwise), 94..95
+// zero.
 constexpr int kRecWords = 96;
 // Revision of the sweep kernel's schedule behaviour: part of the autotuner's
 // cache key, raised when a kernel change can move the best schedule.
@@ -121,8 +123,8 @@ hipError_t launch_sweep_level(const DevProblem *probs, int nprob, const long lon
                               const long long *bsp_tasks, long long begin, long long end, const int *stops,
                               hipStream_t s);
 hipError_t launch_xcc_probe(int *out, int nblocks, hipStream_t s);
-hipError_t launch_task_records(int C, const int *nbr, const unsigned *perm, const unsigned char *inmask, int *rec,
-                               hipStream_t s);
+hipError_t launch_task_records(int C, const int *nbr, const unsigned *perm, const unsigned char *inmask,
+                               const int *indeg, int *rec, hipStream_t s);
 hipError_t launch_octant_operators(int C, const float *S, const float *F, const unsigned char *inmask, float *T,
                                    hipStream_t s);
 // Workgroup widths of the sweep kernel: 64, 128, 192, 256 or 512.
