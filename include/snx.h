@@ -184,8 +184,15 @@ snx_status snx_profile_sweep(snx_problem *p, int32_t nsweeps, const float *phi_i
  * resident workgroups of the sweep launch, tasks run by the workgroup that made
  * them ready, threads per workgroup, then shader-clock cycles summed over
  * workgroups spent waiting on the queue, staging cell data, building the
- * per-angle operators, solving, and publishing to downwind cells.  Synchronous. */
+ * per-angle operators, solving, and publishing to downwind cells (zero unless
+ * enabled by snx_set_sweep_stats).  Synchronous. */
 snx_status snx_sweep_stats(snx_problem *p, int64_t *out);
+
+/* Turns the per-phase cycle statistics of the dependency-driven sweep on
+ * (phases != 0) or off (the default: reading the shader clock at every phase
+ * of every task costs about 2 % of sweep time).  Counts of tasks, polls and
+ * continuations are always gathered. */
+snx_status snx_set_sweep_stats(snx_problem *p, int32_t phases);
 
 /* ------------------------------------------------------------------ batches
  * Many independent problems (uneven sizes, group and angle counts) share one
@@ -223,6 +230,8 @@ snx_status snx_batch_solve(snx_batch *b, double tol, int32_t max_it, const float
 snx_status snx_batch_profile_sweep(snx_batch *b, int32_t nsweeps, double *ms, void *stream);
 /* As snx_sweep_stats, for the most recent sweep of the batch. */
 snx_status snx_batch_stats(snx_batch *b, int64_t *out);
+/* As snx_set_sweep_stats, for the batch's sweeps. */
+snx_status snx_batch_set_sweep_stats(snx_batch *b, int32_t phases);
 
 
 /* ---- learned initial guess ------------------------------------------------

@@ -72,6 +72,7 @@ struct Sched {
     bool one = false;                        // every task is one round of lanes (maxAG <= threads)
     int threads = 256, wg_per_cu = 0, grid = 0, chunk = 8;
     int mode = SNX_SWEEP_AMT;                // SNX_SWEEP_AMT or SNX_SWEEP_BSP
+    bool phase_stats = false;                // gather the per-phase cycle statistics (snx_set_sweep_stats)
     long long *d_bsp_tasks = nullptr;        // tasks of every problem ordered by level (BSP comparator)
     std::vector<long long> bsp_off;          // [levels + 1] offsets into d_bsp_tasks
     unsigned long long watchdog = 0;
@@ -121,6 +122,7 @@ struct snx_problem {
     unsigned long long watchdog_ticks = 0;
     int threads = 0, wg_per_cu = 0, chunk = 8;     // requested sweep schedule (threads 0: automatic)
     int mode = SNX_SWEEP_AMT;
+    bool phase_stats = false;           // per-phase cycle statistics of the sweep (snx_set_sweep_stats)
     int nq = 1;                         // task queues = XCDs seen on the device
     int xcc_queue[kMaxXcc] = {0};       // home queue of each hardware XCC id
     Sched sched;                        // the problem's own schedule of one
@@ -328,8 +330,8 @@ snx_status enqueue_sweep(Sched &sc, const int *stops, hipStream_t s, hipEvent_t 
                                            stops, s), "sweep prologue");
     if (ev0) HIPCHK_E(sc.err, hipEventRecord(ev0, s), "event");
     HIPCHK_E(sc.err, launch_sweep_kernel(sc.d_probs, sc.nprob(), sc.d_base, sc.d_ctl, sc.d_queue, sc.threads, sc.one,
-                                         sc.grid,
-                                         sc.maxA, sc.maxG, sc.maxin, sc.watchdog, s), "sweep launch");
+                                         sc.grid, sc.maxA, sc.maxG, sc.maxin, sc.watchdog, sc.phase_stats, s),
+             "sweep launch");
     if (ev1) HIPCHK_E(sc.err, hipEventRecord(ev1, s), "event");
     return SNX_OK;
 }
@@ -851,6 +853,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     HIPCHK(p, hipStreamSynchronize(s), "setup");
     snx_status st = build_sched(p->sched, {p}, p->threads, p->wg_per_cu, p->chunk, s);
     p->sched.mode = p->mode;
+    p->sched.phase_stats = p->phase_stats;
     if (st) {
         std::string msg = p->sched.err;
         drop_device(p);
@@ -941,6 +944,16 @@ snx_status snx_set_sweep_mode(snx_problem *p, int32_t mode) {
     p->mode = mode;
     if (p->ready) {
         p->sched.mode = mode;
+        p->sched.drop_graphs();
+    }
+    return SNX_OK;
+}
+
+snx_status snx_set_sweep_stats(snx_problem *p, int32_t phases) {
+    if (!p) return SNX_E_ARG;
+    p->phase_stats = phases != 0;
+    if (p->ready) {
+        p->sched.phase_stats = p->phase_stats;
         p->sched.drop_graphs();
     }
     return SNX_OK;
@@ -1068,6 +1081,13 @@ snx_status snx_batch_set_sweep_mode(snx_batch *b, int32_t mode) {
     if (mode != SNX_SWEEP_AMT && mode != SNX_SWEEP_BSP) return fail_msg(b->sched.err, SNX_E_ARG, "unknown sweep mode");
     b->mode = mode;
     b->sched.mode = mode;
+    b->sched.drop_graphs();
+    return SNX_OK;
+}
+
+snx_status snx_batch_set_sweep_stats(snx_batch *b, int32_t phases) {
+    if (!b) return SNX_E_ARG;
+    b->sched.phase_stats = phases != 0;
     b->sched.drop_graphs();
     return SNX_OK;
 }

@@ -289,7 +289,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
     const DevProblem *__restrict__ probs, int nprob, const long long *__restrict__ task_base,
     SweepCtl *__restrict__ ctl, unsigned long long *__restrict__ queue, int maxA, int maxG, int maxin,
     unsigned long long watchdog, const long long *__restrict__ bsp_tasks, long long bsp_begin, long long bsp_end,
-    const int *__restrict__ stops) {
+    const int *__restrict__ stops, int phase_stats) {
     extern __shared__ __align__(16) float lds[];
     __shared__ long long s_task;
     __shared__ int s_q;
@@ -301,6 +301,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
     const unsigned epoch = ctl->epoch;
     const int nq = ctl->nq;
     const int tid = threadIdx.x;
+    const bool ph0 = phase_stats && tid == 0;   // thread 0 keeps the phase clock (optional: it costs issue slots)
     int q = ctl->xcc_queue[xcc_id()];       // home queue: the one of this XCD
 
     // Stage buffers (stage_floats each): cell data, task record (own and
@@ -322,8 +323,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
     float *sUp = s_up;
 
     // Workgroup statistics, kept in LDS and touched by thread 0 only: polls, tasks,
-    // continued tasks, tasks not yet added to the queue's done count, and the
-    // shader-clock cycles of the five phases of a task.
+    // continued tasks, tasks not yet added to the queue's done count, and (when
+    // phase_stats is set) the shader-clock cycles of the five phases of a task.
     __shared__ unsigned long long s_stat[4], s_ph[5], s_mark;
     if (tid == 0) {
         for (int i = 0; i < 4; ++i) s_stat[i] = 0;
@@ -354,7 +355,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
     int cface = -1, cbuf = 0;             // continuation: its face in the last task's record, and that record's buffer
     for (;;) {
         long long task = cont;
-        if (tid == 0) s_mark = clock64();
+        if (ph0) s_mark = clock64();
         if constexpr (BSP) {
             if (bsp_i >= bsp_end) break;
             task = bsp_tasks[bsp_i];
@@ -371,9 +372,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 s_task = pop_task(ctl, queue, q, nq, epoch, watchdog, polls);
                 s_stat[0] += polls;
                 s_q = q;
-                const unsigned long long t = clock64();
-                s_ph[0] += t - s_mark;
-                s_mark = t;
+                if (phase_stats) {
+                    const unsigned long long t = clock64();
+                    s_ph[0] += t - s_mark;
+                    s_mark = t;
+                }
             }
             lds_barrier();
             task = s_task;
@@ -516,7 +519,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         // their registers free while the operators are built
         if constexpr (!ONE)
             if (tid < AG) load_up(K, mask, nb, pm, tid, AG, psi_o, L);
-        if (tid == 0) { const unsigned long long t = clock64(); s_ph[1] += t - s_mark; s_mark = t; }
+        if (ph0) { const unsigned long long t = clock64(); s_ph[1] += t - s_mark; s_mark = t; }
 
         // ------------------------------------- per-angle operators B_n, C_n,f
         {   // Angles are dealt to waves (wave-uniform loop), entries to lanes: lane l
@@ -565,7 +568,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         // while the lanes solve (it is idle there when A*G <= NT - 64)
         if constexpr (ONE)
             if (tid == NT - 64) push_ready();
-        if (tid == 0) { const unsigned long long t = clock64(); s_ph[2] += t - s_mark; s_mark = t; }
+        if (ph0) { const unsigned long long t = clock64(); s_ph[2] += t - s_mark; s_mark = t; }
 
         // ------------------------------------------------ rounds of lanes
         int buf = 0;
@@ -734,7 +737,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             }
         }
 
-        if (tid == 0) { const unsigned long long t = clock64(); s_ph[3] += t - s_mark; s_mark = t; }
+        if (ph0) { const unsigned long long t = clock64(); s_ph[3] += t - s_mark; s_mark = t; }
         // Octant slot: the task's compensated partial sums.  Only the reduction
         // kernel reads them, so in the dependency-driven sweep they are written
         // after the downwind counters: the wait before the counters covers only ψ.
@@ -775,7 +778,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         cbuf = cur;
         cur ^= 1;
         write_slot();
-        if (tid == 0) s_ph[4] += clock64() - s_mark;
+        if (ph0) s_ph[4] += clock64() - s_mark;
         if (tid == 0) {
             ++s_stat[3];
             ++s_stat[1];
@@ -850,9 +853,9 @@ template <int NT, bool ONE, bool BSP>
 hipError_t launch_nt(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                      unsigned long long *queue, int maxA, int maxG, int maxin, int grid, size_t lds,
                      unsigned long long watchdog, const long long *bsp_tasks, long long b0, long long b1,
-                     const int *stops, hipStream_t s) {
+                     const int *stops, int phase_stats, hipStream_t s) {
     hipLaunchKernelGGL((k_sweep<NT, ONE, BSP>), dim3(grid), dim3(NT), lds, s, probs, nprob, task_base, ctl, queue,
-                       maxA, maxG, maxin, watchdog, bsp_tasks, b0, b1, stops);
+                       maxA, maxG, maxin, watchdog, bsp_tasks, b0, b1, stops, phase_stats);
     return hipGetLastError();
 }
 
@@ -899,13 +902,14 @@ hipError_t launch_xcc_probe(int *out, int nblocks, hipStream_t s) {
 
 hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                                unsigned long long *queue, int threads, bool one, int grid, int maxA, int maxG,
-                               int maxin, unsigned long long watchdog, hipStream_t s) {
+                               int maxin, unsigned long long watchdog, bool phase_stats, hipStream_t s) {
     const size_t lds = sweep_lds_bytes(threads, maxA, maxG, maxin, one);
+    const int ps = phase_stats ? 1 : 0;
 #define SNX_LAUNCH(NT)                                                                                             \
     return one ? launch_nt<NT, true, false>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds,      \
-                                            watchdog, nullptr, 0, 0, nullptr, s)                                   \
+                                            watchdog, nullptr, 0, 0, nullptr, ps, s)                               \
                : launch_nt<NT, false, false>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds,     \
-                                             watchdog, nullptr, 0, 0, nullptr, s)
+                                             watchdog, nullptr, 0, 0, nullptr, ps, s)
     switch (threads) {
         case 64: SNX_LAUNCH(64);
         case 128: SNX_LAUNCH(128);
@@ -927,9 +931,9 @@ hipError_t launch_sweep_level(const DevProblem *probs, int nprob, const long lon
     const int g = (int)std::min<long long>(grid, n);
 #define SNX_LAUNCH(NT)                                                                                             \
     return one ? launch_nt<NT, true, true>(probs, nprob, task_base, ctl, nullptr, maxA, maxG, maxin, g, lds, 0,     \
-                                           bsp_tasks, begin, end, stops, s)                                        \
+                                           bsp_tasks, begin, end, stops, 0, s)                                     \
                : launch_nt<NT, false, true>(probs, nprob, task_base, ctl, nullptr, maxA, maxG, maxin, g, lds, 0,    \
-                                            bsp_tasks, begin, end, stops, s)
+                                            bsp_tasks, begin, end, stops, 0, s)
     switch (threads) {
         case 64: SNX_LAUNCH(64);
         case 128: SNX_LAUNCH(128);

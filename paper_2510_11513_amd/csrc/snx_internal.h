@@ -116,7 +116,7 @@ hipError_t launch_sweep_prologue(SweepCtl *ctl, unsigned long long *queue, const
                                  const int *seeds, const int *seed_off, const int *stops, hipStream_t s);
 hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                                unsigned long long *queue, int threads, bool one, int grid, int maxA, int maxG, int maxin,
-                               unsigned long long watchdog, hipStream_t s);
+                               unsigned long long watchdog, bool phase_stats, hipStream_t s);
 // One level of the bulk-synchronous comparator: tasks bsp_tasks[begin, end).
 hipError_t launch_sweep_level(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                               int threads, bool one, int grid, int maxA, int maxG, int maxin,
