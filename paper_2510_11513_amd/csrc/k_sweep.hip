@@ -302,6 +302,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
     const int nq = ctl->nq;
     const int tid = threadIdx.x;
     const bool ph0 = phase_stats && tid == 0;   // thread 0 keeps the phase clock (optional: it costs issue slots)
+    // Per-(group, dof) work (partial sums, slots) starts at the second wave, so
+    // the first wave, which also publishes to the downwind counters, carries the
+    // least of it.
+    const int rt = tid >= 64 ? tid - 64 : tid + NT - 64;
     int q = ctl->xcc_queue[xcc_id()];       // home queue: the one of this XCD
 
     // Stage buffers (stage_floats each): cell data, task record (own and
@@ -500,7 +504,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             }
         }
         if (new_om && tid < A) reinterpret_cast<float4 *>(sOm)[tid] = om4;
-        for (int i = tid; i < G * 8; i += NT) { sRs[i] = 0.f; sRc[i] = 0.f; }
+        for (int i = rt; i < G * 8; i += NT) { sRs[i] = 0.f; sRc[i] = 0.f; }
         lds_barrier();                // the staged data come from LDS-destined loads of every wave
         if (tid == 0) s_nready = 0;   // after the barrier: every thread has read the last task's count
         if constexpr (ONE)
@@ -710,7 +714,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             // compensated accumulation in increasing angle order, one (group, dof) per reducer;
             // the other buffer takes the next round's values meanwhile
             const int hi = min(base + NT, AG);
-            for (int e = tid; e < G * 8; e += NT) {
+            for (int e = rt; e < G * 8; e += NT) {
                 const int g = e >> 3, d = e & 7;
                 float s = sRs[e], c = sRc[e];
                 const int q0 = ONE ? g : base + ((g - base % G) % G + G) % G;   // first lane of group g
@@ -743,7 +747,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         // after the downwind counters: the wait before the counters covers only ψ.
         const size_t sbase = ((size_t)o * C + K) * G * 8;
         auto write_slot = [&]() {
-            for (int e = tid; e < G * 8; e += NT) {
+            for (int e = rt; e < G * 8; e += NT) {
                 gp(P.slot)[sbase + e] = sRs[e];
                 gp(P.slotc)[sbase + e] = sRc[e];
             }
