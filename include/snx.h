@@ -246,12 +246,15 @@ snx_status snx_batch_set_sweep_stats(snx_batch *b, int32_t phases);
  * of the cells across K's faces.  With hidden width H = 64 and L layers:
  *   h0 = relu(x W_in + b_in), h_l = relu([h_{l-1}, mean_nbr h_{l-1}] W_l + b_l),
  *   z = h_L w_out + b_out,  z predicts y = log(mean of the 8 dofs of phi + 1e-4).
- * Parameters are one FP32 vector in the order W_in [8][H], b_in [H],
+ * Parameters are one FP32 vector in the order W_in [12][H], b_in [H],
  * (W_l [2H][H], b_l [H]) for l = 1..L, w_out [H], b_out [1], row-major.  The
  * layer products run in BF16 (weights and activations) with FP32 accumulation.
- * Node features x [C*G][8] FP32: log sigma_t, c = sigma_s/sigma_t, q,
- * log(q/sigma_a + 1e-2), (boundary faces)/3, log(sigma_t * volume^(1/3)),
- * log(max(1 - c, 1e-6)), 1.  nbr is [C][6] int32, -1 on the boundary.
+ * Node features x [C*G][12] FP32: log sigma_t, c = sigma_s/sigma_t, q,
+ * log(q/sigma_a + 1e-2), (boundary faces)/3, log(sigma_t * h),
+ * log(max(1 - c, 1e-6)), the cell centroid's distance to the nearest side of
+ * the mesh's bounding box and its coordinates u in [0,1]^3 relative to the box,
+ * log(max(sigma_a * h, 1e-12)), with h = volume^(1/3).  nbr is [C][6] int32,
+ * -1 on the boundary.
  * The loss is the mean over nodes of (z - y)^2; training is AdamW
  * (beta1 0.9, beta2 0.999, eps 1e-8, decoupled weight decay).  Gradients are
  * reduced in a fixed order, so training is deterministic.  Every call is
@@ -266,7 +269,7 @@ snx_status snx_gnn_create(snx_gnn **out, int32_t device, int32_t hidden, int32_t
 /* Free the network and its device memory.  NULL is ignored. */
 void snx_gnn_destroy(snx_gnn *g);
 const char *snx_gnn_last_error(const snx_gnn *g);
-/* Number of FP32 parameters (33665 for 4 layers). */
+/* Number of FP32 parameters (33921 for 4 layers). */
 snx_status snx_gnn_num_params(const snx_gnn *g, int64_t *n);
 /* Copy the parameters to / from a host array of snx_gnn_num_params floats.
  * Setting them also resets the optimiser state.  Synchronous. */
@@ -277,7 +280,7 @@ snx_status snx_gnn_set_params(snx_gnn *g, const float *host);
  * SNX_E_ARG.  Synchronous. */
 snx_status snx_gnn_save(snx_gnn *g, const char *path);
 snx_status snx_gnn_load(snx_gnn *g, const char *path);
-/* Node features of a set-up problem into device x [C*G][8], and its face
+/* Node features of a set-up problem into device x [C*G][12], and its face
  * adjacency into device nbr [C][6] (nbr may be NULL).  SNX_E_STATE if p is
  * not set up. */
 snx_status snx_gnn_features(snx_problem *p, float *x, int32_t *nbr, void *stream);

@@ -5,7 +5,7 @@ converged cell-average scalar flux; the prediction seeds source iteration.
 Nodes of one group are joined across shared faces (the mesh's face adjacency;
 groups are independent, so the graph is one copy per group).
 
-    h0   = relu(x W_in + b_in)                     x: 8 node features
+    h0   = relu(x W_in + b_in)                     x: 12 node features
     m_l  = mean of h_{l-1} over face neighbours    (0 for a cell with none)
     h_l  = relu([h_{l-1}, m_l] W_l + b_l)          W_l: (2H) x H, l = 1..L
     z    = h_L w_out + b_out                       predicted log(phi_avg + delta)
@@ -20,7 +20,7 @@ from __future__ import annotations
 import numpy as np
 
 DELTA = 1e-4
-NFEAT = 8
+NFEAT = 12
 
 
 def param_shapes(hidden: int = 64, layers: int = 4):
@@ -45,17 +45,25 @@ def pack(params, hidden=64, layers=4):
     return np.concatenate([params[name].ravel() for name, _ in param_shapes(hidden, layers)])
 
 
-def features(sigma_t, sigma_s, q, volume, n_boundary_faces):
-    """Node features [C, G, 8] of a problem (per-cell volume and boundary-face count)."""
+def features(sigma_t, sigma_s, q, volume, n_boundary_faces, centroid, lo, hi):
+    """Node features [C, G, 12] of a problem: per-cell volume, boundary-face count,
+    centroid [C, 3] and the mesh's bounding box lo, hi [3]."""
     st = np.asarray(sigma_t, np.float64)
     ss = np.asarray(sigma_s, np.float64)
     qq = np.asarray(q, np.float64)
     c = ss / st
     sa = st - ss
-    vol = np.asarray(volume, np.float64)[:, None] * np.ones_like(st)
-    nb = np.asarray(n_boundary_faces, np.float64)[:, None] * np.ones_like(st)
-    x = np.stack([np.log(st), c, qq, np.log(qq / sa + 1e-2), nb / 3.0, np.log(st * np.cbrt(vol)),
-                  np.log(np.maximum(1.0 - c, 1e-6)), np.ones_like(st)], axis=-1)
+    one = np.ones_like(st)
+    vol = np.asarray(volume, np.float64)[:, None] * one
+    nb = np.asarray(n_boundary_faces, np.float64)[:, None] * one
+    u = (np.asarray(centroid, np.float64) - np.asarray(lo, np.float64)) / (np.asarray(hi, np.float64)
+                                                                          - np.asarray(lo, np.float64))
+    db = np.minimum(u, 1.0 - u).min(axis=1)
+    h = np.cbrt(vol)
+    x = np.stack([np.log(st), c, qq, np.log(qq / sa + 1e-2), nb / 3.0, np.log(st * h),
+                  np.log(np.maximum(1.0 - c, 1e-6)), db[:, None] * one,
+                  u[:, 0, None] * one, u[:, 1, None] * one, u[:, 2, None] * one,
+                  np.log(np.maximum(sa * h, 1e-12))], axis=-1)
     return x
 
 

@@ -849,6 +849,16 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     hp.M = dM; hp.S = dS; hp.T = dT; hp.F = dF; hp.nbr = d_nbr; hp.perm = d_perm; hp.inmask = dmask; hp.indeg = dindeg;
     hp.sigt = dsigt; hp.sigs = dsigs; hp.q = dq; hp.r = dr; hp.omega = dom; hp.w = dw; hp.psib = dpsib;
     hp.psi = dpsi; hp.slot = dslot; hp.slotc = dslotc; hp.cnt = dcnt; hp.rec = drec;
+    hp.xyz = d_xyz; hp.cv = d_cv;
+    for (int a = 0; a < 3; ++a) {
+        double lo = p->xyz[a], hi = p->xyz[a];
+        for (int v = 1; v < p->nvert; ++v) {
+            lo = std::min(lo, p->xyz[3 * v + a]);
+            hi = std::max(hi, p->xyz[3 * v + a]);
+        }
+        hp.lo[a] = (float)lo;
+        hp.hi[a] = (float)hi;
+    }
     HIPCHK(p, launch_fill_f32(dr, C * G * 8, 0.f, s), "fill");
     HIPCHK(p, hipStreamSynchronize(s), "setup");
     snx_status st = build_sched(p->sched, {p}, p->threads, p->wg_per_cu, p->chunk, s);

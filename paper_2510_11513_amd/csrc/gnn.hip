@@ -15,7 +15,7 @@ using namespace snx;
 namespace {
 
 constexpr int H = 64;
-constexpr int NFEAT = 8;
+constexpr int NFEAT = kGnnFeatures;
 
 thread_local std::string g_gnn_error;
 

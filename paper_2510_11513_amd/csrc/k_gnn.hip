@@ -230,14 +230,14 @@ __global__ __launch_bounds__(256) void k_input_fwd(const float *__restrict__ x, 
     const long long v = t >> 2;
     if (v >= Nn) return;
     const int c0 = (int)(t & 3) * 16;
-    float xv[8];
+    float xv[kGnnFeatures];
 #pragma unroll
-    for (int f = 0; f < 8; ++f) xv[f] = x[v * 8 + f];
+    for (int f = 0; f < kGnnFeatures; ++f) xv[f] = x[v * kGnnFeatures + f];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         float s = bin[c0 + i];
 #pragma unroll
-        for (int f = 0; f < 8; ++f) s = fmaf(xv[f], Win[f * H + c0 + i], s);
+        for (int f = 0; f < kGnnFeatures; ++f) s = fmaf(xv[f], Win[f * H + c0 + i], s);
         h0[v * H + c0 + i] = (bf16)fmaxf(s, 0.f);
     }
 }
@@ -248,22 +248,25 @@ __global__ __launch_bounds__(256) void k_input_bwd(const float *__restrict__ x, 
                                                    const float *__restrict__ dH0, long long Nn,
                                                    float *__restrict__ dWpart, float *__restrict__ dbpart) {
     const int j = threadIdx.x & 63, lane = threadIdx.x >> 6;
-    float aw[8] = {0, 0, 0, 0, 0, 0, 0, 0}, ab = 0.f;
+    constexpr int NF = kGnnFeatures;
+    float aw[NF], ab = 0.f;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) aw[f] = 0.f;
     for (long long v = (long long)blockIdx.x * 4 + lane; v < Nn; v += (long long)gridDim.x * 4) {
         const float d = (float)h0[v * H + j] > 0.f ? dH0[v * H + j] : 0.f;
 #pragma unroll
-        for (int f = 0; f < 8; ++f) aw[f] = fmaf(x[v * 8 + f], d, aw[f]);
+        for (int f = 0; f < NF; ++f) aw[f] = fmaf(x[v * NF + f], d, aw[f]);
         ab += d;
     }
-    __shared__ float s[4][9][H];
+    __shared__ float s[4][NF + 1][H];
 #pragma unroll
-    for (int f = 0; f < 8; ++f) s[lane][f][j] = aw[f];
-    s[lane][8][j] = ab;
+    for (int f = 0; f < NF; ++f) s[lane][f][j] = aw[f];
+    s[lane][NF][j] = ab;
     __syncthreads();
     if (lane == 0) {
-        for (int f = 0; f < 9; ++f) {
+        for (int f = 0; f <= NF; ++f) {
             const float tot = ((s[0][f][j] + s[1][f][j]) + s[2][f][j]) + s[3][f][j];
-            if (f < 8) dWpart[(size_t)blockIdx.x * 8 * H + f * H + j] = tot;
+            if (f < NF) dWpart[(size_t)blockIdx.x * NF * H + f * H + j] = tot;
             else dbpart[(size_t)blockIdx.x * H + j] = tot;
         }
     }
@@ -346,10 +349,14 @@ __global__ void k_to_bf16(const float *__restrict__ W, bf16 *__restrict__ Wb, bf
     Wt[c * 2 * H + r] = q;
 }
 
-// Node features of (cell, group) pairs from a problem's device tables.
+// Node features of (cell, group) pairs from a problem's device tables: the
+// cell's cross sections and source, its size in mean free paths, its boundary
+// faces and its position in the mesh's bounding box (u in [0,1]^3 and the
+// distance to the nearest side of the box).
 __global__ void k_features(const float *__restrict__ sigt, const float *__restrict__ sigs, const float *__restrict__ q,
-                           const float *__restrict__ M, const int *__restrict__ nbr, int C, int G,
-                           float *__restrict__ x, int *__restrict__ nbr_out) {
+                           const float *__restrict__ M, const int *__restrict__ nbr, const double *__restrict__ xyz,
+                           const int *__restrict__ cv, float3 lo, float3 hi, int C, int G, float *__restrict__ x,
+                           int *__restrict__ nbr_out) {
     const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= (long long)C * G) return;
     const long long K = v / G;
@@ -357,17 +364,31 @@ __global__ void k_features(const float *__restrict__ sigt, const float *__restri
     for (int e = 0; e < 64; ++e) vol += M[K * 64 + e];
     int nb = 0;
     for (int f = 0; f < 6; ++f) nb += nbr[K * 6 + f] < 0;
+    double cx = 0.0, cy = 0.0, cz = 0.0;
+    for (int j = 0; j < 8; ++j) {
+        const long long n = cv[K * 8 + j];
+        cx += xyz[3 * n]; cy += xyz[3 * n + 1]; cz += xyz[3 * n + 2];
+    }
+    const float ux = (float)((cx * 0.125 - lo.x) / (hi.x - lo.x));
+    const float uy = (float)((cy * 0.125 - lo.y) / (hi.y - lo.y));
+    const float uz = (float)((cz * 0.125 - lo.z) / (hi.z - lo.z));
+    const float db = fminf(fminf(fminf(ux, 1.f - ux), fminf(uy, 1.f - uy)), fminf(uz, 1.f - uz));
     const float st = sigt[v], ss = sigs[v], qq = q[v];
     const float c = ss / st, sa = st - ss;
-    float *o = x + v * 8;
+    const float h = cbrtf(vol);
+    float *o = x + v * kGnnFeatures;
     o[0] = logf(st);
     o[1] = c;
     o[2] = qq;
     o[3] = logf(qq / sa + 1e-2f);
     o[4] = (float)nb / 3.f;
-    o[5] = logf(st * cbrtf(vol));
+    o[5] = logf(st * h);
     o[6] = logf(fmaxf(1.f - c, 1e-6f));
-    o[7] = 1.f;
+    o[7] = db;
+    o[8] = ux;
+    o[9] = uy;
+    o[10] = uz;
+    o[11] = logf(fmaxf(sa * h, 1e-12f));
     if (nbr_out && (v % G) == 0)
         for (int f = 0; f < 6; ++f) nbr_out[K * 6 + f] = nbr[K * 6 + f];
 }
@@ -461,7 +482,8 @@ hipError_t gnn_to_bf16(const float *W, void *Wb, void *Wt, hipStream_t s) {
 
 hipError_t gnn_features(const DevProblem &P, float *x, int *nbr_out, hipStream_t s) {
     hipLaunchKernelGGL(k_features, dim3(blocks((long long)P.C * P.G, 256)), dim3(256), 0, s, P.sigt, P.sigs, P.q, P.M,
-                       P.nbr, P.C, P.G, x, nbr_out);
+                       P.nbr, P.xyz, P.cv, make_float3(P.lo[0], P.lo[1], P.lo[2]),
+                       make_float3(P.hi[0], P.hi[1], P.hi[2]), P.C, P.G, x, nbr_out);
     return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@ constexpr float kInv4Pi = 0.0795774715459476679f;
 constexpr int kMaxQueues = 16;   // task queues of a sweep (one per XCD of the device)
 constexpr int kMaxXcc = 32;      // range of hardware XCC ids mapped to queues
 constexpr int kReduceItems = 4;  // (cell, group) items per thread of the batched reduction
+constexpr int kGnnFeatures = 12; // node features of the learned initial guess (see snx_gnn_features)
 // Task record of one (octant, cell), 96 ints (24 int4): words 0..12 the cell's
 // descriptor (neighbour ids [6], node permutations [6], inflow mask of the
 // octant), word 13 the in-degree of the downwind neighbour across face f in
@@ -92,6 +93,9 @@ struct DevProblem {
     float *slotc;                // [8][C][G][8]  their compensation terms
     unsigned *cnt;               // [8][C]        dependency counters (count up across sweeps)
     const int *rec;              // [8][C][kRecWords] task records (see kRecWords)
+    const double *xyz;           // [nvert][3]    vertex coordinates (the network's cell positions)
+    const int *cv;               // [C][8]        cell vertices
+    float lo[3], hi[3];          // bounding box of the mesh
 };
 
 // Iteration record of snx_solve's device-side control.

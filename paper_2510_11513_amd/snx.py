@@ -19,6 +19,7 @@ STATUS = {0: "SNX_OK", -1: "SNX_E_ARG", -2: "SNX_E_STATE", -3: "SNX_E_MESH", -4:
           -5: "SNX_E_DEVICE", -6: "SNX_E_OOM", -7: "SNX_E_NOCONV"}
 SNX_E_NOCONV = -7
 SWEEP_AMT, SWEEP_BSP = 0, 1
+NFEAT = 12          # node features of the learned initial guess (snx_gnn_features)
 
 EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_set_quadrature",
            "snx_quadrature_product", "snx_set_materials", "snx_set_boundary", "snx_setup", "snx_sweep",
@@ -396,7 +397,7 @@ class Batch:
 class Gnn:
     """The message-passing network of the learned initial guess, on one GPU.
 
-    Device inputs are torch tensors: features x [C*G, 8] float32, adjacency
+    Device inputs are torch tensors: features x [C*G, NFEAT] float32, adjacency
     nbr [C, 6] int32, targets y [C*G] float32.
     """
 
@@ -448,10 +449,10 @@ class Gnn:
 
     @staticmethod
     def features(problem: "Problem", stream=None):
-        """(x [C*G, 8], nbr [C, 6]) of a set-up problem, on its device."""
+        """(x [C*G, NFEAT], nbr [C, 6]) of a set-up problem, on its device."""
         import torch
         dev = torch.device("cuda", problem.device)
-        x = torch.empty((problem.ncell * problem.G, 8), dtype=torch.float32, device=dev)
+        x = torch.empty((problem.ncell * problem.G, NFEAT), dtype=torch.float32, device=dev)
         nbr = torch.empty((problem.ncell, 6), dtype=torch.int32, device=dev)
         rc = load().snx_gnn_features(problem.h, _ptr(x), _ptr(nbr), _stream(stream))
         problem._check(rc, "gnn_features")
@@ -470,8 +471,8 @@ class Gnn:
     @staticmethod
     def _shape(x, nbr):
         C = nbr.shape[0]
-        if x.shape[0] % C or x.shape[1] != 8 or nbr.shape[1] != 6:
-            raise ValueError("x must be [C*G, 8] and nbr [C, 6]")
+        if x.shape[0] % C or x.shape[1] != NFEAT or nbr.shape[1] != 6:
+            raise ValueError(f"x must be [C*G, {NFEAT}] and nbr [C, 6]")
         if x.dtype.itemsize != 4 or nbr.dtype.itemsize != 4 or not x.is_contiguous() or not nbr.is_contiguous():
             raise ValueError("x float32 and nbr int32, contiguous")
         return C, x.shape[0] // C

@@ -14,6 +14,11 @@ def _tiny_graph(n=3, G=2, seed=0):
     return m, g["nbr"], g["M"].sum(axis=(1, 2)), (g["nbr"] < 0).sum(axis=1)
 
 
+def _position(m):
+    """Cell centroids and the mesh's bounding box."""
+    return m.xyz[m.cell_vert].mean(axis=1), m.xyz.min(axis=0), m.xyz.max(axis=0)
+
+
 def test_backward_matches_central_finite_differences():
     m, nbr, vol, nb = _tiny_graph()
     rng = np.random.default_rng(1)
@@ -22,7 +27,7 @@ def test_backward_matches_central_finite_differences():
     st = rng.uniform(0.1, 10, (m.ncell, G))
     ss = st * rng.uniform(0.9, 0.99, (m.ncell, G))
     q = rng.uniform(0, 1, (m.ncell, G))
-    x = gnn.features(st, ss, q, vol, nb)
+    x = gnn.features(st, ss, q, vol, nb, *_position(m))
     y = rng.normal(0, 1, (m.ncell, G))
     theta = gnn.init_params(3, hidden, layers) + rng.normal(0, 0.05, gnn.pack(
         {k: np.zeros(s) for k, s in gnn.param_shapes(hidden, layers)}, hidden, layers).shape)
@@ -60,3 +65,19 @@ def test_bf16_rounding():
     assert r[3] == 1.0 + 2 ** -7
     assert r[4] == -2.5
     assert abs(r[5] - 1e-3) / 1e-3 < 2 ** -8
+
+
+def test_position_features_on_a_regular_grid():
+    # unjittered n^3 grid of the unit cube: centroids (i + 1/2)/n, box [0, 1]^3
+    n = 4
+    m = inputs.make_mesh(n, 0.0, seed=0)
+    G = 1
+    one = np.ones((m.ncell, G))
+    x = gnn.features(one, 0.5 * one, one, np.full(m.ncell, 1.0 / n ** 3), np.zeros(m.ncell), *_position(m))
+    cen = m.xyz[m.cell_vert].mean(axis=1)
+    idx = np.rint(cen * n - 0.5)
+    assert np.abs(x[:, 0, 8:11] - (idx + 0.5) / n).max() < 1e-12
+    assert np.abs(x[:, 0, 7] - np.minimum(idx + 0.5, n - idx - 0.5).min(axis=1) / n).max() < 1e-12
+    # sigma_t = 1, c = 1/2, h = 1/n: log(sigma_t h) and log(sigma_a h)
+    assert np.abs(x[:, 0, 5] - np.log(1.0 / n)).max() < 1e-12
+    assert np.abs(x[:, 0, 11] - np.log(0.5 / n)).max() < 1e-12

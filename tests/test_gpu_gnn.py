@@ -25,7 +25,9 @@ def _reference_inputs(pr):
     g = o.geometry()
     vol = g["M"].sum(axis=(1, 2))
     nb = (g["nbr"] < 0).sum(axis=1)
-    x = ref.features(pr.mat.sigma_t, pr.mat.sigma_s, pr.mat.q, vol, nb)
+    cen = pr.mesh.xyz[pr.mesh.cell_vert].mean(axis=1)
+    x = ref.features(pr.mat.sigma_t, pr.mat.sigma_s, pr.mat.q, vol, nb, cen, pr.mesh.xyz.min(axis=0),
+                     pr.mesh.xyz.max(axis=0))
     return x, g["nbr"], o
 
 
@@ -52,7 +54,7 @@ def test_features_and_adjacency_match_reference():
     torch.cuda.synchronize()
     xr, nbr_r, _ = _reference_inputs(pr)
     assert np.array_equal(nbr.cpu().numpy(), nbr_r)
-    xg = x.cpu().numpy().reshape(pr.mesh.ncell, pr.mat.ngroup, 8).astype(np.float64)
+    xg = x.cpu().numpy().reshape(pr.mesh.ncell, pr.mat.ngroup, ref.NFEAT).astype(np.float64)
     assert np.abs(xg - xr).max() <= 2e-5 * max(1.0, np.abs(xr).max())
 
 
@@ -142,7 +144,7 @@ def test_save_load_roundtrip_and_shape_check(tmp_path):
     with pytest.raises(snx.SnxError) as e:
         c.load_file(path)
     assert e.value.code == -1
-    assert a.nparams == 8 * 64 + 64 + 4 * (128 * 64 + 64) + 65
+    assert a.nparams == ref.NFEAT * 64 + 64 + 4 * (128 * 64 + 64) + 65
 
 
 def test_learned_start_converges_to_the_same_solution_as_zero_start_and_oracle():
