@@ -51,12 +51,6 @@ namespace {
 template <typename T>
 __device__ __forceinline__ GLOBAL T *gp(T *p) { return (GLOBAL T *)p; }
 
-__device__ __forceinline__ float ld_agent(const GLOBAL float *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(GLOBAL float *p, float v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // Workgroup barrier ordering LDS accesses only.  Unlike __syncthreads it does
@@ -70,8 +64,8 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 // Workgroup barrier for data written to LDS by ordinary LDS stores only: it
-// waits for the wave's LDS operations, not for its LDS-destined loads (which
-// may still be staging the next task) nor its global accesses.
+// waits for the wave's LDS operations, not for its LDS-destined loads (each
+// wave waits for the ones whose data it reads) nor its global accesses.
 __device__ __forceinline__ void lds_store_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
@@ -112,13 +106,6 @@ __device__ __forceinline__ void face_apply(const float *C, const float (&u)[4], 
         const float4 ck = c[k];
         t[k] = __builtin_fmaf(ck.w, u[3], __builtin_fmaf(ck.z, u[2], __builtin_fmaf(ck.y, u[1], ck.x * u[0])));
     }
-}
-
-// cell-local vertex j on a face of the given axis -> face-local index
-__device__ __forceinline__ int face_index(int axis, int j) {
-    if (axis == 0) return j >> 1;
-    if (axis == 1) return (j & 1) | ((j >> 2) << 1);
-    return j & 3;
 }
 
 // Knuth's TwoSum: s + e == a + b exactly.
@@ -272,10 +259,12 @@ __device__ long long pop_task(SweepCtl *ctl, unsigned long long *queue, int &q, 
     return -1;
 }
 
-// LDS layout (floats): M[64] T[3][64] Fin[6][48] om[A][4] Bop[A][64] Cop[A][maxin][16]
-//                      wpsi[2][NT][8] red_s[G][8] red_c[G][8]
+// LDS layout (floats): stage buffers [ONE ? 2 : 1][stage_floats] (M, T of the
+// octant, the face matrices, the task record, ONE: source dofs), om[A][4],
+// Bop[A][64], Cop[A][maxin][16], multi-round wpsi[2][NT][8], red_s[G][8],
+// red_c[G][8]; ONE: a static trace array [12][NT] that also takes wpsi.
 // ONE: every problem of the launch has A*G <= NT, so a task is one round of
-// lanes; nothing is prefetched for a next round, the upwind traces go to a
+// lanes; nothing is prefetched for a next round, the upwind traces go to the
 // static LDS array and wpsi reuses it, which lowers the register and LDS
 // footprint and lets more workgroups be resident.
 //
@@ -336,8 +325,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         s_npush = 0;
     }
     // Queues the ready tasks the last task did not continue with: one atomic
-    // reserves their slots.  Thread 0 runs it while the next task's stage loads
-    // are in flight, so the round trip overlaps them.
+    // reserves their slots.  One thread runs it during the next task (ONE: the
+    // last wave's first lane after the operator build, else thread 0 while the
+    // stage loads are in flight), so the round trip overlaps other work.
     auto push_ready = [&]() {
         const int np = s_npush;
         if (np <= 0) return;
