@@ -60,14 +60,16 @@ def lib():
         L.snxo_set_boundary.argtypes = [vp, ct.c_int, nullable_d]
         L.snxo_set_hooks.argtypes = [vp, nullable_d, nullable_d]
         L.snxo_setup.argtypes = [vp]
-        L.snxo_sweep.argtypes = [vp, nullable_d, _dp, nullable_d, nullable_d, nullable_d]
-        L.snxo_sweep_angle.argtypes = [vp, nullable_d, ct.c_int, ct.c_int, _dp]
+        L.snxo_set_designation.argtypes = [vp, ct.c_int]
+        L.snxo_sweep.argtypes = [vp, nullable_d, nullable_d, _dp, nullable_d, nullable_d, nullable_d]
+        L.snxo_sweep_angle.argtypes = [vp, nullable_d, ct.c_int, ct.c_int, nullable_d, _dp]
         L.snxo_solve.argtypes = [vp, ct.c_double, ct.c_int, nullable_d, _dp,
                                  ct.POINTER(ct.c_int), ct.POINTER(ct.c_double), nullable_d]
         L.snxo_balance.argtypes = [vp, nullable_d, _dp, _dp, _dp]
         L.snxo_integrated_flux.argtypes = [vp, _dp, _dp]
         L.snxo_get_geometry.argtypes = [vp] + [nullable_d] * 7
         L.snxo_get_dag.argtypes = [vp, nullable_d, nullable_d, nullable_d]
+        L.snxo_get_angle_inflow.argtypes = [vp, _ip]
         L.snxo_last_error.argtypes = [vp]
         L.snxo_last_error.restype = ct.c_char_p
         _lib = L
@@ -104,7 +106,8 @@ class Oracle:
     """
 
     def __init__(self, xyz, cell_vert, omega, w, sigma_t, sigma_s, q,
-                 boundary_kind: int = 0, psi_b=None, ang_src=None, bnd_in=None, setup: bool = True):
+                 boundary_kind: int = 0, psi_b=None, ang_src=None, bnd_in=None, setup: bool = True,
+                 designation: int = 0):
         L = lib()
         h = ct.c_void_p()
         self._check(L.snxo_create(ct.byref(h)), "create")
@@ -125,6 +128,8 @@ class Oracle:
         self.psi_b = None if psi_b is None else np.ascontiguousarray(psi_b, np.float64)
         self._check(L.snxo_set_boundary(h, boundary_kind, _ptr(self.psi_b)), "set_boundary")
         self.set_hooks(ang_src, bnd_in)
+        self.designation = int(designation)
+        self._check(L.snxo_set_designation(h, self.designation), "set_designation")
         if setup:
             self.setup()
 
@@ -156,13 +161,19 @@ class Oracle:
     def zeros_phi(self):
         return np.zeros((self.ncell, self.G, 8))
 
-    def sweep(self, phi_in=None, want_psi=False, want_leak=False, want_leak_ang=False):
+    def sweep(self, phi_in=None, want_psi=False, want_leak=False, want_leak_ang=False, psi_prev=None):
+        """One source iteration.  psi_prev[nang][ncell][G][8] (None = zero) is the
+        previous sweep's angular flux, read on lagged faces (designation 1)."""
         phi_out = self.zeros_phi()
         pin = None if phi_in is None else np.ascontiguousarray(phi_in, np.float64)
+        pprev = None if psi_prev is None else np.ascontiguousarray(psi_prev, np.float64)
+        if pprev is not None and pprev.shape != (self.nang, self.ncell, self.G, 8):
+            raise ValueError("psi_prev must be [nang][ncell][G][8]")
         psi = np.zeros((self.nang, self.ncell, self.G, 8)) if want_psi else None
         leak = np.zeros((self.ncell, self.G)) if want_leak else None
         leak_ang = np.zeros((self.nang, self.ncell, self.G)) if want_leak_ang else None
-        self._check(lib().snxo_sweep(self.h, _ptr(pin), phi_out, _ptr(psi), _ptr(leak), _ptr(leak_ang)), "sweep")
+        self._check(lib().snxo_sweep(self.h, _ptr(pin), _ptr(pprev), phi_out, _ptr(psi), _ptr(leak),
+                                     _ptr(leak_ang)), "sweep")
         out = {"phi": phi_out}
         if want_psi:
             out["psi"] = psi
@@ -172,11 +183,15 @@ class Oracle:
             out["leak_ang"] = leak_ang
         return out
 
-    def sweep_angle(self, phi_in, n, g):
-        """psi[ncell][8] of angle n and group g alone, for the same phi_in as sweep()."""
+    def sweep_angle(self, phi_in, n, g, psi_prev=None):
+        """psi[ncell][8] of angle n and group g alone, for the same phi_in (and
+        psi_prev[ncell][8] of this (n, g), None = zero) as sweep()."""
         psi = np.zeros((self.ncell, 8))
         pin = None if phi_in is None else np.ascontiguousarray(phi_in, np.float64)
-        self._check(lib().snxo_sweep_angle(self.h, _ptr(pin), int(n), int(g), psi), "sweep_angle")
+        pprev = None if psi_prev is None else np.ascontiguousarray(psi_prev, np.float64)
+        if pprev is not None and pprev.shape != (self.ncell, 8):
+            raise ValueError("psi_prev must be [ncell][8]")
+        self._check(lib().snxo_sweep_angle(self.h, _ptr(pin), int(n), int(g), _ptr(pprev), psi), "sweep_angle")
         return psi
 
     def solve(self, tol, max_it, phi0=None, allow_noconv=False):
@@ -209,6 +224,12 @@ class Oracle:
         self._check(lib().snxo_get_geometry(self.h, *[_ptr(g[k]) for k in
                     ("M", "S", "F", "area", "nbr", "nbr_face", "perm")]), "get_geometry")
         return g
+
+    def angle_inflow(self):
+        """Designation 1: [nang][ncell] inflow-face bit masks of each angle."""
+        ain = np.zeros((self.nang, self.ncell), np.int32)
+        self._check(lib().snxo_get_angle_inflow(self.h, ain), "get_angle_inflow")
+        return ain
 
     def dag(self):
         C = self.ncell

@@ -31,6 +31,8 @@ struct snxo_problem {
     double *M, *S, *F, *area;       /* [C][64], [C][3][64], [C][6][3][16], [C][6][3] */
     int32_t *nbr, *nbrf, *perm;     /* [C][6], [C][6], [C][6][4] */
     int32_t *inflow, *level, *order;/* [8][C] each */
+    int designation;                /* 0 per octant, 1 per angle (snxo_set_designation) */
+    int32_t *ain;                   /* designation 1: [nang][C] inflow faces of each angle */
     char err[256];
 };
 
@@ -187,9 +189,9 @@ int snxo_quadrature(int npolar, int nazim, double *omega, double *w) {
 static void free_derived(snxo_problem *p) {
     free(p->M); free(p->S); free(p->F); free(p->area);
     free(p->nbr); free(p->nbrf); free(p->perm);
-    free(p->inflow); free(p->level); free(p->order);
+    free(p->inflow); free(p->level); free(p->order); free(p->ain);
     p->M = p->S = p->F = p->area = NULL;
-    p->nbr = p->nbrf = p->perm = p->inflow = p->level = p->order = NULL;
+    p->nbr = p->nbrf = p->perm = p->inflow = p->level = p->order = p->ain = NULL;
     p->ready = 0;
 }
 
@@ -264,6 +266,13 @@ int snxo_set_boundary(snxo_problem *p, int kind, const double *psi_b) {
         p->psib = dup_d(psi_b, (size_t)p->G);
         if (!p->psib) return fail(p, SNXO_E_OOM, "out of memory");
     }
+    return SNXO_OK;
+}
+
+int snxo_set_designation(snxo_problem *p, int kind) {
+    if (!p || (kind != 0 && kind != 1)) return fail(p, SNXO_E_ARG, "designation must be 0 or 1");
+    p->designation = kind;
+    free_derived(p);
     return SNXO_OK;
 }
 
@@ -503,6 +512,28 @@ static int build_dag(snxo_problem *p) {
     return SNXO_OK;
 }
 
+/* Designation 1: face f of K is inflow for angle n when Omega_n . A_f < 0 (the
+ * mesh traversal of each direction, Section 2.1).  These graphs may have
+ * cycles; the sweep keeps the octant's order and lags the faces that go
+ * against it, so no order is derived from them here. */
+static int build_angle_inflow(snxo_problem *p) {
+    int C = p->ncell;
+    for (int n = 0; n < p->nang; ++n) {
+        const double *om = p->omega + 3 * n;
+        for (int K = 0; K < C; ++K) {
+            int mask = 0;
+            for (int f = 0; f < 6; ++f) {
+                const double *A = p->area + 18L * K + 3 * f;
+                double d = om[0] * A[0] + om[1] * A[1] + om[2] * A[2];
+                if (d == 0.0) return fail(p, SNXO_E_MESH, "face tangent to a direction");
+                if (d < 0.0) mask |= 1 << f;
+            }
+            p->ain[(long)n * C + K] = mask;
+        }
+    }
+    return SNXO_OK;
+}
+
 int snxo_setup(snxo_problem *p) {
     if (!p || !p->cv || !p->omega || !p->sigt) return fail(p, SNXO_E_STATE, "mesh, quadrature and materials must be set");
     free_derived(p);
@@ -517,13 +548,16 @@ int snxo_setup(snxo_problem *p) {
     p->inflow = malloc(sizeof(int32_t) * 8 * C);
     p->level = malloc(sizeof(int32_t) * 8 * C);
     p->order = malloc(sizeof(int32_t) * 8 * C);
-    if (!p->M || !p->S || !p->F || !p->area || !p->nbr || !p->nbrf || !p->perm || !p->inflow || !p->level || !p->order) {
+    if (p->designation == 1) p->ain = malloc(sizeof(int32_t) * (size_t)p->nang * C);
+    if (!p->M || !p->S || !p->F || !p->area || !p->nbr || !p->nbrf || !p->perm || !p->inflow || !p->level || !p->order
+        || (p->designation == 1 && !p->ain)) {
         free_derived(p);
         return fail(p, SNXO_E_OOM, "out of memory");
     }
     int rc = build_topology(p);
     if (!rc) rc = build_geometry(p);
     if (!rc) rc = build_dag(p);
+    if (!rc && p->designation == 1) rc = build_angle_inflow(p);
     if (rc) { free_derived(p); return rc; }
     p->ready = 1;
     return SNXO_OK;
@@ -534,14 +568,18 @@ int snxo_setup(snxo_problem *p) {
 /* One (cell, angle, group) local system of the upwind DG form:
  *   A = sum_a Om_a S^a + sigma_t M - sum_{f in} sum_a Om_a F^a_f
  *   b = M q - sum_{f in} (Om . F_f) psi_up_f
- * with q the nodal source values and psi_up the upwind trace at f's nodes. */
+ * with q the nodal source values and psi_up the upwind trace at f's nodes.
+ * "in" is the octant's inflow set (designation 0) or the angle's own
+ * (designation 1).  psi_up is read from psi_cur, which holds the newest value
+ * of every cell: this sweep's for cells already visited, the previous sweep's
+ * (or zero) for the rest. */
 static int solve_local(const snxo_problem *p, int K, int n, int g, const double *qnodal,
                        const double *psi_cur /*[C][8] this angle and group*/, double x[8],
                        double *leak_out) {
     const double *om = p->omega + 3 * n;
     const double *M = p->M + 64L * K, *S = p->S + 192L * K;
     int o = n / (p->nang / 8);
-    int mask = p->inflow[(long)o * p->ncell + K];
+    int mask = p->designation == 1 ? p->ain[(long)n * p->ncell + K] : p->inflow[(long)o * p->ncell + K];
     double sigt = p->sigt[(long)K * p->G + g];
     double A[64], b[8], up[6][4];
     for (int i = 0; i < 8; ++i) {
@@ -596,7 +634,12 @@ static int solve_local(const snxo_problem *p, int K, int n, int g, const double 
     return 0;
 }
 
-int snxo_sweep(snxo_problem *p, const double *phi_in, double *phi_out,
+/* The cells of an angle are visited in the octant's topological order, so
+ * under designation 0 every inflow neighbour is already done.  Under
+ * designation 1 an inflow neighbour that comes later in that order still
+ * holds the previous sweep's value in psi_cur (initialised from psi_prev):
+ * that face is lagged. */
+int snxo_sweep(snxo_problem *p, const double *phi_in, const double *psi_prev, double *phi_out,
                double *psi_all, double *leak, double *leak_ang) {
     if (!p || !p->ready) return fail(p, SNXO_E_STATE, "setup has not run");
     if (!phi_out) return fail(p, SNXO_E_ARG, "phi_out is NULL");
@@ -613,6 +656,9 @@ int snxo_sweep(snxo_problem *p, const double *phi_in, double *phi_out,
         for (int o = 0; o < 8; ++o)
             for (int a = 0; a < per; ++a) {
                 int n = o * per + a;
+                for (long K = 0; K < C; ++K)
+                    for (int j = 0; j < 8; ++j)
+                        psi_cur[8 * K + j] = psi_prev ? psi_prev[(((long)n * C + K) * G + g) * 8 + j] : 0.0;
                 for (int t = 0; t < C; ++t) {
                     int K = p->order[(long)o * C + t];
                     double qn[8], x[8], L = 0.0;
@@ -645,12 +691,14 @@ int snxo_sweep(snxo_problem *p, const double *phi_in, double *phi_out,
  * source iteration are independent (Eq. 1 with the scattering source taken
  * from phi_in), so this is the same loop as one (n, g) pass of snxo_sweep;
  * it lets large problems be checked on sampled (angle, group) pairs. */
-int snxo_sweep_angle(snxo_problem *p, const double *phi_in, int n, int g, double *psi_out) {
+int snxo_sweep_angle(snxo_problem *p, const double *phi_in, int n, int g, const double *psi_prev,
+                     double *psi_out) {
     if (!p || !p->ready) return fail(p, SNXO_E_STATE, "setup has not run");
     if (!psi_out) return fail(p, SNXO_E_ARG, "psi_out is NULL");
     int C = p->ncell, G = p->G, nang = p->nang, per = nang / 8;
     if (n < 0 || n >= nang || g < 0 || g >= G) return fail(p, SNXO_E_ARG, "angle or group out of range");
     int o = n / per;
+    for (long i = 0; i < 8L * C; ++i) psi_out[i] = psi_prev ? psi_prev[i] : 0.0;
     for (int t = 0; t < C; ++t) {
         int K = p->order[(long)o * C + t];
         double qn[8], x[8];
@@ -685,12 +733,14 @@ int snxo_solve(snxo_problem *p, double tol, int max_it, const double *phi0,
     if (!phi_out || max_it < 1) return fail(p, SNXO_E_ARG, "bad solve arguments");
     size_t n = 8 * (size_t)p->ncell * p->G;
     double *cur = malloc(sizeof(double) * n);
-    if (!cur) return fail(p, SNXO_E_OOM, "out of memory");
+    /* designation 1: the angular flux carried between sweeps */
+    double *psi = p->designation == 1 ? calloc(n * (size_t)p->nang, sizeof(double)) : NULL;
+    if (!cur || (p->designation == 1 && !psi)) { free(cur); free(psi); return fail(p, SNXO_E_OOM, "out of memory"); }
     if (phi0) memcpy(cur, phi0, sizeof(double) * n); else memset(cur, 0, sizeof(double) * n);
     int it = 0, rc = SNXO_OK;
     double e = INFINITY;
     while (it < max_it) {
-        rc = snxo_sweep(p, cur, phi_out, NULL, NULL, NULL);
+        rc = snxo_sweep(p, cur, psi, phi_out, psi, NULL, NULL);
         if (rc) break;
         e = rel_change(phi_out, cur, n);
         if (hist) hist[it] = e;
@@ -699,6 +749,7 @@ int snxo_solve(snxo_problem *p, double tol, int max_it, const double *phi0,
         if (e <= tol) break;
     }
     free(cur);
+    free(psi);
     if (iters) *iters = it;
     if (eps) *eps = e;
     if (rc) return rc;
@@ -771,5 +822,12 @@ int snxo_get_dag(snxo_problem *p, int32_t *inflow, int32_t *level, int32_t *orde
     if (inflow) memcpy(inflow, p->inflow, sizeof(int32_t) * 8 * C);
     if (level) memcpy(level, p->level, sizeof(int32_t) * 8 * C);
     if (order) memcpy(order, p->order, sizeof(int32_t) * 8 * C);
+    return SNXO_OK;
+}
+
+int snxo_get_angle_inflow(snxo_problem *p, int32_t *ain) {
+    if (!p || !p->ready) return fail(p, SNXO_E_STATE, "setup has not run");
+    if (p->designation != 1 || !ain) return fail(p, SNXO_E_ARG, "per-angle masks exist under designation 1 only");
+    memcpy(ain, p->ain, sizeof(int32_t) * (size_t)p->nang * p->ncell);
     return SNXO_OK;
 }

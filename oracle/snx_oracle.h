@@ -15,6 +15,9 @@
  *     Table 1 (mass, stiffness, face normals, face nodes, neighbours);
  *   - the sweep: cells visited in a topological order of the upwind
  *     dependency DAG (Section 2.1), octant by octant, angle by angle;
+ *   - upwind faces designated once per octant, or per angle (the mesh
+ *     traversal of each direction, Section 2.1) with lagged faces where a
+ *     direction's own dependencies go against its octant's order;
  *   - source iteration, and the integrated flux of Eq. 3.
  *
  * All arithmetic is double precision; local systems use LU with partial
@@ -69,22 +72,38 @@ int  snxo_set_boundary(snxo_problem *p, int kind, const double *psi_b);
  * of an angle-dependent source replacing (Q + sigma_s phi)/(4 pi).
  * bnd_in[ncell][6][nang][G][4]: nodal inflow values on boundary faces. */
 int  snxo_set_hooks(snxo_problem *p, const double *ang_src, const double *bnd_in);
+/* Upwind designation (before snxo_setup; default 0).
+ * kind 0: per octant, face f of cell K is inflow for every angle of octant o
+ *         when s_o . A_f < 0 (s_o the octant's sign vector, A_f the outward
+ *         area vector).
+ * kind 1: per angle, face f of K is inflow for angle n when Omega_n . A_f < 0.
+ *         Cells are still visited in the octant's topological order; an
+ *         inflow face whose neighbour comes later in that order reads the
+ *         neighbour's angular flux of the previous sweep (psi_prev), so every
+ *         cycle of a direction's own dependency graph is broken at the faces
+ *         that go against the octant's order. */
+int  snxo_set_designation(snxo_problem *p, int kind);
 /* Topology, geometry, upwind designation and levelling. */
 int  snxo_setup(snxo_problem *p);
 
 /* One source iteration: phi_out = sum_n w_n psi_n where psi solves the sweep
- * with scattering source from phi_in.  Optional outputs (NULL to skip):
+ * with scattering source from phi_in.  psi_prev[nang][ncell][G][8] (NULL =
+ * zero) is the previous sweep's angular flux, read on lagged faces of
+ * designation 1 only.  Optional outputs (NULL to skip):
  * psi_all[nang][ncell][G][8], leak[ncell][G] (angle-weighted net outflow),
  * leak_ang[nang][ncell][G] (per-angle net outflow). */
-int  snxo_sweep(snxo_problem *p, const double *phi_in, double *phi_out,
+int  snxo_sweep(snxo_problem *p, const double *phi_in, const double *psi_prev, double *phi_out,
                 double *psi_all, double *leak, double *leak_ang);
 
 /* The sweep of one (angle n, group g) alone (angles and groups of a source
- * iteration are independent given phi_in): psi_out[ncell][8]. */
-int  snxo_sweep_angle(snxo_problem *p, const double *phi_in, int n, int g, double *psi_out);
+ * iteration are independent given phi_in and psi_prev): psi_out[ncell][8];
+ * psi_prev[ncell][8] of the same (n, g), nullable as in snxo_sweep. */
+int  snxo_sweep_angle(snxo_problem *p, const double *phi_in, int n, int g, const double *psi_prev,
+                      double *psi_out);
 
 /* Source iteration from phi0 (NULL = zero) until the relative max-norm change
- * is <= tol or max_it sweeps.  hist[max_it] (nullable) receives each change. */
+ * is <= tol or max_it sweeps.  hist[max_it] (nullable) receives each change.
+ * Designation 1 carries the angular flux from sweep to sweep, zero at the start. */
 int  snxo_solve(snxo_problem *p, double tol, int max_it, const double *phi0,
                 double *phi_out, int *iters, double *eps, double *hist);
 
@@ -105,6 +124,8 @@ int  snxo_get_geometry(snxo_problem *p, double *M, double *S, double *F, double 
 /* inflow[8][ncell] bit f set when face f is inflow; level[8][ncell];
  * order[8][ncell] the topological order used by the sweep. */
 int  snxo_get_dag(snxo_problem *p, int32_t *inflow, int32_t *level, int32_t *order);
+/* Designation 1: ain[nang][ncell], bit f set when face f is inflow for angle n. */
+int  snxo_get_angle_inflow(snxo_problem *p, int32_t *ain);
 const char *snxo_last_error(snxo_problem *p);
 
 #ifdef __cplusplus

@@ -38,8 +38,9 @@ def kron3(ax, ay, az):
     return np.kron(az, np.kron(ay, ax))
 
 
-def dense_angle_matrix(geo, dag, omega, n, nang, sigt_g):
-    """Global matrix of one angle's upwind DG system (interior coupling only)."""
+def dense_angle_matrix(geo, dag, omega, n, nang, sigt_g, masks=None):
+    """Global matrix of one angle's upwind DG system (interior coupling only).
+    masks[C] overrides the octant's inflow masks (e.g. the angle's own)."""
     C = geo["M"].shape[0]
     o = n // (nang // 8)
     om = omega[n]
@@ -47,7 +48,7 @@ def dense_angle_matrix(geo, dag, omega, n, nang, sigt_g):
     for K in range(C):
         A = np.einsum("a,aij->ij", om, geo["S"][K]) + sigt_g[K] * geo["M"][K]
         Gm[8 * K:8 * K + 8, 8 * K:8 * K + 8] += A
-        mask = dag["inflow"][o, K]
+        mask = dag["inflow"][o, K] if masks is None else masks[K]
         for f in range(6):
             if not (mask >> f) & 1:
                 continue
@@ -62,14 +63,14 @@ def dense_angle_matrix(geo, dag, omega, n, nang, sigt_g):
     return Gm
 
 
-def boundary_rhs(geo, dag, omega, n, nang, psi_b):
+def boundary_rhs(geo, dag, omega, n, nang, psi_b, masks=None):
     """-(Omega.F) psi_b on inflow boundary faces for a constant inflow psi_b."""
     C = geo["M"].shape[0]
     o = n // (nang // 8)
     om = omega[n]
     rhs = np.zeros(8 * C)
     for K in range(C):
-        mask = dag["inflow"][o, K]
+        mask = dag["inflow"][o, K] if masks is None else masks[K]
         for f in range(6):
             if (mask >> f) & 1 and geo["nbr"][K, f] < 0:
                 fn = face_nodes(f)
