@@ -100,6 +100,25 @@ snx_status snx_set_materials(snx_problem *p, int32_t ngroup, const double *sigma
  * kind 1 = isotropic inflow psi_in[G] (host float64). */
 snx_status snx_set_boundary(snx_problem *p, int32_t kind, const double *psi_in);
 
+/* Upwind designation, used by the next snx_setup (a change undoes any earlier
+ * setup).
+ * SNX_DESIGNATION_OCTANT (default): face f of cell K is inflow for every
+ *   direction of octant o when s_o . A_f < 0 (s_o the octant's sign vector,
+ *   A_f the outward area vector); one acyclic dependency graph per octant.
+ * SNX_DESIGNATION_ANGLE: face f of K is inflow for direction n when
+ *   Omega_n . A_f < 0, decided in FP64 (the per-direction mesh traversal of
+ *   §2.1).  On distorted meshes these graphs can contain cycles.  Tasks still
+ *   follow the octant's graph: a face that is inflow for a direction but
+ *   downwind in the octant's order reads the neighbour's angular flux from the
+ *   problem's previous sweep (zero after snx_setup).  Every cycle is broken
+ *   this way, and source iteration converges to the per-direction upwind
+ *   solution, independently of which faces lag.
+ * SNX_E_ARG for another kind; snx_setup returns SNX_E_MESH when a face is
+ * tangent to a direction. */
+#define SNX_DESIGNATION_OCTANT 0
+#define SNX_DESIGNATION_ANGLE 1
+snx_status snx_set_designation(snx_problem *p, int32_t kind);
+
 /* Build everything one mesh needs, on the device: face matching, element
  * matrices (FP64 integration, FP32 storage), per-octant upwind designation
  * (face f of cell K is inflow for octant o when s_o . A_f < 0, A_f the face's
@@ -137,6 +156,14 @@ snx_status snx_integrated_flux(snx_problem *p, const float *phi, double *out, vo
 /* Level structure from setup: host level[8][ncell] (t-level of each cell per
  * octant) and host nlevels[8]; either may be NULL.  Synchronous. */
 snx_status snx_get_levels(snx_problem *p, int32_t *level, int32_t *nlevels);
+
+/* Designation statistics from setup, host out[4]: the designation, the
+ * (direction, cell, face) triples whose inflow bit differs from the octant's,
+ * the lagged triples among them (interior faces inflow for the direction and
+ * downwind in the octant's order), and the (cell, octant) tasks with at least
+ * one differing direction.  The counts are zero under per-octant designation.
+ * Synchronous. */
+snx_status snx_designation_stats(snx_problem *p, int64_t *out);
 
 /* The angular flux psi (Eq. 1) of one direction and group from the most recent
  * sweep of this problem (alone or in a batch): device out[ncell][8] (FP32, the

@@ -70,6 +70,7 @@ struct Sched {
     int maxA = 0, maxG = 0, maxin = 1;
     int maxAG = 0;                           // largest (angles per octant) * G of the problems
     bool one = false;                        // every task is one round of lanes (maxAG <= threads)
+    bool pa = false;                         // a problem uses per-angle designation: the kernel variant with it
     int threads = 256, wg_per_cu = 0, grid = 0, chunk = 8;
     int mode = SNX_SWEEP_AMT;                // SNX_SWEEP_AMT or SNX_SWEEP_BSP
     bool phase_stats = false;                // gather the per-phase cycle statistics (snx_set_sweep_stats)
@@ -107,6 +108,7 @@ struct snx_problem {
     std::vector<double> xyz, omega, w, sigt, sigs, q, psib;
     std::vector<int> cv;
     bool have_mesh = false, have_quad = false, have_mat = false;
+    int designation = SNX_DESIGNATION_OCTANT;
 
     // set-up results
     bool ready = false;
@@ -114,6 +116,7 @@ struct snx_problem {
     DevProblem hp{};
     std::vector<int> level, nlev;
     std::vector<std::vector<int>> seeds_by_octant;   // local task ids (8*K + o) of level-0 cells
+    unsigned long long desig_counts[3] = {0, 0, 0};  // per-angle designation statistics (snx_designation_stats)
     int maxin = 1;
     int *d_err = nullptr;
     float *d_phi[2] = {nullptr, nullptr};
@@ -182,7 +185,7 @@ snx_status configure_grid(Sched &sc) {
     sc.one = sc.maxAG <= sc.threads;
     const size_t lds = sweep_lds_bytes(sc.threads, sc.maxA, sc.maxG, sc.maxin, sc.one);
     if (lds > 64 * 1024) return fail_msg(sc.err, SNX_E_ARG, "task does not fit in 64 KB of LDS (too many angles or groups)");
-    const int occ = sweep_occupancy(sc.threads, sc.one, lds);
+    const int occ = sweep_occupancy(sc.threads, sc.one, sc.pa, lds);
     if (occ <= 0) return fail_msg(sc.err, SNX_E_ARG, "sweep kernel cannot be resident with this schedule");
     const int per_cu = sc.wg_per_cu > 0 ? std::min(sc.wg_per_cu, occ) : occ;
     long long grid = (long long)cu_count(sc.device) * per_cu;
@@ -222,6 +225,7 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
     std::vector<int> blk(n + 1, 0), rblk(n + 1, 0), seed_off(8 * n + 1, 0), seeds;
     sc.maxA = sc.maxG = sc.maxAG = 0;
     sc.maxin = 1;
+    sc.pa = false;
     for (int i = 0; i < n; ++i) {
         snx_problem *p = probs[i];
         DevProblem P = p->hp;
@@ -234,6 +238,7 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
         sc.maxG = std::max(sc.maxG, p->G);
         sc.maxAG = std::max(sc.maxAG, p->A * p->G);
         sc.maxin = std::max(sc.maxin, p->maxin);
+        sc.pa = sc.pa || p->hp.amask != nullptr;
         for (int o = 0; o < 8; ++o) {
             seed_off[i * 8 + o] = (int)seeds.size();
             seeds.insert(seeds.end(), p->seeds_by_octant[o].begin(), p->seeds_by_octant[o].end());
@@ -322,7 +327,7 @@ snx_status enqueue_sweep(Sched &sc, const int *stops, hipStream_t s, hipEvent_t 
         for (size_t l = 0; l + 1 < sc.bsp_off.size(); ++l)
             HIPCHK_E(sc.err, launch_sweep_level(sc.d_probs, sc.nprob(), sc.d_base, sc.d_ctl, sc.threads, sc.one,
                                                 sc.grid, sc.maxA, sc.maxG, sc.maxin, sc.d_bsp_tasks, sc.bsp_off[l],
-                                                sc.bsp_off[l + 1], stops, s), "level launch");
+                                                sc.bsp_off[l + 1], stops, sc.pa, s), "level launch");
         if (ev1) HIPCHK_E(sc.err, hipEventRecord(ev1, s), "event");
         return SNX_OK;
     }
@@ -330,7 +335,7 @@ snx_status enqueue_sweep(Sched &sc, const int *stops, hipStream_t s, hipEvent_t 
                                            stops, s), "sweep prologue");
     if (ev0) HIPCHK_E(sc.err, hipEventRecord(ev0, s), "event");
     HIPCHK_E(sc.err, launch_sweep_kernel(sc.d_probs, sc.nprob(), sc.d_base, sc.d_ctl, sc.d_queue, sc.threads, sc.one,
-                                         sc.grid, sc.maxA, sc.maxG, sc.maxin, sc.watchdog, sc.phase_stats, s),
+                                         sc.grid, sc.maxA, sc.maxG, sc.maxin, sc.watchdog, sc.phase_stats, sc.pa, s),
              "sweep launch");
     if (ev1) HIPCHK_E(sc.err, hipEventRecord(ev1, s), "event");
     return SNX_OK;
@@ -515,8 +520,8 @@ std::string tune_key(const Sched &sc) {
     while ((1LL << (cb + 1)) <= cells) ++cb;
     while ((1LL << (sb + 1)) <= solves) ++sb;
     char buf[256];
-    std::snprintf(buf, sizeof buf, "%s|cu%d|np%d|A%d|G%d|c%d|s%d|k%d", prop.gcnArchName, cu_count(sc.device),
-                  sc.nprob(), sc.maxA, sc.maxG, cb, sb, kSweepRevision);
+    std::snprintf(buf, sizeof buf, "%s|cu%d|np%d|A%d|G%d|c%d|s%d|k%d%s", prop.gcnArchName, cu_count(sc.device),
+                  sc.nprob(), sc.maxA, sc.maxG, cb, sb, kSweepRevision, sc.pa ? "|pa" : "");
     return buf;
 }
 
@@ -733,6 +738,15 @@ snx_status snx_set_boundary(snx_problem *p, int32_t kind, const double *psi_in) 
     return SNX_OK;
 }
 
+snx_status snx_set_designation(snx_problem *p, int32_t kind) {
+    if (!p) return SNX_E_ARG;
+    if (kind != SNX_DESIGNATION_OCTANT && kind != SNX_DESIGNATION_ANGLE)
+        return fail(p, SNX_E_ARG, "designation must be SNX_DESIGNATION_OCTANT or SNX_DESIGNATION_ANGLE");
+    p->designation = kind;
+    drop_device(p);
+    return SNX_OK;
+}
+
 snx_status snx_setup(snx_problem *p, void *stream) {
     if (!p) return SNX_E_ARG;
     if (!p->have_mesh || !p->have_quad || !p->have_mat) return fail(p, SNX_E_STATE, "mesh, quadrature and materials must be set");
@@ -835,8 +849,32 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     p->maxin = 1;
     for (int o = 0; o < 8; ++o) p->maxin = std::max(p->maxin, nlev[8 + o]);
 
+    // per-angle designation: each direction's inflow faces, decided in FP64
+    unsigned char *damask = nullptr, *dlagm = nullptr;
+    std::fill(p->desig_counts, p->desig_counts + 3, 0ull);
+    if (p->designation == SNX_DESIGNATION_ANGLE) {
+        double *d_om64;
+        unsigned long long *dcounts;
+        HIPCHK(p, m.alloc((void **)&damask, 8 * C * A), "device allocation");
+        HIPCHK(p, m.alloc((void **)&dlagm, 8 * C), "device allocation");
+        HIPCHK(p, m.alloc((void **)&d_om64, sizeof(double) * 3 * p->nang), "device allocation");
+        HIPCHK(p, m.alloc((void **)&dcounts, sizeof(unsigned long long) * 3), "device allocation");
+        HIPCHK(p, hipMemcpyAsync(d_om64, p->omega.data(), sizeof(double) * 3 * p->nang, hipMemcpyHostToDevice, s),
+               "copy");
+        HIPCHK(p, hipMemsetAsync(dcounts, 0, sizeof(unsigned long long) * 3, s), "memset");
+        HIPCHK(p, launch_angle_masks(p->C, p->A, d_om64, d_nbr, p->d_area, dmask, damask, dlagm, dcounts, p->d_err, s),
+               "per-angle designation");
+        HIPCHK(p, hipMemcpyAsync(&herr, p->d_err, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+        HIPCHK(p, hipMemcpyAsync(p->desig_counts, dcounts, sizeof(unsigned long long) * 3, hipMemcpyDeviceToHost, s),
+               "copy");
+        HIPCHK(p, hipStreamSynchronize(s), "per-angle designation");
+        if (herr & 8) { drop_device(p); return fail(p, SNX_E_MESH, "a face is tangent to a direction"); }
+        // lagged faces read the previous sweep's angular flux: zero before the first
+        HIPCHK(p, launch_fill_f32(dpsi, 8 * C * 8 * A * G, 0.f, s), "fill");
+    }
+
     HIPCHK(p, launch_octant_operators(p->C, dS, dF, dmask, dT, s), "octant operators");
-    HIPCHK(p, launch_task_records(p->C, d_nbr, d_perm, dmask, dindeg, drec, s), "task records");
+    HIPCHK(p, launch_task_records(p->C, d_nbr, d_perm, dmask, dindeg, dlagm, drec, s), "task records");
 
     // level-0 tasks of every octant are the seeds of a sweep
     std::vector<int> seeds_host(8 * C);
@@ -847,6 +885,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
 
     hp.C = p->C; hp.G = p->G; hp.A = p->A; hp.nang = p->nang; hp.task_base = 0; hp.epoch = depoch;
     hp.M = dM; hp.S = dS; hp.T = dT; hp.F = dF; hp.nbr = d_nbr; hp.perm = d_perm; hp.inmask = dmask; hp.indeg = dindeg;
+    hp.amask = damask;
     hp.sigt = dsigt; hp.sigs = dsigs; hp.q = dq; hp.r = dr; hp.omega = dom; hp.w = dw; hp.psib = dpsib;
     hp.psi = dpsi; hp.slot = dslot; hp.slotc = dslotc; hp.cnt = dcnt; hp.rec = drec;
     hp.xyz = d_xyz; hp.cv = d_cv;
@@ -935,6 +974,14 @@ snx_status snx_get_levels(snx_problem *p, int32_t *level, int32_t *nlevels) {
     if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
     if (level) std::memcpy(level, p->level.data(), sizeof(int) * p->level.size());
     if (nlevels) std::memcpy(nlevels, p->nlev.data(), sizeof(int) * 8);
+    return SNX_OK;
+}
+
+snx_status snx_designation_stats(snx_problem *p, int64_t *out) {
+    if (!p || !out) return SNX_E_ARG;
+    if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
+    out[0] = p->designation;
+    for (int i = 0; i < 3; ++i) out[1 + i] = (int64_t)p->desig_counts[i];
     return SNX_OK;
 }
 

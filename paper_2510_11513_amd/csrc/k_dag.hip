@@ -132,7 +132,7 @@ __global__ void k_octant_operators(int C, const float *__restrict__ S, const flo
 // holds that cell's descriptor when it starts it.
 __global__ void k_task_records(int C, const int *__restrict__ nbr, const unsigned *__restrict__ perm,
                                const unsigned char *__restrict__ inmask, const int *__restrict__ indeg,
-                               int *__restrict__ rec) {
+                               const unsigned char *__restrict__ lagm, int *__restrict__ rec) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;   // o * C + K
     if (t >= 8LL * C) return;
     const int o = (int)(t / C), K = (int)(t - (long long)o * C);
@@ -145,7 +145,8 @@ __global__ void k_task_records(int C, const int *__restrict__ nbr, const unsigne
         d[12] = inmask[(size_t)o * C + cell];
     };
     desc(K, r);
-    r[13] = r[14] = r[15] = 0;
+    r[13] = lagm ? (int)lagm[t] << 18 : 0;
+    r[14] = r[15] = 0;
     const int mask = inmask[t];
     for (int f = 0; f < 6; ++f) {
         int *d = r + 16 + 13 * f;
@@ -160,13 +161,63 @@ __global__ void k_task_records(int C, const int *__restrict__ nbr, const unsigne
     r[94] = r[95] = 0;
 }
 
+// Per-angle designation (each direction's own mesh traversal, Section 2.1):
+// face f of K is inflow for direction n when Omega_n . A_f < 0, decided in FP64.
+// Tasks stay (cell, octant) and follow the octant's DAG; the sweep corrects the
+// operators of the directions that differ from the octant's designation, and a
+// face that is inflow for a direction but downwind in the octant's order takes
+// the neighbour's angular flux of the previous sweep (a lagged face).  One
+// thread per (octant, cell).
+__global__ void k_angle_masks(int C, int A, const double *__restrict__ omega, const int *__restrict__ nbr,
+                              const double *__restrict__ area, const unsigned char *__restrict__ inmask,
+                              unsigned char *__restrict__ amask, unsigned char *__restrict__ lagm,
+                              unsigned long long *__restrict__ counts, int *__restrict__ err) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;   // o * C + K
+    if (t >= 8LL * C) return;
+    const int o = (int)(t / C), K = (int)(t - (long long)o * C);
+    const int om = inmask[t];
+    int interior = 0;
+    for (int f = 0; f < 6; ++f) interior |= nbr[(size_t)K * 6 + f] >= 0 ? 1 << f : 0;
+    int any = 0;
+    unsigned long long ndiff = 0, nlag = 0;
+    for (int a = 0; a < A; ++a) {
+        const double *w = omega + 3 * ((size_t)o * A + a);
+        int mask = 0;
+        for (int f = 0; f < 6; ++f) {
+            const double *Af = area + ((size_t)K * 6 + f) * 3;
+            const double d = w[0] * Af[0] + w[1] * Af[1] + w[2] * Af[2];
+            if (d == 0.0) atomicOr(err, 8);
+            mask |= d < 0.0 ? 1 << f : 0;
+        }
+        amask[(size_t)t * A + a] = (unsigned char)mask;
+        any |= mask ^ om;
+        ndiff += __popc(mask ^ om);
+        nlag += __popc(mask & ~om & interior);
+    }
+    lagm[t] = (unsigned char)any;
+    if (ndiff) {
+        atomicAdd(&counts[0], ndiff);
+        atomicAdd(&counts[1], nlag);
+        atomicAdd(&counts[2], 1ull);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_task_records(int C, const int *nbr, const unsigned *perm, const unsigned char *inmask,
-                               const int *indeg, int *rec, hipStream_t s) {
+                               const int *indeg, const unsigned char *lagm, int *rec, hipStream_t s) {
     const long long n = 8LL * C;
     hipLaunchKernelGGL(k_task_records, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, C, nbr, perm, inmask,
-                       indeg, rec);
+                       indeg, lagm, rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_angle_masks(int C, int A, const double *omega, const int *nbr, const double *area,
+                              const unsigned char *inmask, unsigned char *amask, unsigned char *lagm,
+                              unsigned long long *counts, int *err, hipStream_t s) {
+    const long long n = 8LL * C;
+    hipLaunchKernelGGL(k_angle_masks, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, C, A, omega, nbr, area,
+                       inmask, amask, lagm, counts, err);
     return hipGetLastError();
 }
 

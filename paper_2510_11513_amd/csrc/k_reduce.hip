@@ -257,10 +257,13 @@ __global__ __launch_bounds__(256) void k_balance(const DevProblem *__restrict__ 
             }
         const size_t cell_psi = (size_t)8 * A * G;
         for (int o = 0; o < 8; ++o) {
-            const int mask = P.inmask[(size_t)o * C + K];
             const float *psi_o = P.psi + (size_t)o * C * cell_psi;
             for (int a = 0; a < A; ++a) {
                 const int n = o * A + a;
+                // upwind faces of the octant, or of the direction under per-angle
+                // designation (whose lagged faces read this sweep's neighbour trace
+                // here, so the cell imbalance also measures the lag)
+                const int mask = P.amask ? (int)P.amask[((size_t)o * C + K) * A + a] : (int)P.inmask[(size_t)o * C + K];
                 const double ox = P.omega[3 * n], oy = P.omega[3 * n + 1], oz = P.omega[3 * n + 2];
                 double L = 0.0;
                 for (int f = 0; f < 6; ++f) {

@@ -273,7 +273,7 @@ __device__ long long pop_task(SweepCtl *ctl, unsigned long long *queue, int &q, 
 // with a grid-stride loop, and the next level is the next launch; no counters,
 // queues or continuation.  Task bodies are the same code, so results are the
 // same bits.  stops (nullable) marks converged problems of a batch.
-template <int NT, bool ONE, bool BSP>
+template <int NT, bool ONE, bool BSP, bool PA>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_ONE : 4))) void k_sweep(
     const DevProblem *__restrict__ probs, int nprob, const long long *__restrict__ task_base,
     SweepCtl *__restrict__ ctl, unsigned long long *__restrict__ queue, int maxA, int maxG, int maxin,
@@ -440,6 +440,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         LaneIn L;
         // a continuation is in the same problem and octant: its directions are in LDS
         const bool new_om = !ONE || cface < 0;
+        // per-angle designation: every wave holds the per-direction inflow masks
+        // of this (octant, cell), lane a those of direction a (A <= 64)
+        int amv = 0;
+        if constexpr (PA)
+            if (P.amask && (tid & 63) < A) amv = gp(P.amask)[((size_t)o * C + K) * A + (tid & 63)];
         if (new_om && tid < A) {
             const int n = o * A + tid;
             om4 = make_float4(gp(P.omega)[3 * n + 0], gp(P.omega)[3 * n + 1], gp(P.omega)[3 * n + 2], gp(P.w)[n]);
@@ -501,6 +506,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             if (cface < 0) early_up(s_desc);
         const int mask = uni(s_desc[12]);
         const int nin = __popc(mask);
+        // faces where some direction's designation differs from the octant's
+        const int lagm = PA && P.amask ? uni((s_desc[13] >> 18) & 63) : 0;
         int nb[6];
         unsigned pm[6];
 #pragma unroll
@@ -552,6 +559,43 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 for (int n = wv; n < A; n += kWaves) {
                     const float4 om = reinterpret_cast<const float4 *>(sOm)[n];
                     if (s1 < nin) sC[(n * maxin + s1) * 16 + (lane & 15)] = om.x * cx + om.y * cy + om.z * cz;
+                }
+            }
+            if (PA && lagm) {
+                // Per-angle designation: direction n's operator is
+                // B_n = Om.S - sum over its own inflow faces of Om.F_f, so each face
+                // where its designation differs from the octant's adds Om.F_f
+                // (inflow for the octant only) or subtracts it (inflow for the
+                // direction only), and the inflow slot of an octant-inflow face
+                // that is outflow for the direction is cleared.  Each lane updates
+                // the entries it wrote above, so no barrier is needed.
+                auto slot_face = [&](int s) {
+                    int m = mask;
+                    for (int k = 0; k < s; ++k) m &= m - 1;
+                    return m ? __ffs(m) - 1 : -1;
+                };
+                const int fs0 = s0 < nin ? slot_face(s0) : -1;
+                const int fs1 = 4 + s0 < nin ? slot_face(4 + s0) : -1;
+                const int i = lane >> 3, j = lane & 7;
+                for (int n = wv; n < A; n += kWaves) {
+                    const int dif = __builtin_amdgcn_readlane(amv, n) ^ mask;
+                    if (!dif) continue;
+                    const float4 om = om4s[n];
+                    float dB = 0.f;
+                    for (int m = dif; m; m &= m - 1) {
+                        const int f = __builtin_ctz(m), axis = f >> 1, side = f & 1;
+                        if (((i >> axis) & 1) == side && ((j >> axis) & 1) == side) {
+                            const int ki = axis == 0 ? i >> 1 : (axis == 1 ? (i & 1) | ((i >> 2) << 1) : i & 3);
+                            const int kj = axis == 0 ? j >> 1 : (axis == 1 ? (j & 1) | ((j >> 2) << 1) : j & 3);
+                            const float *Ff = sF + 48 * f + 4 * ki + kj;
+                            const float c = om.x * Ff[0] + om.y * Ff[16] + om.z * Ff[32];
+                            dB += (mask >> f) & 1 ? c : -c;
+                        }
+                    }
+                    sB[n * 64 + lane] += dB;
+                    const int gone = dif & mask;
+                    if (fs0 >= 0 && ((gone >> fs0) & 1)) sC[(n * maxin + s0) * 16 + (lane & 15)] = 0.f;
+                    if (fs1 >= 0 && ((gone >> fs1) & 1)) sC[(n * maxin + 4 + s0) * 16 + (lane & 15)] = 0.f;
                 }
             }
         }
@@ -643,6 +687,40 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                             t = __builtin_fmaf(Cs[k * 4 + 1], u[1], t);
                             t = __builtin_fmaf(Cs[k * 4 + 2], u[2], t);
                             t = __builtin_fmaf(Cs[k * 4 + 3], u[3], t);
+                            b[face_vertex(f, k)] -= t;
+                        }
+                    }
+                }
+                if (const int lf = PA ? lagm & ~mask : 0) {
+                    // Per-angle designation: a face that is inflow for this direction
+                    // but downwind in the octant's order takes the neighbour's trace
+                    // from the previous sweep (its task runs after this one, so the
+                    // value is still there), or psi_b on the boundary.
+                    const int mine = __builtin_amdgcn_ds_bpermute(n << 2, amv);
+                    const float4 om = reinterpret_cast<const float4 *>(sOm)[n];
+#pragma unroll
+                    for (int f = 0; f < 6; ++f) {
+                        if (!((lf >> f) & 1) || !((mine >> f) & 1)) continue;
+                        float u[4];
+                        if (nb[f] >= 0) {
+                            const __amdgpu_buffer_rsrc_t rs = cell_block(psi_o, nb[f], 8 * AG);
+#pragma unroll
+                            for (int l = 0; l < 4; ++l)
+                                u[l] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                    rs, 4 * pi, (int)((pm[f] >> (8 * l)) & 0xff) * AG * 4, kCoherentAccess));
+                        } else {
+#pragma unroll
+                            for (int l = 0; l < 4; ++l) u[l] = psib;
+                        }
+                        const float *Ff = sF + 48 * f;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            float t = 0.f;
+#pragma unroll
+                            for (int l = 0; l < 4; ++l) {
+                                const float c = om.x * Ff[4 * k + l] + om.y * Ff[16 + 4 * k + l] + om.z * Ff[32 + 4 * k + l];
+                                t = __builtin_fmaf(c, u[l], t);
+                            }
                             b[face_vertex(f, k)] -= t;
                         }
                     }
@@ -847,14 +925,21 @@ template <int NT, bool ONE, bool BSP>
 hipError_t launch_nt(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                      unsigned long long *queue, int maxA, int maxG, int maxin, int grid, size_t lds,
                      unsigned long long watchdog, const long long *bsp_tasks, long long b0, long long b1,
-                     const int *stops, int phase_stats, hipStream_t s) {
-    hipLaunchKernelGGL((k_sweep<NT, ONE, BSP>), dim3(grid), dim3(NT), lds, s, probs, nprob, task_base, ctl, queue,
-                       maxA, maxG, maxin, watchdog, bsp_tasks, b0, b1, stops, phase_stats);
+                     const int *stops, int phase_stats, bool pa, hipStream_t s) {
+    if (pa)
+        hipLaunchKernelGGL((k_sweep<NT, ONE, BSP, true>), dim3(grid), dim3(NT), lds, s, probs, nprob, task_base, ctl,
+                           queue, maxA, maxG, maxin, watchdog, bsp_tasks, b0, b1, stops, phase_stats);
+    else
+        hipLaunchKernelGGL((k_sweep<NT, ONE, BSP, false>), dim3(grid), dim3(NT), lds, s, probs, nprob, task_base, ctl,
+                           queue, maxA, maxG, maxin, watchdog, bsp_tasks, b0, b1, stops, phase_stats);
     return hipGetLastError();
 }
 
 template <int NT, bool ONE>
-const void *kernel_ptr() { return reinterpret_cast<const void *>(&k_sweep<NT, ONE, false>); }
+const void *kernel_ptr(bool pa) {
+    return pa ? reinterpret_cast<const void *>(&k_sweep<NT, ONE, false, true>)
+              : reinterpret_cast<const void *>(&k_sweep<NT, ONE, false, false>);
+}
 
 }  // namespace
 
@@ -868,14 +953,14 @@ size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin, bool one) {
     return floats * sizeof(float);
 }
 
-int sweep_occupancy(int threads, bool one, size_t lds) {
+int sweep_occupancy(int threads, bool one, bool pa, size_t lds) {
     const void *k = nullptr;
     switch (threads) {
-        case 64: k = one ? kernel_ptr<64, true>() : kernel_ptr<64, false>(); break;
-        case 128: k = one ? kernel_ptr<128, true>() : kernel_ptr<128, false>(); break;
-        case 192: k = one ? kernel_ptr<192, true>() : kernel_ptr<192, false>(); break;
-        case 256: k = one ? kernel_ptr<256, true>() : kernel_ptr<256, false>(); break;
-        case 512: k = one ? kernel_ptr<512, true>() : kernel_ptr<512, false>(); break;
+        case 64: k = one ? kernel_ptr<64, true>(pa) : kernel_ptr<64, false>(pa); break;
+        case 128: k = one ? kernel_ptr<128, true>(pa) : kernel_ptr<128, false>(pa); break;
+        case 192: k = one ? kernel_ptr<192, true>(pa) : kernel_ptr<192, false>(pa); break;
+        case 256: k = one ? kernel_ptr<256, true>(pa) : kernel_ptr<256, false>(pa); break;
+        case 512: k = one ? kernel_ptr<512, true>(pa) : kernel_ptr<512, false>(pa); break;
         default: return 0;
     }
     int nb = 0;
@@ -896,14 +981,14 @@ hipError_t launch_xcc_probe(int *out, int nblocks, hipStream_t s) {
 
 hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                                unsigned long long *queue, int threads, bool one, int grid, int maxA, int maxG,
-                               int maxin, unsigned long long watchdog, bool phase_stats, hipStream_t s) {
+                               int maxin, unsigned long long watchdog, bool phase_stats, bool pa, hipStream_t s) {
     const size_t lds = sweep_lds_bytes(threads, maxA, maxG, maxin, one);
     const int ps = phase_stats ? 1 : 0;
 #define SNX_LAUNCH(NT)                                                                                             \
     return one ? launch_nt<NT, true, false>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds,      \
-                                            watchdog, nullptr, 0, 0, nullptr, ps, s)                               \
+                                            watchdog, nullptr, 0, 0, nullptr, ps, pa, s)                           \
                : launch_nt<NT, false, false>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds,     \
-                                             watchdog, nullptr, 0, 0, nullptr, ps, s)
+                                             watchdog, nullptr, 0, 0, nullptr, ps, pa, s)
     switch (threads) {
         case 64: SNX_LAUNCH(64);
         case 128: SNX_LAUNCH(128);
@@ -918,16 +1003,16 @@ hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long lo
 hipError_t launch_sweep_level(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                               int threads, bool one, int grid, int maxA, int maxG, int maxin,
                               const long long *bsp_tasks, long long begin, long long end, const int *stops,
-                              hipStream_t s) {
+                              bool pa, hipStream_t s) {
     const size_t lds = sweep_lds_bytes(threads, maxA, maxG, maxin, one);
     const long long n = end - begin;
     if (n <= 0) return hipSuccess;
     const int g = (int)std::min<long long>(grid, n);
 #define SNX_LAUNCH(NT)                                                                                             \
     return one ? launch_nt<NT, true, true>(probs, nprob, task_base, ctl, nullptr, maxA, maxG, maxin, g, lds, 0,     \
-                                           bsp_tasks, begin, end, stops, 0, s)                                     \
+                                           bsp_tasks, begin, end, stops, 0, pa, s)                                 \
                : launch_nt<NT, false, true>(probs, nprob, task_base, ctl, nullptr, maxA, maxG, maxin, g, lds, 0,    \
-                                            bsp_tasks, begin, end, stops, 0, s)
+                                            bsp_tasks, begin, end, stops, 0, pa, s)
     switch (threads) {
         case 64: SNX_LAUNCH(64);
         case 128: SNX_LAUNCH(128);

@@ -22,7 +22,9 @@ constexpr int kGnnFeatures = 12; // node features of the learned initial guess (
 // Task record of one (octant, cell), 96 ints (24 int4): words 0..12 the cell's
 // descriptor (neighbour ids [6], node permutations [6], inflow mask of the
 // octant), word 13 the in-degree of the downwind neighbour across face f in
-// bits 3f..3f+2, 14..15 zero, then for each face f at 16 + 13 f the descriptor
+// bits 3f..3f+2 and, under per-angle designation, in bits 18..23 the faces on
+// which some direction of the octant differs from the octant's designation,
+// 14..15 zero, then for each face f at 16 + 13 f the descriptor
 // of the neighbour across f when f is a downwind face (zero otherwise), 94..95
 // zero.
 constexpr int kRecWords = 96;
@@ -79,6 +81,8 @@ struct DevProblem {
     const int *nbr;              // [C][6]        neighbour across face, -1 on the boundary
     const unsigned *perm;        // [C][6]        neighbour's local vertex at my face node k, 8 bits each
     const unsigned char *inmask; // [8][C]        inflow-face bit mask per octant
+    const unsigned char *amask;  // [8][C][A]     per-angle designation: inflow faces of each direction; nullptr
+                                 //               for per-octant designation
     const float *T;              // [8][C][3][64] T^a = S^a - sum_{f inflow} F^a_f (embedded), per octant
     const int *indeg;            // [8][C]        interior inflow faces per octant
     const float *sigt;           // [C][G]
@@ -120,22 +124,31 @@ hipError_t launch_sweep_prologue(SweepCtl *ctl, unsigned long long *queue, const
                                  const int *seeds, const int *seed_off, const int *stops, hipStream_t s);
 hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                                unsigned long long *queue, int threads, bool one, int grid, int maxA, int maxG, int maxin,
-                               unsigned long long watchdog, bool phase_stats, hipStream_t s);
+                               unsigned long long watchdog, bool phase_stats, bool pa, hipStream_t s);
 // One level of the bulk-synchronous comparator: tasks bsp_tasks[begin, end).
 hipError_t launch_sweep_level(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                               int threads, bool one, int grid, int maxA, int maxG, int maxin,
                               const long long *bsp_tasks, long long begin, long long end, const int *stops,
-                              hipStream_t s);
+                              bool pa, hipStream_t s);
 hipError_t launch_xcc_probe(int *out, int nblocks, hipStream_t s);
 hipError_t launch_task_records(int C, const int *nbr, const unsigned *perm, const unsigned char *inmask,
-                               const int *indeg, int *rec, hipStream_t s);
+                               const int *indeg, const unsigned char *lagm, int *rec, hipStream_t s);
+// Per-angle designation: amask[8][C][A] (bit f: Omega_n . A_f < 0), lagm[8][C]
+// (faces where a direction of the octant differs from the octant's mask) and
+// counts[3] += differing (direction, cell, face) triples, lagged ones (interior
+// faces inflow for the direction and outflow for the octant), cells x octants
+// with a difference; err |= 8 for a face tangent to a direction.
+hipError_t launch_angle_masks(int C, int A, const double *omega, const int *nbr, const double *area,
+                              const unsigned char *inmask, unsigned char *amask, unsigned char *lagm,
+                              unsigned long long *counts, int *err, hipStream_t s);
 hipError_t launch_octant_operators(int C, const float *S, const float *F, const unsigned char *inmask, float *T,
                                    hipStream_t s);
 // Workgroup widths of the sweep kernel: 64, 128, 192, 256 or 512.
 bool sweep_threads_valid(int threads);
 // `one`: every problem of the launch has (angles per octant) * G <= threads.
 size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin, bool one);
-int sweep_occupancy(int threads, bool one, size_t lds);
+// pa: the kernel variant with per-angle designation (any problem of the schedule uses it)
+int sweep_occupancy(int threads, bool one, bool pa, size_t lds);
 hipError_t launch_source(const DevProblem *probs, int prob, int C, int G, const float *phi, int *stop_flag,
                          hipStream_t s);
 hipError_t launch_reduce(const DevProblem *probs, int prob, int C, int G, float *phi_out, const float *phi_old,
