@@ -87,6 +87,27 @@ def paper_shape(steps: int = 25):
             "paper_cpu_s_context": PAPER_SHAPE_CPU_S}
 
 
+def per_angle(prob, threads: int, wg_per_cu: int, ms_octant: float, its_octant: int, sweeps: int):
+    """The same workload under per-angle designation (each direction's own inflow
+    faces, lagged where they go against the octant's order): sweep time in the
+    same schedule, the designation counts, and source iterations to the
+    workload's tolerance beside the per-octant count."""
+    from paper_2510_11513_amd import snx
+    p = snx.Problem.from_problem(prob, setup=False, designation=snx.DESIGNATION_ANGLE)
+    p.set_schedule(threads=threads, wg_per_cu=wg_per_cu)
+    p.setup()
+    phi = p.sweep(None)
+    ms = p.profile_sweep(sweeps, phi_in=phi)
+    ds = p.designation_stats()
+    _, info = p.solve(prob.tol, 5000)
+    p.close()
+    return {"sweep_ms": round(ms, 4), "per_octant_sweep_ms": round(ms_octant, 4),
+            "ratio": round(ms / ms_octant, 3), "differing_triples": ds["differing"],
+            "lagged_triples": ds["lagged"], "tasks_with_difference": ds["tasks"],
+            "iterations_to_tol": info["iterations"], "per_octant_iterations_to_tol": its_octant,
+            "tol": prob.tol}
+
+
 def kernel_hash() -> str:
     path = os.path.join(ROOT, "paper_2510_11513_amd", "csrc", "k_sweep.hip")
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
@@ -169,6 +190,8 @@ def main():
     ap.add_argument("--learned", type=int, default=4,
                     help="held-out high-scattering instances for the learned-start comparison (0 = skip)")
     ap.add_argument("--paper-shape", type=int, default=1, help="also time the paper's 25-sweep 16^3 shape (0 = skip)")
+    ap.add_argument("--per-angle", type=int, default=1,
+                    help="also time the workload under per-angle designation (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -256,6 +279,11 @@ def main():
     tflops = fpt * solves_per_step / (ms_sweep * 1e-3) / 1e12
     out["valu"] = {"achieved": round(tflops, 2), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                    "frac": round(tflops / FP32_VALU_PEAK_TFLOPS, 4), "flops_per_solve": round(fpt, 1)}
+    if args.per_angle:
+        print("[bench] per-angle designation", file=sys.stderr, flush=True)
+        _, info_oct = p.solve(prob.tol, 5000)
+        out["per_angle"] = per_angle(prob, stats["threads"], tuned[1] if tuned else args.wg_per_cu, ms_sweep,
+                                     info_oct["iterations"], max(5, min(args.steps, 20)))
     if args.paper_shape:
         out["paper_shape"] = paper_shape()
     if args.learned > 0:
