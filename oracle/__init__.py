@@ -61,6 +61,9 @@ def lib():
         L.snxo_set_hooks.argtypes = [vp, nullable_d, nullable_d]
         L.snxo_setup.argtypes = [vp]
         L.snxo_set_designation.argtypes = [vp, ct.c_int]
+        L.snxo_set_group_scattering.argtypes = [vp, ct.c_int, nullable_d, nullable_d]
+        L.snxo_solve_outer.argtypes = [vp, ct.c_int, ct.c_int, ct.c_double, nullable_d, _dp,
+                                       ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), ct.POINTER(ct.c_double)]
         L.snxo_sweep.argtypes = [vp, nullable_d, nullable_d, _dp, nullable_d, nullable_d, nullable_d]
         L.snxo_sweep_angle.argtypes = [vp, nullable_d, ct.c_int, ct.c_int, nullable_d, _dp]
         L.snxo_solve.argtypes = [vp, ct.c_double, ct.c_int, nullable_d, _dp,
@@ -151,6 +154,31 @@ class Oracle:
 
     def setup(self):
         self._check(lib().snxo_setup(self.h), "setup")
+
+    def set_group_scattering(self, cell_mat, sigma_gg):
+        """cell_mat[ncell] int, sigma_gg[nmat][G][G] from group g' (axis 1) into g (axis 2);
+        None clears it."""
+        if sigma_gg is None:
+            self._cmat = self._sgg = None
+            self._check(lib().snxo_set_group_scattering(self.h, 0, None, None), "set_group_scattering")
+            return
+        self._cmat = np.ascontiguousarray(cell_mat, np.int32)
+        self._sgg = np.ascontiguousarray(sigma_gg, np.float64)
+        if self._sgg.ndim != 3 or self._sgg.shape[1:] != (self.G, self.G) or self._cmat.shape != (self.ncell,):
+            raise ValueError("cell_mat must be [ncell] and sigma_gg [nmat][G][G]")
+        self._check(lib().snxo_set_group_scattering(self.h, self._sgg.shape[0], _ptr(self._cmat), _ptr(self._sgg)),
+                    "set_group_scattering")
+
+    def solve_outer(self, outer, inner, tol=0.0, phi0=None, allow_noconv=False):
+        """Inner/outer iterations (see snxo_solve_outer)."""
+        phi = self.zeros_phi()
+        ko, ki, eps = ct.c_int(0), ct.c_int(0), ct.c_double(0.0)
+        p0 = None if phi0 is None else np.ascontiguousarray(phi0, np.float64)
+        rc = lib().snxo_solve_outer(self.h, int(outer), int(inner), float(tol), _ptr(p0), phi, ct.byref(ko),
+                                    ct.byref(ki), ct.byref(eps))
+        if rc and not (allow_noconv and rc == -7):
+            self._check(rc, "solve_outer")
+        return {"phi": phi, "outers": ko.value, "inners": ki.value, "eps": eps.value, "status": rc}
 
     def __del__(self):
         h = getattr(self, "h", None)

@@ -32,6 +32,9 @@ struct snxo_problem {
     int32_t *nbr, *nbrf, *perm;     /* [C][6], [C][6], [C][6][4] */
     int32_t *inflow, *level, *order;/* [8][C] each */
     int designation;                /* 0 per octant, 1 per angle (snxo_set_designation) */
+    int nmat;                       /* group-to-group scattering (snxo_set_group_scattering), 0 = none */
+    int32_t *cmat;                  /* [C] material of each cell */
+    double *sgg;                    /* [nmat][G][G] from group g' (row) into group g (column) */
     int32_t *ain;                   /* designation 1: [nang][C] inflow faces of each angle */
     char err[256];
 };
@@ -206,6 +209,7 @@ void snxo_destroy(snxo_problem *p) {
     free_derived(p);
     free(p->xyz); free(p->cv); free(p->omega); free(p->w);
     free(p->sigt); free(p->sigs); free(p->q); free(p->psib);
+    free(p->cmat); free(p->sgg);
     free(p);
 }
 
@@ -273,6 +277,25 @@ int snxo_set_designation(snxo_problem *p, int kind) {
     if (!p || (kind != 0 && kind != 1)) return fail(p, SNXO_E_ARG, "designation must be 0 or 1");
     p->designation = kind;
     free_derived(p);
+    return SNXO_OK;
+}
+
+int snxo_set_group_scattering(snxo_problem *p, int nmat, const int32_t *cell_mat, const double *sigma_gg) {
+    if (!p || p->G < 1 || p->ncell < 1) return fail(p, SNXO_E_STATE, "set the mesh and materials first");
+    free(p->cmat); free(p->sgg);
+    p->cmat = NULL; p->sgg = NULL; p->nmat = 0;
+    if (nmat == 0) return SNXO_OK;
+    if (nmat < 0 || !cell_mat || !sigma_gg) return fail(p, SNXO_E_ARG, "bad group scattering arguments");
+    for (int K = 0; K < p->ncell; ++K)
+        if (cell_mat[K] < 0 || cell_mat[K] >= nmat) return fail(p, SNXO_E_ARG, "material index out of range");
+    size_t n = (size_t)nmat * p->G * p->G;
+    for (size_t i = 0; i < n; ++i)
+        if (!(sigma_gg[i] >= 0.0)) return fail(p, SNXO_E_ARG, "scattering cross sections must be >= 0");
+    p->cmat = malloc(sizeof(int32_t) * (size_t)p->ncell);
+    p->sgg = dup_d(sigma_gg, n);
+    if (!p->cmat || !p->sgg) return fail(p, SNXO_E_OOM, "out of memory");
+    memcpy(p->cmat, cell_mat, sizeof(int32_t) * (size_t)p->ncell);
+    p->nmat = nmat;
     return SNXO_OK;
 }
 
@@ -634,13 +657,42 @@ static int solve_local(const snxo_problem *p, int K, int n, int g, const double 
     return 0;
 }
 
+/* Nodal isotropic source of (cell K, group g) per unit solid angle:
+ * (Q + scattering into g) / (4 pi) at each of the 8 nodes (Eq. 1 with
+ * isotropic scattering).  Without a group matrix the scattering is
+ * sigma_s phi_g (within the group).  With one it is
+ * sum over g' of sigma(g' -> g) phi_g', the diagonal taken from phi_in and the
+ * other groups from qouter when given (the cross-group source of an outer
+ * iteration, held fixed during its inner iterations), else from phi_in too. */
+static void source_nodal(const snxo_problem *p, const double *phi_in, const double *qouter, int K, int g,
+                         double qn[8]) {
+    int G = p->G;
+    for (int j = 0; j < 8; ++j) {
+        double ph = phi_in ? phi_in[((long)K * G + g) * 8 + j] : 0.0;
+        double sc;
+        if (!p->sgg) {
+            sc = p->sigs[(long)K * G + g] * ph;
+        } else {
+            const double *S = p->sgg + (size_t)p->cmat[K] * G * G;
+            sc = S[(long)g * G + g] * ph;
+            if (qouter) {
+                sc += qouter[((long)K * G + g) * 8 + j];
+            } else {
+                for (int h = 0; h < G; ++h)
+                    if (h != g && phi_in) sc += S[(long)h * G + g] * phi_in[((long)K * G + h) * 8 + j];
+            }
+        }
+        qn[j] = (p->q[(long)K * G + g] + sc) / (4.0 * PI);
+    }
+}
+
 /* The cells of an angle are visited in the octant's topological order, so
  * under designation 0 every inflow neighbour is already done.  Under
  * designation 1 an inflow neighbour that comes later in that order still
  * holds the previous sweep's value in psi_cur (initialised from psi_prev):
  * that face is lagged. */
-int snxo_sweep(snxo_problem *p, const double *phi_in, const double *psi_prev, double *phi_out,
-               double *psi_all, double *leak, double *leak_ang) {
+static int sweep_src(snxo_problem *p, const double *phi_in, const double *qouter, const double *psi_prev,
+                     double *phi_out, double *psi_all, double *leak, double *leak_ang) {
     if (!p || !p->ready) return fail(p, SNXO_E_STATE, "setup has not run");
     if (!phi_out) return fail(p, SNXO_E_ARG, "phi_out is NULL");
     int C = p->ncell, G = p->G, nang = p->nang, per = nang / 8;
@@ -665,10 +717,7 @@ int snxo_sweep(snxo_problem *p, const double *phi_in, const double *psi_prev, do
                     if (p->ang_src) {
                         for (int j = 0; j < 8; ++j) qn[j] = p->ang_src[(((long)K * nang + n) * G + g) * 8 + j];
                     } else {
-                        for (int j = 0; j < 8; ++j) {
-                            double ph = phi_in ? phi_in[((long)K * G + g) * 8 + j] : 0.0;
-                            qn[j] = (p->q[(long)K * G + g] + p->sigs[(long)K * G + g] * ph) / (4.0 * PI);
-                        }
+                        source_nodal(p, phi_in, qouter, K, g, qn);
                     }
                     if (solve_local(p, K, n, g, qn, psi_cur, x, (leak || leak_ang) ? &L : NULL)) { bad = 1; break; }
                     for (int j = 0; j < 8; ++j) {
@@ -684,6 +733,11 @@ int snxo_sweep(snxo_problem *p, const double *phi_in, const double *psi_prev, do
     }
     if (bad) return fail(p, SNXO_E_MESH, "singular local system or out of memory");
     return SNXO_OK;
+}
+
+int snxo_sweep(snxo_problem *p, const double *phi_in, const double *psi_prev, double *phi_out,
+               double *psi_all, double *leak, double *leak_ang) {
+    return sweep_src(p, phi_in, NULL, psi_prev, phi_out, psi_all, leak, leak_ang);
 }
 
 /* The sweep of one (angle n, group g) alone: psi_out[ncell][8] receives that
@@ -705,10 +759,7 @@ int snxo_sweep_angle(snxo_problem *p, const double *phi_in, int n, int g, const 
         if (p->ang_src) {
             for (int j = 0; j < 8; ++j) qn[j] = p->ang_src[(((long)K * nang + n) * G + g) * 8 + j];
         } else {
-            for (int j = 0; j < 8; ++j) {
-                double ph = phi_in ? phi_in[((long)K * G + g) * 8 + j] : 0.0;
-                qn[j] = (p->q[(long)K * G + g] + p->sigs[(long)K * G + g] * ph) / (4.0 * PI);
-            }
+            source_nodal(p, phi_in, NULL, K, g, qn);
         }
         if (solve_local(p, K, n, g, qn, psi_out, x, NULL)) return fail(p, SNXO_E_MESH, "singular local system");
         for (int j = 0; j < 8; ++j) psi_out[8L * K + j] = x[j];
@@ -756,6 +807,61 @@ int snxo_solve(snxo_problem *p, double tol, int max_it, const double *phi0,
     return e <= tol ? SNXO_OK : SNXO_E_NOCONV;
 }
 
+/* Inner and outer iterations (the benchmark of Section 3.6 runs five of each):
+ * each outer iteration fixes the cross-group scattering source from its
+ * starting flux, then runs `inner` source iterations with the within-group
+ * scattering only; it ends with the relative max-norm change of the flux over
+ * the outer iteration.  Stops after `outer` outer iterations, or earlier when
+ * tol > 0 and the change is <= tol.  Without a group matrix the cross-group
+ * source is zero.  Designation 1 carries the angular flux across all sweeps. */
+int snxo_solve_outer(snxo_problem *p, int outer, int inner, double tol, const double *phi0, double *phi_out,
+                     int *outers_done, int *inners_done, double *eps) {
+    if (!p || !p->ready) return fail(p, SNXO_E_STATE, "setup has not run");
+    if (!phi_out || outer < 1 || inner < 1 || !(tol >= 0.0)) return fail(p, SNXO_E_ARG, "bad solve arguments");
+    int C = p->ncell, G = p->G;
+    size_t n = 8 * (size_t)C * G;
+    double *start = malloc(sizeof(double) * n), *x = malloc(sizeof(double) * n), *qo = calloc(n, sizeof(double));
+    double *psi = p->designation == 1 ? calloc(n * (size_t)p->nang, sizeof(double)) : NULL;
+    if (!start || !x || !qo || (p->designation == 1 && !psi)) {
+        free(start); free(x); free(qo); free(psi);
+        return fail(p, SNXO_E_OOM, "out of memory");
+    }
+    if (phi0) memcpy(start, phi0, sizeof(double) * n); else memset(start, 0, sizeof(double) * n);
+    int k = 0, it = 0, rc = SNXO_OK;
+    double e = INFINITY;
+    while (k < outer) {
+        if (p->sgg)
+            for (int K = 0; K < C; ++K) {
+                const double *S = p->sgg + (size_t)p->cmat[K] * G * G;
+                for (int g = 0; g < G; ++g)
+                    for (int j = 0; j < 8; ++j) {
+                        double v = 0.0;
+                        for (int h = 0; h < G; ++h)
+                            if (h != g) v += S[(long)h * G + g] * start[((long)K * G + h) * 8 + j];
+                        qo[((long)K * G + g) * 8 + j] = v;
+                    }
+            }
+        memcpy(x, start, sizeof(double) * n);
+        for (int i = 0; i < inner && !rc; ++i) {
+            rc = sweep_src(p, x, qo, psi, phi_out, psi, NULL, NULL);
+            if (!rc) memcpy(x, phi_out, sizeof(double) * n);
+            ++it;
+        }
+        if (rc) break;
+        e = rel_change(x, start, n);
+        memcpy(start, x, sizeof(double) * n);
+        ++k;
+        if (tol > 0.0 && e <= tol) break;
+    }
+    memcpy(phi_out, start, sizeof(double) * n);
+    free(start); free(x); free(qo); free(psi);
+    if (outers_done) *outers_done = k;
+    if (inners_done) *inners_done = it;
+    if (eps) *eps = e;
+    if (rc) return rc;
+    return (tol == 0.0 || e <= tol) ? SNXO_OK : SNXO_E_NOCONV;
+}
+
 /* Cell balance of one sweep: source 1^T M (Q + sigma_s phi_in) equals
  * absorption sigma_t 1^T M phi_out plus angle-weighted net outflow. */
 int snxo_balance(snxo_problem *p, const double *phi_in, const double *phi_out,
@@ -767,11 +873,11 @@ int snxo_balance(snxo_problem *p, const double *phi_in, const double *phi_out,
         double src = 0.0, ab = 0.0, lk = 0.0, worst = 0.0;
         for (int K = 0; K < C; ++K) {
             const double *M = p->M + 64L * K;
-            double s = 0.0, a = 0.0;
+            double s = 0.0, a = 0.0, qn[8];
+            source_nodal(p, phi_in, NULL, K, g, qn);
             for (int i = 0; i < 8; ++i)
                 for (int j = 0; j < 8; ++j) {
-                    double ph = phi_in ? phi_in[((long)K * G + g) * 8 + j] : 0.0;
-                    s += M[8 * i + j] * (p->q[(long)K * G + g] + p->sigs[(long)K * G + g] * ph);
+                    s += M[8 * i + j] * 4.0 * PI * qn[j];
                     a += M[8 * i + j] * p->sigt[(long)K * G + g] * phi_out[((long)K * G + g) * 8 + j];
                 }
             double l = leak[(long)K * G + g];

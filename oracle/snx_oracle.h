@@ -18,7 +18,9 @@
  *   - upwind faces designated once per octant, or per angle (the mesh
  *     traversal of each direction, Section 2.1) with lagged faces where a
  *     direction's own dependencies go against its octant's order;
- *   - source iteration, and the integrated flux of Eq. 3.
+ *   - source iteration, inner and outer iterations over a group-to-group
+ *     scattering matrix (the benchmark of Section 3.6), and the integrated
+ *     flux of Eq. 3.
  *
  * All arithmetic is double precision; local systems use LU with partial
  * pivoting.  Every reading of a point the paper leaves open (node ordering,
@@ -68,6 +70,12 @@ int  snxo_set_materials(snxo_problem *p, int ngroup, const double *sigma_t,
                         const double *sigma_s, const double *q);
 /* kind 0 = vacuum, 1 = isotropic inflow psi_b[g] on every inflow boundary face. */
 int  snxo_set_boundary(snxo_problem *p, int kind, const double *psi_b);
+/* Group-to-group isotropic scattering (after snxo_set_materials; nmat = 0
+ * clears it): cell_mat[ncell] material of each cell, sigma_gg[nmat][G][G]
+ * with [m][g'][g] the cross section from group g' into group g.  When set, its
+ * diagonal replaces sigma_s and the source of group g is
+ * Q + sum_g' sigma(g' -> g) phi_g'. */
+int  snxo_set_group_scattering(snxo_problem *p, int nmat, const int32_t *cell_mat, const double *sigma_gg);
 /* Test hooks (may be NULL to clear).  ang_src[ncell][nang][G][8]: nodal values
  * of an angle-dependent source replacing (Q + sigma_s phi)/(4 pi).
  * bnd_in[ncell][6][nang][G][4]: nodal inflow values on boundary faces. */
@@ -106,6 +114,15 @@ int  snxo_sweep_angle(snxo_problem *p, const double *phi_in, int n, int g, const
  * Designation 1 carries the angular flux from sweep to sweep, zero at the start. */
 int  snxo_solve(snxo_problem *p, double tol, int max_it, const double *phi0,
                 double *phi_out, int *iters, double *eps, double *hist);
+
+/* Inner and outer iterations: each outer iteration fixes the cross-group
+ * source sum_{g' != g} sigma(g' -> g) phi_g' from its starting flux and runs
+ * `inner` source iterations with the within-group scattering; it ends with the
+ * relative max-norm change over the outer iteration.  Runs `outer` outer
+ * iterations, or stops earlier when tol > 0 and the change is <= tol (then
+ * SNXO_E_NOCONV if it never is).  Counts and the last change are returned. */
+int  snxo_solve_outer(snxo_problem *p, int outer, int inner, double tol, const double *phi0, double *phi_out,
+                      int *outers_done, int *inners_done, double *eps);
 
 /* Particle balance of one sweep phi_in -> phi_out with its leak[ncell][G]:
  * out[G][4] = source, absorption, leakage, max cell relative imbalance. */
