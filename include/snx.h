@@ -100,6 +100,21 @@ snx_status snx_set_materials(snx_problem *p, int32_t ngroup, const double *sigma
  * kind 1 = isotropic inflow psi_in[G] (host float64). */
 snx_status snx_set_boundary(snx_problem *p, int32_t kind, const double *psi_in);
 
+/* Group-to-group isotropic scattering (the energy coupling that the paper's
+ * outer iterations resolve, §3.6; after snx_set_materials, before snx_setup;
+ * nmat = 0 removes it).  cell_mat: host int32 [ncell], the material of each
+ * cell (0 <= m < nmat).  sigma_gg: host float64 [nmat][G][G], entry [m][g'][g]
+ * the cross section from group g' into group g (finite, >= 0).  Its diagonal
+ * replaces the sigma_s of snx_set_materials, and the source of group g becomes
+ * Q_g + sum over g' of sigma(g' -> g) phi_g'.  Under a matrix:
+ * - snx_sweep takes the whole source from phi_in (one Jacobi step over groups);
+ * - snx_solve is snx_solve_outer with one inner iteration;
+ * - snx_balance counts the cross-group source;
+ * - batches reject the problem (SNX_E_ARG at snx_batch_create).
+ * Errors: SNX_E_STATE before the materials, SNX_E_ARG for an index out of
+ * range or a negative or non-finite entry. */
+snx_status snx_set_group_scattering(snx_problem *p, int32_t nmat, const int32_t *cell_mat, const double *sigma_gg);
+
 /* Upwind designation, used by the next snx_setup (a change undoes any earlier
  * setup).
  * SNX_DESIGNATION_OCTANT (default): face f of cell K is inflow for every
@@ -141,6 +156,24 @@ snx_status snx_sweep(snx_problem *p, const float *phi_in, float *phi_out, void *
  * SNX_E_DEVICE on a watchdog expiry. */
 snx_status snx_solve(snx_problem *p, double tol, int32_t max_it, const float *phi0,
                      float *phi, snx_solve_info *info, void *stream);
+
+/* Inner and outer iterations (the paper's benchmark runs five of each, §3.6).
+ * - Each outer iteration computes the cross-group scattering source
+ *   sum over g' != g of sigma(g' -> g) phi_g' from its starting flux.
+ * - It then runs `inner` source iterations with the within-group scattering,
+ *   graph-captured as in snx_solve.
+ * - It ends with the FP64 relative max-norm change of the flux over the outer
+ *   iteration.
+ * The solve stops after `outer` outer iterations, or earlier when tol > 0 and
+ * the change is <= tol.  Without a group matrix the cross-group source is zero.
+ * phi0: device [ncell][G][8], or NULL for a zero start; it may equal phi.
+ * phi: device out.
+ * info (nullable) receives the total inner iterations, the last outer change,
+ * the wall time and the solve rate.
+ * Synchronous on stream.  Returns SNX_E_NOCONV when tol > 0 is not reached;
+ * phi then still holds the last iterate. */
+snx_status snx_solve_outer(snx_problem *p, int32_t outer, int32_t inner, double tol, const float *phi0, float *phi,
+                           snx_solve_info *info, void *stream);
 
 /* Particle balance (FP64) of the most recent sweep, which must have started
  * from device phi_in (NULL = zero) and produced device phi_out.  host out[G][4]

@@ -109,6 +109,9 @@ struct snx_problem {
     std::vector<int> cv;
     bool have_mesh = false, have_quad = false, have_mat = false;
     int designation = SNX_DESIGNATION_OCTANT;
+    int nmat = 0;                       // group-to-group scattering (snx_set_group_scattering), 0 = none
+    std::vector<int> cmat;              // [C]
+    std::vector<double> sgg;            // [nmat][G][G], from g' into g
 
     // set-up results
     bool ready = false;
@@ -120,6 +123,8 @@ struct snx_problem {
     int maxin = 1;
     int *d_err = nullptr;
     float *d_phi[2] = {nullptr, nullptr};
+    float *d_outer = nullptr;                        // second iterate buffer of snx_solve_outer
+    unsigned long long *d_change = nullptr;          // [2] FP64 bits of the outer change norm
     double *d_partial = nullptr, *d_out4 = nullptr;
     double *d_area = nullptr;
     unsigned long long watchdog_ticks = 0;
@@ -728,6 +733,30 @@ snx_status snx_set_materials(snx_problem *p, int32_t ngroup, const double *sigma
     return SNX_OK;
 }
 
+snx_status snx_set_group_scattering(snx_problem *p, int32_t nmat, const int32_t *cell_mat, const double *sigma_gg) {
+    if (!p) return SNX_E_ARG;
+    if (!p->have_mat) return fail(p, SNX_E_STATE, "set the materials before the group scattering");
+    if (nmat == 0) {
+        p->nmat = 0;
+        p->cmat.clear();
+        p->sgg.clear();
+        drop_device(p);
+        return SNX_OK;
+    }
+    if (nmat < 0 || !cell_mat || !sigma_gg) return fail(p, SNX_E_ARG, "bad group scattering arguments");
+    for (int K = 0; K < p->C; ++K)
+        if (cell_mat[K] < 0 || cell_mat[K] >= nmat) return fail(p, SNX_E_ARG, "material index out of range");
+    const size_t n = (size_t)nmat * p->G * p->G;
+    for (size_t i = 0; i < n; ++i)
+        if (!(sigma_gg[i] >= 0.0) || !std::isfinite(sigma_gg[i]))
+            return fail(p, SNX_E_ARG, "scattering cross sections must be finite and >= 0");
+    p->nmat = nmat;
+    p->cmat.assign(cell_mat, cell_mat + p->C);
+    p->sgg.assign(sigma_gg, sigma_gg + n);
+    drop_device(p);
+    return SNX_OK;
+}
+
 snx_status snx_set_boundary(snx_problem *p, int32_t kind, const double *psi_in) {
     if (!p) return SNX_E_ARG;
     if (kind != 0 && kind != 1) return fail(p, SNX_E_ARG, "boundary kind must be 0 or 1");
@@ -804,6 +833,8 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     ALLOC(p->d_phi[1], sizeof(float) * C * G * 8);
     ALLOC(p->d_partial, sizeof(double) * partial_blocks(p->C, p->G) * G * 4);
     ALLOC(p->d_out4, sizeof(double) * G * 4);
+    ALLOC(p->d_outer, sizeof(float) * C * G * 8);
+    ALLOC(p->d_change, sizeof(unsigned long long) * 2);
 #undef ALLOC
 
     // host -> device (FP64 mesh; FP32 materials and quadrature)
@@ -820,7 +851,15 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     HIPCHK(p, hipMemcpyAsync(d_perm, perm.data(), sizeof(unsigned) * 6 * C, hipMemcpyHostToDevice, s), "copy");
     HIPCHK(p, hipStreamSynchronize(s), "sync");
     HIPCHK(p, up32(dsigt, p->sigt), "copy");
-    HIPCHK(p, up32(dsigs, p->sigs), "copy");
+    if (p->nmat) {
+        // the group matrix's diagonal is the within-group scattering
+        std::vector<double> diag(C * G);
+        for (size_t K = 0; K < C; ++K)
+            for (size_t g = 0; g < G; ++g) diag[K * G + g] = p->sgg[((size_t)p->cmat[K] * G + g) * G + g];
+        HIPCHK(p, up32(dsigs, diag), "copy");
+    } else {
+        HIPCHK(p, up32(dsigs, p->sigs), "copy");
+    }
     HIPCHK(p, up32(dq, p->q), "copy");
     HIPCHK(p, up32(dom, p->omega), "copy");
     HIPCHK(p, up32(dw, p->w), "copy");
@@ -848,6 +887,22 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     p->nlev.assign(nlev.begin(), nlev.begin() + 8);
     p->maxin = 1;
     for (int o = 0; o < 8; ++o) p->maxin = std::max(p->maxin, nlev[8 + o]);
+
+    // group-to-group scattering: matrix, materials, cross-group source and outer iterates
+    float *dqo = nullptr, *dsgg = nullptr;
+    int *dcmat = nullptr;
+    if (p->nmat) {
+        const size_t nm = (size_t)p->nmat * G * G;
+        HIPCHK(p, m.alloc((void **)&dsgg, sizeof(float) * nm), "device allocation");
+        HIPCHK(p, m.alloc((void **)&dcmat, sizeof(int) * C), "device allocation");
+        HIPCHK(p, m.alloc((void **)&dqo, sizeof(float) * C * G * 8), "device allocation");
+        std::vector<float> sf(nm);
+        for (size_t i = 0; i < nm; ++i) sf[i] = (float)p->sgg[i];
+        HIPCHK(p, hipMemcpyAsync(dsgg, sf.data(), sizeof(float) * nm, hipMemcpyHostToDevice, s), "copy");
+        HIPCHK(p, hipMemcpyAsync(dcmat, p->cmat.data(), sizeof(int) * C, hipMemcpyHostToDevice, s), "copy");
+        HIPCHK(p, launch_fill_f32(dqo, C * G * 8, 0.f, s), "fill");
+        HIPCHK(p, hipStreamSynchronize(s), "copy");     // sf is a local buffer
+    }
 
     // per-angle designation: each direction's inflow faces, decided in FP64
     unsigned char *damask = nullptr, *dlagm = nullptr;
@@ -886,6 +941,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     hp.C = p->C; hp.G = p->G; hp.A = p->A; hp.nang = p->nang; hp.task_base = 0; hp.epoch = depoch;
     hp.M = dM; hp.S = dS; hp.T = dT; hp.F = dF; hp.nbr = d_nbr; hp.perm = d_perm; hp.inmask = dmask; hp.indeg = dindeg;
     hp.amask = damask;
+    hp.qo = dqo; hp.sgg = dsgg; hp.cmat = dcmat;
     hp.sigt = dsigt; hp.sigs = dsigs; hp.q = dq; hp.r = dr; hp.omega = dom; hp.w = dw; hp.psib = dpsib;
     hp.psi = dpsi; hp.slot = dslot; hp.slotc = dslotc; hp.cnt = dcnt; hp.rec = drec;
     hp.xyz = d_xyz; hp.cv = d_cv;
@@ -924,6 +980,8 @@ snx_status snx_sweep(snx_problem *p, const float *phi_in, float *phi_out, void *
     if (!phi_out || phi_in == phi_out) return fail(p, SNX_E_ARG, "phi_out must be non-NULL and distinct from phi_in");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
+    if (p->nmat)   // one Jacobi step over groups: the cross-group source from phi_in too
+        HIPCHK(p, launch_outer_source(p->sched.d_probs, 0, p->C, p->G, phi_in, s), "outer source");
     HIPCHK(p, launch_source(p->sched.d_probs, 0, p->C, p->G, phi_in, nullptr, s), "source");
     SCHED_ERR(p, enqueue_sweep(p->sched, nullptr, s));
     HIPCHK(p, launch_reduce(p->sched.d_probs, 0, p->C, p->G, phi_out, nullptr, false, nullptr, nullptr, s), "reduce");
@@ -936,11 +994,66 @@ snx_status snx_solve(snx_problem *p, double tol, int32_t max_it, const float *ph
     if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
     if (!phi || max_it < 1 || !(tol >= 0.0)) return fail(p, SNX_E_ARG, "bad solve arguments");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
+    if (p->nmat) return snx_solve_outer(p, max_it, 1, tol, phi0, phi, info, stream);
     const float *in[1] = {phi0};
     float *out[1] = {phi};
     snx_status st = sched_solve(p->sched, tol, max_it, in, out, info, (hipStream_t)stream);
     if (st) return fail(p, st, p->sched.err);
     return SNX_OK;
+}
+
+snx_status snx_solve_outer(snx_problem *p, int32_t outer, int32_t inner, double tol, const float *phi0, float *phi,
+                           snx_solve_info *info, void *stream) {
+    if (!p) return SNX_E_ARG;
+    if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
+    if (!phi || outer < 1 || inner < 1 || !(tol >= 0.0)) return fail(p, SNX_E_ARG, "bad solve arguments");
+    HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t n = (size_t)p->C * p->G * 8;
+    // The outer iterates alternate between the caller's phi and a library
+    // buffer.  Without a group matrix the cross-group source is zero: inner x
+    // outer source iterations with the change measured every `inner`.
+    float *bufs[2] = {phi, p->d_outer};
+    int cur = 0;
+    if (phi0 && phi0 != phi)
+        HIPCHK(p, hipMemcpyAsync(bufs[0], phi0, sizeof(float) * n, hipMemcpyDeviceToDevice, s), "copy");
+    else if (!phi0)
+        HIPCHK(p, launch_fill_f32(bufs[0], n, 0.f, s), "fill");
+    unsigned long long *hch = reinterpret_cast<unsigned long long *>(p->pinned);
+    int k = 0, total = 0;
+    double eps = INFINITY;
+    while (k < outer) {
+        if (p->nmat) HIPCHK(p, launch_outer_source(p->sched.d_probs, 0, p->C, p->G, bufs[cur], s), "outer source");
+        const float *in[1] = {bufs[cur]};
+        float *out[1] = {bufs[cur ^ 1]};
+        snx_status st = sched_solve(p->sched, 0.0, inner, in, out, nullptr, s);
+        if (st && st != SNX_E_NOCONV) return fail(p, st, p->sched.err);
+        total += inner;
+        HIPCHK(p, hipMemsetAsync(p->d_change, 0, sizeof(unsigned long long) * 2, s), "memset");
+        HIPCHK(p, launch_max_change(bufs[cur ^ 1], bufs[cur], (long long)n, p->d_change, s), "change");
+        HIPCHK(p, hipMemcpyAsync(hch, p->d_change, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost, s), "copy");
+        HIPCHK(p, hipStreamSynchronize(s), "solve");
+        double num, den;
+        std::memcpy(&num, &hch[0], sizeof(double));
+        std::memcpy(&den, &hch[1], sizeof(double));
+        eps = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
+        cur ^= 1;
+        ++k;
+        if (tol > 0.0 && eps <= tol) break;
+    }
+    if (bufs[cur] != phi) HIPCHK(p, hipMemcpyAsync(phi, bufs[cur], sizeof(float) * n, hipMemcpyDeviceToDevice, s), "copy");
+    HIPCHK(p, hipStreamSynchronize(s), "solve");
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    const bool conv = tol == 0.0 || eps <= tol;
+    if (info) {
+        info->iterations = total;
+        info->status = conv ? SNX_OK : SNX_E_NOCONV;
+        info->residual = eps;
+        info->wall_ms = ms;
+        info->solves_per_s = ms > 0 ? (double)total * p->C * p->nang * p->G / (ms * 1e-3) : 0.0;
+    }
+    return conv ? SNX_OK : fail(p, SNX_E_NOCONV, "outer iterations ended before the tolerance");
 }
 
 snx_status snx_balance(snx_problem *p, const float *phi_in, const float *phi_out, double *out, void *stream) {
@@ -949,6 +1062,8 @@ snx_status snx_balance(snx_problem *p, const float *phi_in, const float *phi_out
     if (!phi_out || !out) return fail(p, SNX_E_ARG, "phi_out and out are required");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
+    if (p->nmat)   // the cross-group part of the source is the one phi_in gives
+        HIPCHK(p, launch_outer_source(p->sched.d_probs, 0, p->C, p->G, phi_in, s), "outer source");
     HIPCHK(p, launch_balance(p->sched.d_probs, 0, p->C, p->G, phi_in, phi_out, p->d_partial, p->d_out4, s), "balance");
     HIPCHK(p, hipMemcpyAsync(out, p->d_out4, sizeof(double) * 4 * p->G, hipMemcpyDeviceToHost, s), "copy");
     HIPCHK(p, hipStreamSynchronize(s), "balance");
@@ -1107,6 +1222,7 @@ snx_status snx_batch_create(snx_batch **out, int32_t n, snx_problem *const *prob
     for (snx_problem *p : v) {
         if (!p || !p->ready) { g_create_error = "every problem of a batch must be set up"; return SNX_E_STATE; }
         if (p->device != v[0]->device) { g_create_error = "the problems of a batch must share a device"; return SNX_E_ARG; }
+        if (p->nmat) { g_create_error = "batches take within-group scattering only (no group-to-group matrix)"; return SNX_E_ARG; }
     }
     snx_batch *b = new (std::nothrow) snx_batch();
     if (!b) { g_create_error = "out of host memory"; return SNX_E_OOM; }

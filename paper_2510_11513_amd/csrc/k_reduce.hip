@@ -2,10 +2,14 @@
 //
 //   phi_K,g    = sum_o (slot_o + comp_o)             per-octant partials of Eq. 2,
 //                                                   added in octant order with TwoSum
-//   r_K,g      = M_K (Q_K,g + sigma_s,K,g phi_K,g) / (4 pi)      next sweep's source
+//   r_K,g      = M_K (Q_K,g + sigma_s,K,g phi_K,g + qo_K,g) / (4 pi)   next sweep's source,
+//                qo the cross-group scattering source of the current outer
+//                iteration (absent without a group-to-group matrix)
 //   eps        = ||phi_new - phi_old||_inf / ||phi_new||_inf      in FP64
 //   balance    : 1^T M (Q + sigma_s phi_in) = sigma_t 1^T M phi_out + sum_n w_n L_n
 #include "snx_internal.h"
+
+#include <algorithm>
 
 namespace snx {
 namespace {
@@ -17,10 +21,15 @@ __device__ inline void two_sum(float a, float b, float &s, float &e) {
 }
 
 __device__ inline void source_dofs(const float *__restrict__ M, float q, float ss, const float (&phi)[8],
-                                   float (&r)[8]) {
+                                   const float *__restrict__ qo, float (&r)[8]) {
     float src[8];
+    if (qo) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) src[j] = (q + ss * phi[j]) * kInv4Pi;
+        for (int j = 0; j < 8; ++j) src[j] = (q + (ss * phi[j] + qo[j])) * kInv4Pi;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) src[j] = (q + ss * phi[j]) * kInv4Pi;
+    }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         float acc = 0.f;
@@ -41,10 +50,63 @@ __global__ void k_source(const DevProblem *__restrict__ probs, int prob, const f
     float ph[8], r[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) ph[j] = phi ? phi[t * 8 + j] : 0.f;
-    source_dofs(P.M + (size_t)K * 64, P.q[t], P.sigs[t], ph, r);
+    source_dofs(P.M + (size_t)K * 64, P.q[t], P.sigs[t], ph, P.qo ? P.qo + t * 8 : nullptr, r);
     float4 *out = reinterpret_cast<float4 *>(P.r + t * 8);
     out[0] = make_float4(r[0], r[1], r[2], r[3]);
     out[1] = make_float4(r[4], r[5], r[6], r[7]);
+}
+
+// Cross-group scattering source of an outer iteration from a given phi (NULL =
+// zero): qo_K,g = sum over g' != g of sigma(g' -> g) phi_K,g' at each node, in
+// increasing g'.  One thread per (cell, group).
+__global__ void k_outer_source(const DevProblem *__restrict__ probs, int prob, const float *__restrict__ phi) {
+    const DevProblem &P = probs[prob];
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)P.C * P.G) return;
+    const int G = P.G, K = (int)(t / G), g = (int)(t - (long long)K * G);
+    const float *S = P.sgg + (size_t)P.cmat[K] * G * G;
+    float v[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) v[d] = 0.f;
+    if (phi) {
+        for (int h = 0; h < G; ++h) {
+            if (h == g) continue;
+            const float sh = S[(size_t)h * G + g];
+            const float *ph = phi + ((size_t)K * G + h) * 8;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) v[d] = __builtin_fmaf(sh, ph[d], v[d]);
+        }
+    }
+    float4 *out = reinterpret_cast<float4 *>(P.qo + t * 8);
+    out[0] = make_float4(v[0], v[1], v[2], v[3]);
+    out[1] = make_float4(v[4], v[5], v[6], v[7]);
+}
+
+// FP64 max-norm terms of a - b: out[0] = max |a - b|, out[1] = max |a| (both
+// non-negative, so their bit patterns order like the values); out must be zero.
+__global__ __launch_bounds__(256) void k_max_change(const float *__restrict__ a, const float *__restrict__ b,
+                                                    long long n, unsigned long long *__restrict__ out) {
+    double num = 0.0, den = 0.0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const double x = (double)a[i], y = (double)b[i];
+        num = fmax(num, fabs(x - y));
+        den = fmax(den, fabs(x));
+    }
+    __shared__ double s_num[256], s_den[256];
+    s_num[threadIdx.x] = num;
+    s_den[threadIdx.x] = den;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            s_num[threadIdx.x] = fmax(s_num[threadIdx.x], s_num[threadIdx.x + w]);
+            s_den[threadIdx.x] = fmax(s_den[threadIdx.x], s_den[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(&out[0], (unsigned long long)__double_as_longlong(s_num[0]));
+        atomicMax(&out[1], (unsigned long long)__double_as_longlong(s_den[0]));
+    }
 }
 
 __device__ inline unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
@@ -82,7 +144,7 @@ __device__ inline void reduce_one(const DevProblem &P, long long t, float *__res
     if (update_source) {
         const int K = (int)(t / P.G);
         float r[8];
-        source_dofs(P.M + (size_t)K * 64, P.q[t], P.sigs[t], ph, r);
+        source_dofs(P.M + (size_t)K * 64, P.q[t], P.sigs[t], ph, P.qo ? P.qo + t * 8 : nullptr, r);
         float4 *ro = reinterpret_cast<float4 *>(P.r + t * 8);
         ro[0] = make_float4(r[0], r[1], r[2], r[3]);
         ro[1] = make_float4(r[4], r[5], r[6], r[7]);
@@ -193,7 +255,7 @@ __global__ __launch_bounds__(256) void k_source_batch(const DevProblem *__restri
     const float *f = phi ? phi[p] : nullptr;
 #pragma unroll
     for (int j = 0; j < 8; ++j) ph[j] = f ? f[t * 8 + j] : 0.f;
-    source_dofs(P.M + (size_t)K * 64, P.q[t], P.sigs[t], ph, r);
+    source_dofs(P.M + (size_t)K * 64, P.q[t], P.sigs[t], ph, P.qo ? P.qo + t * 8 : nullptr, r);
     float4 *out = reinterpret_cast<float4 *>(P.r + t * 8);
     out[0] = make_float4(r[0], r[1], r[2], r[3]);
     out[1] = make_float4(r[4], r[5], r[6], r[7]);
@@ -252,7 +314,8 @@ __global__ __launch_bounds__(256) void k_balance(const DevProblem *__restrict__ 
         for (int i = 0; i < 8; ++i)
             for (int j = 0; j < 8; ++j) {
                 const double pin = phi_in ? (double)phi_in[t * 8 + j] : 0.0;
-                src += (double)M[i * 8 + j] * (q + ss * pin);
+                const double qo = P.qo ? (double)P.qo[t * 8 + j] : 0.0;   // cross-group source from phi_in
+                src += (double)M[i * 8 + j] * (q + ss * pin + qo);
                 ab += (double)M[i * 8 + j] * st * (double)phi_out[t * 8 + j];
             }
         const size_t cell_psi = (size_t)8 * A * G;
@@ -431,6 +494,18 @@ hipError_t launch_integrated_flux(const float *M, const float *phi, int C, int G
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_finish_partials, dim3((G + 63) / 64), dim3(64), 0, s, partial, (int)nblk, G, 4, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_outer_source(const DevProblem *probs, int prob, int C, int G, const float *phi, hipStream_t s) {
+    const long long n = (long long)C * G;
+    hipLaunchKernelGGL(k_outer_source, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, probs, prob, phi);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_change(const float *a, const float *b, long long n, unsigned long long *out, hipStream_t s) {
+    const long long blocks = std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_max_change, dim3((unsigned)std::max<long long>(blocks, 1)), dim3(256), 0, s, a, b, n, out);
     return hipGetLastError();
 }
 

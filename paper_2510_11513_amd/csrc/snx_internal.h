@@ -97,6 +97,10 @@ struct DevProblem {
     float *slotc;                // [8][C][G][8]  their compensation terms
     unsigned *cnt;               // [8][C]        dependency counters (count up across sweeps)
     const int *rec;              // [8][C][kRecWords] task records (see kRecWords)
+    float *qo;                   // [C][G][8]     cross-group scattering source of the current outer
+                                 //               iteration; nullptr without a group-to-group matrix
+    const float *sgg;            // [nmat][G][G]  group-to-group scattering, from g' (row) into g
+    const int *cmat;             // [C]           material of each cell (group-to-group matrix)
     const double *xyz;           // [nvert][3]    vertex coordinates (the network's cell positions)
     const int *cv;               // [C][8]        cell vertices
     float lo[3], hi[3];          // bounding box of the mesh
@@ -159,6 +163,10 @@ hipError_t launch_integrated_flux(const float *M, const float *phi, int C, int G
                                   hipStream_t s);
 size_t partial_blocks(int C, int G);
 hipError_t launch_fill_f32(float *p, size_t n, float v, hipStream_t s);
+// P.qo of problem `prob` from phi (NULL = zero): sum over g' != g of sigma(g' -> g) phi_g'.
+hipError_t launch_outer_source(const DevProblem *probs, int prob, int C, int G, const float *phi, hipStream_t s);
+// out[0] |= max |a - b|, out[1] |= max |a| as FP64 bit patterns (out zeroed by the caller).
+hipError_t launch_max_change(const float *a, const float *b, long long n, unsigned long long *out, hipStream_t s);
 hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s);
 hipError_t launch_copy_f32(float *dst, const float *src, size_t n, const int *stop_flag, hipStream_t s);
 hipError_t launch_gather_psi(const float *psi, int C, int A, int G, int angle, int group, float *out, hipStream_t s);

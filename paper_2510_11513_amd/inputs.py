@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "Mesh", "Materials", "Problem", "make_mesh", "block_index",
     "materials_uniform", "materials_two_block", "materials_loguniform_blocks",
-    "group_scale", "config_problem", "batch_problems", "instance_seed",
+    "group_scale", "config_problem", "batch_problems", "instance_seed", "split_scattering",
 ]
 
 
@@ -168,6 +168,27 @@ def materials_loguniform_blocks(mesh: Mesh, G: int, rng: np.random.Generator, bl
     c = rng.uniform(c_lo, c_hi, size=nblk)
     q = rng.uniform(0.0, 1.0, size=nblk)   # sources are drawn last
     return _expand(st[bidx], c[bidx], q[bidx], G, scaled)
+
+
+def split_scattering(mat: Materials, within: float = 0.6):
+    """Group-to-group scattering matrices with the same total scattering per
+    group as mat.sigma_s: group g keeps the fraction `within` and passes the
+    rest down to the higher-index groups with weights 1/2, 1/4, ... (normalised),
+    and the last group keeps all of it.  Returns (cell_mat [ncell] int32,
+    sigma_gg [nmat][G][G] with [m][g'][g] the cross section from g' into g), one
+    material per distinct sigma_s row."""
+    rows, cell_mat = np.unique(mat.sigma_s, axis=0, return_inverse=True)
+    G = rows.shape[1]
+    frac = np.zeros((G, G))
+    for g in range(G):
+        if g == G - 1:
+            frac[g, g] = 1.0
+            continue
+        down = 0.5 ** np.arange(1, G - g)
+        frac[g, g] = within
+        frac[g, g + 1:] = (1.0 - within) * down / down.sum()
+    sgg = rows[:, :, None] * frac[None, :, :]
+    return np.ascontiguousarray(cell_mat.reshape(-1), np.int32), np.ascontiguousarray(sgg)
 
 
 def config_problem(config: int, index: int = 0, scaled: bool = True, n: int | None = None) -> Problem:

@@ -32,7 +32,7 @@ EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_s
            "snx_gnn_load", "snx_gnn_features", "snx_gnn_targets", "snx_gnn_forward", "snx_gnn_grad",
            "snx_gnn_train_step", "snx_gnn_predict", "snx_set_sweep_mode", "snx_batch_set_sweep_mode",
            "snx_get_psi", "snx_set_sweep_stats", "snx_batch_set_sweep_stats", "snx_set_designation",
-           "snx_designation_stats"]
+           "snx_designation_stats", "snx_set_group_scattering", "snx_solve_outer"]
 _NO_STATUS = ("snx_destroy", "snx_last_error", "snx_batch_destroy", "snx_batch_last_error", "snx_gnn_destroy",
               "snx_gnn_last_error")
 
@@ -83,6 +83,8 @@ def load(path: str = LIB_PATH):
     L.snx_get_levels.argtypes = [_vp, _vp, _vp]
     L.snx_get_psi.argtypes = [_vp, ct.c_int32, ct.c_int32, _vp, _vp]
     L.snx_set_designation.argtypes = [_vp, ct.c_int32]
+    L.snx_set_group_scattering.argtypes = [_vp, ct.c_int32, _vp, _vp]
+    L.snx_solve_outer.argtypes = [_vp, ct.c_int32, ct.c_int32, ct.c_double, _vp, _vp, ct.POINTER(SolveInfo), _vp]
     L.snx_designation_stats.argtypes = [_vp, _vp]
     L.snx_set_sweep_stats.argtypes = [_vp, ct.c_int32]
     L.snx_batch_set_sweep_stats.argtypes = [_vp, ct.c_int32]
@@ -217,6 +219,19 @@ class Problem:
         ptr = None if arr is None else arr.ctypes.data_as(ct.c_void_p)
         self._check(load().snx_set_boundary(self.h, kind, ptr), "set_boundary")
 
+    def set_group_scattering(self, cell_mat, sigma_gg):
+        """Group-to-group scattering: cell_mat[ncell] material ids, sigma_gg[nmat][G][G]
+        from group g' (axis 1) into g (axis 2); None removes it.  Takes effect at setup."""
+        if sigma_gg is None:
+            self._check(load().snx_set_group_scattering(self.h, 0, None, None), "set_group_scattering")
+            return
+        cm = np.ascontiguousarray(cell_mat, np.int32)
+        sg = np.ascontiguousarray(sigma_gg, np.float64)
+        if sg.ndim != 3 or sg.shape[1] != sg.shape[2] or cm.ndim != 1:
+            raise ValueError("cell_mat must be [ncell] and sigma_gg [nmat][G][G]")
+        self._check(load().snx_set_group_scattering(self.h, sg.shape[0], cm.ctypes.data_as(ct.c_void_p),
+                                                    sg.ctypes.data_as(ct.c_void_p)), "set_group_scattering")
+
     def set_designation(self, kind: int):
         """DESIGNATION_OCTANT (default) or DESIGNATION_ANGLE (per direction, lagged
         faces where a direction goes against its octant's order); takes effect at setup."""
@@ -263,6 +278,18 @@ class Problem:
         info = SolveInfo()
         rc = load().snx_solve(self.h, tol, max_it, _ptr(phi0), _ptr(phi), ct.byref(info), _stream(stream))
         self._check(rc, "solve", allow=(SNX_E_NOCONV,) if allow_noconv else ())
+        return phi, {"iterations": info.iterations, "status": info.status, "residual": info.residual,
+                     "wall_ms": info.wall_ms, "solves_per_s": info.solves_per_s, "rc": rc}
+
+    def solve_outer(self, outer: int, inner: int, tol: float = 0.0, phi0=None, phi=None, stream=None,
+                    allow_noconv=False):
+        """Inner/outer iterations (snx_solve_outer); returns (phi, info)."""
+        if phi is None:
+            phi = self.empty_phi()
+        info = SolveInfo()
+        rc = load().snx_solve_outer(self.h, int(outer), int(inner), float(tol), _ptr(phi0), _ptr(phi),
+                                    ct.byref(info), _stream(stream))
+        self._check(rc, "solve_outer", allow=(SNX_E_NOCONV,) if allow_noconv else ())
         return phi, {"iterations": info.iterations, "status": info.status, "residual": info.residual,
                      "wall_ms": info.wall_ms, "solves_per_s": info.solves_per_s, "rc": rc}
 
