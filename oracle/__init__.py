@@ -61,6 +61,7 @@ def lib():
         L.snxo_set_hooks.argtypes = [vp, nullable_d, nullable_d]
         L.snxo_setup.argtypes = [vp]
         L.snxo_set_designation.argtypes = [vp, ct.c_int]
+        L.snxo_set_reflective.argtypes = [vp, ct.c_int]
         L.snxo_set_group_scattering.argtypes = [vp, ct.c_int, nullable_d, nullable_d]
         L.snxo_solve_outer.argtypes = [vp, ct.c_int, ct.c_int, ct.c_double, nullable_d, _dp,
                                        ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), ct.POINTER(ct.c_double)]
@@ -154,6 +155,10 @@ class Oracle:
 
     def setup(self):
         self._check(lib().snxo_setup(self.h), "setup")
+
+    def set_reflective(self, planes: int):
+        """Reflective boundary planes, bit 2*axis + side (before setup)."""
+        self._check(lib().snxo_set_reflective(self.h, int(planes)), "set_reflective")
 
     def set_group_scattering(self, cell_mat, sigma_gg):
         """cell_mat[ncell] int, sigma_gg[nmat][G][G] from group g' (axis 1) into g (axis 2);

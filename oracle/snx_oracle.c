@@ -32,6 +32,8 @@ struct snxo_problem {
     int32_t *nbr, *nbrf, *perm;     /* [C][6], [C][6], [C][6][4] */
     int32_t *inflow, *level, *order;/* [8][C] each */
     int designation;                /* 0 per octant, 1 per angle (snxo_set_designation) */
+    int refl;                       /* reflective planes (snxo_set_reflective): bit 2*axis + side */
+    int32_t *rdir;                  /* [nang][3] the direction mirrored across each axis (setup) */
     int nmat;                       /* group-to-group scattering (snxo_set_group_scattering), 0 = none */
     int32_t *cmat;                  /* [C] material of each cell */
     double *sgg;                    /* [nmat][G][G] from group g' (row) into group g (column) */
@@ -192,9 +194,9 @@ int snxo_quadrature(int npolar, int nazim, double *omega, double *w) {
 static void free_derived(snxo_problem *p) {
     free(p->M); free(p->S); free(p->F); free(p->area);
     free(p->nbr); free(p->nbrf); free(p->perm);
-    free(p->inflow); free(p->level); free(p->order); free(p->ain);
+    free(p->inflow); free(p->level); free(p->order); free(p->ain); free(p->rdir);
     p->M = p->S = p->F = p->area = NULL;
-    p->nbr = p->nbrf = p->perm = p->inflow = p->level = p->order = p->ain = NULL;
+    p->nbr = p->nbrf = p->perm = p->inflow = p->level = p->order = p->ain = p->rdir = NULL;
     p->ready = 0;
 }
 
@@ -276,6 +278,13 @@ int snxo_set_boundary(snxo_problem *p, int kind, const double *psi_b) {
 int snxo_set_designation(snxo_problem *p, int kind) {
     if (!p || (kind != 0 && kind != 1)) return fail(p, SNXO_E_ARG, "designation must be 0 or 1");
     p->designation = kind;
+    free_derived(p);
+    return SNXO_OK;
+}
+
+int snxo_set_reflective(snxo_problem *p, int planes) {
+    if (!p || planes < 0 || planes > 63) return fail(p, SNXO_E_ARG, "planes is a 6-bit mask");
+    p->refl = planes;
     free_derived(p);
     return SNXO_OK;
 }
@@ -557,6 +566,44 @@ static int build_angle_inflow(snxo_problem *p) {
     return SNXO_OK;
 }
 
+/* Reflective planes: for each direction and axis, the direction with that
+ * component negated (it must be in the quadrature set). */
+static int build_reflection(snxo_problem *p) {
+    p->rdir = malloc(sizeof(int32_t) * 3 * (size_t)p->nang);
+    if (!p->rdir) return fail(p, SNXO_E_OOM, "out of memory");
+    for (int n = 0; n < p->nang; ++n)
+        for (int a = 0; a < 3; ++a) {
+            double want[3] = {p->omega[3 * n], p->omega[3 * n + 1], p->omega[3 * n + 2]};
+            want[a] = -want[a];
+            int found = -1;
+            for (int m = 0; m < p->nang && found < 0; ++m) {
+                const double *om = p->omega + 3 * m;
+                if (fabs(om[0] - want[0]) + fabs(om[1] - want[1]) + fabs(om[2] - want[2]) < 1e-12) found = m;
+            }
+            if (found < 0) return fail(p, SNXO_E_ARG, "quadrature not symmetric under reflection");
+            p->rdir[3 * n + a] = found;
+        }
+    return SNXO_OK;
+}
+
+/* Reflective plane of boundary face f of K, or -1: the face's area vector lies
+ * along an axis (its other two components at most 1e-12 of its length, which
+ * rounding leaves on faces of a coordinate plane), and bit 2*axis + side (side
+ * 1 for the outward +axis) of the mask is set. */
+static int reflective_axis(const snxo_problem *p, int K, int f) {
+    if (!p->refl || p->nbr[6 * K + f] >= 0) return -1;
+    const double *A = p->area + 18L * K + 3 * f;
+    double len = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+    for (int a = 0; a < 3; ++a) {
+        int b = (a + 1) % 3, c = (a + 2) % 3;
+        if (fabs(A[b]) <= 1e-12 * len && fabs(A[c]) <= 1e-12 * len) {
+            int side = A[a] > 0.0;
+            return (p->refl >> (2 * a + side)) & 1 ? a : -1;
+        }
+    }
+    return -1;
+}
+
 int snxo_setup(snxo_problem *p) {
     if (!p || !p->cv || !p->omega || !p->sigt) return fail(p, SNXO_E_STATE, "mesh, quadrature and materials must be set");
     free_derived(p);
@@ -581,6 +628,7 @@ int snxo_setup(snxo_problem *p) {
     if (!rc) rc = build_geometry(p);
     if (!rc) rc = build_dag(p);
     if (!rc && p->designation == 1) rc = build_angle_inflow(p);
+    if (!rc && p->refl) rc = build_reflection(p);
     if (rc) { free_derived(p); return rc; }
     p->ready = 1;
     return SNXO_OK;
@@ -597,8 +645,8 @@ int snxo_setup(snxo_problem *p) {
  * of every cell: this sweep's for cells already visited, the previous sweep's
  * (or zero) for the rest. */
 static int solve_local(const snxo_problem *p, int K, int n, int g, const double *qnodal,
-                       const double *psi_cur /*[C][8] this angle and group*/, double x[8],
-                       double *leak_out) {
+                       const double *psi_cur /*[C][8] this angle and group*/,
+                       const double *psi_prev /*[nang][C][G][8] or NULL*/, double x[8], double *leak_out) {
     const double *om = p->omega + 3 * n;
     const double *M = p->M + 64L * K, *S = p->S + 192L * K;
     int o = n / (p->nang / 8);
@@ -622,6 +670,11 @@ static int solve_local(const snxo_problem *p, int K, int n, int g, const double 
         int N = p->nbr[6 * K + f];
         for (int l = 0; l < 4; ++l) {
             if (N >= 0) up[f][l] = psi_cur[8L * N + p->perm[24 * K + 4 * f + l]];
+            else if (reflective_axis(p, K, f) >= 0) {
+                /* the mirrored direction's own trace at these nodes, from the previous sweep */
+                int m = p->rdir[3 * n + reflective_axis(p, K, f)];
+                up[f][l] = psi_prev ? psi_prev[(((long)m * p->ncell + K) * p->G + g) * 8 + fn[l]] : 0.0;
+            }
             else if (p->bnd_in) up[f][l] = p->bnd_in[((((long)K * 6 + f) * p->nang + n) * p->G + g) * 4 + l];
             else if (p->bkind == 1) up[f][l] = p->psib[g];
             else up[f][l] = 0.0;
@@ -719,7 +772,10 @@ static int sweep_src(snxo_problem *p, const double *phi_in, const double *qouter
                     } else {
                         source_nodal(p, phi_in, qouter, K, g, qn);
                     }
-                    if (solve_local(p, K, n, g, qn, psi_cur, x, (leak || leak_ang) ? &L : NULL)) { bad = 1; break; }
+                    if (solve_local(p, K, n, g, qn, psi_cur, psi_prev, x, (leak || leak_ang) ? &L : NULL)) {
+                        bad = 1;
+                        break;
+                    }
                     for (int j = 0; j < 8; ++j) {
                         psi_cur[8L * K + j] = x[j];
                         phi_out[((long)K * G + g) * 8 + j] += p->w[n] * x[j];
@@ -751,6 +807,7 @@ int snxo_sweep_angle(snxo_problem *p, const double *phi_in, int n, int g, const 
     if (!psi_out) return fail(p, SNXO_E_ARG, "psi_out is NULL");
     int C = p->ncell, G = p->G, nang = p->nang, per = nang / 8;
     if (n < 0 || n >= nang || g < 0 || g >= G) return fail(p, SNXO_E_ARG, "angle or group out of range");
+    if (p->refl) return fail(p, SNXO_E_ARG, "reflective planes couple directions: use snxo_sweep");
     int o = n / per;
     for (long i = 0; i < 8L * C; ++i) psi_out[i] = psi_prev ? psi_prev[i] : 0.0;
     for (int t = 0; t < C; ++t) {
@@ -761,7 +818,7 @@ int snxo_sweep_angle(snxo_problem *p, const double *phi_in, int n, int g, const 
         } else {
             source_nodal(p, phi_in, NULL, K, g, qn);
         }
-        if (solve_local(p, K, n, g, qn, psi_out, x, NULL)) return fail(p, SNXO_E_MESH, "singular local system");
+        if (solve_local(p, K, n, g, qn, psi_out, NULL, x, NULL)) return fail(p, SNXO_E_MESH, "singular local system");
         for (int j = 0; j < 8; ++j) psi_out[8L * K + j] = x[j];
     }
     return SNXO_OK;
@@ -784,14 +841,22 @@ int snxo_solve(snxo_problem *p, double tol, int max_it, const double *phi0,
     if (!phi_out || max_it < 1) return fail(p, SNXO_E_ARG, "bad solve arguments");
     size_t n = 8 * (size_t)p->ncell * p->G;
     double *cur = malloc(sizeof(double) * n);
-    /* designation 1: the angular flux carried between sweeps */
-    double *psi = p->designation == 1 ? calloc(n * (size_t)p->nang, sizeof(double)) : NULL;
-    if (!cur || (p->designation == 1 && !psi)) { free(cur); free(psi); return fail(p, SNXO_E_OOM, "out of memory"); }
+    /* designation 1 and reflective planes: the angular flux carried between
+     * sweeps (previous and next kept apart: a reflective face reads another
+     * direction's previous values) */
+    int carry = p->designation == 1 || p->refl;
+    double *psi = carry ? calloc(n * (size_t)p->nang, sizeof(double)) : NULL;
+    double *psi2 = carry ? calloc(n * (size_t)p->nang, sizeof(double)) : NULL;
+    if (!cur || (carry && (!psi || !psi2))) {
+        free(cur); free(psi); free(psi2);
+        return fail(p, SNXO_E_OOM, "out of memory");
+    }
     if (phi0) memcpy(cur, phi0, sizeof(double) * n); else memset(cur, 0, sizeof(double) * n);
     int it = 0, rc = SNXO_OK;
     double e = INFINITY;
     while (it < max_it) {
-        rc = snxo_sweep(p, cur, psi, phi_out, psi, NULL, NULL);
+        rc = snxo_sweep(p, cur, psi, phi_out, psi2, NULL, NULL);
+        { double *t = psi; psi = psi2; psi2 = t; }
         if (rc) break;
         e = rel_change(phi_out, cur, n);
         if (hist) hist[it] = e;
@@ -801,6 +866,7 @@ int snxo_solve(snxo_problem *p, double tol, int max_it, const double *phi0,
     }
     free(cur);
     free(psi);
+    free(psi2);
     if (iters) *iters = it;
     if (eps) *eps = e;
     if (rc) return rc;
@@ -821,9 +887,11 @@ int snxo_solve_outer(snxo_problem *p, int outer, int inner, double tol, const do
     int C = p->ncell, G = p->G;
     size_t n = 8 * (size_t)C * G;
     double *start = malloc(sizeof(double) * n), *x = malloc(sizeof(double) * n), *qo = calloc(n, sizeof(double));
-    double *psi = p->designation == 1 ? calloc(n * (size_t)p->nang, sizeof(double)) : NULL;
-    if (!start || !x || !qo || (p->designation == 1 && !psi)) {
-        free(start); free(x); free(qo); free(psi);
+    int carry = p->designation == 1 || p->refl;
+    double *psi = carry ? calloc(n * (size_t)p->nang, sizeof(double)) : NULL;
+    double *psi2 = carry ? calloc(n * (size_t)p->nang, sizeof(double)) : NULL;
+    if (!start || !x || !qo || (carry && (!psi || !psi2))) {
+        free(start); free(x); free(qo); free(psi); free(psi2);
         return fail(p, SNXO_E_OOM, "out of memory");
     }
     if (phi0) memcpy(start, phi0, sizeof(double) * n); else memset(start, 0, sizeof(double) * n);
@@ -843,7 +911,8 @@ int snxo_solve_outer(snxo_problem *p, int outer, int inner, double tol, const do
             }
         memcpy(x, start, sizeof(double) * n);
         for (int i = 0; i < inner && !rc; ++i) {
-            rc = sweep_src(p, x, qo, psi, phi_out, psi, NULL, NULL);
+            rc = sweep_src(p, x, qo, psi, phi_out, psi2, NULL, NULL);
+            { double *t = psi; psi = psi2; psi2 = t; }
             if (!rc) memcpy(x, phi_out, sizeof(double) * n);
             ++it;
         }
@@ -854,7 +923,7 @@ int snxo_solve_outer(snxo_problem *p, int outer, int inner, double tol, const do
         if (tol > 0.0 && e <= tol) break;
     }
     memcpy(phi_out, start, sizeof(double) * n);
-    free(start); free(x); free(qo); free(psi);
+    free(start); free(x); free(qo); free(psi); free(psi2);
     if (outers_done) *outers_done = k;
     if (inners_done) *inners_done = it;
     if (eps) *eps = e;

@@ -70,6 +70,14 @@ int  snxo_set_materials(snxo_problem *p, int ngroup, const double *sigma_t,
                         const double *sigma_s, const double *q);
 /* kind 0 = vacuum, 1 = isotropic inflow psi_b[g] on every inflow boundary face. */
 int  snxo_set_boundary(snxo_problem *p, int kind, const double *psi_b);
+/* Reflective boundary planes (before snxo_setup; default none): bit
+ * 2*axis + side makes the boundary faces whose outward area vector points
+ * along -axis (side 0) or +axis (side 1) reflective.  On such a face the inflow
+ * of direction n is the outflow of its mirror image (the direction with that
+ * component negated, which the quadrature must hold) at the same nodes, taken
+ * from the previous sweep (psi_prev), as on the GPU where octants run
+ * concurrently.  snxo_sweep_angle refuses reflective problems. */
+int  snxo_set_reflective(snxo_problem *p, int planes);
 /* Group-to-group isotropic scattering (after snxo_set_materials; nmat = 0
  * clears it): cell_mat[ncell] material of each cell, sigma_gg[nmat][G][G]
  * with [m][g'][g] the cross section from group g' into group g.  When set, its
