@@ -100,6 +100,20 @@ snx_status snx_set_materials(snx_problem *p, int32_t ngroup, const double *sigma
  * kind 1 = isotropic inflow psi_in[G] (host float64). */
 snx_status snx_set_boundary(snx_problem *p, int32_t kind, const double *psi_in);
 
+/* Reflective boundary planes (UnSNAP's reason not to sweep octants
+ * concurrently, §2.1; before snx_setup, a change undoes any earlier setup).
+ * planes: bit 2*axis + side (0..5) marks the boundary faces whose area vector
+ * points along -axis (side 0) or +axis (side 1) as reflective.  A face counts
+ * when its area vector's other components are within 1e-12 of its length.
+ * On such a face the inflow of direction n, at each face node, is the outflow
+ * of its mirror image (n with that component negated) at the same node.  The
+ * octants still run concurrently: that outflow is the one of the problem's
+ * previous sweep (zero after snx_setup), and source iteration converges to the
+ * reflective solution.  snx_setup returns SNX_E_ARG when the quadrature lacks
+ * the mirror images at the same index of the mirrored octant (product sets have
+ * them). */
+snx_status snx_set_reflective(snx_problem *p, int32_t planes);
+
 /* Group-to-group isotropic scattering (the energy coupling that the paper's
  * outer iterations resolve, §3.6; after snx_set_materials, before snx_setup;
  * nmat = 0 removes it).  cell_mat: host int32 [ncell], the material of each

@@ -70,7 +70,8 @@ struct Sched {
     int maxA = 0, maxG = 0, maxin = 1;
     int maxAG = 0;                           // largest (angles per octant) * G of the problems
     bool one = false;                        // every task is one round of lanes (maxAG <= threads)
-    bool pa = false;                         // a problem uses per-angle designation: the kernel variant with it
+    bool ext = false;                        // a problem uses per-angle designation or reflective planes:
+                                             // the kernel variant with them
     int threads = 256, wg_per_cu = 0, grid = 0, chunk = 8;
     int mode = SNX_SWEEP_AMT;                // SNX_SWEEP_AMT or SNX_SWEEP_BSP
     bool phase_stats = false;                // gather the per-phase cycle statistics (snx_set_sweep_stats)
@@ -109,6 +110,8 @@ struct snx_problem {
     std::vector<int> cv;
     bool have_mesh = false, have_quad = false, have_mat = false;
     int designation = SNX_DESIGNATION_OCTANT;
+    int refl = 0;                       // reflective planes (snx_set_reflective), bit 2*axis + side
+    int nref = 0;                       // reflective boundary faces found at setup
     int nmat = 0;                       // group-to-group scattering (snx_set_group_scattering), 0 = none
     std::vector<int> cmat;              // [C]
     std::vector<double> sgg;            // [nmat][G][G], from g' into g
@@ -190,7 +193,7 @@ snx_status configure_grid(Sched &sc) {
     sc.one = sc.maxAG <= sc.threads;
     const size_t lds = sweep_lds_bytes(sc.threads, sc.maxA, sc.maxG, sc.maxin, sc.one);
     if (lds > 64 * 1024) return fail_msg(sc.err, SNX_E_ARG, "task does not fit in 64 KB of LDS (too many angles or groups)");
-    const int occ = sweep_occupancy(sc.threads, sc.one, sc.pa, lds);
+    const int occ = sweep_occupancy(sc.threads, sc.one, sc.ext, lds);
     if (occ <= 0) return fail_msg(sc.err, SNX_E_ARG, "sweep kernel cannot be resident with this schedule");
     const int per_cu = sc.wg_per_cu > 0 ? std::min(sc.wg_per_cu, occ) : occ;
     long long grid = (long long)cu_count(sc.device) * per_cu;
@@ -230,7 +233,7 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
     std::vector<int> blk(n + 1, 0), rblk(n + 1, 0), seed_off(8 * n + 1, 0), seeds;
     sc.maxA = sc.maxG = sc.maxAG = 0;
     sc.maxin = 1;
-    sc.pa = false;
+    sc.ext = false;
     for (int i = 0; i < n; ++i) {
         snx_problem *p = probs[i];
         DevProblem P = p->hp;
@@ -243,7 +246,7 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
         sc.maxG = std::max(sc.maxG, p->G);
         sc.maxAG = std::max(sc.maxAG, p->A * p->G);
         sc.maxin = std::max(sc.maxin, p->maxin);
-        sc.pa = sc.pa || p->hp.amask != nullptr;
+        sc.ext = sc.ext || p->hp.amask != nullptr || p->hp.refl_in != nullptr;
         for (int o = 0; o < 8; ++o) {
             seed_off[i * 8 + o] = (int)seeds.size();
             seeds.insert(seeds.end(), p->seeds_by_octant[o].begin(), p->seeds_by_octant[o].end());
@@ -327,12 +330,19 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
 // sweep kernel alone.
 snx_status enqueue_sweep(Sched &sc, const int *stops, hipStream_t s, hipEvent_t ev0 = nullptr,
                          hipEvent_t ev1 = nullptr) {
+    // reflective planes: the last sweep's outflow becomes this sweep's inflow
+    for (int i = 0; i < sc.nprob(); ++i) {
+        const DevProblem &P = sc.hprobs[i];
+        if (P.refl_in)
+            HIPCHK_E(sc.err, launch_copy_f32(P.refl_in, P.refl_out, (size_t)8 * P.nref * 4 * P.A * P.G,
+                                             stops ? stops + i : nullptr, s), "reflective copy");
+    }
     if (sc.mode == SNX_SWEEP_BSP) {   // one launch per level; the kernel boundary is the barrier
         if (ev0) HIPCHK_E(sc.err, hipEventRecord(ev0, s), "event");
         for (size_t l = 0; l + 1 < sc.bsp_off.size(); ++l)
             HIPCHK_E(sc.err, launch_sweep_level(sc.d_probs, sc.nprob(), sc.d_base, sc.d_ctl, sc.threads, sc.one,
                                                 sc.grid, sc.maxA, sc.maxG, sc.maxin, sc.d_bsp_tasks, sc.bsp_off[l],
-                                                sc.bsp_off[l + 1], stops, sc.pa, s), "level launch");
+                                                sc.bsp_off[l + 1], stops, sc.ext, s), "level launch");
         if (ev1) HIPCHK_E(sc.err, hipEventRecord(ev1, s), "event");
         return SNX_OK;
     }
@@ -340,7 +350,7 @@ snx_status enqueue_sweep(Sched &sc, const int *stops, hipStream_t s, hipEvent_t 
                                            stops, s), "sweep prologue");
     if (ev0) HIPCHK_E(sc.err, hipEventRecord(ev0, s), "event");
     HIPCHK_E(sc.err, launch_sweep_kernel(sc.d_probs, sc.nprob(), sc.d_base, sc.d_ctl, sc.d_queue, sc.threads, sc.one,
-                                         sc.grid, sc.maxA, sc.maxG, sc.maxin, sc.watchdog, sc.phase_stats, sc.pa, s),
+                                         sc.grid, sc.maxA, sc.maxG, sc.maxin, sc.watchdog, sc.phase_stats, sc.ext, s),
              "sweep launch");
     if (ev1) HIPCHK_E(sc.err, hipEventRecord(ev1, s), "event");
     return SNX_OK;
@@ -526,7 +536,7 @@ std::string tune_key(const Sched &sc) {
     while ((1LL << (sb + 1)) <= solves) ++sb;
     char buf[256];
     std::snprintf(buf, sizeof buf, "%s|cu%d|np%d|A%d|G%d|c%d|s%d|k%d%s", prop.gcnArchName, cu_count(sc.device),
-                  sc.nprob(), sc.maxA, sc.maxG, cb, sb, kSweepRevision, sc.pa ? "|pa" : "");
+                  sc.nprob(), sc.maxA, sc.maxG, cb, sb, kSweepRevision, sc.ext ? "|ext" : "");
     return buf;
 }
 
@@ -733,6 +743,14 @@ snx_status snx_set_materials(snx_problem *p, int32_t ngroup, const double *sigma
     return SNX_OK;
 }
 
+snx_status snx_set_reflective(snx_problem *p, int32_t planes) {
+    if (!p) return SNX_E_ARG;
+    if (planes < 0 || planes > 63) return fail(p, SNX_E_ARG, "planes is a 6-bit mask (bit 2*axis + side)");
+    p->refl = planes;
+    drop_device(p);
+    return SNX_OK;
+}
+
 snx_status snx_set_group_scattering(snx_problem *p, int32_t nmat, const int32_t *cell_mat, const double *sigma_gg) {
     if (!p) return SNX_E_ARG;
     if (!p->have_mat) return fail(p, SNX_E_STATE, "set the materials before the group scattering");
@@ -928,8 +946,61 @@ snx_status snx_setup(snx_problem *p, void *stream) {
         HIPCHK(p, launch_fill_f32(dpsi, 8 * C * 8 * A * G, 0.f, s), "fill");
     }
 
+    // reflective planes: boundary faces whose area vector lies along a reflective
+    // axis direction (tangential parts within 1e-12 of its length), one slot each
+    unsigned char *drmask = nullptr;
+    int *drbase = nullptr;
+    float *drefl_in = nullptr, *drefl_out = nullptr;
+    p->nref = 0;
+    if (p->refl) {
+        // the mirror image of direction a of octant o must be direction a of octant o ^ (1 << axis)
+        for (int n = 0; n < p->nang; ++n)
+            for (int ax = 0; ax < 3; ++ax) {
+                if (!((p->refl >> (2 * ax)) & 3)) continue;
+                const int m = (int)(((n / A) ^ (1 << ax)) * A + n % A);
+                double d = 0.0;
+                for (int c = 0; c < 3; ++c) d += std::fabs(p->omega[3 * m + c] - (c == ax ? -1.0 : 1.0) * p->omega[3 * n + c]);
+                if (!(d < 1e-12)) {
+                    drop_device(p);
+                    return fail(p, SNX_E_ARG, "the quadrature is not symmetric under the reflective planes");
+                }
+            }
+        std::vector<double> harea(18 * C);
+        HIPCHK(p, hipMemcpy(harea.data(), p->d_area, sizeof(double) * 18 * C, hipMemcpyDeviceToHost), "copy");
+        std::vector<unsigned char> rm(C, 0);
+        std::vector<int> rb(C, 0);
+        for (size_t K = 0; K < C; ++K) {
+            rb[K] = p->nref;
+            for (int f = 0; f < 6; ++f) {
+                if (nbr[K * 6 + f] >= 0) continue;
+                const double *Af = &harea[(K * 6 + f) * 3];
+                const double len = std::sqrt(Af[0] * Af[0] + Af[1] * Af[1] + Af[2] * Af[2]);
+                for (int ax = 0; ax < 3; ++ax) {
+                    if (std::fabs(Af[(ax + 1) % 3]) > 1e-12 * len || std::fabs(Af[(ax + 2) % 3]) > 1e-12 * len) continue;
+                    if ((p->refl >> (2 * ax + (Af[ax] > 0.0))) & 1) {
+                        rm[K] |= (unsigned char)(1 << f);
+                        ++p->nref;
+                    }
+                    break;
+                }
+            }
+        }
+        if (p->nref) {
+            const size_t nr = (size_t)8 * p->nref * 4 * A * G;
+            HIPCHK(p, m.alloc((void **)&drmask, C), "device allocation");
+            HIPCHK(p, m.alloc((void **)&drbase, sizeof(int) * C), "device allocation");
+            HIPCHK(p, m.alloc((void **)&drefl_in, sizeof(float) * nr), "device allocation");
+            HIPCHK(p, m.alloc((void **)&drefl_out, sizeof(float) * nr), "device allocation");
+            HIPCHK(p, hipMemcpy(drmask, rm.data(), C, hipMemcpyHostToDevice), "copy");
+            HIPCHK(p, hipMemcpy(drbase, rb.data(), sizeof(int) * C, hipMemcpyHostToDevice), "copy");
+            HIPCHK(p, launch_fill_f32(drefl_in, nr, 0.f, s), "fill");
+            HIPCHK(p, launch_fill_f32(drefl_out, nr, 0.f, s), "fill");
+        }
+    }
+
     HIPCHK(p, launch_octant_operators(p->C, dS, dF, dmask, dT, s), "octant operators");
-    HIPCHK(p, launch_task_records(p->C, d_nbr, d_perm, dmask, dindeg, dlagm, drec, s), "task records");
+    HIPCHK(p, launch_task_records(p->C, d_nbr, d_perm, dmask, dindeg, dlagm, drmask, drbase, drec, s),
+           "task records");
 
     // level-0 tasks of every octant are the seeds of a sweep
     std::vector<int> seeds_host(8 * C);
@@ -942,6 +1013,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     hp.M = dM; hp.S = dS; hp.T = dT; hp.F = dF; hp.nbr = d_nbr; hp.perm = d_perm; hp.inmask = dmask; hp.indeg = dindeg;
     hp.amask = damask;
     hp.qo = dqo; hp.sgg = dsgg; hp.cmat = dcmat;
+    hp.refl_in = drefl_in; hp.refl_out = drefl_out; hp.nref = p->nref;
     hp.sigt = dsigt; hp.sigs = dsigs; hp.q = dq; hp.r = dr; hp.omega = dom; hp.w = dw; hp.psib = dpsib;
     hp.psi = dpsi; hp.slot = dslot; hp.slotc = dslotc; hp.cnt = dcnt; hp.rec = drec;
     hp.xyz = d_xyz; hp.cv = d_cv;

@@ -132,7 +132,8 @@ __global__ void k_octant_operators(int C, const float *__restrict__ S, const flo
 // holds that cell's descriptor when it starts it.
 __global__ void k_task_records(int C, const int *__restrict__ nbr, const unsigned *__restrict__ perm,
                                const unsigned char *__restrict__ inmask, const int *__restrict__ indeg,
-                               const unsigned char *__restrict__ lagm, int *__restrict__ rec) {
+                               const unsigned char *__restrict__ lagm, const unsigned char *__restrict__ rmask,
+                               const int *__restrict__ rbase, int *__restrict__ rec) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;   // o * C + K
     if (t >= 8LL * C) return;
     const int o = (int)(t / C), K = (int)(t - (long long)o * C);
@@ -145,8 +146,9 @@ __global__ void k_task_records(int C, const int *__restrict__ nbr, const unsigne
         d[12] = inmask[(size_t)o * C + cell];
     };
     desc(K, r);
-    r[13] = lagm ? (int)lagm[t] << 18 : 0;
-    r[14] = r[15] = 0;
+    r[13] = (lagm ? (int)lagm[t] << 18 : 0) | (rmask ? (int)rmask[K] << 24 : 0);
+    r[14] = rmask ? rbase[K] : 0;
+    r[15] = 0;
     const int mask = inmask[t];
     for (int f = 0; f < 6; ++f) {
         int *d = r + 16 + 13 * f;
@@ -205,10 +207,11 @@ __global__ void k_angle_masks(int C, int A, const double *__restrict__ omega, co
 }  // namespace
 
 hipError_t launch_task_records(int C, const int *nbr, const unsigned *perm, const unsigned char *inmask,
-                               const int *indeg, const unsigned char *lagm, int *rec, hipStream_t s) {
+                               const int *indeg, const unsigned char *lagm, const unsigned char *rmask,
+                               const int *rbase, int *rec, hipStream_t s) {
     const long long n = 8LL * C;
     hipLaunchKernelGGL(k_task_records, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, C, nbr, perm, inmask,
-                       indeg, lagm, rec);
+                       indeg, lagm, rmask, rbase, rec);
     return hipGetLastError();
 }
 

@@ -321,6 +321,9 @@ __global__ __launch_bounds__(256) void k_balance(const DevProblem *__restrict__ 
         const size_t cell_psi = (size_t)8 * A * G;
         for (int o = 0; o < 8; ++o) {
             const float *psi_o = P.psi + (size_t)o * C * cell_psi;
+            // reflective faces of the cell and their first slot (task record words 13, 14)
+            const int *rec = P.rec + ((size_t)o * C + K) * kRecWords;
+            const int rmask = P.refl_in ? (rec[13] >> 24) & 63 : 0, rbase = rec[14];
             for (int a = 0; a < A; ++a) {
                 const int n = o * A + a;
                 // upwind faces of the octant, or of the direction under per-angle
@@ -343,6 +346,11 @@ __global__ __launch_bounds__(256) void k_balance(const DevProblem *__restrict__ 
                         } else if (N >= 0) {
                             const int jn = (P.perm[(size_t)K * 6 + f] >> (8 * k)) & 0xff;
                             val[k] = psi_o[(size_t)N * cell_psi + ((size_t)jn * A + a) * G + g];
+                        } else if ((rmask >> f) & 1) {
+                            // the mirror image's outflow that this sweep read (see the sweep kernel)
+                            const int slot = rbase + __popc(rmask & ((1 << f) - 1));
+                            const int om = o ^ (1 << axis);
+                            val[k] = P.refl_in[((size_t)(om * P.nref + slot) * 4 + k) * A * G + (size_t)a * G + g];
                         } else {
                             val[k] = P.psib ? (double)P.psib[g] : 0.0;
                         }

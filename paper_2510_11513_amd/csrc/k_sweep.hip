@@ -273,7 +273,7 @@ __device__ long long pop_task(SweepCtl *ctl, unsigned long long *queue, int &q, 
 // with a grid-stride loop, and the next level is the next launch; no counters,
 // queues or continuation.  Task bodies are the same code, so results are the
 // same bits.  stops (nullable) marks converged problems of a batch.
-template <int NT, bool ONE, bool BSP, bool PA>
+template <int NT, bool ONE, bool BSP, bool EXT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_ONE : 4))) void k_sweep(
     const DevProblem *__restrict__ probs, int nprob, const long long *__restrict__ task_base,
     SweepCtl *__restrict__ ctl, unsigned long long *__restrict__ queue, int maxA, int maxG, int maxin,
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         // per-angle designation: every wave holds the per-direction inflow masks
         // of this (octant, cell), lane a those of direction a (A <= 64)
         int amv = 0;
-        if constexpr (PA)
+        if constexpr (EXT)
             if (P.amask && (tid & 63) < A) amv = gp(P.amask)[((size_t)o * C + K) * A + (tid & 63)];
         if (new_om && tid < A) {
             const int n = o * A + tid;
@@ -507,7 +507,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         const int mask = uni(s_desc[12]);
         const int nin = __popc(mask);
         // faces where some direction's designation differs from the octant's
-        const int lagm = PA && P.amask ? uni((s_desc[13] >> 18) & 63) : 0;
+        const int lagm = EXT && P.amask ? uni((s_desc[13] >> 18) & 63) : 0;
+        // faces on reflective planes and the first reflective slot of the cell
+        const int rmask = EXT && P.refl_in ? uni((s_desc[13] >> 24) & 63) : 0;
+        const int rbase = rmask ? uni(s_desc[14]) : 0;
+        // Reflective plane: the inflow of a direction is its mirror image's outflow
+        // at the same nodes, from the previous sweep.  The mirror image lies in the
+        // octant o ^ (1 << axis) at the same index within its octant (the
+        // quadrature's symmetry, checked at set-up), so lane p reads lane p of
+        // that octant's record of the face.
+        auto refl_row = [&](int f, float *base) {
+            const int slot = rbase + __popc(rmask & ((1 << f) - 1));
+            return base + (size_t)(((o ^ (1 << (f >> 1))) * P.nref + slot) * 4) * AG;
+        };
+        auto refl_own = [&](int f, float *base) {
+            const int slot = rbase + __popc(rmask & ((1 << f) - 1));
+            return base + (size_t)((o * P.nref + slot) * 4) * AG;
+        };
         int nb[6];
         unsigned pm[6];
 #pragma unroll
@@ -561,7 +577,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                     if (s1 < nin) sC[(n * maxin + s1) * 16 + (lane & 15)] = om.x * cx + om.y * cy + om.z * cz;
                 }
             }
-            if (PA && lagm) {
+            if (EXT && lagm) {
                 // Per-angle designation: direction n's operator is
                 // B_n = Om.S - sum over its own inflow faces of Om.F_f, so each face
                 // where its designation differs from the octant's adds Om.F_f
@@ -643,6 +659,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                                 for (int l = 0; l < 4; ++l) u[j][l] = (bnd >> j) & 1 ? psib : u[j][l];
                         }
                     };
+                    // reflective slots among `taken` (faces in slot order) read the mirror
+                    // image's outflow of the previous sweep
+                    auto reflect = [&](float (&u)[3][4], int taken) {
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            if (!taken) break;
+                            const int f = __builtin_ctz(taken);
+                            taken &= taken - 1;
+                            if ((rmask >> f) & 1) {
+                                const float *src = refl_row(f, P.refl_in);
+#pragma unroll
+                                for (int l = 0; l < 4; ++l) u[j][l] = src[l * AG + pi];
+                            }
+                        }
+                    };
                     auto apply = [&](int taken, int s0, const float (&u)[3][4]) {
 #pragma unroll
                         for (int j = 0; j < 3; ++j) {
@@ -662,6 +693,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
 #pragma unroll
                             for (int l = 0; l < 4; ++l) u0[j][l] = sUp[(j * 4 + l) * NT + tid];
                         set_boundary(u0, bnd0);
+                        if constexpr (EXT)
+                            if (rmask & taken0) reflect(u0, taken0);
                         apply(taken0, 0, u0);
                     }
                     int rest = mask & ~taken0;
@@ -671,6 +704,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                         const int taken = load_slots(rest, K, pi, AG, psi_o, s_desc, u, bnd);
                         rest &= ~taken;
                         set_boundary(u, bnd);
+                        if constexpr (EXT)
+                            if (rmask & taken) reflect(u, taken);
                         apply(taken, s0, u);
                     }
                 } else {
@@ -681,6 +716,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                         float u[4];
 #pragma unroll
                         for (int l = 0; l < 4; ++l) u[l] = nb[f] >= 0 ? L.up[f][l] : psib;
+                        if constexpr (EXT)
+                            if ((rmask >> f) & 1) {
+                                const float *src = refl_row(f, P.refl_in);
+#pragma unroll
+                                for (int l = 0; l < 4; ++l) u[l] = src[l * AG + pi];
+                            }
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
                             float t = Cs[k * 4] * u[0];
@@ -691,7 +732,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                         }
                     }
                 }
-                if (const int lf = PA ? lagm & ~mask : 0) {
+                if (const int lf = EXT ? lagm & ~mask : 0) {
                     // Per-angle designation: a face that is inflow for this direction
                     // but downwind in the octant's order takes the neighbour's trace
                     // from the previous sweep (its task runs after this one, so the
@@ -768,6 +809,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
 #pragma unroll
                     for (int j = k + 1; j < 8; ++j) t = __builtin_fmaf(-U[k][j], b[j], t);
                     b[k] = t * inv[k];
+                }
+                if constexpr (EXT) {
+                    // reflective faces this octant leaves through: their nodal outflow
+                    // for the mirror images' next sweep
+                    if (const int ro = rmask & ~mask) {
+#pragma unroll
+                        for (int f = 0; f < 6; ++f) {
+                            if (!((ro >> f) & 1)) continue;
+                            float *dst = refl_own(f, P.refl_out);
+#pragma unroll
+                            for (int l = 0; l < 4; ++l) dst[l * AG + pi] = b[face_vertex(f, l)];
+                        }
+                    }
                 }
                 const __amdgpu_buffer_rsrc_t rk = cell_block(psi_o, K, 8 * AG);
                 const float wn = sOm[4 * n + 3];
@@ -925,8 +979,8 @@ template <int NT, bool ONE, bool BSP>
 hipError_t launch_nt(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                      unsigned long long *queue, int maxA, int maxG, int maxin, int grid, size_t lds,
                      unsigned long long watchdog, const long long *bsp_tasks, long long b0, long long b1,
-                     const int *stops, int phase_stats, bool pa, hipStream_t s) {
-    if (pa)
+                     const int *stops, int phase_stats, bool ext, hipStream_t s) {
+    if (ext)
         hipLaunchKernelGGL((k_sweep<NT, ONE, BSP, true>), dim3(grid), dim3(NT), lds, s, probs, nprob, task_base, ctl,
                            queue, maxA, maxG, maxin, watchdog, bsp_tasks, b0, b1, stops, phase_stats);
     else
@@ -936,8 +990,8 @@ hipError_t launch_nt(const DevProblem *probs, int nprob, const long long *task_b
 }
 
 template <int NT, bool ONE>
-const void *kernel_ptr(bool pa) {
-    return pa ? reinterpret_cast<const void *>(&k_sweep<NT, ONE, false, true>)
+const void *kernel_ptr(bool ext) {
+    return ext ? reinterpret_cast<const void *>(&k_sweep<NT, ONE, false, true>)
               : reinterpret_cast<const void *>(&k_sweep<NT, ONE, false, false>);
 }
 
@@ -953,14 +1007,14 @@ size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin, bool one) {
     return floats * sizeof(float);
 }
 
-int sweep_occupancy(int threads, bool one, bool pa, size_t lds) {
+int sweep_occupancy(int threads, bool one, bool ext, size_t lds) {
     const void *k = nullptr;
     switch (threads) {
-        case 64: k = one ? kernel_ptr<64, true>(pa) : kernel_ptr<64, false>(pa); break;
-        case 128: k = one ? kernel_ptr<128, true>(pa) : kernel_ptr<128, false>(pa); break;
-        case 192: k = one ? kernel_ptr<192, true>(pa) : kernel_ptr<192, false>(pa); break;
-        case 256: k = one ? kernel_ptr<256, true>(pa) : kernel_ptr<256, false>(pa); break;
-        case 512: k = one ? kernel_ptr<512, true>(pa) : kernel_ptr<512, false>(pa); break;
+        case 64: k = one ? kernel_ptr<64, true>(ext) : kernel_ptr<64, false>(ext); break;
+        case 128: k = one ? kernel_ptr<128, true>(ext) : kernel_ptr<128, false>(ext); break;
+        case 192: k = one ? kernel_ptr<192, true>(ext) : kernel_ptr<192, false>(ext); break;
+        case 256: k = one ? kernel_ptr<256, true>(ext) : kernel_ptr<256, false>(ext); break;
+        case 512: k = one ? kernel_ptr<512, true>(ext) : kernel_ptr<512, false>(ext); break;
         default: return 0;
     }
     int nb = 0;
@@ -981,14 +1035,14 @@ hipError_t launch_xcc_probe(int *out, int nblocks, hipStream_t s) {
 
 hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                                unsigned long long *queue, int threads, bool one, int grid, int maxA, int maxG,
-                               int maxin, unsigned long long watchdog, bool phase_stats, bool pa, hipStream_t s) {
+                               int maxin, unsigned long long watchdog, bool phase_stats, bool ext, hipStream_t s) {
     const size_t lds = sweep_lds_bytes(threads, maxA, maxG, maxin, one);
     const int ps = phase_stats ? 1 : 0;
 #define SNX_LAUNCH(NT)                                                                                             \
     return one ? launch_nt<NT, true, false>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds,      \
-                                            watchdog, nullptr, 0, 0, nullptr, ps, pa, s)                           \
+                                            watchdog, nullptr, 0, 0, nullptr, ps, ext, s)                           \
                : launch_nt<NT, false, false>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds,     \
-                                             watchdog, nullptr, 0, 0, nullptr, ps, pa, s)
+                                             watchdog, nullptr, 0, 0, nullptr, ps, ext, s)
     switch (threads) {
         case 64: SNX_LAUNCH(64);
         case 128: SNX_LAUNCH(128);
@@ -1003,16 +1057,16 @@ hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long lo
 hipError_t launch_sweep_level(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                               int threads, bool one, int grid, int maxA, int maxG, int maxin,
                               const long long *bsp_tasks, long long begin, long long end, const int *stops,
-                              bool pa, hipStream_t s) {
+                              bool ext, hipStream_t s) {
     const size_t lds = sweep_lds_bytes(threads, maxA, maxG, maxin, one);
     const long long n = end - begin;
     if (n <= 0) return hipSuccess;
     const int g = (int)std::min<long long>(grid, n);
 #define SNX_LAUNCH(NT)                                                                                             \
     return one ? launch_nt<NT, true, true>(probs, nprob, task_base, ctl, nullptr, maxA, maxG, maxin, g, lds, 0,     \
-                                           bsp_tasks, begin, end, stops, 0, pa, s)                                 \
+                                           bsp_tasks, begin, end, stops, 0, ext, s)                                 \
                : launch_nt<NT, false, true>(probs, nprob, task_base, ctl, nullptr, maxA, maxG, maxin, g, lds, 0,    \
-                                            bsp_tasks, begin, end, stops, 0, pa, s)
+                                            bsp_tasks, begin, end, stops, 0, ext, s)
     switch (threads) {
         case 64: SNX_LAUNCH(64);
         case 128: SNX_LAUNCH(128);

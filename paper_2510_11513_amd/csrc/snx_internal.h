@@ -22,9 +22,11 @@ constexpr int kGnnFeatures = 12; // node features of the learned initial guess (
 // Task record of one (octant, cell), 96 ints (24 int4): words 0..12 the cell's
 // descriptor (neighbour ids [6], node permutations [6], inflow mask of the
 // octant), word 13 the in-degree of the downwind neighbour across face f in
-// bits 3f..3f+2 and, under per-angle designation, in bits 18..23 the faces on
+// bits 3f..3f+2, under per-angle designation in bits 18..23 the faces on
 // which some direction of the octant differs from the octant's designation,
-// 14..15 zero, then for each face f at 16 + 13 f the descriptor
+// and in bits 24..29 the cell's faces on reflective planes; word 14 the first
+// reflective slot of the cell (its reflective faces take consecutive slots in
+// face order), 15 zero, then for each face f at 16 + 13 f the descriptor
 // of the neighbour across f when f is a downwind face (zero otherwise), 94..95
 // zero.
 constexpr int kRecWords = 96;
@@ -100,6 +102,10 @@ struct DevProblem {
     float *qo;                   // [C][G][8]     cross-group scattering source of the current outer
                                  //               iteration; nullptr without a group-to-group matrix
     const float *sgg;            // [nmat][G][G]  group-to-group scattering, from g' (row) into g
+    float *refl_in;              // [8][nref][4][A][G] reflective planes: outflow of the previous sweep at
+                                 //               each reflective face's nodes per octant (read), or nullptr
+    float *refl_out;             // the same written by this sweep (copied to refl_in before the next one)
+    int nref;                    // reflective boundary faces
     const int *cmat;             // [C]           material of each cell (group-to-group matrix)
     const double *xyz;           // [nvert][3]    vertex coordinates (the network's cell positions)
     const int *cv;               // [C][8]        cell vertices
@@ -128,15 +134,16 @@ hipError_t launch_sweep_prologue(SweepCtl *ctl, unsigned long long *queue, const
                                  const int *seeds, const int *seed_off, const int *stops, hipStream_t s);
 hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                                unsigned long long *queue, int threads, bool one, int grid, int maxA, int maxG, int maxin,
-                               unsigned long long watchdog, bool phase_stats, bool pa, hipStream_t s);
+                               unsigned long long watchdog, bool phase_stats, bool ext, hipStream_t s);
 // One level of the bulk-synchronous comparator: tasks bsp_tasks[begin, end).
 hipError_t launch_sweep_level(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                               int threads, bool one, int grid, int maxA, int maxG, int maxin,
                               const long long *bsp_tasks, long long begin, long long end, const int *stops,
-                              bool pa, hipStream_t s);
+                              bool ext, hipStream_t s);
 hipError_t launch_xcc_probe(int *out, int nblocks, hipStream_t s);
 hipError_t launch_task_records(int C, const int *nbr, const unsigned *perm, const unsigned char *inmask,
-                               const int *indeg, const unsigned char *lagm, int *rec, hipStream_t s);
+                               const int *indeg, const unsigned char *lagm, const unsigned char *rmask,
+                               const int *rbase, int *rec, hipStream_t s);
 // Per-angle designation: amask[8][C][A] (bit f: Omega_n . A_f < 0), lagm[8][C]
 // (faces where a direction of the octant differs from the octant's mask) and
 // counts[3] += differing (direction, cell, face) triples, lagged ones (interior
@@ -151,8 +158,9 @@ hipError_t launch_octant_operators(int C, const float *S, const float *F, const 
 bool sweep_threads_valid(int threads);
 // `one`: every problem of the launch has (angles per octant) * G <= threads.
 size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin, bool one);
-// pa: the kernel variant with per-angle designation (any problem of the schedule uses it)
-int sweep_occupancy(int threads, bool one, bool pa, size_t lds);
+// ext: the kernel variant with per-angle designation and reflective planes (any
+// problem of the schedule uses one of them)
+int sweep_occupancy(int threads, bool one, bool ext, size_t lds);
 hipError_t launch_source(const DevProblem *probs, int prob, int C, int G, const float *phi, int *stop_flag,
                          hipStream_t s);
 hipError_t launch_reduce(const DevProblem *probs, int prob, int C, int G, float *phi_out, const float *phi_old,
