@@ -62,6 +62,8 @@ def lib():
         L.snxo_setup.argtypes = [vp]
         L.snxo_set_designation.argtypes = [vp, ct.c_int]
         L.snxo_set_reflective.argtypes = [vp, ct.c_int]
+        L.snxo_set_anisotropy.argtypes = [vp, ct.c_int, nullable_d]
+        L.snxo_get_harmonics.argtypes = [vp, _dp]
         L.snxo_set_group_scattering.argtypes = [vp, ct.c_int, nullable_d, nullable_d]
         L.snxo_solve_outer.argtypes = [vp, ct.c_int, ct.c_int, ct.c_double, nullable_d, _dp,
                                        ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), ct.POINTER(ct.c_double)]
@@ -155,6 +157,23 @@ class Oracle:
 
     def setup(self):
         self._check(lib().snxo_setup(self.h), "setup")
+
+    def set_anisotropy(self, sigma_l):
+        """sigma_l[ncell][G][L]: Legendre moments 1..L of the within-group scattering
+        law (None or L = 0: isotropic).  Before setup."""
+        if sigma_l is None or np.asarray(sigma_l).shape[-1] == 0:
+            self._sigl = None
+            self._check(lib().snxo_set_anisotropy(self.h, 0, None), "set_anisotropy")
+            return
+        self._sigl = np.ascontiguousarray(sigma_l, np.float64)
+        if self._sigl.shape[:2] != (self.ncell, self.G):
+            raise ValueError("sigma_l must be [ncell][G][L]")
+        self._check(lib().snxo_set_anisotropy(self.h, self._sigl.shape[2], _ptr(self._sigl)), "set_anisotropy")
+
+    def harmonics(self, L):
+        y = np.zeros((self.nang, (L + 1) ** 2))
+        self._check(lib().snxo_get_harmonics(self.h, y), "get_harmonics")
+        return y
 
     def set_reflective(self, planes: int):
         """Reflective boundary planes, bit 2*axis + side (before setup)."""

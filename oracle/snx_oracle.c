@@ -33,6 +33,9 @@ struct snxo_problem {
     int32_t *inflow, *level, *order;/* [8][C] each */
     int designation;                /* 0 per octant, 1 per angle (snxo_set_designation) */
     int refl;                       /* reflective planes (snxo_set_reflective): bit 2*axis + side */
+    int L;                          /* anisotropic scattering order (snxo_set_anisotropy), 0 = isotropic */
+    double *sigl;                   /* [C][G][L] Legendre moments sigma_1..sigma_L of the within-group law */
+    double *ylm;                    /* [nang][(L+1)^2] real orthonormal spherical harmonics (setup) */
     int32_t *rdir;                  /* [nang][3] the direction mirrored across each axis (setup) */
     int nmat;                       /* group-to-group scattering (snxo_set_group_scattering), 0 = none */
     int32_t *cmat;                  /* [C] material of each cell */
@@ -194,7 +197,8 @@ int snxo_quadrature(int npolar, int nazim, double *omega, double *w) {
 static void free_derived(snxo_problem *p) {
     free(p->M); free(p->S); free(p->F); free(p->area);
     free(p->nbr); free(p->nbrf); free(p->perm);
-    free(p->inflow); free(p->level); free(p->order); free(p->ain); free(p->rdir);
+    free(p->inflow); free(p->level); free(p->order); free(p->ain); free(p->rdir); free(p->ylm);
+    p->ylm = NULL;
     p->M = p->S = p->F = p->area = NULL;
     p->nbr = p->nbrf = p->perm = p->inflow = p->level = p->order = p->ain = p->rdir = NULL;
     p->ready = 0;
@@ -211,7 +215,7 @@ void snxo_destroy(snxo_problem *p) {
     free_derived(p);
     free(p->xyz); free(p->cv); free(p->omega); free(p->w);
     free(p->sigt); free(p->sigs); free(p->q); free(p->psib);
-    free(p->cmat); free(p->sgg);
+    free(p->cmat); free(p->sgg); free(p->sigl);
     free(p);
 }
 
@@ -279,6 +283,23 @@ int snxo_set_designation(snxo_problem *p, int kind) {
     if (!p || (kind != 0 && kind != 1)) return fail(p, SNXO_E_ARG, "designation must be 0 or 1");
     p->designation = kind;
     free_derived(p);
+    return SNXO_OK;
+}
+
+int snxo_set_anisotropy(snxo_problem *p, int L, const double *sigma_l) {
+    if (!p || p->G < 1 || p->ncell < 1) return fail(p, SNXO_E_STATE, "set the mesh and materials first");
+    if (L < 0 || L > 7 || (L > 0 && !sigma_l)) return fail(p, SNXO_E_ARG, "0 <= L <= 7 and sigma_l required");
+    free(p->sigl);
+    p->sigl = NULL;
+    p->L = 0;
+    free_derived(p);
+    if (L == 0) return SNXO_OK;
+    size_t n = (size_t)p->ncell * p->G * L;
+    for (size_t i = 0; i < n; ++i)
+        if (!isfinite(sigma_l[i])) return fail(p, SNXO_E_ARG, "sigma_l must be finite");
+    p->sigl = dup_d(sigma_l, n);
+    if (!p->sigl) return fail(p, SNXO_E_OOM, "out of memory");
+    p->L = L;
     return SNXO_OK;
 }
 
@@ -566,6 +587,44 @@ static int build_angle_inflow(snxo_problem *p) {
     return SNXO_OK;
 }
 
+/* Real orthonormal spherical harmonics of every direction up to degree L,
+ * index l*l + l + m (m = -l..l): Y_l0 = N_l0 P_l(mu), Y_lm = sqrt2 N_lm P_l^m(mu)
+ * cos(m phi) and Y_l,-m = sqrt2 N_lm P_l^m(mu) sin(m phi) for m > 0, with
+ * N_lm^2 = (2l+1)/(4 pi) (l-m)!/(l+m)!, mu = Omega_z, phi the azimuth of
+ * (Omega_x, Omega_y) and P_l^m from the three-term recurrence in l. */
+static int build_harmonics(snxo_problem *p) {
+    int L = p->L, nm = (L + 1) * (L + 1);
+    p->ylm = malloc(sizeof(double) * (size_t)p->nang * nm);
+    if (!p->ylm) return fail(p, SNXO_E_OOM, "out of memory");
+    for (int n = 0; n < p->nang; ++n) {
+        const double *om = p->omega + 3 * n;
+        double mu = om[2], phi = atan2(om[1], om[0]), st = sqrt(fmax(0.0, 1.0 - mu * mu));
+        double P[8][8];                 /* P[l][m] */
+        for (int m = 0; m <= L; ++m) {
+            double pmm = 1.0;           /* (2m-1)!! sin^m */
+            for (int k = 1; k <= m; ++k) pmm *= (2.0 * k - 1.0) * st;
+            P[m][m] = pmm;
+            if (m + 1 <= L) P[m + 1][m] = (2.0 * m + 1.0) * mu * pmm;
+            for (int l = m + 2; l <= L; ++l)
+                P[l][m] = ((2.0 * l - 1.0) * mu * P[l - 1][m] - (l + m - 1.0) * P[l - 2][m]) / (l - m);
+        }
+        double *y = p->ylm + (size_t)n * nm;
+        for (int l = 0; l <= L; ++l)
+            for (int m = 0; m <= l; ++m) {
+                double ratio = 1.0;     /* (l-m)!/(l+m)! */
+                for (int k = l - m + 1; k <= l + m; ++k) ratio /= k;
+                double N = sqrt((2.0 * l + 1.0) / (4.0 * PI) * ratio);
+                if (m == 0) {
+                    y[l * l + l] = N * P[l][0];
+                } else {
+                    y[l * l + l + m] = sqrt(2.0) * N * P[l][m] * cos(m * phi);
+                    y[l * l + l - m] = sqrt(2.0) * N * P[l][m] * sin(m * phi);
+                }
+            }
+    }
+    return SNXO_OK;
+}
+
 /* Reflective planes: for each direction and axis, the direction with that
  * component negated (it must be in the quadrature set). */
 static int build_reflection(snxo_problem *p) {
@@ -629,6 +688,7 @@ int snxo_setup(snxo_problem *p) {
     if (!rc) rc = build_dag(p);
     if (!rc && p->designation == 1) rc = build_angle_inflow(p);
     if (!rc && p->refl) rc = build_reflection(p);
+    if (!rc && p->L) rc = build_harmonics(p);
     if (rc) { free_derived(p); return rc; }
     p->ready = 1;
     return SNXO_OK;
@@ -751,6 +811,25 @@ static int sweep_src(snxo_problem *p, const double *phi_in, const double *qouter
     int C = p->ncell, G = p->G, nang = p->nang, per = nang / 8;
     memset(phi_out, 0, sizeof(double) * 8 * (size_t)C * G);
     if (leak) memset(leak, 0, sizeof(double) * (size_t)C * G);
+    /* Anisotropic scattering: the flux moments phi_lm = sum_n w_n Y_lm(Omega_n)
+     * psi_n of degree 1..L, from the previous sweep's angular flux (the scalar
+     * flux phi_in carries degree 0).  The source of direction n then gains
+     * sum_{l>=1} sigma_l sum_m Y_lm(Omega_n) phi_lm, the expansion of the
+     * scattering law sum_l (2l+1)/(4 pi) sigma_l P_l(Omega . Omega'). */
+    int nm = (p->L + 1) * (p->L + 1);
+    double *mom = NULL;
+    if (p->L) {
+        mom = calloc((size_t)C * G * nm * 8, sizeof(double));
+        if (!mom) return fail(p, SNXO_E_OOM, "out of memory");
+        if (psi_prev)
+            for (int n = 0; n < nang; ++n)
+                for (long K = 0; K < C; ++K)
+                    for (int g = 0; g < G; ++g)
+                        for (int k = 1; k < nm; ++k)
+                            for (int j = 0; j < 8; ++j)
+                                mom[(((size_t)K * G + g) * nm + k) * 8 + j] +=
+                                    p->w[n] * p->ylm[(size_t)n * nm + k] * psi_prev[(((long)n * C + K) * G + g) * 8 + j];
+    }
     int bad = 0;
     /* Groups are independent: each group's angle sum runs sequentially over
      * (octant, angle) so the result does not depend on the thread count. */
@@ -771,6 +850,12 @@ static int sweep_src(snxo_problem *p, const double *phi_in, const double *qouter
                         for (int j = 0; j < 8; ++j) qn[j] = p->ang_src[(((long)K * nang + n) * G + g) * 8 + j];
                     } else {
                         source_nodal(p, phi_in, qouter, K, g, qn);
+                        for (int l = 1; l <= p->L; ++l) {
+                            double sl = p->sigl[((size_t)K * G + g) * p->L + (l - 1)];
+                            for (int k = l * l; k < (l + 1) * (l + 1); ++k)
+                                for (int j = 0; j < 8; ++j)
+                                    qn[j] += sl * p->ylm[(size_t)n * nm + k] * mom[(((size_t)K * G + g) * nm + k) * 8 + j];
+                        }
                     }
                     if (solve_local(p, K, n, g, qn, psi_cur, psi_prev, x, (leak || leak_ang) ? &L : NULL)) {
                         bad = 1;
@@ -787,6 +872,7 @@ static int sweep_src(snxo_problem *p, const double *phi_in, const double *qouter
             }
         free(psi_cur);
     }
+    free(mom);
     if (bad) return fail(p, SNXO_E_MESH, "singular local system or out of memory");
     return SNXO_OK;
 }
@@ -807,7 +893,7 @@ int snxo_sweep_angle(snxo_problem *p, const double *phi_in, int n, int g, const 
     if (!psi_out) return fail(p, SNXO_E_ARG, "psi_out is NULL");
     int C = p->ncell, G = p->G, nang = p->nang, per = nang / 8;
     if (n < 0 || n >= nang || g < 0 || g >= G) return fail(p, SNXO_E_ARG, "angle or group out of range");
-    if (p->refl) return fail(p, SNXO_E_ARG, "reflective planes couple directions: use snxo_sweep");
+    if (p->refl || p->L) return fail(p, SNXO_E_ARG, "reflective planes and anisotropy couple directions: use snxo_sweep");
     int o = n / per;
     for (long i = 0; i < 8L * C; ++i) psi_out[i] = psi_prev ? psi_prev[i] : 0.0;
     for (int t = 0; t < C; ++t) {
@@ -844,7 +930,7 @@ int snxo_solve(snxo_problem *p, double tol, int max_it, const double *phi0,
     /* designation 1 and reflective planes: the angular flux carried between
      * sweeps (previous and next kept apart: a reflective face reads another
      * direction's previous values) */
-    int carry = p->designation == 1 || p->refl;
+    int carry = p->designation == 1 || p->refl || p->L;
     double *psi = carry ? calloc(n * (size_t)p->nang, sizeof(double)) : NULL;
     double *psi2 = carry ? calloc(n * (size_t)p->nang, sizeof(double)) : NULL;
     if (!cur || (carry && (!psi || !psi2))) {
@@ -887,7 +973,7 @@ int snxo_solve_outer(snxo_problem *p, int outer, int inner, double tol, const do
     int C = p->ncell, G = p->G;
     size_t n = 8 * (size_t)C * G;
     double *start = malloc(sizeof(double) * n), *x = malloc(sizeof(double) * n), *qo = calloc(n, sizeof(double));
-    int carry = p->designation == 1 || p->refl;
+    int carry = p->designation == 1 || p->refl || p->L;
     double *psi = carry ? calloc(n * (size_t)p->nang, sizeof(double)) : NULL;
     double *psi2 = carry ? calloc(n * (size_t)p->nang, sizeof(double)) : NULL;
     if (!start || !x || !qo || (carry && (!psi || !psi2))) {
@@ -1004,5 +1090,12 @@ int snxo_get_angle_inflow(snxo_problem *p, int32_t *ain) {
     if (!p || !p->ready) return fail(p, SNXO_E_STATE, "setup has not run");
     if (p->designation != 1 || !ain) return fail(p, SNXO_E_ARG, "per-angle masks exist under designation 1 only");
     memcpy(ain, p->ain, sizeof(int32_t) * (size_t)p->nang * p->ncell);
+    return SNXO_OK;
+}
+
+int snxo_get_harmonics(snxo_problem *p, double *y) {
+    if (!p || !p->ready) return fail(p, SNXO_E_STATE, "setup has not run");
+    if (!p->L || !y) return fail(p, SNXO_E_ARG, "harmonics exist with anisotropic scattering only");
+    memcpy(y, p->ylm, sizeof(double) * (size_t)p->nang * (p->L + 1) * (p->L + 1));
     return SNXO_OK;
 }

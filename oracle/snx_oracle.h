@@ -70,6 +70,17 @@ int  snxo_set_materials(snxo_problem *p, int ngroup, const double *sigma_t,
                         const double *sigma_s, const double *q);
 /* kind 0 = vacuum, 1 = isotropic inflow psi_b[g] on every inflow boundary face. */
 int  snxo_set_boundary(snxo_problem *p, int kind, const double *psi_b);
+/* Anisotropic within-group scattering (after snxo_set_materials, before
+ * snxo_setup; L = 0 clears): the scattering law
+ * sum_{l=0..L} (2l+1)/(4 pi) sigma_l P_l(Omega . Omega') with sigma_0 the
+ * sigma_s of snxo_set_materials (or of the group matrix's diagonal) and
+ * sigma_l[ncell][G][L] holding sigma_1..sigma_L.  The degree >= 1 flux moments
+ * come from the previous sweep's angular flux (psi_prev), the scalar flux from
+ * phi_in; L <= 7. */
+int  snxo_set_anisotropy(snxo_problem *p, int L, const double *sigma_l);
+/* Real orthonormal spherical harmonics of the directions used by the
+ * anisotropic source: y[nang][(L+1)^2], index l*l + l + m. */
+int  snxo_get_harmonics(snxo_problem *p, double *y);
 /* Reflective boundary planes (before snxo_setup; default none): bit
  * 2*axis + side makes the boundary faces whose outward area vector points
  * along -axis (side 0) or +axis (side 1) reflective.  On such a face the inflow
