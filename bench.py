@@ -132,6 +132,38 @@ def per_angle(prob, threads: int, wg_per_cu: int, ms_octant: float, its_octant: 
             "tol": prob.tol}
 
 
+def extensions(prob, threads: int, wg_per_cu: int, steps: int):
+    """Per-iteration cost of the optional physics on the same workload: each
+    variant is set up in the benchmark's schedule and timed over `steps`
+    graph-captured source iterations (wall clock around one solve call)."""
+    import numpy as np
+    import torch
+    from paper_2510_11513_amd import inputs, snx
+    sigl = lambda L: prob.mat.sigma_s[:, :, None] * 0.5 ** np.arange(1, L + 1)[None, None, :]
+    variants = {
+        "plain": lambda p: None,
+        "reflective_6_planes": lambda p: p.set_reflective(63),
+        "anisotropic_L1": lambda p: p.set_anisotropy(sigl(1)),
+        "anisotropic_L3": lambda p: p.set_anisotropy(sigl(3)),
+        "group_to_group_matrix": lambda p: p.set_group_scattering(*inputs.split_scattering(prob.mat)),
+    }
+    out = {}
+    for name, configure in variants.items():
+        p = snx.Problem.from_problem(prob, setup=False)
+        configure(p)
+        p.set_schedule(threads=threads, wg_per_cu=wg_per_cu, chunk=steps)
+        p.setup()
+        phi = p.empty_phi()
+        p.solve(0.0, steps, phi=phi, allow_noconv=True)         # graph build and warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.solve(0.0, steps, phi=phi, allow_noconv=True)
+        torch.cuda.synchronize()
+        out[name + "_ms_per_iteration"] = round((time.perf_counter() - t0) / steps * 1e3, 4)
+        p.close()
+    return out
+
+
 def kernel_hash() -> str:
     path = os.path.join(ROOT, "paper_2510_11513_amd", "csrc", "k_sweep.hip")
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
@@ -216,6 +248,8 @@ def main():
     ap.add_argument("--paper-shape", type=int, default=1, help="also time the paper's 25-sweep 16^3 shape (0 = skip)")
     ap.add_argument("--per-angle", type=int, default=1,
                     help="also time the workload under per-angle designation (0 = skip)")
+    ap.add_argument("--extensions", type=int, default=1,
+                    help="also time reflective planes, anisotropy and group coupling on the workload (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -308,6 +342,9 @@ def main():
         _, info_oct = p.solve(prob.tol, 5000)
         out["per_angle"] = per_angle(prob, stats["threads"], tuned[1] if tuned else args.wg_per_cu, ms_sweep,
                                      info_oct["iterations"], max(5, min(args.steps, 20)))
+    if args.extensions:
+        print("[bench] optional physics", file=sys.stderr, flush=True)
+        out["extensions"] = extensions(prob, stats["threads"], tuned[1] if tuned else args.wg_per_cu, 10)
     if args.paper_shape:
         out["paper_shape"] = paper_shape()
     if args.learned > 0:

@@ -100,6 +100,24 @@ snx_status snx_set_materials(snx_problem *p, int32_t ngroup, const double *sigma
  * kind 1 = isotropic inflow psi_in[G] (host float64). */
 snx_status snx_set_boundary(snx_problem *p, int32_t kind, const double *psi_in);
 
+/* Anisotropic within-group scattering through flux moments (the moment
+ * dimension of the paper's table of arrays: source, scalar_flux_moments and
+ * the expansion coefficients ec; after snx_set_materials, before snx_setup;
+ * L = 0 restores isotropic scattering).
+ * - The law is sum over l = 0..L of (2l+1)/(4 pi) sigma_l P_l(Omega . Omega').
+ *   sigma_0 is the within-group sigma_s.  sigma_l is host float64
+ *   [ncell][G][L], holding sigma_1..sigma_L.  L <= 3.
+ * - Direction n gets sum over l >= 1 of sigma_l sum over m of
+ *   Y_lm(Omega_n) phi_lm on top of the isotropic source.  Y are real
+ *   orthonormal spherical harmonics; phi_lm = sum_n w_n Y_lm(Omega_n) psi_n are
+ *   the moments of the problem's previous sweep (zero after snx_setup).  The
+ *   scalar flux comes from phi_in as before, so the exchange layout is unchanged.
+ * - Each sweep first computes the moments and a per-direction source array
+ *   (the size of the angular flux).
+ * - Errors: SNX_E_STATE before the materials; SNX_E_ARG for L > 3 or a
+ *   non-finite sigma_l. */
+snx_status snx_set_anisotropy(snx_problem *p, int32_t L, const double *sigma_l);
+
 /* Reflective boundary planes (UnSNAP's reason not to sweep octants
  * concurrently, §2.1; before snx_setup, a change undoes any earlier setup).
  * planes: bit 2*axis + side (0..5) marks the boundary faces whose area vector

@@ -82,6 +82,84 @@ __global__ void k_outer_source(const DevProblem *__restrict__ probs, int prob, c
     out[1] = make_float4(v[4], v[5], v[6], v[7]);
 }
 
+// Anisotropic scattering (the flux-moment arrays of the paper's table of
+// arrays).  Step 1: the degree >= 1 moments of the previous sweep's angular
+// flux, phi_lm = sum_n w_n Y_lm(Omega_n) psi_n, one thread per (cell, node,
+// group) with the group fastest, so each direction's reads are contiguous.
+constexpr int kMaxMoments = 16;   // (L + 1)^2 for L <= 3
+__global__ __launch_bounds__(256) void k_moments(const DevProblem *__restrict__ probs, int prob,
+                                                 const int *__restrict__ stop_flag) {
+    if (stop_flag && *stop_flag) return;
+    const DevProblem &P = probs[prob];
+    const int C = P.C, G = P.G, A = P.A, nm = (P.L + 1) * (P.L + 1);
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)C * 8 * G) return;
+    const int g = (int)(t % G), d = (int)((t / G) % 8), K = (int)(t / (8LL * G));
+    float acc[kMaxMoments];
+#pragma unroll
+    for (int k = 0; k < kMaxMoments; ++k) acc[k] = 0.f;
+    const size_t AG = (size_t)A * G;
+    for (int o = 0; o < 8; ++o) {
+        const float *ps = P.psi + (((size_t)o * C + K) * 8 + d) * AG + g;
+        for (int a = 0; a < A; ++a) {
+            const int n = o * A + a;
+            const float wv = P.w[n] * ps[(size_t)a * G];
+            const float *y = P.ylm + (size_t)n * nm;
+#pragma unroll
+            for (int k = 1; k < kMaxMoments; ++k)
+                if (k < nm) acc[k] = __builtin_fmaf(y[k], wv, acc[k]);
+        }
+    }
+    float *out = P.mom + ((size_t)K * G + g) * nm * 8 + d;
+#pragma unroll
+    for (int k = 1; k < kMaxMoments; ++k)
+        if (k < nm) out[(size_t)k * 8] = acc[k];
+}
+
+// Step 2: per-direction source dofs r_n = M s_n with
+//   s_n = (Q + sigma_s phi + qo) / (4 pi) + sum_{l>=1} sigma_l sum_m Y_lm(Omega_n) phi_lm
+// (the expansion of sum_l (2l+1)/(4 pi) sigma_l P_l(Omega . Omega')), written in
+// the layout of the angular flux.  One thread per (octant, cell, angle, group),
+// group fastest.
+__global__ __launch_bounds__(256) void k_ang_source(const DevProblem *__restrict__ probs, int prob,
+                                                    const float *__restrict__ phi, const int *__restrict__ stop_flag) {
+    if (stop_flag && *stop_flag) return;
+    const DevProblem &P = probs[prob];
+    const int C = P.C, G = P.G, A = P.A, L = P.L, nm = (L + 1) * (L + 1);
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 8LL * C * A * G) return;
+    const int g = (int)(t % G), a = (int)((t / G) % A);
+    const long long oc = t / ((long long)A * G);
+    const int K = (int)(oc % C), o = (int)(oc / C), n = o * A + a;
+    const long long cg = (long long)K * G + g;
+    const float q = P.q[cg], ss = P.sigs[cg];
+    float s[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const float ph = phi ? phi[cg * 8 + j] : 0.f;
+        const float qo = P.qo ? P.qo[cg * 8 + j] : 0.f;
+        s[j] = (q + (ss * ph + qo)) * kInv4Pi;
+    }
+    const float *mom = P.mom + cg * nm * 8;
+    for (int l = 1; l <= L; ++l) {
+        const float sl = P.sigl[cg * L + (l - 1)];
+        for (int k = l * l; k < (l + 1) * (l + 1); ++k) {
+            const float c = sl * P.ylm[(size_t)n * nm + k];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s[j] = __builtin_fmaf(c, mom[(size_t)k * 8 + j], s[j]);
+        }
+    }
+    const float *M = P.M + (size_t)K * 64;
+    float *out = P.rang + ((size_t)o * C + K) * 8 * A * G + (size_t)a * G + g;
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        float r = 0.f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r = __builtin_fmaf(M[d * 8 + j], s[j], r);
+        out[(size_t)d * A * G] = r;
+    }
+}
+
 // FP64 max-norm terms of a - b: out[0] = max |a - b|, out[1] = max |a| (both
 // non-negative, so their bit patterns order like the values); out must be zero.
 __global__ __launch_bounds__(256) void k_max_change(const float *__restrict__ a, const float *__restrict__ b,
@@ -508,6 +586,19 @@ hipError_t launch_integrated_flux(const float *M, const float *phi, int C, int G
 hipError_t launch_outer_source(const DevProblem *probs, int prob, int C, int G, const float *phi, hipStream_t s) {
     const long long n = (long long)C * G;
     hipLaunchKernelGGL(k_outer_source, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, probs, prob, phi);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const DevProblem *probs, int prob, int C, int G, const int *stop_flag, hipStream_t s) {
+    const long long n = (long long)C * 8 * G;
+    hipLaunchKernelGGL(k_moments, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, probs, prob, stop_flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_ang_source(const DevProblem *probs, int prob, int C, int A, int G, const float *phi,
+                             const int *stop_flag, hipStream_t s) {
+    const long long n = 8LL * C * A * G;
+    hipLaunchKernelGGL(k_ang_source, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, probs, prob, phi, stop_flag);
     return hipGetLastError();
 }
 

@@ -641,6 +641,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
 #pragma unroll
                     for (int d = 0; d < 8; ++d) b[d] = L.r[d];
                 }
+                if constexpr (EXT)
+                    if (P.rang) {
+                        // anisotropic scattering: this direction's own source dofs
+                        const __amdgpu_buffer_rsrc_t rr = cell_block(P.rang + (size_t)o * C * cell_psi, K, 8 * AG);
+#pragma unroll
+                        for (int d = 0; d < 8; ++d)
+                            b[d] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rr, 4 * pi, d * AG * 4, 0));
+                    }
                 const float psib = L.psib;
                 if constexpr (ONE) {
                     // Inflow faces in slot order (slot s = s-th set bit of the mask),

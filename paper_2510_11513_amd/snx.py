@@ -32,7 +32,8 @@ EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_s
            "snx_gnn_load", "snx_gnn_features", "snx_gnn_targets", "snx_gnn_forward", "snx_gnn_grad",
            "snx_gnn_train_step", "snx_gnn_predict", "snx_set_sweep_mode", "snx_batch_set_sweep_mode",
            "snx_get_psi", "snx_set_sweep_stats", "snx_batch_set_sweep_stats", "snx_set_designation",
-           "snx_designation_stats", "snx_set_group_scattering", "snx_solve_outer", "snx_set_reflective"]
+           "snx_designation_stats", "snx_set_group_scattering", "snx_solve_outer", "snx_set_reflective",
+           "snx_set_anisotropy"]
 _NO_STATUS = ("snx_destroy", "snx_last_error", "snx_batch_destroy", "snx_batch_last_error", "snx_gnn_destroy",
               "snx_gnn_last_error")
 
@@ -84,6 +85,7 @@ def load(path: str = LIB_PATH):
     L.snx_get_psi.argtypes = [_vp, ct.c_int32, ct.c_int32, _vp, _vp]
     L.snx_set_designation.argtypes = [_vp, ct.c_int32]
     L.snx_set_reflective.argtypes = [_vp, ct.c_int32]
+    L.snx_set_anisotropy.argtypes = [_vp, ct.c_int32, _vp]
     L.snx_set_group_scattering.argtypes = [_vp, ct.c_int32, _vp, _vp]
     L.snx_solve_outer.argtypes = [_vp, ct.c_int32, ct.c_int32, ct.c_double, _vp, _vp, ct.POINTER(SolveInfo), _vp]
     L.snx_designation_stats.argtypes = [_vp, _vp]
@@ -219,6 +221,18 @@ class Problem:
         arr = None if psi_in is None else np.ascontiguousarray(psi_in, np.float64)
         ptr = None if arr is None else arr.ctypes.data_as(ct.c_void_p)
         self._check(load().snx_set_boundary(self.h, kind, ptr), "set_boundary")
+
+    def set_anisotropy(self, sigma_l):
+        """sigma_l[ncell][G][L] (L <= 3): Legendre moments 1..L of the within-group
+        scattering law; None restores isotropic scattering.  Takes effect at setup."""
+        if sigma_l is None:
+            self._check(load().snx_set_anisotropy(self.h, 0, None), "set_anisotropy")
+            return
+        sl = np.ascontiguousarray(sigma_l, np.float64)
+        if sl.ndim != 3:
+            raise ValueError("sigma_l must be [ncell][G][L]")
+        self._check(load().snx_set_anisotropy(self.h, sl.shape[2], sl.ctypes.data_as(ct.c_void_p)),
+                    "set_anisotropy")
 
     def set_reflective(self, planes: int):
         """Reflective boundary planes, bit 2*axis + side; takes effect at setup."""

@@ -1,0 +1,171 @@
+"""Anisotropic scattering on the GPU vs the FP64 oracle (through the C ABI).
+
+The degree >= 1 flux moments come from the previous sweep's angular flux: the
+GPU keeps it as problem state, the oracle reads psi_prev.  Chained sweeps are
+compared sweep by sweep; then a converged solve, and the combination with
+reflective planes, group coupling and per-angle designation.  The scattering
+moments follow a Henyey-Greenstein-like law, sigma_l = sigma_s * 0.5^l.
+
+Tolerance: 1e-5 relative per group on the scalar flux.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_11513_amd import inputs
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _problem(n, G, npol, naz, seed, kind=0, c=(0.2, 0.8)):
+    rng = np.random.default_rng(seed)
+    mesh = inputs.make_mesh(n, 0.2, rng=rng)
+    mat = inputs.materials_loguniform_blocks(mesh, G, rng, 2, c[0], c[1])
+    prob = inputs.Problem(f"aniso_n{n}G{G}", mesh, mat, npol, naz, 1e-6)
+    if kind == 1:
+        prob.boundary_kind = 1
+        prob.psi_b = rng.uniform(0.1, 1.0, G)
+    return prob
+
+
+def _sigl(prob, L):
+    return prob.mat.sigma_s[:, :, None] * 0.5 ** np.arange(1, L + 1)[None, None, :]
+
+
+def _pair(prob, L, threads=None, mode=None, planes=0, groups=False, designation=0):
+    from paper_2510_11513_amd import snx
+    p = snx.Problem.from_problem(prob, setup=False, designation=designation)
+    o = oracle.Oracle.from_problem(prob, setup=False, designation=designation)
+    if groups:
+        cm, sgg = inputs.split_scattering(prob.mat)
+        p.set_group_scattering(cm, sgg)
+        o.set_group_scattering(cm, sgg)
+    p.set_anisotropy(_sigl(prob, L))
+    o.set_anisotropy(_sigl(prob, L))
+    if planes:
+        p.set_reflective(planes)
+        o.set_reflective(planes)
+    if threads:
+        p.set_schedule(threads=threads)
+    p.setup()
+    o.setup()
+    if mode is not None:
+        p.set_sweep_mode(mode)
+    return p, o
+
+
+def _phi_in(prob, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 2.0, (prob.mesh.ncell, prob.mat.ngroup, 8)).astype(np.float32)
+
+
+def _chain(p, phi32, k):
+    torch = _torch()
+    pin = torch.from_numpy(phi32).cuda()
+    outs = []
+    for _ in range(k):
+        out = p.sweep(pin)
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy().astype(np.float64))
+    return outs
+
+
+CASES = {
+    "L1": (lambda: _problem(4, 3, 2, 2, seed=1), 1, None),
+    "L2_inflow": (lambda: _problem(4, 4, 2, 3, seed=2, kind=1), 2, None),
+    "L3_ragged_n5": (lambda: _problem(5, 5, 3, 3, seed=3), 3, None),
+    "L2_multi_round_threads64": (lambda: _problem(4, 16, 3, 4, seed=4), 2, 64),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_chained_sweeps_match_the_oracle(name):
+    make, L, threads = CASES[name]
+    prob = make()
+    print(f"[case] anisotropic {name}: C={prob.mesh.ncell} G={prob.mat.ngroup} nang={prob.nang} L={L}", flush=True)
+    p, o = _pair(prob, L, threads=threads)
+    phi32 = _phi_in(prob, 7)
+    outs = _chain(p, phi32, 3)
+    prev = None
+    for k in range(3):
+        r = o.sweep(phi32.astype(np.float64), want_psi=True, psi_prev=prev)
+        err = H.rel_err_per_group(outs[k], r["phi"])
+        print(f"[case] sweep {k}: phi max rel err {err.max():.2e}", flush=True)
+        assert err.max() <= TOL, (k, err)
+        prev = r["psi"]
+    assert np.abs(outs[1] - outs[0]).max() > 1e-4 * np.abs(outs[0]).max()   # the moments enter
+    p.close()
+
+
+def test_bulk_synchronous_mode_gives_the_same_bits():
+    from paper_2510_11513_amd import snx
+    prob = _problem(4, 3, 2, 2, seed=5)
+    phi32 = _phi_in(prob, 8)
+    pa, _ = _pair(prob, 2)
+    pb, _ = _pair(prob, 2, mode=snx.SWEEP_BSP)
+    for x, y in zip(_chain(pa, phi32, 3), _chain(pb, phi32, 3)):
+        assert np.array_equal(x, y)
+
+
+def test_converged_solution():
+    prob = _problem(4, 3, 2, 3, seed=6, c=(0.2, 0.6))
+    p, o = _pair(prob, 2)
+    phi, info = p.solve(1e-6, 2000)
+    assert info["status"] == 0, info
+    ref = o.solve(1e-12, 5000)
+    err = H.rel_err_per_group(phi.cpu().numpy().astype(np.float64), ref["phi"])
+    print(f"[case] anisotropic solve: iterations gpu {info['iterations']} oracle {ref['iters']}, "
+          f"rel err {err.max():.2e}", flush=True)
+    assert err.max() <= TOL, err
+    p.close()
+
+
+def test_with_reflection_group_coupling_and_per_angle_designation():
+    prob = _problem(4, 4, 2, 3, seed=9, kind=1)
+    p, o = _pair(prob, 1, planes=0b010001, groups=True, designation=1)
+    phi, info = p.solve_outer(5, 5, 0.0)
+    ref = o.solve_outer(5, 5, 0.0)
+    err = H.rel_err_per_group(phi.cpu().numpy().astype(np.float64), ref["phi"])
+    print(f"[case] anisotropic + reflective + groups + per-angle 5x5: rel err {err.max():.2e}", flush=True)
+    assert err.max() <= TOL, err
+    p.close()
+
+
+def test_batch_with_an_anisotropic_problem():
+    torch = _torch()
+    from paper_2510_11513_amd import snx
+    probs = [_problem(4, 3, 2, 2, seed=10), _problem(3, 4, 1, 2, seed=11)]
+    Ls = [2, 0]
+    gp, ors = [], []
+    for pr, L in zip(probs, Ls):
+        q = snx.Problem.from_problem(pr, setup=False)
+        o = oracle.Oracle.from_problem(pr, setup=False)
+        if L:
+            q.set_anisotropy(_sigl(pr, L))
+            o.set_anisotropy(_sigl(pr, L))
+        q.setup()
+        o.setup()
+        gp.append(q)
+        ors.append(o)
+    batch = snx.Batch(gp)
+    phis = [_phi_in(pr, 40 + i) for i, pr in enumerate(probs)]
+    prev = [None, None]
+    for k in range(3):
+        outs = batch.sweep([torch.from_numpy(x).cuda() for x in phis])
+        torch.cuda.synchronize()
+        for i in range(len(probs)):
+            r = ors[i].sweep(phis[i].astype(np.float64), want_psi=True, psi_prev=prev[i])
+            prev[i] = r["psi"]
+            err = H.rel_err_per_group(outs[i].cpu().numpy().astype(np.float64), r["phi"])
+            assert err.max() <= TOL, (k, i, err)
+    batch.close()
+    for q in gp:
+        q.close()
