@@ -65,8 +65,9 @@ def pmc_summary(fetch_db: str, write_db: str, out_path: str, fetch_cmd: str, wri
     def copy_value(d):   # the plain 1 GiB copy is the largest dispatch of the runtime's copy kernel
         return max(max(v) for k, v in d.items() if "copyBuffer" in k or "copy" in k.lower())
 
-    def sweep_values(d):   # dependency-driven sweep dispatches that did work (not the per-level comparator)
-        vals = [x for k, v in d.items() if re.search(r"k_sweep<\d+, (true|false), false>", k) for x in v]
+    def sweep_values(d):   # default dependency-driven sweeps that did work (not the per-level comparator
+        #                     nor the variant for the optional physics)
+        vals = [x for k, v in d.items() if re.search(r"k_sweep<\d+, (true|false), false, false>", k) for x in v]
         top = max(vals)
         return [x for x in vals if x > 0.5 * top]
 
