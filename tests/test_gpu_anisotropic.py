@@ -169,3 +169,24 @@ def test_batch_with_an_anisotropic_problem():
     batch.close()
     for q in gp:
         q.close()
+
+
+@pytest.mark.parametrize("n,G,npol,naz,L,planes,designation", [
+    (1, 1, 1, 1, 1, 0b111111, 0),     # one cell, one group, every plane reflective
+    (3, 100, 1, 2, 2, 0b000011, 1),   # G > 64: several rounds of lanes, per-angle designation
+    (2, 7, 2, 2, 3, 0b110000, 1),     # odd group count, L = 3
+])
+def test_edge_shapes_with_all_extensions(n, G, npol, naz, L, planes, designation):
+    prob = _problem(n, G, npol, naz, seed=50 + n * G, kind=1)
+    print(f"[case] edge n={n} G={G} quad={npol}x{naz} L={L} planes={planes:06b} designation={designation}",
+          flush=True)
+    p, o = _pair(prob, L, planes=planes, designation=designation, groups=G > 1)
+    phi32 = _phi_in(prob, 3)
+    outs = _chain(p, phi32, 2)
+    prev = None
+    for k in range(2):
+        r = o.sweep(phi32.astype(np.float64), want_psi=True, psi_prev=prev)
+        err = H.rel_err_per_group(outs[k], r["phi"])
+        assert err.max() <= TOL, (k, err)
+        prev = r["psi"]
+    p.close()
