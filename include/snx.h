@@ -112,8 +112,9 @@ snx_status snx_set_boundary(snx_problem *p, int32_t kind, const double *psi_in);
  *   orthonormal spherical harmonics; phi_lm = sum_n w_n Y_lm(Omega_n) psi_n are
  *   the moments of the problem's previous sweep (zero after snx_setup).  The
  *   scalar flux comes from phi_in as before, so the exchange layout is unchanged.
- * - Each sweep first computes the moments and a per-direction source array
- *   (the size of the angular flux).
+ * - Before each sweep one pass over the last angular flux forms the moments
+ *   and their source dofs sigma_l M phi_lm ([ncell][G][(L+1)^2][8]); the
+ *   sweep adds each direction's harmonic-weighted sum per lane.
  * - Errors: SNX_E_STATE before the materials; SNX_E_ARG for L > 3 or a
  *   non-finite sigma_l. */
 snx_status snx_set_anisotropy(snx_problem *p, int32_t L, const double *sigma_l);

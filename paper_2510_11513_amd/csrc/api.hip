@@ -248,7 +248,7 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
         sc.maxG = std::max(sc.maxG, p->G);
         sc.maxAG = std::max(sc.maxAG, p->A * p->G);
         sc.maxin = std::max(sc.maxin, p->maxin);
-        sc.ext = sc.ext || p->hp.amask != nullptr || p->hp.refl_in != nullptr || p->hp.rang != nullptr;
+        sc.ext = sc.ext || p->hp.amask != nullptr || p->hp.refl_in != nullptr || p->hp.mom != nullptr;
         for (int o = 0; o < 8; ++o) {
             seed_off[i * 8 + o] = (int)seeds.size();
             seeds.insert(seeds.end(), p->seeds_by_octant[o].begin(), p->seeds_by_octant[o].end());
@@ -359,15 +359,13 @@ snx_status enqueue_sweep(Sched &sc, const int *stops, hipStream_t s, hipEvent_t 
 }
 
 // Anisotropic problems of the schedule: flux moments of their last sweep's psi
-// and the per-direction sources from scalar fluxes phi[p] (entries may be NULL);
-// stops (device, nullable) retires problems.
-snx_status enqueue_ang_sources(Sched &sc, const float *const *phi, const int *stops, hipStream_t s) {
+// and the moments' source dofs; stops (device, nullable) retires problems.  The
+// isotropic source comes from the source update as before.
+snx_status enqueue_ang_sources(Sched &sc, const int *stops, hipStream_t s) {
     for (int i = 0; i < sc.nprob(); ++i) {
         const DevProblem &P = sc.hprobs[i];
-        if (!P.rang) continue;
-        const int *stop = stops ? stops + i : nullptr;
-        HIPCHK_E(sc.err, launch_moments(sc.d_probs, i, P.C, P.G, stop, s), "moments");
-        HIPCHK_E(sc.err, launch_ang_source(sc.d_probs, i, P.C, P.A, P.G, phi ? phi[i] : nullptr, stop, s), "source");
+        if (!P.mom) continue;
+        HIPCHK_E(sc.err, launch_moments(sc.d_probs, i, P.C, P.G, stops ? stops + i : nullptr, s), "moments");
     }
     return SNX_OK;
 }
@@ -393,7 +391,7 @@ snx_status sched_sweep(Sched &sc, const float *const *phi_in, float *const *phi_
     const int n = sc.nprob();
     HIPCHK_E(sc.err, launch_iter_init_batch(sc.d_ic, sc.d_stop, n, 1, 0.0, s), "init");
     HIPCHK_E(sc.err, launch_source_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_user, nullptr, s), "source");
-    st = enqueue_ang_sources(sc, phi_in, nullptr, s);
+    st = enqueue_ang_sources(sc, nullptr, s);
     if (st) return st;
     st = enqueue_sweep(sc, nullptr, s);
     if (st) return st;
@@ -415,11 +413,7 @@ snx_status build_graph(Sched &sc, int parity) {
             hipError_t e = launch_reduce_batch(sc.d_probs, n, sc.d_rblk_base, sc.nrblk, sc.d_buf + (cur ^ 1) * n,
                                                sc.d_buf + cur * n, 1, sc.d_ic, sc.d_stop, cs);
             if (e != hipSuccess) st = hip_fail_msg(sc.err, e, "reduce launch");
-            if (!st) {   // anisotropic problems: the next sweep's per-direction sources from the new phi
-                std::vector<const float *> fresh(n);
-                for (int k = 0; k < n; ++k) fresh[k] = sc.probs[k]->d_phi[cur ^ 1];
-                st = enqueue_ang_sources(sc, fresh.data(), sc.d_stop, cs);
-            }
+            if (!st) st = enqueue_ang_sources(sc, sc.d_stop, cs);   // anisotropic: moments of this sweep
         }
     }
     hipGraph_t g = nullptr;
@@ -444,12 +438,8 @@ snx_status sched_solve(Sched &sc, double tol, int max_it, const float *const *ph
     HIPCHK_E(sc.err, launch_iter_init_batch(sc.d_ic, sc.d_stop, n, max_it, tol, s), "init");
     HIPCHK_E(sc.err, launch_copy_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_buf, sc.d_user, s), "copy");
     HIPCHK_E(sc.err, launch_source_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_buf, nullptr, s), "source");
-    {
-        std::vector<const float *> start(n);
-        for (int i = 0; i < n; ++i) start[i] = sc.probs[i]->d_phi[0];
-        st = enqueue_ang_sources(sc, start.data(), nullptr, s);
-        if (st) return st;
-    }
+    st = enqueue_ang_sources(sc, nullptr, s);
+    if (st) return st;
     char *pin = reinterpret_cast<char *>(sc.pinned);
     IterCtl *hic = reinterpret_cast<IterCtl *>(pin + 16 * (size_t)n);
     int *hstop = reinterpret_cast<int *>(pin + 64 * (size_t)n);
@@ -990,7 +980,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
 
     // anisotropic scattering: harmonics of the directions (FP64 on the host, from
     // the standard library's associated Legendre functions), moments, sources
-    float *dsigl = nullptr, *dylm = nullptr, *dmom = nullptr, *drang = nullptr;
+    float *dsigl = nullptr, *dylm = nullptr, *dmom = nullptr, *drmom = nullptr;
     if (p->L) {
         const int L = p->L, nm = (L + 1) * (L + 1);
         std::vector<float> y((size_t)p->nang * nm);
@@ -1014,10 +1004,11 @@ snx_status snx_setup(snx_problem *p, void *stream) {
         HIPCHK(p, m.alloc((void **)&dsigl, sizeof(float) * sl.size()), "device allocation");
         HIPCHK(p, m.alloc((void **)&dylm, sizeof(float) * y.size()), "device allocation");
         HIPCHK(p, m.alloc((void **)&dmom, sizeof(float) * C * G * nm * 8), "device allocation");
-        HIPCHK(p, m.alloc((void **)&drang, sizeof(float) * 8 * C * 8 * A * G), "device allocation");
+        HIPCHK(p, m.alloc((void **)&drmom, sizeof(float) * C * G * nm * 8), "device allocation");
         HIPCHK(p, hipMemcpy(dsigl, sl.data(), sizeof(float) * sl.size(), hipMemcpyHostToDevice), "copy");
         HIPCHK(p, hipMemcpy(dylm, y.data(), sizeof(float) * y.size(), hipMemcpyHostToDevice), "copy");
         HIPCHK(p, launch_fill_f32(dmom, C * G * nm * 8, 0.f, s), "fill");
+        HIPCHK(p, launch_fill_f32(drmom, C * G * nm * 8, 0.f, s), "fill");
         // the moments of the first sweep come from a zero angular flux
         HIPCHK(p, launch_fill_f32(dpsi, 8 * C * 8 * A * G, 0.f, s), "fill");
     }
@@ -1090,7 +1081,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     hp.amask = damask;
     hp.qo = dqo; hp.sgg = dsgg; hp.cmat = dcmat;
     hp.refl_in = drefl_in; hp.refl_out = drefl_out; hp.nref = p->nref;
-    hp.L = p->L; hp.sigl = dsigl; hp.ylm = dylm; hp.mom = dmom; hp.rang = drang;
+    hp.L = p->L; hp.sigl = dsigl; hp.ylm = dylm; hp.mom = dmom; hp.rmom = drmom;
     hp.sigt = dsigt; hp.sigs = dsigs; hp.q = dq; hp.r = dr; hp.omega = dom; hp.w = dw; hp.psib = dpsib;
     hp.psi = dpsi; hp.slot = dslot; hp.slotc = dslotc; hp.cnt = dcnt; hp.rec = drec;
     hp.xyz = d_xyz; hp.cv = d_cv;
@@ -1132,10 +1123,8 @@ snx_status snx_sweep(snx_problem *p, const float *phi_in, float *phi_out, void *
     if (p->nmat)   // one Jacobi step over groups: the cross-group source from phi_in too
         HIPCHK(p, launch_outer_source(p->sched.d_probs, 0, p->C, p->G, phi_in, s), "outer source");
     HIPCHK(p, launch_source(p->sched.d_probs, 0, p->C, p->G, phi_in, nullptr, s), "source");
-    if (p->hp.rang) {   // anisotropic: moments of the last sweep's psi, then each direction's source
+    if (p->hp.mom)   // anisotropic: moments of the last sweep's psi and their source dofs
         HIPCHK(p, launch_moments(p->sched.d_probs, 0, p->C, p->G, nullptr, s), "moments");
-        HIPCHK(p, launch_ang_source(p->sched.d_probs, 0, p->C, p->A, p->G, phi_in, nullptr, s), "source");
-    }
     SCHED_ERR(p, enqueue_sweep(p->sched, nullptr, s));
     HIPCHK(p, launch_reduce(p->sched.d_probs, 0, p->C, p->G, phi_out, nullptr, false, nullptr, nullptr, s), "reduce");
     return SNX_OK;

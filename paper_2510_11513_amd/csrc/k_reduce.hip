@@ -116,47 +116,33 @@ __global__ __launch_bounds__(256) void k_moments(const DevProblem *__restrict__ 
         if (k < nm) out[(size_t)k * 8] = acc[k];
 }
 
-// Step 2: per-direction source dofs r_n = M s_n with
-//   s_n = (Q + sigma_s phi + qo) / (4 pi) + sum_{l>=1} sigma_l sum_m Y_lm(Omega_n) phi_lm
-// (the expansion of sum_l (2l+1)/(4 pi) sigma_l P_l(Omega . Omega')), written in
-// the layout of the angular flux.  One thread per (octant, cell, angle, group),
-// group fastest.
-__global__ __launch_bounds__(256) void k_ang_source(const DevProblem *__restrict__ probs, int prob,
-                                                    const float *__restrict__ phi, const int *__restrict__ stop_flag) {
+// Step 2: the source dofs of each moment, sigma_l M phi_lm (degree >= 1), one
+// thread per (cell, group).  A direction's source is then the isotropic
+// r = M (Q + sigma_s phi + qo) / (4 pi) plus sum_k Y_k(Omega_n) of these, which
+// the sweep adds per lane: the expansion of
+// sum_l (2l+1)/(4 pi) sigma_l P_l(Omega . Omega') over real orthonormal harmonics.
+__global__ __launch_bounds__(256) void k_moment_sources(const DevProblem *__restrict__ probs, int prob,
+                                                        const int *__restrict__ stop_flag) {
     if (stop_flag && *stop_flag) return;
     const DevProblem &P = probs[prob];
-    const int C = P.C, G = P.G, A = P.A, L = P.L, nm = (L + 1) * (L + 1);
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 8LL * C * A * G) return;
-    const int g = (int)(t % G), a = (int)((t / G) % A);
-    const long long oc = t / ((long long)A * G);
-    const int K = (int)(oc % C), o = (int)(oc / C), n = o * A + a;
-    const long long cg = (long long)K * G + g;
-    const float q = P.q[cg], ss = P.sigs[cg];
-    float s[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const float ph = phi ? phi[cg * 8 + j] : 0.f;
-        const float qo = P.qo ? P.qo[cg * 8 + j] : 0.f;
-        s[j] = (q + (ss * ph + qo)) * kInv4Pi;
-    }
-    const float *mom = P.mom + cg * nm * 8;
-    for (int l = 1; l <= L; ++l) {
-        const float sl = P.sigl[cg * L + (l - 1)];
-        for (int k = l * l; k < (l + 1) * (l + 1); ++k) {
-            const float c = sl * P.ylm[(size_t)n * nm + k];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) s[j] = __builtin_fmaf(c, mom[(size_t)k * 8 + j], s[j]);
-        }
-    }
+    const int C = P.C, G = P.G, L = P.L, nm = (L + 1) * (L + 1);
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;   // K * G + g
+    if (t >= (long long)C * G) return;
+    const int K = (int)(t / G);
     const float *M = P.M + (size_t)K * 64;
-    float *out = P.rang + ((size_t)o * C + K) * 8 * A * G + (size_t)a * G + g;
+    for (int l = 1; l <= L; ++l) {
+        const float sl = P.sigl[t * L + (l - 1)];
+        for (int k = l * l; k < (l + 1) * (l + 1); ++k) {
+            const float *m = P.mom + ((size_t)t * nm + k) * 8;
+            float *r = P.rmom + ((size_t)t * nm + k) * 8;
 #pragma unroll
-    for (int d = 0; d < 8; ++d) {
-        float r = 0.f;
+            for (int d = 0; d < 8; ++d) {
+                float acc = 0.f;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) r = __builtin_fmaf(M[d * 8 + j], s[j], r);
-        out[(size_t)d * A * G] = r;
+                for (int j = 0; j < 8; ++j) acc = __builtin_fmaf(M[d * 8 + j], m[j], acc);
+                r[d] = sl * acc;
+            }
+        }
     }
 }
 
@@ -592,13 +578,8 @@ hipError_t launch_outer_source(const DevProblem *probs, int prob, int C, int G, 
 hipError_t launch_moments(const DevProblem *probs, int prob, int C, int G, const int *stop_flag, hipStream_t s) {
     const long long n = (long long)C * 8 * G;
     hipLaunchKernelGGL(k_moments, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, probs, prob, stop_flag);
-    return hipGetLastError();
-}
-
-hipError_t launch_ang_source(const DevProblem *probs, int prob, int C, int A, int G, const float *phi,
-                             const int *stop_flag, hipStream_t s) {
-    const long long n = 8LL * C * A * G;
-    hipLaunchKernelGGL(k_ang_source, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, probs, prob, phi, stop_flag);
+    const long long m = (long long)C * G;
+    hipLaunchKernelGGL(k_moment_sources, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, probs, prob, stop_flag);
     return hipGetLastError();
 }
 

@@ -642,12 +642,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                     for (int d = 0; d < 8; ++d) b[d] = L.r[d];
                 }
                 if constexpr (EXT)
-                    if (P.rang) {
-                        // anisotropic scattering: this direction's own source dofs
-                        const __amdgpu_buffer_rsrc_t rr = cell_block(P.rang + (size_t)o * C * cell_psi, K, 8 * AG);
+                    if (P.mom) {
+                        // anisotropic scattering: sum over moments of degree >= 1 of
+                        // Y_k(Omega_n) sigma_l M phi_lm on top of the isotropic source
+                        const int nm = (P.L + 1) * (P.L + 1);
+                        const float *y = P.ylm + (size_t)(o * A + n) * nm;
+                        const float *rm = P.rmom + ((size_t)K * G + g) * nm * 8;
+                        for (int k = 1; k < nm; ++k) {
+                            const float yk = y[k];
 #pragma unroll
-                        for (int d = 0; d < 8; ++d)
-                            b[d] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rr, 4 * pi, d * AG * 4, 0));
+                            for (int d = 0; d < 8; ++d) b[d] = __builtin_fmaf(yk, rm[k * 8 + d], b[d]);
+                        }
                     }
                 const float psib = L.psib;
                 if constexpr (ONE) {

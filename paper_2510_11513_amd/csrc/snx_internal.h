@@ -109,8 +109,9 @@ struct DevProblem {
     int L;                       // anisotropic scattering degree (0: isotropic)
     const float *sigl;           // [C][G][L]     Legendre moments sigma_1..sigma_L of the scattering law
     const float *ylm;            // [8*A][(L+1)^2] real orthonormal spherical harmonics of the directions
-    float *mom;                  // [C][G][(L+1)^2][8] flux moments of the previous sweep (degree >= 1)
-    float *rang;                 // [8][C][8][A][G] per-direction source dofs (anisotropic), or nullptr
+    float *mom;                  // [C][G][(L+1)^2][8] flux moments of the previous sweep (degree >= 1),
+                                 //               nullptr when isotropic
+    float *rmom;                 // [C][G][(L+1)^2][8] their source dofs sigma_l M phi_lm (degree >= 1)
     const int *cmat;             // [C]           material of each cell (group-to-group matrix)
     const double *xyz;           // [nvert][3]    vertex coordinates (the network's cell positions)
     const int *cv;               // [C][8]        cell vertices
@@ -179,11 +180,10 @@ hipError_t launch_fill_f32(float *p, size_t n, float v, hipStream_t s);
 // P.qo of problem `prob` from phi (NULL = zero): sum over g' != g of sigma(g' -> g) phi_g'.
 hipError_t launch_outer_source(const DevProblem *probs, int prob, int C, int G, const float *phi, hipStream_t s);
 // out[0] |= max |a - b|, out[1] |= max |a| as FP64 bit patterns (out zeroed by the caller).
-// Anisotropic scattering: flux moments of degree >= 1 from P.psi, then the
-// per-direction source dofs P.rang from them and the scalar flux phi.
+// Anisotropic scattering: flux moments of degree >= 1 from P.psi (P.mom), then
+// their source dofs sigma_l M phi_lm (P.rmom), which the sweep weighs by each
+// direction's harmonics.
 hipError_t launch_moments(const DevProblem *probs, int prob, int C, int G, const int *stop_flag, hipStream_t s);
-hipError_t launch_ang_source(const DevProblem *probs, int prob, int C, int A, int G, const float *phi,
-                             const int *stop_flag, hipStream_t s);
 hipError_t launch_max_change(const float *a, const float *b, long long n, unsigned long long *out, hipStream_t s);
 hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s);
 hipError_t launch_copy_f32(float *dst, const float *src, size_t n, const int *stop_flag, hipStream_t s);
