@@ -3,8 +3,10 @@
  *
  * The library solves steady, fixed-source, multigroup linear Boltzmann
  * transport (Eq. 1 of "An Asynchronous Many-Task Algorithm for Unstructured
- * S_N Transport on Shared Memory Systems") with within-group isotropic
- * scattering and no group coupling, on unstructured hexahedral meshes,
+ * S_N Transport on Shared Memory Systems") on unstructured hexahedral meshes,
+ * with within-group isotropic scattering by default and, optionally,
+ * group-to-group scattering with inner/outer iterations, anisotropic
+ * scattering moments, reflective boundary planes and per-direction upwinding,
  * discretised by S_N discrete ordinates grouped in octants (Section 2) and
  * first-order discontinuous Galerkin finite elements (one 8x8 "assemble and
  * solve" per cell, angle and group; Table 1 lists the element arrays).  One
