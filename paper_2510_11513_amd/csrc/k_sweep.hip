@@ -273,6 +273,11 @@ __device__ long long pop_task(SweepCtl *ctl, unsigned long long *queue, int &q, 
 // with a grid-stride loop, and the next level is the next launch; no counters,
 // queues or continuation.  Task bodies are the same code, so results are the
 // same bits.  stops (nullable) marks converged problems of a batch.
+//
+// EXT: the variant for the optional physics of a problem: per-direction
+// upwinding (lagged faces), reflective planes and anisotropic moments.  Each
+// part is guarded by its own array being present, so the variant also runs
+// plain problems of a mixed batch; without EXT none of its code is compiled.
 template <int NT, bool ONE, bool BSP, bool EXT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_ONE : 4))) void k_sweep(
     const DevProblem *__restrict__ probs, int nprob, const long long *__restrict__ task_base,

@@ -190,3 +190,27 @@ def test_edge_shapes_with_all_extensions(n, G, npol, naz, L, planes, designation
         assert err.max() <= TOL, (k, err)
         prev = r["psi"]
     p.close()
+
+
+def test_tuned_schedule_of_the_extended_variant():
+    """The autotuner times the extended kernel variant (its own cache key and
+    occupancy); the tuned schedule must still match the oracle."""
+    prob = _problem(5, 6, 2, 2, seed=60, kind=1)
+    p, o = _pair(prob, 1, planes=0b000101, designation=1)
+    threads, wg = p.tune(None)
+    st = p.sweep_stats()
+    print(f"[case] tuned extended variant: threads={threads} wg/cu={wg} grid={st['grid']}", flush=True)
+    assert threads == st["threads"]
+    # tuning ran sweeps: start the comparison from a fresh problem state, in the
+    # tuned schedule
+    p.set_schedule(threads=threads, wg_per_cu=wg)
+    p.setup()
+    assert p.sweep_stats()["threads"] == threads
+    phi32 = _phi_in(prob, 61)
+    outs = _chain(p, phi32, 2)
+    prev = None
+    for k in range(2):
+        r = o.sweep(phi32.astype(np.float64), want_psi=True, psi_prev=prev)
+        assert H.rel_err_per_group(outs[k], r["phi"]).max() <= TOL, k
+        prev = r["psi"]
+    p.close()
