@@ -260,12 +260,21 @@ snx_status snx_set_schedule(snx_problem *p, int32_t threads, int32_t wg_per_cu, 
 #define SNX_SWEEP_BSP 1
 snx_status snx_set_sweep_mode(snx_problem *p, int32_t mode);
 
-/* Schedule autotuner: times a few sweeps of every (threads, workgroups per
- * CU) candidate on this problem and keeps the fastest.  cache_path (nullable)
- * is a text file of JSON lines keyed by device and problem shape: a hit skips
- * the timing, a miss appends the result.  host chosen[2] (nullable) receives
- * (threads, workgroups per CU).  Synchronous. */
+/* Schedule autotuner: times a few sweeps of every candidate on this problem
+ * and keeps the fastest.  The candidates are the dependency-driven sweep at
+ * every (threads, workgroups per CU) and the bulk-synchronous one at every
+ * width, so the tuner also picks the sweep mode (small meshes favour the
+ * bulk-synchronous one, whose level launch costs less than a chain of
+ * dependent tasks).  cache_path (nullable) is a text file of JSON lines keyed
+ * by device and problem shape: a hit skips the timing, a miss appends the
+ * result.  host chosen[2] (nullable) receives (threads, workgroups per CU);
+ * snx_get_schedule reports the mode.  Synchronous. */
 snx_status snx_tune(snx_problem *p, const char *cache_path, int32_t *chosen, void *stream);
+
+/* The problem's sweep schedule after setup or tuning, host out[4]: threads per
+ * task workgroup, the workgroups-per-CU cap (0: occupancy), the graph chunk
+ * length of snx_solve, and the sweep mode (SNX_SWEEP_AMT or SNX_SWEEP_BSP). */
+snx_status snx_get_schedule(snx_problem *p, int32_t *out);
 
 /* Times the sweep kernel alone: nsweeps source iterations from device phi_in
  * (NULL = zero) into device phi_out, with HIP events recorded on `stream`

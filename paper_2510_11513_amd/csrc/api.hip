@@ -559,7 +559,7 @@ std::string tune_key(const Sched &sc) {
     return buf;
 }
 
-bool cache_lookup(const char *path, const std::string &key, int &threads, int &wg) {
+bool cache_lookup(const char *path, const std::string &key, int &threads, int &wg, int &mode) {
     if (!path) return false;
     FILE *f = std::fopen(path, "r");
     if (!f) return false;
@@ -567,11 +567,13 @@ bool cache_lookup(const char *path, const std::string &key, int &threads, int &w
     bool found = false;
     while (std::fgets(line, sizeof line, f)) {
         char k[300];
-        int t = 0, w = 0;
-        if (std::sscanf(line, "{\"key\": \"%299[^\"]\", \"threads\": %d, \"wg_per_cu\": %d", k, &t, &w) == 3 &&
-            key == k) {
+        int t = 0, w = 0, m = SNX_SWEEP_AMT;
+        if (std::sscanf(line, "{\"key\": \"%299[^\"]\", \"threads\": %d, \"wg_per_cu\": %d, \"mode\": %d", k, &t,
+                        &w, &m) == 4 &&
+            key == k && (m == SNX_SWEEP_AMT || m == SNX_SWEEP_BSP)) {
             threads = t;
             wg = w;
+            mode = m;
             found = true;   // the last entry for a key wins
         }
     }
@@ -579,21 +581,22 @@ bool cache_lookup(const char *path, const std::string &key, int &threads, int &w
     return found;
 }
 
-void cache_store(const char *path, const std::string &key, int threads, int wg, double ms) {
+void cache_store(const char *path, const std::string &key, int threads, int wg, int mode, double ms) {
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"wg_per_cu\": %d, \"ms\": %.6f}\n", key.c_str(), threads, wg,
-                 ms);
+    std::fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"wg_per_cu\": %d, \"mode\": %d, \"ms\": %.6f}\n",
+                 key.c_str(), threads, wg, mode, ms);
     std::fclose(f);
 }
 
 snx_status tune_sched(Sched &sc, const char *cache, hipStream_t s, int *out_threads, int *out_wg, double *out_ms) {
     const std::string key = tune_key(sc);
-    int t = 0, w = 0;
-    if (cache_lookup(cache, key, t, w) && t >= sc.maxG) {
+    int t = 0, w = 0, md = SNX_SWEEP_AMT;
+    if (cache_lookup(cache, key, t, w, md) && t >= sc.maxG) {
         sc.threads = t;
         sc.wg_per_cu = w;
+        sc.mode = md;
         sc.drop_graphs();
         if (!configure_grid(sc)) {
             *out_threads = t;
@@ -602,18 +605,24 @@ snx_status tune_sched(Sched &sc, const char *cache, hipStream_t s, int *out_thre
             return SNX_OK;
         }
     }
-    // two passes over the candidates, each candidate's best pass counts (clock and
-    // thermal drift during the first pass does not decide)
-    struct Cand { int th, wg; double ms; };
+    // Candidates: the dependency-driven sweep at every (threads, workgroups per CU)
+    // and the level-synchronous one at every width (its grid only caps a level's
+    // workgroups).  Small meshes favour the second: a level launch costs less than
+    // the latency of a chain of dependent tasks through device-coherent memory.
+    // Two passes, each candidate's best pass counts (clock and thermal drift
+    // during the first pass does not decide).
+    struct Cand { int th, wg, mode; double ms; };
     std::vector<Cand> cands;
     for (int th : {64, 128, 192, 256, 512}) {
         if (th < sc.maxG) continue;
-        for (int wg : {0, 2, 4, 8}) cands.push_back({th, wg, 1e300});
+        for (int wg : {0, 2, 4, 8}) cands.push_back({th, wg, SNX_SWEEP_AMT, 1e300});
+        cands.push_back({th, 0, SNX_SWEEP_BSP, 1e300});
     }
     for (int pass = 0; pass < 2; ++pass)
         for (Cand &c : cands) {
             sc.threads = c.th;
             sc.wg_per_cu = c.wg;
+            sc.mode = c.mode;
             if (configure_grid(sc)) continue;
             double ms = 0.0;
             snx_status st = time_sweeps(sc, 1, s, &ms);           // warm-up
@@ -622,15 +631,16 @@ snx_status tune_sched(Sched &sc, const char *cache, hipStream_t s, int *out_thre
             c.ms = std::min(c.ms, ms);
         }
     double best = 1e300;
-    int bt = sc.threads, bw = sc.wg_per_cu;
+    int bt = sc.threads, bw = sc.wg_per_cu, bm = sc.mode;
     for (const Cand &c : cands)
-        if (c.ms < best) { best = c.ms; bt = c.th; bw = c.wg; }
+        if (c.ms < best) { best = c.ms; bt = c.th; bw = c.wg; bm = c.mode; }
     sc.threads = bt;
     sc.wg_per_cu = bw;
+    sc.mode = bm;
     sc.drop_graphs();
     snx_status st = configure_grid(sc);
     if (st) return st;
-    cache_store(cache, key, bt, bw, best);
+    cache_store(cache, key, bt, bw, bm, best);
     *out_threads = bt;
     *out_wg = bw;
     *out_ms = best;
@@ -1300,7 +1310,18 @@ snx_status snx_tune(snx_problem *p, const char *cache_path, int32_t *chosen, voi
     SCHED_ERR(p, tune_sched(p->sched, cache_path, (hipStream_t)stream, &t, &w, &ms));
     p->threads = t;
     p->wg_per_cu = w;
+    p->mode = p->sched.mode;
     if (chosen) { chosen[0] = t; chosen[1] = w; }
+    return SNX_OK;
+}
+
+snx_status snx_get_schedule(snx_problem *p, int32_t *out) {
+    if (!p || !out) return SNX_E_ARG;
+    if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
+    out[0] = p->sched.threads;
+    out[1] = p->sched.wg_per_cu;
+    out[2] = p->sched.chunk;
+    out[3] = p->sched.mode;
     return SNX_OK;
 }
 
@@ -1428,6 +1449,7 @@ snx_status snx_batch_tune(snx_batch *b, const char *cache_path, int32_t *chosen,
     double ms = 0;
     snx_status st = tune_sched(b->sched, cache_path, (hipStream_t)stream, &t, &w, &ms);
     if (st) return st;
+    b->mode = b->sched.mode;
     if (chosen) { chosen[0] = t; chosen[1] = w; }
     return SNX_OK;
 }

@@ -32,7 +32,7 @@ constexpr int kGnnFeatures = 12; // node features of the learned initial guess (
 constexpr int kRecWords = 96;
 // Revision of the sweep kernel's schedule behaviour: part of the autotuner's
 // cache key, raised when a kernel change can move the best schedule.
-constexpr int kSweepRevision = 2;
+constexpr int kSweepRevision = 3;
 
 // LDS stage buffer of one sweep task (floats): the cell data M, T of the octant
 // and the six face matrices (136 float4s) and the task record (24 int4s); for

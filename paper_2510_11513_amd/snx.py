@@ -33,7 +33,7 @@ EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_s
            "snx_gnn_train_step", "snx_gnn_predict", "snx_set_sweep_mode", "snx_batch_set_sweep_mode",
            "snx_get_psi", "snx_set_sweep_stats", "snx_batch_set_sweep_stats", "snx_set_designation",
            "snx_designation_stats", "snx_set_group_scattering", "snx_solve_outer", "snx_set_reflective",
-           "snx_set_anisotropy"]
+           "snx_set_anisotropy", "snx_get_schedule"]
 _NO_STATUS = ("snx_destroy", "snx_last_error", "snx_batch_destroy", "snx_batch_last_error", "snx_gnn_destroy",
               "snx_gnn_last_error")
 
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
     L.snx_get_psi.argtypes = [_vp, ct.c_int32, ct.c_int32, _vp, _vp]
     L.snx_set_designation.argtypes = [_vp, ct.c_int32]
     L.snx_set_reflective.argtypes = [_vp, ct.c_int32]
+    L.snx_get_schedule.argtypes = [_vp, _vp]
     L.snx_set_anisotropy.argtypes = [_vp, ct.c_int32, _vp]
     L.snx_set_group_scattering.argtypes = [_vp, ct.c_int32, _vp, _vp]
     L.snx_solve_outer.argtypes = [_vp, ct.c_int32, ct.c_int32, ct.c_double, _vp, _vp, ct.POINTER(SolveInfo), _vp]
@@ -338,6 +339,12 @@ class Problem:
 
     def set_schedule(self, threads: int = 0, wg_per_cu: int = 0, chunk: int = 0):
         self._check(load().snx_set_schedule(self.h, threads, wg_per_cu, chunk), "set_schedule")
+
+    def schedule(self):
+        """The sweep schedule: threads, workgroups per CU (0: occupancy), chunk, mode."""
+        out = np.zeros(4, np.int32)
+        self._check(load().snx_get_schedule(self.h, out.ctypes.data_as(ct.c_void_p)), "get_schedule")
+        return {"threads": int(out[0]), "wg_per_cu": int(out[1]), "chunk": int(out[2]), "mode": int(out[3])}
 
     def set_sweep_mode(self, mode: int):
         """SWEEP_AMT (dependency-driven, default) or SWEEP_BSP (level by level, the comparator)."""

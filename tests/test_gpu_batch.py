@@ -87,7 +87,7 @@ def test_tuner_picks_a_valid_schedule_and_caches(tmp_path):
     batch = snx.Batch(gp)
     cache = tmp_path / "tune.jsonl"
     t, w = batch.tune(cache)
-    assert t in (64, 128, 256, 512) and t >= max(pr.mat.ngroup for pr in probs)
+    assert t in (64, 128, 192, 256, 512) and t >= max(pr.mat.ngroup for pr in probs)
     lines = cache.read_text().strip().splitlines()
     assert len(lines) == 1 and '"threads": %d' % t in lines[0]
     assert batch.tune(cache) == (t, w)                   # cache hit: same choice, no new line
@@ -99,6 +99,8 @@ def test_tuner_picks_a_valid_schedule_and_caches(tmp_path):
         assert H.rel_err_per_group(out[i].cpu().numpy().astype(np.float64), ref).max() <= TOL
     t1, w1 = gp[0].tune(tmp_path / "single.jsonl")
     assert t1 >= probs[0].mat.ngroup
+    sch = gp[0].schedule()        # the tuner also picks the sweep mode
+    assert sch["threads"] == t1 and sch["mode"] in (snx.SWEEP_AMT, snx.SWEEP_BSP)
 
 
 def test_batch_rejects_unready_problem():
