@@ -87,11 +87,16 @@ __global__ void k_outer_source(const DevProblem *__restrict__ probs, int prob, c
 // flux, phi_lm = sum_n w_n Y_lm(Omega_n) psi_n, one thread per (cell, node,
 // group) with the group fastest, so each direction's reads are contiguous.
 constexpr int kMaxMoments = 16;   // (L + 1)^2 for L <= 3
+// The harmonics of every direction go to LDS (at most 8 * 64 * 16 floats) once
+// per block; the launch passes that size as dynamic LDS.
 __global__ __launch_bounds__(256) void k_moments(const DevProblem *__restrict__ probs, int prob,
                                                  const int *__restrict__ stop_flag) {
     if (stop_flag && *stop_flag) return;
     const DevProblem &P = probs[prob];
     const int C = P.C, G = P.G, A = P.A, nm = (P.L + 1) * (P.L + 1);
+    extern __shared__ float s_ylm[];
+    for (int i = threadIdx.x; i < 8 * A * nm; i += blockDim.x) s_ylm[i] = P.ylm[i];
+    __syncthreads();
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)C * 8 * G) return;
     const int g = (int)(t % G), d = (int)((t / G) % 8), K = (int)(t / (8LL * G));
@@ -101,13 +106,21 @@ __global__ __launch_bounds__(256) void k_moments(const DevProblem *__restrict__ 
     const size_t AG = (size_t)A * G;
     for (int o = 0; o < 8; ++o) {
         const float *ps = P.psi + (((size_t)o * C + K) * 8 + d) * AG + g;
-        for (int a = 0; a < A; ++a) {
-            const int n = o * A + a;
-            const float wv = P.w[n] * ps[(size_t)a * G];
-            const float *y = P.ylm + (size_t)n * nm;
+        // eight directions' loads in flight together, then their moments
+        for (int a0 = 0; a0 < A; a0 += 8) {
+            float v[8];
 #pragma unroll
-            for (int k = 1; k < kMaxMoments; ++k)
-                if (k < nm) acc[k] = __builtin_fmaf(y[k], wv, acc[k]);
+            for (int j = 0; j < 8; ++j) v[j] = a0 + j < A ? ps[(size_t)(a0 + j) * G] : 0.f;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (a0 + j >= A) break;
+                const int n = o * A + a0 + j;
+                const float wv = P.w[n] * v[j];
+                const float *y = s_ylm + n * nm;
+#pragma unroll
+                for (int k = 1; k < kMaxMoments; ++k)
+                    if (k < nm) acc[k] = __builtin_fmaf(y[k], wv, acc[k]);
+            }
         }
     }
     float *out = P.mom + ((size_t)K * G + g) * nm * 8 + d;
@@ -129,19 +142,30 @@ __global__ __launch_bounds__(256) void k_moment_sources(const DevProblem *__rest
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;   // K * G + g
     if (t >= (long long)C * G) return;
     const int K = (int)(t / G);
-    const float *M = P.M + (size_t)K * 64;
+    float Mr[64];                        // the cell's mass matrix, loaded once
+    const float4 *M4 = reinterpret_cast<const float4 *>(P.M + (size_t)K * 64);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const float4 v = M4[i];
+        Mr[4 * i] = v.x; Mr[4 * i + 1] = v.y; Mr[4 * i + 2] = v.z; Mr[4 * i + 3] = v.w;
+    }
     for (int l = 1; l <= L; ++l) {
         const float sl = P.sigl[t * L + (l - 1)];
         for (int k = l * l; k < (l + 1) * (l + 1); ++k) {
-            const float *m = P.mom + ((size_t)t * nm + k) * 8;
-            float *r = P.rmom + ((size_t)t * nm + k) * 8;
+            const float4 *m4 = reinterpret_cast<const float4 *>(P.mom + ((size_t)t * nm + k) * 8);
+            const float4 ma = m4[0], mb = m4[1];
+            const float m[8] = {ma.x, ma.y, ma.z, ma.w, mb.x, mb.y, mb.z, mb.w};
+            float r[8];
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
                 float acc = 0.f;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) acc = __builtin_fmaf(M[d * 8 + j], m[j], acc);
+                for (int j = 0; j < 8; ++j) acc = __builtin_fmaf(Mr[d * 8 + j], m[j], acc);
                 r[d] = sl * acc;
             }
+            float4 *r4 = reinterpret_cast<float4 *>(P.rmom + ((size_t)t * nm + k) * 8);
+            r4[0] = make_float4(r[0], r[1], r[2], r[3]);
+            r4[1] = make_float4(r[4], r[5], r[6], r[7]);
         }
     }
 }
@@ -577,7 +601,9 @@ hipError_t launch_outer_source(const DevProblem *probs, int prob, int C, int G, 
 
 hipError_t launch_moments(const DevProblem *probs, int prob, int C, int G, const int *stop_flag, hipStream_t s) {
     const long long n = (long long)C * 8 * G;
-    hipLaunchKernelGGL(k_moments, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, probs, prob, stop_flag);
+    const size_t ylm_bytes = sizeof(float) * 8 * kMaxAnglesPerOctant * kMaxMoments;   // 32 KB at most
+    hipLaunchKernelGGL(k_moments, dim3((unsigned)((n + 255) / 256)), dim3(256), ylm_bytes, s, probs, prob,
+                       stop_flag);
     const long long m = (long long)C * G;
     hipLaunchKernelGGL(k_moment_sources, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, probs, prob, stop_flag);
     return hipGetLastError();

@@ -652,11 +652,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                         // Y_k(Omega_n) sigma_l M phi_lm on top of the isotropic source
                         const int nm = (P.L + 1) * (P.L + 1);
                         const float *y = P.ylm + (size_t)(o * A + n) * nm;
-                        const float *rm = P.rmom + ((size_t)K * G + g) * nm * 8;
-                        for (int k = 1; k < nm; ++k) {
-                            const float yk = y[k];
+                        const float4 *rm = reinterpret_cast<const float4 *>(P.rmom + ((size_t)K * G + g) * nm * 8);
+                        // four moments' loads in flight together
+                        for (int k0 = 1; k0 < nm; k0 += 4) {
+                            float yk[4];
+                            float4 ra[4], rb[4];
 #pragma unroll
-                            for (int d = 0; d < 8; ++d) b[d] = __builtin_fmaf(yk, rm[k * 8 + d], b[d]);
+                            for (int j = 0; j < 4; ++j) {
+                                const int k = k0 + j < nm ? k0 + j : k0;
+                                yk[j] = k0 + j < nm ? y[k] : 0.f;
+                                ra[j] = rm[2 * k];
+                                rb[j] = rm[2 * k + 1];
+                            }
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                b[0] = __builtin_fmaf(yk[j], ra[j].x, b[0]); b[1] = __builtin_fmaf(yk[j], ra[j].y, b[1]);
+                                b[2] = __builtin_fmaf(yk[j], ra[j].z, b[2]); b[3] = __builtin_fmaf(yk[j], ra[j].w, b[3]);
+                                b[4] = __builtin_fmaf(yk[j], rb[j].x, b[4]); b[5] = __builtin_fmaf(yk[j], rb[j].y, b[5]);
+                                b[6] = __builtin_fmaf(yk[j], rb[j].z, b[6]); b[7] = __builtin_fmaf(yk[j], rb[j].w, b[7]);
+                            }
                         }
                     }
                 const float psib = L.psib;
