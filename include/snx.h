@@ -145,7 +145,8 @@ snx_status snx_set_reflective(snx_problem *p, int32_t planes);
  * - snx_sweep takes the whole source from phi_in (one Jacobi step over groups);
  * - snx_solve is snx_solve_outer with one inner iteration;
  * - snx_balance counts the cross-group source;
- * - batches reject the problem (SNX_E_ARG at snx_batch_create).
+ * - in a batch, snx_batch_sweep does the same per problem, and
+ *   snx_batch_solve runs snx_batch_solve_outer with one inner iteration.
  * Errors: SNX_E_STATE before the materials, SNX_E_ARG for an index out of
  * range or a negative or non-finite entry. */
 snx_status snx_set_group_scattering(snx_problem *p, int32_t nmat, const int32_t *cell_mat, const double *sigma_gg);
@@ -318,6 +319,14 @@ snx_status snx_batch_set_sweep_mode(snx_batch *b, int32_t mode);
 snx_status snx_batch_set_schedule(snx_batch *b, int32_t threads, int32_t wg_per_cu, int32_t chunk);
 /* As snx_tune, over the whole batch. */
 snx_status snx_batch_tune(snx_batch *b, const char *cache_path, int32_t *chosen, void *stream);
+/* As snx_solve_outer, for every problem of the batch at once.  The inner
+ * iterations of all problems share each graph replay.  Each problem's outer
+ * change is measured on its own, and a problem whose change is <= tol (tol > 0)
+ * sits out the later outer iterations.  phi0 (nullable, or NULL entries) and
+ * phi are arrays of n device pointers.  infos[n] (nullable) is filled per
+ * problem.  Synchronous.  Returns SNX_E_NOCONV when any problem misses tol. */
+snx_status snx_batch_solve_outer(snx_batch *b, int32_t outer, int32_t inner, double tol, const float *const *phi0,
+                                 float *const *phi, snx_solve_info *infos, void *stream);
 /* One source iteration of every problem: host arrays of n device pointers
  * phi_in (nullable array, nullable entries = zero flux) and phi_out.
  * Synchronous. */

@@ -390,6 +390,10 @@ snx_status sched_sweep(Sched &sc, const float *const *phi_in, float *const *phi_
     if (st) return st;
     const int n = sc.nprob();
     HIPCHK_E(sc.err, launch_iter_init_batch(sc.d_ic, sc.d_stop, n, 1, 0.0, s), "init");
+    for (int i = 0; i < n; ++i)   // group-to-group matrices: one Jacobi step over groups
+        if (sc.hprobs[i].qo)
+            HIPCHK_E(sc.err, launch_outer_source(sc.d_probs, i, sc.hprobs[i].C, sc.hprobs[i].G, phi_in ? phi_in[i] : nullptr,
+                                                 s), "outer source");
     HIPCHK_E(sc.err, launch_source_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_user, nullptr, s), "source");
     st = enqueue_ang_sources(sc, nullptr, s);
     if (st) return st;
@@ -430,15 +434,21 @@ snx_status build_graph(Sched &sc, int parity) {
 // relative change is <= tol or max_it; graph replays of `chunk` iterations,
 // with converged problems retired from later sweeps.
 snx_status sched_solve(Sched &sc, double tol, int max_it, const float *const *phi0, float *const *phi,
-                       snx_solve_info *infos, hipStream_t s) {
+                       snx_solve_info *infos, hipStream_t s, const std::vector<int> *retired = nullptr) {
     const int n = sc.nprob();
     const auto t0 = std::chrono::steady_clock::now();
     snx_status st = upload_user(sc, phi0, nullptr, s);
     if (st) return st;
     HIPCHK_E(sc.err, launch_iter_init_batch(sc.d_ic, sc.d_stop, n, max_it, tol, s), "init");
+    if (retired) {   // problems left out of this solve (their phi is passed through unchanged)
+        std::vector<int> init(n);
+        for (int i = 0; i < n; ++i) init[i] = (*retired)[i] ? 3 : 0;
+        HIPCHK_E(sc.err, hipMemcpyAsync(sc.d_stop, init.data(), sizeof(int) * n, hipMemcpyHostToDevice, s), "copy");
+        HIPCHK_E(sc.err, hipStreamSynchronize(s), "copy");
+    }
     HIPCHK_E(sc.err, launch_copy_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_buf, sc.d_user, s), "copy");
-    HIPCHK_E(sc.err, launch_source_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_buf, nullptr, s), "source");
-    st = enqueue_ang_sources(sc, nullptr, s);
+    HIPCHK_E(sc.err, launch_source_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_buf, sc.d_stop, s), "source");
+    st = enqueue_ang_sources(sc, sc.d_stop, s);
     if (st) return st;
     char *pin = reinterpret_cast<char *>(sc.pinned);
     IterCtl *hic = reinterpret_cast<IterCtl *>(pin + 16 * (size_t)n);
@@ -1385,7 +1395,6 @@ snx_status snx_batch_create(snx_batch **out, int32_t n, snx_problem *const *prob
     for (snx_problem *p : v) {
         if (!p || !p->ready) { g_create_error = "every problem of a batch must be set up"; return SNX_E_STATE; }
         if (p->device != v[0]->device) { g_create_error = "the problems of a batch must share a device"; return SNX_E_ARG; }
-        if (p->nmat) { g_create_error = "batches take within-group scattering only (no group-to-group matrix)"; return SNX_E_ARG; }
     }
     snx_batch *b = new (std::nothrow) snx_batch();
     if (!b) { g_create_error = "out of host memory"; return SNX_E_OOM; }
@@ -1475,7 +1484,93 @@ snx_status snx_batch_solve(snx_batch *b, double tol, int32_t max_it, const float
     for (int i = 0; i < b->sched.nprob(); ++i)
         if (!phi[i]) return fail_msg(b->sched.err, SNX_E_ARG, "every phi must be non-NULL");
     if (hipSetDevice(b->device) != hipSuccess) return fail_msg(b->sched.err, SNX_E_DEVICE, "hipSetDevice failed");
+    for (const snx_problem *p : b->sched.probs)
+        if (p->nmat) return snx_batch_solve_outer(b, max_it, 1, tol, phi0, phi, infos, stream);
     return sched_solve(b->sched, tol, max_it, phi0, phi, infos, (hipStream_t)stream);
+}
+
+snx_status snx_batch_solve_outer(snx_batch *b, int32_t outer, int32_t inner, double tol, const float *const *phi0,
+                                 float *const *phi, snx_solve_info *infos, void *stream) {
+    if (!b) return SNX_E_ARG;
+    Sched &sc = b->sched;
+    if (!phi || outer < 1 || inner < 1 || !(tol >= 0.0)) return fail_msg(sc.err, SNX_E_ARG, "bad solve arguments");
+    const int n = sc.nprob();
+    for (int i = 0; i < n; ++i)
+        if (!phi[i]) return fail_msg(sc.err, SNX_E_ARG, "every phi must be non-NULL");
+    if (hipSetDevice(b->device) != hipSuccess) return fail_msg(sc.err, SNX_E_DEVICE, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    // each problem's outer iterates alternate between the caller's phi and its library buffer
+    std::vector<float *> bufs[2];
+    for (int i = 0; i < n; ++i) {
+        snx_problem *p = sc.probs[i];
+        const size_t cnt = (size_t)p->C * p->G * 8;
+        bufs[0].push_back(phi[i]);
+        bufs[1].push_back(p->d_outer);
+        if (phi0 && phi0[i] && phi0[i] != phi[i])
+            HIPCHK_E(sc.err, hipMemcpyAsync(phi[i], phi0[i], sizeof(float) * cnt, hipMemcpyDeviceToDevice, s), "copy");
+        else if (!phi0 || !phi0[i])
+            HIPCHK_E(sc.err, launch_fill_f32(phi[i], cnt, 0.f, s), "fill");
+    }
+    std::vector<int> retired(n, 0), total(n, 0);
+    std::vector<double> eps(n, INFINITY);
+    int cur = 0;
+    for (int k = 0; k < outer; ++k) {
+        for (int i = 0; i < n; ++i)
+            if (!retired[i] && sc.hprobs[i].qo)
+                HIPCHK_E(sc.err, launch_outer_source(sc.d_probs, i, sc.hprobs[i].C, sc.hprobs[i].G, bufs[cur][i], s),
+                         "outer source");
+        snx_status st = sched_solve(sc, 0.0, inner, bufs[cur].data(), bufs[cur ^ 1].data(), nullptr, s, &retired);
+        if (st && st != SNX_E_NOCONV) return st;
+        for (int i = 0; i < n; ++i) {
+            if (retired[i]) continue;
+            snx_problem *p = sc.probs[i];
+            total[i] += inner;
+            HIPCHK_E(sc.err, hipMemsetAsync(p->d_change, 0, sizeof(unsigned long long) * 2, s), "memset");
+            HIPCHK_E(sc.err, launch_max_change(bufs[cur ^ 1][i], bufs[cur][i], (long long)p->C * p->G * 8, p->d_change,
+                                               s), "change");
+        }
+        std::vector<unsigned long long> bits(2 * (size_t)n, 0ull);
+        for (int i = 0; i < n; ++i)
+            if (!retired[i])
+                HIPCHK_E(sc.err, hipMemcpyAsync(&bits[2 * i], sc.probs[i]->d_change, sizeof(unsigned long long) * 2,
+                                                hipMemcpyDeviceToHost, s), "copy");
+        HIPCHK_E(sc.err, hipStreamSynchronize(s), "solve");
+        cur ^= 1;
+        bool all = true;
+        for (int i = 0; i < n; ++i) {
+            if (retired[i]) continue;
+            double num, den;
+            std::memcpy(&num, &bits[2 * i], sizeof(double));
+            std::memcpy(&den, &bits[2 * i + 1], sizeof(double));
+            eps[i] = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
+            // a retired problem's later solves pass its iterate through, so both of
+            // its buffers end up holding it
+            if (tol > 0.0 && eps[i] <= tol) retired[i] = 1;
+            all = all && retired[i];
+        }
+        if (all) break;
+    }
+    for (int i = 0; i < n; ++i)
+        if (bufs[cur][i] != phi[i])
+            HIPCHK_E(sc.err, hipMemcpyAsync(phi[i], bufs[cur][i], sizeof(float) * sc.probs[i]->C * sc.probs[i]->G * 8,
+                                            hipMemcpyDeviceToDevice, s), "copy");
+    HIPCHK_E(sc.err, hipStreamSynchronize(s), "solve");
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    bool conv = true;
+    for (int i = 0; i < n; ++i) {
+        const bool ok = tol == 0.0 || eps[i] <= tol;
+        conv = conv && ok;
+        if (infos) {
+            const snx_problem *p = sc.probs[i];
+            infos[i].iterations = total[i];
+            infos[i].status = ok ? SNX_OK : SNX_E_NOCONV;
+            infos[i].residual = eps[i];
+            infos[i].wall_ms = ms;
+            infos[i].solves_per_s = ms > 0 ? (double)total[i] * p->C * p->nang * p->G / (ms * 1e-3) : 0.0;
+        }
+    }
+    return conv ? SNX_OK : fail_msg(sc.err, SNX_E_NOCONV, "outer iterations ended before the tolerance");
 }
 
 snx_status snx_batch_profile_sweep(snx_batch *b, int32_t nsweeps, double *ms, void *stream) {

@@ -33,7 +33,7 @@ EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_s
            "snx_gnn_train_step", "snx_gnn_predict", "snx_set_sweep_mode", "snx_batch_set_sweep_mode",
            "snx_get_psi", "snx_set_sweep_stats", "snx_batch_set_sweep_stats", "snx_set_designation",
            "snx_designation_stats", "snx_set_group_scattering", "snx_solve_outer", "snx_set_reflective",
-           "snx_set_anisotropy", "snx_get_schedule"]
+           "snx_set_anisotropy", "snx_get_schedule", "snx_batch_solve_outer"]
 _NO_STATUS = ("snx_destroy", "snx_last_error", "snx_batch_destroy", "snx_batch_last_error", "snx_gnn_destroy",
               "snx_gnn_last_error")
 
@@ -86,6 +86,7 @@ def load(path: str = LIB_PATH):
     L.snx_set_designation.argtypes = [_vp, ct.c_int32]
     L.snx_set_reflective.argtypes = [_vp, ct.c_int32]
     L.snx_get_schedule.argtypes = [_vp, _vp]
+    L.snx_batch_solve_outer.argtypes = [_vp, ct.c_int32, ct.c_int32, ct.c_double, _vp, _vp, _vp, _vp]
     L.snx_set_anisotropy.argtypes = [_vp, ct.c_int32, _vp]
     L.snx_set_group_scattering.argtypes = [_vp, ct.c_int32, _vp, _vp]
     L.snx_solve_outer.argtypes = [_vp, ct.c_int32, ct.c_int32, ct.c_double, _vp, _vp, ct.POINTER(SolveInfo), _vp]
@@ -445,6 +446,19 @@ class Batch:
         p0 = None if phi0 is None else _ptr_array(phi0)
         rc = load().snx_batch_solve(self.h, tol, max_it, p0, _ptr_array(phi), infos, _stream(stream))
         self._check(rc, "batch_solve", allow=(SNX_E_NOCONV,) if allow_noconv else ())
+        return phi, [{"iterations": i.iterations, "status": i.status, "residual": i.residual,
+                      "wall_ms": i.wall_ms, "solves_per_s": i.solves_per_s} for i in infos], rc
+
+    def solve_outer(self, outer: int, inner: int, tol: float = 0.0, phi0=None, phi=None, stream=None,
+                    allow_noconv=False):
+        """Inner/outer iterations of every problem (snx_batch_solve_outer)."""
+        if phi is None:
+            phi = [p.empty_phi() for p in self.problems]
+        infos = (SolveInfo * len(self.problems))()
+        p0 = None if phi0 is None else _ptr_array(phi0)
+        rc = load().snx_batch_solve_outer(self.h, int(outer), int(inner), float(tol), p0, _ptr_array(phi), infos,
+                                          _stream(stream))
+        self._check(rc, "batch_solve_outer", allow=(SNX_E_NOCONV,) if allow_noconv else ())
         return phi, [{"iterations": i.iterations, "status": i.status, "residual": i.residual,
                       "wall_ms": i.wall_ms, "solves_per_s": i.solves_per_s} for i in infos], rc
 

@@ -117,12 +117,49 @@ def test_converged_outer_iteration_and_plain_solve():
     p.close()
 
 
-def test_batch_rejects_a_group_matrix():
+def test_batch_with_group_matrices():
+    """Two coupled problems and a plain one in one batch: a sweep with the
+    coupled sources, five outer x five inner iterations, and a converged outer
+    solve in which each problem retires on its own tolerance."""
+    torch = _torch()
     from paper_2510_11513_amd import snx
-    prob = _problem(3, 3, 1, 1, seed=7)
-    p, _, _ = _pair(prob)
-    q = snx.Problem.from_problem(_problem(3, 3, 1, 1, seed=8))
-    with pytest.raises(snx.SnxError):
-        snx.Batch([p, q])
-    p.close()
-    q.close()
+    c = (0.2, 0.7)      # a change of 1e-6 then bounds the error by a few 1e-6 (FP32 iterates)
+    probs = [_problem(4, 5, 2, 2, seed=70, c=c), _problem(3, 3, 1, 2, seed=71, kind=1, c=c),
+             _problem(4, 4, 2, 2, seed=72, c=c)]
+    coupled = [True, True, False]
+    gp, ors = [], []
+    for pr, cpl in zip(probs, coupled):
+        q = snx.Problem.from_problem(pr, setup=False)
+        o = oracle.Oracle.from_problem(pr, setup=False)
+        if cpl:
+            cm, sgg = inputs.split_scattering(pr.mat, 0.4)
+            q.set_group_scattering(cm, sgg)
+            o.set_group_scattering(cm, sgg)
+        q.setup()
+        o.setup()
+        gp.append(q)
+        ors.append(o)
+    batch = snx.Batch(gp)
+    phis = [_phi_in(pr, 80 + i) for i, pr in enumerate(probs)]
+    outs = batch.sweep([torch.from_numpy(x).cuda() for x in phis])
+    torch.cuda.synchronize()
+    for i, o in enumerate(ors):
+        err = H.rel_err_per_group(outs[i].cpu().numpy().astype(np.float64), o.sweep(phis[i].astype(np.float64))["phi"])
+        assert err.max() <= TOL, ("sweep", i, err)
+    res, infos, _ = batch.solve_outer(5, 5, 0.0)
+    for i, o in enumerate(ors):
+        ref = o.solve_outer(5, 5, 0.0)
+        err = H.rel_err_per_group(res[i].cpu().numpy().astype(np.float64), ref["phi"])
+        print(f"[case] batch 5x5 problem {i}: rel err {err.max():.2e}", flush=True)
+        assert infos[i]["iterations"] == 25 and err.max() <= TOL, (i, err)
+    res, infos, rc = batch.solve_outer(300, 3, 1e-6)
+    assert rc == 0, infos
+    for i, o in enumerate(ors):
+        ref = o.solve_outer(600, 3, 1e-12)
+        err = H.rel_err_per_group(res[i].cpu().numpy().astype(np.float64), ref["phi"])
+        print(f"[case] batch converged problem {i}: {infos[i]['iterations']} inner iterations, rel err {err.max():.2e}",
+              flush=True)
+        assert infos[i]["status"] == 0 and err.max() <= TOL, (i, err)
+    batch.close()
+    for q in gp:
+        q.close()
