@@ -4,9 +4,11 @@ bulk-synchronous one, over a range of angles per octant and energy groups).
 
     python -m paper_2510_11513_amd.compare_bsp [--n 16] [--sweeps 10]
 
-Both schemes run the same task code in the library's default schedule for the
-problem; each time is the sweep kernel alone (HIP events over `sweeps`
-sweeps, after one untimed sweep).  Prints a table and one JSON line.
+Both schemes run the same task code.  Each is timed at its best schedule of
+a small search (AMT: threads 64, 128, 256 x workgroups per CU at occupancy or
+2; BSP: threads 64, 128, 256); a time is the sweep kernel alone (HIP events
+over `sweeps` sweeps, after one untimed sweep).  Prints a table and one JSON
+line.
 """
 from __future__ import annotations
 
@@ -39,18 +41,28 @@ def run(n: int, sweeps: int):
             p = snx.Problem.from_problem(prob)
             phi = p.sweep(None)
             torch.cuda.synchronize()
-            ms_amt = p.profile_sweep(sweeps, phi_in=phi)
-            p.set_sweep_mode(snx.SWEEP_BSP)
-            ms_bsp = p.profile_sweep(sweeps, phi_in=phi)
-            st = p.sweep_stats()
+            best = {snx.SWEEP_AMT: (1e300, None), snx.SWEEP_BSP: (1e300, None)}
+            for mode, wgs in ((snx.SWEEP_AMT, (64, 2)), (snx.SWEEP_BSP, (64,))):
+                p.set_sweep_mode(mode)
+                for th in (64, 128, 256):
+                    if th < G:
+                        continue
+                    for wg in wgs:      # 64: capped by occupancy
+                        p.set_schedule(threads=th, wg_per_cu=wg)
+                        p.sweep(phi)
+                        ms = p.profile_sweep(sweeps, phi_in=phi)
+                        if ms < best[mode][0]:
+                            best[mode] = (ms, (th, wg))
             p.close()
+            ms_amt, sched_amt = best[snx.SWEEP_AMT]
+            ms_bsp, sched_bsp = best[snx.SWEEP_BSP]
             solves = mesh.ncell * prob.nang * G
-            rows.append({"angles_per_octant": npol * naz, "groups": G, "threads": st["threads"],
-                         "amt_ms": round(ms_amt, 4), "bsp_ms": round(ms_bsp, 4),
+            rows.append({"angles_per_octant": npol * naz, "groups": G, "amt_schedule": sched_amt,
+                         "bsp_threads": sched_bsp[0], "amt_ms": round(ms_amt, 4), "bsp_ms": round(ms_bsp, 4),
                          "speedup_amt_over_bsp": round(ms_bsp / ms_amt, 3),
                          "amt_solves_per_s": solves / (ms_amt * 1e-3)})
-            print(f"angles/octant {npol * naz:3d} groups {G:3d} threads {st['threads']:4d}: "
-                  f"AMT {ms_amt:8.3f} ms  BSP {ms_bsp:8.3f} ms  speedup {ms_bsp / ms_amt:5.2f}", flush=True)
+            print(f"angles/octant {npol * naz:3d} groups {G:3d}: AMT {ms_amt:8.3f} ms {sched_amt}  "
+                  f"BSP {ms_bsp:8.3f} ms (threads {sched_bsp[0]})  speedup {ms_bsp / ms_amt:5.2f}", flush=True)
     return rows
 
 
