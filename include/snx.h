@@ -143,10 +143,11 @@ snx_status snx_set_reflective(snx_problem *p, int32_t planes);
  * replaces the sigma_s of snx_set_materials, and the source of group g becomes
  * Q_g + sum over g' of sigma(g' -> g) phi_g'.  Under a matrix:
  * - snx_sweep takes the whole source from phi_in (one Jacobi step over groups);
- * - snx_solve is snx_solve_outer with one inner iteration;
+ * - snx_solve renews the whole source from every sweep's flux: its iterates
+ *   are those of snx_solve_outer with one inner iteration, all of them inside
+ *   the solve's graph replays, stopped by snx_solve's own convergence test;
  * - snx_balance counts the cross-group source;
- * - in a batch, snx_batch_sweep does the same per problem, and
- *   snx_batch_solve runs snx_batch_solve_outer with one inner iteration.
+ * - in a batch, snx_batch_sweep and snx_batch_solve do the same per problem.
  * Errors: SNX_E_STATE before the materials, SNX_E_ARG for an index out of
  * range or a negative or non-finite entry. */
 snx_status snx_set_group_scattering(snx_problem *p, int32_t nmat, const int32_t *cell_mat, const double *sigma_gg);

@@ -75,6 +75,8 @@ struct Sched {
     int threads = 256, wg_per_cu = 0, grid = 0, chunk = 8;
     int mode = SNX_SWEEP_AMT;                // SNX_SWEEP_AMT or SNX_SWEEP_BSP
     bool phase_stats = false;                // gather the per-phase cycle statistics (snx_set_sweep_stats)
+    bool fixed_outer = false;                // group-to-group matrices: keep the cross-group source fixed
+                                             // (inner iterations of an outer one); else renew it every iteration
     long long *d_bsp_tasks = nullptr;        // tasks of every problem ordered by level (BSP comparator)
     std::vector<long long> bsp_off;          // [levels + 1] offsets into d_bsp_tasks
     unsigned long long watchdog = 0;
@@ -358,6 +360,26 @@ snx_status enqueue_sweep(Sched &sc, const int *stops, hipStream_t s, hipEvent_t 
     return SNX_OK;
 }
 
+// Inner iterations of outer ones, for the lifetime of the object: the graph
+// chunk is the inner count and the cross-group source stays fixed; both are
+// restored after (graphs are rebuilt when either changes).
+struct OuterScope {
+    Sched &sc;
+    int saved;
+    OuterScope(Sched &s, int chunk) : sc(s), saved(s.chunk) {
+        if (chunk != saved || !sc.fixed_outer) {
+            sc.chunk = chunk;
+            sc.fixed_outer = true;
+            sc.drop_graphs();
+        }
+    }
+    ~OuterScope() {
+        sc.chunk = saved;
+        sc.fixed_outer = false;
+        sc.drop_graphs();
+    }
+};
+
 // Anisotropic problems of the schedule: flux moments of their last sweep's psi
 // and the moments' source dofs; stops (device, nullable) retires problems.  The
 // isotropic source comes from the source update as before.
@@ -418,6 +440,17 @@ snx_status build_graph(Sched &sc, int parity) {
                                                sc.d_buf + cur * n, 1, sc.d_ic, sc.d_stop, cs);
             if (e != hipSuccess) st = hip_fail_msg(sc.err, e, "reduce launch");
             if (!st) st = enqueue_ang_sources(sc, sc.d_stop, cs);   // anisotropic: moments of this sweep
+            for (int k = 0; k < n && !st && !sc.fixed_outer; ++k) {
+                // group-to-group matrices: the next sweep's cross-group source from the new
+                // flux, then its source dofs again (the reduction used the previous one)
+                const DevProblem &P = sc.hprobs[k];
+                if (!P.qo) continue;
+                hipError_t e2 = launch_outer_source(sc.d_probs, k, P.C, P.G, sc.probs[k]->d_phi[cur ^ 1], cs,
+                                                    sc.d_stop + k);
+                if (e2 == hipSuccess) e2 = launch_source(sc.d_probs, k, P.C, P.G, sc.probs[k]->d_phi[cur ^ 1],
+                                                         sc.d_stop + k, cs);
+                if (e2 != hipSuccess) st = hip_fail_msg(sc.err, e2, "outer source launch");
+            }
         }
     }
     hipGraph_t g = nullptr;
@@ -447,6 +480,11 @@ snx_status sched_solve(Sched &sc, double tol, int max_it, const float *const *ph
         HIPCHK_E(sc.err, hipStreamSynchronize(s), "copy");
     }
     HIPCHK_E(sc.err, launch_copy_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_buf, sc.d_user, s), "copy");
+    if (!sc.fixed_outer)   // group-to-group matrices: the whole source from the start flux (Jacobi over groups)
+        for (int i = 0; i < n; ++i)
+            if (sc.hprobs[i].qo)
+                HIPCHK_E(sc.err, launch_outer_source(sc.d_probs, i, sc.hprobs[i].C, sc.hprobs[i].G,
+                                                     sc.probs[i]->d_phi[0], s, sc.d_stop + i), "outer source");
     HIPCHK_E(sc.err, launch_source_batch(sc.d_probs, n, sc.d_blk_base, sc.nblk, sc.d_buf, sc.d_stop, s), "source");
     st = enqueue_ang_sources(sc, sc.d_stop, s);
     if (st) return st;
@@ -1156,7 +1194,6 @@ snx_status snx_solve(snx_problem *p, double tol, int32_t max_it, const float *ph
     if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
     if (!phi || max_it < 1 || !(tol >= 0.0)) return fail(p, SNX_E_ARG, "bad solve arguments");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
-    if (p->nmat) return snx_solve_outer(p, max_it, 1, tol, phi0, phi, info, stream);
     const float *in[1] = {phi0};
     float *out[1] = {phi};
     snx_status st = sched_solve(p->sched, tol, max_it, in, out, info, (hipStream_t)stream);
@@ -1183,6 +1220,7 @@ snx_status snx_solve_outer(snx_problem *p, int32_t outer, int32_t inner, double 
     else if (!phi0)
         HIPCHK(p, launch_fill_f32(bufs[0], n, 0.f, s), "fill");
     unsigned long long *hch = reinterpret_cast<unsigned long long *>(p->pinned);
+    OuterScope outer_scope(p->sched, inner);   // replays of exactly the inner iterations, fixed cross-group source
     int k = 0, total = 0;
     double eps = INFINITY;
     while (k < outer) {
@@ -1484,8 +1522,6 @@ snx_status snx_batch_solve(snx_batch *b, double tol, int32_t max_it, const float
     for (int i = 0; i < b->sched.nprob(); ++i)
         if (!phi[i]) return fail_msg(b->sched.err, SNX_E_ARG, "every phi must be non-NULL");
     if (hipSetDevice(b->device) != hipSuccess) return fail_msg(b->sched.err, SNX_E_DEVICE, "hipSetDevice failed");
-    for (const snx_problem *p : b->sched.probs)
-        if (p->nmat) return snx_batch_solve_outer(b, max_it, 1, tol, phi0, phi, infos, stream);
     return sched_solve(b->sched, tol, max_it, phi0, phi, infos, (hipStream_t)stream);
 }
 
@@ -1514,6 +1550,7 @@ snx_status snx_batch_solve_outer(snx_batch *b, int32_t outer, int32_t inner, dou
     }
     std::vector<int> retired(n, 0), total(n, 0);
     std::vector<double> eps(n, INFINITY);
+    OuterScope outer_scope(sc, inner);          // replays of exactly the inner iterations, fixed cross-group source
     int cur = 0;
     for (int k = 0; k < outer; ++k) {
         for (int i = 0; i < n; ++i)

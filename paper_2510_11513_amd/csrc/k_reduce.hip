@@ -59,7 +59,9 @@ __global__ void k_source(const DevProblem *__restrict__ probs, int prob, const f
 // Cross-group scattering source of an outer iteration from a given phi (NULL =
 // zero): qo_K,g = sum over g' != g of sigma(g' -> g) phi_K,g' at each node, in
 // increasing g'.  One thread per (cell, group).
-__global__ void k_outer_source(const DevProblem *__restrict__ probs, int prob, const float *__restrict__ phi) {
+__global__ void k_outer_source(const DevProblem *__restrict__ probs, int prob, const float *__restrict__ phi,
+                               const int *__restrict__ stop_flag) {
+    if (stop_flag && *stop_flag) return;
     const DevProblem &P = probs[prob];
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)P.C * P.G) return;
@@ -593,9 +595,11 @@ hipError_t launch_integrated_flux(const float *M, const float *phi, int C, int G
     return hipGetLastError();
 }
 
-hipError_t launch_outer_source(const DevProblem *probs, int prob, int C, int G, const float *phi, hipStream_t s) {
+hipError_t launch_outer_source(const DevProblem *probs, int prob, int C, int G, const float *phi, hipStream_t s,
+                               const int *stop_flag) {
     const long long n = (long long)C * G;
-    hipLaunchKernelGGL(k_outer_source, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, probs, prob, phi);
+    hipLaunchKernelGGL(k_outer_source, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, probs, prob, phi,
+                       stop_flag);
     return hipGetLastError();
 }
 

@@ -178,7 +178,8 @@ hipError_t launch_integrated_flux(const float *M, const float *phi, int C, int G
 size_t partial_blocks(int C, int G);
 hipError_t launch_fill_f32(float *p, size_t n, float v, hipStream_t s);
 // P.qo of problem `prob` from phi (NULL = zero): sum over g' != g of sigma(g' -> g) phi_g'.
-hipError_t launch_outer_source(const DevProblem *probs, int prob, int C, int G, const float *phi, hipStream_t s);
+hipError_t launch_outer_source(const DevProblem *probs, int prob, int C, int G, const float *phi, hipStream_t s,
+                               const int *stop_flag = nullptr);
 // out[0] |= max |a - b|, out[1] |= max |a| as FP64 bit patterns (out zeroed by the caller).
 // Anisotropic scattering: flux moments of degree >= 1 from P.psi (P.mom), then
 // their source dofs sigma_l M phi_lm (P.rmom), which the sweep weighs by each
