@@ -163,3 +163,58 @@ def test_batch_with_group_matrices():
     batch.close()
     for q in gp:
         q.close()
+
+
+def test_plain_solve_iterates_across_graph_replays():
+    """snx_solve renews the cross-group source after every sweep inside its
+    graph replays: a fixed number of iterations that crosses replay boundaries
+    equals the oracle's source iteration iterate for iterate, before and after
+    an outer solve (which keeps the source fixed within its inner iterations),
+    for one problem and for a batch with a plain problem beside the coupled
+    one."""
+    torch = _torch()
+    from paper_2510_11513_amd import snx
+    prob = _problem(4, 5, 2, 2, seed=90, kind=1)
+    p, o, _ = _pair(prob, within=0.4)
+    phi0 = _phi_in(prob, 91)
+    for k in (1, 11):
+        for when in ("before", "after"):
+            if when == "after":
+                p.solve_outer(2, 3, 0.0)
+            phi, info = p.solve(0.0, k, phi0=torch.from_numpy(phi0).cuda(), allow_noconv=True)
+            assert info["iterations"] == k, info
+            ref = o.solve(0.0, k, phi0=phi0.astype(np.float64), allow_noconv=True)
+            err = H.rel_err_per_group(phi.cpu().numpy().astype(np.float64), ref["phi"])
+            print(f"[case] plain coupled solve, {k} iterations, {when} an outer solve: rel err {err.max():.2e}",
+                  flush=True)
+            assert err.max() <= TOL, (k, when, err)
+    # the oracle's plain source iteration is one inner iteration per outer
+    a = o.solve(0.0, 11, phi0=phi0.astype(np.float64), allow_noconv=True)["phi"]
+    b = o.solve_outer(11, 1, 0.0, phi0=phi0.astype(np.float64), allow_noconv=True)["phi"]
+    assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+    p.close()
+
+    probs = [_problem(4, 5, 2, 2, seed=92), _problem(3, 4, 1, 2, seed=93)]
+    gp, ors = [], []
+    for i, pr in enumerate(probs):
+        q = snx.Problem.from_problem(pr, setup=False)
+        r = oracle.Oracle.from_problem(pr, setup=False)
+        if i == 0:
+            cm, sgg = inputs.split_scattering(pr.mat, 0.4)
+            q.set_group_scattering(cm, sgg)
+            r.set_group_scattering(cm, sgg)
+        q.setup()
+        r.setup()
+        gp.append(q)
+        ors.append(r)
+    batch = snx.Batch(gp)
+    phis = [_phi_in(pr, 94 + i) for i, pr in enumerate(probs)]
+    res, infos, _ = batch.solve(0.0, 11, phi0=[torch.from_numpy(x).cuda() for x in phis], allow_noconv=True)
+    for i, r in enumerate(ors):
+        ref = r.solve(0.0, 11, phi0=phis[i].astype(np.float64), allow_noconv=True)
+        err = H.rel_err_per_group(res[i].cpu().numpy().astype(np.float64), ref["phi"])
+        print(f"[case] batch plain solve problem {i}: rel err {err.max():.2e}", flush=True)
+        assert infos[i]["iterations"] == 11 and err.max() <= TOL, (i, err)
+    batch.close()
+    for q in gp:
+        q.close()
