@@ -122,6 +122,30 @@ def make_mesh(n: int, jitter: float = 0.2, seed: int = 0, permute: bool = True,
                 ijk=np.ascontiguousarray(cijk[cperm]), vert_ijk=np.ascontiguousarray(vert_ijk[vperm]))
 
 
+def rotate_cells(mesh: Mesh, rng: np.random.Generator) -> Mesh:
+    """The same mesh with each cell's local vertex order turned by a random
+    rotation of the reference cube (one of the 24 with determinant +1), so
+    that neighbouring cells see a shared face in every relative orientation.
+    Local vertex v' of the new order is the old vertex at R applied to v''s
+    reference corner; the Jacobian keeps its sign."""
+    rots = []
+    for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        for signs in range(8):
+            R = np.zeros((3, 3))
+            for d in range(3):
+                R[d, perm[d]] = -1.0 if (signs >> d) & 1 else 1.0
+            if np.linalg.det(R) > 0:
+                rots.append(R)
+    corner = np.array([[2 * ((v >> d) & 1) - 1 for d in range(3)] for v in range(8)], np.float64)
+    of_corner = {tuple(c): v for v, c in enumerate(corner.astype(int))}
+    cv = mesh.cell_vert.copy()
+    for K in range(mesh.ncell):
+        R = rots[rng.integers(len(rots))]
+        old = mesh.cell_vert[K]
+        cv[K] = [old[of_corner[tuple((R @ corner[v]).astype(int))]] for v in range(8)]
+    return Mesh(n=mesh.n, xyz=mesh.xyz, cell_vert=np.ascontiguousarray(cv), ijk=mesh.ijk, vert_ijk=mesh.vert_ijk)
+
+
 def block_index(mesh: Mesh, block: int) -> np.ndarray:
     """Index of the block^3 block each cell lies in (ragged blocks at the far edges)."""
     nb = (mesh.n + block - 1) // block
