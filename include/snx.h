@@ -152,6 +152,25 @@ snx_status snx_set_reflective(snx_problem *p, int32_t planes);
  * range or a negative or non-finite entry. */
 snx_status snx_set_group_scattering(snx_problem *p, int32_t nmat, const int32_t *cell_mat, const double *sigma_gg);
 
+/* Element order, used by the next snx_setup (a change undoes any earlier
+ * setup): 1 (default), 2 or 3.  The paper's benchmarks run first-, second- and
+ * third-order elements (Section 3.6 and its table of run times).  Order p is
+ * the Lagrange element of degree p in each reference coordinate on the
+ * trilinear hexahedron, with N = (p+1)^3 nodes at the Gauss-Lobatto-Legendre
+ * points (local node j = a + (p+1) b + (p+1)^2 c along the reference axes) and
+ * integrals by the (p+1)-point Gauss rule per direction; order 1 is the
+ * element of the rest of this header.  At order p > 1 every flux array of
+ * snx_sweep, snx_solve and snx_profile_sweep holds [ncell][G][N] floats in
+ * that node order, the sweep runs level by level over the octant DAGs (one
+ * launch per level), and these are refused with SNX_E_ARG: per-angle
+ * designation, reflective planes, anisotropic and group-to-group scattering
+ * (at snx_setup), snx_solve_outer, snx_balance, snx_integrated_flux,
+ * snx_get_psi, snx_tune, batches and the learned initial guess.
+ * Errors: SNX_E_ARG for an order outside 1..3. */
+snx_status snx_set_order(snx_problem *p, int32_t order);
+/* The order and the nodes per cell, N = (order+1)^3 (either pointer may be NULL). */
+snx_status snx_get_order(snx_problem *p, int32_t *order, int32_t *nodes);
+
 /* Upwind designation, used by the next snx_setup (a change undoes any earlier
  * setup).
  * SNX_DESIGNATION_OCTANT (default): face f of cell K is inflow for every

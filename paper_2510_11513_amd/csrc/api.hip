@@ -119,6 +119,7 @@ struct snx_problem {
     int nmat = 0;                       // group-to-group scattering (snx_set_group_scattering), 0 = none
     std::vector<int> cmat;              // [C]
     std::vector<double> sgg;            // [nmat][G][G], from g' into g
+    int order = 1;                      // element order (snx_set_order): 1, 2 or 3
 
     // set-up results
     bool ready = false;
@@ -141,6 +142,14 @@ struct snx_problem {
     int nq = 1;                         // task queues = XCDs seen on the device
     int xcc_queue[kMaxXcc] = {0};       // home queue of each hardware XCC id
     Sched sched;                        // the problem's own schedule of one
+    // higher-order elements (order > 1): their matrices, fluxes and level lists
+    struct Ho {
+        float *M = nullptr, *S = nullptr, *F = nullptr, *R = nullptr, *psi = nullptr;
+        float *phi[2] = {nullptr, nullptr};
+        int *perm = nullptr, *tasks = nullptr;
+        std::vector<int> off;           // [levels + 1] offsets into tasks (all octants, by level)
+        HoDev dev{};
+    } ho;
 };
 
 struct snx_batch {
@@ -178,6 +187,79 @@ void drop_device(snx_problem *p) {
     p->mem.release();
     p->ready = false;
     p->hp = DevProblem{};
+    p->ho = snx_problem::Ho{};
+}
+
+// ------------------------------------------------------- higher-order elements
+
+int ho_nodes(const snx_problem *p) { return (p->order + 1) * (p->order + 1) * (p->order + 1); }
+
+// Node map of each shared face at order P: for my face node at position
+// i + m j (i along the face's first free axis u, j along the second v) the
+// neighbour's local node.  The shared face's corners fix it: byte l of perm is
+// the neighbour's local vertex at my face corner l = bu + 2 bv, so each of the
+// neighbour's free axes follows one of mine, possibly reversed, and the nodes,
+// symmetric about 0 on each axis, follow with it.
+snx_status ho_node_maps(snx_problem *p, int P, const std::vector<int> &nbr, const std::vector<int> &nbrf,
+                        const std::vector<unsigned> &perm, std::vector<int> &out) {
+    const int m = P + 1, NF = m * m;
+    out.assign((size_t)p->C * 6 * NF, -1);
+    auto axes = [](int f, int &u, int &v) {
+        const int a = f >> 1;
+        u = a == 0 ? 1 : 0;
+        v = a == 2 ? 1 : 2;
+    };
+    for (int K = 0; K < p->C; ++K)
+        for (int f = 0; f < 6; ++f) {
+            const int N = nbr[6 * (size_t)K + f], g = nbrf[6 * (size_t)K + f];
+            if (N < 0) continue;
+            int u, v, u2, v2;
+            axes(f, u, v);
+            axes(g, u2, v2);
+            int cu[4], cw[4];   // the neighbour's corner bits along u2 and v2 at my corner l
+            for (int l = 0; l < 4; ++l) {
+                const int w = (int)((perm[6 * (size_t)K + f] >> (8 * l)) & 0xffu);
+                if (((w >> (g >> 1)) & 1) != (g & 1)) return fail(p, SNX_E_MESH, "neighbour vertex off the shared face");
+                cu[l] = (w >> u2) & 1;
+                cw[l] = (w >> v2) & 1;
+            }
+            const bool u_follows_u = cu[1] != cu[0];
+            for (int l = 0; l < 4; ++l) {   // the map is one of the square's eight symmetries
+                const int bu = l & 1, bv = l >> 1;
+                const int eu = cu[0] ^ (u_follows_u ? bu : bv), ev = cw[0] ^ (u_follows_u ? bv : bu);
+                if (eu != cu[l] || ev != cw[l]) return fail(p, SNX_E_MESH, "shared face corners do not match");
+            }
+            (void)u;
+            (void)v;
+            for (int j = 0; j < m; ++j)
+                for (int i = 0; i < m; ++i) {
+                    const int a = u_follows_u ? i : j, b = u_follows_u ? j : i;
+                    int idx[3];
+                    idx[g >> 1] = (g & 1) * P;
+                    idx[u2] = cu[0] ? P - a : a;
+                    idx[v2] = cw[0] ? P - b : b;
+                    out[((size_t)K * 6 + f) * NF + i + m * j] = idx[0] + m * idx[1] + m * m * idx[2];
+                }
+        }
+    return SNX_OK;
+}
+
+// Reference tables of the order-P element: Gauss-Lobatto-Legendre nodes and
+// the (P+1)-point Gauss-Legendre rule (closed forms).
+HoRef ho_reference(int P) {
+    HoRef r{};
+    if (P == 2) {
+        const double a = std::sqrt(0.6);
+        const double node[3] = {-1.0, 0.0, 1.0}, gx[3] = {-a, 0.0, a}, gw[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+        for (int i = 0; i < 3; ++i) { r.node[i] = node[i]; r.gx[i] = gx[i]; r.gw[i] = gw[i]; }
+    } else {
+        const double s5 = std::sqrt(0.2), t = 2.0 / 7.0 * std::sqrt(1.2);
+        const double x1 = std::sqrt(3.0 / 7.0 - t), x2 = std::sqrt(3.0 / 7.0 + t);
+        const double w1 = (18.0 + std::sqrt(30.0)) / 36.0, w2 = (18.0 - std::sqrt(30.0)) / 36.0;
+        const double node[4] = {-1.0, -s5, s5, 1.0}, gx[4] = {-x2, -x1, x1, x2}, gw[4] = {w2, w1, w1, w2};
+        for (int i = 0; i < 4; ++i) { r.node[i] = node[i]; r.gx[i] = gx[i]; r.gw[i] = gw[i]; }
+    }
+    return r;
 }
 
 // Workgroup width: the requested one if valid and at least G, else the
@@ -888,6 +970,9 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     if (!p) return SNX_E_ARG;
     if (!p->have_mesh || !p->have_quad || !p->have_mat) return fail(p, SNX_E_STATE, "mesh, quadrature and materials must be set");
     if (p->bkind == 1 && (int)p->psib.size() != p->G) return fail(p, SNX_E_STATE, "boundary inflow size differs from G");
+    if (p->order > 1 && (p->designation != SNX_DESIGNATION_OCTANT || p->refl || p->L || p->nmat))
+        return fail(p, SNX_E_ARG, "per-angle designation, reflective planes, anisotropic and group-to-group "
+                                  "scattering are not available at order > 1");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     drop_device(p);
@@ -1162,6 +1247,51 @@ snx_status snx_setup(snx_problem *p, void *stream) {
         drop_device(p);
         return fail(p, st, msg);
     }
+    if (p->order > 1) {
+        // higher-order elements: node maps of the shared faces, element
+        // matrices, and the tasks of all octants bucketed by level
+        const int P = p->order, N = ho_nodes(p), NF = (P + 1) * (P + 1);
+        std::vector<int> hmap;
+        st = ho_node_maps(p, P, nbr, nbrf, perm, hmap);
+        if (st) {
+            std::string msg = p->err;
+            drop_device(p);
+            return fail(p, st, msg);
+        }
+        snx_problem::Ho &H = p->ho;
+        const size_t NN = (size_t)N * N;
+#define HALLOC(ptr, bytes) HIPCHK(p, m.alloc((void **)&(ptr), (bytes)), "device allocation")
+        HALLOC(H.M, sizeof(float) * C * NN);
+        HALLOC(H.S, sizeof(float) * 3 * C * NN);
+        HALLOC(H.F, sizeof(float) * 18 * C * NF * NF);
+        HALLOC(H.R, sizeof(float) * C * G * N);
+        HALLOC(H.psi, sizeof(float) * p->nang * C * G * N);
+        HALLOC(H.phi[0], sizeof(float) * C * G * N);
+        HALLOC(H.phi[1], sizeof(float) * C * G * N);
+        HALLOC(H.perm, sizeof(int) * 6 * C * NF);
+        HALLOC(H.tasks, sizeof(int) * 8 * C);
+#undef HALLOC
+        int maxlev = 0;
+        for (int l : p->level) maxlev = std::max(maxlev, l);
+        H.off.assign(maxlev + 2, 0);
+        for (int l : p->level) ++H.off[l + 1];
+        for (int l = 0; l <= maxlev; ++l) H.off[l + 1] += H.off[l];
+        std::vector<int> tasks(8 * C), fillp(H.off.begin(), H.off.end() - 1);
+        for (int o = 0; o < 8; ++o)
+            for (size_t K = 0; K < C; ++K) tasks[fillp[p->level[(size_t)o * C + K]]++] = (int)(8 * K + o);
+        HIPCHK(p, hipMemcpyAsync(H.perm, hmap.data(), sizeof(int) * hmap.size(), hipMemcpyHostToDevice, s), "copy");
+        HIPCHK(p, hipMemcpyAsync(H.tasks, tasks.data(), sizeof(int) * tasks.size(), hipMemcpyHostToDevice, s), "copy");
+        HIPCHK(p, hipMemsetAsync(p->d_err, 0, sizeof(int), s), "memset");
+        HIPCHK(p, launch_ho_geometry(P, d_xyz, d_cv, d_nbr, d_nbrf, H.perm, p->C, ho_reference(P), H.M, H.S, H.F,
+                                     p->d_err, s), "geometry");
+        HIPCHK(p, hipMemcpyAsync(&herr, p->d_err, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+        HIPCHK(p, hipStreamSynchronize(s), "geometry");
+        if (herr & 1) { drop_device(p); return fail(p, SNX_E_MESH, "non-positive Jacobian at a Gauss point"); }
+        HoDev &D = H.dev;
+        D.C = p->C; D.G = p->G; D.A = p->A;
+        D.M = H.M; D.S = H.S; D.F = H.F; D.perm = H.perm; D.nbr = hp.nbr; D.inmask = hp.inmask;
+        D.sigt = hp.sigt; D.omega = hp.omega; D.psib = hp.psib; D.R = H.R; D.psi = H.psi; D.tasks = H.tasks;
+    }
     p->ready = true;
     return SNX_OK;
 }
@@ -1172,12 +1302,92 @@ snx_status snx_setup(snx_problem *p, void *stream) {
         if (st_) return fail((p), st_, (p)->sched.err);      \
     } while (0)
 
+}  // extern "C"
+
+namespace {
+
+// One higher-order sweep: the source from phi_in, the levels in order, the
+// angle reduction into phi_out.  e0/e1 (optional) bracket the level launches.
+snx_status ho_sweep(snx_problem *p, const float *phi_in, float *phi_out, hipStream_t s, hipEvent_t e0 = nullptr,
+                    hipEvent_t e1 = nullptr) {
+    snx_problem::Ho &H = p->ho;
+    const int N = ho_nodes(p);
+    HIPCHK(p, launch_ho_source(H.M, p->hp.q, p->hp.sigs, phi_in, H.R, p->C, p->G, N, s), "source");
+    if (e0) HIPCHK(p, hipEventRecord(e0, s), "event");
+    for (size_t l = 0; l + 1 < H.off.size(); ++l)
+        HIPCHK(p, launch_ho_sweep_level(p->order, H.dev, H.off[l], H.off[l + 1] - H.off[l], s), "level launch");
+    if (e1) HIPCHK(p, hipEventRecord(e1, s), "event");
+    HIPCHK(p, launch_ho_reduce(H.psi, p->hp.w, p->nang, (long long)p->C * p->G * N, phi_out, s), "reduce");
+    return SNX_OK;
+}
+
+// Source iteration at order > 1 until the FP64 relative max-norm change of phi
+// is <= tol or max_it sweeps.
+snx_status ho_solve(snx_problem *p, double tol, int max_it, const float *phi0, float *phi, snx_solve_info *info,
+                    hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t n = (size_t)p->C * p->G * ho_nodes(p);
+    float *cur = p->ho.phi[0], *nxt = p->ho.phi[1];
+    if (phi0) HIPCHK(p, hipMemcpyAsync(cur, phi0, sizeof(float) * n, hipMemcpyDeviceToDevice, s), "copy");
+    else HIPCHK(p, launch_fill_f32(cur, n, 0.f, s), "fill");
+    int it = 0;
+    double eps = INFINITY;
+    while (it < max_it) {
+        snx_status st = ho_sweep(p, cur, nxt, s);
+        if (st) return st;
+        HIPCHK(p, hipMemsetAsync(p->d_change, 0, 2 * sizeof(unsigned long long), s), "memset");
+        HIPCHK(p, launch_max_change(nxt, cur, (long long)n, p->d_change, s), "change");
+        unsigned long long h[2] = {0, 0};
+        HIPCHK(p, hipMemcpyAsync(h, p->d_change, sizeof h, hipMemcpyDeviceToHost, s), "copy");
+        HIPCHK(p, hipStreamSynchronize(s), "solve");
+        double num, den;
+        std::memcpy(&num, &h[0], sizeof num);
+        std::memcpy(&den, &h[1], sizeof den);
+        eps = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
+        ++it;
+        std::swap(cur, nxt);
+        if (eps <= tol) break;
+    }
+    HIPCHK(p, hipMemcpyAsync(phi, cur, sizeof(float) * n, hipMemcpyDeviceToDevice, s), "copy");
+    HIPCHK(p, hipStreamSynchronize(s), "solve");
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    const bool conv = eps <= tol;
+    if (info) {
+        info->iterations = it;
+        info->status = conv ? SNX_OK : SNX_E_NOCONV;
+        info->residual = eps;
+        info->wall_ms = ms;
+        info->solves_per_s = ms > 0 ? (double)p->C * p->nang * p->G * it / (ms * 1e-3) : 0.0;
+    }
+    return conv ? SNX_OK : fail(p, SNX_E_NOCONV, "source iteration ended before the tolerance");
+}
+
+}  // namespace
+
+extern "C" {
+
+snx_status snx_set_order(snx_problem *p, int32_t order) {
+    if (!p) return SNX_E_ARG;
+    if (order < 1 || order > 3) return fail(p, SNX_E_ARG, "order must be 1, 2 or 3");
+    p->order = order;
+    drop_device(p);
+    return SNX_OK;
+}
+
+snx_status snx_get_order(snx_problem *p, int32_t *order, int32_t *nodes) {
+    if (!p) return SNX_E_ARG;
+    if (order) *order = p->order;
+    if (nodes) *nodes = ho_nodes(p);
+    return SNX_OK;
+}
+
 snx_status snx_sweep(snx_problem *p, const float *phi_in, float *phi_out, void *stream) {
     if (!p) return SNX_E_ARG;
     if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
     if (!phi_out || phi_in == phi_out) return fail(p, SNX_E_ARG, "phi_out must be non-NULL and distinct from phi_in");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
+    if (p->order > 1) return ho_sweep(p, phi_in, phi_out, s);
     if (p->nmat)   // one Jacobi step over groups: the cross-group source from phi_in too
         HIPCHK(p, launch_outer_source(p->sched.d_probs, 0, p->C, p->G, phi_in, s), "outer source");
     HIPCHK(p, launch_source(p->sched.d_probs, 0, p->C, p->G, phi_in, nullptr, s), "source");
@@ -1194,6 +1404,7 @@ snx_status snx_solve(snx_problem *p, double tol, int32_t max_it, const float *ph
     if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
     if (!phi || max_it < 1 || !(tol >= 0.0)) return fail(p, SNX_E_ARG, "bad solve arguments");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
+    if (p->order > 1) return ho_solve(p, tol, max_it, phi0, phi, info, (hipStream_t)stream);
     const float *in[1] = {phi0};
     float *out[1] = {phi};
     snx_status st = sched_solve(p->sched, tol, max_it, in, out, info, (hipStream_t)stream);
@@ -1205,6 +1416,7 @@ snx_status snx_solve_outer(snx_problem *p, int32_t outer, int32_t inner, double 
                            snx_solve_info *info, void *stream) {
     if (!p) return SNX_E_ARG;
     if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
+    if (p->order > 1) return fail(p, SNX_E_ARG, "snx_solve_outer is not available at order > 1");
     if (!phi || outer < 1 || inner < 1 || !(tol >= 0.0)) return fail(p, SNX_E_ARG, "bad solve arguments");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
@@ -1259,6 +1471,7 @@ snx_status snx_solve_outer(snx_problem *p, int32_t outer, int32_t inner, double 
 snx_status snx_balance(snx_problem *p, const float *phi_in, const float *phi_out, double *out, void *stream) {
     if (!p) return SNX_E_ARG;
     if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
+    if (p->order > 1) return fail(p, SNX_E_ARG, "snx_balance is not available at order > 1");
     if (!phi_out || !out) return fail(p, SNX_E_ARG, "phi_out and out are required");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
@@ -1273,6 +1486,7 @@ snx_status snx_balance(snx_problem *p, const float *phi_in, const float *phi_out
 snx_status snx_integrated_flux(snx_problem *p, const float *phi, double *out, void *stream) {
     if (!p) return SNX_E_ARG;
     if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
+    if (p->order > 1) return fail(p, SNX_E_ARG, "snx_integrated_flux is not available at order > 1");
     if (!phi || !out) return fail(p, SNX_E_ARG, "phi and out are required");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
@@ -1303,6 +1517,7 @@ snx_status snx_designation_stats(snx_problem *p, int64_t *out) {
 snx_status snx_get_psi(snx_problem *p, int32_t angle, int32_t group, float *out, void *stream) {
     if (!p || !out) return SNX_E_ARG;
     if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
+    if (p->order > 1) return fail(p, SNX_E_ARG, "snx_get_psi is not available at order > 1");
     if (angle < 0 || angle >= p->nang || group < 0 || group >= p->G)
         return fail(p, SNX_E_ARG, "angle or group out of range");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
@@ -1352,6 +1567,7 @@ snx_status snx_set_schedule(snx_problem *p, int32_t threads, int32_t wg_per_cu, 
 snx_status snx_tune(snx_problem *p, const char *cache_path, int32_t *chosen, void *stream) {
     if (!p) return SNX_E_ARG;
     if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
+    if (p->order > 1) return fail(p, SNX_E_ARG, "snx_tune is not available at order > 1");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
     int t = 0, w = 0;
     double ms = 0;
@@ -1384,7 +1600,8 @@ snx_status snx_profile_sweep(snx_problem *p, int32_t nsweeps, const float *phi_i
     snx_status st = SNX_OK;
     for (auto &e : ev)
         if (hipEventCreate(&e) != hipSuccess) { st = fail(p, SNX_E_DEVICE, "hipEventCreate failed"); break; }
-    for (int i = 0; i < nsweeps && !st; ++i) {
+    for (int i = 0; i < nsweeps && !st && p->order > 1; ++i) st = ho_sweep(p, phi_in, phi_out, s, ev[2 * i], ev[2 * i + 1]);
+    for (int i = 0; i < nsweeps && !st && p->order == 1; ++i) {
         hipError_t e = launch_source(p->sched.d_probs, 0, p->C, p->G, phi_in, nullptr, s);
         if (e != hipSuccess) { st = fail(p, SNX_E_DEVICE, "source launch failed"); break; }
         st = enqueue_sweep(p->sched, nullptr, s, ev[2 * i], ev[2 * i + 1]);
@@ -1408,7 +1625,7 @@ snx_status snx_profile_sweep(snx_problem *p, int32_t nsweeps, const float *phi_i
 }  // extern "C"
 
 bool snx::problem_view(const snx_problem *p, DevProblem *out, int *device) {
-    if (!p || !p->ready) return false;
+    if (!p || !p->ready || p->order > 1) return false;
     *out = p->hp;
     *device = p->device;
     return true;
@@ -1432,6 +1649,7 @@ snx_status snx_batch_create(snx_batch **out, int32_t n, snx_problem *const *prob
     std::vector<snx_problem *> v(probs, probs + n);
     for (snx_problem *p : v) {
         if (!p || !p->ready) { g_create_error = "every problem of a batch must be set up"; return SNX_E_STATE; }
+        if (p->order > 1) { g_create_error = "batches hold first-order problems only"; return SNX_E_ARG; }
         if (p->device != v[0]->device) { g_create_error = "the problems of a batch must share a device"; return SNX_E_ARG; }
     }
     snx_batch *b = new (std::nothrow) snx_batch();

@@ -1,0 +1,405 @@
+// Higher-order elements (orders 2 and 3): element matrices, the sweep of one
+// level of the octant DAGs, the source and the angle reduction.
+//
+// The element is the order-p Lagrange element on a trilinear hexahedron: nodes
+// at the Gauss-Lobatto-Legendre points in each reference coordinate (local node
+// j = a + m b + m^2 c with m = p + 1), integrals by the m-point Gauss rule per
+// direction.  The paper's benchmarks run first-, second- and third-order
+// elements (Section 3.6 and its table of run times); the equations of one
+// (cell, direction, group) are those of first order with N = m^3 nodes:
+//     (sum_a Om_a S^a + sigma_t M - sum_{f in} Om . F_f) psi = M q - sum_{f in} (Om . F_f) psi_up.
+//
+// A system has N unknowns, too many for one lane's registers at N = 27 or 64,
+// so a wave solves it cooperatively: lane r holds row r of the matrix and
+// entry r of the right-hand side, the pivot row goes to every lane through
+// LDS, and unpivoted LU (the operator's symmetric part is positive
+// definite: sigma_t M plus the upwind face terms) eliminates below it.  At
+// order 2 each half-wave solves its own system.
+#include "snx_internal.h"
+
+namespace snx {
+
+namespace {
+
+constexpr double kFourPi = 12.566370614359172953850573533118;
+
+template <int P> struct HoShape {
+    static constexpr int m = P + 1, N = m * m * m, NF = m * m;
+};
+
+// node index j -> its index along reference axis d
+template <int P> __device__ __forceinline__ int node_axis(int j, int d) {
+    constexpr int m = P + 1;
+    return d == 0 ? j % m : d == 1 ? (j / m) % m : j / (m * m);
+}
+// the two free axes of face f in increasing order
+__device__ __forceinline__ void face_axes(int f, int &u, int &v) {
+    const int axis = f >> 1;
+    u = axis == 0 ? 1 : 0;
+    v = axis == 2 ? 1 : 2;
+}
+// position of node j on face f (index along u + m * index along v), or -1 when
+// j is not on the face
+template <int P> __device__ __forceinline__ int face_pos(int f, int j) {
+    int u, v;
+    face_axes(f, u, v);
+    if (node_axis<P>(j, f >> 1) != (f & 1) * P) return -1;
+    return node_axis<P>(j, u) + (P + 1) * node_axis<P>(j, v);
+}
+
+// trilinear vertex function v and its reference gradient at xi
+__device__ __forceinline__ void trilinear(int v, const double xi[3], double &f, double df[3]) {
+    double h[3], dh[3];
+    for (int d = 0; d < 3; ++d) {
+        const double c = ((v >> d) & 1) ? 1.0 : -1.0;
+        h[d] = 0.5 * (1.0 + c * xi[d]);
+        dh[d] = 0.5 * c;
+    }
+    f = h[0] * h[1] * h[2];
+    df[0] = dh[0] * h[1] * h[2];
+    df[1] = h[0] * dh[1] * h[2];
+    df[2] = h[0] * h[1] * dh[2];
+}
+
+// Lagrange polynomial a of the nodes at x, and its derivative
+template <int P> __device__ __forceinline__ void lagrange(const double *node, int a, double x, double &val,
+                                                          double &der) {
+    double v = 1.0, d = 0.0;
+    for (int b = 0; b <= P; ++b) {
+        if (b == a) continue;
+        const double den = node[a] - node[b];
+        d = d * (x - node[b]) / den + v / den;   // product rule, one factor at a time
+        v *= (x - node[b]) / den;
+    }
+    val = v;
+    der = d;
+}
+
+// ------------------------------------------------------------------ geometry
+
+// One workgroup per cell: M_ij = int phi_i phi_j dV and
+// S^a_ij = int phi_i d phi_j / d x_a dV in FP64 by the m^3-point Gauss rule.
+template <int P>
+__global__ __launch_bounds__(256) void k_ho_volume(const double *__restrict__ xyz, const int *__restrict__ cv, HoRef ref,
+                                                   float *__restrict__ M, float *__restrict__ S, int *__restrict__ err) {
+    constexpr int m = P + 1, N = m * m * m, Q = m * m * m;
+    const int K = blockIdx.x, tid = threadIdx.x;
+    __shared__ double sX[8][3];
+    __shared__ double sWd[Q], sJi[Q][9];   // weight * det J; (J^-1)[b][a] = d xi_b / d x_a at [b * 3 + a]
+    __shared__ double sL[m][m], sD[m][m];  // Lagrange value / derivative of node a at Gauss point t
+    if (tid < 24) sX[tid / 3][tid % 3] = xyz[3 * (size_t)cv[8 * (size_t)K + tid / 3] + tid % 3];
+    if (tid < m * m) lagrange<P>(ref.node, tid / m, ref.gx[tid % m], sL[tid / m][tid % m], sD[tid / m][tid % m]);
+    __syncthreads();
+    if (tid < Q) {
+        const int qa = tid % m, qb = (tid / m) % m, qc = tid / (m * m);
+        const double xi[3] = {ref.gx[qa], ref.gx[qb], ref.gx[qc]};
+        double J[3][3] = {};
+        for (int v = 0; v < 8; ++v) {
+            double f, df[3];
+            trilinear(v, xi, f, df);
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) J[a][b] += sX[v][a] * df[b];
+        }
+        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        const double c01 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+        const double c02 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        const double det = J[0][0] * c00 + J[1][0] * c01 + J[2][0] * c02;
+        if (!(det > 0.0)) atomicOr(err, 1);
+        const double id = 1.0 / det;
+        // inverse by the adjugate: inv[b][a]
+        sJi[tid][0] = c00 * id;
+        sJi[tid][1] = c01 * id;
+        sJi[tid][2] = c02 * id;
+        sJi[tid][3] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id;
+        sJi[tid][4] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+        sJi[tid][5] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+        sJi[tid][6] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id;
+        sJi[tid][7] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+        sJi[tid][8] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+        sWd[tid] = ref.gw[qa] * ref.gw[qb] * ref.gw[qc] * det;
+    }
+    __syncthreads();
+    for (int e = tid; e < N * N; e += blockDim.x) {
+        const int i = e / N, j = e % N;
+        const int ia = node_axis<P>(i, 0), ib = node_axis<P>(i, 1), ic = node_axis<P>(i, 2);
+        const int ja = node_axis<P>(j, 0), jb = node_axis<P>(j, 1), jc = node_axis<P>(j, 2);
+        double mm = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int q = 0; q < Q; ++q) {
+            const int qa = q % m, qb = (q / m) % m, qc = q / (m * m);
+            const double wp = sWd[q] * sL[ia][qa] * sL[ib][qb] * sL[ic][qc];
+            const double la = sL[ja][qa], lb = sL[jb][qb], lc = sL[jc][qc];
+            const double g0 = sD[ja][qa] * lb * lc, g1 = la * sD[jb][qb] * lc, g2 = la * lb * sD[jc][qc];
+            const double *Ji = sJi[q];
+            mm += wp * la * lb * lc;
+            s0 += wp * (Ji[0] * g0 + Ji[3] * g1 + Ji[6] * g2);
+            s1 += wp * (Ji[1] * g0 + Ji[4] * g1 + Ji[7] * g2);
+            s2 += wp * (Ji[2] * g0 + Ji[5] * g1 + Ji[8] * g2);
+        }
+        const size_t NN = (size_t)N * N;
+        M[K * NN + e] = (float)mm;
+        S[(3 * (size_t)K + 0) * NN + e] = (float)s0;
+        S[(3 * (size_t)K + 1) * NN + e] = (float)s1;
+        S[(3 * (size_t)K + 2) * NN + e] = (float)s2;
+    }
+}
+
+// One workgroup per (cell, face): F^a_kl = int_f n_a phi_k phi_l dA over the
+// face's nodes by the m^2-point Gauss rule, n dA = +-(dx/du x dx/dv) outward.
+// An interior face is integrated on the side with the smaller (cell, face)
+// index, which also writes the negated values at the neighbour's nodes.
+template <int P>
+__global__ __launch_bounds__(256) void k_ho_faces(const double *__restrict__ xyz, const int *__restrict__ cv,
+                                                  const int *__restrict__ nbr, const int *__restrict__ nbrf,
+                                                  const int *__restrict__ hoperm, HoRef ref, float *__restrict__ F) {
+    constexpr int m = P + 1, NF = m * m, QF = m * m;
+    const int K = blockIdx.x / 6, f = blockIdx.x % 6, tid = threadIdx.x;
+    const int Nb = nbr[6 * K + f], g = nbrf[6 * K + f];
+    if (Nb >= 0 && 6 * Nb + g < 6 * K + f) return;   // the neighbour's side writes this face
+    __shared__ double sX[8][3], sN[QF][3], sL[m][m];
+    if (tid < 24) sX[tid / 3][tid % 3] = xyz[3 * (size_t)cv[8 * (size_t)K + tid / 3] + tid % 3];
+    if (tid < m * m) {
+        double d;
+        lagrange<P>(ref.node, tid / m, ref.gx[tid % m], sL[tid / m][tid % m], d);
+    }
+    __syncthreads();
+    const int axis = f >> 1, side = f & 1;
+    int u, v;
+    face_axes(f, u, v);
+    if (tid < QF) {
+        const int qu = tid % m, qv = tid / m;
+        double xi[3];
+        xi[axis] = side ? 1.0 : -1.0;
+        xi[u] = ref.gx[qu];
+        xi[v] = ref.gx[qv];
+        double tu[3] = {0, 0, 0}, tv[3] = {0, 0, 0};
+        for (int vv = 0; vv < 8; ++vv) {
+            double fv, df[3];
+            trilinear(vv, xi, fv, df);
+            for (int a = 0; a < 3; ++a) {
+                tu[a] += sX[vv][a] * df[u];
+                tv[a] += sX[vv][a] * df[v];
+            }
+        }
+        // dx/du x dx/dv points along +xi_axis for axes 0 and 2, along -xi_axis for axis 1
+        const double sgn = (axis == 1 ? -1.0 : 1.0) * (side ? 1.0 : -1.0) * ref.gw[qu] * ref.gw[qv];
+        sN[tid][0] = sgn * (tu[1] * tv[2] - tu[2] * tv[1]);
+        sN[tid][1] = sgn * (tu[2] * tv[0] - tu[0] * tv[2]);
+        sN[tid][2] = sgn * (tu[0] * tv[1] - tu[1] * tv[0]);
+    }
+    __syncthreads();
+    if (tid >= NF * NF) return;
+    const int k = tid / NF, l = tid % NF;
+    // face node at position k: index k % m along u, k / m along v (its factor along the axis is 1 on the face)
+    double F3[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < QF; ++q) {
+        const int qu = q % m, qv = q / m;
+        const double pk = sL[k % m][qu] * sL[k / m][qv], pl = sL[l % m][qu] * sL[l / m][qv];
+        for (int a = 0; a < 3; ++a) F3[a] += sN[q][a] * pk * pl;
+    }
+    const size_t FF = (size_t)NF * NF;
+    for (int a = 0; a < 3; ++a) F[((6 * (size_t)K + f) * 3 + a) * FF + tid] = (float)F3[a];
+    if (Nb < 0) return;
+    const int pk = face_pos<P>(g, hoperm[(6 * (size_t)K + f) * NF + k]);
+    const int pl = face_pos<P>(g, hoperm[(6 * (size_t)K + f) * NF + l]);
+    if (pk < 0 || pl < 0) return;   // not produced by the host's node maps; kept out of bounds-unsafe writes
+    for (int a = 0; a < 3; ++a) F[((6 * (size_t)Nb + g) * 3 + a) * FF + pk * NF + pl] = (float)-F3[a];
+}
+
+// --------------------------------------------------------------------- sweep
+
+// Orders LDS accesses of one wave: what a lane wrote before is seen by every
+// lane after.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One workgroup per (task, direction) of a level: B = Om . S - sum_{f in}
+// Om . F_f and M go to LDS once, then the workgroup's wave halves solve the
+// direction's groups, one system each.
+template <int P>
+__global__ __launch_bounds__(256) void k_ho_sweep(HoDev D, int begin) {
+    constexpr int m = P + 1, N = m * m * m, NF = m * m;
+    constexpr int LD = (N % 2 == 0) ? N + 1 : N + 2;        // odd row stride: lanes' rows sit in different banks
+    constexpr int LP = ((N + 1) + 3) / 4 * 4;               // pivot buffer: row and rhs, 16-byte aligned
+    constexpr int H = N <= 32 ? 32 : 64, SPW = 64 / H, SPB = 4 * SPW;
+    __shared__ float sB[N * LD], sM[N * LD];
+    __shared__ float sOF[6][NF * NF];
+    __shared__ __align__(16) float sPiv[4 * SPW][LP];
+
+    const int A = D.A, C = D.C, G = D.G;
+    const int t = begin + (int)(blockIdx.x / (unsigned)A), dir = (int)(blockIdx.x % (unsigned)A);
+    const int task = D.tasks[t];
+    const int K = task >> 3, o = task & 7, n = o * A + dir;
+    const int mask = D.inmask[(size_t)o * C + K];
+    const float ox = D.omega[3 * n], oy = D.omega[3 * n + 1], oz = D.omega[3 * n + 2];
+    const int tid = threadIdx.x;
+    const size_t NN = (size_t)N * N, FF = (size_t)NF * NF;
+    const float *S = D.S + 3 * (size_t)K * NN;
+    const float *Mk = D.M + (size_t)K * NN;
+    const float *Fk = D.F + 6 * 3 * (size_t)K * FF;
+
+    for (int e = tid; e < N * N; e += 256) {
+        const int i = e / N, j = e % N;
+        float b = ox * S[e] + oy * S[NN + e] + oz * S[2 * NN + e];
+        for (int f = 0; f < 6; ++f) {
+            if (!((mask >> f) & 1)) continue;
+            const int pi = face_pos<P>(f, i), pj = face_pos<P>(f, j);
+            if (pi < 0 || pj < 0) continue;
+            const float *Ff = Fk + (size_t)f * 3 * FF + pi * NF + pj;
+            b -= ox * Ff[0] + oy * Ff[FF] + oz * Ff[2 * FF];
+        }
+        sB[i * LD + j] = b;
+        sM[i * LD + j] = Mk[e];
+    }
+    for (int e = tid; e < 6 * NF * NF; e += 256) {
+        const int f = e / (NF * NF), kl = e % (NF * NF);
+        if (!((mask >> f) & 1)) continue;
+        const float *Ff = Fk + (size_t)f * 3 * FF + kl;
+        sOF[f][kl] = ox * Ff[0] + oy * Ff[FF] + oz * Ff[2 * FF];
+    }
+    __syncthreads();
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int half = lane / H, r = lane % H;
+    const int rr = r < N ? r : N - 1;                        // lanes past the last row compute on a copy of it
+    float *piv = sPiv[wave * SPW + half];
+    const float4 *piv4 = reinterpret_cast<const float4 *>(piv);
+    int fpos[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) fpos[f] = ((mask >> f) & 1) ? face_pos<P>(f, rr) : -1;
+
+    for (int g0 = 0; g0 < G; g0 += SPB) {
+        const int g = g0 + wave * SPW + half;
+        const bool valid = g < G && r < N;
+        const int gg = g < G ? g : G - 1;
+        const float sig = D.sigt[(size_t)K * G + gg];
+        float row[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) row[j] = __builtin_fmaf(sig, sM[rr * LD + j], sB[rr * LD + j]);
+        float b = D.R[((size_t)K * G + gg) * N + rr];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            if (fpos[f] < 0) continue;
+            const int nb = D.nbr[6 * K + f];
+            const float *of = sOF[f] + fpos[f] * NF;
+            if (nb >= 0) {
+                const float *up = D.psi + (((size_t)n * C + nb) * G + gg) * N;
+                const int *pm = D.perm + (6 * (size_t)K + f) * NF;
+                for (int l = 0; l < NF; ++l) b -= of[l] * up[pm[l]];
+            } else {
+                const float pb = D.psib ? D.psib[gg] : 0.f;
+                float s = 0.f;
+                for (int l = 0; l < NF; ++l) s += of[l];
+                b -= s * pb;
+            }
+        }
+        // unpivoted LU by rows: step k broadcasts row k, the rows below eliminate column k
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            if (r == k) {
+#pragma unroll
+                for (int j = k; j < N; ++j) piv[j] = row[j];
+                piv[N] = b;
+            }
+            wave_lds_sync();
+            const float ipk = __builtin_amdgcn_rcpf(piv[k]);
+            const float l = r > k ? row[k] * ipk : 0.f;
+#pragma unroll
+            for (int c = (k + 1) / 4; c < (N + 3) / 4; ++c) {
+                const float4 v = piv4[c];
+                const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int j = 4 * c + e;
+                    if (j > k && j < N) row[j] = __builtin_fmaf(-l, vv[e], row[j]);
+                }
+            }
+            b = __builtin_fmaf(-l, piv[N], b);
+            wave_lds_sync();
+        }
+        // back substitution, one column at a time: lane k finishes x_k, the rows above take it out
+        float x = 0.f;
+#pragma unroll
+        for (int k = N - 1; k >= 0; --k) {
+            if (r == k) {
+                x = b / row[k];
+                piv[0] = x;
+            }
+            wave_lds_sync();
+            const float xk = piv[0];
+            b = __builtin_fmaf(r < k ? -row[k] : 0.f, xk, b);
+            wave_lds_sync();
+        }
+        if (valid) D.psi[(((size_t)n * C + K) * G + g) * N + r] = x;
+    }
+}
+
+// R = M (Q + sigma_s phi) / (4 pi) at every (cell, group, node); phi NULL = zero
+__global__ __launch_bounds__(256) void k_ho_source(const float *__restrict__ M, const float *__restrict__ q,
+                                                   const float *__restrict__ sigs, const float *__restrict__ phi,
+                                                   float *__restrict__ R, int C, int G, int N) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)C * G * N) return;
+    const long long kg = e / N;
+    const int i = (int)(e % N), K = (int)(kg / G);
+    const float Q = q[kg], ss = sigs[kg];
+    const float *Mi = M + ((size_t)K * N + i) * N;
+    const float *ph = phi ? phi + kg * N : nullptr;
+    double s = 0.0;
+    for (int j = 0; j < N; ++j) s += (double)Mi[j] * (double)(ph ? Q + ss * ph[j] : Q);
+    R[e] = (float)(s / kFourPi);
+}
+
+// phi = sum_n w_n psi_n at every (cell, group, node), in increasing n, FP64
+__global__ __launch_bounds__(256) void k_ho_reduce(const float *__restrict__ psi, const float *__restrict__ w, int nang,
+                                                   long long cgn, float *__restrict__ phi) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= cgn) return;
+    double s = 0.0;
+    for (int n = 0; n < nang; ++n) s += (double)w[n] * (double)psi[(size_t)n * cgn + e];
+    phi[e] = (float)s;
+}
+
+unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_ho_geometry(int P, const double *xyz, const int *cv, const int *nbr, const int *nbrf,
+                              const int *hoperm, int C, const HoRef &ref, float *M, float *S, float *F, int *err,
+                              hipStream_t s) {
+    if (P == 2) {
+        hipLaunchKernelGGL(k_ho_volume<2>, dim3(C), dim3(256), 0, s, xyz, cv, ref, M, S, err);
+        hipLaunchKernelGGL(k_ho_faces<2>, dim3(6 * C), dim3(256), 0, s, xyz, cv, nbr, nbrf, hoperm, ref, F);
+    } else if (P == 3) {
+        hipLaunchKernelGGL(k_ho_volume<3>, dim3(C), dim3(256), 0, s, xyz, cv, ref, M, S, err);
+        hipLaunchKernelGGL(k_ho_faces<3>, dim3(6 * C), dim3(256), 0, s, xyz, cv, nbr, nbrf, hoperm, ref, F);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ho_sweep_level(int P, const HoDev &D, int begin, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const dim3 grid((unsigned)count * (unsigned)D.A);
+    if (P == 2) hipLaunchKernelGGL(k_ho_sweep<2>, grid, dim3(256), 0, s, D, begin);
+    else if (P == 3) hipLaunchKernelGGL(k_ho_sweep<3>, grid, dim3(256), 0, s, D, begin);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_ho_source(const float *M, const float *q, const float *sigs, const float *phi, float *R, int C,
+                            int G, int N, hipStream_t s) {
+    hipLaunchKernelGGL(k_ho_source, dim3(blocks_for((long long)C * G * N)), dim3(256), 0, s, M, q, sigs, phi, R, C,
+                       G, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_ho_reduce(const float *psi, const float *w, int nang, long long cgn, float *phi, hipStream_t s) {
+    hipLaunchKernelGGL(k_ho_reduce, dim3(blocks_for(cgn)), dim3(256), 0, s, psi, w, nang, cgn, phi);
+    return hipGetLastError();
+}
+
+}  // namespace snx

@@ -118,6 +118,29 @@ struct DevProblem {
     float lo[3], hi[3];          // bounding box of the mesh
 };
 
+// Higher-order elements (orders 2 and 3).  Reference tables of the order-p
+// element: the Gauss-Lobatto-Legendre nodes and the Gauss points and weights,
+// p + 1 of each.
+struct HoRef {
+    double node[4], gx[4], gw[4];
+};
+// Device view of a higher-order problem (N = (p+1)^3 nodes, NF = (p+1)^2 per face).
+struct HoDev {
+    int C, G, A;
+    const float *M;              // [C][N][N]          mass
+    const float *S;              // [C][3][N][N]       streaming S^a_ij = int phi_i d phi_j / d x_a
+    const float *F;              // [C][6][3][NF][NF]  face matrices on the face's nodes
+    const int *perm;             // [C][6][NF]         neighbour's local node at my face node k
+    const int *nbr;              // [C][6]
+    const unsigned char *inmask; // [8][C]             inflow faces per octant
+    const float *sigt;           // [C][G]
+    const float *omega;          // [8*A][3]
+    const float *psib;           // [G] or nullptr
+    const float *R;              // [C][G][N]          M (Q + sigma_s phi) / (4 pi)
+    float *psi;                  // [8*A][C][G][N]
+    const int *tasks;            // 8*K + o, ordered by level of the octant DAGs
+};
+
 // Iteration record of snx_solve's device-side control.
 struct IterCtl {
     unsigned long long num_bits;  // max |phi_new - phi_old| (FP64 bit pattern, non-negative)
@@ -223,6 +246,15 @@ hipError_t gnn_features(const DevProblem &P, float *x, int *nbr_out, hipStream_t
 hipError_t gnn_inv_degree(const int *nbr, int C, float *inv_deg, hipStream_t s);
 hipError_t gnn_targets(const float *phi, long long Nn, float *y, hipStream_t s);
 hipError_t gnn_expand(const float *z, long long Nn, float *phi, hipStream_t s);
+
+hipError_t launch_ho_geometry(int P, const double *xyz, const int *cv, const int *nbr, const int *nbrf,
+                              const int *hoperm, int C, const HoRef &ref, float *M, float *S, float *F, int *err,
+                              hipStream_t s);
+// Tasks D.tasks[begin, begin + count) of one level, one workgroup per (task, direction).
+hipError_t launch_ho_sweep_level(int P, const HoDev &D, int begin, int count, hipStream_t s);
+hipError_t launch_ho_source(const float *M, const float *q, const float *sigs, const float *phi, float *R, int C,
+                            int G, int N, hipStream_t s);
+hipError_t launch_ho_reduce(const float *psi, const float *w, int nang, long long cgn, float *phi, hipStream_t s);
 
 // Device view of a set-up problem (false if it is not set up).
 bool problem_view(const snx_problem *p, DevProblem *out, int *device);

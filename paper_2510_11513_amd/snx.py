@@ -33,7 +33,7 @@ EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_s
            "snx_gnn_train_step", "snx_gnn_predict", "snx_set_sweep_mode", "snx_batch_set_sweep_mode",
            "snx_get_psi", "snx_set_sweep_stats", "snx_batch_set_sweep_stats", "snx_set_designation",
            "snx_designation_stats", "snx_set_group_scattering", "snx_solve_outer", "snx_set_reflective",
-           "snx_set_anisotropy", "snx_get_schedule", "snx_batch_solve_outer"]
+           "snx_set_anisotropy", "snx_get_schedule", "snx_batch_solve_outer", "snx_set_order", "snx_get_order"]
 _NO_STATUS = ("snx_destroy", "snx_last_error", "snx_batch_destroy", "snx_batch_last_error", "snx_gnn_destroy",
               "snx_gnn_last_error")
 
@@ -84,6 +84,8 @@ def load(path: str = LIB_PATH):
     L.snx_get_levels.argtypes = [_vp, _vp, _vp]
     L.snx_get_psi.argtypes = [_vp, ct.c_int32, ct.c_int32, _vp, _vp]
     L.snx_set_designation.argtypes = [_vp, ct.c_int32]
+    L.snx_set_order.argtypes = [_vp, ct.c_int32]
+    L.snx_get_order.argtypes = [_vp, _vp, _vp]
     L.snx_set_reflective.argtypes = [_vp, ct.c_int32]
     L.snx_get_schedule.argtypes = [_vp, _vp]
     L.snx_batch_solve_outer.argtypes = [_vp, ct.c_int32, ct.c_int32, ct.c_double, _vp, _vp, _vp, _vp]
@@ -182,6 +184,7 @@ class Problem:
         self.h = h
         self.device = device
         self.ncell = self.G = self.nang = 0
+        self.nodes = 8          # nodes per cell: (order + 1)^3
 
     def _check(self, rc, what, allow=()):
         if rc and rc not in allow:
@@ -253,6 +256,11 @@ class Problem:
         self._check(load().snx_set_group_scattering(self.h, sg.shape[0], cm.ctypes.data_as(ct.c_void_p),
                                                     sg.ctypes.data_as(ct.c_void_p)), "set_group_scattering")
 
+    def set_order(self, order: int):
+        """Element order 1, 2 or 3 (nodes per cell (order + 1)^3); takes effect at setup."""
+        self._check(load().snx_set_order(self.h, int(order)), "set_order")
+        self.nodes = (int(order) + 1) ** 3
+
     def set_designation(self, kind: int):
         """DESIGNATION_OCTANT (default) or DESIGNATION_ANGLE (per direction, lagged
         faces where a direction goes against its octant's order); takes effect at setup."""
@@ -267,11 +275,14 @@ class Problem:
         self._check(load().snx_setup(self.h, _stream(stream)), "setup")
 
     @classmethod
-    def from_problem(cls, prob, device: int = 0, setup: bool = True, quadrature=None, designation: int = 0):
+    def from_problem(cls, prob, device: int = 0, setup: bool = True, quadrature=None, designation: int = 0,
+                     order: int = 1):
         """Loads a generated problem (paper_2510_11513_amd.inputs.Problem) into the library."""
         p = cls(device)
         if designation:
             p.set_designation(designation)
+        if order != 1:
+            p.set_order(order)
         p.set_mesh(prob.mesh.xyz, prob.mesh.cell_vert)
         om, w = quadrature if quadrature is not None else quadrature_product(prob.npolar, prob.nazim)
         p.set_quadrature(om, w)
@@ -285,17 +296,26 @@ class Problem:
     # ------------------------------------------------------------- compute
     def empty_phi(self):
         import torch
-        return torch.empty((self.ncell, self.G, 8), dtype=torch.float32, device=f"cuda:{self.device}")
+        return torch.empty((self.ncell, self.G, self.nodes), dtype=torch.float32, device=f"cuda:{self.device}")
+
+    def _flux(self, *ts):
+        """Refuses flux tensors of the wrong size before the library reads them."""
+        want = self.ncell * self.G * self.nodes
+        for t in ts:
+            if t is not None and (t.numel() != want or not t.is_contiguous()):
+                raise ValueError(f"flux arrays hold [ncell][G][{self.nodes}] contiguous floats")
 
     def sweep(self, phi_in=None, phi_out=None, stream=None):
         if phi_out is None:
             phi_out = self.empty_phi()
+        self._flux(phi_in, phi_out)
         self._check(load().snx_sweep(self.h, _ptr(phi_in), _ptr(phi_out), _stream(stream)), "sweep")
         return phi_out
 
     def solve(self, tol: float, max_it: int, phi0=None, phi=None, stream=None, allow_noconv=False):
         if phi is None:
             phi = self.empty_phi()
+        self._flux(phi0, phi)
         info = SolveInfo()
         rc = load().snx_solve(self.h, tol, max_it, _ptr(phi0), _ptr(phi), ct.byref(info), _stream(stream))
         self._check(rc, "solve", allow=(SNX_E_NOCONV,) if allow_noconv else ())
@@ -355,6 +375,7 @@ class Problem:
         """Mean duration (ms) of the sweep kernel alone, from HIP events on its stream."""
         if phi_out is None:
             phi_out = self.empty_phi()
+        self._flux(phi_in, phi_out)
         ms = ct.c_double(0.0)
         self._check(load().snx_profile_sweep(self.h, nsweeps, _ptr(phi_in), _ptr(phi_out), ct.byref(ms),
                                              _stream(stream)), "profile_sweep")
