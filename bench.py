@@ -37,6 +37,13 @@ FP32_VALU_PEAK_TFLOPS = 78.6      # MI355X, FP32 vector without packed instructi
 PAPER_SHAPE_CPU_S = {"AMT, AMD EPYC 9354 2x32 cores": 1.85, "AMT, Intel Xeon Gold 6430 2x32 cores": 1.99,
                      "AMT, NVIDIA Grace 2x72 cores": 1.09, "BSP, NVIDIA Grace 2x72 cores": 1.75}
 
+# The same table's AMT columns at second and third order (AMD Genoa, Intel
+# Sapphire Rapids, NVIDIA Grace nodes), seconds, for context only.
+PAPER_HO_CPU_S = {2: {"AMT, AMD EPYC 9354 2x32 cores": 20.45, "AMT, Intel Xeon Gold 6430 2x32 cores": 15.15,
+                      "AMT, NVIDIA Grace 2x72 cores": 5.87},
+                  3: {"AMT, AMD EPYC 9354 2x32 cores": 80.15, "AMT, Intel Xeon Gold 6430 2x32 cores": 90.30,
+                      "AMT, NVIDIA Grace 2x72 cores": 39.48}}
+
 WORKLOADS = {
     "cfg2": (2, "32^3 jittered hex (32768 cells), 96 angles (3x4 product), 16 groups, two-material 4^3 blocks"),
     "cfg1": (1, "8^3 jittered hex (512 cells), 32 angles (2x2), 4 groups, sigma_t 1, c 0.5"),
@@ -110,6 +117,56 @@ def paper_shape(outer: int = 5, inner: int = 5):
             "last_outer_change": info["residual"], "sweep_mode": mode,
             "plain_25_sweeps_s": round(dt_plain, 5), "plain_solves_per_s": solves / dt_plain,
             "paper_cpu_s_context": PAPER_SHAPE_CPU_S}
+
+
+def ho_flops_per_solve(order: int, G: int, inflow_faces: int = 3) -> float:
+    """Algorithmic FLOP of one (cell, direction, group) system at order p (an FMA
+    counts two), N = (p+1)^3 nodes, NF = (p+1)^2 per face: the rows
+    sigma_t M + B (N^2 FMA), the inflow of three faces (NF^2 FMA each),
+    unpivoted LU with the right-hand side (per step k, N-k-1 multipliers and
+    (N-k-1)(N-k) FMA), back substitution (N(N-1)/2 FMA, N divisions), and the
+    per-direction operator B = Omega.S - Omega.F_in (3 N^2 FMA) over G groups."""
+    N, NF = (order + 1) ** 3, (order + 1) ** 2
+    elim = sum((N - k - 1) * (1 + 2 * (N - k)) for k in range(N))
+    back = N * (N - 1) + N
+    return 2.0 * N * N + 2.0 * inflow_faces * NF * NF + elim + back + 6.0 * N * N / G
+
+
+def higher_order(steps: int = 25):
+    """Second and third order on the paper's timing shape (16^3 cells, 128
+    angles, 16 groups; Section 3.6 and its run-time table): the level-by-level
+    sweep kernels alone (HIP events) and 25 source iterations end to end.  The
+    paper's 25 sweeps are five outer times five inner iterations with
+    group coupling; these are 25 plain sweeps."""
+    import torch
+    from paper_2510_11513_amd import inputs, snx
+    prob = inputs.config_problem(0)
+    G = prob.mat.ngroup
+    solves = prob.mesh.ncell * prob.nang * G
+    out = {"workload": f"16^3 jittered hex, 128 angles, 16 groups, {steps} source iterations"}
+    for order in (2, 3):
+        print(f"[bench] order {order}", file=sys.stderr, flush=True)
+        p = snx.Problem.from_problem(prob, order=order)
+        phi = p.empty_phi()
+        p.solve(0.0, 2, phi=phi, allow_noconv=True)       # warm-up
+        ms = p.profile_sweep(5, phi_in=phi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.solve(0.0, steps, phi=phi, allow_noconv=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        p.close()
+        fps = ho_flops_per_solve(order, G)
+        tflops = fps * solves / (ms * 1e-3) / 1e12
+        out[f"order{order}"] = {
+            "nodes": (order + 1) ** 3, "sweep_ms": round(ms, 3), "solves_per_s": solves / (ms * 1e-3),
+            "unknowns_per_s": solves * (order + 1) ** 3 / (ms * 1e-3),
+            "s_for_25": round(dt * 25.0 / steps, 4),
+            "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": FP32_VALU_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tflops / FP32_VALU_PEAK_TFLOPS, 4),
+                         "flops_per_solve": round(fps, 1)},
+            "paper_cpu_s_context": PAPER_HO_CPU_S[order]}
+    return out
 
 
 def per_angle(prob, threads: int, wg_per_cu: int, ms_octant: float, its_octant: int, sweeps: int):
@@ -249,6 +306,8 @@ def main():
     ap.add_argument("--paper-shape", type=int, default=1, help="also time the paper's 25-sweep 16^3 shape (0 = skip)")
     ap.add_argument("--per-angle", type=int, default=1,
                     help="also time the workload under per-angle designation (0 = skip)")
+    ap.add_argument("--higher-order", type=int, default=1,
+                    help="also time second and third order on the paper's 16^3 shape (0 = skip)")
     ap.add_argument("--extensions", type=int, default=1,
                     help="also time reflective planes, anisotropy and group coupling on the workload (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -352,6 +411,8 @@ def main():
         out["extensions"] = extensions(prob, stats["threads"], tuned[1] if tuned else args.wg_per_cu, 10)
     if args.paper_shape:
         out["paper_shape"] = paper_shape()
+    if args.higher_order:
+        out["higher_order"] = higher_order()
     if args.learned > 0:
         print("[bench] learned vs zero start", file=sys.stderr, flush=True)
         out["learned"] = learned_start(args.learned)

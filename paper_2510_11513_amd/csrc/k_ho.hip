@@ -15,6 +15,8 @@
 // LDS, and unpivoted LU (the operator's symmetric part is positive
 // definite: sigma_t M plus the upwind face terms) eliminates below it.  At
 // order 2 each half-wave solves its own system.
+#include <utility>
+
 #include "snx_internal.h"
 
 namespace snx {
@@ -208,11 +210,62 @@ __global__ __launch_bounds__(256) void k_ho_faces(const double *__restrict__ xyz
 // --------------------------------------------------------------------- sweep
 
 // Orders LDS accesses of one wave: what a lane wrote before is seen by every
-// lane after.
+// lane after.  A wave's LDS instructions execute in issue order, so keeping
+// the compiler from moving memory accesses across this point is enough.
 __device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    asm volatile("" ::: "memory");
+}
+
+// Elimination step k of the unpivoted LU by rows: lane k broadcasts its row
+// (columns k.., and its right-hand side at [N]) through LDS, every lane below
+// takes column k out of its own row.  A template per step keeps every row
+// index static, so the row stays in registers.
+template <int N, int k>
+__device__ __forceinline__ void lu_step(float (&row)[N], float &b, float *piv, int r) {
+    if (r == k) {   // whole 16-byte chunks from the one holding column k (entries left of k go unread)
+        float4 *w4 = reinterpret_cast<float4 *>(piv);
+#pragma unroll
+        for (int c = k / 4; c < (N + 3) / 4; ++c) {
+            const int j = 4 * c;
+            w4[c] = make_float4(row[j], j + 1 < N ? row[j + 1] : 0.f, j + 2 < N ? row[j + 2] : 0.f,
+                                j + 3 < N ? row[j + 3] : 0.f);
+        }
+        piv[N] = b;
+    }
+    wave_lds_sync();
+    const float4 *piv4 = reinterpret_cast<const float4 *>(piv);
+    const float l = r > k ? row[k] * __builtin_amdgcn_rcpf(piv[k]) : 0.f;
+#pragma unroll
+    for (int c = (k + 1) / 4; c < (N + 3) / 4; ++c) {
+        const float4 v = piv4[c];
+        const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 4 * c + e;
+            if (j > k && j < N) row[j] = __builtin_fmaf(-l, vv[e], row[j]);
+        }
+    }
+    b = __builtin_fmaf(-l, piv[N], b);
+    // the next step's write comes after these reads in issue order
+}
+// Back substitution, column k = N-1-i: lane k finishes x_k, the rows above take it out.
+template <int N, int i>
+__device__ __forceinline__ void back_step(const float (&row)[N], float &b, float &x, float *piv, int r) {
+    constexpr int k = N - 1 - i;
+    if (r == k) {
+        x = b / row[k];
+        piv[0] = x;
+    }
+    wave_lds_sync();
+    const float xk = piv[0];
+    b = __builtin_fmaf(r < k ? -row[k] : 0.f, xk, b);
+}
+template <int N, int... K>
+__device__ __forceinline__ void lu_solve(float (&row)[N], float &b, float &x, float *piv, int r,
+                                         std::integer_sequence<int, K...>) {
+    (lu_step<N, K>(row, b, piv, r), ...);
+    (back_step<N, K>(row, b, x, piv, r), ...);
 }
 
 // One workgroup per (task, direction) of a level: B = Om . S - sum_{f in}
@@ -265,7 +318,6 @@ __global__ __launch_bounds__(256) void k_ho_sweep(HoDev D, int begin) {
     const int half = lane / H, r = lane % H;
     const int rr = r < N ? r : N - 1;                        // lanes past the last row compute on a copy of it
     float *piv = sPiv[wave * SPW + half];
-    const float4 *piv4 = reinterpret_cast<const float4 *>(piv);
     int fpos[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) fpos[f] = ((mask >> f) & 1) ? face_pos<P>(f, rr) : -1;
@@ -295,43 +347,8 @@ __global__ __launch_bounds__(256) void k_ho_sweep(HoDev D, int begin) {
                 b -= s * pb;
             }
         }
-        // unpivoted LU by rows: step k broadcasts row k, the rows below eliminate column k
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            if (r == k) {
-#pragma unroll
-                for (int j = k; j < N; ++j) piv[j] = row[j];
-                piv[N] = b;
-            }
-            wave_lds_sync();
-            const float ipk = __builtin_amdgcn_rcpf(piv[k]);
-            const float l = r > k ? row[k] * ipk : 0.f;
-#pragma unroll
-            for (int c = (k + 1) / 4; c < (N + 3) / 4; ++c) {
-                const float4 v = piv4[c];
-                const float vv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int j = 4 * c + e;
-                    if (j > k && j < N) row[j] = __builtin_fmaf(-l, vv[e], row[j]);
-                }
-            }
-            b = __builtin_fmaf(-l, piv[N], b);
-            wave_lds_sync();
-        }
-        // back substitution, one column at a time: lane k finishes x_k, the rows above take it out
         float x = 0.f;
-#pragma unroll
-        for (int k = N - 1; k >= 0; --k) {
-            if (r == k) {
-                x = b / row[k];
-                piv[0] = x;
-            }
-            wave_lds_sync();
-            const float xk = piv[0];
-            b = __builtin_fmaf(r < k ? -row[k] : 0.f, xk, b);
-            wave_lds_sync();
-        }
+        lu_solve<N>(row, b, x, piv, r, std::make_integer_sequence<int, N>{});
         if (valid) D.psi[(((size_t)n * C + K) * G + g) * N + r] = x;
     }
 }
