@@ -301,6 +301,8 @@ class Problem:
     def _flux(self, *ts):
         """Refuses flux tensors of the wrong size before the library reads them."""
         want = self.ncell * self.G * self.nodes
+        if want == 0:       # no mesh or materials yet: the library reports the state error
+            return
         for t in ts:
             if t is not None and (t.numel() != want or not t.is_contiguous()):
                 raise ValueError(f"flux arrays hold [ncell][G][{self.nodes}] contiguous floats")
