@@ -253,23 +253,29 @@ __device__ __forceinline__ void lu_step(float (&row)[N], float &b, float *piv, i
     b = __builtin_fmaf(-l, piv[N], b);
     // the next step's write comes after these reads in issue order
 }
-// Back substitution, column k = N-1-i: lane k finishes x_k, the rows above take it out.
-template <int N, int i>
-__device__ __forceinline__ void back_step(const float (&row)[N], float &b, float &x, float *piv, int r) {
+// Back substitution, column k = N-1-i: lane k finishes x_k, which every lane
+// of its system reads straight from lane k's register (no LDS round trip),
+// and the rows above take it out.  H: lanes per system (32: two systems per wave).
+template <int N, int H, int i>
+__device__ __forceinline__ void back_step(const float (&row)[N], float &b, float &x, int r, int half) {
     constexpr int k = N - 1 - i;
-    if (r == k) {
-        x = b / row[k];
-        piv[0] = x;
+    const int cand = __builtin_bit_cast(int, b * __builtin_amdgcn_rcpf(row[k]));   // x_k in lane k
+    float xk;
+    if constexpr (H == 64) {
+        xk = __builtin_bit_cast(float, __builtin_amdgcn_readlane(cand, k));
+    } else {
+        const float x0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(cand, k));
+        const float x1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(cand, H + k));
+        xk = half ? x1 : x0;
     }
-    wave_lds_sync();
-    const float xk = piv[0];
+    if (r == k) x = xk;
     b = __builtin_fmaf(r < k ? -row[k] : 0.f, xk, b);
 }
-template <int N, int... K>
-__device__ __forceinline__ void lu_solve(float (&row)[N], float &b, float &x, float *piv, int r,
+template <int N, int H, int... K>
+__device__ __forceinline__ void lu_solve(float (&row)[N], float &b, float &x, float *piv, int r, int half,
                                          std::integer_sequence<int, K...>) {
     (lu_step<N, K>(row, b, piv, r), ...);
-    (back_step<N, K>(row, b, x, piv, r), ...);
+    (back_step<N, H, K>(row, b, x, r, half), ...);
 }
 
 // One workgroup per (task, direction) of a level: B = Om . S - sum_{f in}
@@ -352,7 +358,7 @@ __device__ __forceinline__ void ho_sweep_body(const HoDev &D, int begin) {
             }
         }
         float x = 0.f;
-        lu_solve<N>(row, b, x, piv, r, std::make_integer_sequence<int, N>{});
+        lu_solve<N, H>(row, b, x, piv, r, half, std::make_integer_sequence<int, N>{});
         if (valid) D.psi[(((size_t)n * C + K) * G + g) * N + r] = x;
     }
 }
