@@ -213,8 +213,7 @@ snx_status ho_node_maps(snx_problem *p, int P, const std::vector<int> &nbr, cons
         for (int f = 0; f < 6; ++f) {
             const int N = nbr[6 * (size_t)K + f], g = nbrf[6 * (size_t)K + f];
             if (N < 0) continue;
-            int u, v, u2, v2;
-            axes(f, u, v);
+            int u2, v2;
             axes(g, u2, v2);
             int cu[4], cw[4];   // the neighbour's corner bits along u2 and v2 at my corner l
             for (int l = 0; l < 4; ++l) {
@@ -229,8 +228,6 @@ snx_status ho_node_maps(snx_problem *p, int P, const std::vector<int> &nbr, cons
                 const int eu = cu[0] ^ (u_follows_u ? bu : bv), ev = cw[0] ^ (u_follows_u ? bv : bu);
                 if (eu != cu[l] || ev != cw[l]) return fail(p, SNX_E_MESH, "shared face corners do not match");
             }
-            (void)u;
-            (void)v;
             for (int j = 0; j < m; ++j)
                 for (int i = 0; i < m; ++i) {
                     const int a = u_follows_u ? i : j, b = u_follows_u ? j : i;

@@ -25,10 +25,6 @@ namespace {
 
 constexpr double kFourPi = 12.566370614359172953850573533118;
 
-template <int P> struct HoShape {
-    static constexpr int m = P + 1, N = m * m * m, NF = m * m;
-};
-
 // node index j -> its index along reference axis d
 template <int P> __device__ __forceinline__ int node_axis(int j, int d) {
     constexpr int m = P + 1;
