@@ -249,6 +249,51 @@ __device__ __forceinline__ void lu_step(float (&row)[N], float &b, float *piv, i
     b = __builtin_fmaf(-l, piv[N], b);
     // the next step's write comes after these reads in issue order
 }
+// Two elimination steps, pivots k and k+1, with one LDS round trip: lanes k
+// and k+1 broadcast their rows, every lane forms row k+1 with column k
+// eliminated from the two (its multiplier m1 and pivot d), then takes columns
+// k and k+1 out of its own row at once: row -= c0 row_k + c1 row_k+1, with
+// c1 = l1 and c0 = l0 - l1 m1 (l0, l1 its own multipliers).  Lane k+1 itself
+// only takes out column k.  Same arithmetic as two single steps, up to
+// rounding order.
+template <int N, int LP, int k>
+__device__ __forceinline__ void lu_step2(float (&row)[N], float &b, float *piv, int r) {
+    float *piv1 = piv + LP;
+    if (r == k || r == k + 1) {
+        float4 *w4 = reinterpret_cast<float4 *>(r == k ? piv : piv1);
+#pragma unroll
+        for (int c = k / 4; c < (N + 3) / 4; ++c) {
+            const int j = 4 * c;
+            w4[c] = make_float4(row[j], j + 1 < N ? row[j + 1] : 0.f, j + 2 < N ? row[j + 2] : 0.f,
+                                j + 3 < N ? row[j + 3] : 0.f);
+        }
+        (r == k ? piv : piv1)[N] = b;
+    }
+    wave_lds_sync();
+    const float4 *p0 = reinterpret_cast<const float4 *>(piv);
+    const float4 *p1 = reinterpret_cast<const float4 *>(piv1);
+    const float pk = piv[k], pk1 = piv[k + 1], qk = piv1[k], qk1 = piv1[k + 1];
+    const float ipk = __builtin_amdgcn_rcpf(pk);
+    const float m1 = qk * ipk;                                  // row k+1's multiplier of row k
+    const float d = __builtin_fmaf(-m1, pk1, qk1);              // row k+1's pivot after that
+    const float l0 = row[k] * ipk;
+    const float l1 = __builtin_fmaf(-l0, pk1, row[k + 1]) * __builtin_amdgcn_rcpf(d);
+    const float c0 = r > k + 1 ? __builtin_fmaf(-l1, m1, l0) : (r == k + 1 ? m1 : 0.f);
+    const float c1 = r > k + 1 ? l1 : 0.f;
+#pragma unroll
+    for (int c = (k + 1) / 4; c < (N + 3) / 4; ++c) {
+        const float4 v = p0[c], w = p1[c];
+        const float vv[4] = {v.x, v.y, v.z, v.w}, ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 4 * c + e;
+            if (j > k && j < N) row[j] = __builtin_fmaf(-c1, ww[e], __builtin_fmaf(-c0, vv[e], row[j]));
+        }
+        if (N > 32 && (c + 1) % kChunks == 0) __builtin_amdgcn_sched_barrier(0);
+    }
+    b = __builtin_fmaf(-c1, piv1[N], __builtin_fmaf(-c0, piv[N], b));
+}
+
 // Back substitution, column k = N-1-i: lane k finishes x_k, which every lane
 // of its system reads straight from lane k's register (no LDS round trip),
 // and the rows above take it out.  H: lanes per system (32: two systems per wave).
@@ -267,10 +312,15 @@ __device__ __forceinline__ void back_step(const float (&row)[N], float &b, float
     if (r == k) x = xk;
     b = __builtin_fmaf(r < k ? -row[k] : 0.f, xk, b);
 }
-template <int N, int H, int... K>
+template <int N, int H, int LP, int... K, int... I>
 __device__ __forceinline__ void lu_solve(float (&row)[N], float &b, float &x, float *piv, int r, int half,
-                                         std::integer_sequence<int, K...>) {
-    (lu_step<N, K>(row, b, piv, r), ...);
+                                         std::integer_sequence<int, K...>, std::integer_sequence<int, I...>) {
+    if constexpr (N <= 32) {   // order 2: pivots in pairs (order 3 would need more registers than it has)
+        (lu_step2<N, LP, 2 * I>(row, b, piv, r), ...);
+        if constexpr (N % 2) lu_step<N, N - 1>(row, b, piv, r);   // the odd last one
+    } else {
+        (lu_step<N, K>(row, b, piv, r), ...);
+    }
     (back_step<N, H, K>(row, b, x, r, half), ...);
 }
 
@@ -285,7 +335,9 @@ __device__ __forceinline__ void ho_sweep_body(const HoDev &D, int begin) {
     constexpr int H = N <= 32 ? 32 : 64, SPW = 64 / H, SPB = 4 * SPW;
     __shared__ float sB[N * LD], sM[N * LD];
     __shared__ float sOF[6][NF * NF];
-    __shared__ __align__(16) float sPiv[4 * SPW][LP];
+    // pivot row k (and k+1 where pivots go in pairs); order 3 stays within 40 KB of LDS,
+    // so that four workgroups fit a CU
+    __shared__ __align__(16) float sPiv[4 * SPW][N <= 32 ? 2 * LP : LP];
 
     const int A = D.A, C = D.C, G = D.G;
     const int t = begin + (int)(blockIdx.x / (unsigned)A), dir = (int)(blockIdx.x % (unsigned)A);
@@ -354,7 +406,8 @@ __device__ __forceinline__ void ho_sweep_body(const HoDev &D, int begin) {
             }
         }
         float x = 0.f;
-        lu_solve<N, H>(row, b, x, piv, r, half, std::make_integer_sequence<int, N>{});
+        lu_solve<N, H, LP>(row, b, x, piv, r, half, std::make_integer_sequence<int, N>{},
+                           std::make_integer_sequence<int, N / 2>{});
         if (valid) D.psi[(((size_t)n * C + K) * G + g) * N + r] = x;
     }
 }
