@@ -217,7 +217,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // (columns k.., and its right-hand side at [N]) through LDS, every lane below
 // takes column k out of its own row.  A template per step keeps every row
 // index static, so the row stays in registers.
-constexpr int kChunks = 4;   // 16-byte pivot chunks loaded ahead at order 3
+constexpr int kChunks = 4;   // 16-byte pivot chunks (of each pivot row) loaded ahead at order 3
 
 template <int N, int k>
 __device__ __forceinline__ void lu_step(float (&row)[N], float &b, float *piv, int r) {
@@ -315,12 +315,8 @@ __device__ __forceinline__ void back_step(const float (&row)[N], float &b, float
 template <int N, int H, int LP, int... K, int... I>
 __device__ __forceinline__ void lu_solve(float (&row)[N], float &b, float &x, float *piv, int r, int half,
                                          std::integer_sequence<int, K...>, std::integer_sequence<int, I...>) {
-    if constexpr (N <= 32) {   // order 2: pivots in pairs (order 3 would need more registers than it has)
-        (lu_step2<N, LP, 2 * I>(row, b, piv, r), ...);
-        if constexpr (N % 2) lu_step<N, N - 1>(row, b, piv, r);   // the odd last one
-    } else {
-        (lu_step<N, K>(row, b, piv, r), ...);
-    }
+    (lu_step2<N, LP, 2 * I>(row, b, piv, r), ...);             // pivots in pairs
+    if constexpr (N % 2) lu_step<N, N - 1>(row, b, piv, r);      // the odd last one
     (back_step<N, H, K>(row, b, x, r, half), ...);
 }
 
@@ -335,9 +331,7 @@ __device__ __forceinline__ void ho_sweep_body(const HoDev &D, int begin) {
     constexpr int H = N <= 32 ? 32 : 64, SPW = 64 / H, SPB = 4 * SPW;
     __shared__ float sB[N * LD], sM[N * LD];
     __shared__ float sOF[6][NF * NF];
-    // pivot row k (and k+1 where pivots go in pairs); order 3 stays within 40 KB of LDS,
-    // so that four workgroups fit a CU
-    __shared__ __align__(16) float sPiv[4 * SPW][N <= 32 ? 2 * LP : LP];
+    __shared__ __align__(16) float sPiv[4 * SPW][2 * LP];   // pivot rows k and k+1
 
     const int A = D.A, C = D.C, G = D.G;
     const int t = begin + (int)(blockIdx.x / (unsigned)A), dir = (int)(blockIdx.x % (unsigned)A);
@@ -412,13 +406,12 @@ __device__ __forceinline__ void ho_sweep_body(const HoDev &D, int begin) {
     }
 }
 
-// Order 2 keeps its registers (four waves per SIMD); order 3 is held to 128
-// VGPRs so that four waves per SIMD hide the LDS round trip of each LU step
-// (measured 16% faster than its natural 192 registers, a few spills aside).
+// One kernel per order.  With pivots in pairs, order 3 runs fastest on its
+// natural register count (two waves per SIMD, each with twice the work between
+// LDS round trips); capping it at three or four waves per SIMD spilled and was
+// slower.
 __global__ __launch_bounds__(256) void k_ho_sweep2(HoDev D, int begin) { ho_sweep_body<2>(D, begin); }
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_ho_sweep3(HoDev D, int begin) {
-    ho_sweep_body<3>(D, begin);
-}
+__global__ __launch_bounds__(256) void k_ho_sweep3(HoDev D, int begin) { ho_sweep_body<3>(D, begin); }
 
 // R = M (Q + sigma_s phi) / (4 pi) at every (cell, group, node); phi NULL = zero
 __global__ __launch_bounds__(256) void k_ho_source(const float *__restrict__ M, const float *__restrict__ q,
