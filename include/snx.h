@@ -162,7 +162,8 @@ snx_status snx_set_group_scattering(snx_problem *p, int32_t nmat, const int32_t 
  * element of the rest of this header.  At order p > 1 every flux array of
  * snx_sweep, snx_solve and snx_profile_sweep holds [ncell][G][N] floats in
  * that node order, the sweep runs level by level over the octant DAGs (one
- * launch per level), and these are refused with SNX_E_ARG: per-angle
+ * launch per level; snx_set_schedule and snx_set_sweep_mode do not apply),
+ * and these are refused with SNX_E_ARG: per-angle
  * designation, reflective planes, anisotropic and group-to-group scattering
  * (at snx_setup), snx_solve_outer, snx_balance, snx_integrated_flux,
  * snx_get_psi, snx_tune, batches and the learned initial guess.
