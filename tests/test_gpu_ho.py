@@ -128,3 +128,45 @@ def test_refused_options_and_sizes():
     with pytest.raises(ValueError):
         p.sweep(wrong)
     p.close()
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_full_size_mirror_symmetry(order):
+    """At the benchmark's size (16^3 cells, 128 angles, 16 groups) and launch
+    configuration: on an unjittered mesh with uniform materials and inflow, one
+    sweep's flux is symmetric under x -> 1 - x (cell (i, j, k) node (a, b, c)
+    against cell (15 - i, j, k) node (p - a, b, c)); the product quadrature
+    holds every direction's mirror image.  The octants run in different
+    orders, so any error of the face maps, the octant designation or the
+    level lists shows as an asymmetry."""
+    torch = _torch()
+    from paper_2510_11513_amd import snx
+    n, G = 16, 16
+    mesh = inputs.make_mesh(n, 0.0, seed=7)
+    mat = inputs.materials_uniform(mesh, G, 1.0, 0.5, 1.0, scaled=True)
+    prob = inputs.Problem("ho_mirror", mesh, mat, 4, 4, 1e-6)
+    prob.boundary_kind = 1
+    prob.psi_b = np.linspace(0.1, 0.5, G)
+    p = snx.Problem.from_problem(prob, order=order)
+    m = order + 1
+    rng = np.random.default_rng(5)
+    # a flux that is itself mirror-symmetric (a function of |x - 1/2|, y, z per node)
+    ijk = mesh.ijk
+    N = m ** 3
+    base = rng.uniform(0.5, 1.5, (n, n, n, G, m, m, m))
+    base = 0.5 * (base + base[::-1, :, :, :, ::-1, :, :])
+    phi_in = np.empty((mesh.ncell, G, N), np.float32)
+    for K in range(mesh.ncell):
+        i, j, k = ijk[K]
+        # node j = a + m b + m^2 c: axis order (c, b, a) in a C-ordered [m][m][m] block
+        phi_in[K] = base[i, j, k].transpose(0, 3, 2, 1).reshape(G, N)
+    out = p.sweep(torch.from_numpy(phi_in).cuda())
+    torch.cuda.synchronize()
+    phi = out.cpu().numpy().astype(np.float64).reshape(mesh.ncell, G, m, m, m)   # [K][g][c][b][a]
+    where = {tuple(v): K for K, v in enumerate(ijk)}
+    mirror = np.array([where[(n - 1 - i, j, k)] for i, j, k in ijk])
+    asym = np.abs(phi - phi[mirror][:, :, :, :, ::-1]).max(axis=(0, 2, 3, 4)) / np.abs(phi).max(axis=(0, 2, 3, 4))
+    print(f"[case] order {order} full size: max relative asymmetry per group {asym.max():.2e}", flush=True)
+    assert np.all(np.isfinite(phi)) and phi.min() > 0
+    assert asym.max() <= 1e-5, asym
+    p.close()
