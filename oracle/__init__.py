@@ -76,6 +76,8 @@ def lib():
         L.snxo_get_geometry.argtypes = [vp] + [nullable_d] * 7
         L.snxo_get_dag.argtypes = [vp, nullable_d, nullable_d, nullable_d]
         L.snxo_get_angle_inflow.argtypes = [vp, _ip]
+        L.snxo_get_angle_order.argtypes = [vp, nullable_d, nullable_d]
+        L.snxo_set_octant_order.argtypes = [vp, ct.c_int]
         L.snxo_last_error.argtypes = [vp]
         L.snxo_last_error.restype = ct.c_char_p
         _lib = L
@@ -179,6 +181,11 @@ class Oracle:
         """Reflective boundary planes, bit 2*axis + side (before setup)."""
         self._check(lib().snxo_set_reflective(self.h, int(planes)), "set_reflective")
 
+    def set_octant_order(self, sequential: bool):
+        """True: octants in sequence, reflected inflow from the current sweep where the
+        mirrored octant came earlier; False (default): from the previous sweep."""
+        self._check(lib().snxo_set_octant_order(self.h, int(bool(sequential))), "set_octant_order")
+
     def set_group_scattering(self, cell_mat, sigma_gg):
         """cell_mat[ncell] int, sigma_gg[nmat][G][G] from group g' (axis 1) into g (axis 2);
         None clears it."""
@@ -277,8 +284,15 @@ class Oracle:
                     ("M", "S", "F", "area", "nbr", "nbr_face", "perm")]), "get_geometry")
         return g
 
+    def angle_order(self):
+        """Designation 2: ([nang][ncell] sweep order of each direction, [nang][ncell] lagged-face masks)."""
+        order = np.zeros((self.nang, self.ncell), np.int32)
+        lag = np.zeros((self.nang, self.ncell), np.int32)
+        self._check(lib().snxo_get_angle_order(self.h, _ptr(order), _ptr(lag)), "get_angle_order")
+        return order, lag
+
     def angle_inflow(self):
-        """Designation 1: [nang][ncell] inflow-face bit masks of each angle."""
+        """Designations 1 and 2: [nang][ncell] inflow-face bit masks of each angle."""
         ain = np.zeros((self.nang, self.ncell), np.int32)
         self._check(lib().snxo_get_angle_inflow(self.h, ain), "get_angle_inflow")
         return ain

@@ -31,7 +31,10 @@ struct snxo_problem {
     double *M, *S, *F, *area;       /* [C][64], [C][3][64], [C][6][3][16], [C][6][3] */
     int32_t *nbr, *nbrf, *perm;     /* [C][6], [C][6], [C][6][4] */
     int32_t *inflow, *level, *order;/* [8][C] each */
-    int designation;                /* 0 per octant, 1 per angle (snxo_set_designation) */
+    int designation;                /* 0 per octant, 1 per angle in the octant's order, 2 per angle in
+                                       each direction's own order (snxo_set_designation) */
+    int octseq;                     /* 1: octants in sequence, reflected inflow from the current sweep
+                                       where the mirrored octant came earlier (snxo_set_octant_order) */
     int refl;                       /* reflective planes (snxo_set_reflective): bit 2*axis + side */
     int L;                          /* anisotropic scattering order (snxo_set_anisotropy), 0 = isotropic */
     double *sigl;                   /* [C][G][L] Legendre moments sigma_1..sigma_L of the within-group law */
@@ -40,7 +43,9 @@ struct snxo_problem {
     int nmat;                       /* group-to-group scattering (snxo_set_group_scattering), 0 = none */
     int32_t *cmat;                  /* [C] material of each cell */
     double *sgg;                    /* [nmat][G][G] from group g' (row) into group g (column) */
-    int32_t *ain;                   /* designation 1: [nang][C] inflow faces of each angle */
+    int32_t *ain;                   /* designations 1, 2: [nang][C] inflow faces of each angle */
+    int32_t *aord;                  /* designation 2: [nang][C] each direction's topological order */
+    int32_t *alag;                  /* designation 2: [nang][C] inflow faces lagged to break cycles */
     char err[256];
 };
 
@@ -198,7 +203,9 @@ static void free_derived(snxo_problem *p) {
     free(p->M); free(p->S); free(p->F); free(p->area);
     free(p->nbr); free(p->nbrf); free(p->perm);
     free(p->inflow); free(p->level); free(p->order); free(p->ain); free(p->rdir); free(p->ylm);
+    free(p->aord); free(p->alag);
     p->ylm = NULL;
+    p->aord = p->alag = NULL;
     p->M = p->S = p->F = p->area = NULL;
     p->nbr = p->nbrf = p->perm = p->inflow = p->level = p->order = p->ain = p->rdir = NULL;
     p->ready = 0;
@@ -280,7 +287,7 @@ int snxo_set_boundary(snxo_problem *p, int kind, const double *psi_b) {
 }
 
 int snxo_set_designation(snxo_problem *p, int kind) {
-    if (!p || (kind != 0 && kind != 1)) return fail(p, SNXO_E_ARG, "designation must be 0 or 1");
+    if (!p || kind < 0 || kind > 2) return fail(p, SNXO_E_ARG, "designation must be 0, 1 or 2");
     p->designation = kind;
     free_derived(p);
     return SNXO_OK;
@@ -300,6 +307,12 @@ int snxo_set_anisotropy(snxo_problem *p, int L, const double *sigma_l) {
     p->sigl = dup_d(sigma_l, n);
     if (!p->sigl) return fail(p, SNXO_E_OOM, "out of memory");
     p->L = L;
+    return SNXO_OK;
+}
+
+int snxo_set_octant_order(snxo_problem *p, int sequential) {
+    if (!p || (sequential != 0 && sequential != 1)) return fail(p, SNXO_E_ARG, "octant order must be 0 or 1");
+    p->octseq = sequential;
     return SNXO_OK;
 }
 
@@ -587,6 +600,120 @@ static int build_angle_inflow(snxo_problem *p) {
     return SNXO_OK;
 }
 
+/* Designation 2: each direction sweeps the mesh in its own upwind order
+ * (Section 2.1).  Cell K depends on its neighbour N across every face f with
+ * Omega_n . A_f^K < 0.  On distorted meshes this graph can have cycles; the
+ * paper does not say how to treat them.  Here they are broken as follows.
+ *   1. The strongly connected components of the direction's graph are found
+ *      (Tarjan's algorithm).  An edge between two components never lies on a
+ *      cycle and is kept.
+ *   2. Inside a component, cells are ranked by the upwind distance
+ *      Omega_n . c_K of their vertex centroid c_K (cell id on a tie).  An edge
+ *      N -> K from a cell ranked after K is lagged: K reads N's angular flux of
+ *      the previous sweep on that face.  The kept edges inside a component all
+ *      go up in rank, so the rest of the graph is acyclic.
+ *   3. Kahn's algorithm over the kept edges gives the direction's order.
+ * The rank uses the geometry only, so a renumbering of the cells changes
+ * neither the lagged faces nor the result. */
+static double upwind_key(const snxo_problem *p, int K, const double *om) {
+    double c[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < 8; ++j)
+        for (int a = 0; a < 3; ++a) c[a] += p->xyz[3 * p->cv[8 * K + j] + a] / 8.0;
+    return om[0] * c[0] + om[1] * c[1] + om[2] * c[2];
+}
+
+static int ranked_after(const double *key, int N, int K) {
+    return key[N] > key[K] || (key[N] == key[K] && N > K);
+}
+
+static int build_angle_order(snxo_problem *p) {
+    int C = p->ncell;
+    int32_t *idx = malloc(sizeof(int32_t) * C), *low = malloc(sizeof(int32_t) * C);
+    int32_t *comp = malloc(sizeof(int32_t) * C), *stk = malloc(sizeof(int32_t) * C);
+    int32_t *cs_v = malloc(sizeof(int32_t) * C), *cs_f = malloc(sizeof(int32_t) * C);
+    int32_t *indeg = malloc(sizeof(int32_t) * C);
+    char *onstk = malloc((size_t)C);
+    double *key = malloc(sizeof(double) * C);
+    int rc = SNXO_OK;
+    if (!idx || !low || !comp || !stk || !cs_v || !cs_f || !indeg || !onstk || !key) {
+        rc = fail(p, SNXO_E_OOM, "out of memory");
+        goto done;
+    }
+    for (int n = 0; n < p->nang; ++n) {
+        const int32_t *in = p->ain + (long)n * C;
+        int32_t *lag = p->alag + (long)n * C, *ord = p->aord + (long)n * C;
+        for (int K = 0; K < C; ++K) {
+            idx[K] = -1;
+            onstk[K] = 0;
+            key[K] = upwind_key(p, K, p->omega + 3 * n);
+        }
+        /* 1. Tarjan's strongly connected components, iteratively.  The
+         * successors of v are its neighbours across its outflow faces. */
+        int counter = 0, sp = 0, ncomp = 0;
+        for (int r = 0; r < C; ++r) {
+            if (idx[r] >= 0) continue;
+            int cp = 0;
+            cs_v[cp] = r; cs_f[cp] = 0; ++cp;
+            idx[r] = low[r] = counter++;
+            stk[sp++] = r; onstk[r] = 1;
+            while (cp > 0) {
+                int v = cs_v[cp - 1];
+                if (cs_f[cp - 1] < 6) {
+                    int f = cs_f[cp - 1]++;
+                    int w = p->nbr[6 * v + f];
+                    if (w < 0 || ((in[v] >> f) & 1)) continue;
+                    if (idx[w] < 0) {
+                        idx[w] = low[w] = counter++;
+                        stk[sp++] = w; onstk[w] = 1;
+                        cs_v[cp] = w; cs_f[cp] = 0; ++cp;
+                    } else if (onstk[w] && idx[w] < low[v]) {
+                        low[v] = idx[w];
+                    }
+                } else {
+                    --cp;
+                    if (low[v] == idx[v]) {
+                        int w;
+                        do { w = stk[--sp]; onstk[w] = 0; comp[w] = ncomp; } while (w != v);
+                        ++ncomp;
+                    }
+                    if (cp > 0 && low[v] < low[cs_v[cp - 1]]) low[cs_v[cp - 1]] = low[v];
+                }
+            }
+        }
+        /* 2. lag the edges inside a component that go down in rank */
+        for (int K = 0; K < C; ++K) {
+            int m = 0;
+            indeg[K] = 0;
+            for (int f = 0; f < 6; ++f) {
+                int N = p->nbr[6 * K + f];
+                if (N < 0 || !((in[K] >> f) & 1)) continue;
+                if (comp[N] == comp[K] && ranked_after(key, N, K)) m |= 1 << f;
+                else indeg[K]++;
+            }
+            lag[K] = m;
+        }
+        /* 3. Kahn's algorithm over the kept edges, first-in first-out from the
+         * cells in id order */
+        int head = 0, tail = 0;
+        for (int K = 0; K < C; ++K)
+            if (indeg[K] == 0) ord[tail++] = K;
+        while (head < tail) {
+            int v = ord[head++];
+            for (int f = 0; f < 6; ++f) {
+                int w = p->nbr[6 * v + f];
+                if (w < 0 || ((in[v] >> f) & 1)) continue;
+                int g = p->nbrf[6 * v + f];
+                if ((lag[w] >> g) & 1) continue;
+                if (--indeg[w] == 0) ord[tail++] = w;
+            }
+        }
+        if (tail != C) { rc = fail(p, SNXO_E_CYCLE, "cycle left after lagging"); goto done; }
+    }
+done:
+    free(idx); free(low); free(comp); free(stk); free(cs_v); free(cs_f); free(indeg); free(onstk); free(key);
+    return rc;
+}
+
 /* Real orthonormal spherical harmonics of every direction up to degree L,
  * index l*l + l + m (m = -l..l): Y_l0 = N_l0 P_l(mu), Y_lm = sqrt2 N_lm P_l^m(mu)
  * cos(m phi) and Y_l,-m = sqrt2 N_lm P_l^m(mu) sin(m phi) for m > 0, with
@@ -677,16 +804,21 @@ int snxo_setup(snxo_problem *p) {
     p->inflow = malloc(sizeof(int32_t) * 8 * C);
     p->level = malloc(sizeof(int32_t) * 8 * C);
     p->order = malloc(sizeof(int32_t) * 8 * C);
-    if (p->designation == 1) p->ain = malloc(sizeof(int32_t) * (size_t)p->nang * C);
+    if (p->designation >= 1) p->ain = malloc(sizeof(int32_t) * (size_t)p->nang * C);
+    if (p->designation == 2) {
+        p->aord = malloc(sizeof(int32_t) * (size_t)p->nang * C);
+        p->alag = malloc(sizeof(int32_t) * (size_t)p->nang * C);
+    }
     if (!p->M || !p->S || !p->F || !p->area || !p->nbr || !p->nbrf || !p->perm || !p->inflow || !p->level || !p->order
-        || (p->designation == 1 && !p->ain)) {
+        || (p->designation >= 1 && !p->ain) || (p->designation == 2 && (!p->aord || !p->alag))) {
         free_derived(p);
         return fail(p, SNXO_E_OOM, "out of memory");
     }
     int rc = build_topology(p);
     if (!rc) rc = build_geometry(p);
     if (!rc) rc = build_dag(p);
-    if (!rc && p->designation == 1) rc = build_angle_inflow(p);
+    if (!rc && p->designation >= 1) rc = build_angle_inflow(p);
+    if (!rc && p->designation == 2) rc = build_angle_order(p);
     if (!rc && p->refl) rc = build_reflection(p);
     if (!rc && p->L) rc = build_harmonics(p);
     if (rc) { free_derived(p); return rc; }
@@ -701,16 +833,24 @@ int snxo_setup(snxo_problem *p) {
  *   b = M q - sum_{f in} (Om . F_f) psi_up_f
  * with q the nodal source values and psi_up the upwind trace at f's nodes.
  * "in" is the octant's inflow set (designation 0) or the angle's own
- * (designation 1).  psi_up is read from psi_cur, which holds the newest value
- * of every cell: this sweep's for cells already visited, the previous sweep's
- * (or zero) for the rest. */
+ * (designations 1 and 2).  psi_up is read from psi_cur, which holds the newest
+ * value of every cell: this sweep's for cells already visited, the previous
+ * sweep's (or zero) for the rest.  Two exceptions:
+ *   - designation 2, a face lagged to break a cycle: the neighbour's value of
+ *     the previous sweep, psi_lag[N * lag_stride + node] (NULL = zero);
+ *   - a reflective face: the mirrored direction m's own trace at these nodes,
+ *     from this sweep (psi_now, octants in sequence) when m's octant came
+ *     earlier, else from the previous sweep (psi_prev). */
 static int solve_local(const snxo_problem *p, int K, int n, int g, const double *qnodal,
                        const double *psi_cur /*[C][8] this angle and group*/,
-                       const double *psi_prev /*[nang][C][G][8] or NULL*/, double x[8], double *leak_out) {
+                       const double *psi_prev /*[nang][C][G][8] or NULL*/,
+                       const double *psi_lag, long lag_stride,
+                       const double *psi_now /*[nang][C][8] this group, or NULL*/, double x[8], double *leak_out) {
     const double *om = p->omega + 3 * n;
     const double *M = p->M + 64L * K, *S = p->S + 192L * K;
-    int o = n / (p->nang / 8);
-    int mask = p->designation == 1 ? p->ain[(long)n * p->ncell + K] : p->inflow[(long)o * p->ncell + K];
+    int per = p->nang / 8, o = n / per;
+    int mask = p->designation >= 1 ? p->ain[(long)n * p->ncell + K] : p->inflow[(long)o * p->ncell + K];
+    int lagged = p->designation == 2 ? p->alag[(long)n * p->ncell + K] : 0;
     double sigt = p->sigt[(long)K * p->G + g];
     double A[64], b[8], up[6][4];
     for (int i = 0; i < 8; ++i) {
@@ -729,11 +869,15 @@ static int solve_local(const snxo_problem *p, int K, int n, int g, const double 
         const double *F = p->F + 288L * K + 48 * f;
         int N = p->nbr[6 * K + f];
         for (int l = 0; l < 4; ++l) {
-            if (N >= 0) up[f][l] = psi_cur[8L * N + p->perm[24 * K + 4 * f + l]];
+            if (N >= 0 && ((lagged >> f) & 1))
+                up[f][l] = psi_lag ? psi_lag[(long)N * lag_stride + p->perm[24 * K + 4 * f + l]] : 0.0;
+            else if (N >= 0) up[f][l] = psi_cur[8L * N + p->perm[24 * K + 4 * f + l]];
             else if (reflective_axis(p, K, f) >= 0) {
-                /* the mirrored direction's own trace at these nodes, from the previous sweep */
                 int m = p->rdir[3 * n + reflective_axis(p, K, f)];
-                up[f][l] = psi_prev ? psi_prev[(((long)m * p->ncell + K) * p->G + g) * 8 + fn[l]] : 0.0;
+                if (psi_now && m / per < o)
+                    up[f][l] = psi_now[((long)m * p->ncell + K) * 8 + fn[l]];
+                else
+                    up[f][l] = psi_prev ? psi_prev[(((long)m * p->ncell + K) * p->G + g) * 8 + fn[l]] : 0.0;
             }
             else if (p->bnd_in) up[f][l] = p->bnd_in[((((long)K * 6 + f) * p->nang + n) * p->G + g) * 4 + l];
             else if (p->bkind == 1) up[f][l] = p->psib[g];
@@ -803,7 +947,10 @@ static void source_nodal(const snxo_problem *p, const double *phi_in, const doub
  * under designation 0 every inflow neighbour is already done.  Under
  * designation 1 an inflow neighbour that comes later in that order still
  * holds the previous sweep's value in psi_cur (initialised from psi_prev):
- * that face is lagged. */
+ * that face is lagged.  Under designation 2 the cells of direction n are
+ * visited in n's own order, where every inflow neighbour is done except
+ * across the faces lagged to break cycles, which read psi_prev.  Octants run
+ * in the order 0..7 (a group's whole sweep is sequential). */
 static int sweep_src(snxo_problem *p, const double *phi_in, const double *qouter, const double *psi_prev,
                      double *phi_out, double *psi_all, double *leak, double *leak_ang) {
     if (!p || !p->ready) return fail(p, SNXO_E_STATE, "setup has not run");
@@ -836,15 +983,20 @@ static int sweep_src(snxo_problem *p, const double *phi_in, const double *qouter
     #pragma omp parallel for schedule(dynamic, 1) reduction(|:bad)
     for (int g = 0; g < G; ++g) {
         double *psi_cur = malloc(sizeof(double) * 8 * (size_t)C);
-        if (!psi_cur) { bad = 1; continue; }
+        /* octants in sequence: this group's angular flux of the current sweep,
+         * read by reflective faces whose mirrored octant came earlier */
+        double *psi_now = (p->refl && p->octseq) ? malloc(sizeof(double) * 8 * (size_t)C * nang) : NULL;
+        if (!psi_cur || (p->refl && p->octseq && !psi_now)) { free(psi_cur); free(psi_now); bad = 1; continue; }
         for (int o = 0; o < 8; ++o)
             for (int a = 0; a < per; ++a) {
                 int n = o * per + a;
                 for (long K = 0; K < C; ++K)
                     for (int j = 0; j < 8; ++j)
                         psi_cur[8 * K + j] = psi_prev ? psi_prev[(((long)n * C + K) * G + g) * 8 + j] : 0.0;
+                const int32_t *ord = p->designation == 2 ? p->aord + (long)n * C : p->order + (long)o * C;
+                const double *lag = psi_prev ? psi_prev + ((long)n * C * G + g) * 8 : NULL;
                 for (int t = 0; t < C; ++t) {
-                    int K = p->order[(long)o * C + t];
+                    int K = ord[t];
                     double qn[8], x[8], L = 0.0;
                     if (p->ang_src) {
                         for (int j = 0; j < 8; ++j) qn[j] = p->ang_src[(((long)K * nang + n) * G + g) * 8 + j];
@@ -857,12 +1009,14 @@ static int sweep_src(snxo_problem *p, const double *phi_in, const double *qouter
                                     qn[j] += sl * p->ylm[(size_t)n * nm + k] * mom[(((size_t)K * G + g) * nm + k) * 8 + j];
                         }
                     }
-                    if (solve_local(p, K, n, g, qn, psi_cur, psi_prev, x, (leak || leak_ang) ? &L : NULL)) {
+                    if (solve_local(p, K, n, g, qn, psi_cur, psi_prev, lag, 8L * G, psi_now, x,
+                                    (leak || leak_ang) ? &L : NULL)) {
                         bad = 1;
                         break;
                     }
                     for (int j = 0; j < 8; ++j) {
                         psi_cur[8L * K + j] = x[j];
+                        if (psi_now) psi_now[((long)n * C + K) * 8 + j] = x[j];
                         phi_out[((long)K * G + g) * 8 + j] += p->w[n] * x[j];
                         if (psi_all) psi_all[(((long)n * C + K) * G + g) * 8 + j] = x[j];
                     }
@@ -871,6 +1025,7 @@ static int sweep_src(snxo_problem *p, const double *phi_in, const double *qouter
                 }
             }
         free(psi_cur);
+        free(psi_now);
     }
     free(mom);
     if (bad) return fail(p, SNXO_E_MESH, "singular local system or out of memory");
@@ -895,16 +1050,18 @@ int snxo_sweep_angle(snxo_problem *p, const double *phi_in, int n, int g, const 
     if (n < 0 || n >= nang || g < 0 || g >= G) return fail(p, SNXO_E_ARG, "angle or group out of range");
     if (p->refl || p->L) return fail(p, SNXO_E_ARG, "reflective planes and anisotropy couple directions: use snxo_sweep");
     int o = n / per;
+    const int32_t *ord = p->designation == 2 ? p->aord + (long)n * C : p->order + (long)o * C;
     for (long i = 0; i < 8L * C; ++i) psi_out[i] = psi_prev ? psi_prev[i] : 0.0;
     for (int t = 0; t < C; ++t) {
-        int K = p->order[(long)o * C + t];
+        int K = ord[t];
         double qn[8], x[8];
         if (p->ang_src) {
             for (int j = 0; j < 8; ++j) qn[j] = p->ang_src[(((long)K * nang + n) * G + g) * 8 + j];
         } else {
             source_nodal(p, phi_in, NULL, K, g, qn);
         }
-        if (solve_local(p, K, n, g, qn, psi_out, NULL, x, NULL)) return fail(p, SNXO_E_MESH, "singular local system");
+        if (solve_local(p, K, n, g, qn, psi_out, NULL, psi_prev, 8, NULL, x, NULL))
+            return fail(p, SNXO_E_MESH, "singular local system");
         for (int j = 0; j < 8; ++j) psi_out[8L * K + j] = x[j];
     }
     return SNXO_OK;
@@ -930,7 +1087,7 @@ int snxo_solve(snxo_problem *p, double tol, int max_it, const double *phi0,
     /* designation 1 and reflective planes: the angular flux carried between
      * sweeps (previous and next kept apart: a reflective face reads another
      * direction's previous values) */
-    int carry = p->designation == 1 || p->refl || p->L;
+    int carry = p->designation >= 1 || p->refl || p->L;
     double *psi = carry ? calloc(n * (size_t)p->nang, sizeof(double)) : NULL;
     double *psi2 = carry ? calloc(n * (size_t)p->nang, sizeof(double)) : NULL;
     if (!cur || (carry && (!psi || !psi2))) {
@@ -973,7 +1130,7 @@ int snxo_solve_outer(snxo_problem *p, int outer, int inner, double tol, const do
     int C = p->ncell, G = p->G;
     size_t n = 8 * (size_t)C * G;
     double *start = malloc(sizeof(double) * n), *x = malloc(sizeof(double) * n), *qo = calloc(n, sizeof(double));
-    int carry = p->designation == 1 || p->refl || p->L;
+    int carry = p->designation >= 1 || p->refl || p->L;
     double *psi = carry ? calloc(n * (size_t)p->nang, sizeof(double)) : NULL;
     double *psi2 = carry ? calloc(n * (size_t)p->nang, sizeof(double)) : NULL;
     if (!start || !x || !qo || (carry && (!psi || !psi2))) {
@@ -1088,8 +1245,17 @@ int snxo_get_dag(snxo_problem *p, int32_t *inflow, int32_t *level, int32_t *orde
 
 int snxo_get_angle_inflow(snxo_problem *p, int32_t *ain) {
     if (!p || !p->ready) return fail(p, SNXO_E_STATE, "setup has not run");
-    if (p->designation != 1 || !ain) return fail(p, SNXO_E_ARG, "per-angle masks exist under designation 1 only");
+    if (p->designation < 1 || !ain) return fail(p, SNXO_E_ARG, "per-angle masks exist under designations 1 and 2 only");
     memcpy(ain, p->ain, sizeof(int32_t) * (size_t)p->nang * p->ncell);
+    return SNXO_OK;
+}
+
+int snxo_get_angle_order(snxo_problem *p, int32_t *order, int32_t *lag) {
+    if (!p || !p->ready) return fail(p, SNXO_E_STATE, "setup has not run");
+    if (p->designation != 2) return fail(p, SNXO_E_ARG, "per-direction orders exist under designation 2 only");
+    size_t n = (size_t)p->nang * p->ncell;
+    if (order) memcpy(order, p->aord, sizeof(int32_t) * n);
+    if (lag) memcpy(lag, p->alag, sizeof(int32_t) * n);
     return SNXO_OK;
 }
 

@@ -16,8 +16,11 @@
  *   - the sweep: cells visited in a topological order of the upwind
  *     dependency DAG (Section 2.1), octant by octant, angle by angle;
  *   - upwind faces designated once per octant, or per angle (the mesh
- *     traversal of each direction, Section 2.1) with lagged faces where a
- *     direction's own dependencies go against its octant's order;
+ *     traversal of each direction, Section 2.1), either in the octant's order
+ *     with lagged faces where a direction's own dependencies go against it, or
+ *     in each direction's own order with cycles broken deterministically;
+ *   - reflective planes with the octants in sequence (the reason UnSNAP keeps
+ *     them so, Section 2.1) or concurrent;
  *   - source iteration, inner and outer iterations over a group-to-group
  *     scattering matrix (the benchmark of Section 3.6), and the integrated
  *     flux of Eq. 3.
@@ -85,10 +88,21 @@ int  snxo_get_harmonics(snxo_problem *p, double *y);
  * 2*axis + side makes the boundary faces whose outward area vector points
  * along -axis (side 0) or +axis (side 1) reflective.  On such a face the inflow
  * of direction n is the outflow of its mirror image (the direction with that
- * component negated, which the quadrature must hold) at the same nodes, taken
- * from the previous sweep (psi_prev), as on the GPU where octants run
- * concurrently.  snxo_sweep_angle refuses reflective problems. */
+ * component negated, which the quadrature must hold) at the same nodes.  Where
+ * that outflow comes from is set by snxo_set_octant_order.
+ * snxo_sweep_angle refuses reflective problems. */
 int  snxo_set_reflective(snxo_problem *p, int planes);
+/* Octant order of a sweep, for reflective planes (default 0; any time).
+ * 1: the octants are swept in sequence 0..7, as UnSNAP does so that reflective
+ *    faces can use the newest values (Section 2.1 and its footnote): the
+ *    mirrored outflow is the current sweep's when the mirror image's octant
+ *    came earlier in the sequence, else the previous sweep's (psi_prev).  On
+ *    the planes x = 1, y = 1, z = 1 of the unit cube (side 1) every reflected
+ *    inflow is then current.
+ * 0: the octants are concurrent: every mirrored outflow is the previous
+ *    sweep's, as on the GPU.
+ * Both iterations converge to the same reflective solution. */
+int  snxo_set_octant_order(snxo_problem *p, int sequential);
 /* Group-to-group isotropic scattering (after snxo_set_materials; nmat = 0
  * clears it): cell_mat[ncell] material of each cell, sigma_gg[nmat][G][G]
  * with [m][g'][g] the cross section from group g' into group g.  When set, its
@@ -108,7 +122,15 @@ int  snxo_set_hooks(snxo_problem *p, const double *ang_src, const double *bnd_in
  *         inflow face whose neighbour comes later in that order reads the
  *         neighbour's angular flux of the previous sweep (psi_prev), so every
  *         cycle of a direction's own dependency graph is broken at the faces
- *         that go against the octant's order. */
+ *         that go against the octant's order (the GPU's reading).
+ * kind 2: per angle as kind 1, each direction swept in its own topological
+ *         order (the mesh traversal of Section 2.1).  Cycles are broken only
+ *         inside the strongly connected components of the direction's graph:
+ *         there a face whose upwind cell has the larger Omega_n . centroid
+ *         (cell id on a tie) is lagged and reads the neighbour's angular flux
+ *         of the previous sweep (psi_prev).  See snxo_get_angle_order.
+ * All three converge to a solution independent of which faces lag; kinds 1
+ * and 2 to the same one. */
 int  snxo_set_designation(snxo_problem *p, int kind);
 /* Topology, geometry, upwind designation and levelling. */
 int  snxo_setup(snxo_problem *p);
@@ -160,8 +182,12 @@ int  snxo_get_geometry(snxo_problem *p, double *M, double *S, double *F, double 
 /* inflow[8][ncell] bit f set when face f is inflow; level[8][ncell];
  * order[8][ncell] the topological order used by the sweep. */
 int  snxo_get_dag(snxo_problem *p, int32_t *inflow, int32_t *level, int32_t *order);
-/* Designation 1: ain[nang][ncell], bit f set when face f is inflow for angle n. */
+/* Designations 1 and 2: ain[nang][ncell], bit f set when face f is inflow for angle n. */
 int  snxo_get_angle_inflow(snxo_problem *p, int32_t *ain);
+/* Designation 2: order[nang][ncell] each direction's sweep order and
+ * lag[nang][ncell] the inflow faces lagged to break its cycles (bit f);
+ * either may be NULL. */
+int  snxo_get_angle_order(snxo_problem *p, int32_t *order, int32_t *lag);
 const char *snxo_last_error(snxo_problem *p);
 
 #ifdef __cplusplus

@@ -407,6 +407,38 @@ def test_integrated_flux_identical_groups():
     assert 0 < fl[0, 1] < 1.0 / (1.0 * 0.5)
 
 
+@pytest.mark.parametrize("jittered", [False, True])
+def test_integrated_flux_volume_integral_closed_forms(jittered):
+    """The volume column of Eq. 3's integrated flux, 1^T M phi per group, is the
+    integral of the trilinear field phi over the mesh.  It holds exactly under
+    the 2x2x2 rule: 1^T M phi = sum_q detJ phi_h (the basis sums to one), and
+    phi_h detJ has degree at most 3 in each reference coordinate.  A linear
+    function a + b.x is reproduced by its nodal values on any trilinear cell,
+    so the unit cube gives a + b.(1/2, 1/2, 1/2); a constant gives itself.  The
+    plain column is the sum of the nodal values."""
+    m = inputs.make_mesh(4, 0.3 if jittered else 0.0, seed=13)
+    C = m.ncell
+    coefs = np.array([[2.5, 0.0, 0.0, 0.0],       # constant
+                      [0.3, 1.0, -2.0, 0.5],      # linear
+                      [-1.0, 0.25, 3.0, -4.0]])
+    G = len(coefs)
+    o = _oracle_for(m, G=G)
+    X = m.xyz[m.cell_vert]                         # [C][8][3]: node j of cell K is its vertex j
+    phi = coefs[None, :, None, 0] + np.einsum("gd,kjd->kgj", coefs[:, 1:], X)
+    fl = o.integrated_flux(phi)
+    want = coefs[:, 0] + coefs[:, 1:].sum(axis=1) * 0.5
+    assert np.abs(fl[:, 1] - want).max() < 1e-13
+    assert np.abs(fl[:, 0] - phi.sum(axis=(0, 2))).max() < 1e-12 * np.abs(phi).sum()
+    # per cell the column is the cell's volume for phi = 1 (the volumes tile the cube)
+    vol = o.integrated_flux(np.ones((C, G, 8)))[:, 1]
+    assert np.abs(vol - 1.0).max() < 1e-14
+    # a wrong weighting fails: dropping the Jacobian's variation or using a diagonal of M
+    g = o.geometry()
+    lumped = np.einsum("kii,kgi->g", g["M"], phi)
+    if jittered:
+        assert np.abs(lumped - want).max() > 1e-4
+
+
 def test_regression_golden_solution():
     """A tiny converged solve pinned in tests/golden (written by make_golden.py from the oracle)."""
     import os
