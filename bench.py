@@ -7,10 +7,15 @@ all octants, angles and groups, the compensated angle reduction and the FP64
 convergence residual (graph-captured, as snx_solve runs it).  Setup (element
 matrices, designation, levelling) is done once per mesh before timing.
 
-Default workload: 32^3 jittered hex grid (32,768 cells, ids permuted),
-3x4 product quadrature (96 angles), 16 groups, two materials in a seeded
-4^3-block checkerboard (sigma_t 0.5 / 5.0, c 0.3 / 0.9, source 1 / 0),
-per-group cross-section scaling 0.8..1.2, vacuum boundaries.
+Default workload (the largest single-GPU shape): 64^3 jittered hex grid
+(262,144 cells, ids permuted), 4x8 product quadrature (256 angles), 64 groups,
+sigma_t log-uniform in [0.1, 10] and c uniform in [0, 0.95] in 8^3-cell
+blocks, block sources U(0, 1), per-group cross-section scaling 0.8..1.2,
+vacuum boundaries.  The 32^3 / 96-angle / 16-group two-material workload is
+measured beside it (`secondary`), together with per-angle designation, the
+optional physics, the paper's 16^3 shape, second and third order, the AMT/BSP
+grid over angles and groups, the learned start on 200 held-out instances and
+the FP64 oracle on the host cores.
 
 Prints one JSON line (rank 0).  `value` is cell-angle-group solves per second
 over the timed steps with all inputs resident in HBM.
@@ -222,6 +227,47 @@ def extensions(prob, threads: int, wg_per_cu: int, steps: int):
     return out
 
 
+def bsp_grid(n: int = 16, sweeps: int = 10):
+    """AMT over BSP across angle and group counts (the paper's comparison in
+    Section 3.6, its figure of AMT speed-up over BSP): a 16^3 jittered grid
+    (sigma_t 1, c 0.5) swept with the dependency-driven scheme and with the
+    level-synchronous one, each at its best schedule of a small search (AMT:
+    threads 64, 128, 256 x workgroups per CU at occupancy or 2; BSP: threads
+    64, 128, 256); times are the sweep kernel alone (HIP events over `sweeps`
+    sweeps after one untimed sweep)."""
+    import numpy as np
+    import torch
+    from paper_2510_11513_amd import inputs, snx
+    rows = []
+    for npol, naz in ((2, 2), (2, 4), (4, 4), (4, 8)):
+        for G in (4, 8, 16, 32, 64):
+            rng = np.random.default_rng(1000 * n + 10 * npol * naz + G)
+            mesh = inputs.make_mesh(n, 0.2, rng=rng)
+            mat = inputs.materials_uniform(mesh, G, 1.0, 0.5, 1.0, scaled=True)
+            prob = inputs.Problem(f"bsp_n{n}_a{npol * naz}_g{G}", mesh, mat, npol, naz, 1e-6)
+            p = snx.Problem.from_problem(prob)
+            phi = p.sweep(None)
+            torch.cuda.synchronize()
+            best = {snx.SWEEP_AMT: (1e300, None), snx.SWEEP_BSP: (1e300, None)}
+            for mode, wgs in ((snx.SWEEP_AMT, (64, 2)), (snx.SWEEP_BSP, (64,))):
+                p.set_sweep_mode(mode)
+                for th in (64, 128, 256):
+                    if th < G:
+                        continue
+                    for wg in wgs:      # 64: capped by occupancy
+                        p.set_schedule(threads=th, wg_per_cu=wg)
+                        p.sweep(phi)
+                        ms = p.profile_sweep(sweeps, phi_in=phi)
+                        if ms < best[mode][0]:
+                            best[mode] = (ms, (th, wg))
+            p.close()
+            (ms_amt, sched), (ms_bsp, sched_bsp) = best[snx.SWEEP_AMT], best[snx.SWEEP_BSP]
+            rows.append({"angles_per_octant": npol * naz, "groups": G, "amt_ms": round(ms_amt, 4),
+                         "bsp_ms": round(ms_bsp, 4), "bsp_over_amt": round(ms_bsp / ms_amt, 3),
+                         "amt_schedule": list(sched), "bsp_threads": sched_bsp[0]})
+    return {"workload": f"{n}^3 jittered hex, sigma_t 1, c 0.5; angles per octant x groups", "rows": rows}
+
+
 def kernel_hash() -> str:
     path = os.path.join(ROOT, "paper_2510_11513_amd", "csrc", "k_sweep.hip")
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
@@ -240,76 +286,228 @@ def measured_traffic(workload: str):
     return float(t.group(1))
 
 
-def cpu_baseline(prob, groups: int, sweeps: int):
-    """The FP64 oracle (test infrastructure), untuned, on a bounded sample of the same workload."""
-    import numpy as np
+def host_threads() -> int:
+    """Host threads for the oracle: the OpenMP thread count the environment sets, else the CPU count."""
+    return max(1, int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1))
+
+
+def sample_pairs(nang: int, G: int, count: int):
+    """`count` (direction, group) pairs spread over every octant and group, in a fixed order."""
+    per = nang // 8
+    return [((k % 8) * per + (k * 5) % per, (k * 7) % G) for k in range(count)]
+
+
+def oracle_rate(o, pairs, threads: int):
+    """Solves/s of the FP64 oracle sweeping the given (direction, group) pairs
+    from a zero flux, on `threads` host threads (each pair is one whole sweep
+    of the mesh for that direction and group; pairs are independent)."""
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.perf_counter()
+    if threads == 1:
+        for n, g in pairs:
+            o.sweep_angle(None, n, g)
+    else:
+        with ThreadPoolExecutor(threads) as ex:   # ctypes releases the GIL during each sweep
+            list(ex.map(lambda ng: o.sweep_angle(None, ng[0], ng[1]), pairs))
+    dt = time.perf_counter() - t0
+    return len(pairs) * o.ncell / dt, dt
+
+
+def cpu_baseline(prob, budget_s: float = 8.0):
+    """The FP64 oracle (test infrastructure), untuned, on a bounded sample of the
+    same workload: whole-mesh sweeps of sampled (direction, group) pairs, first
+    on one host thread, then on every host thread at once.  Solves/s per
+    sweep extrapolate to the workload's C * A * G solves."""
+    import oracle
+    o = oracle.Oracle.from_problem(prob)
+    C, G, nang = prob.mesh.ncell, prob.mat.ngroup, prob.nang
+    threads = host_threads()
+    per_pair = oracle_rate(o, sample_pairs(nang, G, 1), 1)[1]      # one pair, also a warm-up
+    n1 = max(2, min(64, int(budget_s / max(per_pair, 1e-6))))
+    r1, t1 = oracle_rate(o, sample_pairs(nang, G, n1), 1)
+    nt = max(threads, min(8 * threads, int(budget_s * threads / max(per_pair, 1e-6))))
+    rt, tt = oracle_rate(o, sample_pairs(nang, G, nt), threads)
+    del o
+    solves = C * nang * G
+    return {"value": rt, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nt} whole-mesh FP64 sweeps of sampled (direction, group) pairs of the same problem "
+                      f"({nt * C:.3g} solves, {tt:.2f} s) on {threads} host threads; per sweep of all "
+                      f"{solves:.3g} solves this extrapolates to {solves / rt:.1f} s",
+            "one_thread": {"value": r1, "pairs": n1, "s": round(t1, 3),
+                           "extrapolated_s_per_sweep": round(solves / r1, 1)},
+            "extrapolated_s_per_sweep": round(solves / rt, 2)}
+
+
+def oracle_timings(budget_s: float = 3.0):
+    """The same sampled oracle timing, 1 thread and all threads, on the 8^3,
+    32^3 and the paper's 16^3 workloads."""
     import oracle
     from paper_2510_11513_amd import inputs
-    G = prob.mat.ngroup
-    gs = max(1, min(groups, G))
-    mat = inputs.Materials(prob.mat.sigma_t[:, :gs].copy(), prob.mat.sigma_s[:, :gs].copy(), prob.mat.q[:, :gs].copy())
-    sub = inputs.Problem(prob.name, prob.mesh, mat, prob.npolar, prob.nazim, prob.tol)
-    o = oracle.Oracle.from_problem(sub)
-    phi = np.zeros((prob.mesh.ncell, gs, 8))
-    t0 = time.perf_counter()
-    for _ in range(sweeps):
-        phi = o.sweep(phi)["phi"]
-    dt = time.perf_counter() - t0
-    solves = prob.mesh.ncell * prob.nang * gs * sweeps
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": solves / dt, "unit": "solves/s", "cores": min(threads, gs), "kind": "oracle",
-            "sample": f"{sweeps} FP64 source iteration(s) of the same mesh and quadrature for groups 0..{gs - 1} "
-                      f"of {G} ({solves:.3g} solves, {dt:.2f} s; the oracle runs one OpenMP thread per group)"}
+    threads = host_threads()
+    out = {"threads": threads}
+    for name in ("cfg1", "cfg2", "paper16"):
+        prob = inputs.config_problem(WORKLOADS[name][0])
+        o = oracle.Oracle.from_problem(prob)
+        nang, G = prob.nang, prob.mat.ngroup
+        per_pair = oracle_rate(o, sample_pairs(nang, G, 1), 1)[1]
+        n1 = max(4, min(nang * G, int(budget_s / max(per_pair, 1e-6))))
+        r1, _ = oracle_rate(o, sample_pairs(nang, G, n1), 1)
+        nt = max(threads, min(nang * G, int(budget_s * threads / max(per_pair, 1e-6))))
+        rt, _ = oracle_rate(o, sample_pairs(nang, G, nt), threads)
+        solves = prob.mesh.ncell * nang * G
+        out[name] = {"one_thread_solves_per_s": r1, "all_threads_solves_per_s": rt, "pairs": [n1, nt],
+                     "s_per_sweep_one_thread": round(solves / r1, 3),
+                     "s_per_sweep_all_threads": round(solves / rt, 3)}
+        del o
+    return out
 
 
 def learned_start(count: int):
     """Time to 1e-6 from the trained network's start vs zero start (and the Q/sigma_a control),
-    on the first held-out instances of the high-scattering workload, inference included."""
+    on the first `count` held-out instances of the high-scattering workload, inference included."""
     from paper_2510_11513_amd import learned, snx
     path = os.path.join(ROOT, "paper_2510_11513_amd", "weights", "gnn_l4_h64.bin")
     if not os.path.exists(path):
         return None
     net = snx.Gnn(0, 4)
     net.load_file(path)
-    recs = learned.evaluate(net, list(range(count)), log=None)
+    t0 = time.perf_counter()
+
+    def log(rec):
+        if rec["done"] % 25 == 0 or rec["done"] == count:
+            print(f"[bench] learned start: {rec['done']} of {count} instances", file=sys.stderr, flush=True)
+
+    recs = learned.evaluate(net, list(range(count)), log=log)
+    net.close()
     summ = learned.summarize(recs)
-    ev = os.path.join(ROOT, "paper_2510_11513_amd", "weights", "gnn_l4_h64.eval.json")
-    full = json.load(open(ev))["summary"] if os.path.exists(ev) else None
+    r = lambda k: round(summ[k], 4)
     return {"workload": "32^3 jittered hex, 96 angles, 16 groups, sigma_t log-uniform [0.1, 10] and c in "
                         "[0.9, 0.99] in 4^3 blocks; tol 1e-6", "instances": count,
-            "wall_ratio_learned_over_zero_median": round(summ["b/a_wall_median"], 4),
-            "iter_ratio_learned_over_zero_median": round(summ["b/a_iterations_median"], 4),
-            "wall_ratio_control_over_zero_median": round(summ["c/a_wall_median"], 4),
+            "wall_ratio_learned_over_zero_median": r("b/a_wall_median"),
+            "wall_ratio_learned_over_zero_mean": r("b/a_wall_mean"),
+            "iter_ratio_learned_over_zero_median": r("b/a_iterations_median"),
+            "wall_ratio_control_over_zero_median": r("c/a_wall_median"),
+            "iter_ratio_control_over_zero_median": r("c/a_iterations_median"),
+            "zero_start_iterations_median": summ["a_iterations_median"],
             "zero_start_ms_median": round(summ["a_wall_ms_median"], 2),
-            "learned_vs_zero_max_rel_diff": summ["b_vs_a_max"],
-            "heldout_200_recorded": None if full is None else {
-                k: round(full[k], 4) for k in ("b/a_wall_median", "b/a_wall_mean", "b/a_iterations_median",
-                                               "c/a_wall_median")}}
+            "learned_ms_median": round(float(sorted(x["b_ms"] for x in recs)[len(recs) // 2]), 2),
+            "predict_ms_median": round(float(sorted(x["predict_ms"] for x in recs)[len(recs) // 2]), 3),
+            "learned_vs_zero_max_rel_diff": summ["b_vs_a_max"], "control_vs_zero_max_rel_diff": summ["c_vs_a_max"],
+            "s": round(time.perf_counter() - t0, 1)}
+
+
+def phase_stats(p):
+    """One sweep with the per-phase shader-clock statistics on: where a
+    workgroup's cycles go (queue wait, staging, operator build, solve,
+    publish), and the queue polls that found no ready task."""
+    p.set_sweep_stats(True)
+    p.sweep(p.empty_phi())
+    st = p.sweep_stats()
+    p.set_sweep_stats(False)
+    tot = max(1, sum(st["cycles"].values()))
+    return {"tasks": st["tasks"], "continued": st["continued"], "empty_polls": st["empty_polls"],
+            "cycle_share": {k: round(v / tot, 4) for k, v in st["cycles"].items()},
+            "cycles_per_task": round(tot / max(1, st["tasks"]), 1)}
+
+
+def measure_sweep(p, prob, sweeps: int):
+    """Sweep-kernel duration (HIP events on the library's stream), the HBM and
+    VALU rooflines, and the bulk-synchronous comparator in the same schedule."""
+    from paper_2510_11513_amd import snx
+    C, G, nang = prob.mesh.ncell, prob.mat.ngroup, prob.nang
+    phi = p.sweep(None)
+    ms_sweep = p.profile_sweep(sweeps, phi_in=phi)
+    stats = p.sweep_stats()
+    solves = C * nang * G
+    bpt = bytes_per_task(prob.mesh.n, nang, nang // 8, G)
+    achieved = bpt * solves / (ms_sweep * 1e-3) / 1e9
+    tuned_mode = p.schedule()["mode"]
+    p.set_sweep_mode(snx.SWEEP_BSP)
+    ms_bsp = p.profile_sweep(sweeps, phi_in=phi)
+    p.set_sweep_mode(snx.SWEEP_AMT)
+    ms_amt = p.profile_sweep(sweeps, phi_in=phi) if tuned_mode == snx.SWEEP_BSP else ms_sweep
+    p.set_sweep_mode(tuned_mode)
+    fpt = flops_per_task(G)
+    tflops = fpt * solves / (ms_sweep * 1e-3) / 1e12
+    return ms_sweep, stats, {
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": "k_sweep", "kernel_ms": round(ms_sweep, 4),
+                     "bytes_per_solve": round(bpt, 2), "solves_per_launch": solves},
+        "bsp_comparator": {"sweep_ms": round(ms_bsp, 4), "amt_sweep_ms": round(ms_amt, 4),
+                           "bsp_over_amt": round(ms_bsp / ms_amt, 3)},
+        "valu": {"achieved": round(tflops, 2), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": round(tflops / FP32_VALU_PEAK_TFLOPS, 4), "flops_per_solve": round(fpt, 1)}}
+
+
+def secondary(name: str, tune_cache: str, args):
+    """The 32^3 workload beside the headline: sweep kernel, rooflines, BSP
+    comparator, phase statistics, one graph-captured source iteration,
+    per-angle designation and the optional physics."""
+    import torch
+    from paper_2510_11513_amd import inputs, snx
+    cfg, desc = WORKLOADS[name]
+    prob = inputs.config_problem(cfg)
+    p = snx.Problem.from_problem(prob)
+    tuned = p.tune(tune_cache)
+    sweeps = 20
+    ms_sweep, stats, meas = measure_sweep(p, prob, sweeps)
+    phi = p.empty_phi()
+    p.set_schedule(chunk=sweeps)
+    p.solve(0.0, sweeps, phi=phi, allow_noconv=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.solve(0.0, sweeps, phi=phi, allow_noconv=True)
+    torch.cuda.synchronize()
+    ms_it = (time.perf_counter() - t0) / sweeps * 1e3
+    solves = prob.mesh.ncell * prob.nang * prob.mat.ngroup
+    out = {"workload": f"{name}: {desc}", "solves_per_step": solves, "ms_per_iteration": round(ms_it, 4),
+           "solves_per_s": solves / (ms_it * 1e-3), "sweep_threads": stats["threads"],
+           "sweep_wg_per_cu_cap": tuned[1],
+           "sweep_mode": "bsp" if p.schedule()["mode"] == snx.SWEEP_BSP else "amt", **meas,
+           "phases": phase_stats(p)}
+    out["roofline"]["traffic"] = measured_traffic(name)
+    if args.per_angle:
+        print("[bench] per-angle designation", file=sys.stderr, flush=True)
+        _, info_oct = p.solve(prob.tol, 5000)
+        out["per_angle"] = per_angle(prob, stats["threads"], tuned[1], ms_sweep, info_oct["iterations"], sweeps)
+    p.close()
+    if args.extensions:
+        print("[bench] optional physics", file=sys.stderr, flush=True)
+        out["extensions"] = extensions(prob, stats["threads"], tuned[1], 10)
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="cfg3", choices=sorted(WORKLOADS))
+    ap.add_argument("--secondary", default="cfg2", choices=sorted(WORKLOADS) + ["none"],
+                    help="workload measured beside the headline (per-angle designation and optional physics run "
+                         "on it)")
     ap.add_argument("--threads", type=int, default=0, help="sweep workgroup size (0 = library default)")
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--no-tune", action="store_true", help="skip the schedule autotuner (library default schedule)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2510_11513_amd", "tuning", "mi355x.jsonl"),
                     help="autotuner cache (JSON lines); a hit reuses the recorded schedule without timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-groups", type=int, default=16)
-    ap.add_argument("--cpu-sweeps", type=int, default=4)
-    ap.add_argument("--learned", type=int, default=4,
+    ap.add_argument("--cpu-budget", type=float, default=8.0,
+                    help="seconds of oracle work per thread count in the CPU baseline")
+    ap.add_argument("--oracle-timings", type=int, default=1,
+                    help="also time the oracle at 1 and all threads on the 8^3, 32^3 and 16^3 workloads (0 = skip)")
+    ap.add_argument("--learned", type=int, default=200,
                     help="held-out high-scattering instances for the learned-start comparison (0 = skip)")
     ap.add_argument("--paper-shape", type=int, default=1, help="also time the paper's 25-sweep 16^3 shape (0 = skip)")
     ap.add_argument("--per-angle", type=int, default=1,
-                    help="also time the workload under per-angle designation (0 = skip)")
+                    help="also time the secondary workload under per-angle designation (0 = skip)")
     ap.add_argument("--higher-order", type=int, default=1,
                     help="also time second and third order on the paper's 16^3 shape (0 = skip)")
     ap.add_argument("--extensions", type=int, default=1,
-                    help="also time reflective planes, anisotropy and group coupling on the workload (0 = skip)")
+                    help="also time reflective planes, anisotropy and group coupling on the secondary workload "
+                         "(0 = skip)")
+    ap.add_argument("--bsp-grid", type=int, default=1,
+                    help="also compare AMT and BSP over angles and groups on a 16^3 grid (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -319,7 +517,6 @@ def main():
               "(sharding is described in the design notes); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_2510_11513_amd import inputs, snx
 
@@ -367,16 +564,8 @@ def main():
           flush=True)
 
     # live duration of the dominant kernel (the sweep) from HIP events on its stream
-    ms_sweep = p.profile_sweep(max(5, min(args.steps, 20)), phi_in=phi)
-    stats = p.sweep_stats()
-    bpt = bytes_per_task(prob.mesh.n, nang, nang // 8, G)
-    bytes_launch = bpt * solves_per_step
-    achieved = bytes_launch / (ms_sweep * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_sweep", "kernel_ms": round(ms_sweep, 4), "bytes_per_solve": round(bpt, 2),
-                "solves_per_launch": solves_per_step}
+    ms_sweep, stats, meas = measure_sweep(p, prob, max(5, min(args.steps, 20)))
+    meas["roofline"]["traffic"] = measured_traffic(args.workload)
     out = {"metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -384,41 +573,31 @@ def main():
                       "solves_per_step": solves_per_step, "sweep_grid": stats["grid"],
                       "sweep_threads": stats["threads"], "sweep_wg_per_cu_cap": tuned[1] if tuned else None,
                       "sweep_mode": "bsp" if p.schedule()["mode"] == snx.SWEEP_BSP else "amt",
-                      "continued_tasks": stats["continued"],
-                      "setup_s": round(t_setup, 3)},
-           "roofline": roofline}
-    # the paper's comparison: the same sweep level by level (bulk-synchronous), same task code
-    tuned_mode = p.schedule()["mode"]
-    p.set_sweep_mode(snx.SWEEP_BSP)
-    ms_bsp = p.profile_sweep(max(5, min(args.steps, 20)), phi_in=phi)
-    p.set_sweep_mode(snx.SWEEP_AMT)
-    ms_amt = p.profile_sweep(max(5, min(args.steps, 20)), phi_in=phi) if tuned_mode == snx.SWEEP_BSP else ms_sweep
-    p.set_sweep_mode(tuned_mode)
-    out["bsp_comparator"] = {"sweep_ms": round(ms_bsp, 4), "amt_sweep_ms": round(ms_amt, 4),
-                             "bsp_over_amt": round(ms_bsp / ms_amt, 3)}
-    # the other candidate bound: algorithmic FP32 arithmetic over the same kernel time
-    fpt = flops_per_task(G)
-    tflops = fpt * solves_per_step / (ms_sweep * 1e-3) / 1e12
-    out["valu"] = {"achieved": round(tflops, 2), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                   "frac": round(tflops / FP32_VALU_PEAK_TFLOPS, 4), "flops_per_solve": round(fpt, 1)}
-    if args.per_angle:
-        print("[bench] per-angle designation", file=sys.stderr, flush=True)
-        _, info_oct = p.solve(prob.tol, 5000)
-        out["per_angle"] = per_angle(prob, stats["threads"], tuned[1] if tuned else args.wg_per_cu, ms_sweep,
-                                     info_oct["iterations"], max(5, min(args.steps, 20)))
-    if args.extensions:
-        print("[bench] optional physics", file=sys.stderr, flush=True)
-        out["extensions"] = extensions(prob, stats["threads"], tuned[1] if tuned else args.wg_per_cu, 10)
+                      "continued_tasks": stats["continued"], "setup_s": round(t_setup, 3)},
+           "roofline": meas.pop("roofline"), **meas}
+    out["phases"] = phase_stats(p)
+    p.close()
+    del phi
+    torch.cuda.empty_cache()
+    if args.secondary != "none" and args.secondary != args.workload:
+        print(f"[bench] secondary workload {args.secondary}", file=sys.stderr, flush=True)
+        out["secondary"] = secondary(args.secondary, args.tune_cache, args)
     if args.paper_shape:
+        print("[bench] paper shape", file=sys.stderr, flush=True)
         out["paper_shape"] = paper_shape()
     if args.higher_order:
         out["higher_order"] = higher_order()
+    if args.bsp_grid:
+        print("[bench] AMT/BSP grid", file=sys.stderr, flush=True)
+        out["bsp_grid"] = bsp_grid()
     if args.learned > 0:
         print("[bench] learned vs zero start", file=sys.stderr, flush=True)
         out["learned"] = learned_start(args.learned)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_groups, args.cpu_sweeps)
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_budget)
+        if args.oracle_timings:
+            out["oracle_timings"] = oracle_timings()
     print(json.dumps(out), flush=True)
 
 

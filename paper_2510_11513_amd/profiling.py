@@ -2,11 +2,16 @@
 
     python -m paper_2510_11513_amd.profiling stats <run_results.db> <out.md> "<command>"
     python -m paper_2510_11513_amd.profiling pmc <fetch.db> <write.db> <out.md> "<fetch command>" "<write command>"
+    python -m paper_2510_11513_amd.profiling sq <sq.db> <out.md> "<command>" <tasks per sweep> <solves per sweep> \
+        [<bench JSON line file>]
 
 `stats` lists every kernel's dispatch count and duration.  `pmc` scales the
 FETCH_SIZE and WRITE_SIZE counters (KiB per dispatch) of the sweep kernel by
 what the same counters read for a plain 1 GiB device copy recorded in the same
-run, giving HBM bytes per sweep launch.
+run, giving HBM bytes per sweep launch.  `sq` summarises the shader
+sequencer counters of the default sweep kernel (waves, instruction mix, wave
+cycles, dependency waits) per task and per 64 solves, and, given the
+benchmark's JSON line, the in-kernel phase statistics of the same workload.
 """
 from __future__ import annotations
 
@@ -62,8 +67,9 @@ def _counter(db: str, counter: str):
 def pmc_summary(fetch_db: str, write_db: str, out_path: str, fetch_cmd: str, write_cmd: str) -> str:
     fetch, write = _counter(fetch_db, "FETCH_SIZE"), _counter(write_db, "WRITE_SIZE")
 
-    def copy_value(d):   # the plain 1 GiB copy is the largest dispatch of the runtime's copy kernel
-        return max(max(v) for k, v in d.items() if "copyBuffer" in k or "copy" in k.lower())
+    def copy_value(d):   # the plain 1 GiB copy is the largest dispatch of the runtime's copy kernel (the
+        #                   library's own copy kernels do not count)
+        return max(max(v) for k, v in d.items() if "rocclr_copyBuffer" in k)
 
     def sweep_values(d):   # default dependency-driven sweeps that did work (not the per-level comparator
         #                     nor the variant for the optional physics)
@@ -93,8 +99,63 @@ def pmc_summary(fetch_db: str, write_db: str, out_path: str, fetch_cmd: str, wri
     return text
 
 
+SQ_COUNTERS = ("SQ_WAVES", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU",
+               "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_WAIT_INST_ANY", "GRBM_GUI_ACTIVE")
+
+
+def sq_summary(db: str, out_path: str, command: str, tasks: int, solves: int, bench_json: str | None = None,
+               simds: int = 1024, xcds: int = 8) -> str:
+    vals = {}
+    for c in SQ_COUNTERS:
+        d = _counter(db, c)
+        v = [x for k, xs in d.items() if re.search(r"k_sweep<\d+, (true|false), false, false>", k) for x in xs]
+        vals[c] = sum(v) / len(v) if v else float("nan")
+        n = len(v)
+    rounds = solves / 64.0
+    gui_xcd = vals["GRBM_GUI_ACTIVE"] / xcds
+    lines = ["# Shader sequencer counters of the sweep kernel (rocprofv3)", "", f"command: `{command}`", "",
+             f"Mean per dispatch of the dependency-driven sweep kernel over {n} dispatches; {tasks} (cell, octant) "
+             f"tasks and {solves} solves per dispatch.", "",
+             "| counter | per dispatch | per task | per 64 solves |", "|---|---|---|---|"]
+    for c in SQ_COUNTERS:
+        lines.append(f"| {c} | {vals[c]:.4e} | {vals[c] / tasks:.1f} | {vals[c] / rounds:.2f} |")
+    lines += ["", "Derived (formulas stated; GRBM_GUI_ACTIVE is read as the sum over the XCDs):", "",
+              f"- resident waves: SQ_WAVES = {vals['SQ_WAVES']:.0f} = {vals['SQ_WAVES'] / (simds // 4):.1f} per CU "
+              f"(persistent launch: every wave stays for the whole sweep)",
+              f"- VALU issue share: 4 * SQ_ACTIVE_INST_VALU / (SIMDs * GRBM_GUI_ACTIVE / XCDs) = "
+              f"{4 * vals['SQ_ACTIVE_INST_VALU'] / (simds * gui_xcd):.2f}",
+              f"- share of wave cycles waiting on a dependency (s_waitcnt): SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES = "
+              f"{vals['SQ_WAIT_INST_ANY'] / vals['SQ_WAVE_CYCLES']:.3f}",
+              f"- instruction mix per 64 solves: VALU {vals['SQ_INSTS_VALU'] / rounds:.0f}, SALU "
+              f"{vals['SQ_INSTS_SALU'] / rounds:.0f}, LDS {vals['SQ_INSTS_LDS'] / rounds:.0f}"]
+    if bench_json:
+        import json
+        rec = json.loads(open(bench_json).read().strip().splitlines()[-1])
+        lines += ["", "In-kernel phase statistics (`snx_set_sweep_stats`, one sweep, shader-clock cycles summed over "
+                  "workgroups) of the same code, from the `phases` objects of `python3 bench.py --gpus 1 --steps 20 "
+                  "--warmup 5`:", "",
+                  "| workload | tasks | continued by the same workgroup | empty queue polls | cycles per task | "
+                  "queue wait | stage | operator build | solve | publish |", "|---|---|---|---|---|---|---|---|---|---|"]
+        for name, r in (("headline", rec), ("secondary", rec.get("secondary", {}))):
+            ph = r.get("phases")
+            if not ph:
+                continue
+            wl = (r["config"]["workload"] if name == "headline" else r["workload"]).split(":")[0]
+            cs = ph["cycle_share"]
+            lines.append(f"| {wl} | {ph['tasks']} | {ph['continued']} | {ph['empty_polls']} | "
+                         f"{ph['cycles_per_task']:.0f} | {cs['queue_wait']:.3f} | {cs['stage']:.3f} | "
+                         f"{cs['build']:.3f} | {cs['solve']:.3f} | {cs['publish']:.3f} |")
+    text = "\n".join(lines) + "\n"
+    with open(out_path, "w") as fh:
+        fh.write(text)
+    return text
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         print(stats_summary(sys.argv[2], sys.argv[3], sys.argv[4]))
     elif sys.argv[1] == "pmc":
         print(pmc_summary(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6]))
+    elif sys.argv[1] == "sq":
+        print(sq_summary(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), int(sys.argv[6]),
+                         sys.argv[7] if len(sys.argv) > 7 else None))
