@@ -243,6 +243,18 @@ snx_status snx_balance(snx_problem *p, const float *phi_in, const float *phi_out
  * cells and dofs, volume integral 1^T M phi).  Synchronous. */
 snx_status snx_integrated_flux(snx_problem *p, const float *phi, double *out, void *stream);
 
+/* As snx_integrated_flux, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels, with the per-block partial sums in a fixed
+ * 8 MiB device array that the library holds on each device from the first
+ * snx_create on it until the process ends.  The call allocates nothing.
+ * Limit: (ceil(ncell * G / 256) + 1) * G * 4 <= 2^20 (e.g. 32^3 cells with 16
+ * groups); larger problems get SNX_E_ARG.  Every call on one device shares
+ * that array and leaves its last contents there (each call writes every
+ * entry it reads), so calls that overlap on one device, from several threads
+ * or streams, race.  Synchronous; host out[G][2] as snx_integrated_flux. */
+snx_status snx_integrated_flux_noalloc(snx_problem *p, const float *phi, double *out, void *stream);
+
 /* Level structure from setup: host level[8][ncell] (t-level of each cell per
  * octant) and host nlevels[8]; either may be NULL.  Synchronous. */
 snx_status snx_get_levels(snx_problem *p, int32_t *level, int32_t *nlevels);

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -18,9 +19,35 @@
 
 using namespace snx;
 
+// Fixed device scratch of the entry points that allocate nothing
+// (snx_integrated_flux_noalloc): every device the library runs on holds its
+// own copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, not a device address: kernels and copies get the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchDoubles = size_t(1) << 20;   // 8 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
 namespace {
 
 thread_local std::string g_create_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_addr[kMaxDevices] = {};
+
+// This device's copy of `scratch`, looked up once per device with the device current.
+hipError_t scratch_address(int device, double **addr) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!g_scratch_addr[device]) {
+        void *a = nullptr;
+        hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[device] = static_cast<double *>(a);
+    }
+    *addr = g_scratch_addr[device];
+    return hipSuccess;
+}
 
 struct DevAlloc {
     std::vector<void *> ptrs;
@@ -104,7 +131,8 @@ struct Sched {
 struct snx_problem {
     int device = 0;
     std::string err;
-    void *pinned = nullptr;            // host staging for small read-backs
+    void *pinned = nullptr;            // host staging for small read-backs (4096 bytes)
+    double *scratch = nullptr;         // device address of this device's fixed scratch
 
     // host inputs
     int C = 0, nvert = 0, nang = 0, A = 0, G = 0, bkind = 0;
@@ -793,8 +821,10 @@ snx_status snx_create(snx_problem **out, int32_t device) {
     p->device = device;
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = hipHostMalloc(&p->pinned, 4096, hipHostMallocDefault);
+    if (e == hipSuccess) e = scratch_address(device, &p->scratch);
     if (e != hipSuccess) {
         g_create_error = std::string("HIP initialisation failed: ") + hipGetErrorString(e);
+        if (p->pinned) (void)hipHostFree(p->pinned);
         delete p;
         return SNX_E_DEVICE;
     }
@@ -1492,6 +1522,30 @@ snx_status snx_integrated_flux(snx_problem *p, const float *phi, double *out, vo
     HIPCHK(p, hipMemcpyAsync(tmp.data(), p->d_out4, sizeof(double) * 4 * p->G, hipMemcpyDeviceToHost, s), "copy");
     HIPCHK(p, hipStreamSynchronize(s), "integrated flux");
     for (int g = 0; g < p->G; ++g) { out[2 * g] = tmp[4 * g]; out[2 * g + 1] = tmp[4 * g + 1]; }
+    return SNX_OK;
+}
+
+snx_status snx_integrated_flux_noalloc(snx_problem *p, const float *phi, double *out, void *stream) {
+    if (!p) return SNX_E_ARG;
+    if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
+    if (p->order > 1) return fail(p, SNX_E_ARG, "snx_integrated_flux_noalloc is not available at order > 1");
+    if (!phi || !out) return fail(p, SNX_E_ARG, "phi and out are required");
+    // the same kernels as snx_integrated_flux: per-block partial[nblk][G][4], then out4[G][4]
+    const size_t nblk = partial_blocks(p->C, p->G);
+    const size_t need = (nblk + 1) * (size_t)p->G * 4;
+    if (need > kScratchDoubles)
+        return fail(p, SNX_E_ARG, "ncell * G is too large for the fixed scratch of snx_integrated_flux_noalloc "
+                                  "((ceil(ncell * G / 256) + 1) * G * 4 doubles must fit in 2^20)");
+    if (!p->scratch) return fail(p, SNX_E_STATE, "no fixed scratch on this device");
+    HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    double *partial = p->scratch, *out4 = p->scratch + nblk * (size_t)p->G * 4;
+    HIPCHK(p, launch_integrated_flux(p->hp.M, phi, p->C, p->G, partial, out4, s), "integrated flux");
+    // columns 0 and 1 of out4 into the pinned staging (G <= 256: at most 4096 bytes), then to out
+    HIPCHK(p, hipMemcpy2DAsync(p->pinned, 2 * sizeof(double), out4, 4 * sizeof(double), 2 * sizeof(double),
+                               (size_t)p->G, hipMemcpyDeviceToHost, s), "copy");
+    HIPCHK(p, hipStreamSynchronize(s), "integrated flux");
+    std::memcpy(out, p->pinned, sizeof(double) * 2 * p->G);
     return SNX_OK;
 }
 

@@ -33,7 +33,8 @@ EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_s
            "snx_gnn_train_step", "snx_gnn_predict", "snx_set_sweep_mode", "snx_batch_set_sweep_mode",
            "snx_get_psi", "snx_set_sweep_stats", "snx_batch_set_sweep_stats", "snx_set_designation",
            "snx_designation_stats", "snx_set_group_scattering", "snx_solve_outer", "snx_set_reflective",
-           "snx_set_anisotropy", "snx_get_schedule", "snx_batch_solve_outer", "snx_set_order", "snx_get_order"]
+           "snx_set_anisotropy", "snx_get_schedule", "snx_batch_solve_outer", "snx_set_order", "snx_get_order",
+           "snx_integrated_flux_noalloc"]
 _NO_STATUS = ("snx_destroy", "snx_last_error", "snx_batch_destroy", "snx_batch_last_error", "snx_gnn_destroy",
               "snx_gnn_last_error")
 
@@ -81,6 +82,7 @@ def load(path: str = LIB_PATH):
     L.snx_solve.argtypes = [_vp, ct.c_double, ct.c_int32, _vp, _vp, ct.POINTER(SolveInfo), _vp]
     L.snx_balance.argtypes = [_vp, _vp, _vp, _dp, _vp]
     L.snx_integrated_flux.argtypes = [_vp, _vp, _dp, _vp]
+    L.snx_integrated_flux_noalloc.argtypes = [_vp, _vp, _dp, _vp]
     L.snx_get_levels.argtypes = [_vp, _vp, _vp]
     L.snx_get_psi.argtypes = [_vp, ct.c_int32, ct.c_int32, _vp, _vp]
     L.snx_set_designation.argtypes = [_vp, ct.c_int32]
@@ -344,6 +346,13 @@ class Problem:
     def integrated_flux(self, phi, stream=None):
         out = np.zeros((self.G, 2))
         self._check(load().snx_integrated_flux(self.h, _ptr(phi), out, _stream(stream)), "integrated_flux")
+        return out
+
+    def integrated_flux_noalloc(self, phi, stream=None):
+        """As integrated_flux, through the library's fixed device scratch (allocates nothing)."""
+        out = np.zeros((self.G, 2))
+        self._check(load().snx_integrated_flux_noalloc(self.h, _ptr(phi), out, _stream(stream)),
+                    "integrated_flux_noalloc")
         return out
 
     def levels(self):
