@@ -14,6 +14,14 @@ pytestmark = pytest.mark.gpu
 
 WEIGHTS = os.path.join(os.path.dirname(__file__), "..", "paper_2510_11513_amd", "weights", "gnn_l4_h64.bin")
 
+# Unit roundoff of bfloat16 (8 significant bits).  The reference rounds the layer
+# weights to bfloat16 as the GPU does, but keeps activations in FP64; the GPU
+# rounds the activations entering each of the four hidden-layer products, so
+# to first order the forward output moves by at most about 4u of its largest
+# value, and a gradient, which also rounds the backward products' inputs, by
+# about 8u of its block's largest entry.  Both are checked element by element.
+U_BF16 = 2.0 ** -8
+
 
 def _problem(n=6, index=0):
     return inputs.config_problem(5, index, scaled=True, n=n)
@@ -71,7 +79,8 @@ def test_forward_matches_fp64_reference_within_bf16_tolerance():
     xr, nbr_r, _ = _reference_inputs(pr)
     zr, _ = ref.forward(_quantised(theta), xr, nbr_r)
     err = np.abs(z - zr).max() / np.abs(zr).max()
-    assert err <= 2e-2, err
+    print(f"[case] forward: max |z - z_ref| / max |z_ref| = {err:.2e} (bound {4 * U_BF16:.2e})", flush=True)
+    assert err <= 4 * U_BF16, err
     # the prediction is the forward pass mapped to a flux on every dof
     phi0 = net.predict(p).cpu().numpy()
     want = np.maximum(np.exp(z.astype(np.float64)) - ref.DELTA, 0.0)
@@ -102,8 +111,9 @@ def test_gradient_matches_fp64_reference_within_bf16_tolerance(n, G):
         k = int(np.prod(shp))
         g, gr = grad[i:i + k].astype(np.float64), grad_r[i:i + k]
         i += k
-        err = np.linalg.norm(g - gr) / max(np.linalg.norm(gr), 1e-30)
-        assert err <= 3e-2, (name, err)
+        err = np.abs(g - gr).max() / max(np.abs(gr).max(), 1e-30)
+        print(f"[case] gradient {name}: max |g - g_ref| / max |g_ref| = {err:.2e}", flush=True)
+        assert err <= 8 * U_BF16, (name, err)
     assert np.array_equal(net.grad(x, nbr, y)[1], grad)         # fixed-order reductions: repeatable bits
 
 

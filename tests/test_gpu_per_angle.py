@@ -168,6 +168,28 @@ def test_solve_converges_to_the_oracle_solution():
     p.close()
 
 
+@pytest.mark.parametrize("seed,kind", [(6, 1), (7, 0)])
+def test_solve_converges_to_the_per_direction_order_oracle(seed, kind):
+    """The paper's traversal: each direction sweeps the mesh in its own upwind
+    order, lagging only faces that close a cycle (oracle designation 2).  The
+    GPU keeps the octant's order and lags every face that goes against it; both
+    iterations have the per-direction upwind solution as their fixed point."""
+    prob = _problem(4, 3, 2, 3, seed=seed, kind=kind, mesh_seed=0)
+    p = _gpu(prob)
+    # a fixed count: c <= 0.9 contracts the error below FP32 round-off long before
+    # (a relative change of 1e-7 is itself at FP32 resolution)
+    phi, info = p.solve(0.0, 400, allow_noconv=True)
+    assert info["iterations"] == 400, info
+    o = oracle.Oracle.from_problem(prob, designation=2)
+    assert o.angle_order()[1].any()                 # this mesh has faces that close cycles
+    ref = o.solve(1e-12, 5000)
+    err = H.rel_err_per_group(phi.cpu().numpy().astype(np.float64), ref["phi"])
+    print(f"[case] per-direction order oracle: iterations gpu {info['iterations']} oracle {ref['iters']}, "
+          f"rel err {err.max():.2e}", flush=True)
+    assert err.max() <= TOL, err
+    p.close()
+
+
 def test_batch_with_mixed_designations():
     torch = _torch()
     from paper_2510_11513_amd import snx

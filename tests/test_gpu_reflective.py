@@ -131,6 +131,28 @@ def test_converged_solution_and_balance():
     p.close()
 
 
+@pytest.mark.parametrize("planes", [0b101010, 0b000111])
+def test_converged_solution_matches_the_oracle_with_octants_in_sequence(planes):
+    """The paper's order: octants in sequence, reflected inflow from the current
+    sweep where the mirrored octant came earlier (Section 2.1 and its footnote).
+    The GPU runs the octants concurrently with every reflected inflow lagged a
+    sweep; both iterations have the same fixed point."""
+    prob = _problem(4, 3, 2, 2, seed=16, c=(0.2, 0.6))
+    p, _ = _pair(prob, planes)
+    phi, info = p.solve(1e-6, 3000)
+    assert info["status"] == 0, info
+    o = oracle.Oracle.from_problem(prob, setup=False)
+    o.set_reflective(planes)
+    o.set_octant_order(True)
+    o.setup()
+    ref = o.solve(1e-12, 5000)
+    err = H.rel_err_per_group(phi.cpu().numpy().astype(np.float64), ref["phi"])
+    print(f"[case] reflective planes {planes:06b}, oracle octants in sequence: iterations gpu "
+          f"{info['iterations']} oracle {ref['iters']}, rel err {err.max():.2e}", flush=True)
+    assert err.max() <= TOL, err
+    p.close()
+
+
 def test_per_angle_designation_with_group_coupling_and_reflection():
     prob = _problem(4, 5, 2, 3, seed=9, kind=1, jitter=0.3)
     p, o = _pair(prob, 0b001001, designation=1, groups=True)
