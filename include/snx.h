@@ -166,7 +166,7 @@ snx_status snx_set_group_scattering(snx_problem *p, int32_t nmat, const int32_t 
  * and these are refused with SNX_E_ARG: per-angle
  * designation, reflective planes, anisotropic and group-to-group scattering
  * (at snx_setup), snx_solve_outer, snx_balance, snx_integrated_flux,
- * snx_get_psi, snx_tune, batches and the learned initial guess.
+ * snx_tune, batches and the learned initial guess.
  * Errors: SNX_E_ARG for an order outside 1..3. */
 snx_status snx_set_order(snx_problem *p, int32_t order);
 /* The order and the nodes per cell, N = (order+1)^3 (either pointer may be NULL). */
@@ -269,7 +269,8 @@ snx_status snx_designation_stats(snx_problem *p, int64_t *out);
 
 /* The angular flux psi (Eq. 1) of one direction and group from the most recent
  * sweep of this problem (alone or in a batch): device out[ncell][8] (FP32, the
- * caller's cell order; the direction index is the one of snx_set_quadrature).
+ * caller's cell order; the direction index is the one of snx_set_quadrature);
+ * at order p > 1, out[ncell][(p+1)^3] in the node order of snx_set_order.
  * Before any sweep the values are unspecified.  SNX_E_ARG for an angle or
  * group out of range.  Asynchronous on `stream`. */
 snx_status snx_get_psi(snx_problem *p, int32_t angle, int32_t group, float *out, void *stream);

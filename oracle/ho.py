@@ -272,52 +272,15 @@ class HOOracle:
         nodes; bnd: optional [C, 6, nang, G, nf] inflow values at the face
         nodes of boundary faces (instead of psi_b).  Returns a dict with phi
         [C, G, N], and psi [nang, C, G, N] and leak [C, G] on request."""
-        C, G, N, nf = self.C, self.G, self.N, self.nf
+        C, G, N = self.C, self.G, self.N
         qn = self.source_nodal(phi_in)
-        per = self.nang // 8
         psi = np.zeros((self.nang, C, G, N))
         phi = np.zeros((C, G, N))
         leak = np.zeros((C, G)) if want_leak else None
         for n in range(self.nang):
-            o = n // per
-            om = self.omega[n]
-            for K in self.order[o]:
-                mask = self.inflow[o, K]
-                A0 = np.einsum("a,aij->ij", om, self.S[K])
-                A = A0[None, :, :] + self.st[K][:, None, None] * self.M[K][None, :, :]
-                src = qn[K] if ang_src is None else qn[K] + ang_src[n, K]
-                b = src @ self.M[K].T                                  # [G, N]: M q
-                ups = {}
-                for f in range(6):
-                    if not (mask >> f) & 1:
-                        continue
-                    fn = self.face_nodes[f]
-                    of = np.einsum("a,akl->kl", om, self.F[K, f])
-                    Nb = self.nbr[K, f]
-                    if Nb >= 0:
-                        up = psi[n, Nb][:, self.perm[K, f]]             # [G, nf]
-                    elif bnd is not None:
-                        up = bnd[K, f, n]
-                    elif self.psi_b is not None:
-                        up = np.repeat(self.psi_b[:, None], nf, axis=1)
-                    else:
-                        up = np.zeros((G, nf))
-                    ups[f] = (of, up)
-                    A[:, fn[:, None], fn[None, :]] -= of[None, :, :]
-                    b[:, fn] -= up @ of.T
-                x = np.linalg.solve(A, b[:, :, None])[:, :, 0]
-                psi[n, K] = x
-                if want_leak:
-                    lk = np.zeros(G)
-                    for f in range(6):
-                        fn = self.face_nodes[f]
-                        if f in ups:
-                            of, up = ups[f]
-                            lk += (up @ of.T).sum(axis=1)
-                        else:
-                            of = np.einsum("a,akl->kl", om, self.F[K, f])
-                            lk += (x[:, fn] @ of.T).sum(axis=1)
-                    leak[K] += self.w[n] * lk
+            lk = self._sweep_direction(n, qn, psi[n], None if ang_src is None else ang_src[n], bnd, want_leak)
+            if want_leak:
+                leak += self.w[n] * lk
             phi += self.w[n] * psi[n]
         out = {"phi": phi}
         if want_psi:
@@ -325,6 +288,62 @@ class HOOracle:
         if want_leak:
             out["leak"] = leak
         return out
+
+    def sweep_angle(self, phi_in, n):
+        """psi [C, G, N] of direction n alone: for a given phi_in the directions
+        of one source iteration are independent, so this is the direction-n
+        pass of sweep()."""
+        psi_n = np.zeros((self.C, self.G, self.N))
+        self._sweep_direction(int(n), self.source_nodal(phi_in), psi_n, None, None, False)
+        return psi_n
+
+    def _sweep_direction(self, n, qn, psi_n, src_n, bnd, want_leak):
+        """Cells of direction n in its octant's topological order: the local
+        system of every group, psi_n [C, G, N] filled in place.  Returns the
+        per-(cell, group) net outflow when want_leak."""
+        C, G, nf = self.C, self.G, self.nf
+        per = self.nang // 8
+        o = n // per
+        om = self.omega[n]
+        leak = np.zeros((C, G)) if want_leak else None
+        for K in self.order[o]:
+            mask = self.inflow[o, K]
+            A0 = np.einsum("a,aij->ij", om, self.S[K])
+            A = A0[None, :, :] + self.st[K][:, None, None] * self.M[K][None, :, :]
+            src = qn[K] if src_n is None else qn[K] + src_n[K]
+            b = src @ self.M[K].T                                  # [G, N]: M q
+            ups = {}
+            for f in range(6):
+                if not (mask >> f) & 1:
+                    continue
+                fn = self.face_nodes[f]
+                of = np.einsum("a,akl->kl", om, self.F[K, f])
+                Nb = self.nbr[K, f]
+                if Nb >= 0:
+                    up = psi_n[Nb][:, self.perm[K, f]]              # [G, nf]
+                elif bnd is not None:
+                    up = bnd[K, f, n]
+                elif self.psi_b is not None:
+                    up = np.repeat(self.psi_b[:, None], nf, axis=1)
+                else:
+                    up = np.zeros((G, nf))
+                ups[f] = (of, up)
+                A[:, fn[:, None], fn[None, :]] -= of[None, :, :]
+                b[:, fn] -= up @ of.T
+            x = np.linalg.solve(A, b[:, :, None])[:, :, 0]
+            psi_n[K] = x
+            if want_leak:
+                lk = np.zeros(G)
+                for f in range(6):
+                    fn = self.face_nodes[f]
+                    if f in ups:
+                        of, up = ups[f]
+                        lk += (up @ of.T).sum(axis=1)
+                    else:
+                        of = np.einsum("a,akl->kl", om, self.F[K, f])
+                        lk += (x[:, fn] @ of.T).sum(axis=1)
+                leak[K] = lk
+        return leak
 
     def solve(self, tol, max_it, phi0=None):
         """Source iteration until the relative max-norm change of phi is

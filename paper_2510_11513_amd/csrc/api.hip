@@ -172,9 +172,11 @@ struct snx_problem {
     Sched sched;                        // the problem's own schedule of one
     // higher-order elements (order > 1): their matrices, fluxes and level lists
     struct Ho {
-        float *M = nullptr, *S = nullptr, *F = nullptr, *R = nullptr, *psi = nullptr;
+        float *M = nullptr, *R = nullptr, *psi = nullptr;
+        double *S = nullptr, *F = nullptr;   // streaming and face matrices in FP64
         float *phi[2] = {nullptr, nullptr};
         int *perm = nullptr, *tasks = nullptr;
+        double *omega64 = nullptr;      // [nang][3] directions in FP64
         std::vector<int> off;           // [levels + 1] offsets into tasks (all octants, by level)
         HoDev dev{};
     } ho;
@@ -1289,14 +1291,15 @@ snx_status snx_setup(snx_problem *p, void *stream) {
         const size_t NN = (size_t)N * N;
 #define HALLOC(ptr, bytes) HIPCHK(p, m.alloc((void **)&(ptr), (bytes)), "device allocation")
         HALLOC(H.M, sizeof(float) * C * NN);
-        HALLOC(H.S, sizeof(float) * 3 * C * NN);
-        HALLOC(H.F, sizeof(float) * 18 * C * NF * NF);
+        HALLOC(H.S, sizeof(double) * 3 * C * NN);
+        HALLOC(H.F, sizeof(double) * 18 * C * NF * NF);
         HALLOC(H.R, sizeof(float) * C * G * N);
         HALLOC(H.psi, sizeof(float) * p->nang * C * G * N);
         HALLOC(H.phi[0], sizeof(float) * C * G * N);
         HALLOC(H.phi[1], sizeof(float) * C * G * N);
         HALLOC(H.perm, sizeof(int) * 6 * C * NF);
         HALLOC(H.tasks, sizeof(int) * 8 * C);
+        HALLOC(H.omega64, sizeof(double) * 3 * p->nang);
 #undef HALLOC
         int maxlev = 0;
         for (int l : p->level) maxlev = std::max(maxlev, l);
@@ -1308,6 +1311,8 @@ snx_status snx_setup(snx_problem *p, void *stream) {
             for (size_t K = 0; K < C; ++K) tasks[fillp[p->level[(size_t)o * C + K]]++] = (int)(8 * K + o);
         HIPCHK(p, hipMemcpyAsync(H.perm, hmap.data(), sizeof(int) * hmap.size(), hipMemcpyHostToDevice, s), "copy");
         HIPCHK(p, hipMemcpyAsync(H.tasks, tasks.data(), sizeof(int) * tasks.size(), hipMemcpyHostToDevice, s), "copy");
+        HIPCHK(p, hipMemcpyAsync(H.omega64, p->omega.data(), sizeof(double) * 3 * p->nang, hipMemcpyHostToDevice, s),
+               "copy");
         HIPCHK(p, hipMemsetAsync(p->d_err, 0, sizeof(int), s), "memset");
         HIPCHK(p, launch_ho_geometry(P, d_xyz, d_cv, d_nbr, d_nbrf, H.perm, p->C, ho_reference(P), H.M, H.S, H.F,
                                      p->d_err, s), "geometry");
@@ -1317,7 +1322,8 @@ snx_status snx_setup(snx_problem *p, void *stream) {
         HoDev &D = H.dev;
         D.C = p->C; D.G = p->G; D.A = p->A;
         D.M = H.M; D.S = H.S; D.F = H.F; D.perm = H.perm; D.nbr = hp.nbr; D.inmask = hp.inmask;
-        D.sigt = hp.sigt; D.omega = hp.omega; D.psib = hp.psib; D.R = H.R; D.psi = H.psi; D.tasks = H.tasks;
+        D.sigt = hp.sigt; D.omega = hp.omega; D.omega64 = H.omega64; D.psib = hp.psib; D.R = H.R; D.psi = H.psi;
+        D.tasks = H.tasks;
     }
     p->ready = true;
     return SNX_OK;
@@ -1568,10 +1574,17 @@ snx_status snx_designation_stats(snx_problem *p, int64_t *out) {
 snx_status snx_get_psi(snx_problem *p, int32_t angle, int32_t group, float *out, void *stream) {
     if (!p || !out) return SNX_E_ARG;
     if (!p->ready) return fail(p, SNX_E_STATE, "snx_setup has not succeeded");
-    if (p->order > 1) return fail(p, SNX_E_ARG, "snx_get_psi is not available at order > 1");
     if (angle < 0 || angle >= p->nang || group < 0 || group >= p->G)
         return fail(p, SNX_E_ARG, "angle or group out of range");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
+    if (p->order > 1) {
+        // order p keeps psi[nang][C][G][N]: C rows of N floats, G * N apart
+        const size_t N = (size_t)(p->order + 1) * (p->order + 1) * (p->order + 1);
+        const float *src = p->ho.psi + ((size_t)angle * p->C * p->G + group) * N;
+        HIPCHK(p, hipMemcpy2DAsync(out, N * sizeof(float), src, (size_t)p->G * N * sizeof(float), N * sizeof(float),
+                                   (size_t)p->C, hipMemcpyDeviceToDevice, (hipStream_t)stream), "copy");
+        return SNX_OK;
+    }
     HIPCHK(p, launch_gather_psi(p->hp.psi, p->C, p->A, p->G, angle, group, out, (hipStream_t)stream), "gather");
     return SNX_OK;
 }

@@ -15,6 +15,20 @@
 // LDS, and unpivoted LU (the operator's symmetric part is positive
 // definite: sigma_t M plus the upwind face terms) eliminates below it.  At
 // order 2 each half-wave solves its own system.
+//
+// These systems are far less well conditioned than the first-order ones
+// (condition numbers up to ~2e3 on the 16^3 shape, where sigma_t h ~ 0.05 makes
+// them streaming-dominated), and an upwind error travels downstream almost
+// undamped, so a plain FP32 solve loses accuracy along every path through the
+// mesh.  Each solve is therefore followed by mixed-precision iterative
+// refinement: the residual b - A x is formed in FP64 against the operator
+// assembled in FP64 (B = Om . S - sum Om . F kept in LDS as an FP32 pair
+// hi + lo, the right-hand side's face terms from the same operators), and the
+// correction reuses the FP32 LU factors, whose multipliers stay in the row
+// entries that elimination leaves behind.  The streaming and face matrices
+// S and F are stored in FP64: rounded separately to FP32 they no longer satisfy
+// the discrete divergence identity that makes the face terms cancel on a
+// constant, an error these systems amplify (M stays FP32).
 #include <utility>
 
 #include "snx_internal.h"
@@ -79,7 +93,7 @@ template <int P> __device__ __forceinline__ void lagrange(const double *node, in
 // S^a_ij = int phi_i d phi_j / d x_a dV in FP64 by the m^3-point Gauss rule.
 template <int P>
 __global__ __launch_bounds__(256) void k_ho_volume(const double *__restrict__ xyz, const int *__restrict__ cv, HoRef ref,
-                                                   float *__restrict__ M, float *__restrict__ S, int *__restrict__ err) {
+                                                   float *__restrict__ M, double *__restrict__ S, int *__restrict__ err) {
     constexpr int m = P + 1, N = m * m * m, Q = m * m * m;
     const int K = blockIdx.x, tid = threadIdx.x;
     __shared__ double sX[8][3];
@@ -135,9 +149,9 @@ __global__ __launch_bounds__(256) void k_ho_volume(const double *__restrict__ xy
         }
         const size_t NN = (size_t)N * N;
         M[K * NN + e] = (float)mm;
-        S[(3 * (size_t)K + 0) * NN + e] = (float)s0;
-        S[(3 * (size_t)K + 1) * NN + e] = (float)s1;
-        S[(3 * (size_t)K + 2) * NN + e] = (float)s2;
+        S[(3 * (size_t)K + 0) * NN + e] = s0;
+        S[(3 * (size_t)K + 1) * NN + e] = s1;
+        S[(3 * (size_t)K + 2) * NN + e] = s2;
     }
 }
 
@@ -148,7 +162,7 @@ __global__ __launch_bounds__(256) void k_ho_volume(const double *__restrict__ xy
 template <int P>
 __global__ __launch_bounds__(256) void k_ho_faces(const double *__restrict__ xyz, const int *__restrict__ cv,
                                                   const int *__restrict__ nbr, const int *__restrict__ nbrf,
-                                                  const int *__restrict__ hoperm, HoRef ref, float *__restrict__ F) {
+                                                  const int *__restrict__ hoperm, HoRef ref, double *__restrict__ F) {
     constexpr int m = P + 1, NF = m * m, QF = m * m;
     const int K = blockIdx.x / 6, f = blockIdx.x % 6, tid = threadIdx.x;
     const int Nb = nbr[6 * K + f], g = nbrf[6 * K + f];
@@ -195,12 +209,12 @@ __global__ __launch_bounds__(256) void k_ho_faces(const double *__restrict__ xyz
         for (int a = 0; a < 3; ++a) F3[a] += sN[q][a] * pk * pl;
     }
     const size_t FF = (size_t)NF * NF;
-    for (int a = 0; a < 3; ++a) F[((6 * (size_t)K + f) * 3 + a) * FF + tid] = (float)F3[a];
+    for (int a = 0; a < 3; ++a) F[((6 * (size_t)K + f) * 3 + a) * FF + tid] = F3[a];
     if (Nb < 0) return;
     const int pk = face_pos<P>(g, hoperm[(6 * (size_t)K + f) * NF + k]);
     const int pl = face_pos<P>(g, hoperm[(6 * (size_t)K + f) * NF + l]);
     if (pk < 0 || pl < 0) return;   // not produced by the host's node maps; kept out of bounds-unsafe writes
-    for (int a = 0; a < 3; ++a) F[((6 * (size_t)Nb + g) * 3 + a) * FF + pk * NF + pl] = (float)-F3[a];
+    for (int a = 0; a < 3; ++a) F[((6 * (size_t)Nb + g) * 3 + a) * FF + pk * NF + pl] = -F3[a];
 }
 
 // --------------------------------------------------------------------- sweep
@@ -256,7 +270,7 @@ __device__ __forceinline__ void lu_step(float (&row)[N], float &b, float *piv, i
 // c1 = l1 and c0 = l0 - l1 m1 (l0, l1 its own multipliers).  Lane k+1 itself
 // only takes out column k.  Same arithmetic as two single steps, up to
 // rounding order.
-template <int N, int LP, int k>
+template <int N, int LP, int k, bool KEEP>
 __device__ __forceinline__ void lu_step2(float (&row)[N], float &b, float *piv, int r) {
     float *piv1 = piv + LP;
     if (r == k || r == k + 1) {
@@ -280,6 +294,9 @@ __device__ __forceinline__ void lu_step2(float (&row)[N], float &b, float *piv, 
     const float l1 = __builtin_fmaf(-l0, pk1, row[k + 1]) * __builtin_amdgcn_rcpf(d);
     const float c0 = r > k + 1 ? __builtin_fmaf(-l1, m1, l0) : (r == k + 1 ? m1 : 0.f);
     const float c1 = r > k + 1 ? l1 : 0.f;
+    // The multipliers go where this step leaves nothing of use (columns k and
+    // k+1 of the rows below the pivots are never read again), for the
+    // refinement's replay: c1 as column k+1 is updated, c0 after the loop.
 #pragma unroll
     for (int c = (k + 1) / 4; c < (N + 3) / 4; ++c) {
         const float4 v = p0[c], w = p1[c];
@@ -287,11 +304,39 @@ __device__ __forceinline__ void lu_step2(float (&row)[N], float &b, float *piv, 
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int j = 4 * c + e;
-            if (j > k && j < N) row[j] = __builtin_fmaf(-c1, ww[e], __builtin_fmaf(-c0, vv[e], row[j]));
+            if (j > k && j < N) {
+                const float u = __builtin_fmaf(-c1, ww[e], __builtin_fmaf(-c0, vv[e], row[j]));
+                row[j] = (KEEP && j == k + 1 && r > k + 1) ? c1 : u;
+            }
         }
         if (N > 32 && (c + 1) % kChunks == 0) __builtin_amdgcn_sched_barrier(0);
     }
     b = __builtin_fmaf(-c1, piv1[N], __builtin_fmaf(-c0, piv[N], b));
+    if constexpr (KEEP) row[k] = r > k ? c0 : row[k];
+}
+
+// x_k of lane k (or H + k in the upper half-wave) for every lane of its system
+template <int H>
+__device__ __forceinline__ float from_lane(float v, int k, int half) {
+    const int bits = __builtin_bit_cast(int, v);
+    if constexpr (H == 64) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(bits, k));
+    } else {
+        const float v0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(bits, k));
+        const float v1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(bits, H + k));
+        return half ? v1 : v0;
+    }
+}
+
+// The elimination of the pivot pair (k, k+1) replayed on a new right-hand side
+// with the stored multipliers: lane k+1 takes out m1 b_k, the lanes below
+// c0 b_k + c1 b_k+1 (b_k+1 as it was before lane k+1's own update).
+template <int N, int H, int k>
+__device__ __forceinline__ void replay_step2(const float (&row)[N], float &b, int r, int half) {
+    const float bk = from_lane<H>(b, k, half), bk1 = from_lane<H>(b, k + 1, half);
+    const float c0 = r > k ? row[k] : 0.f;
+    const float c1 = r > k + 1 ? row[k + 1] : 0.f;
+    b = __builtin_fmaf(-c1, bk1, __builtin_fmaf(-c0, bk, b));
 }
 
 // Back substitution, column k = N-1-i: lane k finishes x_k, which every lane
@@ -312,25 +357,33 @@ __device__ __forceinline__ void back_step(const float (&row)[N], float &b, float
     if (r == k) x = xk;
     b = __builtin_fmaf(r < k ? -row[k] : 0.f, xk, b);
 }
-template <int N, int H, int LP, int... K, int... I>
+template <int N, int H, int LP, bool KEEP, int... K, int... I>
 __device__ __forceinline__ void lu_solve(float (&row)[N], float &b, float &x, float *piv, int r, int half,
                                          std::integer_sequence<int, K...>, std::integer_sequence<int, I...>) {
-    (lu_step2<N, LP, 2 * I>(row, b, piv, r), ...);             // pivots in pairs
-    if constexpr (N % 2) lu_step<N, N - 1>(row, b, piv, r);      // the odd last one
+    (lu_step2<N, LP, 2 * I, KEEP>(row, b, piv, r), ...);       // pivots in pairs
+    if constexpr (N % 2) lu_step<N, N - 1>(row, b, piv, r);      // the odd last one (no row below it)
+    (back_step<N, H, K>(row, b, x, r, half), ...);
+}
+// A second solve with the factors of lu_solve: forward elimination replayed
+// pair by pair, then back substitution.
+template <int N, int H, int... K, int... I>
+__device__ __forceinline__ void lu_resolve(const float (&row)[N], float &b, float &x, int r, int half,
+                                           std::integer_sequence<int, K...>, std::integer_sequence<int, I...>) {
+    (replay_step2<N, H, 2 * I>(row, b, r, half), ...);
     (back_step<N, H, K>(row, b, x, r, half), ...);
 }
 
 // One workgroup per (task, direction) of a level: B = Om . S - sum_{f in}
 // Om . F_f and M go to LDS once, then the workgroup's wave halves solve the
 // direction's groups, one system each.
-template <int P>
+template <int P, int REFINE>
 __device__ __forceinline__ void ho_sweep_body(const HoDev &D, int begin) {
     constexpr int m = P + 1, N = m * m * m, NF = m * m;
     constexpr int LD = (N % 2 == 0) ? N + 1 : N + 2;        // odd row stride: lanes' rows sit in different banks
     constexpr int LP = ((N + 1) + 3) / 4 * 4;               // pivot buffer: row and rhs, 16-byte aligned
     constexpr int H = N <= 32 ? 32 : 64, SPW = 64 / H, SPB = 4 * SPW;
-    __shared__ float sB[N * LD], sM[N * LD];
-    __shared__ float sOF[6][NF * NF];
+    __shared__ float sB[N * LD], sBlo[N * LD], sM[N * LD];   // B = hi + lo (FP64 assembly)
+    __shared__ float sOF[6][NF * NF], sOFlo[6][NF * NF];     // Om . F_f = hi + lo (FP64 assembly)
     __shared__ __align__(16) float sPiv[4 * SPW][2 * LP];   // pivot rows k and k+1
 
     const int A = D.A, C = D.C, G = D.G;
@@ -338,31 +391,36 @@ __device__ __forceinline__ void ho_sweep_body(const HoDev &D, int begin) {
     const int task = D.tasks[t];
     const int K = task >> 3, o = task & 7, n = o * A + dir;
     const int mask = D.inmask[(size_t)o * C + K];
-    const float ox = D.omega[3 * n], oy = D.omega[3 * n + 1], oz = D.omega[3 * n + 2];
+    const double dx = D.omega64[3 * n], dy = D.omega64[3 * n + 1], dz = D.omega64[3 * n + 2];
     const int tid = threadIdx.x;
     const size_t NN = (size_t)N * N, FF = (size_t)NF * NF;
-    const float *S = D.S + 3 * (size_t)K * NN;
+    const double *S = D.S + 3 * (size_t)K * NN;
     const float *Mk = D.M + (size_t)K * NN;
-    const float *Fk = D.F + 6 * 3 * (size_t)K * FF;
+    const double *Fk = D.F + 6 * 3 * (size_t)K * FF;
 
     for (int e = tid; e < N * N; e += 256) {
         const int i = e / N, j = e % N;
-        float b = ox * S[e] + oy * S[NN + e] + oz * S[2 * NN + e];
+        double b = dx * S[e] + dy * S[NN + e] + dz * S[2 * NN + e];
         for (int f = 0; f < 6; ++f) {
             if (!((mask >> f) & 1)) continue;
             const int pi = face_pos<P>(f, i), pj = face_pos<P>(f, j);
             if (pi < 0 || pj < 0) continue;
-            const float *Ff = Fk + (size_t)f * 3 * FF + pi * NF + pj;
-            b -= ox * Ff[0] + oy * Ff[FF] + oz * Ff[2 * FF];
+            const double *Ff = Fk + (size_t)f * 3 * FF + pi * NF + pj;
+            b -= dx * Ff[0] + dy * Ff[FF] + dz * Ff[2 * FF];
         }
-        sB[i * LD + j] = b;
+        const float hi = (float)b;
+        sB[i * LD + j] = hi;
+        sBlo[i * LD + j] = (float)(b - (double)hi);
         sM[i * LD + j] = Mk[e];
     }
     for (int e = tid; e < 6 * NF * NF; e += 256) {
         const int f = e / (NF * NF), kl = e % (NF * NF);
         if (!((mask >> f) & 1)) continue;
-        const float *Ff = Fk + (size_t)f * 3 * FF + kl;
-        sOF[f][kl] = ox * Ff[0] + oy * Ff[FF] + oz * Ff[2 * FF];
+        const double *Ff = Fk + (size_t)f * 3 * FF + kl;
+        const double of = dx * Ff[0] + dy * Ff[FF] + dz * Ff[2 * FF];
+        const float hi = (float)of;
+        sOF[f][kl] = hi;
+        sOFlo[f][kl] = (float)(of - (double)hi);
     }
     __syncthreads();
 
@@ -382,36 +440,72 @@ __device__ __forceinline__ void ho_sweep_body(const HoDev &D, int begin) {
         float row[N];
 #pragma unroll
         for (int j = 0; j < N; ++j) row[j] = __builtin_fmaf(sig, sM[rr * LD + j], sB[rr * LD + j]);
-        float b = D.R[((size_t)K * G + gg) * N + rr];
+        // right-hand side in FP64 with the same face operators as the matrix (an
+        // FP32 one would break the exact cancellation of the face terms on a
+        // constant solution)
+        double bd = (double)D.R[((size_t)K * G + gg) * N + rr];
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
             if (fpos[f] < 0) continue;
             const int nb = D.nbr[6 * K + f];
-            const float *of = sOF[f] + fpos[f] * NF;
+            const float *of = sOF[f] + fpos[f] * NF, *ofl = sOFlo[f] + fpos[f] * NF;
             if (nb >= 0) {
                 const float *up = D.psi + (((size_t)n * C + nb) * G + gg) * N;
                 const int *pm = D.perm + (6 * (size_t)K + f) * NF;
-                for (int l = 0; l < NF; ++l) b -= of[l] * up[pm[l]];
+                for (int l = 0; l < NF; ++l) bd -= ((double)of[l] + (double)ofl[l]) * (double)up[pm[l]];
             } else {
-                const float pb = D.psib ? D.psib[gg] : 0.f;
-                float s = 0.f;
-                for (int l = 0; l < NF; ++l) s += of[l];
-                b -= s * pb;
+                const double pb = D.psib ? (double)D.psib[gg] : 0.0;
+                double s = 0.0;
+                for (int l = 0; l < NF; ++l) s += (double)of[l] + (double)ofl[l];
+                bd -= s * pb;
             }
         }
+        const double b0 = bd;
+        float b = (float)bd;
         float x = 0.f;
-        lu_solve<N, H, LP>(row, b, x, piv, r, half, std::make_integer_sequence<int, N>{},
+        lu_solve<N, H, LP, (REFINE > 0)>(row, b, x, piv, r, half, std::make_integer_sequence<int, N>{},
                            std::make_integer_sequence<int, N / 2>{});
+        // refinement: residual in FP64 against sigma_t M + (B hi + lo), then the
+        // correction from the same factors.  x reaches every lane of the system
+        // through its pivot buffer (a wave's LDS accesses run in issue order).
+#pragma unroll 1
+        for (int it = 0; it < REFINE; ++it) {
+            if (r < N) piv[r] = x;
+            wave_lds_sync();
+            const float4 *x4 = reinterpret_cast<const float4 *>(piv);
+            double res = b0;
+#pragma unroll 1
+            for (int c = 0; c < (N + 3) / 4; ++c) {
+                const float4 xv = x4[c];
+                const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int j = 4 * c + e;
+                    if (j < N) {
+                        const double a = (double)sig * (double)sM[rr * LD + j] +
+                                         ((double)sB[rr * LD + j] + (double)sBlo[rr * LD + j]);
+                        res = __builtin_fma(-a, (double)xs[e], res);
+                    }
+                }
+            }
+            float rb = (float)res, dxk = 0.f;
+            lu_resolve<N, H>(row, rb, dxk, r, half, std::make_integer_sequence<int, N>{},
+                             std::make_integer_sequence<int, N / 2>{});
+            x += dxk;
+            wave_lds_sync();      // every lane has read the old x before the next write
+        }
         if (valid) D.psi[(((size_t)n * C + K) * G + g) * N + r] = x;
     }
 }
 
-// One kernel per order.  With pivots in pairs, order 3 runs fastest on its
-// natural register count (two waves per SIMD, each with twice the work between
-// LDS round trips); capping it at three or four waves per SIMD spilled and was
-// slower.
-__global__ __launch_bounds__(256) void k_ho_sweep2(HoDev D, int begin) { ho_sweep_body<2>(D, begin); }
-__global__ __launch_bounds__(256) void k_ho_sweep3(HoDev D, int begin) { ho_sweep_body<3>(D, begin); }
+// One kernel per order, each with one refinement step.  With pivots in pairs
+// order 3 runs fastest at two waves per SIMD (each with twice the work between
+// LDS round trips); the refinement's replay keeps the multipliers alive, so
+// holding it there spills a few registers.
+__global__ __launch_bounds__(256) void k_ho_sweep2(HoDev D, int begin) { ho_sweep_body<2, 1>(D, begin); }
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_ho_sweep3(HoDev D, int begin) {
+    ho_sweep_body<3, 1>(D, begin);
+}
 
 // R = M (Q + sigma_s phi) / (4 pi) at every (cell, group, node); phi NULL = zero
 __global__ __launch_bounds__(256) void k_ho_source(const float *__restrict__ M, const float *__restrict__ q,
@@ -444,7 +538,7 @@ unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 }  // namespace
 
 hipError_t launch_ho_geometry(int P, const double *xyz, const int *cv, const int *nbr, const int *nbrf,
-                              const int *hoperm, int C, const HoRef &ref, float *M, float *S, float *F, int *err,
+                              const int *hoperm, int C, const HoRef &ref, float *M, double *S, double *F, int *err,
                               hipStream_t s) {
     if (P == 2) {
         hipLaunchKernelGGL(k_ho_volume<2>, dim3(C), dim3(256), 0, s, xyz, cv, ref, M, S, err);

@@ -128,13 +128,14 @@ struct HoRef {
 struct HoDev {
     int C, G, A;
     const float *M;              // [C][N][N]          mass
-    const float *S;              // [C][3][N][N]       streaming S^a_ij = int phi_i d phi_j / d x_a
-    const float *F;              // [C][6][3][NF][NF]  face matrices on the face's nodes
+    const double *S;              // [C][3][N][N]       streaming S^a_ij (FP64) = int phi_i d phi_j / d x_a
+    const double *F;              // [C][6][3][NF][NF]  face matrices on the face's nodes (FP64)
     const int *perm;             // [C][6][NF]         neighbour's local node at my face node k
     const int *nbr;              // [C][6]
     const unsigned char *inmask; // [8][C]             inflow faces per octant
     const float *sigt;           // [C][G]
     const float *omega;          // [8*A][3]
+    const double *omega64;       // [8*A][3]           the directions in FP64 (operator assembly)
     const float *psib;           // [G] or nullptr
     const float *R;              // [C][G][N]          M (Q + sigma_s phi) / (4 pi)
     float *psi;                  // [8*A][C][G][N]
@@ -248,7 +249,7 @@ hipError_t gnn_targets(const float *phi, long long Nn, float *y, hipStream_t s);
 hipError_t gnn_expand(const float *z, long long Nn, float *phi, hipStream_t s);
 
 hipError_t launch_ho_geometry(int P, const double *xyz, const int *cv, const int *nbr, const int *nbrf,
-                              const int *hoperm, int C, const HoRef &ref, float *M, float *S, float *F, int *err,
+                              const int *hoperm, int C, const HoRef &ref, float *M, double *S, double *F, int *err,
                               hipStream_t s);
 // Tasks D.tasks[begin, begin + count) of one level, one workgroup per (task, direction).
 hipError_t launch_ho_sweep_level(int P, const HoDev &D, int begin, int count, hipStream_t s);

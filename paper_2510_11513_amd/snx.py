@@ -363,9 +363,9 @@ class Problem:
         return lev, nl
 
     def psi(self, angle: int, group: int, stream=None):
-        """psi[ncell][8] (device, FP32) of one direction and group from the last sweep."""
+        """psi[ncell][nodes] (device, FP32) of one direction and group from the last sweep."""
         import torch
-        out = torch.empty((self.ncell, 8), dtype=torch.float32, device=f"cuda:{self.device}")
+        out = torch.empty((self.ncell, self.nodes), dtype=torch.float32, device=f"cuda:{self.device}")
         self._check(load().snx_get_psi(self.h, int(angle), int(group), _ptr(out), _stream(stream)), "get_psi")
         return out
 

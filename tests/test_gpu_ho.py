@@ -170,3 +170,58 @@ def test_full_size_mirror_symmetry(order):
     assert np.all(np.isfinite(phi)) and phi.min() > 0
     assert asym.max() <= 1e-5, asym
     p.close()
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_jittered_rotated_8cubed_every_node(order):
+    """8^3 jittered cells, each turned at random, 16 directions, 3 groups with
+    sigma_t from 0.1 to 10 (small pivots in the thin cells): one sweep from a
+    random flux, every node value of every group against the oracle."""
+    torch = _torch()
+    prob = _problem(8, 3, 1, 2, seed=40 + order, kind=1)
+    assert prob.mat.sigma_t.min() < 0.2 and prob.mat.sigma_t.max() > 5.0
+    p, o = _pair(prob, order)
+    N = (order + 1) ** 3
+    rng = np.random.default_rng(41)
+    phi32 = rng.uniform(0.0, 2.0, (prob.mesh.ncell, prob.mat.ngroup, N)).astype(np.float32)
+    print(f"[case] order {order} 8^3 rotated: C={prob.mesh.ncell} nang={prob.nang} G={prob.mat.ngroup}", flush=True)
+    out = p.sweep(torch.from_numpy(phi32).cuda())
+    torch.cuda.synchronize()
+    ref = o.sweep(phi32.astype(np.float64))["phi"]
+    err = H.rel_err_per_group(out.cpu().numpy().astype(np.float64), ref)
+    print(f"[case] order {order} 8^3 rotated: phi max rel err {err.max():.2e}", flush=True)
+    assert err.max() <= TOL, err
+    p.close()
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_full_size_sampled_directions(order):
+    """The benchmark's size and launch configuration (16^3 jittered cells, 128
+    directions, 16 groups): the angular flux of four sampled directions, one per
+    octant of a random choice, every group and node, against the oracle's sweep
+    of those directions alone (the directions of one source iteration are
+    independent for a given input flux)."""
+    torch = _torch()
+    from paper_2510_11513_amd import snx
+    prob = inputs.config_problem(0)
+    p = snx.Problem.from_problem(prob, order=order)
+    om, w = oracle.quadrature(prob.npolar, prob.nazim)
+    N = (order + 1) ** 3
+    rng = np.random.default_rng(50 + order)
+    phi32 = rng.uniform(0.0, 2.0, (prob.mesh.ncell, prob.mat.ngroup, N)).astype(np.float32)
+    print(f"[case] order {order} full size: C={prob.mesh.ncell} nang={prob.nang} G={prob.mat.ngroup}", flush=True)
+    p.sweep(torch.from_numpy(phi32).cuda())
+    torch.cuda.synchronize()
+    o = ho.HOOracle(prob.mesh.xyz, prob.mesh.cell_vert, order, om, w, prob.mat.sigma_t, prob.mat.sigma_s,
+                    prob.mat.q)
+    per = prob.nang // 8
+    for oc in rng.permutation(8)[:4]:
+        n = int(oc * per + rng.integers(per))
+        ref = o.sweep_angle(phi32.astype(np.float64), n)              # [C][G][N]
+        errs = []
+        for g in range(prob.mat.ngroup):
+            got = p.psi(n, g).cpu().numpy().astype(np.float64)
+            errs.append(np.abs(got - ref[:, g]).max() / np.abs(ref[:, g]).max())
+        print(f"[case] order {order} full size direction {n}: max rel err over groups {max(errs):.2e}", flush=True)
+        assert max(errs) <= TOL, (order, n, errs)
+    p.close()
