@@ -176,8 +176,9 @@ def higher_order(steps: int = 25):
 
 def per_angle(prob, threads: int, wg_per_cu: int, ms_octant: float, its_octant: int, sweeps: int):
     """The same workload under per-angle designation (each direction's own inflow
-    faces, lagged where they go against the octant's order): sweep time in the
-    same schedule, the designation counts, and source iterations to the
+    faces): in the octant's order with every face against it lagged, and in each
+    direction's own order with only the faces that close cycles lagged (level by
+    level).  Sweep time, the designation counts, and source iterations to the
     workload's tolerance beside the per-octant count."""
     from paper_2510_11513_amd import snx
     p = snx.Problem.from_problem(prob, setup=False, designation=snx.DESIGNATION_ANGLE)
@@ -188,11 +189,25 @@ def per_angle(prob, threads: int, wg_per_cu: int, ms_octant: float, its_octant: 
     ds = p.designation_stats()
     _, info = p.solve(prob.tol, 5000)
     p.close()
+    # each direction in its own order, only the faces that close cycles lagged
+    q = snx.Problem.from_problem(prob, setup=False, designation=snx.DESIGNATION_DIRECTION)
+    q.set_schedule(threads=threads)
+    t0 = time.perf_counter()
+    q.setup()
+    t_setup = time.perf_counter() - t0
+    phi = q.sweep(None)
+    ms_dir = q.profile_sweep(sweeps, phi_in=phi)
+    dsd = q.designation_stats()
+    _, info_dir = q.solve(prob.tol, 5000)
+    q.close()
     return {"sweep_ms": round(ms, 4), "per_octant_sweep_ms": round(ms_octant, 4),
             "ratio": round(ms / ms_octant, 3), "differing_triples": ds["differing"],
             "lagged_triples": ds["lagged"], "tasks_with_difference": ds["tasks"],
             "iterations_to_tol": info["iterations"], "per_octant_iterations_to_tol": its_octant,
-            "tol": prob.tol}
+            "tol": prob.tol,
+            "per_direction_order": {"sweep_ms": round(ms_dir, 4), "ratio": round(ms_dir / ms_octant, 3),
+                                    "lagged_triples": dsd["lagged"], "iterations_to_tol": info_dir["iterations"],
+                                    "setup_s": round(t_setup, 3)}}
 
 
 def extensions(prob, threads: int, wg_per_cu: int, steps: int):

@@ -185,10 +185,23 @@ snx_status snx_get_order(snx_problem *p, int32_t *order, int32_t *nodes);
  *   problem's previous sweep (zero after snx_setup).  Every cycle is broken
  *   this way, and source iteration converges to the per-direction upwind
  *   solution, independently of which faces lag.
+ * SNX_DESIGNATION_DIRECTION: the same inflow faces, and each direction sweeps
+ *   the mesh in its own upwind order (the traversal of §2.1).  snx_setup finds
+ *   the strongly connected components of every direction's graph (Tarjan's
+ *   algorithm, on the host) and lags only faces inside them: a face whose
+ *   upwind cell has the larger Omega_n . centroid (vertex mean; the larger cell
+ *   id on a tie) reads the neighbour's angular flux of the previous sweep.
+ *   Every other inflow face reads this sweep's flux.  The sweep runs level by
+ *   level over the directions' own levels (one launch per level, a work item
+ *   per cell, octant and level holding the octant's directions at that level;
+ *   snx_set_sweep_mode does not apply, snx_sweep_stats counts no tasks).  Not
+ *   available with reflective planes, anisotropic scattering, in batches or
+ *   at order > 1 (SNX_E_ARG).  snx_designation_stats counts the lagged faces.
  * SNX_E_ARG for another kind; snx_setup returns SNX_E_MESH when a face is
  * tangent to a direction. */
 #define SNX_DESIGNATION_OCTANT 0
 #define SNX_DESIGNATION_ANGLE 1
+#define SNX_DESIGNATION_DIRECTION 2
 snx_status snx_set_designation(snx_problem *p, int32_t kind);
 
 /* Build everything one mesh needs, on the device: face matching, element
@@ -261,8 +274,9 @@ snx_status snx_get_levels(snx_problem *p, int32_t *level, int32_t *nlevels);
 
 /* Designation statistics from setup, host out[4]: the designation, the
  * (direction, cell, face) triples whose inflow bit differs from the octant's,
- * the lagged triples among them (interior faces inflow for the direction and
- * downwind in the octant's order), and the (cell, octant) tasks with at least
+ * the lagged triples (SNX_DESIGNATION_ANGLE: interior faces inflow for the
+ * direction and downwind in the octant's order; SNX_DESIGNATION_DIRECTION: the
+ * faces lagged to break cycles), and the (cell, octant) tasks with at least
  * one differing direction.  The counts are zero under per-octant designation.
  * Synchronous. */
 snx_status snx_designation_stats(snx_problem *p, int64_t *out);

@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsnx.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "k_geometry.hip", "k_dag.hip", "k_sweep.hip", "k_reduce.hip", "k_ho.hip", "k_gnn.hip", "gnn.hip", "host.cpp"]
+SOURCES = ["api.hip", "k_geometry.hip", "k_dag.hip", "k_sweep.hip", "k_sweep_dir.hip", "k_reduce.hip", "k_ho.hip", "k_gnn.hip", "gnn.hip", "host.cpp"]
 
 HIP_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -104,6 +104,8 @@ struct Sched {
     bool phase_stats = false;                // gather the per-phase cycle statistics (snx_set_sweep_stats)
     bool fixed_outer = false;                // group-to-group matrices: keep the cross-group source fixed
                                              // (inner iterations of an outer one); else renew it every iteration
+    const snx_problem *dirp = nullptr;       // the schedule's one problem when it sweeps in per-direction
+                                             // order (level-synchronous, see enqueue_sweep)
     long long *d_bsp_tasks = nullptr;        // tasks of every problem ordered by level (BSP comparator)
     std::vector<long long> bsp_off;          // [levels + 1] offsets into d_bsp_tasks
     unsigned long long watchdog = 0;
@@ -156,6 +158,12 @@ struct snx_problem {
     std::vector<int> level, nlev;
     std::vector<std::vector<int>> seeds_by_octant;   // local task ids (8*K + o) of level-0 cells
     unsigned long long desig_counts[3] = {0, 0, 0};  // per-angle designation statistics (snx_designation_stats)
+    // per-direction sweep order (SNX_DESIGNATION_DIRECTION): work items, lagged faces
+    struct Dir {
+        std::vector<long long> level_off;   // [levels + 1] offsets into the work items
+        long long cyclic = 0;               // directions whose graph had a cycle
+        DirDev dev{};
+    } dir;
     int maxin = 1;
     int *d_err = nullptr;
     float *d_phi[2] = {nullptr, nullptr};
@@ -218,6 +226,7 @@ void drop_device(snx_problem *p) {
     p->ready = false;
     p->hp = DevProblem{};
     p->ho = snx_problem::Ho{};
+    p->dir = snx_problem::Dir{};
 }
 
 // ------------------------------------------------------- higher-order elements
@@ -347,6 +356,12 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
     sc.maxA = sc.maxG = sc.maxAG = 0;
     sc.maxin = 1;
     sc.ext = false;
+    sc.dirp = nullptr;
+    for (snx_problem *p : probs)
+        if (p->designation == SNX_DESIGNATION_DIRECTION) {
+            if (n > 1) return fail_msg(sc.err, SNX_E_ARG, "a problem swept in per-direction order cannot join a batch");
+            sc.dirp = p;
+        }
     for (int i = 0; i < n; ++i) {
         snx_problem *p = probs[i];
         DevProblem P = p->hp;
@@ -443,6 +458,18 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
 // sweep kernel alone.
 snx_status enqueue_sweep(Sched &sc, const int *stops, hipStream_t s, hipEvent_t ev0 = nullptr,
                          hipEvent_t ev1 = nullptr) {
+    if (sc.dirp) {   // per-direction order: lag snapshot, one launch per level, octant slots
+        const snx_problem *p = sc.dirp;
+        const DirDev &D = p->dir.dev;
+        if (ev0) HIPCHK_E(sc.err, hipEventRecord(ev0, s), "event");
+        HIPCHK_E(sc.err, launch_lag_snapshot(D, sc.d_probs, p->G, stops, s), "lag snapshot");
+        for (size_t l = 0; l + 1 < p->dir.level_off.size(); ++l)
+            HIPCHK_E(sc.err, launch_sweep_dir_level(D, sc.d_probs, sc.threads, p->dir.level_off[l],
+                                                    p->dir.level_off[l + 1], stops, s), "level launch");
+        HIPCHK_E(sc.err, launch_dir_slots(sc.d_probs, p->C, p->G, stops, s), "slots");
+        if (ev1) HIPCHK_E(sc.err, hipEventRecord(ev1, s), "event");
+        return SNX_OK;
+    }
     // reflective planes: the last sweep's outflow becomes this sweep's inflow
     for (int i = 0; i < sc.nprob(); ++i) {
         const DevProblem &P = sc.hprobs[i];
@@ -988,8 +1015,8 @@ snx_status snx_set_boundary(snx_problem *p, int32_t kind, const double *psi_in) 
 
 snx_status snx_set_designation(snx_problem *p, int32_t kind) {
     if (!p) return SNX_E_ARG;
-    if (kind != SNX_DESIGNATION_OCTANT && kind != SNX_DESIGNATION_ANGLE)
-        return fail(p, SNX_E_ARG, "designation must be SNX_DESIGNATION_OCTANT or SNX_DESIGNATION_ANGLE");
+    if (kind != SNX_DESIGNATION_OCTANT && kind != SNX_DESIGNATION_ANGLE && kind != SNX_DESIGNATION_DIRECTION)
+        return fail(p, SNX_E_ARG, "designation must be SNX_DESIGNATION_OCTANT, _ANGLE or _DIRECTION");
     p->designation = kind;
     drop_device(p);
     return SNX_OK;
@@ -1002,6 +1029,9 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     if (p->order > 1 && (p->designation != SNX_DESIGNATION_OCTANT || p->refl || p->L || p->nmat))
         return fail(p, SNX_E_ARG, "per-angle designation, reflective planes, anisotropic and group-to-group "
                                   "scattering are not available at order > 1");
+    if (p->designation == SNX_DESIGNATION_DIRECTION && (p->refl || p->L))
+        return fail(p, SNX_E_ARG, "reflective planes and anisotropic scattering are not available with the "
+                                  "per-direction sweep order");
     HIPCHK(p, hipSetDevice(p->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     drop_device(p);
@@ -1129,7 +1159,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     // per-angle designation: each direction's inflow faces, decided in FP64
     unsigned char *damask = nullptr, *dlagm = nullptr;
     std::fill(p->desig_counts, p->desig_counts + 3, 0ull);
-    if (p->designation == SNX_DESIGNATION_ANGLE) {
+    if (p->designation != SNX_DESIGNATION_OCTANT) {
         double *d_om64;
         unsigned long long *dcounts;
         HIPCHK(p, m.alloc((void **)&damask, 8 * C * A), "device allocation");
@@ -1148,6 +1178,43 @@ snx_status snx_setup(snx_problem *p, void *stream) {
         if (herr & 8) { drop_device(p); return fail(p, SNX_E_MESH, "a face is tangent to a direction"); }
         // lagged faces read the previous sweep's angular flux: zero before the first
         HIPCHK(p, launch_fill_f32(dpsi, 8 * C * 8 * A * G, 0.f, s), "fill");
+    }
+    if (p->designation == SNX_DESIGNATION_DIRECTION) {
+        // each direction's own order: components, lagged faces and levels on the host
+        std::vector<unsigned char> am(8 * C * A);
+        HIPCHK(p, hipMemcpy(am.data(), damask, 8 * C * A, hipMemcpyDeviceToHost), "copy");
+        DirHost dh;
+        std::string derr;
+        const int drc = direction_orders(p->C, p->A, nbr, nbrf, am, p->xyz, p->cv, p->omega, dh, derr);
+        if (drc) { drop_device(p); return fail(p, drc, derr); }
+        const size_t nl = dh.lag.size(), ni = dh.items.size();
+        std::vector<long long> src(std::max<size_t>(1, 4 * nl), 0);
+        for (size_t i = 0; i < nl; ++i) {
+            const DirHost::Lag &L = dh.lag[i];
+            const int N = nbr[(size_t)L.K * 6 + L.f];
+            for (int l = 0; l < 4; ++l) {
+                const long long vn = (perm[(size_t)L.K * 6 + L.f] >> (8 * l)) & 0xffu;
+                src[4 * i + l] = ((((long long)L.o * p->C + N) * 8 + vn) * p->A + L.a) * p->G;
+            }
+        }
+        DirDev &D = p->dir.dev;
+        int *ditems; unsigned long long *ddirs; unsigned char *dlagb; int *dlagi; long long *dsrc; float *dlbuf;
+        HIPCHK(p, m.alloc((void **)&ditems, sizeof(int) * std::max<size_t>(1, ni)), "device allocation");
+        HIPCHK(p, m.alloc((void **)&ddirs, sizeof(unsigned long long) * std::max<size_t>(1, ni)), "device allocation");
+        HIPCHK(p, m.alloc((void **)&dlagb, 8 * C * A), "device allocation");
+        HIPCHK(p, m.alloc((void **)&dlagi, sizeof(int) * 8 * C * A), "device allocation");
+        HIPCHK(p, m.alloc((void **)&dsrc, sizeof(long long) * src.size()), "device allocation");
+        HIPCHK(p, m.alloc((void **)&dlbuf, sizeof(float) * std::max<size_t>(1, 4 * nl * G)), "device allocation");
+        HIPCHK(p, hipMemcpy(ditems, dh.items.data(), sizeof(int) * ni, hipMemcpyHostToDevice), "copy");
+        HIPCHK(p, hipMemcpy(ddirs, dh.dirs.data(), sizeof(unsigned long long) * ni, hipMemcpyHostToDevice), "copy");
+        HIPCHK(p, hipMemcpy(dlagb, dh.lagbits.data(), 8 * C * A, hipMemcpyHostToDevice), "copy");
+        HIPCHK(p, hipMemcpy(dlagi, dh.lagidx.data(), sizeof(int) * 8 * C * A, hipMemcpyHostToDevice), "copy");
+        HIPCHK(p, hipMemcpy(dsrc, src.data(), sizeof(long long) * src.size(), hipMemcpyHostToDevice), "copy");
+        D.items = ditems; D.dirs = ddirs; D.amask = damask; D.lagbits = dlagb; D.lagidx = dlagi;
+        D.lagsrc = dsrc; D.lagbuf = dlbuf; D.nlag = (long long)nl; D.lanes = p->A * p->G; D.A = p->A;
+        p->dir.level_off = dh.level_off;
+        p->dir.cyclic = dh.cyclic_directions;
+        p->desig_counts[1] = nl;   // lagged triples: only the faces that break cycles
     }
 
     // anisotropic scattering: harmonics of the directions (FP64 on the host, from

@@ -118,6 +118,25 @@ struct DevProblem {
     float lo[3], hi[3];          // bounding box of the mesh
 };
 
+// Per-direction sweep order (SNX_DESIGNATION_DIRECTION): the work items of the
+// level-synchronous sweep and the faces lagged to break cycles.  Device memory.
+struct DirDev {
+    const int *items;                 // [nitems]      task 8 K + o, bucketed by level
+    const unsigned long long *dirs;   // [nitems]      directions a of octant o solved by the item (bit a)
+    const unsigned char *amask;       // [8][C][A]     inflow faces of each direction (the problem's amask)
+    const unsigned char *lagbits;     // [8][C][A]     interior inflow faces lagged to break cycles
+    const int *lagidx;                // [8][C][A]     first lag slot of the direction's lagged faces (face order)
+    const long long *lagsrc;          // [nlag * 4]    hand-off index of the upwind node, group 0
+    float *lagbuf;                    // [nlag * 4][G] upwind values of the previous sweep
+    long long nlag;                   // lagged (direction, cell, face) triples
+    int lanes;                        // A * G: (direction, group) systems of one octant
+    int A;                            // directions per octant
+};
+hipError_t launch_lag_snapshot(const DirDev &D, const DevProblem *probs, int G, const int *stop, hipStream_t s);
+hipError_t launch_sweep_dir_level(const DirDev &D, const DevProblem *probs, int threads, long long begin,
+                                  long long end, const int *stop, hipStream_t s);
+hipError_t launch_dir_slots(const DevProblem *probs, int C, int G, const int *stop, hipStream_t s);
+
 // Higher-order elements (orders 2 and 3).  Reference tables of the order-p
 // element: the Gauss-Lobatto-Legendre nodes and the Gauss points and weights,
 // p + 1 of each.
@@ -264,5 +283,20 @@ bool problem_view(const snx_problem *p, DevProblem *out, int *device);
 int topology(int C, int nvert, const int *cell_vert, std::vector<int> &nbr, std::vector<int> &nbr_face,
              std::vector<unsigned> &perm, std::string &err);
 int product_quadrature(int npolar, int nazim, double *omega, double *w);
+// Host result of the per-direction ordering (see direction_orders in host.cpp).
+struct DirHost {
+    std::vector<int> items;                  // task 8 K + o of each work item, bucketed by level
+    std::vector<unsigned long long> dirs;    // directions of the item's octant it solves (bit a)
+    std::vector<long long> level_off;        // [levels + 1] offsets into items
+    std::vector<unsigned char> lagbits;      // [8][C][A] lagged inflow faces
+    std::vector<int> lagidx;                 // [8][C][A] first index into lag of the direction's lagged faces
+    struct Lag { int o, K, a, f; };
+    std::vector<Lag> lag;                    // lagged (octant, cell, direction, face), in that order
+    long long cyclic_directions = 0;         // directions whose graph had a cycle
+};
+int direction_orders(int C, int A, const std::vector<int> &nbr, const std::vector<int> &nbr_face,
+                     const std::vector<unsigned char> &amask, const std::vector<double> &xyz,
+                     const std::vector<int> &cell_vert, const std::vector<double> &omega, DirHost &out,
+                     std::string &err);
 
 }  // namespace snx

@@ -19,7 +19,7 @@ STATUS = {0: "SNX_OK", -1: "SNX_E_ARG", -2: "SNX_E_STATE", -3: "SNX_E_MESH", -4:
           -5: "SNX_E_DEVICE", -6: "SNX_E_OOM", -7: "SNX_E_NOCONV"}
 SNX_E_NOCONV = -7
 SWEEP_AMT, SWEEP_BSP = 0, 1
-DESIGNATION_OCTANT, DESIGNATION_ANGLE = 0, 1
+DESIGNATION_OCTANT, DESIGNATION_ANGLE, DESIGNATION_DIRECTION = 0, 1, 2
 NFEAT = 12          # node features of the learned initial guess (snx_gnn_features)
 
 EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_set_quadrature",

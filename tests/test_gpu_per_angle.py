@@ -251,3 +251,125 @@ def test_full_size_bench_workload_sampled():
             assert e <= TOL, (k, n, g, e)
             prev = ref
     p.close()
+
+
+# ------------------------------------------ per-direction order (designation 2)
+
+def _lag_count(o):
+    """Faces the oracle lags to break cycles (designation 2)."""
+    return int(sum(bin(int(x)).count("1") for x in o.angle_order()[1].ravel()))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_direction_order_chained_sweeps_match_the_oracle(name):
+    """Each direction in its own upwind order, faces lagged only inside strongly
+    connected components: three sweeps from the same flux against the oracle's
+    chain (designation 2, given its own previous angular flux), and the exact
+    number of lagged faces."""
+    from paper_2510_11513_amd import snx
+    torch = _torch()
+    make, threads = CASES[name]
+    prob = make()
+    print(f"[case] per-direction order {name}: C={prob.mesh.ncell} G={prob.mat.ngroup} nang={prob.nang} "
+          f"threads={threads}", flush=True)
+    p = _gpu(prob, designation=snx.DESIGNATION_DIRECTION, threads=threads)
+    o = oracle.Oracle.from_problem(prob, designation=2)
+    ds = p.designation_stats()
+    om, _ = oracle.quadrature(prob.npolar, prob.nazim)
+    differing, lagged_octant, tasks = _counts(o, om)
+    assert ds["designation"] == 2 and ds["lagged"] == _lag_count(o), (ds, _lag_count(o))
+    assert (ds["differing"], ds["tasks"]) == (differing, tasks)
+    assert ds["lagged"] < lagged_octant
+    phi32 = _phi_in(prob, 17)
+    pin = torch.from_numpy(phi32).cuda()
+    pairs = [(n, g) for n in range(0, prob.nang, max(1, prob.nang // 7)) for g in (0, prob.mat.ngroup - 1)]
+    psi_prev = None
+    for k in range(3):
+        out = p.sweep(pin)
+        torch.cuda.synchronize()
+        r = o.sweep(phi32.astype(np.float64), want_psi=True, psi_prev=psi_prev)
+        err = H.rel_err_per_group(out.cpu().numpy().astype(np.float64), r["phi"])
+        print(f"[case] sweep {k}: phi max rel err {err.max():.2e}", flush=True)
+        assert err.max() <= TOL, (k, err)
+        for n, g in pairs:
+            ref = r["psi"][n, :, g]
+            got = p.psi(n, g).cpu().numpy().astype(np.float64)
+            e = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300)
+            assert e <= TOL, (k, n, g, e)
+        psi_prev = r["psi"]
+    p.close()
+
+
+def test_direction_order_solve_and_refusals():
+    """A converged solve against the oracle's, with no more iterations than the
+    octant-order reading; an orthogonal mesh lags nothing and matches per-octant
+    designation; batches and reflective planes are refused."""
+    from paper_2510_11513_amd import snx
+    torch = _torch()
+    prob = _problem(4, 3, 2, 3, seed=6, kind=1, mesh_seed=0)
+    p2 = _gpu(prob, designation=snx.DESIGNATION_DIRECTION)
+    p1 = _gpu(prob, designation=snx.DESIGNATION_ANGLE)
+    phi2, i2 = p2.solve(0.0, 400, allow_noconv=True)
+    ref = oracle.Oracle.from_problem(prob, designation=2).solve(1e-12, 5000)
+    err = H.rel_err_per_group(phi2.cpu().numpy().astype(np.float64), ref["phi"])
+    print(f"[case] per-direction order solve: rel err {err.max():.2e}", flush=True)
+    assert err.max() <= TOL, err
+    _, j2 = p2.solve(1e-6, 2000)
+    _, j1 = p1.solve(1e-6, 2000)
+    print(f"[case] iterations to 1e-6: per-direction order {j2['iterations']}, octant order {j1['iterations']}",
+          flush=True)
+    assert j2["iterations"] <= j1["iterations"]
+    with pytest.raises(snx.SnxError):
+        snx.Batch([p2, p1])
+    p1.close()
+    p2.close()
+    flat = _problem(4, 4, 2, 2, seed=5, jitter=0.0)
+    pin = torch.from_numpy(_phi_in(flat, 9)).cuda()
+    q2 = _gpu(flat, designation=snx.DESIGNATION_DIRECTION)
+    q0 = _gpu(flat, designation=snx.DESIGNATION_OCTANT)
+    assert q2.designation_stats()["lagged"] == 0
+    a, b = q2.sweep(pin).cpu().numpy(), q0.sweep(pin).cpu().numpy()
+    assert np.abs(a - b).max() <= 1e-6 * np.abs(b).max()
+    q2.close()
+    q0.close()
+    r = snx.Problem.from_problem(prob, setup=False, designation=snx.DESIGNATION_DIRECTION)
+    r.set_reflective(1)
+    with pytest.raises(snx.SnxError):
+        r.setup()
+    r.close()
+
+
+def test_direction_order_full_size_bench_workload_sampled():
+    """32^3 / 96 directions / 16 groups in per-direction order: two chained sweeps,
+    sampled (direction, group) pairs against the oracle's chained single-pair
+    sweeps, and the lagged-face count at full size."""
+    from paper_2510_11513_amd import snx
+    torch = _torch()
+    prob = inputs.config_problem(2)
+    print(f"[case] per-direction order full size C={prob.mesh.ncell} nang={prob.nang} G={prob.mat.ngroup}",
+          flush=True)
+    p = _gpu(prob, designation=snx.DESIGNATION_DIRECTION)
+    o = oracle.Oracle.from_problem(prob, designation=2)
+    ds = p.designation_stats()
+    print(f"[case] lagged faces: gpu {ds['lagged']} oracle {_lag_count(o)}", flush=True)
+    assert ds["lagged"] == _lag_count(o)
+    phi32 = _phi_in(prob, 41)
+    pin = torch.from_numpy(phi32).cuda()
+    rng = np.random.default_rng(42)
+    per = prob.nang // 8
+    pairs = [(int(oc * per + rng.integers(per)), int(rng.integers(prob.mat.ngroup))) for oc in rng.permutation(8)[:4]]
+    got = []
+    for _ in range(2):
+        p.sweep(pin)
+        torch.cuda.synchronize()
+        got.append({pg: p.psi(*pg).cpu().numpy().astype(np.float64) for pg in pairs})
+    phi64 = phi32.astype(np.float64)
+    for n, g in pairs:
+        prev = None
+        for k in range(2):
+            ref = o.sweep_angle(phi64, n, g, psi_prev=prev)
+            e = np.abs(got[k][(n, g)] - ref).max() / max(np.abs(ref).max(), 1e-300)
+            print(f"[case] full size sweep {k} psi angle={n} group={g} rel err {e:.2e}", flush=True)
+            assert e <= TOL, (k, n, g, e)
+            prev = ref
+    p.close()
