@@ -283,6 +283,47 @@ def bsp_grid(n: int = 16, sweeps: int = 10):
     return {"workload": f"{n}^3 jittered hex, sigma_t 1, c 0.5; angles per octant x groups", "rows": rows}
 
 
+def angle_blocks(prob, ms_whole: float, sweeps: int = 20):
+    """Tasks of one (cell, octant, block of the octant's angles): the problem is
+    swept as a batch of angle-block sub-problems, which the same task machinery
+    runs with dependency counters per block, so a block's tasks traverse the
+    DAG on their own (the granularity of Section 3.4 and Algorithm 1, finer
+    than a whole octant).  Each split at its best width of 64, 128, 192, 256
+    threads; sweep kernel alone (HIP events)."""
+    import numpy as np
+    import torch
+    from paper_2510_11513_amd import snx
+    om, w = snx.quadrature_product(prob.npolar, prob.nazim)
+    A = om.shape[0] // 8
+    rows = [{"blocks": 1, "angles_per_block": A, "tasks": 8 * prob.mesh.ncell, "sweep_ms": round(ms_whole, 4),
+             "over_whole": 1.0}]
+    for nb in (2, 3, 4):
+        if A % nb:
+            continue
+        ab = A // nb
+        subs = []
+        for b in range(nb):
+            idx = np.concatenate([o * A + np.arange(b * ab, (b + 1) * ab) for o in range(8)])
+            subs.append(snx.Problem.from_problem(prob, quadrature=(om[idx].copy(), w[idx].copy())))
+        bt = snx.Batch(subs)
+        best = (1e300, 0)
+        for th in (64, 128, 192, 256):
+            if th < prob.mat.ngroup:
+                continue
+            bt.set_schedule(threads=th)
+            bt.sweep()
+            torch.cuda.synchronize()
+            ms = bt.profile_sweep(sweeps)
+            best = min(best, (ms, th))
+        tasks = bt.stats()["tasks"]
+        bt.close()
+        for q in subs:
+            q.close()
+        rows.append({"blocks": nb, "angles_per_block": ab, "tasks": tasks, "sweep_ms": round(best[0], 4),
+                     "threads": best[1], "over_whole": round(best[0] / ms_whole, 3)})
+    return {"rows": rows}
+
+
 def kernel_hash() -> str:
     path = os.path.join(ROOT, "paper_2510_11513_amd", "csrc", "k_sweep.hip")
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
@@ -485,6 +526,9 @@ def secondary(name: str, tune_cache: str, args):
         print("[bench] per-angle designation", file=sys.stderr, flush=True)
         _, info_oct = p.solve(prob.tol, 5000)
         out["per_angle"] = per_angle(prob, stats["threads"], tuned[1], ms_sweep, info_oct["iterations"], sweeps)
+    if args.angle_blocks:
+        print("[bench] angle blocks", file=sys.stderr, flush=True)
+        out["angle_blocks"] = angle_blocks(prob, ms_sweep)
     p.close()
     if args.extensions:
         print("[bench] optional physics", file=sys.stderr, flush=True)
@@ -516,6 +560,8 @@ def main():
     ap.add_argument("--paper-shape", type=int, default=1, help="also time the paper's 25-sweep 16^3 shape (0 = skip)")
     ap.add_argument("--per-angle", type=int, default=1,
                     help="also time the secondary workload under per-angle designation (0 = skip)")
+    ap.add_argument("--angle-blocks", type=int, default=1,
+                    help="also time angle-block tasks on the secondary workload (0 = skip)")
     ap.add_argument("--higher-order", type=int, default=1,
                     help="also time second and third order on the paper's 16^3 shape (0 = skip)")
     ap.add_argument("--extensions", type=int, default=1,

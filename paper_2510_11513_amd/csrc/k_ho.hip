@@ -22,8 +22,8 @@
 // undamped, so a plain FP32 solve loses accuracy along every path through the
 // mesh.  Each solve is therefore followed by mixed-precision iterative
 // refinement: the residual b - A x is formed in FP64 against the operator
-// assembled in FP64 (B = Om . S - sum Om . F kept in LDS as an FP32 pair
-// hi + lo, the right-hand side's face terms from the same operators), and the
+// assembled in FP64 (B = Om . S - sum Om . F kept in LDS in FP64, the
+// right-hand side's face terms from the same FP64 operators), and the
 // correction reuses the FP32 LU factors, whose multipliers stay in the row
 // entries that elimination leaves behind.  The streaming and face matrices
 // S and F are stored in FP64: rounded separately to FP32 they no longer satisfy
@@ -362,6 +362,7 @@ __device__ __forceinline__ void lu_solve(float (&row)[N], float &b, float &x, fl
                                          std::integer_sequence<int, K...>, std::integer_sequence<int, I...>) {
     (lu_step2<N, LP, 2 * I, KEEP>(row, b, piv, r), ...);       // pivots in pairs
     if constexpr (N % 2) lu_step<N, N - 1>(row, b, piv, r);      // the odd last one (no row below it)
+    asm volatile("" : "+v"(r), "+v"(half));                      // fresh lane masks for this pass
     (back_step<N, H, K>(row, b, x, r, half), ...);
 }
 // A second solve with the factors of lu_solve: forward elimination replayed
@@ -370,126 +371,201 @@ template <int N, int H, int... K, int... I>
 __device__ __forceinline__ void lu_resolve(const float (&row)[N], float &b, float &x, int r, int half,
                                            std::integer_sequence<int, K...>, std::integer_sequence<int, I...>) {
     (replay_step2<N, H, 2 * I>(row, b, r, half), ...);
+    asm volatile("" : "+v"(r), "+v"(half));
     (back_step<N, H, K>(row, b, x, r, half), ...);
 }
 
+// Node of face f at face position (pu, pv): the face's axis coordinate fixed at
+// its side, the two free axes in increasing order (the inverse of face_pos).
+template <int P> __device__ __forceinline__ int face_node(int f, int pu, int pv) {
+    constexpr int m = P + 1;
+    int u, v;
+    face_axes(f, u, v);
+    const int stride[3] = {1, m, m * m};
+    return (f & 1) * P * stride[f >> 1] + pu * stride[u] + pv * stride[v];
+}
+
 // One workgroup per (task, direction) of a level: B = Om . S - sum_{f in}
-// Om . F_f and M go to LDS once, then the workgroup's wave halves solve the
-// direction's groups, one system each.
+// Om . F_f and M go to LDS once, then the workgroup's waves (order 3) or wave
+// halves (order 2) solve the direction's groups, one system each.
+//
+// Every global load a system needs comes one group ahead: the source dofs,
+// sigma_t and the upwind traces of the next group are requested before the
+// current group's solve and land during it (the traces through a small LDS
+// buffer per system, since every row of a system reads all of them).  The
+// element data are requested all at once before any is used.
 template <int P, int REFINE>
 __device__ __forceinline__ void ho_sweep_body(const HoDev &D, int begin) {
     constexpr int m = P + 1, N = m * m * m, NF = m * m;
     constexpr int LD = (N % 2 == 0) ? N + 1 : N + 2;        // odd row stride: lanes' rows sit in different banks
     constexpr int LP = ((N + 1) + 3) / 4 * 4;               // pivot buffer: row and rhs, 16-byte aligned
     constexpr int H = N <= 32 ? 32 : 64, SPW = 64 / H, SPB = 4 * SPW;
-    __shared__ float sB[N * LD], sBlo[N * LD], sM[N * LD];   // B = hi + lo (FP64 assembly)
-    __shared__ float sOF[6][NF * NF], sOFlo[6][NF * NF];     // Om . F_f = hi + lo (FP64 assembly)
-    __shared__ __align__(16) float sPiv[4 * SPW][2 * LP];   // pivot rows k and k+1
+    constexpr int NN = N * N, FF = NF * NF, PER = (NN + 255) / 256;
+    static_assert(FF <= 256 && 6 * NF <= 2 * H, "one face entry per thread, two trace slots per lane");
+    __shared__ double sB[N * LD];                             // B in FP64
+    __shared__ float sM[N * LD];
+    __shared__ double sOF[6][FF];                             // Om . F_f of the inflow faces in FP64
+    __shared__ __align__(16) float sPiv[4 * SPW][2 * LP];    // pivot rows k and k+1; x (FP64) for the residual
+    __shared__ float sTr[4 * SPW][6 * NF];                    // each system's upwind traces, inflow-face order
+    __shared__ int sPm[6][NF], sNb[6], sFl[6];
 
     const int A = D.A, C = D.C, G = D.G;
     const int t = begin + (int)(blockIdx.x / (unsigned)A), dir = (int)(blockIdx.x % (unsigned)A);
     const int task = D.tasks[t];
     const int K = task >> 3, o = task & 7, n = o * A + dir;
     const int mask = D.inmask[(size_t)o * C + K];
+    const int nin = __popc(mask);
     const double dx = D.omega64[3 * n], dy = D.omega64[3 * n + 1], dz = D.omega64[3 * n + 2];
     const int tid = threadIdx.x;
-    const size_t NN = (size_t)N * N, FF = (size_t)NF * NF;
     const double *S = D.S + 3 * (size_t)K * NN;
     const float *Mk = D.M + (size_t)K * NN;
     const double *Fk = D.F + 6 * 3 * (size_t)K * FF;
 
-    for (int e = tid; e < N * N; e += 256) {
-        const int i = e / N, j = e % N;
-        double b = dx * S[e] + dy * S[NN + e] + dz * S[2 * NN + e];
-        for (int f = 0; f < 6; ++f) {
-            if (!((mask >> f) & 1)) continue;
-            const int pi = face_pos<P>(f, i), pj = face_pos<P>(f, j);
-            if (pi < 0 || pj < 0) continue;
-            const double *Ff = Fk + (size_t)f * 3 * FF + pi * NF + pj;
-            b -= dx * Ff[0] + dy * Ff[FF] + dz * Ff[2 * FF];
+    // element data: every load in flight before the first use
+    double s0[PER], s1[PER], s2[PER];
+    float mv[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = tid + 256 * q;
+        if (e < NN) {
+            s0[q] = S[e];
+            s1[q] = S[NN + e];
+            s2[q] = S[2 * NN + e];
+            mv[q] = Mk[e];
         }
-        const float hi = (float)b;
-        sB[i * LD + j] = hi;
-        sBlo[i * LD + j] = (float)(b - (double)hi);
-        sM[i * LD + j] = Mk[e];
     }
-    for (int e = tid; e < 6 * NF * NF; e += 256) {
-        const int f = e / (NF * NF), kl = e % (NF * NF);
-        if (!((mask >> f) & 1)) continue;
-        const double *Ff = Fk + (size_t)f * 3 * FF + kl;
-        const double of = dx * Ff[0] + dy * Ff[FF] + dz * Ff[2 * FF];
-        const float hi = (float)of;
-        sOF[f][kl] = hi;
-        sOFlo[f][kl] = (float)(of - (double)hi);
+    double fo[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        fo[f] = 0.0;
+        if (((mask >> f) & 1) && tid < FF) {
+            const double *Ff = Fk + (size_t)f * 3 * FF + tid;
+            fo[f] = dx * Ff[0] + dy * Ff[FF] + dz * Ff[2 * FF];
+        }
     }
+    if (tid < 6 * NF) {
+        const int f = tid / NF;
+        sPm[f][tid % NF] = ((mask >> f) & 1) ? D.perm[(6 * (size_t)K + f) * NF + tid % NF] : 0;
+    }
+    if (tid < 6) {
+        sNb[tid] = D.nbr[6 * K + tid];
+        int mm = mask;
+        for (int k = 0; k < tid && mm; ++k) mm &= mm - 1;
+        sFl[tid] = mm ? __builtin_ctz(mm) : 0;             // the tid-th inflow face
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = tid + 256 * q;
+        if (e < NN) {
+            const int i = e / N, j = e % N;
+            sB[i * LD + j] = dx * s0[q] + dy * s1[q] + dz * s2[q];
+            sM[i * LD + j] = mv[q];
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+        if (((mask >> f) & 1) && tid < FF) sOF[f][tid] = fo[f];
     __syncthreads();
+    // the inflow faces' terms, one face at a time (faces share edge nodes)
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        if (!((mask >> f) & 1)) continue;
+        if (tid < FF) {
+            const int pi = tid / NF, pj = tid % NF;
+            const int i = face_node<P>(f, pi % m, pi / m), j = face_node<P>(f, pj % m, pj / m);
+            sB[i * LD + j] -= fo[f];
+        }
+        __syncthreads();
+    }
 
     const int lane = tid & 63, wave = tid >> 6;
     const int half = lane / H, r = lane % H;
     const int rr = r < N ? r : N - 1;                        // lanes past the last row compute on a copy of it
-    float *piv = sPiv[wave * SPW + half];
+    const int sys = wave * SPW + half;
+    float *piv = sPiv[sys];
+    float *tr = sTr[sys];
     int fpos[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) fpos[f] = ((mask >> f) & 1) ? face_pos<P>(f, rr) : -1;
 
-    for (int g0 = 0; g0 < G; g0 += SPB) {
-        const int g = g0 + wave * SPW + half;
-        const bool valid = g < G && r < N;
+    // this lane's two trace slots: inflow face k = s / NF (in face order), node l = s % NF
+    const int ntr = nin * NF;
+    auto trace = [&](int s, int g) -> float {
+        if (s >= ntr) return 0.f;
+        const int f = sFl[s / NF], nb = sNb[f];
+        if (nb < 0) return D.psib ? D.psib[g] : 0.f;
+        return D.psi[(((size_t)n * C + nb) * G + g) * N + sPm[f][s % NF]];
+    };
+    float a0, a1, rv, sg;
+    auto fetch = [&](int g) {
         const int gg = g < G ? g : G - 1;
-        const float sig = D.sigt[(size_t)K * G + gg];
+        sg = D.sigt[(size_t)K * G + gg];
+        rv = D.R[((size_t)K * G + gg) * N + rr];
+        a0 = trace(r, gg);
+        a1 = trace(r + H, gg);
+    };
+    fetch(sys);
+
+    for (int g0 = 0; g0 < G; g0 += SPB) {
+        const int g = g0 + sys;
+        const bool valid = g < G && r < N;
+        // The elimination compares the lane's row with each pivot index; kept
+        // opaque here, those compares are made where they are used instead of
+        // being hoisted out of the loop as hundreds of live lane masks.
+        int rl = r, hl = half;
+        asm volatile("" : "+v"(rl), "+v"(hl));
+        if (r < ntr) tr[r] = a0;
+        if (r + H < ntr) tr[r + H] = a1;
+        wave_lds_sync();
+        const float sig = sg;
+        double bd = (double)rv;
+        fetch(g + SPB);                                      // the next group's inputs land during this solve
         float row[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) row[j] = __builtin_fmaf(sig, sM[rr * LD + j], sB[rr * LD + j]);
+        for (int j = 0; j < N; ++j) row[j] = __builtin_fmaf(sig, sM[rr * LD + j], (float)sB[rr * LD + j]);
         // right-hand side in FP64 with the same face operators as the matrix (an
         // FP32 one would break the exact cancellation of the face terms on a
         // constant solution)
-        double bd = (double)D.R[((size_t)K * G + gg) * N + rr];
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
-            if (fpos[f] < 0) continue;
-            const int nb = D.nbr[6 * K + f];
-            const float *of = sOF[f] + fpos[f] * NF, *ofl = sOFlo[f] + fpos[f] * NF;
-            if (nb >= 0) {
-                const float *up = D.psi + (((size_t)n * C + nb) * G + gg) * N;
-                const int *pm = D.perm + (6 * (size_t)K + f) * NF;
-                for (int l = 0; l < NF; ++l) bd -= ((double)of[l] + (double)ofl[l]) * (double)up[pm[l]];
-            } else {
-                const double pb = D.psib ? (double)D.psib[gg] : 0.0;
-                double s = 0.0;
-                for (int l = 0; l < NF; ++l) s += (double)of[l] + (double)ofl[l];
-                bd -= s * pb;
-            }
+            if (fpos[f] < 0) continue;                       // not inflow, or this row's node is not on it
+            const double *of = sOF[f] + fpos[f] * NF;
+            const float *u = tr + __popc(mask & ((1 << f) - 1)) * NF;   // its slot among the inflow faces
+#pragma unroll
+            for (int l = 0; l < NF; ++l) bd -= of[l] * (double)u[l];
         }
         const double b0 = bd;
         float b = (float)bd;
         float x = 0.f;
-        lu_solve<N, H, LP, (REFINE > 0)>(row, b, x, piv, r, half, std::make_integer_sequence<int, N>{},
-                           std::make_integer_sequence<int, N / 2>{});
-        // refinement: residual in FP64 against sigma_t M + (B hi + lo), then the
-        // correction from the same factors.  x reaches every lane of the system
-        // through its pivot buffer (a wave's LDS accesses run in issue order).
+        lu_solve<N, H, LP, (REFINE > 0)>(row, b, x, piv, rl, hl, std::make_integer_sequence<int, N>{},
+                                         std::make_integer_sequence<int, N / 2>{});
+        // refinement: residual in FP64, b0 - B x - sigma_t M x with B in FP64, then
+        // the correction from the same factors.  x reaches every lane of the system
+        // in FP64 through its pivot buffer (a wave's LDS accesses run in issue order).
 #pragma unroll 1
         for (int it = 0; it < REFINE; ++it) {
-            if (r < N) piv[r] = x;
+            double *xd = reinterpret_cast<double *>(piv);
+            if (r < N) xd[r] = (double)x;
             wave_lds_sync();
-            const float4 *x4 = reinterpret_cast<const float4 *>(piv);
-            double res = b0;
-#pragma unroll 1
-            for (int c = 0; c < (N + 3) / 4; ++c) {
-                const float4 xv = x4[c];
-                const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int j = 4 * c + e;
-                    if (j < N) {
-                        const double a = (double)sig * (double)sM[rr * LD + j] +
-                                         ((double)sB[rr * LD + j] + (double)sBlo[rr * LD + j]);
-                        res = __builtin_fma(-a, (double)xs[e], res);
-                    }
-                }
+            const double2 *x2 = reinterpret_cast<const double2 *>(piv);
+            double sb = 0.0, sm = 0.0;
+#pragma unroll 4
+            for (int c = 0; c < N / 2; ++c) {
+                const double2 xv = x2[c];
+                sb = __builtin_fma(sB[rr * LD + 2 * c], xv.x, sb);
+                sm = __builtin_fma((double)sM[rr * LD + 2 * c], xv.x, sm);
+                sb = __builtin_fma(sB[rr * LD + 2 * c + 1], xv.y, sb);
+                sm = __builtin_fma((double)sM[rr * LD + 2 * c + 1], xv.y, sm);
             }
+            if constexpr (N % 2) {
+                const double xl = xd[N - 1];
+                sb = __builtin_fma(sB[rr * LD + N - 1], xl, sb);
+                sm = __builtin_fma((double)sM[rr * LD + N - 1], xl, sm);
+            }
+            const double res = __builtin_fma(-(double)sig, sm, b0 - sb);
             float rb = (float)res, dxk = 0.f;
-            lu_resolve<N, H>(row, rb, dxk, r, half, std::make_integer_sequence<int, N>{},
+            asm volatile("" : "+v"(rl), "+v"(hl));   // not the masks of the first solve either
+            lu_resolve<N, H>(row, rb, dxk, rl, hl, std::make_integer_sequence<int, N>{},
                              std::make_integer_sequence<int, N / 2>{});
             x += dxk;
             wave_lds_sync();      // every lane has read the old x before the next write
@@ -502,7 +578,9 @@ __device__ __forceinline__ void ho_sweep_body(const HoDev &D, int begin) {
 // order 3 runs fastest at two waves per SIMD (each with twice the work between
 // LDS round trips); the refinement's replay keeps the multipliers alive, so
 // holding it there spills a few registers.
-__global__ __launch_bounds__(256) void k_ho_sweep2(HoDev D, int begin) { ho_sweep_body<2, 1>(D, begin); }
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_ho_sweep2(HoDev D, int begin) {
+    ho_sweep_body<2, 1>(D, begin);
+}
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_ho_sweep3(HoDev D, int begin) {
     ho_sweep_body<3, 1>(D, begin);
 }

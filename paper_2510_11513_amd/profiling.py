@@ -151,11 +151,40 @@ def sq_summary(db: str, out_path: str, command: str, tasks: int, solves: int, be
     return text
 
 
+def counter_table(db: str, out_path: str, command: str, kernel: str, units: float, unit_name: str,
+                  title: str) -> str:
+    """Totals of every counter in the run over the dispatches of the kernels whose
+    names match `kernel`, per dispatch and per unit of work (`units` units over
+    all of those dispatches)."""
+    con = sqlite3.connect(db)
+    names = [r[0] for r in con.execute("select distinct counter_name from counters_collection")]
+    lines = [f"# {title} (rocprofv3)", "", f"command: `{command}`", "",
+             f"| counter | dispatches | total | per dispatch | per {unit_name} |", "|---|---|---|---|---|"]
+    tot = {}
+    for c in sorted(names):
+        v = [x for k, xs in _counter(db, c).items() if re.search(kernel, k) for x in xs]
+        if not v:
+            continue
+        tot[c] = sum(v)
+        lines.append(f"| {c} | {len(v)} | {sum(v):.4e} | {sum(v) / len(v):.4e} | {sum(v) / units:.1f} |")
+    if "SQ_WAVE_CYCLES" in tot:
+        for c in ("SQ_WAIT_INST_LDS", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_VALU"):
+            if c in tot:
+                lines.append(f"\n- {c} / SQ_WAVE_CYCLES = {tot[c] / tot['SQ_WAVE_CYCLES']:.3f}")
+    text = "\n".join(lines) + "\n"
+    with open(out_path, "w") as fh:
+        fh.write(text)
+    return text
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         print(stats_summary(sys.argv[2], sys.argv[3], sys.argv[4]))
     elif sys.argv[1] == "pmc":
         print(pmc_summary(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6]))
+    elif sys.argv[1] == "table":
+        print(counter_table(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], float(sys.argv[6]), sys.argv[7],
+                            sys.argv[8]))
     elif sys.argv[1] == "sq":
         print(sq_summary(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), int(sys.argv[6]),
                          sys.argv[7] if len(sys.argv) > 7 else None))
