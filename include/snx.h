@@ -65,7 +65,11 @@ typedef struct snx_solve_info {
     double  solves_per_s;    /* cell-angle-group solves per second over the solve  */
 } snx_solve_info;
 
-/* Create a problem bound to HIP device `device`.  *out receives the handle. */
+/* Create a problem bound to HIP device `device`: one instance of the
+ * fixed-source transport problem of Eq. 1 (mesh, quadrature, cross sections,
+ * source and boundary condition, set below) with everything the sweep keeps
+ * on the device.  *out receives the handle.  Errors: SNX_E_ARG (no such
+ * device), SNX_E_DEVICE, SNX_E_OOM. */
 snx_status snx_create(snx_problem **out, int32_t device);
 /* Free the problem and every device buffer it owns.  NULL is ignored. */
 void snx_destroy(snx_problem *p);
@@ -98,8 +102,12 @@ snx_status snx_quadrature_product(int32_t npolar, int32_t nazim, double *omega, 
 snx_status snx_set_materials(snx_problem *p, int32_t ngroup, const double *sigma_t,
                              const double *sigma_s, const double *q);
 
-/* Boundary condition on inflow boundary faces: kind 0 = vacuum (default),
- * kind 1 = isotropic inflow psi_in[G] (host float64). */
+/* Boundary condition of Eq. 1 on the inflow boundary faces (Omega . n < 0),
+ * which the upwind traces of the sweep (Section 2) take there in place of a
+ * neighbour's: kind 0 = vacuum (default, psi = 0), kind 1 = isotropic inflow
+ * psi = psi_in[g] for every incoming direction (host float64 [G]).  Errors:
+ * SNX_E_ARG (another kind, or kind 1 without psi_in or before the materials
+ * fix G). */
 snx_status snx_set_boundary(snx_problem *p, int32_t kind, const double *psi_in);
 
 /* Anisotropic within-group scattering through flux moments (the moment
@@ -422,11 +430,13 @@ snx_status snx_batch_set_sweep_stats(snx_batch *b, int32_t phases);
  * stream-ordered on `stream` unless it says synchronous. */
 typedef struct snx_gnn snx_gnn;
 
-/* Network on HIP device `device`; hidden must be 64, 1 <= layers <= 8.
- * Weights are drawn normal with variance 2/fan_in from a 64-bit Mersenne
- * twister seeded with `seed`; biases are zero.  Errors: SNX_E_ARG, SNX_E_DEVICE
- * (message from snx_gnn_last_error(NULL)). */
-snx_status snx_gnn_create(snx_gnn **out, int32_t device, int32_t hidden, int32_t layers, uint64_t seed);
+/* Network on the calling thread's current HIP device; hidden must be 64,
+ * 1 <= layers <= 8.  Weights are drawn normal with variance 2/fan_in from a
+ * 64-bit Mersenne twister seeded with `seed`; biases are zero.  Errors:
+ * SNX_E_ARG, SNX_E_DEVICE (message from snx_gnn_last_error(NULL)). */
+snx_status snx_gnn_create(snx_gnn **out, int32_t hidden, int32_t layers, uint64_t seed);
+/* As snx_gnn_create, on HIP device `device`. */
+snx_status snx_gnn_create_on(snx_gnn **out, int32_t device, int32_t hidden, int32_t layers, uint64_t seed);
 /* Free the network and its device memory.  NULL is ignored. */
 void snx_gnn_destroy(snx_gnn *g);
 const char *snx_gnn_last_error(const snx_gnn *g);
@@ -456,11 +466,23 @@ snx_status snx_gnn_forward(snx_gnn *g, const float *x, const int32_t *nbr, int64
  * of snx_gnn_num_params floats, may be NULL).  Synchronous. */
 snx_status snx_gnn_grad(snx_gnn *g, const float *x, const int32_t *nbr, int64_t ncell, int32_t G, const float *y,
                         float *loss, float *grad_host, void *stream);
-/* One AdamW step on the graph (x, nbr, y) with learning rate lr > 0 and
+/* One AdamW step towards a converged flux of a set-up problem: the features
+ * of p and the targets of device phi_target [C][G][8] (snx_gnn_features,
+ * snx_gnn_targets) into the network's workspace, then the step of
+ * snx_gnn_train_step_graph with learning rate lr > 0 and the network's weight
+ * decay (1e-4 unless set).  *loss (may be NULL) is the loss before the step.
+ * SNX_E_STATE if p is not set up, SNX_E_ARG if it lives on another device.
+ * Synchronous (the loss is read back). */
+snx_status snx_gnn_train_step(snx_gnn *g, snx_problem *p, const float *phi_target, float lr, float *loss,
+                              void *stream);
+/* Decoupled weight decay (>= 0) of snx_gnn_train_step. */
+snx_status snx_gnn_set_weight_decay(snx_gnn *g, float weight_decay);
+/* One AdamW step on a graph given as device arrays (x, nbr, y), as a training
+ * loop over many stored instances runs it, with learning rate lr > 0 and
  * decoupled weight decay; *loss (may be NULL) is the loss before the step.
  * Synchronous (the loss is read back). */
-snx_status snx_gnn_train_step(snx_gnn *g, const float *x, const int32_t *nbr, int64_t ncell, int32_t G,
-                              const float *y, float lr, float weight_decay, float *loss, void *stream);
+snx_status snx_gnn_train_step_graph(snx_gnn *g, const float *x, const int32_t *nbr, int64_t ncell, int32_t G,
+                                    const float *y, float lr, float weight_decay, float *loss, void *stream);
 /* Predicted starting flux of a set-up problem into device phi0 [C][G][8]:
  * max(exp(z) - 1e-4, 0) on every dof of a cell.  SNX_E_STATE if p is not set
  * up, SNX_E_ARG if it lives on another device. */

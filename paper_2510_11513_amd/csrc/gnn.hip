@@ -31,6 +31,7 @@ struct snx_gnn {
     std::vector<void *> Wb, Wt;        // bf16 copies of the layer weights: [2H][H] and [H][2H]
     int nparams = 0;
     long long step = 0;
+    float weight_decay = 1e-4f;        // of snx_gnn_train_step (the problem-level step)
     // workspace
     long long cap_nodes = 0;
     int cap_cells = 0;
@@ -154,7 +155,7 @@ snx_status backward(snx_gnn *g, const float *x, const int *nbr, int C, int G, co
 
 extern "C" {
 
-snx_status snx_gnn_create(snx_gnn **out, int32_t device, int32_t hidden, int32_t layers, uint64_t seed) {
+snx_status snx_gnn_create_on(snx_gnn **out, int32_t device, int32_t hidden, int32_t layers, uint64_t seed) {
     if (!out) return gfail(nullptr, SNX_E_ARG, "out is NULL");
     *out = nullptr;
     if (hidden != H) return gfail(nullptr, SNX_E_ARG, "the network's hidden width is 64");
@@ -312,8 +313,8 @@ snx_status snx_gnn_grad(snx_gnn *g, const float *x, const int32_t *nbr, int64_t 
     return SNX_OK;
 }
 
-snx_status snx_gnn_train_step(snx_gnn *g, const float *x, const int32_t *nbr, int64_t ncell, int32_t G, const float *y,
-                              float lr, float weight_decay, float *loss, void *stream) {
+snx_status snx_gnn_train_step_graph(snx_gnn *g, const float *x, const int32_t *nbr, int64_t ncell, int32_t G,
+                                    const float *y, float lr, float weight_decay, float *loss, void *stream) {
     if (!g || !x || !nbr || !y || ncell < 1 || G < 1 || !(lr > 0.f)) return SNX_E_ARG;
     GCHK(g, hipSetDevice(g->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
@@ -324,6 +325,34 @@ snx_status snx_gnn_train_step(snx_gnn *g, const float *x, const int32_t *nbr, in
     const float c1 = 1.f - std::pow(b1, (float)g->step), c2 = 1.f - std::pow(b2, (float)g->step);
     GCHK(g, gnn_adamw(g->params, g->grad, g->m, g->v, g->nparams, lr, b1, b2, 1e-8f, weight_decay, c1, c2, s), "adamw");
     return refresh_bf16(g, s);
+}
+
+snx_status snx_gnn_create(snx_gnn **out, int32_t hidden, int32_t layers, uint64_t seed) {
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return gfail(nullptr, SNX_E_DEVICE, "no current HIP device");
+    return snx_gnn_create_on(out, device, hidden, layers, seed);
+}
+
+snx_status snx_gnn_set_weight_decay(snx_gnn *g, float weight_decay) {
+    if (!g || !(weight_decay >= 0.f)) return SNX_E_ARG;
+    g->weight_decay = weight_decay;
+    return SNX_OK;
+}
+
+snx_status snx_gnn_train_step(snx_gnn *g, snx_problem *p, const float *phi_target, float lr, float *loss,
+                              void *stream) {
+    if (!g || !p || !phi_target || !(lr > 0.f)) return SNX_E_ARG;
+    DevProblem P;
+    int dev = 0;
+    if (!problem_view(p, &P, &dev)) return gfail(g, SNX_E_STATE, "the problem is not set up");
+    if (dev != g->device) return gfail(g, SNX_E_ARG, "network and problem are on different devices");
+    GCHK(g, hipSetDevice(g->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    snx_status st = ensure_workspace(g, (long long)P.C * P.G, P.C);
+    if (st) return st;
+    GCHK(g, gnn_features(P, g->x, g->nbr, s), "features");
+    GCHK(g, gnn_targets(phi_target, (long long)P.C * P.G, g->y, s), "targets");
+    return snx_gnn_train_step_graph(g, g->x, g->nbr, P.C, P.G, g->y, lr, g->weight_decay, loss, stream);
 }
 
 snx_status snx_gnn_predict(snx_gnn *g, snx_problem *p, float *phi0, void *stream) {

@@ -30,7 +30,8 @@ EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_s
            "snx_batch_solve", "snx_batch_profile_sweep", "snx_batch_stats", "snx_gnn_create", "snx_gnn_destroy",
            "snx_gnn_last_error", "snx_gnn_num_params", "snx_gnn_get_params", "snx_gnn_set_params", "snx_gnn_save",
            "snx_gnn_load", "snx_gnn_features", "snx_gnn_targets", "snx_gnn_forward", "snx_gnn_grad",
-           "snx_gnn_train_step", "snx_gnn_predict", "snx_set_sweep_mode", "snx_batch_set_sweep_mode",
+           "snx_gnn_train_step", "snx_gnn_train_step_graph", "snx_gnn_create_on",
+           "snx_gnn_set_weight_decay", "snx_gnn_predict", "snx_set_sweep_mode", "snx_batch_set_sweep_mode",
            "snx_get_psi", "snx_set_sweep_stats", "snx_batch_set_sweep_stats", "snx_set_designation",
            "snx_designation_stats", "snx_set_group_scattering", "snx_solve_outer", "snx_set_reflective",
            "snx_set_anisotropy", "snx_get_schedule", "snx_batch_solve_outer", "snx_set_order", "snx_get_order",
@@ -115,7 +116,9 @@ def load(path: str = LIB_PATH):
     L.snx_batch_profile_sweep.argtypes = [_vp, ct.c_int32, ct.POINTER(ct.c_double), _vp]
     L.snx_batch_stats.argtypes = [_vp, _vp]
     _fp = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
-    L.snx_gnn_create.argtypes = [ct.POINTER(_vp), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_uint64]
+    L.snx_gnn_create.argtypes = [ct.POINTER(_vp), ct.c_int32, ct.c_int32, ct.c_uint64]
+    L.snx_gnn_create_on.argtypes = [ct.POINTER(_vp), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_uint64]
+    L.snx_gnn_set_weight_decay.argtypes = [_vp, ct.c_float]
     L.snx_gnn_destroy.argtypes = [_vp]
     L.snx_gnn_destroy.restype = None
     L.snx_gnn_last_error.argtypes = [_vp]
@@ -129,8 +132,9 @@ def load(path: str = LIB_PATH):
     L.snx_gnn_targets.argtypes = [_vp, ct.c_int64, ct.c_int32, _vp, _vp]
     L.snx_gnn_forward.argtypes = [_vp, _vp, _vp, ct.c_int64, ct.c_int32, _vp, _vp]
     L.snx_gnn_grad.argtypes = [_vp, _vp, _vp, ct.c_int64, ct.c_int32, _vp, ct.POINTER(ct.c_float), _vp, _vp]
-    L.snx_gnn_train_step.argtypes = [_vp, _vp, _vp, ct.c_int64, ct.c_int32, _vp, ct.c_float, ct.c_float,
-                                     ct.POINTER(ct.c_float), _vp]
+    L.snx_gnn_train_step.argtypes = [_vp, _vp, _vp, ct.c_float, ct.POINTER(ct.c_float), _vp]
+    L.snx_gnn_train_step_graph.argtypes = [_vp, _vp, _vp, ct.c_int64, ct.c_int32, _vp, ct.c_float, ct.c_float,
+                                           ct.POINTER(ct.c_float), _vp]
     L.snx_gnn_predict.argtypes = [_vp, _vp, _vp, _vp]
     for name in EXPORTS:
         if name not in _NO_STATUS:
@@ -520,7 +524,7 @@ class Gnn:
         L = load()
         _init_torch()
         h = ct.c_void_p()
-        rc = L.snx_gnn_create(ct.byref(h), device, hidden, layers, seed)
+        rc = L.snx_gnn_create_on(ct.byref(h), device, hidden, layers, seed)
         if rc:
             raise SnxError(rc, L.snx_gnn_last_error(None).decode())
         self.h = h
@@ -608,11 +612,24 @@ class Gnn:
         return loss.value, g
 
     def train_step(self, x, nbr, y, lr: float, weight_decay: float = 0.0, stream=None) -> float:
+        """One AdamW step on a stored graph (snx_gnn_train_step_graph); returns the loss before it."""
         C, G = self._shape(x, nbr)
         loss = ct.c_float()
-        self._check(load().snx_gnn_train_step(self.h, _ptr(x), _ptr(nbr), C, G, _ptr(y), lr, weight_decay,
-                                              ct.byref(loss), _stream(stream)), "train_step")
+        self._check(load().snx_gnn_train_step_graph(self.h, _ptr(x), _ptr(nbr), C, G, _ptr(y), lr, weight_decay,
+                                                    ct.byref(loss), _stream(stream)), "train_step_graph")
         return loss.value
+
+    def train_step_problem(self, problem: "Problem", phi_target, lr: float, stream=None) -> float:
+        """One AdamW step towards a converged flux of a set-up problem (snx_gnn_train_step)."""
+        if phi_target.numel() != problem.ncell * problem.G * 8 or not phi_target.is_contiguous():
+            raise ValueError("phi_target holds [ncell][G][8] contiguous floats")
+        loss = ct.c_float()
+        self._check(load().snx_gnn_train_step(self.h, problem.h, _ptr(phi_target), lr, ct.byref(loss),
+                                              _stream(stream)), "train_step")
+        return loss.value
+
+    def set_weight_decay(self, weight_decay: float):
+        self._check(load().snx_gnn_set_weight_decay(self.h, weight_decay), "set_weight_decay")
 
     def predict(self, problem: "Problem", stream=None):
         """Starting flux [C, G, 8] of a set-up problem."""

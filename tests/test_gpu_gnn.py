@@ -132,6 +132,34 @@ def test_training_reduces_loss_and_is_deterministic():
     assert hist[0][-1] < 0.2 * hist[0][0], (hist[0][0], hist[0][-1])
 
 
+def test_problem_training_step_equals_the_graph_step():
+    """snx_gnn_train_step(network, problem, converged flux) is the graph step on
+    the problem's features and targets with the network's weight decay, bit for
+    bit; snx_gnn_create takes the current device."""
+    import torch
+    from paper_2510_11513_amd import snx
+    pr = _problem(5)
+    p = snx.Problem.from_problem(pr)
+    phi, _ = p.solve(1e-6, 3000)
+    x, nbr = snx.Gnn.features(p)
+    y = snx.Gnn.targets(phi)
+    a, b = snx.Gnn(0, 4, seed=11), snx.Gnn(0, 4, seed=11)
+    b.set_weight_decay(3e-4)
+    la = [a.train_step(x, nbr, y, 2e-3, 3e-4) for _ in range(3)]
+    lb = [b.train_step_problem(p, phi, 2e-3) for _ in range(3)]
+    assert la == lb, (la, lb)
+    assert np.array_equal(a.params(), b.params())
+    with pytest.raises(ValueError):
+        b.train_step_problem(p, phi[:, :1].contiguous(), 2e-3)
+    h = snx.ct.c_void_p()
+    torch.cuda.set_device(0)
+    assert snx.load().snx_gnn_create(snx.ct.byref(h), 64, 4, 11) == 0
+    n = snx.ct.c_int64()
+    assert snx.load().snx_gnn_num_params(h, snx.ct.byref(n)) == 0 and n.value == a.nparams
+    snx.load().snx_gnn_destroy(h)
+    p.close()
+
+
 def test_targets_are_log_cell_average():
     import torch
     from paper_2510_11513_amd import snx
