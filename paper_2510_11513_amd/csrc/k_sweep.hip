@@ -633,6 +633,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         int buf = 0;
         for (int base = 0; ONE ? base == 0 : base < AG; base += NT, buf ^= 1) {
             const int pi = base + tid;
+            // The task's inflow mask and neighbour ids, kept opaque to the compiler
+            // in each round: the per-face tests made on them (inflow face, boundary
+            // face) are then scalar instructions at their use, not 64-bit lane masks
+            // computed once per task and held across the round loop, which ran out
+            // of scalar registers (spilled to vector-register lanes and reloaded by
+            // v_readlane in every round).
+            int fmask = mask;
+            int fnb[6];
+#pragma unroll
+            for (int f = 0; f < 6; ++f) fnb[f] = nb[f];
+            asm volatile("" : "+s"(fmask), "+s"(fnb[0]), "+s"(fnb[1]), "+s"(fnb[2]), "+s"(fnb[3]), "+s"(fnb[4]),
+                         "+s"(fnb[5]));
             float *sWb = ONE ? sUp : sW + buf * NT * 8;   // dof d of lane l: ONE d*NT + l, else 8l + d
             if (pi < AG) {
                 const int n = ONE ? ln : div_small(pi, invG), g = ONE ? lg : pi - n * G;
@@ -729,7 +741,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                             if (rmask & taken0) reflect(u0, taken0);
                         apply(taken0, 0, u0);
                     }
-                    int rest = mask & ~taken0;
+                    int rest = fmask & ~taken0;
                     for (int s0 = 3; rest; s0 += 3) {
                         float u[3][4];
                         int bnd = 0;
@@ -743,11 +755,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 } else {
 #pragma unroll
                     for (int f = 0; f < 6; ++f) {
-                        if (!((mask >> f) & 1)) continue;
-                        const float *Cs = sC + (n * maxin + __popc(mask & ((1 << f) - 1))) * 16;
+                        if (!((fmask >> f) & 1)) continue;
+                        const float *Cs = sC + (n * maxin + __popc(fmask & ((1 << f) - 1))) * 16;
                         float u[4];
 #pragma unroll
-                        for (int l = 0; l < 4; ++l) u[l] = nb[f] >= 0 ? L.up[f][l] : psib;
+                        for (int l = 0; l < 4; ++l) u[l] = fnb[f] >= 0 ? L.up[f][l] : psib;
                         if constexpr (EXT)
                             if ((rmask >> f) & 1) {
                                 const float *src = refl_row(f, P.refl_in);
@@ -764,7 +776,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                         }
                     }
                 }
-                if (const int lf = EXT ? lagm & ~mask : 0) {
+                if (const int lf = EXT ? lagm & ~fmask : 0) {
                     // Per-angle designation: a face that is inflow for this direction
                     // but downwind in the octant's order takes the neighbour's trace
                     // from the previous sweep (its task runs after this one, so the
@@ -775,8 +787,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                     for (int f = 0; f < 6; ++f) {
                         if (!((lf >> f) & 1) || !((mine >> f) & 1)) continue;
                         float u[4];
-                        if (nb[f] >= 0) {
-                            const __amdgpu_buffer_rsrc_t rs = cell_block(psi_o, nb[f], 8 * AG);
+                        if (fnb[f] >= 0) {
+                            const __amdgpu_buffer_rsrc_t rs = cell_block(psi_o, fnb[f], 8 * AG);
 #pragma unroll
                             for (int l = 0; l < 4; ++l)
                                 u[l] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
@@ -805,7 +817,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                     if (pn < AG) {
                         const int nn = div_small(pn, invG), gn = pn - nn * G;
                         load_own(P, K, gn, L);
-                        load_up(K, mask, nb, pm, pn, AG, psi_o, L);
+                        load_up(K, fmask, fnb, pm, pn, AG, psi_o, L);
                     }
                 }
 
@@ -845,7 +857,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 if constexpr (EXT) {
                     // reflective faces this octant leaves through: their nodal outflow
                     // for the mirror images' next sweep
-                    if (const int ro = rmask & ~mask) {
+                    if (const int ro = rmask & ~fmask) {
 #pragma unroll
                         for (int f = 0; f < 6; ++f) {
                             if (!((ro >> f) & 1)) continue;
