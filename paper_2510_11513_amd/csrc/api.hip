@@ -160,7 +160,7 @@ struct snx_problem {
     unsigned long long desig_counts[3] = {0, 0, 0};  // per-angle designation statistics (snx_designation_stats)
     // per-direction sweep order (SNX_DESIGNATION_DIRECTION): work items, lagged faces
     struct Dir {
-        std::vector<long long> level_off;   // [levels + 1] offsets into the work items
+        std::vector<long long> level_off;   // [levels + 1] offsets into the work units
         long long cyclic = 0;               // directions whose graph had a cycle
         DirDev dev{};
     } dir;
@@ -1187,7 +1187,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
         std::string derr;
         const int drc = direction_orders(p->C, p->A, nbr, nbrf, am, p->xyz, p->cv, p->omega, dh, derr);
         if (drc) { drop_device(p); return fail(p, drc, derr); }
-        const size_t nl = dh.lag.size(), ni = dh.items.size();
+        const size_t nl = dh.lag.size();
         std::vector<long long> src(std::max<size_t>(1, 4 * nl), 0);
         for (size_t i = 0; i < nl; ++i) {
             const DirHost::Lag &L = dh.lag[i];
@@ -1197,22 +1197,33 @@ snx_status snx_setup(snx_problem *p, void *stream) {
                 src[4 * i + l] = ((((long long)L.o * p->C + N) * 8 + vn) * p->A + L.a) * p->G;
             }
         }
+        // work units (task, direction), level by level: every direction of an item
+        std::vector<int> units;
+        std::vector<long long> unit_off(dh.level_off.size(), 0);
+        units.reserve(2 * (size_t)C * p->nang);
+        for (size_t l = 0; l + 1 < dh.level_off.size(); ++l) {
+            unit_off[l] = (long long)(units.size() / 2);
+            for (long long i = dh.level_off[l]; i < dh.level_off[l + 1]; ++i)
+                for (unsigned long long d = dh.dirs[i]; d; d &= d - 1) {
+                    units.push_back(dh.items[i]);
+                    units.push_back(__builtin_ctzll(d));
+                }
+        }
+        unit_off.back() = (long long)(units.size() / 2);
         DirDev &D = p->dir.dev;
-        int *ditems; unsigned long long *ddirs; unsigned char *dlagb; int *dlagi; long long *dsrc; float *dlbuf;
-        HIPCHK(p, m.alloc((void **)&ditems, sizeof(int) * std::max<size_t>(1, ni)), "device allocation");
-        HIPCHK(p, m.alloc((void **)&ddirs, sizeof(unsigned long long) * std::max<size_t>(1, ni)), "device allocation");
+        int *dunits; unsigned char *dlagb; int *dlagi; long long *dsrc; float *dlbuf;
+        HIPCHK(p, m.alloc((void **)&dunits, sizeof(int) * std::max<size_t>(2, units.size())), "device allocation");
         HIPCHK(p, m.alloc((void **)&dlagb, 8 * C * A), "device allocation");
         HIPCHK(p, m.alloc((void **)&dlagi, sizeof(int) * 8 * C * A), "device allocation");
         HIPCHK(p, m.alloc((void **)&dsrc, sizeof(long long) * src.size()), "device allocation");
         HIPCHK(p, m.alloc((void **)&dlbuf, sizeof(float) * std::max<size_t>(1, 4 * nl * G)), "device allocation");
-        HIPCHK(p, hipMemcpy(ditems, dh.items.data(), sizeof(int) * ni, hipMemcpyHostToDevice), "copy");
-        HIPCHK(p, hipMemcpy(ddirs, dh.dirs.data(), sizeof(unsigned long long) * ni, hipMemcpyHostToDevice), "copy");
+        HIPCHK(p, hipMemcpy(dunits, units.data(), sizeof(int) * units.size(), hipMemcpyHostToDevice), "copy");
         HIPCHK(p, hipMemcpy(dlagb, dh.lagbits.data(), 8 * C * A, hipMemcpyHostToDevice), "copy");
         HIPCHK(p, hipMemcpy(dlagi, dh.lagidx.data(), sizeof(int) * 8 * C * A, hipMemcpyHostToDevice), "copy");
         HIPCHK(p, hipMemcpy(dsrc, src.data(), sizeof(long long) * src.size(), hipMemcpyHostToDevice), "copy");
-        D.items = ditems; D.dirs = ddirs; D.amask = damask; D.lagbits = dlagb; D.lagidx = dlagi;
-        D.lagsrc = dsrc; D.lagbuf = dlbuf; D.nlag = (long long)nl; D.lanes = p->A * p->G; D.A = p->A;
-        p->dir.level_off = dh.level_off;
+        D.units = dunits; D.amask = damask; D.lagbits = dlagb; D.lagidx = dlagi;
+        D.lagsrc = dsrc; D.lagbuf = dlbuf; D.nlag = (long long)nl; D.G = p->G; D.A = p->A;
+        p->dir.level_off = unit_off;
         p->dir.cyclic = dh.cyclic_directions;
         p->desig_counts[1] = nl;   // lagged triples: only the faces that break cycles
     }

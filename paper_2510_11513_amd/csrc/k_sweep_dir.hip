@@ -7,11 +7,11 @@
 // strongly connected components of that graph (the upwind cell ranked after
 // the downwind one by Omega_n . centroid), and levels the rest.
 //
-// The sweep is level-synchronous over those per-direction levels.  A work item
-// is one (cell, octant) with the set of the octant's directions whose level
-// for that cell is the current one; its workgroup stages the cell's element
-// matrices in LDS and solves one (direction, group) system per lane, with the
-// direction's own inflow faces.  An inflow neighbour sits on an earlier level
+// The sweep is level-synchronous over those per-direction levels.  A work unit
+// is one (cell, octant, direction) on the current level of that direction's
+// order; a wave takes several units, stages their cells' element matrices in
+// LDS and solves one (unit, group) system per lane, with the direction's own
+// inflow faces.  An inflow neighbour sits on an earlier level
 // of the same direction, so its angular flux in the hand-off array is this
 // sweep's, except across a lagged face, which reads the neighbour's flux of
 // the previous sweep from a snapshot taken before the first level.  The angle
@@ -47,55 +47,56 @@ __global__ void k_lag_snapshot(DirDev D, const DevProblem *__restrict__ probs, c
         D.lagbuf[i] = P.psi[D.lagsrc[i / G] + i % G];
 }
 
-// One wave per (item, slice of 64 lanes) over the item's active (direction,
-// group) lanes only: most items hold one or two directions, so lanes are packed
-// by active direction (k-th set bit of the item's direction mask).  The
-// operators of the block's directions are built cooperatively in LDS first
-// (B = Om . S - sum over the direction's inflow faces of Om . F_f, and each
-// inflow face's Om . F_f), so that a lane's row assembly has no face branches;
-// only its right-hand side depends on which faces are inflow.  LDS holds the
-// cell's matrices and the operators of at most `nd` directions.
+// One wave per up to `upw` work units of a level, a unit being one (cell,
+// octant, direction) whose level in that direction's order is the current one;
+// lane l solves group l % G of unit l / G (G <= 64), or, for G > 64, block y
+// takes groups 64 y.. of a single unit.  Packing units rather than one (cell,
+// octant) item per wave fills the lanes: an item holds 1.3 directions on
+// average, so a wave per item left two thirds of its lanes idle.  Each unit's
+// cell matrices and its direction's operators (B = Om . S - sum over the
+// direction's inflow faces of Om . F_f, and each inflow face's Om . F_f) are
+// built cooperatively in LDS first, so that a lane's row assembly has no face
+// branches; only its right-hand side depends on which faces are inflow.
 constexpr int kDirThreads = 64;
+constexpr int kMaxUnits = 8;                 // units per wave (lanes of G <= 8 groups stay partly idle)
+constexpr int kUnitFloats = 544 + 65 + 96;   // M, S, F of the cell; B (odd stride); the inflow faces' Om . F
 
-__device__ __forceinline__ int nth_set_bit(unsigned long long v, int k) {
-    for (int i = 0; i < k; ++i) v &= v - 1;
-    return __builtin_ctzll(v);
-}
-
-__global__ __launch_bounds__(kDirThreads) void k_sweep_dir(DirDev D, const DevProblem *__restrict__ probs, int begin,
-                                                           int nd, const int *stop) {
+__global__ __launch_bounds__(kDirThreads) void k_sweep_dir(DirDev D, const DevProblem *__restrict__ probs,
+                                                           long long begin, long long end, int upw, const int *stop) {
     if (stop && *stop) return;
     const DevProblem &P = probs[0];
     const int C = P.C, A = P.A, G = P.G;
-    const int item = begin + (int)blockIdx.x;
-    const unsigned long long dirs = D.dirs[item];
-    const int lanes = __popcll(dirs) * G;
-    const int lane0 = (int)blockIdx.y * kDirThreads;     // first packed lane of this block
-    if (lane0 >= lanes) return;
-    const int task = D.items[item];
-    const int K = task >> 3, o = task & 7;
-    const int k_lo = lane0 / G, k_hi = min(lanes - 1, lane0 + kDirThreads - 1) / G;   // active directions here
+    const long long u0 = begin + (long long)blockIdx.x * upw;
+    const int nu = (int)min((long long)upw, end - u0);
     extern __shared__ float smem[];
-    float *sM = smem, *sS = smem + 64, *sF = smem + 256;   // 544 floats of cell data
-    float *sB = smem + 544;                                // [nd][65]  odd stride
-    float *sOF = sB + nd * 65;                             // [nd][6][16]
-    __shared__ int sNb[6];
-    __shared__ unsigned sPm[6];
-    for (int e = threadIdx.x; e < 544; e += kDirThreads) {
-        if (e < 64) sM[e] = P.M[(size_t)K * 64 + e];
-        else if (e < 256) sS[e - 64] = P.S[(size_t)K * 192 + e - 64];
-        else sF[e - 256] = P.F[(size_t)K * 288 + e - 256];
-    }
-    if (threadIdx.x < 6) {
-        sNb[threadIdx.x] = P.nbr[(size_t)K * 6 + threadIdx.x];
-        sPm[threadIdx.x] = P.perm[(size_t)K * 6 + threadIdx.x];
+    __shared__ int sNb[kMaxUnits][6], sTask[kMaxUnits], sDir[kMaxUnits];
+    __shared__ unsigned sPm[kMaxUnits][6];
+    const int tid = threadIdx.x;
+    if (tid < nu) {
+        sTask[tid] = D.units[2 * (u0 + tid)];
+        sDir[tid] = D.units[2 * (u0 + tid) + 1];
     }
     __syncthreads();
-    const int na = k_hi - k_lo + 1;
-    for (int idx = threadIdx.x; idx < na * (64 + 96); idx += kDirThreads) {
-        const int kk = idx / (64 + 96), e = idx % (64 + 96);
-        const int a = nth_set_bit(dirs, k_lo + kk);
-        const int n = o * A + a;
+    // the cell data of every unit: all loads in flight together
+    for (int e = tid; e < nu * 544; e += kDirThreads) {
+        const int u = e / 544, i = e % 544;
+        const int K = sTask[u] >> 3;
+        float *sc = smem + u * kUnitFloats;
+        sc[i] = i < 64 ? P.M[(size_t)K * 64 + i]
+                       : (i < 256 ? P.S[(size_t)K * 192 + i - 64] : P.F[(size_t)K * 288 + i - 256]);
+    }
+    if (tid < nu * 6) {
+        const int u = tid / 6, f = tid % 6;
+        const int K = sTask[u] >> 3;
+        sNb[u][f] = P.nbr[(size_t)K * 6 + f];
+        sPm[u][f] = P.perm[(size_t)K * 6 + f];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nu * (64 + 96); idx += kDirThreads) {
+        const int u = idx / (64 + 96), e = idx % (64 + 96);
+        const int task = sTask[u], a = sDir[u];
+        const int K = task >> 3, o = task & 7, n = o * A + a;
+        const float *sS = smem + u * kUnitFloats + 64, *sF = smem + u * kUnitFloats + 256;
         const float ox = P.omega[3 * n], oy = P.omega[3 * n + 1], oz = P.omega[3 * n + 2];
         const int mask = D.amask[((size_t)o * C + K) * A + a];
         if (e < 64) {
@@ -110,25 +111,28 @@ __global__ __launch_bounds__(kDirThreads) void k_sweep_dir(DirDev D, const DevPr
                 const float *F = sF + f * 48 + 4 * k + l;
                 v -= ox * F[0] + oy * F[16] + oz * F[32];
             }
-            sB[kk * 65 + e] = v;
+            smem[u * kUnitFloats + 544 + e] = v;
         } else {
             const int f = (e - 64) >> 4, kl = (e - 64) & 15;
             const float *F = sF + f * 48 + kl;
-            sOF[kk * 96 + f * 16 + kl] = ((mask >> f) & 1) ? ox * F[0] + oy * F[16] + oz * F[32] : 0.f;
+            smem[u * kUnitFloats + 544 + 65 + f * 16 + kl] = ((mask >> f) & 1) ? ox * F[0] + oy * F[16] + oz * F[32]
+                                                                              : 0.f;
         }
     }
     __syncthreads();
 
-    const int p = lane0 + (int)threadIdx.x;
-    if (p >= lanes) return;
-    const int kk = p / G - k_lo, g = p % G;
-    const int a = nth_set_bit(dirs, k_lo + kk);
+    const int u = G <= kDirThreads ? tid / G : 0;
+    const int g = G <= kDirThreads ? tid % G : (int)blockIdx.y * kDirThreads + tid;
+    if (u >= nu || g >= G) return;
+    const int task = sTask[u], a = sDir[u];
+    const int K = task >> 3, o = task & 7;
     const size_t AG = (size_t)A * G;
     const size_t oka = ((size_t)o * C + K) * A + a;
     const int mask = D.amask[oka], lagb = D.lagbits[oka];
     const int lbase = lagb ? D.lagidx[oka] : 0;
     const float sig = P.sigt[(size_t)K * G + g];
-    const float *Bk = sB + kk * 65;
+    const float *sM = smem + u * kUnitFloats;
+    const float *Bk = sM + 544, *sOF = sM + 544 + 65;
     float m[64], b[8];
 #pragma unroll
     for (int e = 0; e < 64; ++e) m[e] = __builtin_fmaf(sig, sM[e], Bk[e]);
@@ -138,28 +142,28 @@ __global__ __launch_bounds__(kDirThreads) void k_sweep_dir(DirDev D, const DevPr
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         if (!((mask >> f) & 1)) continue;
-        const int N = sNb[f];
-        float u[4];
+        const int N = sNb[u][f];
+        float uu[4];
         if (N >= 0 && ((lagb >> f) & 1)) {          // a face lagged to break a cycle: last sweep's flux
             const int slot = lbase + __popc(lagb & ((1 << f) - 1));
 #pragma unroll
-            for (int l = 0; l < 4; ++l) u[l] = D.lagbuf[((size_t)slot * 4 + l) * G + g];
+            for (int l = 0; l < 4; ++l) uu[l] = D.lagbuf[((size_t)slot * 4 + l) * G + g];
         } else if (N >= 0) {                        // an earlier level of this direction: this sweep's
 #pragma unroll
             for (int l = 0; l < 4; ++l) {
-                const int vn = (int)((sPm[f] >> (8 * l)) & 0xffu);
-                u[l] = P.psi[(((size_t)o * C + N) * 8 + vn) * AG + (size_t)a * G + g];
+                const int vn = (int)((sPm[u][f] >> (8 * l)) & 0xffu);
+                uu[l] = P.psi[(((size_t)o * C + N) * 8 + vn) * AG + (size_t)a * G + g];
             }
         } else {
 #pragma unroll
-            for (int l = 0; l < 4; ++l) u[l] = P.psib ? P.psib[g] : 0.f;
+            for (int l = 0; l < 4; ++l) uu[l] = P.psib ? P.psib[g] : 0.f;
         }
-        const float *OF = sOF + kk * 96 + f * 16;
+        const float *OF = sOF + f * 16;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             float t = 0.f;
 #pragma unroll
-            for (int l = 0; l < 4; ++l) t = __builtin_fmaf(OF[4 * k + l], u[l], t);
+            for (int l = 0; l < 4; ++l) t = __builtin_fmaf(OF[4 * k + l], uu[l], t);
             b[face_vertex_of(f, k)] -= t;
         }
     }
@@ -228,14 +232,12 @@ hipError_t launch_lag_snapshot(const DirDev &D, const DevProblem *probs, int G, 
 
 hipError_t launch_sweep_dir_level(const DirDev &D, const DevProblem *probs, int threads, long long begin,
                                   long long end, const int *stop, hipStream_t s) {
-    (void)threads;   // one wave per block: items hold few directions
+    (void)threads;   // one wave per block
     if (end <= begin) return hipSuccess;
-    // a block's 64 lanes span at most 64 / G + 1 directions (and no more than the octant has)
-    const int G = D.lanes / D.A;
-    const int nd = std::min(D.A, kDirThreads / G + 1);
-    const size_t lds = sizeof(float) * (544 + (size_t)nd * (65 + 96));
-    const dim3 grid((unsigned)(end - begin), (unsigned)((D.lanes + kDirThreads - 1) / kDirThreads));
-    hipLaunchKernelGGL(k_sweep_dir, grid, dim3(kDirThreads), lds, s, D, probs, (int)begin, nd, stop);
+    const int upw = D.G <= kDirThreads ? std::min(kMaxUnits, kDirThreads / D.G) : 1;
+    const size_t lds = sizeof(float) * (size_t)upw * kUnitFloats;
+    const dim3 grid((unsigned)((end - begin + upw - 1) / upw), (unsigned)((D.G + kDirThreads - 1) / kDirThreads));
+    hipLaunchKernelGGL(k_sweep_dir, grid, dim3(kDirThreads), lds, s, D, probs, begin, end, upw, stop);
     return hipGetLastError();
 }
 

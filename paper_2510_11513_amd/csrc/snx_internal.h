@@ -121,15 +121,14 @@ struct DevProblem {
 // Per-direction sweep order (SNX_DESIGNATION_DIRECTION): the work items of the
 // level-synchronous sweep and the faces lagged to break cycles.  Device memory.
 struct DirDev {
-    const int *items;                 // [nitems]      task 8 K + o, bucketed by level
-    const unsigned long long *dirs;   // [nitems]      directions a of octant o solved by the item (bit a)
+    const int *units;                 // [nunits][2]   (task 8 K + o, direction a of octant o), bucketed by level
     const unsigned char *amask;       // [8][C][A]     inflow faces of each direction (the problem's amask)
     const unsigned char *lagbits;     // [8][C][A]     interior inflow faces lagged to break cycles
     const int *lagidx;                // [8][C][A]     first lag slot of the direction's lagged faces (face order)
     const long long *lagsrc;          // [nlag * 4]    hand-off index of the upwind node, group 0
     float *lagbuf;                    // [nlag * 4][G] upwind values of the previous sweep
     long long nlag;                   // lagged (direction, cell, face) triples
-    int lanes;                        // A * G: (direction, group) systems of one octant
+    int G;                            // groups: the systems of one unit
     int A;                            // directions per octant
 };
 hipError_t launch_lag_snapshot(const DirDev &D, const DevProblem *probs, int G, const int *stop, hipStream_t s);
