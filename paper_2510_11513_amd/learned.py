@@ -30,6 +30,7 @@ WORKLOAD = 5                 # the high-scattering recipe of inputs.config_probl
 TRAIN_OFFSET = 100000        # training instances draw seeds disjoint from the held-out ones
 TOL = 1e-6
 MAX_IT = 5000
+LAYERS = 4                   # message-passing layers of the shipped network
 
 
 def instance(index: int, n: int | None = None) -> inputs.Problem:
@@ -173,13 +174,14 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--wd", type=float, default=1e-4)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--layers", type=int, default=LAYERS, help="message-passing layers (1..8)")
     ap.add_argument("--n", type=int, default=None, help="mesh edge override (default 32)")
     ap.add_argument("--init", default=None, help="start from this parameter file")
     ap.add_argument("--out", default=None, help="write the trained parameters here")
     ap.add_argument("--summary", default=None, help="write the evaluation records here (JSON)")
     args = ap.parse_args(argv)
 
-    gnn = snx.Gnn(0, 4, seed=args.seed)
+    gnn = snx.Gnn(0, args.layers, seed=args.seed)
     if args.init:
         gnn.load_file(args.init)
     t0 = time.perf_counter()
@@ -197,7 +199,7 @@ def main(argv=None):
     del tr, va
     recs = evaluate(gnn, list(range(args.heldout)), args.n)
     summ = summarize(recs)
-    summ.update(train=args.train, epochs=args.epochs, val_loss=vloss, collect_s=round(t_collect, 1),
+    summ.update(train=args.train, epochs=args.epochs, layers=args.layers, val_loss=vloss, collect_s=round(t_collect, 1),
                 train_s=round(t_train, 1))
     _log({"stage": "summary", **summ})
     if args.summary:
