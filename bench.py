@@ -422,11 +422,10 @@ def learned_start(count: int):
     """Time to 1e-6 from the trained network's start vs zero start (and the Q/sigma_a control),
     on the first `count` held-out instances of the high-scattering workload, inference included."""
     from paper_2510_11513_amd import learned, snx
-    path = os.path.join(ROOT, "paper_2510_11513_amd", "weights", "gnn_l4_h64.bin")
-    if not os.path.exists(path):
+    if not os.path.exists(learned.WEIGHTS):
         return None
-    net = snx.Gnn(0, 4)
-    net.load_file(path)
+    net = snx.Gnn(0, learned.LAYERS)
+    net.load_file(learned.WEIGHTS)
     t0 = time.perf_counter()
 
     def log(rec):

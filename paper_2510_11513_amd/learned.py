@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import os
 import sys
 import time
 
@@ -31,6 +32,7 @@ TRAIN_OFFSET = 100000        # training instances draw seeds disjoint from the h
 TOL = 1e-6
 MAX_IT = 5000
 LAYERS = 4                   # message-passing layers of the shipped network
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", f"gnn_l{LAYERS}_h64.bin")
 
 
 def instance(index: int, n: int | None = None) -> inputs.Problem:

@@ -25,14 +25,14 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2510_11513_amd import inputs
+from paper_2510_11513_amd import inputs, learned
 from tests import helpers as H
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 TUNE_CACHE = os.path.join(ROOT, "paper_2510_11513_amd", "tuning", "mi355x.jsonl")
-WEIGHTS = os.path.join(ROOT, "paper_2510_11513_amd", "weights", "gnn_l4_h64.bin")
+WEIGHTS = learned.WEIGHTS
 
 
 def _phi_in(prob, seed):
@@ -161,12 +161,12 @@ def test_batch_full_size_sampled_parity():
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained parameter file")
 def test_learned_start_full_size_is_an_oracle_fixed_point():
-    from paper_2510_11513_amd import learned, snx
+    from paper_2510_11513_amd import snx
     pr = inputs.config_problem(learned.WORKLOAD, index=7)   # a held-out instance
     print(f"[case] learned start 32^3 high scattering: C={pr.mesh.ncell} nang={pr.nang} G={pr.mat.ngroup}",
           flush=True)
     p = snx.Problem.from_problem(pr)
-    net = snx.Gnn(0, 4)
+    net = snx.Gnn(0, learned.LAYERS)
     net.load_file(WEIGHTS)
     phi_l, il = p.solve(learned.TOL, 5000, phi0=net.predict(p))
     phi_z, iz = p.solve(learned.TOL, 5000)

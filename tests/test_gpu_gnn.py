@@ -7,12 +7,12 @@ import pytest
 
 import oracle
 from oracle import gnn as ref
-from paper_2510_11513_amd import inputs
+from paper_2510_11513_amd import inputs, learned
 from tests import helpers as H
 
 pytestmark = pytest.mark.gpu
 
-WEIGHTS = os.path.join(os.path.dirname(__file__), "..", "paper_2510_11513_amd", "weights", "gnn_l4_h64.bin")
+WEIGHTS = learned.WEIGHTS
 
 # Unit roundoff of bfloat16 (8 significant bits).  The reference rounds the layer
 # weights to bfloat16 as the GPU does, but keeps activations in FP64; the GPU
@@ -192,7 +192,7 @@ def test_learned_start_converges_to_the_same_solution_as_zero_start_and_oracle()
     mat = inputs.materials_loguniform_blocks(mesh, 4, rng, 2, 0.9, 0.99, scaled=True)
     pr = inputs.Problem("learned-small", mesh, mat, 2, 2, 1e-6)
     p = snx.Problem.from_problem(pr)
-    net = snx.Gnn(0, 4, seed=6)
+    net = snx.Gnn(0, learned.LAYERS, seed=6)
     if os.path.exists(WEIGHTS):
         net.load_file(WEIGHTS)
     phi0 = net.predict(p)
@@ -206,8 +206,8 @@ def test_learned_start_converges_to_the_same_solution_as_zero_start_and_oracle()
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained parameter file")
 def test_trained_network_beats_zero_start_on_held_out_instances():
-    from paper_2510_11513_amd import learned, snx
-    net = snx.Gnn(0, 4)
+    from paper_2510_11513_amd import snx
+    net = snx.Gnn(0, learned.LAYERS)
     net.load_file(WEIGHTS)
     recs = learned.evaluate(net, [0, 1, 2], log=None)
     for r in recs:
