@@ -200,9 +200,10 @@ snx_status snx_get_order(snx_problem *p, int32_t *order, int32_t *nodes);
  *   upwind cell has the larger Omega_n . centroid (vertex mean; the larger cell
  *   id on a tie) reads the neighbour's angular flux of the previous sweep.
  *   Every other inflow face reads this sweep's flux.  The sweep runs level by
- *   level over the directions' own levels (one launch per level, a work item
- *   per cell, octant and level holding the octant's directions at that level;
- *   snx_set_sweep_mode does not apply, snx_sweep_stats counts no tasks).  Not
+ *   level over the directions' own levels (one launch per level, one work
+ *   unit per cell, octant and direction on that level, several units per
+ *   wavefront; snx_set_sweep_mode does not apply, snx_sweep_stats counts no
+ *   tasks).  Not
  *   available with reflective planes, anisotropic scattering, in batches or
  *   at order > 1 (SNX_E_ARG).  snx_designation_stats counts the lagged faces.
  * SNX_E_ARG for another kind; snx_setup returns SNX_E_MESH when a face is
