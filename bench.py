@@ -178,7 +178,7 @@ def per_angle(prob, threads: int, wg_per_cu: int, ms_octant: float, its_octant: 
     """The same workload under per-angle designation (each direction's own inflow
     faces): in the octant's order with every face against it lagged, and in each
     direction's own order with only the faces that close cycles lagged (level by
-    level).  Sweep time, the designation counts, and source iterations to the
+    level, and as the dependency-driven unit sweep).  Sweep time, the designation counts, and source iterations to the
     workload's tolerance beside the per-octant count."""
     from paper_2510_11513_amd import snx
     p = snx.Problem.from_problem(prob, setup=False, designation=snx.DESIGNATION_ANGLE)
@@ -199,6 +199,11 @@ def per_angle(prob, threads: int, wg_per_cu: int, ms_octant: float, its_octant: 
     ms_dir = q.profile_sweep(sweeps, phi_in=phi)
     dsd = q.designation_stats()
     _, info_dir = q.solve(prob.tol, 5000)
+    ms_units, ust = None, None
+    if prob.mat.ngroup <= 64:   # the dependency-driven unit sweep (same bits; slower, kept for comparison)
+        q.set_sweep_mode(snx.SWEEP_AMT)
+        ms_units = q.profile_sweep(sweeps, phi_in=phi)
+        ust = q.sweep_stats()
     q.close()
     return {"sweep_ms": round(ms, 4), "per_octant_sweep_ms": round(ms_octant, 4),
             "ratio": round(ms / ms_octant, 3), "differing_triples": ds["differing"],
@@ -207,7 +212,10 @@ def per_angle(prob, threads: int, wg_per_cu: int, ms_octant: float, its_octant: 
             "tol": prob.tol,
             "per_direction_order": {"sweep_ms": round(ms_dir, 4), "ratio": round(ms_dir / ms_octant, 3),
                                     "lagged_triples": dsd["lagged"], "iterations_to_tol": info_dir["iterations"],
-                                    "setup_s": round(t_setup, 3)}}
+                                    "setup_s": round(t_setup, 3), "levels": "one launch per level",
+                                    "unit_sweep_ms": None if ms_units is None else round(ms_units, 4),
+                                    "unit_sweep_rounds": None if ust is None else ust["grid"],
+                                    "unit_sweep_carried": None if ust is None else ust["continued"]}}
 
 
 def extensions(prob, threads: int, wg_per_cu: int, steps: int):

@@ -199,11 +199,14 @@ snx_status snx_get_order(snx_problem *p, int32_t *order, int32_t *nodes);
  *   algorithm, on the host) and lags only faces inside them: a face whose
  *   upwind cell has the larger Omega_n . centroid (vertex mean; the larger cell
  *   id on a tie) reads the neighbour's angular flux of the previous sweep.
- *   Every other inflow face reads this sweep's flux.  The sweep runs level by
- *   level over the directions' own levels (one launch per level, one work
- *   unit per cell, octant and direction on that level, several units per
- *   wavefront; snx_set_sweep_mode does not apply, snx_sweep_stats counts no
- *   tasks).  Not
+ *   Every other inflow face reads this sweep's flux.  The work unit is one
+ *   cell, octant and direction (several units per wavefront).  By default, and
+ *   under SNX_SWEEP_BSP or with G > 64, one launch per level of the directions'
+ *   own levels; under SNX_SWEEP_AMT (set explicitly) with G <= 64 one
+ *   persistent launch runs the units as their counters say they are ready (a
+ *   counter per unit, device queues of ready units, the watchdog of the octant
+ *   sweep).  Both give the same bits (snx_sweep_stats counts units after the
+ *   second).  Not
  *   available with reflective planes, anisotropic scattering, in batches or
  *   at order > 1 (SNX_E_ARG).  snx_designation_stats counts the lagged faces.
  * SNX_E_ARG for another kind; snx_setup returns SNX_E_MESH when a face is
@@ -313,7 +316,9 @@ snx_status snx_set_schedule(snx_problem *p, int32_t threads, int32_t wg_per_cu, 
  * launch per level of the per-octant DAGs (all octants and problems of the
  * schedule together), the launch boundary acting as the barrier.  Both run the
  * same task code, so they give the same bits; the mode applies to snx_sweep,
- * snx_solve and snx_profile_sweep.  snx_sweep_stats reports the last AMT sweep. */
+ * snx_solve and snx_profile_sweep.  snx_sweep_stats reports the last AMT sweep.
+ * Under SNX_DESIGNATION_DIRECTION the default is SNX_SWEEP_BSP (see
+ * snx_set_designation). */
 #define SNX_SWEEP_AMT 0
 #define SNX_SWEEP_BSP 1
 snx_status snx_set_sweep_mode(snx_problem *p, int32_t mode);
@@ -347,7 +352,12 @@ snx_status snx_profile_sweep(snx_problem *p, int32_t nsweeps, const float *phi_i
  * them ready, threads per workgroup, then shader-clock cycles summed over
  * workgroups spent waiting on the queue, staging cell data, building the
  * per-angle operators, solving, and publishing to downwind cells (zero unless
- * enabled by snx_set_sweep_stats).  Synchronous. */
+ * enabled by snx_set_sweep_stats).  After a dependency-driven per-direction
+ * sweep (SNX_DESIGNATION_DIRECTION) the entries are: units (cell, octant,
+ * direction) solved, polls that found no ready unit, abort flag, rounds of the
+ * waves (units solved together), units run by the wave that made them ready,
+ * 64, then cycles waiting for a unit, taking more units, solving, publishing,
+ * and 0.  Synchronous. */
 snx_status snx_sweep_stats(snx_problem *p, int64_t *out);
 
 /* Turns the per-phase cycle statistics of the dependency-driven sweep on

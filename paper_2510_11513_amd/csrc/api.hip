@@ -105,7 +105,8 @@ struct Sched {
     bool fixed_outer = false;                // group-to-group matrices: keep the cross-group source fixed
                                              // (inner iterations of an outer one); else renew it every iteration
     const snx_problem *dirp = nullptr;       // the schedule's one problem when it sweeps in per-direction
-                                             // order (level-synchronous, see enqueue_sweep)
+                                             // order (see enqueue_sweep)
+    bool dir_units = false;                  // its last sweep was the dependency-driven unit sweep
     long long *d_bsp_tasks = nullptr;        // tasks of every problem ordered by level (BSP comparator)
     std::vector<long long> bsp_off;          // [levels + 1] offsets into d_bsp_tasks
     unsigned long long watchdog = 0;
@@ -161,6 +162,8 @@ struct snx_problem {
     // per-direction sweep order (SNX_DESIGNATION_DIRECTION): work items, lagged faces
     struct Dir {
         std::vector<long long> level_off;   // [levels + 1] offsets into the work units
+        long long nunits = 0;               // units per sweep (8 C A)
+        UnitCtl uctl_host;                  // the unit queues' fixed layout (epoch and queue state zero)
         long long cyclic = 0;               // directions whose graph had a cycle
         DirDev dev{};
     } dir;
@@ -174,6 +177,7 @@ struct snx_problem {
     unsigned long long watchdog_ticks = 0;
     int threads = 0, wg_per_cu = 0, chunk = 8;     // requested sweep schedule (threads 0: automatic)
     int mode = SNX_SWEEP_AMT;
+    bool mode_set = false;              // snx_set_sweep_mode was called
     bool phase_stats = false;           // per-phase cycle statistics of the sweep (snx_set_sweep_stats)
     int nq = 1;                         // task queues = XCDs seen on the device
     int xcc_queue[kMaxXcc] = {0};       // home queue of each hardware XCC id
@@ -333,6 +337,15 @@ hipError_t reset_schedule(Sched &sc, hipStream_t s) {
         if (e == hipSuccess) e = launch_fill_u32(P.epoch, 1, 0u, s);
     }
     if (e == hipSuccess) e = hipMemsetAsync(sc.d_queue, 0, sizeof(unsigned long long) * (size_t)sc.total, s);
+    if (sc.dirp && e == hipSuccess) {   // the per-direction order's counters, queue and epoch
+        const DirDev &D = sc.dirp->dir.dev;
+        const long long NU = sc.dirp->dir.nunits;
+        e = launch_fill_u32(D.ucnt, (size_t)NU, 0u, s);
+        if (e == hipSuccess) e = hipMemsetAsync(D.uqueue, 0, sizeof(unsigned long long) * (size_t)NU, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(D.uctl, &sc.dirp->dir.uctl_host, sizeof(UnitCtl), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
     if (e == hipSuccess) e = hipMemcpyAsync(sc.d_ctl, &sc.host_ctl, sizeof(SweepCtl), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return e;
@@ -458,14 +471,20 @@ snx_status build_sched(Sched &sc, const std::vector<snx_problem *> &probs, int t
 // sweep kernel alone.
 snx_status enqueue_sweep(Sched &sc, const int *stops, hipStream_t s, hipEvent_t ev0 = nullptr,
                          hipEvent_t ev1 = nullptr) {
-    if (sc.dirp) {   // per-direction order: lag snapshot, one launch per level, octant slots
+    if (sc.dirp) {   // per-direction order: lag snapshot, the sweep (dependency-driven or by level), octant slots
         const snx_problem *p = sc.dirp;
         const DirDev &D = p->dir.dev;
         if (ev0) HIPCHK_E(sc.err, hipEventRecord(ev0, s), "event");
         HIPCHK_E(sc.err, launch_lag_snapshot(D, sc.d_probs, p->G, stops, s), "lag snapshot");
-        for (size_t l = 0; l + 1 < p->dir.level_off.size(); ++l)
-            HIPCHK_E(sc.err, launch_sweep_dir_level(D, sc.d_probs, sc.threads, p->dir.level_off[l],
-                                                    p->dir.level_off[l + 1], stops, s), "level launch");
+        sc.dir_units = sc.mode == SNX_SWEEP_AMT && p->G <= 64;
+        if (sc.mode == SNX_SWEEP_AMT && p->G <= 64) {   // dependency-driven: one persistent launch
+            HIPCHK_E(sc.err, launch_unit_sweep(D, sc.d_probs, &sc.d_ctl->abort, sc.watchdog, stops, sc.phase_stats, s),
+                     "unit sweep");
+        } else {                                        // level by level
+            for (size_t l = 0; l + 1 < p->dir.level_off.size(); ++l)
+                HIPCHK_E(sc.err, launch_sweep_dir_level(D, sc.d_probs, sc.threads, p->dir.level_off[l],
+                                                        p->dir.level_off[l + 1], stops, s), "level launch");
+        }
         HIPCHK_E(sc.err, launch_dir_slots(sc.d_probs, p->C, p->G, stops, s), "slots");
         if (ev1) HIPCHK_E(sc.err, hipEventRecord(ev1, s), "event");
         return SNX_OK;
@@ -694,6 +713,21 @@ snx_status sched_stats(Sched &sc, int64_t *out) {
     out[2] = (int64_t)h[0].abort;
     out[3] = (int64_t)sc.grid;
     out[5] = (int64_t)sc.threads;
+    if (sc.dirp && sc.dir_units) {   // the per-direction unit sweep's own statistics
+        UnitCtl u;
+        HIPCHK_E(sc.err, hipMemcpy(&u, sc.dirp->dir.dev.uctl, sizeof(UnitCtl), hipMemcpyDeviceToHost), "copy");
+        for (int i = 0; i < 11; ++i)
+            if (i != 2 && i != 5) out[i] = 0;
+        for (int q = 0; q < kUnitQueues; ++q) {
+            const UnitStat &S = u.st[q];
+            out[0] += (int64_t)S.units;
+            out[1] += (int64_t)S.polls;
+            out[3] += (int64_t)S.rounds;
+            out[4] += (int64_t)S.carried;
+            for (int i = 0; i < 4; ++i) out[6 + i] += (int64_t)S.phase[i];
+        }
+        out[5] = 64;
+    }
     return SNX_OK;
 }
 
@@ -1225,6 +1259,46 @@ snx_status snx_setup(snx_problem *p, void *stream) {
         D.lagsrc = dsrc; D.lagbuf = dlbuf; D.nlag = (long long)nl; D.G = p->G; D.A = p->A;
         p->dir.level_off = unit_off;
         p->dir.cyclic = dh.cyclic_directions;
+        // the dependency-driven form: each unit's in-degree (non-lagged interior
+        // inflow faces of its direction), the seeds, the neighbours' faces
+        {
+            const size_t NU = (size_t)8 * C * A;
+            std::vector<unsigned char> uindeg(NU), nbrf8((size_t)C * 6, 255);
+            std::vector<int> qseeds[kUnitQueues], useeds;
+            UnitCtl &H = p->dir.uctl_host;
+            H = UnitCtl{};
+            for (size_t e = 0; e < (size_t)C * 6; ++e)
+                if (nbr[e] >= 0) nbrf8[e] = (unsigned char)nbrf[e];
+            for (size_t u = 0; u < NU; ++u) {   // u = (o C + K) A + a; queue (o A + a) mod kUnitQueues
+                const size_t K = (u / A) % C, oa = (u / ((size_t)A * C)) * A + u % A;
+                const int q = (int)(oa % kUnitQueues);
+                int interior = 0;
+                for (int f = 0; f < 6; ++f) interior |= nbr[K * 6 + f] >= 0 ? 1 << f : 0;
+                uindeg[u] = (unsigned char)__builtin_popcount(am[u] & interior & ~dh.lagbits[u]);
+                ++H.qtotal[q];
+                if (!uindeg[u]) qseeds[q].push_back((int)u);
+            }
+            for (int q = 0; q < kUnitQueues; ++q) {
+                H.qbase[q] = q ? H.qbase[q - 1] + H.qtotal[q - 1] : 0;
+                H.seed_off[q] = (long long)useeds.size();
+                useeds.insert(useeds.end(), qseeds[q].begin(), qseeds[q].end());
+            }
+            H.seed_off[kUnitQueues] = (long long)useeds.size();
+            unsigned *ducnt; unsigned char *dindeg, *dnbrf; int *dseeds; UnitCtl *dctl; unsigned long long *dq;
+            HIPCHK(p, m.alloc((void **)&ducnt, sizeof(unsigned) * NU), "device allocation");
+            HIPCHK(p, m.alloc((void **)&dindeg, NU), "device allocation");
+            HIPCHK(p, m.alloc((void **)&dnbrf, (size_t)C * 6), "device allocation");
+            HIPCHK(p, m.alloc((void **)&dseeds, sizeof(int) * std::max<size_t>(1, useeds.size())), "device allocation");
+            HIPCHK(p, m.alloc((void **)&dctl, sizeof(UnitCtl)), "device allocation");
+            HIPCHK(p, m.alloc((void **)&dq, sizeof(unsigned long long) * NU), "device allocation");
+            HIPCHK(p, hipMemcpy(dindeg, uindeg.data(), NU, hipMemcpyHostToDevice), "copy");
+            HIPCHK(p, hipMemcpy(dnbrf, nbrf8.data(), (size_t)C * 6, hipMemcpyHostToDevice), "copy");
+            if (!useeds.empty())
+                HIPCHK(p, hipMemcpy(dseeds, useeds.data(), sizeof(int) * useeds.size(), hipMemcpyHostToDevice), "copy");
+            D.ucnt = ducnt; D.uindeg = dindeg; D.nbrf = dnbrf; D.seeds = dseeds;
+            D.uctl = dctl; D.uqueue = dq;
+            p->dir.nunits = (long long)NU;
+        }
         p->desig_counts[1] = nl;   // lagged triples: only the faces that break cycles
     }
 
@@ -1347,7 +1421,9 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     HIPCHK(p, launch_fill_f32(dr, C * G * 8, 0.f, s), "fill");
     HIPCHK(p, hipStreamSynchronize(s), "setup");
     snx_status st = build_sched(p->sched, {p}, p->threads, p->wg_per_cu, p->chunk, s);
-    p->sched.mode = p->mode;
+    // per-direction order: level by level unless a mode was chosen (the unit
+    // sweep measured slower at every size tried)
+    p->sched.mode = p->designation == SNX_DESIGNATION_DIRECTION && !p->mode_set ? SNX_SWEEP_BSP : p->mode;
     p->sched.phase_stats = p->phase_stats;
     if (st) {
         std::string msg = p->sched.err;
@@ -1671,6 +1747,7 @@ snx_status snx_set_sweep_mode(snx_problem *p, int32_t mode) {
     if (!p) return SNX_E_ARG;
     if (mode != SNX_SWEEP_AMT && mode != SNX_SWEEP_BSP) return fail(p, SNX_E_ARG, "unknown sweep mode");
     p->mode = mode;
+    p->mode_set = true;
     if (p->ready) {
         p->sched.mode = mode;
         p->sched.drop_graphs();

@@ -118,6 +118,35 @@ struct DevProblem {
     float lo[3], hi[3];          // bounding box of the mesh
 };
 
+// Queues of the dependency-driven per-direction sweep.  A unit (cell, octant,
+// direction) belongs to queue (o A + a) mod kUnitQueues, as do its downwind
+// units; each queue's slots, units and seeds are fixed at set-up.
+constexpr int kUnitQueues = 8;
+struct alignas(128) UnitQ {
+    unsigned head;   // next slot to take
+    unsigned tail;   // next slot to fill
+    unsigned done;   // units of the queue solved, flushed before a wave waits
+    unsigned pad;
+};
+// Statistics of a unit sweep, summed over the waves that start on each XCD.
+struct alignas(128) UnitStat {
+    unsigned long long units;       // units solved
+    unsigned long long rounds;      // rounds of a wave (units solved together)
+    unsigned long long carried;     // units solved by the wave that made them ready
+    unsigned long long polls;       // polls of a queue slot that found it empty
+    unsigned long long phase[4];    // shader-clock cycles: waiting for a unit, taking more units,
+                                    // solving (staging, operators, systems), publishing downwind
+};
+struct UnitCtl {
+    unsigned epoch;                          // sweeps so far (tags entries; counters count to in-degree x epoch)
+    unsigned pad[31];
+    long long qbase[kUnitQueues];            // first slot of each queue
+    long long qtotal[kUnitQueues];           // units of each queue
+    long long seed_off[kUnitQueues + 1];     // each queue's seeds in DirDev::seeds
+    UnitQ q[kUnitQueues];
+    UnitStat st[kUnitQueues];
+};
+
 // Per-direction sweep order (SNX_DESIGNATION_DIRECTION): the work items of the
 // level-synchronous sweep and the faces lagged to break cycles.  Device memory.
 struct DirDev {
@@ -130,11 +159,20 @@ struct DirDev {
     long long nlag;                   // lagged (direction, cell, face) triples
     int G;                            // groups: the systems of one unit
     int A;                            // directions per octant
+    // dependency-driven form (units in natural order (o C + K) A + a)
+    unsigned *ucnt;                   // [8][C][A]     dependency counters (count up across sweeps)
+    const unsigned char *uindeg;      // [8][C][A]     non-lagged interior inflow faces of the unit's direction
+    const unsigned char *nbrf;        // [C][6]        the neighbour's face across face f (255 on the boundary)
+    const int *seeds;                 // [nseeds]      units with in-degree 0, by queue
+    UnitCtl *uctl;
+    unsigned long long *uqueue;       // [8 C A]       ready units by queue, epoch << 32 | unit
 };
 hipError_t launch_lag_snapshot(const DirDev &D, const DevProblem *probs, int G, const int *stop, hipStream_t s);
 hipError_t launch_sweep_dir_level(const DirDev &D, const DevProblem *probs, int threads, long long begin,
                                   long long end, const int *stop, hipStream_t s);
 hipError_t launch_dir_slots(const DevProblem *probs, int C, int G, const int *stop, hipStream_t s);
+hipError_t launch_unit_sweep(const DirDev &D, const DevProblem *probs, unsigned *abortp, unsigned long long watchdog,
+                             const int *stop, bool phase_stats, hipStream_t s);
 
 // Higher-order elements (orders 2 and 3).  Reference tables of the order-p
 // element: the Gauss-Lobatto-Legendre nodes and the Gauss points and weights,
