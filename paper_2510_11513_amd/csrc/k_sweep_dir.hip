@@ -485,17 +485,30 @@ __global__ void k_dir_slots(const DevProblem *__restrict__ probs, const int *sto
     for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
         const long long g = t % G, d = (t / G) & 7, oc = t / (8 * G);   // oc = o * C + K
         const int o = (int)(oc / C);
-        const float *src = P.psi + (oc * 8 + d) * A * G + g;
+        const GLOBAL float *src = gp(P.psi) + (oc * 8 + d) * A * G + g;
+        const GLOBAL float *w = gp(P.w) + o * A;
         float s = 0.f, c = 0.f;
-        for (int a = 0; a < A; ++a) {
-            float u, e;
-            two_sum(s, P.w[o * A + a] * src[(size_t)a * G], u, e);
-            s = u;
-            c += e;
+        // eight directions' loads in flight at a time, summed in direction order
+        for (int a0 = 0; a0 < A; a0 += 8) {
+            float v[8], wv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int a = min(a0 + j, (int)A - 1);
+                v[j] = src[(size_t)a * G];
+                wv[j] = w[a];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (a0 + j >= A) break;
+                float u, e;
+                two_sum(s, wv[j] * v[j], u, e);
+                s = u;
+                c += e;
+            }
         }
         const size_t e = ((size_t)oc * G + g) * 8 + d;
-        P.slot[e] = s;
-        P.slotc[e] = c;
+        gp(P.slot)[e] = s;
+        gp(P.slotc)[e] = c;
     }
 }
 
