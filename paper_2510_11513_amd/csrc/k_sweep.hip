@@ -880,10 +880,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             // compensated accumulation in increasing angle order, one (group, dof) per reducer;
             // the other buffer takes the next round's values meanwhile
             const int hi = min(base + NT, AG);
+            const int bm = ONE ? 0 : base % G;   // group of the round's first lane (wave-uniform)
             for (int e = rt; e < G * 8; e += NT) {
                 const int g = e >> 3, d = e & 7;
                 float s = sRs[e], c = sRc[e];
-                const int q0 = ONE ? g : base + ((g - base % G) % G + G) % G;   // first lane of group g
+                // first lane of group g in this round: base + (g - bm) mod G, with
+                // 0 <= g, bm < G (one conditional add, no per-lane division)
+                const int q0 = ONE ? g : base + (g - bm) + (g < bm ? G : 0);
                 constexpr int LS = ONE ? 1 : 8;   // stride between lanes
                 const float *w = sWb + (q0 - base) * LS + d * (ONE ? NT : 1);
                 const int st = G * LS;            // next angle, same group
