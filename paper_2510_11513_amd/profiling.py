@@ -3,7 +3,7 @@
     python -m paper_2510_11513_amd.profiling stats <run_results.db> <out.md> "<command>"
     python -m paper_2510_11513_amd.profiling pmc <fetch.db> <write.db> <out.md> "<fetch command>" "<write command>"
     python -m paper_2510_11513_amd.profiling sq <sq.db> <out.md> "<command>" <tasks per sweep> <solves per sweep> \
-        [<bench JSON line file>]
+        [<bench JSON line file> ["<the command that wrote it>"]]
 
 `stats` lists every kernel's dispatch count and duration.  `pmc` scales the
 FETCH_SIZE and WRITE_SIZE counters (KiB per dispatch) of the sweep kernel by
@@ -104,7 +104,7 @@ SQ_COUNTERS = ("SQ_WAVES", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_INSTS_VALU", 
 
 
 def sq_summary(db: str, out_path: str, command: str, tasks: int, solves: int, bench_json: str | None = None,
-               simds: int = 1024, xcds: int = 8) -> str:
+               simds: int = 1024, xcds: int = 8, bench_command: str = "python3 bench.py --gpus 1 --steps 20 --warmup 5") -> str:
     vals = {}
     for c in SQ_COUNTERS:
         d = _counter(db, c)
@@ -132,8 +132,7 @@ def sq_summary(db: str, out_path: str, command: str, tasks: int, solves: int, be
         import json
         rec = json.loads(open(bench_json).read().strip().splitlines()[-1])
         lines += ["", "In-kernel phase statistics (`snx_set_sweep_stats`, one sweep, shader-clock cycles summed over "
-                  "workgroups) of the same code, from the `phases` objects of `python3 bench.py --gpus 1 --steps 20 "
-                  "--warmup 5`:", "",
+                  f"workgroups) of the same code, from the `phases` objects of `{bench_command}`:", "",
                   "| workload | tasks | continued by the same workgroup | empty queue polls | cycles per task | "
                   "queue wait | stage | operator build | solve | publish |", "|---|---|---|---|---|---|---|---|---|---|"]
         for name, r in (("headline", rec), ("secondary", rec.get("secondary", {}))):
@@ -187,4 +186,5 @@ if __name__ == "__main__":
                             sys.argv[8]))
     elif sys.argv[1] == "sq":
         print(sq_summary(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), int(sys.argv[6]),
-                         sys.argv[7] if len(sys.argv) > 7 else None))
+                         sys.argv[7] if len(sys.argv) > 7 else None,
+                         **({"bench_command": sys.argv[8]} if len(sys.argv) > 8 else {})))
