@@ -357,8 +357,20 @@ snx_status snx_profile_sweep(snx_problem *p, int32_t nsweeps, const float *phi_i
  * direction) solved, polls that found no ready unit, abort flag, rounds of the
  * waves (units solved together), units run by the wave that made them ready,
  * 64, then cycles waiting for a unit, taking more units, solving, publishing,
- * and 0.  Synchronous. */
+ * and 0.  A sweep that aborted leaves its dependency counters and queues
+ * inconsistent; this call reports the abort once and re-arms them, so the next
+ * sweep starts clean (snx_solve does the same itself before it returns
+ * SNX_E_DEVICE).  Synchronous. */
 snx_status snx_sweep_stats(snx_problem *p, int64_t *out);
+
+/* Watchdog of the dependency-driven sweeps (octant tasks and per-direction
+ * units): a workgroup that waits longer than `seconds` of wall-clock time for
+ * a ready task sets the abort flag, and every workgroup then leaves the sweep
+ * (abort 1 in snx_sweep_stats; snx_solve returns SNX_E_DEVICE).  seconds <= 0
+ * restores the default of 20 s; a tiny value makes any wait abort, which tests
+ * the abort path.  Applies to the next sweep.  Not a fault handler: kernels
+ * always exit normally.  Errors: SNX_E_ARG for NaN or more than 3600 s. */
+snx_status snx_set_watchdog(snx_problem *p, double seconds);
 
 /* Turns the per-phase cycle statistics of the dependency-driven sweep on
  * (phases != 0) or off (the default: reading the shader clock at every phase

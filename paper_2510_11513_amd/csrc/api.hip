@@ -174,7 +174,8 @@ struct snx_problem {
     unsigned long long *d_change = nullptr;          // [2] FP64 bits of the outer change norm
     double *d_partial = nullptr, *d_out4 = nullptr;
     double *d_area = nullptr;
-    unsigned long long watchdog_ticks = 0;
+    unsigned long long watchdog_ticks = 0;  // sweep watchdog in wall-clock ticks (snx_set_watchdog)
+    double tick_hz = 1e8;                   // the device's wall-clock rate
     int threads = 0, wg_per_cu = 0, chunk = 8;     // requested sweep schedule (threads 0: automatic)
     int mode = SNX_SWEEP_AMT;
     bool mode_set = false;              // snx_set_sweep_mode was called
@@ -327,6 +328,8 @@ snx_status configure_grid(Sched &sc) {
     sc.grid = (int)std::max(1LL, grid);
     return SNX_OK;
 }
+
+constexpr double kWatchdogSeconds = 20.0;   // default sweep watchdog: this long without a ready task
 
 // Zero the scheduler state of every problem of the schedule (counters, epochs)
 // and of the schedule (queue slots, abort flag, statistics); upload the layout.
@@ -713,6 +716,9 @@ snx_status sched_stats(Sched &sc, int64_t *out) {
     out[2] = (int64_t)h[0].abort;
     out[3] = (int64_t)sc.grid;
     out[5] = (int64_t)sc.threads;
+    // an aborted sweep leaves counters, queues and epochs inconsistent: re-arm
+    // them (the statistics below are read first)
+    const bool rearm = h[0].abort != 0;
     if (sc.dirp && sc.dir_units) {   // the per-direction unit sweep's own statistics
         UnitCtl u;
         HIPCHK_E(sc.err, hipMemcpy(&u, sc.dirp->dir.dev.uctl, sizeof(UnitCtl), hipMemcpyDeviceToHost), "copy");
@@ -727,6 +733,11 @@ snx_status sched_stats(Sched &sc, int64_t *out) {
             for (int i = 0; i < 4; ++i) out[6 + i] += (int64_t)S.phase[i];
         }
         out[5] = 64;
+    }
+    if (rearm) {
+        hipStream_t s0 = nullptr;
+        HIPCHK_E(sc.err, reset_schedule(sc, s0), "re-arm after an abort");
+        HIPCHK_E(sc.err, hipDeviceSynchronize(), "sync");
     }
     return SNX_OK;
 }
@@ -894,7 +905,8 @@ snx_status snx_create(snx_problem **out, int32_t device) {
     int rate_khz = 0;
     if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || rate_khz <= 0)
         rate_khz = 100000;
-    p->watchdog_ticks = (unsigned long long)rate_khz * 1000ull * 20ull;   // 20 s without a ready task
+    p->tick_hz = (double)rate_khz * 1000.0;
+    p->watchdog_ticks = (unsigned long long)(p->tick_hz * kWatchdogSeconds);   // without a ready task
     // Which XCDs do workgroups land on?  Each distinct XCC id becomes one task queue.
     {
         const int nb = 8 * cu_count(device);
@@ -1851,6 +1863,17 @@ bool snx::problem_view(const snx_problem *p, DevProblem *out, int *device) {
 }
 
 extern "C" {
+
+snx_status snx_set_watchdog(snx_problem *p, double seconds) {
+    if (!p) return SNX_E_ARG;
+    if (!(seconds == seconds) || seconds > 3600.0) return fail(p, SNX_E_ARG, "watchdog outside (0, 3600] s");
+    p->watchdog_ticks = (unsigned long long)(p->tick_hz * (seconds > 0.0 ? seconds : kWatchdogSeconds));
+    if (p->ready) {
+        p->sched.watchdog = p->watchdog_ticks;
+        p->sched.drop_graphs();   // the limit is a kernel argument of the captured sweeps
+    }
+    return SNX_OK;
+}
 
 snx_status snx_sweep_stats(snx_problem *p, int64_t *out) {
     if (!p || !out) return SNX_E_ARG;

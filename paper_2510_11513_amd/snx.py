@@ -102,6 +102,7 @@ def load(path: str = LIB_PATH):
     L.snx_set_sweep_mode.argtypes = [_vp, ct.c_int32]
     L.snx_batch_set_sweep_mode.argtypes = [_vp, ct.c_int32]
     L.snx_sweep_stats.argtypes = [_vp, _vp]
+    L.snx_set_watchdog.argtypes = [_vp, ct.c_double]
     L.snx_profile_sweep.argtypes = [_vp, ct.c_int32, _vp, _vp, ct.POINTER(ct.c_double), _vp]
     L.snx_tune.argtypes = [_vp, ct.c_char_p, _vp, _vp]
     L.snx_batch_create.argtypes = [ct.POINTER(_vp), ct.c_int32, _vp]
@@ -407,6 +408,10 @@ class Problem:
         out = np.zeros(11, np.int64)
         self._check(load().snx_sweep_stats(self.h, out.ctypes.data_as(ct.c_void_p)), "sweep_stats")
         return _stats(out)
+
+    def set_watchdog(self, seconds: float):
+        """Wall-clock limit on a dependency-driven sweep's wait for a ready task (<= 0: the 20 s default)."""
+        self._check(load().snx_set_watchdog(self.h, float(seconds)), "set_watchdog")
 
     def set_sweep_stats(self, phases: bool):
         """Per-phase cycle statistics in sweep_stats() (off by default: they cost ~2 % of sweep time)."""
