@@ -323,12 +323,22 @@ snx_status snx_set_schedule(snx_problem *p, int32_t threads, int32_t wg_per_cu, 
 #define SNX_SWEEP_BSP 1
 snx_status snx_set_sweep_mode(snx_problem *p, int32_t mode);
 
+/* LDS staging depth of the first-order sweep (the paper's task data staged
+ * ahead of its use, §3.3).  1 (default): a continuation task's upwind traces
+ * are requested into LDS together with its cell data (one round trip), and a
+ * multi-round task requests the next round's source dofs, sigma_t and traces
+ * during the current round's solve.  0: each task requests its traces after
+ * its cell data has arrived, and each round its inputs at its start.  The bits
+ * are the same; snx_tune picks it.  SNX_E_ARG for another value. */
+snx_status snx_set_staging_depth(snx_problem *p, int32_t depth);
+snx_status snx_get_staging_depth(snx_problem *p, int32_t *depth);
+
 /* Schedule autotuner: times a few sweeps of every candidate on this problem
  * and keeps the fastest.  The candidates are the dependency-driven sweep at
- * every (threads, workgroups per CU) and the bulk-synchronous one at every
- * width, so the tuner also picks the sweep mode (small meshes favour the
- * bulk-synchronous one, whose level launch costs less than a chain of
- * dependent tasks).  cache_path (nullable) is a text file of JSON lines keyed
+ * every (threads, workgroups per CU, staging depth) and the bulk-synchronous
+ * one at every width, so the tuner also picks the sweep mode (small meshes
+ * favour the bulk-synchronous one, whose level launch costs less than a chain
+ * of dependent tasks) and the staging depth.  cache_path (nullable) is a text file of JSON lines keyed
  * by device and problem shape: a hit skips the timing, a miss appends the
  * result.  host chosen[2] (nullable) receives (threads, workgroups per CU);
  * snx_get_schedule reports the mode.  Synchronous. */

@@ -101,6 +101,8 @@ struct Sched {
                                              // the kernel variant with them
     int threads = 256, wg_per_cu = 0, grid = 0, chunk = 8;
     int mode = SNX_SWEEP_AMT;                // SNX_SWEEP_AMT or SNX_SWEEP_BSP
+    int depth = 1;                           // staging depth (snx_set_staging_depth): 1 = a task's or
+                                             // round's inputs requested one step ahead, 0 = at its start
     bool phase_stats = false;                // gather the per-phase cycle statistics (snx_set_sweep_stats)
     bool fixed_outer = false;                // group-to-group matrices: keep the cross-group source fixed
                                              // (inner iterations of an outer one); else renew it every iteration
@@ -178,6 +180,7 @@ struct snx_problem {
     double tick_hz = 1e8;                   // the device's wall-clock rate
     int threads = 0, wg_per_cu = 0, chunk = 8;     // requested sweep schedule (threads 0: automatic)
     int mode = SNX_SWEEP_AMT;
+    int depth = 1;                      // requested staging depth (snx_set_staging_depth)
     bool mode_set = false;              // snx_set_sweep_mode was called
     bool phase_stats = false;           // per-phase cycle statistics of the sweep (snx_set_sweep_stats)
     int nq = 1;                         // task queues = XCDs seen on the device
@@ -320,7 +323,7 @@ snx_status configure_grid(Sched &sc) {
     sc.one = sc.maxAG <= sc.threads;
     const size_t lds = sweep_lds_bytes(sc.threads, sc.maxA, sc.maxG, sc.maxin, sc.one);
     if (lds > 64 * 1024) return fail_msg(sc.err, SNX_E_ARG, "task does not fit in 64 KB of LDS (too many angles or groups)");
-    const int occ = sweep_occupancy(sc.threads, sc.one, sc.ext, lds);
+    const int occ = sweep_occupancy(sc.threads, sc.one, sc.ext, sc.depth, lds);
     if (occ <= 0) return fail_msg(sc.err, SNX_E_ARG, "sweep kernel cannot be resident with this schedule");
     const int per_cu = sc.wg_per_cu > 0 ? std::min(sc.wg_per_cu, occ) : occ;
     long long grid = (long long)cu_count(sc.device) * per_cu;
@@ -504,7 +507,7 @@ snx_status enqueue_sweep(Sched &sc, const int *stops, hipStream_t s, hipEvent_t 
         for (size_t l = 0; l + 1 < sc.bsp_off.size(); ++l)
             HIPCHK_E(sc.err, launch_sweep_level(sc.d_probs, sc.nprob(), sc.d_base, sc.d_ctl, sc.threads, sc.one,
                                                 sc.grid, sc.maxA, sc.maxG, sc.maxin, sc.d_bsp_tasks, sc.bsp_off[l],
-                                                sc.bsp_off[l + 1], stops, sc.ext, s), "level launch");
+                                                sc.bsp_off[l + 1], stops, sc.depth, sc.ext, s), "level launch");
         if (ev1) HIPCHK_E(sc.err, hipEventRecord(ev1, s), "event");
         return SNX_OK;
     }
@@ -512,7 +515,8 @@ snx_status enqueue_sweep(Sched &sc, const int *stops, hipStream_t s, hipEvent_t 
                                            stops, s), "sweep prologue");
     if (ev0) HIPCHK_E(sc.err, hipEventRecord(ev0, s), "event");
     HIPCHK_E(sc.err, launch_sweep_kernel(sc.d_probs, sc.nprob(), sc.d_base, sc.d_ctl, sc.d_queue, sc.threads, sc.one,
-                                         sc.grid, sc.maxA, sc.maxG, sc.maxin, sc.watchdog, sc.phase_stats, sc.ext, s),
+                                         sc.grid, sc.maxA, sc.maxG, sc.maxin, sc.watchdog, sc.phase_stats, sc.depth,
+                                         sc.ext, s),
              "sweep launch");
     if (ev1) HIPCHK_E(sc.err, hipEventRecord(ev1, s), "event");
     return SNX_OK;
@@ -788,7 +792,7 @@ std::string tune_key(const Sched &sc) {
     return buf;
 }
 
-bool cache_lookup(const char *path, const std::string &key, int &threads, int &wg, int &mode) {
+bool cache_lookup(const char *path, const std::string &key, int &threads, int &wg, int &mode, int &depth) {
     if (!path) return false;
     FILE *f = std::fopen(path, "r");
     if (!f) return false;
@@ -796,13 +800,14 @@ bool cache_lookup(const char *path, const std::string &key, int &threads, int &w
     bool found = false;
     while (std::fgets(line, sizeof line, f)) {
         char k[300];
-        int t = 0, w = 0, m = SNX_SWEEP_AMT;
-        if (std::sscanf(line, "{\"key\": \"%299[^\"]\", \"threads\": %d, \"wg_per_cu\": %d, \"mode\": %d", k, &t,
-                        &w, &m) == 4 &&
-            key == k && (m == SNX_SWEEP_AMT || m == SNX_SWEEP_BSP)) {
+        int t = 0, w = 0, m = SNX_SWEEP_AMT, d = 1;   // entries written before the depth knob: depth 1
+        const int got = std::sscanf(line, "{\"key\": \"%299[^\"]\", \"threads\": %d, \"wg_per_cu\": %d, \"mode\": %d, "
+                                    "\"depth\": %d", k, &t, &w, &m, &d);
+        if (got >= 4 && key == k && (m == SNX_SWEEP_AMT || m == SNX_SWEEP_BSP) && (d == 0 || d == 1)) {
             threads = t;
             wg = w;
             mode = m;
+            depth = got == 5 ? d : 1;
             found = true;   // the last entry for a key wins
         }
     }
@@ -810,22 +815,23 @@ bool cache_lookup(const char *path, const std::string &key, int &threads, int &w
     return found;
 }
 
-void cache_store(const char *path, const std::string &key, int threads, int wg, int mode, double ms) {
+void cache_store(const char *path, const std::string &key, int threads, int wg, int mode, int depth, double ms) {
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"wg_per_cu\": %d, \"mode\": %d, \"ms\": %.6f}\n",
-                 key.c_str(), threads, wg, mode, ms);
+    std::fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"wg_per_cu\": %d, \"mode\": %d, \"depth\": %d, \"ms\": %.6f}\n",
+                 key.c_str(), threads, wg, mode, depth, ms);
     std::fclose(f);
 }
 
 snx_status tune_sched(Sched &sc, const char *cache, hipStream_t s, int *out_threads, int *out_wg, double *out_ms) {
     const std::string key = tune_key(sc);
-    int t = 0, w = 0, md = SNX_SWEEP_AMT;
-    if (cache_lookup(cache, key, t, w, md) && t >= sc.maxG) {
+    int t = 0, w = 0, md = SNX_SWEEP_AMT, dp = 1;
+    if (cache_lookup(cache, key, t, w, md, dp) && t >= sc.maxG) {
         sc.threads = t;
         sc.wg_per_cu = w;
         sc.mode = md;
+        sc.depth = dp;
         sc.drop_graphs();
         if (!configure_grid(sc)) {
             *out_threads = t;
@@ -838,20 +844,24 @@ snx_status tune_sched(Sched &sc, const char *cache, hipStream_t s, int *out_thre
     // and the level-synchronous one at every width (its grid only caps a level's
     // workgroups).  Small meshes favour the second: a level launch costs less than
     // the latency of a chain of dependent tasks through device-coherent memory.
+    // The dependency-driven candidates also try both staging depths (inputs
+    // requested one task or round ahead, or at its start).
     // Two passes, each candidate's best pass counts (clock and thermal drift
     // during the first pass does not decide).
-    struct Cand { int th, wg, mode; double ms; };
+    struct Cand { int th, wg, mode, depth; double ms; };
     std::vector<Cand> cands;
     for (int th : {64, 128, 192, 256, 512}) {
         if (th < sc.maxG) continue;
-        for (int wg : {0, 2, 4, 8}) cands.push_back({th, wg, SNX_SWEEP_AMT, 1e300});
-        cands.push_back({th, 0, SNX_SWEEP_BSP, 1e300});
+        for (int dp : {1, 0})
+            for (int wg : {0, 2, 4, 8}) cands.push_back({th, wg, SNX_SWEEP_AMT, dp, 1e300});
+        cands.push_back({th, 0, SNX_SWEEP_BSP, 1, 1e300});
     }
     for (int pass = 0; pass < 2; ++pass)
         for (Cand &c : cands) {
             sc.threads = c.th;
             sc.wg_per_cu = c.wg;
             sc.mode = c.mode;
+            sc.depth = c.depth;
             if (configure_grid(sc)) continue;
             double ms = 0.0;
             snx_status st = time_sweeps(sc, 1, s, &ms);           // warm-up
@@ -860,16 +870,17 @@ snx_status tune_sched(Sched &sc, const char *cache, hipStream_t s, int *out_thre
             c.ms = std::min(c.ms, ms);
         }
     double best = 1e300;
-    int bt = sc.threads, bw = sc.wg_per_cu, bm = sc.mode;
+    int bt = sc.threads, bw = sc.wg_per_cu, bm = sc.mode, bd = sc.depth;
     for (const Cand &c : cands)
-        if (c.ms < best) { best = c.ms; bt = c.th; bw = c.wg; bm = c.mode; }
+        if (c.ms < best) { best = c.ms; bt = c.th; bw = c.wg; bm = c.mode; bd = c.depth; }
     sc.threads = bt;
     sc.wg_per_cu = bw;
     sc.mode = bm;
+    sc.depth = bd;
     sc.drop_graphs();
     snx_status st = configure_grid(sc);
     if (st) return st;
-    cache_store(cache, key, bt, bw, bm, best);
+    cache_store(cache, key, bt, bw, bm, bd, best);
     *out_threads = bt;
     *out_wg = bw;
     *out_ms = best;
@@ -1436,6 +1447,7 @@ snx_status snx_setup(snx_problem *p, void *stream) {
     // per-direction order: level by level unless a mode was chosen (the unit
     // sweep measured slower at every size tried)
     p->sched.mode = p->designation == SNX_DESIGNATION_DIRECTION && !p->mode_set ? SNX_SWEEP_BSP : p->mode;
+    p->sched.depth = p->depth;
     p->sched.phase_stats = p->phase_stats;
     if (st) {
         std::string msg = p->sched.err;
@@ -1806,7 +1818,26 @@ snx_status snx_tune(snx_problem *p, const char *cache_path, int32_t *chosen, voi
     p->threads = t;
     p->wg_per_cu = w;
     p->mode = p->sched.mode;
+    p->depth = p->sched.depth;
     if (chosen) { chosen[0] = t; chosen[1] = w; }
+    return SNX_OK;
+}
+
+snx_status snx_set_staging_depth(snx_problem *p, int32_t depth) {
+    if (!p) return SNX_E_ARG;
+    if (depth != 0 && depth != 1) return fail(p, SNX_E_ARG, "staging depth must be 0 or 1");
+    p->depth = depth;
+    if (p->ready) {
+        p->sched.depth = depth;
+        p->sched.drop_graphs();
+        SCHED_ERR(p, configure_grid(p->sched));   // the two variants' occupancy may differ
+    }
+    return SNX_OK;
+}
+
+snx_status snx_get_staging_depth(snx_problem *p, int32_t *depth) {
+    if (!p || !depth) return SNX_E_ARG;
+    *depth = p->ready ? p->sched.depth : p->depth;
     return SNX_OK;
 }
 

@@ -278,12 +278,13 @@ __device__ long long pop_task(SweepCtl *ctl, unsigned long long *queue, int &q, 
 // upwinding (lagged faces), reflective planes and anisotropic moments.  Each
 // part is guarded by its own array being present, so the variant also runs
 // plain problems of a mixed batch; without EXT none of its code is compiled.
-template <int NT, bool ONE, bool BSP, bool EXT>
+template <int NT, bool ONE, bool BSP, bool EXT, int DEPTH>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_ONE : 4))) void k_sweep(
     const DevProblem *__restrict__ probs, int nprob, const long long *__restrict__ task_base,
     SweepCtl *__restrict__ ctl, unsigned long long *__restrict__ queue, int maxA, int maxG, int maxin,
     unsigned long long watchdog, const long long *__restrict__ bsp_tasks, long long bsp_begin, long long bsp_end,
     const int *__restrict__ stops, int phase_stats) {
+    constexpr int depth = DEPTH;
     extern __shared__ __align__(16) float lds[];
     __shared__ long long s_task;
     __shared__ int s_q;
@@ -482,8 +483,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         if constexpr (ONE) {
             stage_dma(K, stg, uni(tid & ~63), NT);
             if (tid < AG) load_sig(P, K, lg, L);
-            // a continuation's trace requests go after the stage loads
-            if (cface >= 0) early_up(prev_rec + 16 + 13 * cface);
+            // a continuation's trace requests go after the stage loads (staging
+            // depth 1: one round trip brings the cell data and the traces)
+            if (cface >= 0 && depth > 0) early_up(prev_rec + 16 + 13 * cface);
         } else {
             auto stage_item = [&](int i) -> float4 {
                 if (i < 16) return reinterpret_cast<const GLOBAL float4 *>(gp(P.M) + (size_t)K * 64)[i];
@@ -508,7 +510,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
         lds_barrier();                // the staged data come from LDS-destined loads of every wave
         if (tid == 0) s_nready = 0;   // after the barrier: every thread has read the last task's count
         if constexpr (ONE)
-            if (cface < 0) early_up(s_desc);
+            if (cface < 0 || depth == 0) early_up(s_desc);
         const int mask = uni(s_desc[12]);
         const int nin = __popc(mask);
         // faces where some direction's designation differs from the octant's
@@ -648,6 +650,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
             float *sWb = ONE ? sUp : sW + buf * NT * 8;   // dof d of lane l: ONE d*NT + l, else 8l + d
             if (pi < AG) {
                 const int n = ONE ? ln : div_small(pi, invG), g = ONE ? lg : pi - n * G;
+                if constexpr (!ONE)
+                    if (depth == 0 && base > 0) {
+                        load_own(P, K, g, L);
+                        load_up(K, fmask, fnb, pm, pi, AG, psi_o, L);
+                    }
                 float b[8];
                 if constexpr (ONE) {
                     const float4 r0 = reinterpret_cast<const float4 *>(sR + 8 * g)[0];
@@ -812,9 +819,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? WAVES_
                 }
                 const float sig = L.sig;
                 // the next round's inputs are in flight during this round's solve
+                // (staging depth 1; at depth 0 each round loads its own at its start)
                 if constexpr (!ONE) {
                     const int pn = pi + NT;
-                    if (pn < AG) {
+                    if (depth > 0 && pn < AG) {
                         const int nn = div_small(pn, invG), gn = pn - nn * G;
                         load_own(P, K, gn, L);
                         load_up(K, fmask, fnb, pm, pn, AG, psi_o, L);
@@ -1026,20 +1034,26 @@ template <int NT, bool ONE, bool BSP>
 hipError_t launch_nt(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                      unsigned long long *queue, int maxA, int maxG, int maxin, int grid, size_t lds,
                      unsigned long long watchdog, const long long *bsp_tasks, long long b0, long long b1,
-                     const int *stops, int phase_stats, bool ext, hipStream_t s) {
-    if (ext)
-        hipLaunchKernelGGL((k_sweep<NT, ONE, BSP, true>), dim3(grid), dim3(NT), lds, s, probs, nprob, task_base, ctl,
-                           queue, maxA, maxG, maxin, watchdog, bsp_tasks, b0, b1, stops, phase_stats);
-    else
-        hipLaunchKernelGGL((k_sweep<NT, ONE, BSP, false>), dim3(grid), dim3(NT), lds, s, probs, nprob, task_base, ctl,
-                           queue, maxA, maxG, maxin, watchdog, bsp_tasks, b0, b1, stops, phase_stats);
+                     const int *stops, int phase_stats, int depth, bool ext, hipStream_t s) {
+#define SNX_K(E, D)                                                                                                \
+    hipLaunchKernelGGL((k_sweep<NT, ONE, BSP, E, D>), dim3(grid), dim3(NT), lds, s, probs, nprob, task_base, ctl, \
+                       queue, maxA, maxG, maxin, watchdog, bsp_tasks, b0, b1, stops, phase_stats)
+    if (ext) {
+        if (depth) SNX_K(true, 1); else SNX_K(true, 0);
+    } else {
+        if (depth) SNX_K(false, 1); else SNX_K(false, 0);
+    }
+#undef SNX_K
     return hipGetLastError();
 }
 
 template <int NT, bool ONE>
-const void *kernel_ptr(bool ext) {
-    return ext ? reinterpret_cast<const void *>(&k_sweep<NT, ONE, false, true>)
-              : reinterpret_cast<const void *>(&k_sweep<NT, ONE, false, false>);
+const void *kernel_ptr(bool ext, int depth) {
+    if (depth)
+        return ext ? reinterpret_cast<const void *>(&k_sweep<NT, ONE, false, true, 1>)
+                   : reinterpret_cast<const void *>(&k_sweep<NT, ONE, false, false, 1>);
+    return ext ? reinterpret_cast<const void *>(&k_sweep<NT, ONE, false, true, 0>)
+               : reinterpret_cast<const void *>(&k_sweep<NT, ONE, false, false, 0>);
 }
 
 }  // namespace
@@ -1054,14 +1068,14 @@ size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin, bool one) {
     return floats * sizeof(float);
 }
 
-int sweep_occupancy(int threads, bool one, bool ext, size_t lds) {
+int sweep_occupancy(int threads, bool one, bool ext, int depth, size_t lds) {
     const void *k = nullptr;
     switch (threads) {
-        case 64: k = one ? kernel_ptr<64, true>(ext) : kernel_ptr<64, false>(ext); break;
-        case 128: k = one ? kernel_ptr<128, true>(ext) : kernel_ptr<128, false>(ext); break;
-        case 192: k = one ? kernel_ptr<192, true>(ext) : kernel_ptr<192, false>(ext); break;
-        case 256: k = one ? kernel_ptr<256, true>(ext) : kernel_ptr<256, false>(ext); break;
-        case 512: k = one ? kernel_ptr<512, true>(ext) : kernel_ptr<512, false>(ext); break;
+        case 64: k = one ? kernel_ptr<64, true>(ext, depth) : kernel_ptr<64, false>(ext, depth); break;
+        case 128: k = one ? kernel_ptr<128, true>(ext, depth) : kernel_ptr<128, false>(ext, depth); break;
+        case 192: k = one ? kernel_ptr<192, true>(ext, depth) : kernel_ptr<192, false>(ext, depth); break;
+        case 256: k = one ? kernel_ptr<256, true>(ext, depth) : kernel_ptr<256, false>(ext, depth); break;
+        case 512: k = one ? kernel_ptr<512, true>(ext, depth) : kernel_ptr<512, false>(ext, depth); break;
         default: return 0;
     }
     int nb = 0;
@@ -1082,14 +1096,15 @@ hipError_t launch_xcc_probe(int *out, int nblocks, hipStream_t s) {
 
 hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                                unsigned long long *queue, int threads, bool one, int grid, int maxA, int maxG,
-                               int maxin, unsigned long long watchdog, bool phase_stats, bool ext, hipStream_t s) {
+                               int maxin, unsigned long long watchdog, bool phase_stats, int depth, bool ext,
+                               hipStream_t s) {
     const size_t lds = sweep_lds_bytes(threads, maxA, maxG, maxin, one);
     const int ps = phase_stats ? 1 : 0;
 #define SNX_LAUNCH(NT)                                                                                             \
     return one ? launch_nt<NT, true, false>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds,      \
-                                            watchdog, nullptr, 0, 0, nullptr, ps, ext, s)                           \
+                                            watchdog, nullptr, 0, 0, nullptr, ps, depth, ext, s)                    \
                : launch_nt<NT, false, false>(probs, nprob, task_base, ctl, queue, maxA, maxG, maxin, grid, lds,     \
-                                             watchdog, nullptr, 0, 0, nullptr, ps, ext, s)
+                                             watchdog, nullptr, 0, 0, nullptr, ps, depth, ext, s)
     switch (threads) {
         case 64: SNX_LAUNCH(64);
         case 128: SNX_LAUNCH(128);
@@ -1104,16 +1119,16 @@ hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long lo
 hipError_t launch_sweep_level(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                               int threads, bool one, int grid, int maxA, int maxG, int maxin,
                               const long long *bsp_tasks, long long begin, long long end, const int *stops,
-                              bool ext, hipStream_t s) {
+                              int depth, bool ext, hipStream_t s) {
     const size_t lds = sweep_lds_bytes(threads, maxA, maxG, maxin, one);
     const long long n = end - begin;
     if (n <= 0) return hipSuccess;
     const int g = (int)std::min<long long>(grid, n);
 #define SNX_LAUNCH(NT)                                                                                             \
     return one ? launch_nt<NT, true, true>(probs, nprob, task_base, ctl, nullptr, maxA, maxG, maxin, g, lds, 0,     \
-                                           bsp_tasks, begin, end, stops, 0, ext, s)                                 \
+                                           bsp_tasks, begin, end, stops, 0, depth, ext, s)                          \
                : launch_nt<NT, false, true>(probs, nprob, task_base, ctl, nullptr, maxA, maxG, maxin, g, lds, 0,    \
-                                            bsp_tasks, begin, end, stops, 0, ext, s)
+                                            bsp_tasks, begin, end, stops, 0, depth, ext, s)
     switch (threads) {
         case 64: SNX_LAUNCH(64);
         case 128: SNX_LAUNCH(128);

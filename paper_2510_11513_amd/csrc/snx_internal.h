@@ -220,12 +220,12 @@ hipError_t launch_sweep_prologue(SweepCtl *ctl, unsigned long long *queue, const
                                  const int *seeds, const int *seed_off, const int *stops, hipStream_t s);
 hipError_t launch_sweep_kernel(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                                unsigned long long *queue, int threads, bool one, int grid, int maxA, int maxG, int maxin,
-                               unsigned long long watchdog, bool phase_stats, bool ext, hipStream_t s);
+                               unsigned long long watchdog, bool phase_stats, int depth, bool ext, hipStream_t s);
 // One level of the bulk-synchronous comparator: tasks bsp_tasks[begin, end).
 hipError_t launch_sweep_level(const DevProblem *probs, int nprob, const long long *task_base, SweepCtl *ctl,
                               int threads, bool one, int grid, int maxA, int maxG, int maxin,
                               const long long *bsp_tasks, long long begin, long long end, const int *stops,
-                              bool ext, hipStream_t s);
+                              int depth, bool ext, hipStream_t s);
 hipError_t launch_xcc_probe(int *out, int nblocks, hipStream_t s);
 hipError_t launch_task_records(int C, const int *nbr, const unsigned *perm, const unsigned char *inmask,
                                const int *indeg, const unsigned char *lagm, const unsigned char *rmask,
@@ -246,7 +246,7 @@ bool sweep_threads_valid(int threads);
 size_t sweep_lds_bytes(int threads, int maxA, int maxG, int maxin, bool one);
 // ext: the kernel variant with per-angle designation and reflective planes (any
 // problem of the schedule uses one of them)
-int sweep_occupancy(int threads, bool one, bool ext, size_t lds);
+int sweep_occupancy(int threads, bool one, bool ext, int depth, size_t lds);
 hipError_t launch_source(const DevProblem *probs, int prob, int C, int G, const float *phi, int *stop_flag,
                          hipStream_t s);
 hipError_t launch_reduce(const DevProblem *probs, int prob, int C, int G, float *phi_out, const float *phi_old,

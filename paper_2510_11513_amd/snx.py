@@ -103,6 +103,8 @@ def load(path: str = LIB_PATH):
     L.snx_batch_set_sweep_mode.argtypes = [_vp, ct.c_int32]
     L.snx_sweep_stats.argtypes = [_vp, _vp]
     L.snx_set_watchdog.argtypes = [_vp, ct.c_double]
+    L.snx_set_staging_depth.argtypes = [_vp, ct.c_int32]
+    L.snx_get_staging_depth.argtypes = [_vp, ct.POINTER(ct.c_int32)]
     L.snx_profile_sweep.argtypes = [_vp, ct.c_int32, _vp, _vp, ct.POINTER(ct.c_double), _vp]
     L.snx_tune.argtypes = [_vp, ct.c_char_p, _vp, _vp]
     L.snx_batch_create.argtypes = [ct.POINTER(_vp), ct.c_int32, _vp]
@@ -408,6 +410,15 @@ class Problem:
         out = np.zeros(11, np.int64)
         self._check(load().snx_sweep_stats(self.h, out.ctypes.data_as(ct.c_void_p)), "sweep_stats")
         return _stats(out)
+
+    def set_staging_depth(self, depth: int):
+        """1: inputs requested one task (traces) or round ahead; 0: at their start (same bits)."""
+        self._check(load().snx_set_staging_depth(self.h, int(depth)), "set_staging_depth")
+
+    def staging_depth(self) -> int:
+        d = ct.c_int32()
+        self._check(load().snx_get_staging_depth(self.h, ct.byref(d)), "get_staging_depth")
+        return int(d.value)
 
     def set_watchdog(self, seconds: float):
         """Wall-clock limit on a dependency-driven sweep's wait for a ready task (<= 0: the 20 s default)."""
