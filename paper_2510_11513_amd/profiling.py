@@ -73,7 +73,7 @@ def pmc_summary(fetch_db: str, write_db: str, out_path: str, fetch_cmd: str, wri
 
     def sweep_values(d):   # default dependency-driven sweeps that did work (not the per-level comparator
         #                     nor the variant for the optional physics)
-        vals = [x for k, v in d.items() if re.search(r"k_sweep<\d+, (true|false), false, false>", k) for x in v]
+        vals = [x for k, v in d.items() if re.search(r"k_sweep<\d+, (true|false), false, false(, 1)?>", k) for x in v]
         top = max(vals)
         return [x for x in vals if x > 0.5 * top]
 
@@ -108,7 +108,7 @@ def sq_summary(db: str, out_path: str, command: str, tasks: int, solves: int, be
     vals = {}
     for c in SQ_COUNTERS:
         d = _counter(db, c)
-        v = [x for k, xs in d.items() if re.search(r"k_sweep<\d+, (true|false), false, false>", k) for x in xs]
+        v = [x for k, xs in d.items() if re.search(r"k_sweep<\d+, (true|false), false, false(, 1)?>", k) for x in xs]
         vals[c] = sum(v) / len(v) if v else float("nan")
         n = len(v)
     rounds = solves / 64.0
