@@ -543,13 +543,22 @@ hipError_t launch_unit_sweep(const DirDev &D, const DevProblem *probs, unsigned 
     if (e != hipSuccess) return e;
     const int upw = std::min(kMaxUnits, kDirThreads / D.G);
     const size_t lds = sizeof(float) * (size_t)upw * kUnitFloats;
-    int dev = 0, cus = 0, per = 0;
+    // resident waves for this (device, upw): queried once
+    static thread_local int c_dev = -1, c_upw = -1, c_grid = 0;
+    int dev = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_units, kDirThreads, lds)) != hipSuccess)
-        return e;
-    // every wave resident at once: a wave that waits for a queue slot holds no unit
-    const unsigned grid = (unsigned)std::max(1, per * cus);
+    if (dev != c_dev || upw != c_upw) {
+        int cus = 0, per = 0;
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_units, kDirThreads, lds)) != hipSuccess)
+            return e;
+        c_dev = dev;
+        c_upw = upw;
+        c_grid = std::max(1, per * cus);
+    }
+    // every wave resident at once (not needed for progress: a wave that waits
+    // for a queue slot holds no unit)
+    const unsigned grid = (unsigned)c_grid;
     hipLaunchKernelGGL(k_sweep_units, dim3(grid), dim3(kDirThreads), lds, s, D, probs, upw, abortp, watchdog, stop,
                        phase_stats ? 1 : 0);
     return hipGetLastError();
