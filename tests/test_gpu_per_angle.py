@@ -404,3 +404,31 @@ def test_direction_order_dependency_driven_sweep_gives_the_level_bits(name):
     print(f"[case] per-direction units vs levels {name}: {nsweeps} sweeps and a solve bit-identical", flush=True)
     for p in ps:
         p.close()
+
+
+@pytest.mark.parametrize("G", [1, 64, 100])
+def test_direction_order_group_edge_counts(G):
+    """Designation 2 at G = 1 (eight units per wave, one lane each), G = 64 (one
+    unit fills a wave) and G = 100 (a unit spans two waves: the level launches
+    only; the dependency-driven mode falls back to them): two chained sweeps
+    against the oracle, and the two modes give the same bits."""
+    from paper_2510_11513_amd import snx
+    torch = _torch()
+    prob = _problem(3, G, 1, 2, seed=G, jitter=0.3)
+    print(f"[case] per-direction order G={G} C={prob.mesh.ncell} nang={prob.nang}", flush=True)
+    ps = [_gpu(prob, designation=snx.DESIGNATION_DIRECTION, mode=m) for m in (snx.SWEEP_AMT, snx.SWEEP_BSP)]
+    o = oracle.Oracle.from_problem(prob, designation=2)
+    phi32 = _phi_in(prob, 31)
+    pin = torch.from_numpy(phi32).cuda()
+    psi_prev = None
+    for k in range(2):
+        outs = [p.sweep(pin) for p in ps]
+        torch.cuda.synchronize()
+        assert torch.equal(outs[0], outs[1]), (G, k)
+        assert ps[0].sweep_stats()["abort"] == 0
+        r = o.sweep(phi32.astype(np.float64), want_psi=True, psi_prev=psi_prev)
+        err = H.rel_err_per_group(outs[0].cpu().numpy().astype(np.float64), r["phi"])
+        assert err.max() <= TOL, (G, k, err.max())
+        psi_prev = r["psi"]
+    for p in ps:
+        p.close()
