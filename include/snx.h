@@ -404,6 +404,8 @@ void snx_batch_destroy(snx_batch *b);
 const char *snx_batch_last_error(const snx_batch *b);
 /* As snx_set_sweep_mode, for every problem of the batch. */
 snx_status snx_batch_set_sweep_mode(snx_batch *b, int32_t mode);
+/* As snx_set_staging_depth, for the batch's shared sweep (snx_batch_tune also picks it). */
+snx_status snx_batch_set_staging_depth(snx_batch *b, int32_t depth);
 /* As snx_set_schedule, with threads at least the largest G of the batch. */
 snx_status snx_batch_set_schedule(snx_batch *b, int32_t threads, int32_t wg_per_cu, int32_t chunk);
 /* As snx_tune, over the whole batch. */

@@ -1959,6 +1959,14 @@ snx_status snx_batch_set_sweep_mode(snx_batch *b, int32_t mode) {
     return SNX_OK;
 }
 
+snx_status snx_batch_set_staging_depth(snx_batch *b, int32_t depth) {
+    if (!b) return SNX_E_ARG;
+    if (depth != 0 && depth != 1) return fail_msg(b->sched.err, SNX_E_ARG, "staging depth must be 0 or 1");
+    b->sched.depth = depth;
+    b->sched.drop_graphs();
+    return configure_grid(b->sched);
+}
+
 snx_status snx_batch_set_sweep_stats(snx_batch *b, int32_t phases) {
     if (!b) return SNX_E_ARG;
     b->sched.phase_stats = phases != 0;

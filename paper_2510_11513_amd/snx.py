@@ -35,7 +35,8 @@ EXPORTS = ["snx_create", "snx_destroy", "snx_last_error", "snx_set_mesh", "snx_s
            "snx_get_psi", "snx_set_sweep_stats", "snx_batch_set_sweep_stats", "snx_set_designation",
            "snx_designation_stats", "snx_set_group_scattering", "snx_solve_outer", "snx_set_reflective",
            "snx_set_anisotropy", "snx_get_schedule", "snx_batch_solve_outer", "snx_set_order", "snx_get_order",
-           "snx_integrated_flux_noalloc"]
+           "snx_integrated_flux_noalloc", "snx_set_watchdog", "snx_set_staging_depth", "snx_get_staging_depth",
+           "snx_batch_set_staging_depth"]
 _NO_STATUS = ("snx_destroy", "snx_last_error", "snx_batch_destroy", "snx_batch_last_error", "snx_gnn_destroy",
               "snx_gnn_last_error")
 
@@ -105,6 +106,7 @@ def load(path: str = LIB_PATH):
     L.snx_set_watchdog.argtypes = [_vp, ct.c_double]
     L.snx_set_staging_depth.argtypes = [_vp, ct.c_int32]
     L.snx_get_staging_depth.argtypes = [_vp, ct.POINTER(ct.c_int32)]
+    L.snx_batch_set_staging_depth.argtypes = [_vp, ct.c_int32]
     L.snx_profile_sweep.argtypes = [_vp, ct.c_int32, _vp, _vp, ct.POINTER(ct.c_double), _vp]
     L.snx_tune.argtypes = [_vp, ct.c_char_p, _vp, _vp]
     L.snx_batch_create.argtypes = [ct.POINTER(_vp), ct.c_int32, _vp]
@@ -476,6 +478,9 @@ class Batch:
 
     def set_sweep_mode(self, mode: int):
         self._check(load().snx_batch_set_sweep_mode(self.h, mode), "batch_set_sweep_mode")
+
+    def set_staging_depth(self, depth: int):
+        self._check(load().snx_batch_set_staging_depth(self.h, int(depth)), "batch_set_staging_depth")
 
     def tune(self, cache_path=None, stream=None):
         chosen = np.zeros(2, np.int32)

@@ -70,3 +70,25 @@ def test_tuner_searches_and_caches_the_staging_depth(tmp_path):
     assert q.staging_depth() == d
     p.close()
     q.close()
+
+
+def test_batch_staging_depth_gives_the_same_bits():
+    import torch
+    from paper_2510_11513_amd import snx
+    probs = [_problem(5, 24, 2, 2, seed=21), _problem(6, 8, 2, 3, seed=22)]   # A*G 96 and 48: multi-round at 64
+    outs = []
+    for depth in (1, 0):
+        ps = [snx.Problem.from_problem(pr) for pr in probs]
+        b = snx.Batch(ps)
+        b.set_schedule(threads=64)
+        b.set_staging_depth(depth)
+        rng = np.random.default_rng(3)
+        pin = [torch.from_numpy(rng.uniform(0, 2, (pr.mesh.ncell, pr.mat.ngroup, 8)).astype(np.float32)).cuda()
+               for pr in probs]
+        outs.append([o.clone() for o in b.sweep(pin)])
+        torch.cuda.synchronize()
+        assert b.stats()["abort"] == 0
+        with pytest.raises(snx.SnxError):
+            b.set_staging_depth(-1)
+    for a, c in zip(*outs):
+        assert torch.equal(a, c)
