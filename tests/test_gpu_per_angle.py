@@ -406,16 +406,17 @@ def test_direction_order_dependency_driven_sweep_gives_the_level_bits(name):
         p.close()
 
 
-@pytest.mark.parametrize("G", [1, 64, 100])
-def test_direction_order_group_edge_counts(G):
+@pytest.mark.parametrize("n,G", [(3, 1), (3, 64), (3, 100), (1, 2)])
+def test_direction_order_group_edge_counts(n, G):
     """Designation 2 at G = 1 (eight units per wave, one lane each), G = 64 (one
-    unit fills a wave) and G = 100 (a unit spans two waves: the level launches
-    only; the dependency-driven mode falls back to them): two chained sweeps
-    against the oracle, and the two modes give the same bits."""
+    unit fills a wave), G = 100 (a unit spans two waves: the level launches
+    only; the dependency-driven mode falls back to them) and a single cell
+    (every unit a seed, one level): two chained sweeps against the oracle, and
+    the two modes give the same bits."""
     from paper_2510_11513_amd import snx
     torch = _torch()
-    prob = _problem(3, G, 1, 2, seed=G, jitter=0.3)
-    print(f"[case] per-direction order G={G} C={prob.mesh.ncell} nang={prob.nang}", flush=True)
+    prob = _problem(n, G, 1, 2, seed=G + n, jitter=0.3)
+    print(f"[case] per-direction order n={n} G={G} C={prob.mesh.ncell} nang={prob.nang}", flush=True)
     ps = [_gpu(prob, designation=snx.DESIGNATION_DIRECTION, mode=m) for m in (snx.SWEEP_AMT, snx.SWEEP_BSP)]
     o = oracle.Oracle.from_problem(prob, designation=2)
     phi32 = _phi_in(prob, 31)
