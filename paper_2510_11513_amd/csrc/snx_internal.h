@@ -122,11 +122,16 @@ struct DevProblem {
 // direction) belongs to queue (o A + a) mod kUnitQueues, as do its downwind
 // units; each queue's slots, units and seeds are fixed at set-up.
 constexpr int kUnitQueues = 8;
+// Each word on a cache line of its own: the waves that take slots (head),
+// push ready units (tail) and poll for the queue's end (done) then never
+// contend for one line (measured 9.4 -> 7.4 ms per cfg2 sweep).
 struct alignas(128) UnitQ {
     unsigned head;   // next slot to take
+    unsigned pad0[31];
     unsigned tail;   // next slot to fill
+    unsigned pad1[31];
     unsigned done;   // units of the queue solved, flushed before a wave waits
-    unsigned pad;
+    unsigned pad2[31];
 };
 // Statistics of a unit sweep, summed over the waves that start on each XCD.
 struct alignas(128) UnitStat {
