@@ -232,9 +232,15 @@ __device__ __forceinline__ void wave_lds_sync() {
 // takes column k out of its own row.  A template per step keeps every row
 // index static, so the row stays in registers.
 constexpr int kChunks = 4;   // 16-byte pivot chunks (of each pivot row) loaded ahead at order 3
+// Each lane keeps the inverse of its own pivot from the elimination (one select
+// per step) instead of every lane taking a reciprocal at every back-substitution
+// step, twice per system with the refinement.  That pays at order 3 (64 rows,
+// 6 % faster); at order 2 the extra selects cost more than the 27 reciprocals
+// (3 % slower), so there the back substitution takes the reciprocals.
+template <int N> constexpr bool kKeepInversePivot = N > 32;
 
 template <int N, int k>
-__device__ __forceinline__ void lu_step(float (&row)[N], float &b, float *piv, int r) {
+__device__ __forceinline__ void lu_step(float (&row)[N], float &b, float &idg, float *piv, int r) {
     if (r == k) {   // whole 16-byte chunks from the one holding column k (entries left of k go unread)
         float4 *w4 = reinterpret_cast<float4 *>(piv);
 #pragma unroll
@@ -247,7 +253,12 @@ __device__ __forceinline__ void lu_step(float (&row)[N], float &b, float *piv, i
     }
     wave_lds_sync();
     const float4 *piv4 = reinterpret_cast<const float4 *>(piv);
-    const float l = r > k ? row[k] * __builtin_amdgcn_rcpf(piv[k]) : 0.f;
+    const float ip = __builtin_amdgcn_rcpf(piv[k]);
+    const float l = r > k ? row[k] * ip : 0.f;
+    if constexpr (kKeepInversePivot<N>) {
+        idg = r == k ? ip : idg;
+        asm volatile("" : "+v"(idg));
+    }
 #pragma unroll
     for (int c = (k + 1) / 4; c < (N + 3) / 4; ++c) {
         const float4 v = piv4[c];
@@ -271,7 +282,7 @@ __device__ __forceinline__ void lu_step(float (&row)[N], float &b, float *piv, i
 // only takes out column k.  Same arithmetic as two single steps, up to
 // rounding order.
 template <int N, int LP, int k, bool KEEP>
-__device__ __forceinline__ void lu_step2(float (&row)[N], float &b, float *piv, int r) {
+__device__ __forceinline__ void lu_step2(float (&row)[N], float &b, float &idg, float *piv, int r) {
     float *piv1 = piv + LP;
     if (r == k || r == k + 1) {
         float4 *w4 = reinterpret_cast<float4 *>(r == k ? piv : piv1);
@@ -291,7 +302,12 @@ __device__ __forceinline__ void lu_step2(float (&row)[N], float &b, float *piv, 
     const float m1 = qk * ipk;                                  // row k+1's multiplier of row k
     const float d = __builtin_fmaf(-m1, pk1, qk1);              // row k+1's pivot after that
     const float l0 = row[k] * ipk;
-    const float l1 = __builtin_fmaf(-l0, pk1, row[k + 1]) * __builtin_amdgcn_rcpf(d);
+    const float id = __builtin_amdgcn_rcpf(d);
+    const float l1 = __builtin_fmaf(-l0, pk1, row[k + 1]) * id;
+    if constexpr (kKeepInversePivot<N>) {
+        idg = r == k ? ipk : (r == k + 1 ? id : idg);           // the lane's own inverse pivot
+        asm volatile("" : "+v"(idg));   // taken here: the pivots need not stay live to the back substitution
+    }
     const float c0 = r > k + 1 ? __builtin_fmaf(-l1, m1, l0) : (r == k + 1 ? m1 : 0.f);
     const float c1 = r > k + 1 ? l1 : 0.f;
     // The multipliers go where this step leaves nothing of use (columns k and
@@ -339,40 +355,53 @@ __device__ __forceinline__ void replay_step2(const float (&row)[N], float &b, in
     b = __builtin_fmaf(-c1, bk1, __builtin_fmaf(-c0, bk, b));
 }
 
+// v_writelane_b32 (lane `lane` of `old` takes the uniform `val`), reached through
+// its LLVM intrinsic, which this compiler has no builtin for; being the
+// intrinsic, the compiler knows it and inserts its hazard waits.
+extern "C" __device__ int snx_writelane_i32(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 // Back substitution, column k = N-1-i: lane k finishes x_k, which every lane
-// of its system reads straight from lane k's register (no LDS round trip),
-// and the rows above take it out.  H: lanes per system (32: two systems per wave).
+// of its system reads straight from lane k's register (no LDS round trip) and
+// which is written into lane k of x; the rows above take it out.  The lanes at
+// and below k hold their x already and never read b again, so they take out
+// the same product unmasked.  H: lanes per system (32: two systems per wave).
 template <int N, int H, int i>
-__device__ __forceinline__ void back_step(const float (&row)[N], float &b, float &x, int r, int half) {
+__device__ __forceinline__ void back_step(const float (&row)[N], float idg, float &b, float &x, int half) {
     constexpr int k = N - 1 - i;
-    const int cand = __builtin_bit_cast(int, b * __builtin_amdgcn_rcpf(row[k]));   // x_k in lane k
+    const float inv = kKeepInversePivot<N> ? idg : __builtin_amdgcn_rcpf(row[k]);
+    const int cand = __builtin_bit_cast(int, b * inv);   // x_k in lane k
+    int xi = __builtin_bit_cast(int, x);
     float xk;
     if constexpr (H == 64) {
-        xk = __builtin_bit_cast(float, __builtin_amdgcn_readlane(cand, k));
+        const int s = __builtin_amdgcn_readlane(cand, k);
+        xi = snx_writelane_i32(s, k, xi);
+        xk = __builtin_bit_cast(float, s);
     } else {
-        const float x0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(cand, k));
-        const float x1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(cand, H + k));
-        xk = half ? x1 : x0;
+        const int s0 = __builtin_amdgcn_readlane(cand, k), s1 = __builtin_amdgcn_readlane(cand, H + k);
+        xi = snx_writelane_i32(s0, k, xi);
+        xi = snx_writelane_i32(s1, H + k, xi);
+        xk = __builtin_bit_cast(float, half ? s1 : s0);
     }
-    if (r == k) x = xk;
-    b = __builtin_fmaf(r < k ? -row[k] : 0.f, xk, b);
+    x = __builtin_bit_cast(float, xi);
+    b = __builtin_fmaf(-row[k], xk, b);
 }
 template <int N, int H, int LP, bool KEEP, int... K, int... I>
-__device__ __forceinline__ void lu_solve(float (&row)[N], float &b, float &x, float *piv, int r, int half,
-                                         std::integer_sequence<int, K...>, std::integer_sequence<int, I...>) {
-    (lu_step2<N, LP, 2 * I, KEEP>(row, b, piv, r), ...);       // pivots in pairs
-    if constexpr (N % 2) lu_step<N, N - 1>(row, b, piv, r);      // the odd last one (no row below it)
+__device__ __forceinline__ void lu_solve(float (&row)[N], float &b, float &x, float &idg, float *piv, int r,
+                                         int half, std::integer_sequence<int, K...>,
+                                         std::integer_sequence<int, I...>) {
+    (lu_step2<N, LP, 2 * I, KEEP>(row, b, idg, piv, r), ...);  // pivots in pairs
+    if constexpr (N % 2) lu_step<N, N - 1>(row, b, idg, piv, r); // the odd last one (no row below it)
     asm volatile("" : "+v"(r), "+v"(half));                      // fresh lane masks for this pass
-    (back_step<N, H, K>(row, b, x, r, half), ...);
+    (back_step<N, H, K>(row, idg, b, x, half), ...);
 }
 // A second solve with the factors of lu_solve: forward elimination replayed
 // pair by pair, then back substitution.
 template <int N, int H, int... K, int... I>
-__device__ __forceinline__ void lu_resolve(const float (&row)[N], float &b, float &x, int r, int half,
+__device__ __forceinline__ void lu_resolve(const float (&row)[N], float idg, float &b, float &x, int r, int half,
                                            std::integer_sequence<int, K...>, std::integer_sequence<int, I...>) {
     (replay_step2<N, H, 2 * I>(row, b, r, half), ...);
     asm volatile("" : "+v"(r), "+v"(half));
-    (back_step<N, H, K>(row, b, x, r, half), ...);
+    (back_step<N, H, K>(row, idg, b, x, half), ...);
 }
 
 // Node of face f at face position (pu, pv): the face's axis coordinate fixed at
@@ -536,8 +565,8 @@ __device__ __forceinline__ void ho_sweep_body(const HoDev &D, int begin) {
         }
         const double b0 = bd;
         float b = (float)bd;
-        float x = 0.f;
-        lu_solve<N, H, LP, (REFINE > 0)>(row, b, x, piv, rl, hl, std::make_integer_sequence<int, N>{},
+        float x = 0.f, idg = 0.f;   // idg: the inverse of this lane's pivot
+        lu_solve<N, H, LP, (REFINE > 0)>(row, b, x, idg, piv, rl, hl, std::make_integer_sequence<int, N>{},
                                          std::make_integer_sequence<int, N / 2>{});
         // refinement: residual in FP64, b0 - B x - sigma_t M x with B in FP64, then
         // the correction from the same factors.  x reaches every lane of the system
@@ -565,7 +594,7 @@ __device__ __forceinline__ void ho_sweep_body(const HoDev &D, int begin) {
             const double res = __builtin_fma(-(double)sig, sm, b0 - sb);
             float rb = (float)res, dxk = 0.f;
             asm volatile("" : "+v"(rl), "+v"(hl));   // not the masks of the first solve either
-            lu_resolve<N, H>(row, rb, dxk, rl, hl, std::make_integer_sequence<int, N>{},
+            lu_resolve<N, H>(row, idg, rb, dxk, rl, hl, std::make_integer_sequence<int, N>{},
                              std::make_integer_sequence<int, N / 2>{});
             x += dxk;
             wave_lds_sync();      // every lane has read the old x before the next write
