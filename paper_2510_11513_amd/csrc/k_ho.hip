@@ -231,7 +231,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // (columns k.., and its right-hand side at [N]) through LDS, every lane below
 // takes column k out of its own row.  A template per step keeps every row
 // index static, so the row stays in registers.
-constexpr int kChunks = 4;   // 16-byte pivot chunks (of each pivot row) loaded ahead at order 3
+// 16-byte pivot chunks (of each pivot row) loaded ahead at order 3; the order-3
+// sweep takes 126.3 ms at 3, 126.9 at 2, 128.2 at 4, 134 at 8 and 135 at 1.
+constexpr int kChunks = 3;
 // Each lane keeps the inverse of its own pivot from the elimination (one select
 // per step) instead of every lane taking a reciprocal at every back-substitution
 // step, twice per system with the refinement.  That pays at order 3 (64 rows,
@@ -268,7 +270,7 @@ __device__ __forceinline__ void lu_step(float (&row)[N], float &b, float &idg, f
             const int j = 4 * c + e;
             if (j > k && j < N) row[j] = __builtin_fmaf(-l, vv[e], row[j]);
         }
-        // at most kChunks pivot chunks in flight: fewer live registers, more resident waves
+        // at most kChunks pivot chunks in flight: fewer live registers
         if (N > 32 && (c + 1) % kChunks == 0) __builtin_amdgcn_sched_barrier(0);
     }
     b = __builtin_fmaf(-l, piv[N], b);
