@@ -227,10 +227,6 @@ __device__ __forceinline__ void wave_lds_sync() {
     asm volatile("" ::: "memory");
 }
 
-// Elimination step k of the unpivoted LU by rows: lane k broadcasts its row
-// (columns k.., and its right-hand side at [N]) through LDS, every lane below
-// takes column k out of its own row.  A template per step keeps every row
-// index static, so the row stays in registers.
 // 16-byte pivot chunks (of each pivot row) loaded ahead at order 3; the order-3
 // sweep takes 126.3 ms at 3, 126.9 at 2, 128.2 at 4, 134 at 8 and 135 at 1.
 constexpr int kChunks = 3;
@@ -241,6 +237,10 @@ constexpr int kChunks = 3;
 // (3 % slower), so there the back substitution takes the reciprocals.
 template <int N> constexpr bool kKeepInversePivot = N > 32;
 
+// Elimination step k of the unpivoted LU by rows: lane k broadcasts its row
+// (columns k.., and its right-hand side at [N]) through LDS, every lane below
+// takes column k out of its own row.  A template per step keeps every row
+// index static, so the row stays in registers.
 template <int N, int k>
 __device__ __forceinline__ void lu_step(float (&row)[N], float &b, float &idg, float *piv, int r) {
     if (r == k) {   // whole 16-byte chunks from the one holding column k (entries left of k go unread)
